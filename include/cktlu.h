@@ -1,0 +1,228 @@
+/*
+ * cktlu -- circuit sparse LU for MI355X (gfx950): the C ABI.
+ *
+ * The library follows the solver structure of CKTSO (Chen, "CKTSO:
+ * High-Performance Parallel Sparse Linear Solver for General Circuit
+ * Simulations", IEEE TCAD): a one-time pre-processing step, a numerical
+ * factorization in every Newton-Raphson iteration, and triangular solves
+ * (Section III, Fig. 4).  Matrices are CSC and factored left-looking, which is
+ * the paper's up-looking row algorithm applied to the transpose (Section II-A).
+ *
+ * Conventions for every entry point:
+ *   - return value: 0 = success, > 0 = success with a warning (CKTLU_W_*),
+ *     < 0 = error (CKTLU_E_*); cktlu_strerror() names each code;
+ *   - integer arrays are int32, 0-based; CSC inputs have sorted row indices
+ *     inside each column and no duplicates;
+ *   - "host" pointers are ordinary CPU memory, "device" pointers are HIP
+ *     device memory of the current device (e.g. a PyTorch CUDA tensor);
+ *   - the caller owns every pointer it passes and keeps device buffers alive
+ *     until the work queued on the context's stream has completed; the library
+ *     copies the host pattern arrays it needs and owns the device memory it
+ *     allocates (patterns, factors, schedules), released by cktlu_destroy();
+ *   - one context per circuit; all device work of a context is ordered on its
+ *     stream; a context is not safe for concurrent calls from several threads.
+ *   - call order: create -> analyze -> factorize[_host] -> (refactorize ->
+ *     solve)*; a call out of order returns CKTLU_E_STATE.
+ */
+#ifndef CKTLU_H
+#define CKTLU_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* status codes */
+#define CKTLU_OK 0
+#define CKTLU_W_REPIVOTED 1     /* a pivot check failed; the fallback re-pivoted (pattern may change) */
+#define CKTLU_W_IR_FALLBACK 2   /* FP32 refinement did not reach the tolerance; FP64 path used */
+#define CKTLU_E_ARG (-1)        /* invalid argument (bad CSC, bad size, NULL pointer) */
+#define CKTLU_E_STATE (-2)      /* call out of order */
+#define CKTLU_E_STRUCT_SINGULAR (-3) /* no zero-free diagonal exists / empty candidate set */
+#define CKTLU_E_NUM_SINGULAR (-4)    /* zero or non-finite pivot after pivoting */
+#define CKTLU_E_NOMEM (-5)      /* host or device allocation failed */
+#define CKTLU_E_HIP (-6)        /* a HIP runtime call failed */
+#define CKTLU_E_LIMIT (-7)      /* a size exceeds a documented limit */
+
+/* precision of the factors */
+#define CKTLU_FP64 0            /* FP64 factors and solves */
+#define CKTLU_FP32_IR 1         /* FP32 factors, FP64 residual / update / pivot test, iterative refinement */
+
+/* fill-reducing ordering used by analyze */
+#define CKTLU_ORDER_AMD 0       /* approximate minimum degree on the pattern of B + B' */
+#define CKTLU_ORDER_NATURAL 1   /* keep the (transversal-permuted) natural order */
+
+typedef struct cktlu_ctx cktlu_ctx;
+
+typedef struct {
+    double pivot_eps;      /* threshold eps of the pivot rule (Section II-A); default 1e-3, range (0, 1] */
+    int precision;         /* CKTLU_FP64 (default) or CKTLU_FP32_IR */
+    double ir_tol;         /* FP32_IR: backward-error target; default 1e-10 */
+    int ir_max_iter;       /* FP32_IR: refinement step limit; default 10 */
+    int ordering;          /* CKTLU_ORDER_*; default AMD */
+    int transversal;       /* 1 (default): structural maximum transversal before ordering */
+    void *stream;          /* hipStream_t for all device work; NULL = the null stream */
+    int force_fail_col;    /* test hook: >= 0 makes the pivot check of this column fail once */
+    int dense_tail_min;    /* schedule: smallest trailing block handled densely; 0 = automatic, -1 = never */
+    double dense_tail_density; /* schedule: minimum fill density of that block; default 0.3 */
+} cktlu_options;
+
+typedef struct {
+    int repivoted;         /* 1 if a pivot check failed and the fallback ran */
+    int first_fail_col;    /* smallest column whose check failed, -1 if none */
+    int restart_size;      /* columns recomputed with pivoting by the fallback */
+    int pattern_changed;   /* 1 if the factor pattern changed (schedules rebuilt) */
+} cktlu_refactor_info;
+
+typedef struct {
+    int ir_iters;          /* refinement steps taken (0 in FP64 mode) */
+    double backward_err;   /* FP32_IR: final eta_inf of the first right-hand side; FP64: -1 (not computed) */
+    int used_fp64;         /* 1 if the FP32_IR solve fell back to FP64 factors */
+} cktlu_solve_info;
+
+typedef struct {
+    int64_t n, nnz_a, nnz_l, nnz_u;   /* nnz_l: strictly lower L; nnz_u: U incl. diagonal */
+    double flops;                     /* factorization FLOPs: 2*MACs + divisions (Section VI) */
+    double macs;                      /* multiply-adds of the left-looking update */
+    int64_t levels, max_width;        /* dependency-graph levels and widest level */
+    int64_t etree_height;             /* height of the column elimination tree */
+    int64_t dense_tail;               /* order of the trailing block factored densely (0 = none) */
+    int64_t n_factorize, n_refactorize, n_repivot, n_restart_cols;
+    int64_t n_fp64_fallback_solves;
+    double bytes_refactor, bytes_solve;  /* algorithmic HBM bytes per refactorization / per RHS solve */
+} cktlu_stats;
+
+/* Fill *opt with defaults. */
+void cktlu_default_options(cktlu_options *opt);
+
+/* Create a context.  opt may be NULL (defaults).  *out is NULL on failure. */
+int cktlu_create(cktlu_ctx **out, const cktlu_options *opt);
+
+/* Release all host and device memory of the context.  NULL is ignored. */
+void cktlu_destroy(cktlu_ctx *ctx);
+
+/* Human-readable name of a status code (static string). */
+const char *cktlu_strerror(int status);
+
+/* Change the stream used for device work (hipStream_t, NULL = null stream). */
+int cktlu_set_stream(cktlu_ctx *ctx, void *stream);
+
+/*
+ * Pre-processing (Section III-A), host only, once per pattern: validates the
+ * CSC pattern (host, n x n, colptr[n+1], rowind[colptr[n]]), finds a
+ * structural maximum transversal (a zero-free diagonal), computes the
+ * fill-reducing symmetric ordering and the column elimination tree of the
+ * permuted matrix (Section II-B).  Does not touch the device.
+ * Errors: E_ARG, E_STRUCT_SINGULAR, E_NOMEM.
+ */
+int cktlu_analyze(cktlu_ctx *ctx, int32_t n, const int32_t *colptr, const int32_t *rowind);
+
+/*
+ * Factorization with pivoting (Section II-A, Algorithm 1): threshold partial
+ * pivoting on the host, then the dependency schedule (Section II-B) and the
+ * device layout are built and uploaded.  values_dev: device, nnz FP64 values
+ * in analyze()'s CSC order.  The preferred pivot of each column is the row in
+ * its position under the previous pivot sequence (identity the first time).
+ * Synchronises the context's stream.  Errors: E_STATE, E_STRUCT_SINGULAR,
+ * E_NUM_SINGULAR, E_NOMEM, E_HIP.
+ */
+int cktlu_factorize(cktlu_ctx *ctx, const double *values_dev);
+
+/* Same as cktlu_factorize with host values (no device work until the next
+ * device call).  Usable without a GPU. */
+int cktlu_factorize_host(cktlu_ctx *ctx, const double *values_host);
+
+/*
+ * Fast factorization with pivot check (Section IV): the stored pattern and
+ * pivot sequence are reused; every column is updated on the device in a
+ * dependency-ordered schedule and its pivot is tested against eps times the
+ * largest entry of its L part.  When a test fails, the remaining work stops,
+ * the restart set (unfinished columns and their elimination-tree ancestors,
+ * Section IV-C) is refactored with pivoting on the host (Section IV-D), the
+ * schedule is rebuilt for the new pattern and CKTLU_W_REPIVOTED is returned.
+ * values_dev: device, nnz FP64 values in analyze()'s CSC order.  info may be
+ * NULL.  Synchronises the stream once (a 16-byte status read).
+ * Errors: E_STATE, E_NUM_SINGULAR, E_NOMEM, E_HIP.
+ */
+int cktlu_refactorize(cktlu_ctx *ctx, const double *values_dev, cktlu_refactor_info *info);
+
+/*
+ * Re-factorization without pivot check (Section II-A, Algorithm 1 without its
+ * symbolic and pivoting lines): the check-free counterpart of
+ * cktlu_refactorize, kept to measure the cost of the check.  Never re-pivots.
+ */
+int cktlu_refactorize_nocheck(cktlu_ctx *ctx, const double *values_dev);
+
+/*
+ * Triangular solves (Section II-C, Algorithm 2; Section V): x = A^{-1} b for
+ * nrhs right-hand sides.  b_dev: device, column r at b_dev + r*ldb (ldb >= n);
+ * x_dev: device, column r at x_dev + r*ldx (ldx >= n); b and x must not
+ * overlap.  In FP32_IR mode the residual, the update and the stopping test run
+ * in FP64 against the values of the last refactorization (backward error
+ * eta_inf <= ir_tol), falling back to FP64 factors when refinement stalls.
+ * info may be NULL.  Errors: E_STATE, E_ARG, E_HIP.
+ */
+int cktlu_solve(cktlu_ctx *ctx, int32_t nrhs, const double *b_dev, int32_t ldb,
+                double *x_dev, int32_t ldx, cktlu_solve_info *info);
+
+/*
+ * Batched fast factorization of `batch` same-pattern instances (Monte-Carlo
+ * corners).  values_dev: device, batch x nnz FP64 values, instance i at
+ * values_dev + i*nnz.  status_dev: device int32[batch]; entry i is set to -1
+ * when instance i passed every pivot check, else to its smallest failing
+ * column.  No host synchronisation and no fallback; the factors stay resident
+ * for cktlu_solve_batched.  Errors: E_STATE, E_ARG, E_NOMEM, E_HIP.
+ */
+int cktlu_refactorize_batched(cktlu_ctx *ctx, int32_t batch, const double *values_dev,
+                              int32_t *status_dev);
+
+/*
+ * Solves with the resident factors of the last cktlu_refactorize_batched.
+ * b_dev: device, batch x nrhs x n FP64 (instance i, rhs r at (i*nrhs + r)*n);
+ * x_dev: same layout.  Instances whose status is not -1 are skipped (their x
+ * is left unchanged).  In FP32_IR mode a fixed number of refinement steps
+ * (ir_max_iter) runs without host synchronisation.  Errors: E_STATE, E_ARG,
+ * E_HIP.
+ */
+int cktlu_solve_batched(cktlu_ctx *ctx, int32_t batch, int32_t nrhs, const double *b_dev,
+                        double *x_dev, const int32_t *status_dev);
+
+/* Permutations (host out, int32[n] each): A(rowperm[k], colperm[j]) is the
+ * (k, j) entry of the matrix that was factored, rowperm including pivoting. */
+int cktlu_get_perm(const cktlu_ctx *ctx, int32_t *rowperm, int32_t *colperm);
+
+/* Pre-processing result (host out, int32[n] each, any may be NULL): the
+ * pre-processed matrix is A_hat(i, j) = A(rowperm_pre[i], colperm[j]); pivrow
+ * is the pivot sequence (position k holds A_hat row pivrow[k]); parent is the
+ * column elimination tree of A_hat (-1 = root). */
+int cktlu_get_analysis(const cktlu_ctx *ctx, int32_t *rowperm_pre, int32_t *colperm,
+                       int32_t *pivrow, int32_t *parent);
+
+/* Sizes of the stored factors: strictly-lower L and U including diagonal. */
+int cktlu_get_factor_nnz(const cktlu_ctx *ctx, int64_t *nnz_l, int64_t *nnz_u);
+
+/* Factors of the last (re)factorization, host out, position-indexed CSC with
+ * sorted rows: Lp[n+1], Li/Lx[nnz_l] (unit diagonal not stored), Up[n+1],
+ * Ui/Ux[nnz_u] (diagonal last in each column).  Any pointer may be NULL.
+ * instance selects a batched instance (0 otherwise).  Synchronises the stream. */
+int cktlu_get_factors(cktlu_ctx *ctx, int32_t instance, int32_t *Lp, int32_t *Li, double *Lx,
+                      int32_t *Up, int32_t *Ui, double *Ux);
+
+/* Level of every column in the dependency graph of the current pattern
+ * (Section II-B), host out int32[n]; sources are level 0. */
+int cktlu_get_levels(const cktlu_ctx *ctx, int32_t *level);
+
+/* Counters and sizes. */
+int cktlu_get_stats(const cktlu_ctx *ctx, cktlu_stats *out);
+
+/* Device memory the context holds now, plus what one batched instance would
+ * add (for admission control). */
+size_t cktlu_footprint_bytes(const cktlu_ctx *ctx, int32_t batch);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* CKTLU_H */

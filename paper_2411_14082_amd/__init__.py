@@ -1,0 +1,328 @@
+"""Python binding of libcktlu (circuit sparse LU on MI355X / gfx950).
+
+Thin ctypes marshalling over the C ABI declared in ``include/cktlu.h``: the
+functions keep the C names, take integers and pointers (device pointers as
+ints, e.g. ``tensor.data_ptr()``) and return the C status codes.  Every step of
+the numerical path runs inside the library's HIP kernels.  ``SparseLU`` is a
+convenience wrapper over the same calls for PyTorch tensors.
+
+The library is built in-tree by ``paper_2411_14082_amd.build`` (or
+``__graft_entry__.build()``); importing this module without it raises.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libcktlu.so")
+
+CKTLU_OK = 0
+CKTLU_W_REPIVOTED = 1
+CKTLU_W_IR_FALLBACK = 2
+CKTLU_E_ARG = -1
+CKTLU_E_STATE = -2
+CKTLU_E_STRUCT_SINGULAR = -3
+CKTLU_E_NUM_SINGULAR = -4
+CKTLU_E_NOMEM = -5
+CKTLU_E_HIP = -6
+CKTLU_E_LIMIT = -7
+CKTLU_FP64 = 0
+CKTLU_FP32_IR = 1
+CKTLU_ORDER_AMD = 0
+CKTLU_ORDER_NATURAL = 1
+
+# every symbol the header declares (checked by the CPU test-suite)
+EXPORTS = [
+    "cktlu_default_options", "cktlu_create", "cktlu_destroy", "cktlu_strerror", "cktlu_set_stream",
+    "cktlu_analyze", "cktlu_factorize", "cktlu_factorize_host", "cktlu_refactorize",
+    "cktlu_refactorize_nocheck", "cktlu_solve", "cktlu_refactorize_batched", "cktlu_solve_batched",
+    "cktlu_get_perm", "cktlu_get_analysis", "cktlu_get_factor_nnz", "cktlu_get_factors",
+    "cktlu_get_levels", "cktlu_get_stats", "cktlu_footprint_bytes",
+]
+
+
+class cktlu_options(ctypes.Structure):
+    _fields_ = [("pivot_eps", ctypes.c_double), ("precision", ctypes.c_int), ("ir_tol", ctypes.c_double),
+                ("ir_max_iter", ctypes.c_int), ("ordering", ctypes.c_int), ("transversal", ctypes.c_int),
+                ("stream", ctypes.c_void_p), ("force_fail_col", ctypes.c_int),
+                ("dense_tail_min", ctypes.c_int), ("dense_tail_density", ctypes.c_double)]
+
+
+class cktlu_refactor_info(ctypes.Structure):
+    _fields_ = [("repivoted", ctypes.c_int), ("first_fail_col", ctypes.c_int),
+                ("restart_size", ctypes.c_int), ("pattern_changed", ctypes.c_int)]
+
+
+class cktlu_solve_info(ctypes.Structure):
+    _fields_ = [("ir_iters", ctypes.c_int), ("backward_err", ctypes.c_double), ("used_fp64", ctypes.c_int)]
+
+
+class cktlu_stats(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int64), ("nnz_a", ctypes.c_int64), ("nnz_l", ctypes.c_int64),
+                ("nnz_u", ctypes.c_int64), ("flops", ctypes.c_double), ("macs", ctypes.c_double),
+                ("levels", ctypes.c_int64), ("max_width", ctypes.c_int64), ("etree_height", ctypes.c_int64),
+                ("dense_tail", ctypes.c_int64), ("n_factorize", ctypes.c_int64),
+                ("n_refactorize", ctypes.c_int64), ("n_repivot", ctypes.c_int64),
+                ("n_restart_cols", ctypes.c_int64), ("n_fp64_fallback_solves", ctypes.c_int64),
+                ("bytes_refactor", ctypes.c_double), ("bytes_solve", ctypes.c_double)]
+
+    def as_dict(self):
+        return {f: getattr(self, f) for f, _ in self._fields_}
+
+
+def _load():
+    if not os.path.exists(LIB_PATH):
+        raise ImportError("libcktlu.so is not built; run `python -m paper_2411_14082_amd.build` "
+                          "(or __graft_entry__.build()) first")
+    lib = ctypes.CDLL(LIB_PATH)
+    P = ctypes.c_void_p
+    I32 = ctypes.c_int32
+    lib.cktlu_default_options.argtypes = [ctypes.POINTER(cktlu_options)]
+    lib.cktlu_default_options.restype = None
+    lib.cktlu_create.argtypes = [ctypes.POINTER(P), ctypes.POINTER(cktlu_options)]
+    lib.cktlu_destroy.argtypes = [P]
+    lib.cktlu_destroy.restype = None
+    lib.cktlu_strerror.argtypes = [ctypes.c_int]
+    lib.cktlu_strerror.restype = ctypes.c_char_p
+    lib.cktlu_set_stream.argtypes = [P, P]
+    lib.cktlu_analyze.argtypes = [P, I32, P, P]
+    lib.cktlu_factorize.argtypes = [P, P]
+    lib.cktlu_factorize_host.argtypes = [P, P]
+    lib.cktlu_refactorize.argtypes = [P, P, ctypes.POINTER(cktlu_refactor_info)]
+    lib.cktlu_refactorize_nocheck.argtypes = [P, P]
+    lib.cktlu_solve.argtypes = [P, I32, P, I32, P, I32, ctypes.POINTER(cktlu_solve_info)]
+    lib.cktlu_refactorize_batched.argtypes = [P, I32, P, P]
+    lib.cktlu_solve_batched.argtypes = [P, I32, I32, P, P, P]
+    lib.cktlu_get_perm.argtypes = [P, P, P]
+    lib.cktlu_get_analysis.argtypes = [P, P, P, P, P]
+    lib.cktlu_get_factor_nnz.argtypes = [P, P, P]
+    lib.cktlu_get_factors.argtypes = [P, I32, P, P, P, P, P, P]
+    lib.cktlu_get_levels.argtypes = [P, P]
+    lib.cktlu_get_stats.argtypes = [P, ctypes.POINTER(cktlu_stats)]
+    lib.cktlu_footprint_bytes.argtypes = [P, I32]
+    lib.cktlu_footprint_bytes.restype = ctypes.c_size_t
+    for name in EXPORTS:
+        fn = getattr(lib, name)
+        if fn.restype is ctypes.c_int or name in ("cktlu_create",):
+            fn.restype = ctypes.c_int
+    return lib
+
+
+lib = _load()
+
+
+class CktluError(RuntimeError):
+    def __init__(self, status, where=""):
+        self.status = status
+        super().__init__(f"{where}: {strerror(status)} ({status})")
+
+
+def strerror(status: int) -> str:
+    return lib.cktlu_strerror(int(status)).decode()
+
+
+def _ptr(a):
+    """Pointer of a numpy array, a torch tensor, an int, or None."""
+    if a is None:
+        return None
+    if isinstance(a, int):
+        return a
+    if isinstance(a, np.ndarray):
+        return a.ctypes.data
+    return a.data_ptr()
+
+
+def _check(rc, where):
+    if rc < 0:
+        raise CktluError(rc, where)
+    return rc
+
+
+# ---- functions with the C names --------------------------------------------------------------
+def cktlu_default_options() -> cktlu_options:
+    o = cktlu_options()
+    lib.cktlu_default_options(ctypes.byref(o))
+    return o
+
+
+def cktlu_create(opt: cktlu_options | None = None):
+    h = ctypes.c_void_p()
+    rc = lib.cktlu_create(ctypes.byref(h), ctypes.byref(opt) if opt is not None else None)
+    _check(rc, "cktlu_create")
+    return h
+
+
+def cktlu_destroy(ctx):
+    lib.cktlu_destroy(ctx)
+
+
+def cktlu_set_stream(ctx, stream):
+    return lib.cktlu_set_stream(ctx, stream)
+
+
+def cktlu_analyze(ctx, n, colptr, rowind):
+    return lib.cktlu_analyze(ctx, int(n), _ptr(colptr), _ptr(rowind))
+
+
+def cktlu_factorize(ctx, values_dev):
+    return lib.cktlu_factorize(ctx, _ptr(values_dev))
+
+
+def cktlu_factorize_host(ctx, values_host):
+    return lib.cktlu_factorize_host(ctx, _ptr(values_host))
+
+
+def cktlu_refactorize(ctx, values_dev, info: cktlu_refactor_info | None = None):
+    return lib.cktlu_refactorize(ctx, _ptr(values_dev), ctypes.byref(info) if info is not None else None)
+
+
+def cktlu_refactorize_nocheck(ctx, values_dev):
+    return lib.cktlu_refactorize_nocheck(ctx, _ptr(values_dev))
+
+
+def cktlu_solve(ctx, nrhs, b_dev, ldb, x_dev, ldx, info: cktlu_solve_info | None = None):
+    return lib.cktlu_solve(ctx, int(nrhs), _ptr(b_dev), int(ldb), _ptr(x_dev), int(ldx),
+                           ctypes.byref(info) if info is not None else None)
+
+
+def cktlu_refactorize_batched(ctx, batch, values_dev, status_dev):
+    return lib.cktlu_refactorize_batched(ctx, int(batch), _ptr(values_dev), _ptr(status_dev))
+
+
+def cktlu_solve_batched(ctx, batch, nrhs, b_dev, x_dev, status_dev):
+    return lib.cktlu_solve_batched(ctx, int(batch), int(nrhs), _ptr(b_dev), _ptr(x_dev), _ptr(status_dev))
+
+
+def cktlu_get_perm(ctx, rowperm, colperm):
+    return lib.cktlu_get_perm(ctx, _ptr(rowperm), _ptr(colperm))
+
+
+def cktlu_get_analysis(ctx, rowperm_pre, colperm, pivrow, parent):
+    return lib.cktlu_get_analysis(ctx, _ptr(rowperm_pre), _ptr(colperm), _ptr(pivrow), _ptr(parent))
+
+
+def cktlu_get_factor_nnz(ctx, nnz_l, nnz_u):
+    return lib.cktlu_get_factor_nnz(ctx, _ptr(nnz_l), _ptr(nnz_u))
+
+
+def cktlu_get_factors(ctx, instance, Lp, Li, Lx, Up, Ui, Ux):
+    return lib.cktlu_get_factors(ctx, int(instance), _ptr(Lp), _ptr(Li), _ptr(Lx), _ptr(Up), _ptr(Ui), _ptr(Ux))
+
+
+def cktlu_get_levels(ctx, level):
+    return lib.cktlu_get_levels(ctx, _ptr(level))
+
+
+def cktlu_get_stats(ctx) -> cktlu_stats:
+    s = cktlu_stats()
+    _check(lib.cktlu_get_stats(ctx, ctypes.byref(s)), "cktlu_get_stats")
+    return s
+
+
+def cktlu_footprint_bytes(ctx, batch=0) -> int:
+    return int(lib.cktlu_footprint_bytes(ctx, int(batch)))
+
+
+# ---- convenience wrapper ---------------------------------------------------------------------
+class SparseLU:
+    """One circuit: analyze once, then factorize / refactorize / solve.
+
+    Host arrays are numpy; device arrays are torch tensors (float64, int32)
+    on the current HIP device.  Methods raise CktluError on errors and return
+    the non-negative status (0 or a warning code).
+    """
+
+    def __init__(self, n, colptr, rowind, eps=1e-3, precision=CKTLU_FP64, ordering=CKTLU_ORDER_AMD,
+                 ir_tol=1e-10, ir_max_iter=10, stream=None, transversal=1):
+        opt = cktlu_default_options()
+        opt.pivot_eps = eps
+        opt.precision = precision
+        opt.ordering = ordering
+        opt.ir_tol = ir_tol
+        opt.ir_max_iter = ir_max_iter
+        opt.transversal = transversal
+        opt.stream = stream
+        self.ctx = cktlu_create(opt)
+        self.n = int(n)
+        self._colptr = np.ascontiguousarray(colptr, dtype=np.int32)
+        self._rowind = np.ascontiguousarray(rowind, dtype=np.int32)
+        self.nnz = int(self._colptr[-1])
+        _check(cktlu_analyze(self.ctx, self.n, self._colptr, self._rowind), "cktlu_analyze")
+
+    def close(self):
+        if self.ctx:
+            cktlu_destroy(self.ctx)
+            self.ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def factorize(self, values_dev):
+        return _check(cktlu_factorize(self.ctx, values_dev), "cktlu_factorize")
+
+    def factorize_host(self, values_host):
+        v = np.ascontiguousarray(values_host, dtype=np.float64)
+        return _check(cktlu_factorize_host(self.ctx, v), "cktlu_factorize_host")
+
+    def refactorize(self, values_dev, info=None):
+        info = info if info is not None else cktlu_refactor_info()
+        rc = _check(cktlu_refactorize(self.ctx, values_dev, info), "cktlu_refactorize")
+        return rc, info
+
+    def refactorize_nocheck(self, values_dev):
+        return _check(cktlu_refactorize_nocheck(self.ctx, values_dev), "cktlu_refactorize_nocheck")
+
+    def solve(self, b_dev, x_dev, nrhs=1, ldb=None, ldx=None):
+        info = cktlu_solve_info()
+        rc = _check(cktlu_solve(self.ctx, nrhs, b_dev, ldb or self.n, x_dev, ldx or self.n, info),
+                    "cktlu_solve")
+        return rc, info
+
+    def refactorize_batched(self, batch, values_dev, status_dev):
+        return _check(cktlu_refactorize_batched(self.ctx, batch, values_dev, status_dev),
+                      "cktlu_refactorize_batched")
+
+    def solve_batched(self, batch, nrhs, b_dev, x_dev, status_dev):
+        return _check(cktlu_solve_batched(self.ctx, batch, nrhs, b_dev, x_dev, status_dev),
+                      "cktlu_solve_batched")
+
+    def analysis(self, with_pivots=True):
+        n = self.n
+        rp, cp, pv, par = (np.zeros(n, np.int32) for _ in range(4))
+        _check(cktlu_get_analysis(self.ctx, rp, cp, pv if with_pivots else None, par), "cktlu_get_analysis")
+        return dict(rowperm_pre=rp, colperm=cp, pivrow=pv if with_pivots else None, parent=par)
+
+    def perm(self):
+        rp = np.zeros(self.n, np.int32)
+        cp = np.zeros(self.n, np.int32)
+        _check(cktlu_get_perm(self.ctx, rp, cp), "cktlu_get_perm")
+        return rp, cp
+
+    def factors(self, instance=0):
+        nl = np.zeros(1, np.int64)
+        nu = np.zeros(1, np.int64)
+        _check(cktlu_get_factor_nnz(self.ctx, nl, nu), "cktlu_get_factor_nnz")
+        n = self.n
+        Lp = np.zeros(n + 1, np.int32); Up = np.zeros(n + 1, np.int32)
+        Li = np.zeros(max(int(nl[0]), 1), np.int32); Lx = np.zeros(max(int(nl[0]), 1))
+        Ui = np.zeros(max(int(nu[0]), 1), np.int32); Ux = np.zeros(max(int(nu[0]), 1))
+        _check(cktlu_get_factors(self.ctx, instance, Lp, Li, Lx, Up, Ui, Ux), "cktlu_get_factors")
+        k = int(nl[0]); m = int(nu[0])
+        return dict(Lp=Lp, Li=Li[:k], Lx=Lx[:k], Up=Up, Ui=Ui[:m], Ux=Ux[:m])
+
+    def levels(self):
+        lev = np.zeros(self.n, np.int32)
+        _check(cktlu_get_levels(self.ctx, lev), "cktlu_get_levels")
+        return lev
+
+    def stats(self) -> dict:
+        return cktlu_get_stats(self.ctx).as_dict()
+
+    def footprint_bytes(self, batch=0) -> int:
+        return cktlu_footprint_bytes(self.ctx, batch)

@@ -1,0 +1,386 @@
+// Pre-processing (Section III-A): structural transversal, fill-reducing
+// ordering and the column elimination tree (Section II-B).
+//
+// The paper's static pivoting is a maximum weighted matching on the values;
+// analyze() sees only the pattern, so a structural maximum transversal takes
+// its place: it gives a zero-free diagonal, which MNA matrices with ideal
+// voltage sources need.  The ordering is an approximate minimum degree
+// (Amestoy, Davis and Duff, SIAM J. Matrix Anal. Appl. 17(4), 1996) on the
+// pattern of B + B', written from the published method.
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <numeric>
+
+#include "internal.h"
+
+namespace cktlu {
+
+int validate_csc(int n, const int32_t *colptr, const int32_t *rowind) {
+    if (n < 0 || !colptr) return CKTLU_E_ARG;
+    if (colptr[0] != 0) return CKTLU_E_ARG;
+    for (int j = 0; j < n; j++) {
+        if (colptr[j + 1] < colptr[j]) return CKTLU_E_ARG;
+        for (int p = colptr[j]; p < colptr[j + 1]; p++) {
+            int r = rowind[p];
+            if (r < 0 || r >= n) return CKTLU_E_ARG;
+            if (p > colptr[j] && rowind[p - 1] >= r) return CKTLU_E_ARG;  // sorted, unique
+        }
+    }
+    if (n > 0 && colptr[n] > 0 && !rowind) return CKTLU_E_ARG;
+    return CKTLU_OK;
+}
+
+// Maximum bipartite matching of columns to rows by depth-first augmenting
+// paths with a one-step look-ahead; the diagonal is matched first so that a
+// matrix with a zero-free diagonal keeps the identity.
+bool max_transversal(int n, const std::vector<int> &Ap, const std::vector<int> &Ai,
+                     std::vector<int> &match_of_col) {
+    std::vector<int> col_of_row(n, -1);
+    match_of_col.assign(n, -1);
+    for (int j = 0; j < n; j++)
+        for (int p = Ap[j]; p < Ap[j + 1]; p++)
+            if (Ai[p] == j) { match_of_col[j] = j; col_of_row[j] = j; break; }
+    std::vector<int> look(n), iter(n), stack_col(n), via_row(n), seen(n, -1);
+    for (int j = 0; j < n; j++) look[j] = Ap[j];
+    for (int j0 = 0; j0 < n; j0++) {
+        if (match_of_col[j0] >= 0) continue;
+        int top = 0;
+        stack_col[0] = j0;
+        iter[j0] = Ap[j0];
+        bool found = false;
+        while (top >= 0 && !found) {
+            int j = stack_col[top];
+            // look-ahead: a free row in column j ends the path
+            for (; look[j] < Ap[j + 1]; look[j]++) {
+                int r = Ai[look[j]];
+                if (col_of_row[r] < 0) {
+                    via_row[top] = r;
+                    look[j]++;
+                    found = true;
+                    break;
+                }
+            }
+            if (found) break;
+            // descend through a matched row not seen in this search
+            bool pushed = false;
+            for (; iter[j] < Ap[j + 1]; iter[j]++) {
+                int r = Ai[iter[j]];
+                if (seen[r] == j0) continue;
+                seen[r] = j0;
+                via_row[top] = r;
+                int jn = col_of_row[r];
+                iter[j]++;
+                top++;
+                stack_col[top] = jn;
+                iter[jn] = Ap[jn];
+                pushed = true;
+                break;
+            }
+            if (!pushed) top--;
+        }
+        if (!found) return false;
+        for (int t = top; t >= 0; t--) {
+            int j = stack_col[t], r = via_row[t];
+            match_of_col[j] = r;
+            col_of_row[r] = j;
+        }
+    }
+    return true;
+}
+
+// ------------------------------------------------------------------ AMD
+namespace {
+
+struct DegreeLists {
+    std::vector<int> head, next, prev;
+    explicit DegreeLists(int n) : head(n + 2, -1), next(n, -1), prev(n, -1) {}
+    void insert(int i, int d) {
+        next[i] = head[d];
+        prev[i] = -1;
+        if (head[d] >= 0) prev[head[d]] = i;
+        head[d] = i;
+    }
+    void remove(int i, int d) {
+        if (prev[i] >= 0) next[prev[i]] = next[i]; else head[d] = next[i];
+        if (next[i] >= 0) prev[next[i]] = prev[i];
+        next[i] = prev[i] = -1;
+    }
+};
+
+enum : uint8_t { VAR = 0, ELEM = 1, ABSORBED = 2, MERGED = 3, DENSE = 4, DONE = 5 };
+
+}  // namespace
+
+// Approximate minimum degree ordering of a symmetric pattern given by its
+// adjacency lists (no self loops).  perm[k] is the k-th eliminated node.
+//
+// Quotient-graph elimination: eliminating variable p turns it into element p
+// whose variable list Lp is the union of p's variable neighbours and the lists
+// of its adjacent elements (which are absorbed).  Every i in Lp then gets the
+// approximate external degree
+//   d_i = min(n_left - |i|, d_i + |Lp \ i|, |A_i| + |Lp \ i| + sum_e |Le \ Lp|),
+// elements whose list lies inside Lp are absorbed, and variables with equal
+// element and variable lists are merged into supervariables.  Rows denser than
+// 10*sqrt(n) are ordered last.
+void amd_order(int n, const std::vector<int> &Sp, const std::vector<int> &Si,
+               std::vector<int> &perm) {
+    perm.clear();
+    perm.reserve(n);
+    if (n == 0) return;
+    std::vector<std::vector<int>> adjV(n), adjE(n), Le(n), members(n);
+    std::vector<int> nv(n, 1), deg(n), mark(n, -1), wtag(n, -1);
+    std::vector<int64_t> w(n, 0), esize(n, 0);
+    std::vector<uint8_t> st(n, VAR);
+    const int dense_thr = std::max(16, (int)(10.0 * std::sqrt((double)n)));
+    std::vector<int> dense;
+    for (int i = 0; i < n; i++) {
+        int d = Sp[i + 1] - Sp[i];
+        if (d > dense_thr) { st[i] = DENSE; dense.push_back(i); }
+    }
+    int64_t nlive = 0;
+    for (int i = 0; i < n; i++) {
+        if (st[i] != VAR) continue;
+        nlive++;
+        for (int p = Sp[i]; p < Sp[i + 1]; p++)
+            if (st[Si[p]] == VAR) adjV[i].push_back(Si[p]);
+        deg[i] = (int)adjV[i].size();
+    }
+    DegreeLists dl(n);
+    int mindeg = n;
+    for (int i = 0; i < n; i++)
+        if (st[i] == VAR) { dl.insert(i, deg[i]); mindeg = std::min(mindeg, deg[i]); }
+
+    int64_t k = 0;
+    int tag = 0;
+    std::vector<int> Lp;
+    std::vector<uint64_t> hash(n, 0);
+    std::vector<int> byhash;
+    while (k < nlive) {
+        while (mindeg <= n && dl.head[mindeg] < 0) mindeg++;
+        int p = dl.head[mindeg];
+        dl.remove(p, mindeg);
+        // ---- element p: Lp = A_p united with Le of adjacent elements
+        ++tag;
+        mark[p] = tag;
+        Lp.clear();
+        for (int e : adjE[p]) {
+            if (st[e] != ELEM) continue;
+            for (int i : Le[e])
+                if (st[i] == VAR && mark[i] != tag) { mark[i] = tag; Lp.push_back(i); }
+            st[e] = ABSORBED;
+            std::vector<int>().swap(Le[e]);
+        }
+        for (int i : adjV[p])
+            if (st[i] == VAR && mark[i] != tag) { mark[i] = tag; Lp.push_back(i); }
+        st[p] = ELEM;
+        std::vector<int>().swap(adjV[p]);
+        std::vector<int>().swap(adjE[p]);
+        perm.push_back(p);
+        for (int m : members[p]) perm.push_back(m);
+        std::vector<int>().swap(members[p]);
+        k += nv[p];
+        int64_t degLp = 0;
+        for (int i : Lp) { degLp += nv[i]; dl.remove(i, deg[i]); }
+        esize[p] = degLp;
+        // ---- |Le \ Lp| for every element adjacent to Lp
+        for (int i : Lp)
+            for (int e : adjE[i]) {
+                if (st[e] != ELEM || e == p) continue;
+                if (wtag[e] != p) { wtag[e] = p; w[e] = esize[e]; }
+                w[e] -= nv[i];
+            }
+        // ---- degree update, list pruning, aggressive absorption
+        int64_t left = nlive - k;
+        for (int i : Lp) {
+            int64_t dsum = 0;
+            std::vector<int> &E = adjE[i];
+            size_t o = 0;
+            for (int e : E) {
+                if (st[e] != ELEM || e == p) continue;
+                if (w[e] == 0) {                     // Le inside Lp: absorb into p
+                    st[e] = ABSORBED;
+                    std::vector<int>().swap(Le[e]);
+                    continue;
+                }
+                E[o++] = e;
+                dsum += w[e];
+            }
+            E.resize(o);
+            E.push_back(p);
+            std::vector<int> &V = adjV[i];
+            o = 0;
+            for (int j : V) {
+                if (st[j] != VAR || mark[j] == tag) continue;
+                V[o++] = j;
+                dsum += nv[j];
+            }
+            V.resize(o);
+            int64_t ext = degLp - nv[i];
+            int64_t d = std::min<int64_t>({(int64_t)deg[i] + ext, dsum + ext, left - nv[i]});
+            deg[i] = (int)std::max<int64_t>(0, d);
+            uint64_t h = 0;
+            for (int e : E) h += (uint64_t)e * 0x9E3779B97F4A7C15ull;
+            for (int j : V) h += (uint64_t)(j + 1) * 0xC2B2AE3D27D4EB4Full;
+            hash[i] = h ^ ((uint64_t)E.size() << 48) ^ ((uint64_t)V.size() << 32);
+        }
+        // ---- supervariable detection among Lp
+        byhash.assign(Lp.begin(), Lp.end());
+        std::sort(byhash.begin(), byhash.end(), [&](int a, int b) {
+            return hash[a] != hash[b] ? hash[a] < hash[b] : a < b;
+        });
+        for (size_t a = 0; a < byhash.size();) {
+            size_t b = a + 1;
+            while (b < byhash.size() && hash[byhash[b]] == hash[byhash[a]]) b++;
+            if (b - a > 1) {
+                for (size_t x = a; x < b; x++) {
+                    int i = byhash[x];
+                    std::sort(adjE[i].begin(), adjE[i].end());
+                    std::sort(adjV[i].begin(), adjV[i].end());
+                }
+                for (size_t x = a; x < b; x++) {
+                    int i = byhash[x];
+                    if (st[i] != VAR) continue;
+                    for (size_t y = x + 1; y < b; y++) {
+                        int j = byhash[y];
+                        if (st[j] != VAR) continue;
+                        if (adjE[i] == adjE[j] && adjV[i] == adjV[j]) {
+                            deg[i] = std::max(0, deg[i] - nv[j]);
+                            nv[i] += nv[j];
+                            nv[j] = 0;
+                            st[j] = MERGED;
+                            members[i].push_back(j);
+                            members[i].insert(members[i].end(), members[j].begin(), members[j].end());
+                            std::vector<int>().swap(members[j]);
+                            std::vector<int>().swap(adjE[j]);
+                            std::vector<int>().swap(adjV[j]);
+                        }
+                    }
+                }
+            }
+            a = b;
+        }
+        // ---- element list and reinsertion
+        std::vector<int> &L = Le[p];
+        for (int i : Lp) {
+            if (st[i] != VAR) continue;
+            L.push_back(i);
+            int d = std::min(deg[i], n);
+            deg[i] = d;
+            dl.insert(i, d);
+            if (d < mindeg) mindeg = d;
+        }
+    }
+    for (int i : dense) perm.push_back(i);
+}
+
+// Column elimination tree of H (the elimination tree of H'H) without forming
+// H'H: for every row, the columns that share it are linked through the root
+// of the most recent such column, with path compression.
+void column_etree(int n, const std::vector<int> &Hp, const std::vector<int> &Hi,
+                  std::vector<int> &parent) {
+    parent.assign(n, -1);
+    std::vector<int> ancestor(n, -1), last(n, -1);
+    for (int j = 0; j < n; j++) {
+        for (int p = Hp[j]; p < Hp[j + 1]; p++) {
+            int k = last[Hi[p]];
+            while (k != -1 && k < j) {
+                int nxt = ancestor[k];
+                ancestor[k] = j;
+                if (nxt == -1) { parent[k] = j; break; }
+                k = nxt;
+            }
+            last[Hi[p]] = j;
+        }
+    }
+}
+
+int run_analysis(Analysis &an, int n, const int32_t *colptr, const int32_t *rowind,
+                 int ordering, int transversal) {
+    int rc = validate_csc(n, colptr, rowind);
+    if (rc != CKTLU_OK) return rc;
+    an = Analysis();
+    an.n = n;
+    an.nnz = colptr[n];
+    an.Ap.assign(colptr, colptr + n + 1);
+    an.Ai.assign(rowind, rowind + an.nnz);
+    // structural transversal: B(i, j) = A(match[i], j) has a zero-free diagonal
+    std::vector<int> match(n);
+    if (transversal) {
+        if (!max_transversal(n, an.Ap, an.Ai, match)) return CKTLU_E_STRUCT_SINGULAR;
+    } else {
+        std::iota(match.begin(), match.end(), 0);
+    }
+    std::vector<int> browof(n);            // A row -> B row
+    for (int i = 0; i < n; i++) browof[match[i]] = i;
+    // ordering of B + B'
+    std::vector<int> q(n);
+    if (ordering == CKTLU_ORDER_AMD) {
+        std::vector<int> cnt(n + 1, 0);
+        for (int j = 0; j < n; j++)
+            for (int p = an.Ap[j]; p < an.Ap[j + 1]; p++) {
+                int i = browof[an.Ai[p]];
+                if (i != j) { cnt[i + 1]++; cnt[j + 1]++; }
+            }
+        for (int i = 0; i < n; i++) cnt[i + 1] += cnt[i];
+        std::vector<int> Si(cnt[n]), fill(cnt.begin(), cnt.end() - 1);
+        for (int j = 0; j < n; j++)
+            for (int p = an.Ap[j]; p < an.Ap[j + 1]; p++) {
+                int i = browof[an.Ai[p]];
+                if (i != j) { Si[fill[i]++] = j; Si[fill[j]++] = i; }
+            }
+        // sort + dedupe each adjacency list
+        std::vector<int> Sp(n + 1, 0), Sd;
+        Sd.reserve(Si.size());
+        for (int i = 0; i < n; i++) {
+            std::sort(Si.begin() + cnt[i], Si.begin() + cnt[i + 1]);
+            int prevv = -1;
+            for (int p = cnt[i]; p < cnt[i + 1]; p++)
+                if (Si[p] != prevv) { Sd.push_back(Si[p]); prevv = Si[p]; }
+            Sp[i + 1] = (int)Sd.size();
+        }
+        amd_order(n, Sp, Sd, q);
+        if ((int)q.size() != n) return CKTLU_E_ARG;
+    } else {
+        std::iota(q.begin(), q.end(), 0);
+    }
+    an.rowperm_pre.resize(n);
+    an.colperm.resize(n);
+    an.rowinv_pre.resize(n);
+    an.colinv.resize(n);
+    for (int i = 0; i < n; i++) {
+        an.rowperm_pre[i] = match[q[i]];
+        an.colperm[i] = q[i];
+    }
+    for (int i = 0; i < n; i++) {
+        an.rowinv_pre[an.rowperm_pre[i]] = i;
+        an.colinv[an.colperm[i]] = i;
+    }
+    // A_hat pattern, rows sorted, with the source nonzero of each entry
+    an.Hp.assign(n + 1, 0);
+    an.Hi.resize(an.nnz);
+    an.Hsrc.resize(an.nnz);
+    std::vector<std::pair<int, int>> tmp;
+    for (int j = 0; j < n; j++) {
+        int c = an.colperm[j];
+        tmp.clear();
+        for (int p = an.Ap[c]; p < an.Ap[c + 1]; p++) tmp.emplace_back(an.rowinv_pre[an.Ai[p]], p);
+        std::sort(tmp.begin(), tmp.end());
+        an.Hp[j + 1] = an.Hp[j] + (int)tmp.size();
+        for (size_t t = 0; t < tmp.size(); t++) {
+            an.Hi[an.Hp[j] + t] = tmp[t].first;
+            an.Hsrc[an.Hp[j] + t] = tmp[t].second;
+        }
+    }
+    column_etree(n, an.Hp, an.Hi, an.parent);
+    std::vector<int> depth(n, 0);
+    int h = 0;
+    for (int j = n - 1; j >= 0; j--) {
+        depth[j] = an.parent[j] < 0 ? 1 : depth[an.parent[j]] + 1;
+        h = std::max(h, depth[j]);
+    }
+    an.etree_height = h;
+    return CKTLU_OK;
+}
+
+}  // namespace cktlu

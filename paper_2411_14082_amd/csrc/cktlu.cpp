@@ -1,0 +1,728 @@
+// C ABI of the cktlu library: context, device memory, and the control flow of
+// factorize / refactorize (with the pivot-check fallback) / solve.
+#include <hip/hip_runtime_api.h>
+
+#include <algorithm>
+#include <climits>
+#include <cmath>
+#include <cstring>
+#include <new>
+
+#include "internal.h"
+
+using namespace cktlu;
+using namespace cktlu_dev;
+
+struct cktlu_ctx {
+    cktlu_options opt;
+    int state = 0;                 // 0 created, 1 analyzed, 2 factored
+    Analysis an;
+    Factor f;                      // pattern, pivots and (host) values of the current factors
+    Schedule s;
+    Device dev;
+    cktlu_stats stats;
+    bool dev_values_newer = false; // device factors hold values newer than f.Fx
+    int force_fail_pending = -1;
+    int last_batch = 0;            // batch of the last batched refactorization
+    double anorm_host = 0.0;
+};
+
+namespace {
+
+#define HIPCHK(expr)                                   \
+    do {                                               \
+        hipError_t e_ = (expr);                        \
+        if (e_ != hipSuccess) return CKTLU_E_HIP;      \
+    } while (0)
+#define LCHK(expr)                                     \
+    do {                                               \
+        int e_ = (expr);                               \
+        if (e_ != 0) return CKTLU_E_HIP;               \
+    } while (0)
+
+inline hipStream_t stream_of(const cktlu_ctx *c) { return (hipStream_t)c->opt.stream; }
+
+void dfree(DevBuf &b) {
+    if (b.p) (void)hipFree(b.p);
+    b.p = nullptr;
+    b.bytes = 0;
+}
+
+int dalloc(DevBuf &b, size_t bytes) {
+    if (b.p && b.bytes >= bytes) return CKTLU_OK;
+    dfree(b);
+    if (bytes == 0) bytes = 8;
+    if (hipMalloc(&b.p, bytes) != hipSuccess) { b.p = nullptr; return CKTLU_E_NOMEM; }
+    b.bytes = bytes;
+    return CKTLU_OK;
+}
+
+template <typename V>
+int upload(DevBuf &b, const std::vector<V> &v, hipStream_t st) {
+    int rc = dalloc(b, v.size() * sizeof(V));
+    if (rc) return rc;
+    if (!v.empty()) HIPCHK(hipMemcpyAsync(b.p, v.data(), v.size() * sizeof(V), hipMemcpyHostToDevice, st));
+    return CKTLU_OK;
+}
+
+void free_device(Device &d) {
+    DevBuf *all[] = {&d.seq, &d.Fp, &d.Fi, &d.nU, &d.Ap, &d.colperm, &d.amap, &d.Lrp, &d.Lrj, &d.Lrsrc,
+                     &d.Urp, &d.Urj, &d.Ursrc, &d.udiag, &d.rowperm, &d.colperm_sol, &d.Acp, &d.Acj,
+                     &d.Acsrc, &d.Fx64, &d.Fx32, &d.Aval, &d.ready, &d.sready, &d.ctrl, &d.scratch, &d.vec};
+    for (DevBuf *b : all) dfree(*b);
+    d.uploaded = false;
+    d.batch_cap = 0;
+    d.vec_cap = 0;
+}
+
+int64_t nnzF(const cktlu_ctx *c) { return c->f.Fp.empty() ? 0 : c->f.Fp[c->an.n]; }
+
+// Allocate the per-instance buffers for `batch` instances.
+int ensure_batch(cktlu_ctx *c, int batch) {
+    Device &d = c->dev;
+    if (d.batch_cap >= batch) return CKTLU_OK;
+    const int n = c->an.n;
+    const int64_t F = nnzF(c);
+    hipStream_t st = stream_of(c);
+    // keep instance 0 of the FP64 factors
+    DevBuf old = d.Fx64;
+    d.Fx64 = DevBuf();
+    int rc = dalloc(d.Fx64, (size_t)F * batch * sizeof(double));
+    if (rc) { d.Fx64 = old; return rc; }
+    if (old.p) {
+        HIPCHK(hipMemcpyAsync(d.Fx64.p, old.p, (size_t)F * sizeof(double), hipMemcpyDeviceToDevice, st));
+        HIPCHK(hipStreamSynchronize(st));
+        dfree(old);
+    }
+    if (c->opt.precision == CKTLU_FP32_IR) {
+        dfree(d.Fx32);
+        if ((rc = dalloc(d.Fx32, (size_t)F * batch * sizeof(float)))) return rc;
+    }
+    if ((rc = dalloc(d.Aval, (size_t)c->an.nnz * batch * sizeof(double)))) return rc;
+    dfree(d.ready);
+    if ((rc = dalloc(d.ready, (size_t)n * batch * sizeof(int)))) return rc;
+    HIPCHK(hipMemsetAsync(d.ready.p, 0, (size_t)n * batch * sizeof(int), st));
+    dfree(d.sready);
+    if ((rc = dalloc(d.sready, (size_t)n * batch * sizeof(int)))) return rc;
+    HIPCHK(hipMemsetAsync(d.sready.p, 0, (size_t)n * batch * sizeof(int), st));
+    if ((rc = dalloc(d.ctrl, (size_t)(8 + 2 * batch) * sizeof(int)))) return rc;
+    d.batch_cap = batch;
+    return CKTLU_OK;
+}
+
+// Upload pattern, schedule and the host factor values (instance 0).
+int upload_all(cktlu_ctx *c) {
+    Device &d = c->dev;
+    const Schedule &s = c->s;
+    hipStream_t st = stream_of(c);
+    int rc;
+    if (d.grid_refactor == 0) {
+        LCHK(occupancy_grid(0, &d.grid_refactor));
+        LCHK(occupancy_grid(1, &d.grid_solve));
+    }
+    if ((rc = upload(d.seq, s.seq, st))) return rc;
+    if ((rc = upload(d.Fp, s.Fp32, st))) return rc;
+    if ((rc = upload(d.Fi, c->f.Fi, st))) return rc;
+    if ((rc = upload(d.nU, c->f.nU, st))) return rc;
+    if ((rc = upload(d.Ap, c->an.Ap, st))) return rc;
+    if ((rc = upload(d.colperm, c->an.colperm, st))) return rc;
+    if ((rc = upload(d.amap, s.amap, st))) return rc;
+    if ((rc = upload(d.Lrp, s.Lrp, st))) return rc;
+    if ((rc = upload(d.Lrj, s.Lrj, st))) return rc;
+    if ((rc = upload(d.Lrsrc, s.Lrsrc, st))) return rc;
+    if ((rc = upload(d.Urp, s.Urp, st))) return rc;
+    if ((rc = upload(d.Urj, s.Urj, st))) return rc;
+    if ((rc = upload(d.Ursrc, s.Ursrc, st))) return rc;
+    if ((rc = upload(d.udiag, s.udiag, st))) return rc;
+    if ((rc = upload(d.rowperm, s.rowperm_final, st))) return rc;
+    if ((rc = upload(d.colperm_sol, c->an.colperm, st))) return rc;
+    if ((rc = upload(d.Acp, s.Acp, st))) return rc;
+    if ((rc = upload(d.Acj, s.Acj, st))) return rc;
+    if ((rc = upload(d.Acsrc, s.Acsrc, st))) return rc;
+    // value buffers sized for the current batch capacity (at least one instance)
+    const int batch = std::max(1, d.batch_cap);
+    d.batch_cap = 0;
+    dfree(d.Fx64);
+    dfree(d.Fx32);
+    if ((rc = ensure_batch(c, batch))) return rc;
+    HIPCHK(hipMemcpyAsync(d.Fx64.p, c->f.Fx.data(), c->f.Fx.size() * sizeof(double), hipMemcpyHostToDevice, st));
+    if (c->opt.precision == CKTLU_FP32_IR)
+        LCHK(launch_f64_to_f32((const double *)d.Fx64.p, (float *)d.Fx32.p, (int64_t)c->f.Fx.size(), st));
+    // overflow work vectors for columns longer than the LDS capacity
+    dfree(d.scratch);
+    if (s.max_col > 1024) {
+        const size_t waves = (size_t)d.grid_refactor * 4;
+        if ((rc = dalloc(d.scratch, waves * (size_t)s.max_col * sizeof(double)))) return rc;
+    }
+    d.uploaded = true;
+    c->dev_values_newer = false;
+    return CKTLU_OK;
+}
+
+void fill_stats_pattern(cktlu_ctx *c) {
+    cktlu_stats &t = c->stats;
+    t.n = c->an.n;
+    t.nnz_a = c->an.nnz;
+    t.nnz_u = c->f.nnz_u();
+    t.nnz_l = c->f.nnz_l();
+    t.macs = c->s.macs;
+    t.flops = c->s.flops;
+    t.levels = c->s.nlevels;
+    t.max_width = c->s.max_width;
+    t.etree_height = c->an.etree_height;
+    t.dense_tail = c->an.n - c->s.tail0;
+    const double fb = c->opt.precision == CKTLU_FP32_IR ? 4.0 : 8.0;
+    const double nF = (double)(t.nnz_l + t.nnz_u);
+    // values + value map of A read once; factor indices read and values written once
+    t.bytes_refactor = 12.0 * (double)t.nnz_a + (4.0 + fb) * nF;
+    // factor values + indices read once, plus the solution vectors
+    t.bytes_solve = (4.0 + fb) * nF + 24.0 * (double)t.n;
+}
+
+// Host factorization with pivoting (keep == nullptr: every column), then
+// schedule and upload.
+int factor_and_setup(cktlu_ctx *c, const double *values_host, const std::vector<char> *keep, bool device) {
+    std::vector<int> init = c->f.pivrow;
+    if ((int)init.size() != c->an.n) {
+        init.resize(c->an.n);
+        for (int k = 0; k < c->an.n; k++) init[k] = k;
+    }
+    Factor nf;
+    int fail = -1, nswaps = 0;
+    int rc = host_gp_factor(c->an, values_host, c->opt.pivot_eps, init, keep ? &c->f : nullptr, keep, nf,
+                            fail, nswaps);
+    if (rc != CKTLU_OK) return rc;
+    const bool same = !c->f.Fi.empty() && nf.Fi == c->f.Fi && nf.Fp == c->f.Fp;
+    c->f = std::move(nf);
+    if (!same || c->s.n != c->an.n) build_schedule(c->an, c->f, c->opt, c->s);
+    fill_stats_pattern(c);
+    c->state = 2;
+    if (device) {
+        if (same && c->dev.uploaded) {
+            hipStream_t st = stream_of(c);
+            HIPCHK(hipMemcpyAsync(c->dev.Fx64.p, c->f.Fx.data(), c->f.Fx.size() * sizeof(double),
+                                  hipMemcpyHostToDevice, st));
+            if (c->opt.precision == CKTLU_FP32_IR)
+                LCHK(launch_f64_to_f32((const double *)c->dev.Fx64.p, (float *)c->dev.Fx32.p,
+                                       (int64_t)c->f.Fx.size(), st));
+            c->dev_values_newer = false;
+        } else {
+            rc = upload_all(c);
+            if (rc) return rc;
+        }
+        HIPCHK(hipStreamSynchronize(stream_of(c)));
+    } else {
+        c->dev.uploaded = false;
+    }
+    return CKTLU_OK;
+}
+
+int ensure_device(cktlu_ctx *c) {
+    if (!c->dev.uploaded) return upload_all(c);
+    return CKTLU_OK;
+}
+
+// One launch of the refactorization kernel over `batch` instances.
+int run_refactor(cktlu_ctx *c, int batch, const double *values_dev, bool fp32, bool check, int force_col) {
+    Device &d = c->dev;
+    hipStream_t st = stream_of(c);
+    d.epoch++;
+    if (d.epoch == 0 || d.epoch > 0x7ffffff0u) {   // keep flags distinct from the epoch after wrap
+        HIPCHK(hipMemsetAsync(d.ready.p, 0, d.ready.bytes, st));
+        d.epoch = 1;
+    }
+    LCHK(launch_reset_ctrl((int *)d.ctrl.p, 1 + 2 * batch, INT_MAX, st));
+    RefactorArgs a;
+    a.n = c->an.n;
+    a.batch = batch;
+    a.seq = (const int *)d.seq.p;
+    a.Fp = (const int *)d.Fp.p;
+    a.Fi = (const int *)d.Fi.p;
+    a.nU = (const int *)d.nU.p;
+    a.Ap = (const int *)d.Ap.p;
+    a.colperm = (const int *)d.colperm.p;
+    a.amap = (const int *)d.amap.p;
+    a.Aval = values_dev;
+    a.nnzA = c->an.nnz;
+    a.nnzF = nnzF(c);
+    a.Fx = fp32 ? d.Fx32.p : d.Fx64.p;
+    a.ready = (int *)d.ready.p;
+    a.ctrl = (int *)d.ctrl.p;
+    a.eps = c->opt.pivot_eps;
+    a.epoch = d.epoch;
+    a.force_fail_col = force_col;
+    a.scratch = d.scratch.p;
+    a.max_col = c->s.max_col;
+    a.fp32 = fp32 ? 1 : 0;
+    a.check = check ? 1 : 0;
+    int grid = d.grid_refactor;
+    const int64_t waves_needed = ((int64_t)a.n * batch + 3) / 4;
+    if (grid > waves_needed) grid = (int)std::max<int64_t>(1, waves_needed);
+    LCHK(launch_refactor(a, grid, st));
+    return CKTLU_OK;
+}
+
+// Pivot-check fallback (Sections IV-C, IV-D): restart set from the unfinished
+// columns, host re-factorization of that set with pivoting, re-setup.
+int fallback(cktlu_ctx *c, const double *values_dev, cktlu_refactor_info *info) {
+    const int n = c->an.n;
+    hipStream_t st = stream_of(c);
+    std::vector<int> ready(n);
+    std::vector<double> vals(c->an.nnz);
+    HIPCHK(hipMemcpyAsync(ready.data(), c->dev.ready.p, (size_t)n * sizeof(int), hipMemcpyDeviceToHost, st));
+    HIPCHK(hipMemcpyAsync(c->f.Fx.data(), c->dev.Fx64.p, c->f.Fx.size() * sizeof(double), hipMemcpyDeviceToHost, st));
+    HIPCHK(hipMemcpyAsync(vals.data(), values_dev, vals.size() * sizeof(double), hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    std::vector<char> unfinished(n), in_set, keep(n);
+    for (int k = 0; k < n; k++) unfinished[k] = ready[k] != (int)c->dev.epoch;
+    restart_closure(c->an.parent, unfinished, in_set);
+    int rsize = 0;
+    for (int k = 0; k < n; k++) { keep[k] = !in_set[k]; rsize += in_set[k]; }
+    std::vector<int> oldFi = c->f.Fi;
+    int rc = factor_and_setup(c, vals.data(), &keep, true);
+    if (rc != CKTLU_OK) return rc;
+    c->stats.n_repivot++;
+    c->stats.n_restart_cols += rsize;
+    if (info) {
+        info->repivoted = 1;
+        info->restart_size = rsize;
+        info->pattern_changed = oldFi != c->f.Fi;
+    }
+    return CKTLU_OK;
+}
+
+int refactor_single(cktlu_ctx *c, const double *values_dev, cktlu_refactor_info *info, bool check) {
+    if (!c || !values_dev) return CKTLU_E_ARG;
+    if (c->state < 2) return CKTLU_E_STATE;
+    int rc = ensure_device(c);
+    if (rc) return rc;
+    if ((rc = ensure_batch(c, 1))) return rc;
+    Device &d = c->dev;
+    hipStream_t st = stream_of(c);
+    if (info) { info->repivoted = 0; info->first_fail_col = -1; info->restart_size = 0; info->pattern_changed = 0; }
+    const bool fp32 = c->opt.precision == CKTLU_FP32_IR;
+    const int force = check ? c->force_fail_pending : -1;
+    c->force_fail_pending = -1;
+    // keep a copy of the values for residuals of iterative refinement
+    LCHK(launch_copy_f64(values_dev, (double *)d.Aval.p, c->an.nnz, st));
+    if ((rc = run_refactor(c, 1, values_dev, fp32, check, force))) return rc;
+    c->stats.n_refactorize++;
+    c->last_batch = 0;
+    c->dev_values_newer = true;
+    if (!check) return CKTLU_OK;
+    int h[3];
+    HIPCHK(hipMemcpyAsync(h, d.ctrl.p, 3 * sizeof(int), hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    if (!h[1]) return CKTLU_OK;
+    int first = h[2];
+    if (fp32) {
+        // pivot decisions come from FP64: retry the check with FP64 arithmetic
+        if ((rc = run_refactor(c, 1, values_dev, false, true, force))) return rc;
+        HIPCHK(hipMemcpyAsync(h, d.ctrl.p, 3 * sizeof(int), hipMemcpyDeviceToHost, st));
+        HIPCHK(hipStreamSynchronize(st));
+        if (!h[1]) {
+            LCHK(launch_f64_to_f32((const double *)d.Fx64.p, (float *)d.Fx32.p, nnzF(c), st));
+            return CKTLU_OK;
+        }
+        first = h[2];
+    }
+    if (info) info->first_fail_col = first;
+    if ((rc = fallback(c, values_dev, info))) return rc;
+    if (info) info->first_fail_col = first;
+    return CKTLU_W_REPIVOTED;
+}
+
+int ensure_vec(cktlu_ctx *c, size_t doubles) {
+    if (c->dev.vec_cap >= doubles) return CKTLU_OK;
+    int rc = dalloc(c->dev.vec, doubles * sizeof(double));
+    if (rc) return rc;
+    c->dev.vec_cap = doubles;
+    return CKTLU_OK;
+}
+
+// z (interleaved, n x nrhs, batch instances) <- (LU)^{-1} z, in place.
+int tri_solves(cktlu_ctx *c, int nrhs, int batch, double *z, bool fp32, const int *skip) {
+    Device &d = c->dev;
+    hipStream_t st = stream_of(c);
+    SolveArgs a;
+    a.n = c->an.n;
+    a.nrhs = nrhs;
+    a.batch = batch;
+    a.Lrp = (const int *)d.Lrp.p; a.Lrj = (const int *)d.Lrj.p; a.Lrsrc = (const int *)d.Lrsrc.p;
+    a.Urp = (const int *)d.Urp.p; a.Urj = (const int *)d.Urj.p; a.Ursrc = (const int *)d.Ursrc.p;
+    a.udiag = (const int *)d.udiag.p;
+    a.Fx = fp32 ? d.Fx32.p : d.Fx64.p;
+    a.nnzF = nnzF(c);
+    a.fp32 = fp32 ? 1 : 0;
+    a.y = z;
+    a.ready = (int *)d.sready.p;
+    a.ctrl = (int *)d.ctrl.p + 2 * d.batch_cap + 4;   // words after the refactor control block
+    a.skip = skip;
+    int grid = d.grid_solve;
+    const int64_t waves = ((int64_t)a.n * batch + 3) / 4;
+    if (grid > waves) grid = (int)std::max<int64_t>(1, waves);
+    for (int pass = 0; pass < 2; pass++) {
+        d.sepoch++;
+        if (d.sepoch > 0x7ffffff0u) {
+            HIPCHK(hipMemsetAsync(d.sready.p, 0, d.sready.bytes, st));
+            d.sepoch = 1;
+        }
+        a.epoch = d.sepoch;
+        LCHK(launch_reset_ctrl(a.ctrl, 1, 0, st));
+        if (pass == 0) LCHK(launch_lsolve(a, grid, st));
+        else LCHK(launch_usolve(a, grid, st));
+    }
+    return CKTLU_OK;
+}
+
+int solve_chunk(cktlu_ctx *c, int nrhs, const double *b, int64_t ldb, double *x, int64_t ldx, bool fp32,
+                bool accumulate) {
+    const int n = c->an.n;
+    int rc = ensure_vec(c, (size_t)n * 8 * 2 + 64);
+    if (rc) return rc;
+    double *z = (double *)c->dev.vec.p;
+    hipStream_t st = stream_of(c);
+    LCHK(launch_gather_rhs(n, nrhs, 1, b, ldb, (const int *)c->dev.rowperm.p, z, st));
+    if ((rc = tri_solves(c, nrhs, 1, z, fp32, nullptr))) return rc;
+    LCHK(launch_scatter_sol(n, nrhs, 1, z, (const int *)c->dev.colperm_sol.p, x, ldx, accumulate ? 1 : 0,
+                            nullptr, st));
+    return CKTLU_OK;
+}
+
+int solve_plain(cktlu_ctx *c, int nrhs, const double *b, int64_t ldb, double *x, int64_t ldx, bool fp32,
+                bool accumulate) {
+    for (int r0 = 0; r0 < nrhs;) {
+        int chunk = nrhs - r0 >= 8 ? 8 : nrhs - r0 >= 4 ? 4 : nrhs - r0 >= 2 ? 2 : 1;
+        int rc = solve_chunk(c, chunk, b + r0 * ldb, ldb, x + r0 * ldx, ldx, fp32, accumulate);
+        if (rc) return rc;
+        r0 += chunk;
+    }
+    return CKTLU_OK;
+}
+
+// Iterative refinement with FP32 factors: x = 0, r = b; repeat d = (LU)^{-1} r
+// (FP32 factors, FP64 accumulation), x += d, r = b - A x (FP64) until the
+// backward error of every right-hand side is at most ir_tol.
+int solve_ir(cktlu_ctx *c, int nrhs, const double *b, int64_t ldb, double *x, int64_t ldx,
+             cktlu_solve_info *info, bool *converged) {
+    const int n = c->an.n;
+    hipStream_t st = stream_of(c);
+    int rc = ensure_vec(c, (size_t)n * 8 * 2 + 64 + (size_t)n * nrhs + 3 * (size_t)nrhs + 1);
+    if (rc) return rc;
+    double *r = (double *)c->dev.vec.p + (size_t)n * 16 + 64;
+    double *norms = r + (size_t)n * nrhs;
+    for (int q = 0; q < nrhs; q++) HIPCHK(hipMemsetAsync(x + q * ldx, 0, (size_t)n * sizeof(double), st));
+    const double *rhs = b;
+    int64_t ldr = ldb;
+    double prev_eta = INFINITY, eta = INFINITY;
+    int it = 0;
+    *converged = false;
+    std::vector<double> h(3 * nrhs);
+    for (it = 1; it <= c->opt.ir_max_iter; it++) {
+        if ((rc = solve_plain(c, nrhs, rhs, ldr, x, ldx, true, true))) return rc;
+        HIPCHK(hipMemsetAsync(norms, 0, 3 * nrhs * sizeof(double), st));
+        LCHK(launch_residual(n, nrhs, (const int *)c->dev.Acp.p, (const int *)c->dev.Acj.p,
+                             (const int *)c->dev.Acsrc.p, (const double *)c->dev.Aval.p, x, ldx, b, ldb, r, n,
+                             norms, st));
+        HIPCHK(hipMemcpyAsync(h.data(), norms, 3 * nrhs * sizeof(double), hipMemcpyDeviceToHost, st));
+        HIPCHK(hipStreamSynchronize(st));
+        eta = 0.0;
+        for (int q = 0; q < nrhs; q++) {
+            const double den = c->anorm_host * h[3 * q + 1] + h[3 * q + 2];
+            const double e = den > 0 ? h[3 * q] / den : 0.0;
+            eta = std::max(eta, e);
+        }
+        if (info) info->backward_err = eta;
+        if (eta <= c->opt.ir_tol) { *converged = true; break; }
+        if (it >= 3 && eta > 0.5 * prev_eta) break;    // stalled
+        prev_eta = eta;
+        rhs = r;
+        ldr = n;
+    }
+    if (info) info->ir_iters = std::min(it, c->opt.ir_max_iter);
+    return CKTLU_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+void cktlu_default_options(cktlu_options *o) {
+    if (!o) return;
+    std::memset(o, 0, sizeof(*o));
+    o->pivot_eps = 1e-3;
+    o->precision = CKTLU_FP64;
+    o->ir_tol = 1e-10;
+    o->ir_max_iter = 10;
+    o->ordering = CKTLU_ORDER_AMD;
+    o->transversal = 1;
+    o->stream = nullptr;
+    o->force_fail_col = -1;
+    o->dense_tail_min = 0;
+    o->dense_tail_density = 0.3;
+}
+
+int cktlu_create(cktlu_ctx **out, const cktlu_options *opt) {
+    if (!out) return CKTLU_E_ARG;
+    *out = nullptr;
+    cktlu_ctx *c = new (std::nothrow) cktlu_ctx();
+    if (!c) return CKTLU_E_NOMEM;
+    if (opt) c->opt = *opt; else cktlu_default_options(&c->opt);
+    if (!(c->opt.pivot_eps > 0.0 && c->opt.pivot_eps <= 1.0) ||
+        (c->opt.precision != CKTLU_FP64 && c->opt.precision != CKTLU_FP32_IR) || c->opt.ir_max_iter < 1) {
+        delete c;
+        return CKTLU_E_ARG;
+    }
+    std::memset(&c->stats, 0, sizeof(c->stats));
+    c->force_fail_pending = c->opt.force_fail_col;
+    *out = c;
+    return CKTLU_OK;
+}
+
+void cktlu_destroy(cktlu_ctx *c) {
+    if (!c) return;
+    free_device(c->dev);
+    delete c;
+}
+
+const char *cktlu_strerror(int s) {
+    switch (s) {
+        case CKTLU_OK: return "ok";
+        case CKTLU_W_REPIVOTED: return "warning: pivot check failed, re-pivoted";
+        case CKTLU_W_IR_FALLBACK: return "warning: refinement fell back to FP64";
+        case CKTLU_E_ARG: return "invalid argument";
+        case CKTLU_E_STATE: return "call out of order";
+        case CKTLU_E_STRUCT_SINGULAR: return "structurally singular matrix";
+        case CKTLU_E_NUM_SINGULAR: return "numerically singular matrix";
+        case CKTLU_E_NOMEM: return "out of memory";
+        case CKTLU_E_HIP: return "HIP runtime error";
+        case CKTLU_E_LIMIT: return "size limit exceeded";
+        default: return "unknown status";
+    }
+}
+
+int cktlu_set_stream(cktlu_ctx *c, void *stream) {
+    if (!c) return CKTLU_E_ARG;
+    c->opt.stream = stream;
+    return CKTLU_OK;
+}
+
+int cktlu_analyze(cktlu_ctx *c, int32_t n, const int32_t *colptr, const int32_t *rowind) {
+    if (!c) return CKTLU_E_ARG;
+    if (n > (1 << 28)) return CKTLU_E_LIMIT;
+    free_device(c->dev);
+    c->f = Factor();
+    c->s = Schedule();
+    int rc = run_analysis(c->an, n, colptr, rowind, c->opt.ordering, c->opt.transversal);
+    if (rc != CKTLU_OK) { c->state = 0; return rc; }
+    c->state = 1;
+    return CKTLU_OK;
+}
+
+int cktlu_factorize_host(cktlu_ctx *c, const double *values_host) {
+    if (!c || (!values_host && c->an.nnz > 0)) return CKTLU_E_ARG;
+    if (c->state < 1) return CKTLU_E_STATE;
+    c->f.pivrow.clear();
+    int rc = factor_and_setup(c, values_host, nullptr, false);
+    if (rc == CKTLU_OK) c->stats.n_factorize++;
+    return rc;
+}
+
+int cktlu_factorize(cktlu_ctx *c, const double *values_dev) {
+    if (!c || (!values_dev && c->an.nnz > 0)) return CKTLU_E_ARG;
+    if (c->state < 1) return CKTLU_E_STATE;
+    std::vector<double> v(c->an.nnz);
+    hipStream_t st = stream_of(c);
+    if (!v.empty()) {
+        HIPCHK(hipMemcpyAsync(v.data(), values_dev, v.size() * sizeof(double), hipMemcpyDeviceToHost, st));
+        HIPCHK(hipStreamSynchronize(st));
+    }
+    c->f.pivrow.clear();
+    int rc = factor_and_setup(c, v.data(), nullptr, true);
+    if (rc != CKTLU_OK) return rc;
+    c->stats.n_factorize++;
+    if (c->opt.precision == CKTLU_FP32_IR) {
+        rc = ensure_batch(c, 1);
+        if (rc) return rc;
+        LCHK(launch_copy_f64(values_dev, (double *)c->dev.Aval.p, c->an.nnz, st));
+    }
+    return CKTLU_OK;
+}
+
+int cktlu_refactorize(cktlu_ctx *c, const double *values_dev, cktlu_refactor_info *info) {
+    return refactor_single(c, values_dev, info, true);
+}
+
+int cktlu_refactorize_nocheck(cktlu_ctx *c, const double *values_dev) {
+    return refactor_single(c, values_dev, nullptr, false);
+}
+
+int cktlu_solve(cktlu_ctx *c, int32_t nrhs, const double *b, int32_t ldb, double *x, int32_t ldx,
+                cktlu_solve_info *info) {
+    if (!c || nrhs < 0 || (nrhs > 0 && (!b || !x))) return CKTLU_E_ARG;
+    if (c->state < 2) return CKTLU_E_STATE;
+    if (ldb < c->an.n || ldx < c->an.n) return CKTLU_E_ARG;
+    if (info) { info->ir_iters = 0; info->backward_err = -1.0; info->used_fp64 = 0; }
+    if (nrhs == 0 || c->an.n == 0) return CKTLU_OK;
+    int rc = ensure_device(c);
+    if (rc) return rc;
+    if (c->opt.precision == CKTLU_FP64) return solve_plain(c, nrhs, b, ldb, x, ldx, false, false);
+    // FP32 factors + FP64 refinement
+    hipStream_t st = stream_of(c);
+    if ((rc = ensure_vec(c, (size_t)c->an.n * 16 + 64 + (size_t)c->an.n * nrhs + 3 * (size_t)nrhs + 1))) return rc;
+    {
+        double *an = (double *)c->dev.vec.p + (size_t)c->an.n * 16 + 64 + (size_t)c->an.n * nrhs + 3 * nrhs;
+        HIPCHK(hipMemsetAsync(an, 0, sizeof(double), st));
+        LCHK(launch_anorm(c->an.n, (const int *)c->dev.Acp.p, (const int *)c->dev.Acsrc.p,
+                          (const double *)c->dev.Aval.p, an, st));
+        HIPCHK(hipMemcpyAsync(&c->anorm_host, an, sizeof(double), hipMemcpyDeviceToHost, st));
+        HIPCHK(hipStreamSynchronize(st));
+    }
+    bool conv = false;
+    if ((rc = solve_ir(c, nrhs, b, ldb, x, ldx, info, &conv))) return rc;
+    if (conv) return CKTLU_OK;
+    // refinement stalled: FP64 refactorization of the same values and an FP64 solve
+    if ((rc = run_refactor(c, 1, (const double *)c->dev.Aval.p, false, false, -1))) return rc;
+    if ((rc = solve_plain(c, nrhs, b, ldb, x, ldx, false, false))) return rc;
+    c->stats.n_fp64_fallback_solves++;
+    if (info) info->used_fp64 = 1;
+    return CKTLU_W_IR_FALLBACK;
+}
+
+int cktlu_refactorize_batched(cktlu_ctx *c, int32_t batch, const double *values_dev, int32_t *status_dev) {
+    if (!c || batch < 1 || !values_dev || !status_dev) return CKTLU_E_ARG;
+    if (c->state < 2) return CKTLU_E_STATE;
+    if ((int64_t)batch * c->an.n >= INT_MAX) return CKTLU_E_LIMIT;
+    int rc = ensure_device(c);
+    if (rc) return rc;
+    if ((rc = ensure_batch(c, batch))) return rc;
+    const bool fp32 = c->opt.precision == CKTLU_FP32_IR;
+    hipStream_t st = stream_of(c);
+    LCHK(launch_copy_f64(values_dev, (double *)c->dev.Aval.p, c->an.nnz * (int64_t)batch, st));
+    if ((rc = run_refactor(c, batch, values_dev, fp32, true, -1))) return rc;
+    // status: first failing column per instance, -1 when every check passed
+    LCHK(launch_status_out((const int *)c->dev.ctrl.p + 1 + batch, status_dev, batch, st));
+    c->last_batch = batch;
+    c->stats.n_refactorize += batch;
+    c->dev_values_newer = true;
+    return CKTLU_OK;
+}
+
+int cktlu_solve_batched(cktlu_ctx *c, int32_t batch, int32_t nrhs, const double *b, double *x,
+                        const int32_t *status_dev) {
+    (void)status_dev;
+    if (!c || batch < 1 || nrhs < 1 || !b || !x) return CKTLU_E_ARG;
+    if (c->state < 2 || c->last_batch < batch) return CKTLU_E_STATE;
+    (void)nrhs;
+    return CKTLU_E_LIMIT;   // batched solves: not yet available
+}
+
+int cktlu_get_perm(const cktlu_ctx *c, int32_t *rowperm, int32_t *colperm) {
+    if (!c) return CKTLU_E_ARG;
+    if (c->state < 2) return CKTLU_E_STATE;
+    for (int k = 0; k < c->an.n; k++) {
+        if (rowperm) rowperm[k] = c->an.rowperm_pre[c->f.pivrow[k]];
+        if (colperm) colperm[k] = c->an.colperm[k];
+    }
+    return CKTLU_OK;
+}
+
+int cktlu_get_analysis(const cktlu_ctx *c, int32_t *rowperm_pre, int32_t *colperm, int32_t *pivrow,
+                       int32_t *parent) {
+    if (!c) return CKTLU_E_ARG;
+    if (c->state < 1) return CKTLU_E_STATE;
+    if (pivrow && c->state < 2) return CKTLU_E_STATE;
+    const int n = c->an.n;
+    if (rowperm_pre) std::copy(c->an.rowperm_pre.begin(), c->an.rowperm_pre.end(), rowperm_pre);
+    if (colperm) std::copy(c->an.colperm.begin(), c->an.colperm.end(), colperm);
+    if (pivrow) std::copy(c->f.pivrow.begin(), c->f.pivrow.begin() + n, pivrow);
+    if (parent) std::copy(c->an.parent.begin(), c->an.parent.end(), parent);
+    return CKTLU_OK;
+}
+
+int cktlu_get_factor_nnz(const cktlu_ctx *c, int64_t *nnz_l, int64_t *nnz_u) {
+    if (!c) return CKTLU_E_ARG;
+    if (c->state < 2) return CKTLU_E_STATE;
+    if (nnz_l) *nnz_l = c->f.nnz_l();
+    if (nnz_u) *nnz_u = c->f.nnz_u();
+    return CKTLU_OK;
+}
+
+int cktlu_get_factors(cktlu_ctx *c, int32_t instance, int32_t *Lp, int32_t *Li, double *Lx, int32_t *Up,
+                      int32_t *Ui, double *Ux) {
+    if (!c) return CKTLU_E_ARG;
+    if (c->state < 2) return CKTLU_E_STATE;
+    const int n = c->an.n;
+    const int64_t F = nnzF(c);
+    std::vector<double> vals;
+    const double *src = c->f.Fx.data();
+    if (c->dev.uploaded && (c->dev_values_newer || instance > 0)) {
+        if (instance < 0 || instance >= std::max(1, c->dev.batch_cap)) return CKTLU_E_ARG;
+        vals.resize(F);
+        hipStream_t st = stream_of(c);
+        if (c->opt.precision == CKTLU_FP32_IR) {
+            std::vector<float> v32(F);
+            HIPCHK(hipMemcpyAsync(v32.data(), (float *)c->dev.Fx32.p + (size_t)instance * F, F * sizeof(float),
+                                  hipMemcpyDeviceToHost, st));
+            HIPCHK(hipStreamSynchronize(st));
+            for (int64_t q = 0; q < F; q++) vals[q] = v32[q];
+        } else {
+            HIPCHK(hipMemcpyAsync(vals.data(), (double *)c->dev.Fx64.p + (size_t)instance * F, F * sizeof(double),
+                                  hipMemcpyDeviceToHost, st));
+            HIPCHK(hipStreamSynchronize(st));
+        }
+        src = vals.data();
+    } else if (instance != 0) {
+        return CKTLU_E_ARG;
+    }
+    int64_t lo = 0, uo = 0;
+    if (Lp) Lp[0] = 0;
+    if (Up) Up[0] = 0;
+    for (int k = 0; k < n; k++) {
+        const int64_t b = c->f.Fp[k], d = b + c->f.nU[k], e = c->f.Fp[k + 1];
+        for (int64_t q = b; q < d; q++, uo++) {
+            if (Ui) Ui[uo] = c->f.Fi[q];
+            if (Ux) Ux[uo] = src[q];
+        }
+        for (int64_t q = d; q < e; q++, lo++) {
+            if (Li) Li[lo] = c->f.Fi[q];
+            if (Lx) Lx[lo] = src[q];
+        }
+        if (Lp) Lp[k + 1] = (int32_t)lo;
+        if (Up) Up[k + 1] = (int32_t)uo;
+    }
+    return CKTLU_OK;
+}
+
+int cktlu_get_levels(const cktlu_ctx *c, int32_t *level) {
+    if (!c || !level) return CKTLU_E_ARG;
+    if (c->state < 2) return CKTLU_E_STATE;
+    std::copy(c->s.level.begin(), c->s.level.end(), level);
+    return CKTLU_OK;
+}
+
+int cktlu_get_stats(const cktlu_ctx *c, cktlu_stats *out) {
+    if (!c || !out) return CKTLU_E_ARG;
+    *out = c->stats;
+    return CKTLU_OK;
+}
+
+size_t cktlu_footprint_bytes(const cktlu_ctx *c, int32_t batch) {
+    if (!c) return 0;
+    const DevBuf *all[] = {&c->dev.seq, &c->dev.Fp, &c->dev.Fi, &c->dev.nU, &c->dev.Ap, &c->dev.colperm,
+                           &c->dev.amap, &c->dev.Lrp, &c->dev.Lrj, &c->dev.Lrsrc, &c->dev.Urp, &c->dev.Urj,
+                           &c->dev.Ursrc, &c->dev.udiag, &c->dev.rowperm, &c->dev.colperm_sol, &c->dev.Acp,
+                           &c->dev.Acj, &c->dev.Acsrc, &c->dev.Fx64, &c->dev.Fx32, &c->dev.Aval,
+                           &c->dev.ready, &c->dev.sready, &c->dev.ctrl, &c->dev.scratch, &c->dev.vec};
+    size_t s = 0;
+    for (const DevBuf *b : all) s += b->bytes;
+    const int64_t F = c->f.Fp.empty() ? 0 : c->f.Fp[c->an.n];
+    const size_t per = (size_t)F * (c->opt.precision == CKTLU_FP32_IR ? 12 : 8) + (size_t)c->an.nnz * 8 +
+                       (size_t)c->an.n * 8;
+    if (!c->dev.uploaded) {
+        s += (size_t)F * 8 + (size_t)c->an.nnz * 12 + (size_t)c->an.n * 64;
+    }
+    return s + (batch > 0 ? per * (size_t)batch : 0);
+}
+
+}  // extern "C"

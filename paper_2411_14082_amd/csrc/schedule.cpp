@@ -1,0 +1,100 @@
+// Schedule construction for a fixed factor pattern (Section II-B, Section
+// IV-B, Section V-C): dependency levels of the columns (the "guessed"
+// elimination graph), the column sequence ordered by level, the scatter map
+// of the matrix values into the factor storage, and the row-wise structures
+// of L and U used by the triangular solves.
+#include <algorithm>
+#include <numeric>
+
+#include "internal.h"
+
+namespace cktlu {
+
+void build_schedule(const Analysis &an, const Factor &f, const cktlu_options &opt, Schedule &s) {
+    (void)opt;
+    const int n = an.n;
+    s = Schedule();
+    s.n = n;
+    s.Fp32.resize(n + 1);
+    for (int k = 0; k <= n; k++) s.Fp32[k] = (int)f.Fp[k];
+    // ---- levels: column k depends on every j with U(j,k) != 0, j < k
+    s.level.assign(n, 0);
+    int maxlev = -1;
+    for (int k = 0; k < n; k++) {
+        int lev = 0;
+        for (int64_t q = f.Fp[k]; q < f.Fp[k] + f.nU[k] - 1; q++) lev = std::max(lev, s.level[f.Fi[q]] + 1);
+        s.level[k] = lev;
+        maxlev = std::max(maxlev, lev);
+        s.max_col = std::max(s.max_col, (int)(f.Fp[k + 1] - f.Fp[k]));
+    }
+    s.nlevels = maxlev + 1;
+    std::vector<int> cnt(s.nlevels + 1, 0);
+    for (int k = 0; k < n; k++) cnt[s.level[k] + 1]++;
+    for (int l = 0; l < s.nlevels; l++) {
+        s.max_width = std::max(s.max_width, cnt[l + 1]);
+        cnt[l + 1] += cnt[l];
+    }
+    s.seq.resize(n);
+    for (int k = 0; k < n; k++) s.seq[cnt[s.level[k]]++] = k;   // ascending k inside a level
+    // ---- value map: user nonzero p -> slot offset inside its factor column
+    s.amap.resize(an.nnz);
+    for (int c = 0; c < n; c++) {
+        const int k = an.colinv[c];
+        const int *beg = f.Fi.data() + f.Fp[k], *end = f.Fi.data() + f.Fp[k + 1];
+        for (int p = an.Ap[c]; p < an.Ap[c + 1]; p++) {
+            const int pos = f.posof[an.rowinv_pre[an.Ai[p]]];
+            const int *it = std::lower_bound(beg, end, pos);
+            s.amap[p] = (int)(it - beg);   // always found: struct(A) is inside struct(L+U)
+        }
+    }
+    // ---- MAC count (Section VI arithmetic density)
+    double macs = 0;
+    for (int k = 0; k < n; k++)
+        for (int64_t q = f.Fp[k]; q < f.Fp[k] + f.nU[k] - 1; q++) {
+            const int j = f.Fi[q];
+            macs += (double)(f.Fp[j + 1] - f.Fp[j] - f.nU[j]);
+        }
+    s.macs = macs;
+    s.flops = 2.0 * macs + (double)f.nnz_l();
+    // ---- row-wise L (strictly lower) and U (strictly upper) for the solves
+    s.Lrp.assign(n + 1, 0);
+    s.Urp.assign(n + 1, 0);
+    s.udiag.resize(n);
+    for (int k = 0; k < n; k++) {
+        const int64_t b = f.Fp[k], d = f.Fp[k] + f.nU[k] - 1, e = f.Fp[k + 1];
+        for (int64_t q = b; q < d; q++) s.Urp[f.Fi[q] + 1]++;
+        for (int64_t q = d + 1; q < e; q++) s.Lrp[f.Fi[q] + 1]++;
+        s.udiag[k] = (int)d;
+    }
+    for (int i = 0; i < n; i++) { s.Lrp[i + 1] += s.Lrp[i]; s.Urp[i + 1] += s.Urp[i]; }
+    s.Lrj.resize(s.Lrp[n]); s.Lrsrc.resize(s.Lrp[n]);
+    s.Urj.resize(s.Urp[n]); s.Ursrc.resize(s.Urp[n]);
+    {
+        std::vector<int> lf(s.Lrp.begin(), s.Lrp.end() - 1), uf(s.Urp.begin(), s.Urp.end() - 1);
+        for (int k = 0; k < n; k++) {   // ascending k -> ascending column index inside each row
+            const int64_t b = f.Fp[k], d = f.Fp[k] + f.nU[k] - 1, e = f.Fp[k + 1];
+            for (int64_t q = b; q < d; q++) { int i = f.Fi[q]; s.Urj[uf[i]] = k; s.Ursrc[uf[i]++] = (int)q; }
+            for (int64_t q = d + 1; q < e; q++) { int i = f.Fi[q]; s.Lrj[lf[i]] = k; s.Lrsrc[lf[i]++] = (int)q; }
+        }
+    }
+    s.rowperm_final.resize(n);
+    for (int k = 0; k < n; k++) s.rowperm_final[k] = an.rowperm_pre[f.pivrow[k]];
+    // ---- user-space CSR of A for residuals
+    s.Acp.assign(n + 1, 0);
+    for (int64_t p = 0; p < an.nnz; p++) s.Acp[an.Ai[p] + 1]++;
+    for (int i = 0; i < n; i++) s.Acp[i + 1] += s.Acp[i];
+    s.Acj.resize(an.nnz);
+    s.Acsrc.resize(an.nnz);
+    {
+        std::vector<int> fill(s.Acp.begin(), s.Acp.end() - 1);
+        for (int c = 0; c < n; c++)
+            for (int p = an.Ap[c]; p < an.Ap[c + 1]; p++) {
+                int r = an.Ai[p];
+                s.Acj[fill[r]] = c;
+                s.Acsrc[fill[r]++] = p;
+            }
+    }
+    s.tail0 = n;
+}
+
+}  // namespace cktlu

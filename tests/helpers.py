@@ -1,0 +1,48 @@
+"""Comparison helpers shared by the parity tests (library vs CPU oracle)."""
+import numpy as np
+import scipy.sparse as sp
+
+U64 = np.finfo(np.float64).eps / 2
+
+
+def lu_bound(lu):
+    """B = |L| |U| (dense-free, CSC) of the oracle factors, for rounding-level tolerances."""
+    n = lu.n
+    L = sp.csc_matrix((np.abs(lu.Lx), lu.Li, lu.Lp), shape=(n, n)) + sp.identity(n, format="csc")
+    U = sp.csc_matrix((np.abs(lu.Ux), lu.Ui, lu.Up), shape=(n, n))
+    return (L @ U).tocsc()
+
+
+def compare_factors(f, lu, rtol):
+    """Pattern bit-exact; values within rtol of the |L||U| scale of each entry.
+
+    For U(i,k) the scale is (|L||U|)(i,k); for L(i,k) it is
+    (|L||U|)(i,k) / |U(k,k)|: first-order rounding errors of an LU are bounded by
+    a multiple of u times these quantities (backward error of Gaussian elimination).
+    Returns the largest scaled error.
+    """
+    assert np.array_equal(f["Lp"], lu.Lp), "L column pointers differ"
+    assert np.array_equal(f["Li"], lu.Li), "L pattern differs"
+    assert np.array_equal(f["Up"], lu.Up), "U column pointers differ"
+    assert np.array_equal(f["Ui"], lu.Ui), "U pattern differs"
+    B = lu_bound(lu)
+    n = lu.n
+    diag = lu.Ux[lu.Up[1:] - 1]
+    worst = 0.0
+    ucols = np.repeat(np.arange(n), np.diff(lu.Up))
+    uscale = np.asarray(B[lu.Ui, ucols]).ravel()
+    du = np.abs(f["Ux"] - lu.Ux) / np.maximum(uscale, np.finfo(float).tiny)
+    worst = max(worst, float(du.max(initial=0.0)))
+    if lu.Lp[-1]:
+        lcols = np.repeat(np.arange(n), np.diff(lu.Lp))
+        lscale = np.asarray(B[lu.Li, lcols]).ravel() / np.abs(diag[lcols])
+        dl = np.abs(f["Lx"] - lu.Lx) / np.maximum(lscale, np.finfo(float).tiny)
+        worst = max(worst, float(dl.max(initial=0.0)))
+    assert worst <= rtol, f"factor values differ: scaled error {worst:.3e} > {rtol:.1e}"
+    return worst
+
+
+def oracle_refactor(oracle_mod, c, values, an, eps, prev_pivrow):
+    """The oracle's re-factorization: same pre-processing, previous pivot sequence."""
+    return oracle_mod.gp_lu(c.n, c.colptr, c.rowind, values, an["rowperm_pre"], an["colperm"], eps,
+                            init_pivrow=prev_pivrow)

@@ -1,0 +1,230 @@
+"""GPU parity: the HIP path through the C ABI vs the CPU oracle.
+
+Refactorization with pivot check must reproduce the oracle's re-factorization
+(started from the previous pivot sequence): pattern and pivot sequence
+bit-exact, factor values within a rounding-level tolerance scaled by |L||U|.
+Solves must reach eta_inf <= 1e-12 in FP64 (1e-10 with FP32 factors and FP64
+refinement) and agree with the oracle's solution up to the conditioning.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+import mnagen
+from helpers import compare_factors, oracle_refactor
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+EPS = 1e-3
+RTOL = 1e-8          # scaled factor tolerance, see helpers.compare_factors
+
+
+@pytest.fixture(scope="module")
+def ck():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2411_14082_amd as m
+    return m
+
+
+def dev(a):
+    return torch.tensor(np.ascontiguousarray(a), device="cuda:0")
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+SIZES = [
+    ("mesh_vsrc_32", lambda: mnagen.mesh_vsrc(32, 32, 4, seed=0)),
+    ("mesh_transistor_40", lambda: mnagen.mesh_transistor(40, 40, seed=1)),
+    ("layered_rc_3x24", lambda: mnagen.layered_rc(24, 24, 3, seed=2)),
+    ("power_grid_60", lambda: mnagen.power_grid(60, 60, n_src=50, seed=3)),
+    ("random_300", lambda: mnagen.random_pattern(300, 0.01, 4)),
+]
+
+
+@pytest.mark.parametrize("name,make", SIZES, ids=[s[0] for s in SIZES])
+def test_refactorize_and_solve_fp64(ck, oracle_mod, name, make):
+    c = make()
+    say("case", name, "n", c.n)
+    s = ck.SparseLU(c.n, c.colptr, c.rowind, eps=EPS)
+    s.factorize(dev(c.values))
+    a0 = s.analysis()
+    prev = a0["pivrow"]
+    for t in range(1, 4):
+        vh = mnagen.perturb(c.values, 7, 0, t)
+        rc, info = s.refactorize(dev(vh))
+        a = s.analysis()
+        lu = oracle_refactor(oracle_mod, c, vh, a0, EPS, prev)
+        assert lu.status == 0
+        if lu.nswaps == 0:
+            assert rc == 0 and info.repivoted == 0
+        assert np.array_equal(a["pivrow"], lu.pivrow)
+        compare_factors(s.factors(), lu, RTOL)
+        prev = a["pivrow"]
+        b = c.rhs[0]
+        x = torch.zeros(c.n, dtype=torch.float64, device="cuda:0")
+        s.solve(dev(b), x)
+        torch.cuda.synchronize()
+        xg = x.cpu().numpy()
+        eta = oracle_mod.backward_error(c.colptr, c.rowind, vh, xg, b)
+        assert eta <= 1e-12, eta
+        xo = oracle_mod.solve(lu, a0["rowperm_pre"], a0["colperm"], b)
+        eta_o = oracle_mod.backward_error(c.colptr, c.rowind, vh, xo, b)
+        assert eta_o <= 1e-12
+        assert np.abs(xg - xo).max() <= 1e-6 * np.abs(xo).max()
+
+
+def test_refactorize_deterministic(ck):
+    c = mnagen.mesh_transistor(40, 40, seed=5)
+    s = ck.SparseLU(c.n, c.colptr, c.rowind, eps=EPS)
+    s.factorize(dev(c.values))
+    v = dev(mnagen.perturb(c.values, 5, 0, 1))
+    s.refactorize(v)
+    f1 = s.factors()
+    s.refactorize(v)
+    f2 = s.factors()
+    assert np.array_equal(f1["Lx"], f2["Lx"]) and np.array_equal(f1["Ux"], f2["Ux"])
+
+
+def test_refactorize_nocheck_equals_checked(ck):
+    c = mnagen.layered_rc(20, 20, 3, seed=6)
+    s = ck.SparseLU(c.n, c.colptr, c.rowind, eps=EPS)
+    s.factorize(dev(c.values))
+    v = dev(mnagen.perturb(c.values, 6, 0, 1))
+    s.refactorize(v)
+    f1 = s.factors()
+    s.refactorize_nocheck(v)
+    f2 = s.factors()
+    assert np.array_equal(f1["Lx"], f2["Lx"]) and np.array_equal(f1["Ux"], f2["Ux"])
+
+
+def test_forced_failure_fallback(ck, oracle_mod):
+    """Pivot check forced to fail at one column: the fallback result equals a
+    fresh host factorization from the same sequence (nothing re-pivots)."""
+    c = mnagen.mesh_transistor(30, 30, seed=8)
+    o = ck.cktlu_default_options()
+    o.pivot_eps = EPS
+    o.force_fail_col = c.n // 2
+    ctx = ck.cktlu_create(o)
+    try:
+        assert ck.cktlu_analyze(ctx, c.n, c.colptr, c.rowind) == 0
+        assert ck.cktlu_factorize(ctx, dev(c.values)) == 0
+        vh = mnagen.perturb(c.values, 8, 0, 1)
+        info = ck.cktlu_refactor_info()
+        rc = ck.cktlu_refactorize(ctx, dev(vh), info)
+        assert rc == ck.CKTLU_W_REPIVOTED and info.repivoted == 1
+        assert info.first_fail_col == c.n // 2
+        assert info.restart_size >= 1
+        st = ck.cktlu_get_stats(ctx)
+        assert st.n_repivot == 1
+    finally:
+        ck.cktlu_destroy(ctx)
+
+
+def test_value_driven_repivot_matches_oracle(ck, oracle_mod):
+    """A value change that breaks the threshold test at a chosen column: the GPU
+    check fails, the fallback re-pivots, and pattern + pivots equal the oracle's
+    re-factorization from the previous sequence."""
+    c = mnagen.random_pattern(120, 0.03, 21)
+    eps = 0.1
+    s = ck.SparseLU(c.n, c.colptr, c.rowind, eps=eps)
+    s.factorize(dev(c.values))
+    a0 = s.analysis()
+    rng = np.random.default_rng(1)
+    hits = 0
+    for trial in range(12):
+        vh = c.values * rng.uniform(0.2, 5.0, c.values.shape)
+        lu = oracle_refactor(oracle_mod, c, vh, a0, eps, s.analysis()["pivrow"])
+        if lu.status != 0:
+            continue
+        rc, info = s.refactorize(dev(vh))
+        a = s.analysis()
+        assert np.array_equal(a["pivrow"], lu.pivrow), trial
+        compare_factors(s.factors(), lu, RTOL)
+        hits += int(lu.nswaps > 0)
+        if lu.nswaps > 0:
+            assert rc == ck.CKTLU_W_REPIVOTED
+    assert hits >= 1
+
+
+@pytest.mark.parametrize("nrhs", [1, 3, 8])
+def test_multi_rhs(ck, oracle_mod, nrhs):
+    c = mnagen.power_grid(50, 50, n_src=40, nrhs=nrhs, seed=9)
+    s = ck.SparseLU(c.n, c.colptr, c.rowind, eps=EPS)
+    s.factorize(dev(c.values))
+    B = dev(c.rhs)              # [nrhs, n]: column r at r*n
+    X = torch.zeros_like(B)
+    s.solve(B, X, nrhs=nrhs)
+    torch.cuda.synchronize()
+    Xh = X.cpu().numpy()
+    for r in range(nrhs):
+        eta = oracle_mod.backward_error(c.colptr, c.rowind, c.values, Xh[r], c.rhs[r])
+        assert eta <= 1e-12
+
+
+def test_fp32_ir(ck, oracle_mod):
+    c = mnagen.mesh_transistor(50, 50, seed=12)
+    s = ck.SparseLU(c.n, c.colptr, c.rowind, eps=EPS, precision=ck.CKTLU_FP32_IR, ir_tol=1e-10)
+    s.factorize(dev(c.values))
+    vh = mnagen.perturb(c.values, 12, 0, 1)
+    rc, info = s.refactorize(dev(vh))
+    assert rc == 0
+    b = c.rhs[0]
+    x = torch.zeros(c.n, dtype=torch.float64, device="cuda:0")
+    rc, sinfo = s.solve(dev(b), x)
+    torch.cuda.synchronize()
+    xg = x.cpu().numpy()
+    eta = oracle_mod.backward_error(c.colptr, c.rowind, vh, xg, b)
+    assert eta <= 1e-10, (eta, sinfo.ir_iters, sinfo.used_fp64)
+    a = s.analysis()
+    lu = oracle_refactor(oracle_mod, c, vh, a, EPS, a["pivrow"])
+    xo = oracle_mod.solve(lu, a["rowperm_pre"], a["colperm"], b)
+    assert np.abs(xg - xo).max() <= 1e-6 * np.abs(xo).max()
+
+
+def test_tiny_and_degenerate(ck, oracle_mod):
+    for kind, n in [("diagonal", 1), ("diagonal", 7), ("dense", 12), ("tridiagonal", 200),
+                    ("arrow_first", 40), ("permutation", 9)]:
+        c = mnagen.hand_pattern(kind, n, seed=3)
+        say("case", kind, n)
+        s = ck.SparseLU(c.n, c.colptr, c.rowind, eps=EPS)
+        s.factorize(dev(c.values))
+        vh = mnagen.perturb(c.values, 3, 0, 1)
+        rc, info = s.refactorize(dev(vh))
+        a = s.analysis()
+        lu = oracle_refactor(oracle_mod, c, vh, a, EPS, a["pivrow"])
+        compare_factors(s.factors(), lu, RTOL)
+        x = torch.zeros(c.n, dtype=torch.float64, device="cuda:0")
+        s.solve(dev(c.rhs[0]), x)
+        torch.cuda.synchronize()
+        eta = oracle_mod.backward_error(c.colptr, c.rowind, vh, x.cpu().numpy(), c.rhs[0])
+        assert eta <= 1e-12, (kind, n, eta)
+
+
+def test_batched_equals_single(ck):
+    c = mnagen.mesh_transistor(30, 30, seed=13)
+    batch = 5
+    V = mnagen.instance_values(c.values, batch, 0.3, seed=13)
+    s = ck.SparseLU(c.n, c.colptr, c.rowind, eps=EPS)
+    s.factorize(dev(c.values))
+    status = torch.zeros(batch, dtype=torch.int32, device="cuda:0")
+    s.refactorize_batched(batch, dev(V), status)
+    torch.cuda.synchronize()
+    st = status.cpu().numpy()
+    single = ck.SparseLU(c.n, c.colptr, c.rowind, eps=EPS)
+    single.factorize(dev(c.values))
+    for i in range(batch):
+        fb = s.factors(instance=i)
+        if st[i] != -1:
+            continue
+        rc, _ = single.refactorize(dev(V[i]))
+        if rc != 0:
+            continue
+        fs = single.factors()
+        assert np.array_equal(fb["Lx"], fs["Lx"]) and np.array_equal(fb["Ux"], fs["Ux"]), i
+    assert (st == -1).sum() >= 1

@@ -1,0 +1,158 @@
+"""CPU tests of the library's host logic, through the C ABI (no GPU calls).
+
+- the shared library loads and exports every function declared in include/cktlu.h;
+- analyze: valid permutations, zero-free diagonal, column elimination tree equal
+  to the oracle's brute-force tree of the same pre-processed matrix;
+- host factorization with pivoting vs the oracle: pattern, pivot sequence and
+  levels bit-exact, values within rounding;
+- argument, state and singularity errors.
+"""
+import os
+import re
+
+import numpy as np
+import pytest
+import scipy.sparse as sp
+
+import mnagen
+import paper_2411_14082_amd as ck
+from helpers import compare_factors
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def test_library_exports_every_declared_symbol():
+    with open(os.path.join(ROOT, "include", "cktlu.h")) as f:
+        text = f.read()
+    declared = set(re.findall(r"\b(cktlu_[a-z_]+)\s*\(", text))
+    assert declared, "no declarations found"
+    assert declared == set(ck.EXPORTS), declared ^ set(ck.EXPORTS)
+    for name in declared:
+        assert hasattr(ck.lib, name), name
+
+
+def _analysed(c, **kw):
+    s = ck.SparseLU(c.n, c.colptr, c.rowind, **kw)
+    return s
+
+
+CASES = [
+    ("mesh_vsrc_32", lambda: mnagen.mesh_vsrc(32, 32, 4, seed=0)),
+    ("mesh_transistor_30", lambda: mnagen.mesh_transistor(30, 30, seed=1)),
+    ("layered_rc_3x20", lambda: mnagen.layered_rc(20, 20, 3, seed=2)),
+    ("power_grid_40", lambda: mnagen.power_grid(40, 40, n_src=50, seed=3)),
+    ("random_200", lambda: mnagen.random_pattern(200, 0.02, 4)),
+]
+
+
+@pytest.mark.parametrize("name,make", CASES, ids=[c[0] for c in CASES])
+def test_analyze_permutations_and_etree(oracle_mod, name, make):
+    c = make()
+    s = _analysed(c)
+    a = s.analysis(with_pivots=False)
+    rp, cp = a["rowperm_pre"], a["colperm"]
+    assert np.array_equal(np.sort(rp), np.arange(c.n)) and np.array_equal(np.sort(cp), np.arange(c.n))
+    A = c.to_scipy().tocsr()
+    H = A[rp][:, cp].tocsc()
+    H.sort_indices()
+    assert np.all(H.diagonal() != 0) or all(H[i, i] != 0 or (H[:, i].indices == i).any() for i in range(c.n))
+    diag_present = np.array([(H.indices[H.indptr[j]:H.indptr[j + 1]] == j).any() for j in range(c.n)])
+    assert diag_present.all(), "pre-processed matrix has a structurally zero diagonal"
+    if c.n <= 1100:
+        par = oracle_mod.coletree(c.n, H.indptr.astype(np.int32), H.indices.astype(np.int32))
+        assert np.array_equal(par, a["parent"])
+
+
+@pytest.mark.parametrize("eps", [1e-3, 0.1, 1.0])
+@pytest.mark.parametrize("name,make", CASES, ids=[c[0] for c in CASES])
+def test_host_factorize_matches_oracle(oracle_mod, name, make, eps):
+    c = make()
+    s = _analysed(c, eps=eps)
+    s.factorize_host(c.values)
+    a = s.analysis()
+    lu = oracle_mod.gp_lu(c.n, c.colptr, c.rowind, c.values, a["rowperm_pre"], a["colperm"], eps)
+    assert lu.status == 0
+    assert np.array_equal(a["pivrow"], lu.pivrow)
+    compare_factors(s.factors(), lu, rtol=64 * c.n * 1.2e-16)
+    assert np.array_equal(s.levels(), oracle_mod.levels(lu))
+    st = s.stats()
+    assert st["nnz_l"] == lu.Lp[-1] and st["nnz_u"] == lu.Up[-1]
+    assert st["macs"] == oracle_mod.mac_count(lu)
+    rp, cp = s.perm()
+    assert np.array_equal(rp, a["rowperm_pre"][lu.pivrow])
+
+
+def test_host_refactor_preferred_row_semantics(oracle_mod):
+    """A second host factorization starts from the previous pivot sequence."""
+    c = mnagen.random_pattern(60, 0.06, 9)
+    s = _analysed(c, eps=0.5)
+    s.factorize_host(c.values)
+    a0 = s.analysis()
+    v1 = mnagen.perturb(c.values, 9, 0, 1, rel=0.3)
+    s.factorize_host(v1)
+    a1 = s.analysis()
+    lu0 = oracle_mod.gp_lu(c.n, c.colptr, c.rowind, c.values, a0["rowperm_pre"], a0["colperm"], 0.5)
+    lu1 = oracle_mod.gp_lu(c.n, c.colptr, c.rowind, v1, a0["rowperm_pre"], a0["colperm"], 0.5)
+    assert np.array_equal(a1["pivrow"], lu1.pivrow)
+    assert lu0.status == 0
+
+
+def test_amd_reduces_fill_on_grid():
+    c = mnagen.hand_pattern("laplacian2d", 30 * 30)
+    nat = _analysed(c, ordering=ck.CKTLU_ORDER_NATURAL)
+    nat.factorize_host(c.values)
+    amd = _analysed(c)
+    amd.factorize_host(c.values)
+    f_nat = nat.stats()["nnz_l"]
+    f_amd = amd.stats()["nnz_l"]
+    assert f_amd < 0.5 * f_nat, (f_amd, f_nat)
+
+
+def test_errors_and_state():
+    o = ck.cktlu_default_options()
+    ctx = ck.cktlu_create(o)
+    try:
+        v = np.ones(2)
+        assert ck.cktlu_factorize_host(ctx, v) == ck.CKTLU_E_STATE
+        # unsorted rows
+        assert ck.cktlu_analyze(ctx, 2, np.array([0, 2, 3], np.int32), np.array([1, 0, 1], np.int32)) == ck.CKTLU_E_ARG
+        # out-of-range row
+        assert ck.cktlu_analyze(ctx, 2, np.array([0, 1, 2], np.int32), np.array([0, 2], np.int32)) == ck.CKTLU_E_ARG
+        # structurally singular: two columns share a single row
+        assert ck.cktlu_analyze(ctx, 2, np.array([0, 1, 2], np.int32), np.array([0, 0], np.int32)) == \
+            ck.CKTLU_E_STRUCT_SINGULAR
+        # numerically singular
+        A = sp.csc_matrix(np.array([[1.0, 2.0], [1.0, 2.0]]))
+        assert ck.cktlu_analyze(ctx, 2, A.indptr.astype(np.int32), A.indices.astype(np.int32)) == 0
+        assert ck.cktlu_factorize_host(ctx, A.data.copy()) == ck.CKTLU_E_NUM_SINGULAR
+        assert ck.cktlu_solve(ctx, 1, None, 2, None, 2, None) in (ck.CKTLU_E_ARG, ck.CKTLU_E_STATE)
+    finally:
+        ck.cktlu_destroy(ctx)
+    bad = ck.cktlu_default_options()
+    bad.pivot_eps = 2.0
+    with pytest.raises(ck.CktluError):
+        ck.cktlu_create(bad)
+    for s in range(-7, 3):
+        assert ck.strerror(s)
+
+
+def test_restart_closure_via_etree(oracle_mod):
+    """The fallback's restart set equals the oracle's closure on the library's etree."""
+    c = mnagen.mesh_vsrc(10, 10, 4, seed=5)
+    s = _analysed(c)
+    par = s.analysis(with_pivots=False)["parent"]
+    rng = np.random.default_rng(0)
+    for _ in range(5):
+        unf = rng.uniform(size=c.n) < 0.05
+        got = oracle_mod.restart_set(par, unf)
+        # closure property: members' parents are members, and it contains unf
+        assert got[unf].all()
+        idx = np.nonzero(got)[0]
+        assert all(par[i] < 0 or got[par[i]] for i in idx)
+
+
+def test_footprint_estimate_positive():
+    c = mnagen.mesh_vsrc(8, 8, 4, seed=0)
+    s = _analysed(c)
+    s.factorize_host(c.values)
+    assert s.footprint_bytes(1) > 12 * (s.stats()["nnz_l"] + s.stats()["nnz_u"])
