@@ -6,6 +6,8 @@
 #include <climits>
 #include <cmath>
 #include <cstring>
+#include <cstdio>
+#include <cstdlib>
 #include <new>
 
 #include "internal.h"
@@ -29,15 +31,27 @@ struct cktlu_ctx {
 
 namespace {
 
+// CKTLU_DEBUG=1 in the environment prints the site of every HIP failure.
+bool debug_on() {
+    static int v = -1;
+    if (v < 0) { const char *e = getenv("CKTLU_DEBUG"); v = (e && *e && *e != '0') ? 1 : 0; }
+    return v == 1;
+}
+void debug_hip(int e, const char *what, int line) {
+    if (debug_on())
+        fprintf(stderr, "[cktlu] %s failed at cktlu.cpp:%d: %s (%d)\n", what, line,
+                hipGetErrorString((hipError_t)e), e);
+}
+
 #define HIPCHK(expr)                                   \
     do {                                               \
         hipError_t e_ = (expr);                        \
-        if (e_ != hipSuccess) return CKTLU_E_HIP;      \
+        if (e_ != hipSuccess) { debug_hip((int)e_, #expr, __LINE__); return CKTLU_E_HIP; } \
     } while (0)
 #define LCHK(expr)                                     \
     do {                                               \
         int e_ = (expr);                               \
-        if (e_ != 0) return CKTLU_E_HIP;               \
+        if (e_ != 0) { debug_hip(e_, #expr, __LINE__); return CKTLU_E_HIP; } \
     } while (0)
 
 inline hipStream_t stream_of(const cktlu_ctx *c) { return (hipStream_t)c->opt.stream; }
@@ -66,7 +80,7 @@ int upload(DevBuf &b, const std::vector<V> &v, hipStream_t st) {
 }
 
 void free_device(Device &d) {
-    DevBuf *all[] = {&d.seq, &d.Fp, &d.Fi, &d.nU, &d.Ap, &d.colperm, &d.amap, &d.Lrp, &d.Lrj, &d.Lrsrc,
+    DevBuf *all[] = {&d.seq, &d.Dp, &d.Dlen, &d.Fi, &d.nU, &d.Ap, &d.colperm, &d.amap, &d.Lrp, &d.Lrj, &d.Lrsrc,
                      &d.Urp, &d.Urj, &d.Ursrc, &d.udiag, &d.rowperm, &d.colperm_sol, &d.Acp, &d.Acj,
                      &d.Acsrc, &d.Fx64, &d.Fx32, &d.Aval, &d.ready, &d.sready, &d.ctrl, &d.scratch, &d.vec};
     for (DevBuf *b : all) dfree(*b);
@@ -75,7 +89,56 @@ void free_device(Device &d) {
     d.vec_cap = 0;
 }
 
-int64_t nnzF(const cktlu_ctx *c) { return c->f.Fp.empty() ? 0 : c->f.Fp[c->an.n]; }
+// entries of one instance of the (padded) device factor storage
+int64_t nnzF(const cktlu_ctx *c) { return c->s.nnz_dev; }
+
+// host factor values (compact) -> device layout (columns on cache-line boundaries)
+std::vector<double> pad_values(const cktlu_ctx *c, const double *compact) {
+    std::vector<double> out(c->s.nnz_dev, 0.0);
+    for (int k = 0; k < c->an.n; k++)
+        std::copy(compact + c->f.Fp[k], compact + c->f.Fp[k + 1], out.begin() + c->s.Dp[k]);
+    return out;
+}
+
+// device layout -> compact host order
+void unpad_values(const cktlu_ctx *c, const double *padded, double *compact) {
+    for (int k = 0; k < c->an.n; k++)
+        std::copy(padded + c->s.Dp[k], padded + c->s.Dp[k] + c->s.Dlen[k], compact + c->f.Fp[k]);
+}
+
+// Control block layout (int32 words, B = batch capacity):
+//   [0] refactor ticket, [1, 1+B) interrupt flags, [1+B, 1+2B) first failing
+//   column, [2B+4] solve ticket, [2B+8, 2B+12) watchdog words (flag, waiting
+//   column, awaited column, ticket).
+// A spin-wait that exceeds kSpinLimit polls (about a second) sets the
+// watchdog word and gives up, so every wavefront always reaches its exit.
+constexpr int kSpinLimit = 1 << 22;
+int *err_word(cktlu_ctx *c) { return (int *)c->dev.ctrl.p + 2 * c->dev.batch_cap + 8; }
+
+// Reads and clears the watchdog word (synchronises the stream).
+int check_watchdog(cktlu_ctx *c) {
+    int w[4] = {0, 0, 0, 0};
+    hipStream_t st = (hipStream_t)c->opt.stream;
+    HIPCHK(hipMemcpyAsync(w, err_word(c), sizeof(w), hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    if (w[0] != 0) {
+        if (debug_on()) {
+            int h[3];
+            std::vector<int> rd(c->an.n);
+            (void)hipMemcpy(h, c->dev.ctrl.p, sizeof(h), hipMemcpyDeviceToHost);
+            (void)hipMemcpy(rd.data(), c->dev.ready.p, rd.size() * sizeof(int), hipMemcpyDeviceToHost);
+            int done = 0;
+            for (int v : rd) done += v == (int)c->dev.epoch;
+            fprintf(stderr, "[cktlu] watchdog %d: column %d waited on column %d (ticket %d); ticket counter %d, "
+                    "interrupted %d, first fail %d, %d of %d columns ready (epoch %u, ready[awaited]=%d)\n",
+                    w[0], w[1], w[2], w[3], h[0], h[1], h[2], done, c->an.n, c->dev.epoch,
+                    (w[2] >= 0 && w[2] < c->an.n) ? rd[w[2]] : -1);
+        }
+        HIPCHK(hipMemsetAsync(err_word(c), 0, sizeof(w), st));
+        return CKTLU_E_HIP;
+    }
+    return CKTLU_OK;
+}
 
 // Allocate the per-instance buffers for `batch` instances.
 int ensure_batch(cktlu_ctx *c, int batch) {
@@ -105,7 +168,9 @@ int ensure_batch(cktlu_ctx *c, int batch) {
     dfree(d.sready);
     if ((rc = dalloc(d.sready, (size_t)n * batch * sizeof(int)))) return rc;
     HIPCHK(hipMemsetAsync(d.sready.p, 0, (size_t)n * batch * sizeof(int), st));
-    if ((rc = dalloc(d.ctrl, (size_t)(8 + 2 * batch) * sizeof(int)))) return rc;
+    dfree(d.ctrl);
+    if ((rc = dalloc(d.ctrl, (size_t)(16 + 2 * batch) * sizeof(int)))) return rc;
+    HIPCHK(hipMemsetAsync(d.ctrl.p, 0, (size_t)(16 + 2 * batch) * sizeof(int), st));
     d.batch_cap = batch;
     return CKTLU_OK;
 }
@@ -121,8 +186,9 @@ int upload_all(cktlu_ctx *c) {
         LCHK(occupancy_grid(1, &d.grid_solve));
     }
     if ((rc = upload(d.seq, s.seq, st))) return rc;
-    if ((rc = upload(d.Fp, s.Fp32, st))) return rc;
-    if ((rc = upload(d.Fi, c->f.Fi, st))) return rc;
+    if ((rc = upload(d.Dp, s.Dp, st))) return rc;
+    if ((rc = upload(d.Dlen, s.Dlen, st))) return rc;
+    if ((rc = upload(d.Fi, s.Fi_dev, st))) return rc;
     if ((rc = upload(d.nU, c->f.nU, st))) return rc;
     if ((rc = upload(d.Ap, c->an.Ap, st))) return rc;
     if ((rc = upload(d.colperm, c->an.colperm, st))) return rc;
@@ -145,9 +211,13 @@ int upload_all(cktlu_ctx *c) {
     dfree(d.Fx64);
     dfree(d.Fx32);
     if ((rc = ensure_batch(c, batch))) return rc;
-    HIPCHK(hipMemcpyAsync(d.Fx64.p, c->f.Fx.data(), c->f.Fx.size() * sizeof(double), hipMemcpyHostToDevice, st));
+    {
+        const std::vector<double> padded = pad_values(c, c->f.Fx.data());
+        HIPCHK(hipMemcpyAsync(d.Fx64.p, padded.data(), padded.size() * sizeof(double), hipMemcpyHostToDevice, st));
+        HIPCHK(hipStreamSynchronize(st));
+    }
     if (c->opt.precision == CKTLU_FP32_IR)
-        LCHK(launch_f64_to_f32((const double *)d.Fx64.p, (float *)d.Fx32.p, (int64_t)c->f.Fx.size(), st));
+        LCHK(launch_f64_to_f32((const double *)d.Fx64.p, (float *)d.Fx32.p, nnzF(c), st));
     // overflow work vectors for columns longer than the LDS capacity
     dfree(d.scratch);
     if (s.max_col > 1024) {
@@ -200,11 +270,12 @@ int factor_and_setup(cktlu_ctx *c, const double *values_host, const std::vector<
     if (device) {
         if (same && c->dev.uploaded) {
             hipStream_t st = stream_of(c);
-            HIPCHK(hipMemcpyAsync(c->dev.Fx64.p, c->f.Fx.data(), c->f.Fx.size() * sizeof(double),
+            const std::vector<double> padded = pad_values(c, c->f.Fx.data());
+            HIPCHK(hipMemcpyAsync(c->dev.Fx64.p, padded.data(), padded.size() * sizeof(double),
                                   hipMemcpyHostToDevice, st));
+            HIPCHK(hipStreamSynchronize(st));
             if (c->opt.precision == CKTLU_FP32_IR)
-                LCHK(launch_f64_to_f32((const double *)c->dev.Fx64.p, (float *)c->dev.Fx32.p,
-                                       (int64_t)c->f.Fx.size(), st));
+                LCHK(launch_f64_to_f32((const double *)c->dev.Fx64.p, (float *)c->dev.Fx32.p, nnzF(c), st));
             c->dev_values_newer = false;
         } else {
             rc = upload_all(c);
@@ -236,7 +307,8 @@ int run_refactor(cktlu_ctx *c, int batch, const double *values_dev, bool fp32, b
     a.n = c->an.n;
     a.batch = batch;
     a.seq = (const int *)d.seq.p;
-    a.Fp = (const int *)d.Fp.p;
+    a.Dp = (const int *)d.Dp.p;
+    a.Dlen = (const int *)d.Dlen.p;
     a.Fi = (const int *)d.Fi.p;
     a.nU = (const int *)d.nU.p;
     a.Ap = (const int *)d.Ap.p;
@@ -255,6 +327,8 @@ int run_refactor(cktlu_ctx *c, int batch, const double *values_dev, bool fp32, b
     a.max_col = c->s.max_col;
     a.fp32 = fp32 ? 1 : 0;
     a.check = check ? 1 : 0;
+    a.err = err_word(c);
+    a.spin_limit = kSpinLimit;
     int grid = d.grid_refactor;
     const int64_t waves_needed = ((int64_t)a.n * batch + 3) / 4;
     if (grid > waves_needed) grid = (int)std::max<int64_t>(1, waves_needed);
@@ -270,9 +344,11 @@ int fallback(cktlu_ctx *c, const double *values_dev, cktlu_refactor_info *info) 
     std::vector<int> ready(n);
     std::vector<double> vals(c->an.nnz);
     HIPCHK(hipMemcpyAsync(ready.data(), c->dev.ready.p, (size_t)n * sizeof(int), hipMemcpyDeviceToHost, st));
-    HIPCHK(hipMemcpyAsync(c->f.Fx.data(), c->dev.Fx64.p, c->f.Fx.size() * sizeof(double), hipMemcpyDeviceToHost, st));
+    std::vector<double> padded(nnzF(c));
+    HIPCHK(hipMemcpyAsync(padded.data(), c->dev.Fx64.p, padded.size() * sizeof(double), hipMemcpyDeviceToHost, st));
     HIPCHK(hipMemcpyAsync(vals.data(), values_dev, vals.size() * sizeof(double), hipMemcpyDeviceToHost, st));
     HIPCHK(hipStreamSynchronize(st));
+    unpad_values(c, padded.data(), c->f.Fx.data());
     std::vector<char> unfinished(n), in_set, keep(n);
     for (int k = 0; k < n; k++) unfinished[k] = ready[k] != (int)c->dev.epoch;
     restart_closure(c->an.parent, unfinished, in_set);
@@ -312,7 +388,7 @@ int refactor_single(cktlu_ctx *c, const double *values_dev, cktlu_refactor_info 
     if (!check) return CKTLU_OK;
     int h[3];
     HIPCHK(hipMemcpyAsync(h, d.ctrl.p, 3 * sizeof(int), hipMemcpyDeviceToHost, st));
-    HIPCHK(hipStreamSynchronize(st));
+    if ((rc = check_watchdog(c))) return rc;
     if (!h[1]) return CKTLU_OK;
     int first = h[2];
     if (fp32) {
@@ -358,6 +434,8 @@ int tri_solves(cktlu_ctx *c, int nrhs, int batch, double *z, bool fp32, const in
     a.ready = (int *)d.sready.p;
     a.ctrl = (int *)d.ctrl.p + 2 * d.batch_cap + 4;   // words after the refactor control block
     a.skip = skip;
+    a.err = err_word(c);
+    a.spin_limit = kSpinLimit;
     int grid = d.grid_solve;
     const int64_t waves = ((int64_t)a.n * batch + 3) / 4;
     if (grid > waves) grid = (int)std::max<int64_t>(1, waves);
@@ -671,6 +749,9 @@ int cktlu_get_factors(cktlu_ctx *c, int32_t instance, int32_t *Lp, int32_t *Li, 
                                   hipMemcpyDeviceToHost, st));
             HIPCHK(hipStreamSynchronize(st));
         }
+        std::vector<double> compact(c->f.Fx.size());
+        unpad_values(c, vals.data(), compact.data());
+        vals.swap(compact);
         src = vals.data();
     } else if (instance != 0) {
         return CKTLU_E_ARG;
@@ -709,7 +790,7 @@ int cktlu_get_stats(const cktlu_ctx *c, cktlu_stats *out) {
 
 size_t cktlu_footprint_bytes(const cktlu_ctx *c, int32_t batch) {
     if (!c) return 0;
-    const DevBuf *all[] = {&c->dev.seq, &c->dev.Fp, &c->dev.Fi, &c->dev.nU, &c->dev.Ap, &c->dev.colperm,
+    const DevBuf *all[] = {&c->dev.seq, &c->dev.Dp, &c->dev.Dlen, &c->dev.Fi, &c->dev.nU, &c->dev.Ap, &c->dev.colperm,
                            &c->dev.amap, &c->dev.Lrp, &c->dev.Lrj, &c->dev.Lrsrc, &c->dev.Urp, &c->dev.Urj,
                            &c->dev.Ursrc, &c->dev.udiag, &c->dev.rowperm, &c->dev.colperm_sol, &c->dev.Acp,
                            &c->dev.Acj, &c->dev.Acsrc, &c->dev.Fx64, &c->dev.Fx32, &c->dev.Aval,

@@ -64,7 +64,11 @@ struct Schedule {
     std::vector<int> level, seq;              // level of each column; columns by (level, index)
     int nlevels = 0, max_width = 0;
     std::vector<int> amap;                    // user nonzero -> slot offset inside its column
-    std::vector<int> Fp32;                    // int32 copy of Fp (nnz(F) < 2^31)
+    // device layout of the factor storage: column k occupies [Dp[k], Dp[k] + Dlen[k]);
+    // every column starts on a kColAlign-entry boundary so that no cache line holds
+    // entries of two columns
+    std::vector<int> Dp, Dlen, Fi_dev;        // Fi_dev: rows at device positions, padding = INT_MAX
+    int64_t nnz_dev = 0;
     // CSR of strictly-lower L and strictly-upper U (position space) for the solves
     std::vector<int> Lrp, Lrj, Lrsrc, Urp, Urj, Ursrc, udiag;
     std::vector<int> rowperm_final;           // position k <- user row
@@ -89,7 +93,7 @@ struct Device {
     int prec = CKTLU_FP64;
     int batch_cap = 0;                 // instances the value buffers hold
     // pattern / schedule
-    DevBuf seq, Fp, Fi, nU, Ap, colperm, amap;
+    DevBuf seq, Dp, Dlen, Fi, nU, Ap, colperm, amap;
     DevBuf Lrp, Lrj, Lrsrc, Urp, Urj, Ursrc, udiag, rowperm, colperm_sol;
     DevBuf Acp, Acj, Acsrc;
     // values and sync words
@@ -109,9 +113,12 @@ struct Device {
 // Implemented in kernels.hip.  All return a hipError_t as int.
 namespace cktlu_dev {
 
+constexpr int kColAlign = 32;   // factor column alignment in entries (>= one 128-byte line)
+constexpr int YS = 16;          // doubles per solve-vector row (one 128-byte line); nrhs <= 8
+
 struct RefactorArgs {
     int n, batch;
-    const int *seq, *Fp, *Fi, *nU, *Ap, *colperm, *amap;
+    const int *seq, *Dp, *Dlen, *Fi, *nU, *Ap, *colperm, *amap;
     const double *Aval;        // batch x nnzA
     int64_t nnzA, nnzF;
     void *Fx;                  // batch x nnzF (double or float)
@@ -123,6 +130,8 @@ struct RefactorArgs {
     void *scratch;             // per-wave work vectors of max_col entries
     int max_col;
     int fp32, check;
+    int *err;                  // watchdog word: set when a wait exceeds spin_limit
+    int spin_limit;
 };
 
 int launch_refactor(const RefactorArgs &a, int grid, void *stream);
@@ -141,6 +150,8 @@ struct SolveArgs {
     int *ctrl;                 // ticket words
     unsigned epoch;
     const int *skip;           // per-instance status (-1 = solve), may be null
+    int *err;                  // watchdog word
+    int spin_limit;
 };
 
 int launch_lsolve(const SolveArgs &a, int grid, void *stream);

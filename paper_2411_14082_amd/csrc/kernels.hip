@@ -3,21 +3,30 @@
 // refactor_kernel: fast factorization with pivot check (Section IV-B).  The
 //   paper's cluster mode (level by level) and pipeline mode (an atomic
 //   counter hands out the next node of a dependency-ordered sequence; a node
-//   spins until each predecessor has finished, watching a shared
+//   waits until each predecessor has finished, watching a shared
 //   "interrupted" flag) become one persistent kernel: every wavefront takes
 //   the next column of the level-ordered sequence from a device counter,
-//   applies the left-looking updates of its finished predecessors in
-//   ascending order, tests its pivot against eps times the largest entry of
-//   its L part, stores L and U and publishes a per-column ready flag.  A
+//   applies the left-looking updates of its predecessors in ascending order
+//   as they become ready, tests its pivot against eps times the largest entry
+//   of its L part, stores L and U and publishes a per-column ready flag.  A
 //   failed test records the column and raises the instance's interrupt flag;
 //   waiters see it and stop.  Because the counter hands out columns in
 //   topological order and only running wavefronts hold columns, every awaited
-//   column belongs to a running wavefront, so the spin-waits always end.
+//   column belongs to a running wavefront; a bounded wait (watchdog) turns any
+//   violation into an error instead of a hang.
 //
-// lsolve/usolve_kernel: triangular solves (Section II-C, Section V) in the
-//   row ("pull") form with per-row ready flags: each wavefront takes the next
-//   row, waits for the solution entries it reads, reduces its dot product in
-//   a fixed order and publishes its own entry.  Deterministic.
+// trisolve_kernel: triangular solves (Section II-C, Section V) in the row
+//   ("pull") form with per-row ready flags: each wavefront takes the next row,
+//   waits for the solution entries it reads, reduces its dot product in a
+//   fixed order and publishes its own entry.  Deterministic.
+//
+// Cross-workgroup visibility on a multi-XCD MI355X: each XCD has its own L2,
+// and a plain store can stay in the writer's L2 until the kernel ends.  So
+// every flag is written with an atomic exchange and read with an atomic
+// compare-and-swap (both are performed at the device coherence point), data is
+// written back (release fence) before its flag is set, and every column of the
+// factor storage and every row of the solve vectors starts on its own cache
+// line, so no XCD can hold a line of data it has not yet been signalled for.
 #include <hip/hip_runtime.h>
 
 #include <climits>
@@ -32,18 +41,13 @@ constexpr int WG = 256;
 constexpr int WAVES = WG / WAVE;
 constexpr int CAP = 1024;   // LDS work-vector slots per wavefront
 
-__device__ __forceinline__ int ld_acquire(const int *p) {
-    return __hip_atomic_load(p, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
+__device__ __forceinline__ int flag_read(int *p, int expect) {
+    return atomicCAS(p, expect, expect);   // an RMW: never served from a stale cache line
 }
-__device__ __forceinline__ int ld_relaxed(const int *p) {
-    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-__device__ __forceinline__ void st_release(int *p, int v) {
-    __hip_atomic_store(p, v, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
-}
-__device__ __forceinline__ void st_relaxed(int *p, int v) {
-    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
+__device__ __forceinline__ void flag_write(int *p, int v) { atomicExch(p, v); }
+__device__ __forceinline__ void release_agent() { __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent"); }
+__device__ __forceinline__ void acquire_agent() { __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent"); }
+
 // Orders this wavefront's work-vector accesses (LDS or global) across lanes.
 __device__ __forceinline__ void wave_sync() {
     __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "workgroup");
@@ -71,6 +75,15 @@ __device__ __forceinline__ int find_slot(const int *rows, int len, int r) {
     return lo;
 }
 
+// Watchdog: the first wait that exceeds the limit records (waiter, awaited, ticket).
+__device__ __forceinline__ void watchdog_trip(int *err, int code, int waiter, int awaited, int ticket) {
+    if (atomicCAS(err, 0, code) == 0) {
+        atomicExch(err + 1, waiter);
+        atomicExch(err + 2, awaited);
+        atomicExch(err + 3, ticket);
+    }
+}
+
 // ------------------------------------------------------------ refactorize
 template <typename T, bool CHECK>
 __global__ __launch_bounds__(WG) void refactor_kernel(RefactorArgs a) {
@@ -92,8 +105,7 @@ __global__ __launch_bounds__(WG) void refactor_kernel(RefactorArgs a) {
         if (t >= total) break;
         const int inst = t % a.batch;
         const int k = a.seq[t / a.batch];
-        if (CHECK && ld_relaxed(&interrupted[inst])) continue;
-        const int base = a.Fp[k], len = a.Fp[k + 1] - base, nu = a.nU[k];
+        const int base = a.Dp[k], len = a.Dlen[k], nu = a.nU[k];
         const int *rowsg = a.Fi + base;
         T *Fx = reinterpret_cast<T *>(a.Fx) + (size_t)inst * a.nnzF;
         const double *Av = a.Aval + (size_t)inst * a.nnzA;
@@ -109,20 +121,37 @@ __global__ __launch_bounds__(WG) void refactor_kernel(RefactorArgs a) {
         const int c = a.colperm[k];
         for (int p = a.Ap[c] + lane; p < a.Ap[c + 1]; p += WAVE) x[a.amap[p]] = (T)Av[p];
         wave_sync();
-        int abort = 0;
+        int abort = 0, ready_upto = 0;
         for (int u = 0; u < nu - 1; ++u) {
-            const int j = rows[u];
-            if (lane == 0) {
-                while (ld_acquire(&ready[j]) != epoch) {
-                    if (ld_relaxed(&interrupted[inst])) { abort = 1; break; }
-                    __builtin_amdgcn_s_sleep(1);
+            if (u >= ready_upto) {
+                // poll the next 64 dependencies in parallel; proceed with the ready prefix
+                int spins = 0;
+                for (;;) {
+                    const int idx = u + lane;
+                    bool ok = true;
+                    if (idx < nu - 1) ok = flag_read(&ready[rows[idx]], epoch) == epoch;
+                    const unsigned long long notok = __ballot(!ok);
+                    const int prefix = notok ? __ffsll((long long)notok) - 1 : WAVE;
+                    if (prefix > 0) { ready_upto = u + prefix; break; }
+                    int stop = 0;
+                    if (lane == 0) {
+                        if (flag_read(&interrupted[inst], 1) != 0) stop = 1;
+                        else if (++spins > a.spin_limit) {
+                            watchdog_trip(a.err, 1, k, rows[u], t);
+                            flag_write(&interrupted[inst], 1);
+                            stop = 1;
+                        }
+                    }
+                    stop = __shfl(stop, 0);
+                    if (stop) { abort = 1; break; }
+                    __builtin_amdgcn_s_sleep(2);
                 }
+                if (abort) break;
+                acquire_agent();
             }
-            abort = __shfl(abort, 0);
-            if (abort) break;
-            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+            const int j = rows[u];
             const T xj = x[u];
-            const int lb = a.Fp[j] + a.nU[j], le = a.Fp[j + 1];
+            const int lb = a.Dp[j] + a.nU[j], le = a.Dp[j] + a.Dlen[j];
             for (int q = lb + lane; q < le; q += WAVE) {
                 const int r = a.Fi[q];
                 const T l = Fx[q];
@@ -150,14 +179,14 @@ __global__ __launch_bounds__(WG) void refactor_kernel(RefactorArgs a) {
         if (fail) {
             if (lane == 0) {
                 atomicMin(&firstfail[inst], k);
-                st_relaxed(&interrupted[inst], 1);
+                flag_write(&interrupted[inst], 1);
             }
             continue;
         }
         for (int i = lane; i < nu; i += WAVE) Fx[base + i] = x[i];
         for (int i = nu + lane; i < len; i += WAVE) Fx[base + i] = x[i] / d;
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
-        if (lane == 0) st_release(&ready[k], epoch);
+        release_agent();
+        if (lane == 0) flag_write(&ready[k], epoch);
     }
 }
 
@@ -199,6 +228,7 @@ int launch_refactor(const RefactorArgs &a, int grid, void *stream) {
 }
 
 // ----------------------------------------------------------------- solves
+// y holds one cache line (YS doubles) per row and instance: y[(inst*n + i)*YS + r].
 template <typename T, int NR, bool UPPER>
 __global__ __launch_bounds__(WG) void trisolve_kernel(SolveArgs a) {
     const int lane = threadIdx.x & (WAVE - 1);
@@ -216,17 +246,31 @@ __global__ __launch_bounds__(WG) void trisolve_kernel(SolveArgs a) {
         const int i = UPPER ? a.n - 1 - t / a.batch : t / a.batch;
         if (a.skip && a.skip[inst] != -1) continue;
         const T *Fx = reinterpret_cast<const T *>(a.Fx) + (size_t)inst * a.nnzF;
-        double *y = a.y + (size_t)inst * a.n * NR;
+        double *y = a.y + (size_t)inst * a.n * YS;
         int *ready = a.ready + (size_t)inst * a.n;
         double acc[NR];
 #pragma unroll
         for (int r = 0; r < NR; r++) acc[r] = 0.0;
-        for (int q = rp[i] + lane; q < rp[i + 1]; q += WAVE) {
-            const int j = rj[q];
-            const double l = (double)Fx[rs[q]];
-            while (ld_acquire(&ready[j]) != epoch) __builtin_amdgcn_s_sleep(1);
+        for (int q0 = rp[i]; q0 < rp[i + 1]; q0 += WAVE) {
+            const int q = q0 + lane;
+            const bool act = q < rp[i + 1];
+            const int j = act ? rj[q] : 0;
+            const double l = act ? (double)Fx[rs[q]] : 0.0;
+            bool ok = !act || flag_read(&ready[j], epoch) == epoch;
+            int spins = 0;
+            while (!__all(ok)) {
+                if (!ok) ok = flag_read(&ready[j], epoch) == epoch;
+                if (++spins > a.spin_limit) {   // watchdog: never wait forever
+                    if (lane == 0) watchdog_trip(a.err, 2, i, j, t);
+                    break;
+                }
+                __builtin_amdgcn_s_sleep(2);
+            }
+            acquire_agent();
+            if (act) {
 #pragma unroll
-            for (int r = 0; r < NR; r++) acc[r] += l * y[(size_t)j * NR + r];
+                for (int r = 0; r < NR; r++) acc[r] += l * y[(size_t)j * YS + r];
+            }
         }
 #pragma unroll
         for (int r = 0; r < NR; r++) acc[r] = wave_sum(acc[r]);
@@ -235,12 +279,12 @@ __global__ __launch_bounds__(WG) void trisolve_kernel(SolveArgs a) {
         for (int r = 1; r < NR; r++)
             if (lane == r) mine = acc[r];
         if (lane < NR) {
-            double v = y[(size_t)i * NR + lane] - mine;
+            double v = y[(size_t)i * YS + lane] - mine;
             if (UPPER) v = v / (double)Fx[a.udiag[i]];
-            y[(size_t)i * NR + lane] = v;
+            y[(size_t)i * YS + lane] = v;
         }
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
-        if (lane == 0) st_release(&ready[i], epoch);
+        release_agent();
+        if (lane == 0) flag_write(&ready[i], epoch);
     }
 }
 
@@ -278,7 +322,7 @@ __global__ void gather_rhs_kernel(int n, int nrhs, int batch, const double *b, i
         const int64_t ik = t / nrhs;
         const int k = (int)(ik % n);
         const int64_t i = ik / n;
-        y[t] = b[(i * nrhs + r) * ldb + perm[k]];
+        y[ik * YS + r] = b[(i * nrhs + r) * ldb + perm[k]];
     }
 }
 
@@ -293,7 +337,8 @@ __global__ void scatter_sol_kernel(int n, int nrhs, int batch, const double *z, 
         const int64_t i = ik / n;
         if (skip && skip[i] != -1) continue;
         double *dst = x + (i * nrhs + r) * ldx + perm[k];
-        *dst = accumulate ? *dst + z[t] : z[t];
+        const double v = z[ik * YS + r];
+        *dst = accumulate ? *dst + v : v;
     }
 }
 

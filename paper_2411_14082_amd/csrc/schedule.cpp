@@ -4,6 +4,7 @@
 // of the matrix values into the factor storage, and the row-wise structures
 // of L and U used by the triangular solves.
 #include <algorithm>
+#include <climits>
 #include <numeric>
 
 #include "internal.h"
@@ -15,8 +16,20 @@ void build_schedule(const Analysis &an, const Factor &f, const cktlu_options &op
     const int n = an.n;
     s = Schedule();
     s.n = n;
-    s.Fp32.resize(n + 1);
-    for (int k = 0; k <= n; k++) s.Fp32[k] = (int)f.Fp[k];
+    // ---- device layout: columns padded to whole cache lines
+    const int al = cktlu_dev::kColAlign;
+    s.Dp.assign(n + 1, 0);
+    s.Dlen.resize(n);
+    for (int k = 0; k < n; k++) {
+        const int len = (int)(f.Fp[k + 1] - f.Fp[k]);
+        s.Dlen[k] = len;
+        s.Dp[k + 1] = s.Dp[k] + (len + al - 1) / al * al;
+    }
+    s.nnz_dev = s.Dp[n];
+    s.Fi_dev.assign(s.nnz_dev, INT_MAX);
+    for (int k = 0; k < n; k++)
+        std::copy(f.Fi.begin() + f.Fp[k], f.Fi.begin() + f.Fp[k + 1], s.Fi_dev.begin() + s.Dp[k]);
+    auto dpos = [&](int k, int64_t q) { return (int)(s.Dp[k] + (q - f.Fp[k])); };
     // ---- levels: column k depends on every j with U(j,k) != 0, j < k
     s.level.assign(n, 0);
     int maxlev = -1;
@@ -64,7 +77,7 @@ void build_schedule(const Analysis &an, const Factor &f, const cktlu_options &op
         const int64_t b = f.Fp[k], d = f.Fp[k] + f.nU[k] - 1, e = f.Fp[k + 1];
         for (int64_t q = b; q < d; q++) s.Urp[f.Fi[q] + 1]++;
         for (int64_t q = d + 1; q < e; q++) s.Lrp[f.Fi[q] + 1]++;
-        s.udiag[k] = (int)d;
+        s.udiag[k] = dpos(k, d);
     }
     for (int i = 0; i < n; i++) { s.Lrp[i + 1] += s.Lrp[i]; s.Urp[i + 1] += s.Urp[i]; }
     s.Lrj.resize(s.Lrp[n]); s.Lrsrc.resize(s.Lrp[n]);
@@ -73,8 +86,8 @@ void build_schedule(const Analysis &an, const Factor &f, const cktlu_options &op
         std::vector<int> lf(s.Lrp.begin(), s.Lrp.end() - 1), uf(s.Urp.begin(), s.Urp.end() - 1);
         for (int k = 0; k < n; k++) {   // ascending k -> ascending column index inside each row
             const int64_t b = f.Fp[k], d = f.Fp[k] + f.nU[k] - 1, e = f.Fp[k + 1];
-            for (int64_t q = b; q < d; q++) { int i = f.Fi[q]; s.Urj[uf[i]] = k; s.Ursrc[uf[i]++] = (int)q; }
-            for (int64_t q = d + 1; q < e; q++) { int i = f.Fi[q]; s.Lrj[lf[i]] = k; s.Lrsrc[lf[i]++] = (int)q; }
+            for (int64_t q = b; q < d; q++) { int i = f.Fi[q]; s.Urj[uf[i]] = k; s.Ursrc[uf[i]++] = dpos(k, q); }
+            for (int64_t q = d + 1; q < e; q++) { int i = f.Fi[q]; s.Lrj[lf[i]] = k; s.Lrsrc[lf[i]++] = dpos(k, q); }
         }
     }
     s.rowperm_final.resize(n);
