@@ -1,0 +1,180 @@
+#!/usr/bin/env python
+"""Benchmark: Newton-Raphson refactor + solve steps on one MI355X.
+
+A step is refactorize(values_t) (fast factorization with pivot check) plus
+solve(b) (plus iterative refinement in FP32+IR mode), on the post-layout RC
+mesh workload (3 layers x 300 x 300, vias, transistor stamps; n = 270,000),
+values perturbed +-5% per step, all value sets pre-staged in HBM before the
+timed region.  Prints one JSON line with steps/s, p50/p99 step latency for the
+FP64 path (the headline value) and the FP32+IR path, the roofline of the
+refactorization phase and the CPU oracle baseline.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+WORKLOADS = {
+    "layered_rc_3x300": dict(make=lambda: __import__("mnagen").layered_rc(300, 300, 3, seed=0), cfg=2,
+                             desc="post-layout RC mesh 3x300x300 + vias + transistor stamps"),
+    "mesh_transistor_141": dict(make=lambda: __import__("mnagen").mesh_transistor(141, 141, seed=0), cfg=3,
+                                desc="mesh 141x141 + transistor stamps"),
+    "mesh_vsrc_32": dict(make=lambda: __import__("mnagen").mesh_vsrc(32, 32, 4, seed=0), cfg=1,
+                         desc="mesh 32x32 + 4 ideal voltage sources"),
+}
+HBM_PEAK_GBS = 8000.0
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def run_leg(ck, torch, c, vals_dev, b_dev, precision, steps, warmup):
+    s = ck.SparseLU(c.n, c.colptr, c.rowind, eps=1e-3, precision=precision, ir_tol=1e-10)
+    t0 = time.time()
+    s.factorize(vals_dev[0])
+    t_setup = time.time() - t0
+    x = torch.zeros_like(b_dev)
+    nrep = 0
+    for w in range(warmup):
+        rc, info = s.refactorize(vals_dev[1 + w])
+        nrep += info.repivoted
+        s.solve(b_dev, x)
+    torch.cuda.synchronize()
+    ev = [[torch.cuda.Event(enable_timing=True) for _ in range(3)] for _ in range(steps)]
+    infos = []
+    torch.cuda.synchronize()
+    w0 = time.time()
+    for t in range(steps):
+        e0, e1, e2 = ev[t]
+        e0.record()
+        rc, info = s.refactorize(vals_dev[1 + warmup + t])
+        e1.record()
+        rc2, sinfo = s.solve(b_dev, x)
+        e2.record()
+        nrep += info.repivoted
+        infos.append((sinfo.ir_iters, sinfo.backward_err, sinfo.used_fp64))
+    torch.cuda.synchronize()
+    wall = time.time() - w0
+    step_ms = np.array([ev[t][0].elapsed_time(ev[t][2]) for t in range(steps)])
+    ref_ms = np.array([ev[t][0].elapsed_time(ev[t][1]) for t in range(steps)])
+    sol_ms = np.array([ev[t][1].elapsed_time(ev[t][2]) for t in range(steps)])
+    st = s.stats()
+    s.close()
+    return dict(wall=wall, step_ms=step_ms, ref_ms=ref_ms, sol_ms=sol_ms, stats=st, setup_s=t_setup,
+                repivots=int(nrep), infos=infos, x=x)
+
+
+def cpu_baseline(c, vals, b):
+    """The CPU oracle (single thread): one re-factorization + solve of the same matrix."""
+    import oracle
+    import paper_2411_14082_amd as ck
+    oracle.build(force=False)
+    s = ck.SparseLU(c.n, c.colptr, c.rowind, eps=1e-3)
+    a = s.analysis(with_pivots=False)
+    s.close()
+    lu0 = oracle.gp_lu(c.n, c.colptr, c.rowind, vals[0], a["rowperm_pre"], a["colperm"], 1e-3)
+    t0 = time.time()
+    lu = oracle.gp_lu(c.n, c.colptr, c.rowind, vals[1], a["rowperm_pre"], a["colperm"], 1e-3,
+                      init_pivrow=lu0.pivrow)
+    x = oracle.solve(lu, a["rowperm_pre"], a["colperm"], b)
+    dt = time.time() - t0
+    return dict(value=1.0 / dt, unit="steps/s", cores=1, kind="oracle",
+                sample="1 refactorization (from the previous pivot sequence) + 1 solve of the full matrix, "
+                       "FP64, single thread; %.1f s" % dt), x
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", default="layered_rc_3x300", choices=sorted(WORKLOADS))
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-fp32", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU only: this build has no multi-GPU path "
+              "(instances and requests shard across GPUs without communication; see DESIGN.md)",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import mnagen
+    import paper_2411_14082_amd as ck
+
+    wl = WORKLOADS[args.workload]
+    t0 = time.time()
+    c = wl["make"]()
+    log("workload %s n=%d nnz=%d (%.1fs)" % (args.workload, c.n, c.nnz, time.time() - t0))
+    nvals = 1 + args.warmup + args.steps
+    vals = [c.values] + [mnagen.perturb(c.values, 0, wl["cfg"], t) for t in range(1, nvals)]
+    dev = torch.device("cuda:0")
+    vals_dev = [torch.tensor(v, device=dev) for v in vals]       # staged in HBM before timing
+    b = c.rhs[0]
+    b_dev = torch.tensor(b, device=dev)
+    torch.cuda.synchronize()
+
+    res64 = run_leg(ck, torch, c, vals_dev, b_dev, ck.CKTLU_FP64, args.steps, args.warmup)
+    log("fp64: %.3f steps/s, refactor %.2f ms, solve %.2f ms (setup %.1fs)" %
+        (args.steps / res64["wall"], res64["ref_ms"].mean(), res64["sol_ms"].mean(), res64["setup_s"]))
+    x64 = res64["x"].cpu().numpy()
+    import scipy.sparse as sp
+    A_last = sp.csc_matrix((vals[-1], c.rowind, c.colptr), shape=(c.n, c.n))
+    eta64 = float(np.abs(b - A_last @ x64).max() /
+                  (abs(A_last).sum(axis=1).max() * np.abs(x64).max() + np.abs(b).max()))
+
+    out_fp32 = None
+    if not args.no_fp32:
+        res32 = run_leg(ck, torch, c, vals_dev, b_dev, ck.CKTLU_FP32_IR, args.steps, args.warmup)
+        iters = [i[0] for i in res32["infos"]]
+        errs = [i[1] for i in res32["infos"]]
+        out_fp32 = dict(steps_per_s=args.steps / res32["wall"],
+                        p50_ms=float(np.percentile(res32["step_ms"], 50)),
+                        p99_ms=float(np.percentile(res32["step_ms"], 99)),
+                        refactor_ms=float(res32["ref_ms"].mean()), solve_ms=float(res32["sol_ms"].mean()),
+                        ir_iters_mean=float(np.mean(iters)), backward_err_max=float(np.max(errs)),
+                        fp64_fallbacks=int(sum(i[2] for i in res32["infos"])), repivots=res32["repivots"])
+        log("fp32+ir: %.3f steps/s" % out_fp32["steps_per_s"])
+
+    st = res64["stats"]
+    b_ref = st["bytes_refactor"]
+    achieved = b_ref / (res64["ref_ms"].mean() * 1e-3) / 1e9
+    roofline = dict(bound="hbm", kernel="refactor_level_kernel (all level launches of one refactorization)",
+                    achieved=achieved, peak=HBM_PEAK_GBS, unit="GB/s", frac=achieved / HBM_PEAK_GBS,
+                    traffic=None, bytes_per_launch=b_ref / max(1, st["levels"]),
+                    launches_per_refactor=int(st["levels"]),
+                    avg_launch_us=res64["ref_ms"].mean() * 1e3 / max(1, st["levels"]))
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        cpu, xo = cpu_baseline(c, vals, b)
+        log("cpu oracle: %.4f steps/s" % cpu["value"])
+
+    value = args.steps / res64["wall"]
+    line = {
+        "metric": "NR refactor+solve steps/sec (FP64 path; FP32+IR alongside), 1 GPU",
+        "value": value, "unit": "steps/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": res64["wall"] * 1e3 / args.steps, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": wl["desc"], "n": c.n, "nnz": c.nnz, "nnz_lu": st["nnz_l"] + st["nnz_u"],
+                   "flops_per_refactor": st["flops"], "levels": st["levels"], "value_perturbation": "+-5%"},
+        "p50_ms": float(np.percentile(res64["step_ms"], 50)),
+        "p99_ms": float(np.percentile(res64["step_ms"], 99)),
+        "refactor_ms": float(res64["ref_ms"].mean()), "solve_ms": float(res64["sol_ms"].mean()),
+        "backward_err": eta64, "repivots": res64["repivots"],
+        "fp32_ir": out_fp32,
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

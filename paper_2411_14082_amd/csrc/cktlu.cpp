@@ -5,9 +5,9 @@
 #include <algorithm>
 #include <climits>
 #include <cmath>
-#include <cstring>
 #include <cstdio>
 #include <cstdlib>
+#include <cstring>
 #include <new>
 
 #include "internal.h"
@@ -34,7 +34,10 @@ namespace {
 // CKTLU_DEBUG=1 in the environment prints the site of every HIP failure.
 bool debug_on() {
     static int v = -1;
-    if (v < 0) { const char *e = getenv("CKTLU_DEBUG"); v = (e && *e && *e != '0') ? 1 : 0; }
+    if (v < 0) {
+        const char *e = getenv("CKTLU_DEBUG");
+        v = (e && *e && *e != '0') ? 1 : 0;
+    }
     return v == 1;
 }
 void debug_hip(int e, const char *what, int line) {
@@ -43,15 +46,15 @@ void debug_hip(int e, const char *what, int line) {
                 hipGetErrorString((hipError_t)e), e);
 }
 
-#define HIPCHK(expr)                                   \
-    do {                                               \
-        hipError_t e_ = (expr);                        \
-        if (e_ != hipSuccess) { debug_hip((int)e_, #expr, __LINE__); return CKTLU_E_HIP; } \
+#define HIPCHK(expr)                                                                          \
+    do {                                                                                      \
+        hipError_t e_ = (expr);                                                               \
+        if (e_ != hipSuccess) { debug_hip((int)e_, #expr, __LINE__); return CKTLU_E_HIP; }   \
     } while (0)
-#define LCHK(expr)                                     \
-    do {                                               \
-        int e_ = (expr);                               \
-        if (e_ != 0) { debug_hip(e_, #expr, __LINE__); return CKTLU_E_HIP; } \
+#define LCHK(expr)                                                                            \
+    do {                                                                                      \
+        int e_ = (expr);                                                                      \
+        if (e_ != 0) { debug_hip(e_, #expr, __LINE__); return CKTLU_E_HIP; }                 \
     } while (0)
 
 inline hipStream_t stream_of(const cktlu_ctx *c) { return (hipStream_t)c->opt.stream; }
@@ -79,11 +82,17 @@ int upload(DevBuf &b, const std::vector<V> &v, hipStream_t st) {
     return CKTLU_OK;
 }
 
+DevBuf *all_buffers(Device &d, int i) {
+    DevBuf *all[] = {&d.seq, &d.Dp, &d.Dlen, &d.Fi, &d.nU, &d.Ap, &d.colperm, &d.amap, &d.Lrp, &d.Lrj,
+                     &d.Lrsrc, &d.Urp, &d.Urj, &d.Ursrc, &d.udiag, &d.lseq, &d.useq, &d.rowperm,
+                     &d.colperm_sol, &d.Acp, &d.Acj, &d.Acsrc, &d.Fx64, &d.Fx32, &d.Aval, &d.done,
+                     &d.ctrl, &d.scratch, &d.vec};
+    const int cnt = (int)(sizeof(all) / sizeof(all[0]));
+    return i < cnt ? all[i] : nullptr;
+}
+
 void free_device(Device &d) {
-    DevBuf *all[] = {&d.seq, &d.Dp, &d.Dlen, &d.Fi, &d.nU, &d.Ap, &d.colperm, &d.amap, &d.Lrp, &d.Lrj, &d.Lrsrc,
-                     &d.Urp, &d.Urj, &d.Ursrc, &d.udiag, &d.rowperm, &d.colperm_sol, &d.Acp, &d.Acj,
-                     &d.Acsrc, &d.Fx64, &d.Fx32, &d.Aval, &d.ready, &d.sready, &d.ctrl, &d.scratch, &d.vec};
-    for (DevBuf *b : all) dfree(*b);
+    for (int i = 0; DevBuf *b = all_buffers(d, i); i++) dfree(*b);
     d.uploaded = false;
     d.batch_cap = 0;
     d.vec_cap = 0;
@@ -106,41 +115,8 @@ void unpad_values(const cktlu_ctx *c, const double *padded, double *compact) {
         std::copy(padded + c->s.Dp[k], padded + c->s.Dp[k] + c->s.Dlen[k], compact + c->f.Fp[k]);
 }
 
-// Control block layout (int32 words, B = batch capacity):
-//   [0] refactor ticket, [1, 1+B) interrupt flags, [1+B, 1+2B) first failing
-//   column, [2B+4] solve ticket, [2B+8, 2B+12) watchdog words (flag, waiting
-//   column, awaited column, ticket).
-// A spin-wait that exceeds kSpinLimit polls (about a second) sets the
-// watchdog word and gives up, so every wavefront always reaches its exit.
-constexpr int kSpinLimit = 1 << 22;
-int *err_word(cktlu_ctx *c) { return (int *)c->dev.ctrl.p + 2 * c->dev.batch_cap + 8; }
-
-// Reads and clears the watchdog word (synchronises the stream).
-int check_watchdog(cktlu_ctx *c) {
-    int w[4] = {0, 0, 0, 0};
-    hipStream_t st = (hipStream_t)c->opt.stream;
-    HIPCHK(hipMemcpyAsync(w, err_word(c), sizeof(w), hipMemcpyDeviceToHost, st));
-    HIPCHK(hipStreamSynchronize(st));
-    if (w[0] != 0) {
-        if (debug_on()) {
-            int h[3];
-            std::vector<int> rd(c->an.n);
-            (void)hipMemcpy(h, c->dev.ctrl.p, sizeof(h), hipMemcpyDeviceToHost);
-            (void)hipMemcpy(rd.data(), c->dev.ready.p, rd.size() * sizeof(int), hipMemcpyDeviceToHost);
-            int done = 0;
-            for (int v : rd) done += v == (int)c->dev.epoch;
-            fprintf(stderr, "[cktlu] watchdog %d: column %d waited on column %d (ticket %d); ticket counter %d, "
-                    "interrupted %d, first fail %d, %d of %d columns ready (epoch %u, ready[awaited]=%d)\n",
-                    w[0], w[1], w[2], w[3], h[0], h[1], h[2], done, c->an.n, c->dev.epoch,
-                    (w[2] >= 0 && w[2] < c->an.n) ? rd[w[2]] : -1);
-        }
-        HIPCHK(hipMemsetAsync(err_word(c), 0, sizeof(w), st));
-        return CKTLU_E_HIP;
-    }
-    return CKTLU_OK;
-}
-
-// Allocate the per-instance buffers for `batch` instances.
+// Status words (int32, B = batch capacity): [1, 1+B) interrupt flags,
+// [1+B, 1+2B) smallest failing column per instance.
 int ensure_batch(cktlu_ctx *c, int batch) {
     Device &d = c->dev;
     if (d.batch_cap >= batch) return CKTLU_OK;
@@ -162,15 +138,12 @@ int ensure_batch(cktlu_ctx *c, int batch) {
         if ((rc = dalloc(d.Fx32, (size_t)F * batch * sizeof(float)))) return rc;
     }
     if ((rc = dalloc(d.Aval, (size_t)c->an.nnz * batch * sizeof(double)))) return rc;
-    dfree(d.ready);
-    if ((rc = dalloc(d.ready, (size_t)n * batch * sizeof(int)))) return rc;
-    HIPCHK(hipMemsetAsync(d.ready.p, 0, (size_t)n * batch * sizeof(int), st));
-    dfree(d.sready);
-    if ((rc = dalloc(d.sready, (size_t)n * batch * sizeof(int)))) return rc;
-    HIPCHK(hipMemsetAsync(d.sready.p, 0, (size_t)n * batch * sizeof(int), st));
+    dfree(d.done);
+    if ((rc = dalloc(d.done, (size_t)n * batch * sizeof(int)))) return rc;
+    HIPCHK(hipMemsetAsync(d.done.p, 0, (size_t)n * batch * sizeof(int), st));
     dfree(d.ctrl);
-    if ((rc = dalloc(d.ctrl, (size_t)(16 + 2 * batch) * sizeof(int)))) return rc;
-    HIPCHK(hipMemsetAsync(d.ctrl.p, 0, (size_t)(16 + 2 * batch) * sizeof(int), st));
+    if ((rc = dalloc(d.ctrl, (size_t)(8 + 2 * batch) * sizeof(int)))) return rc;
+    HIPCHK(hipMemsetAsync(d.ctrl.p, 0, (size_t)(8 + 2 * batch) * sizeof(int), st));
     d.batch_cap = batch;
     return CKTLU_OK;
 }
@@ -181,10 +154,6 @@ int upload_all(cktlu_ctx *c) {
     const Schedule &s = c->s;
     hipStream_t st = stream_of(c);
     int rc;
-    if (d.grid_refactor == 0) {
-        LCHK(occupancy_grid(0, &d.grid_refactor));
-        LCHK(occupancy_grid(1, &d.grid_solve));
-    }
     if ((rc = upload(d.seq, s.seq, st))) return rc;
     if ((rc = upload(d.Dp, s.Dp, st))) return rc;
     if ((rc = upload(d.Dlen, s.Dlen, st))) return rc;
@@ -200,6 +169,8 @@ int upload_all(cktlu_ctx *c) {
     if ((rc = upload(d.Urj, s.Urj, st))) return rc;
     if ((rc = upload(d.Ursrc, s.Ursrc, st))) return rc;
     if ((rc = upload(d.udiag, s.udiag, st))) return rc;
+    if ((rc = upload(d.lseq, s.lseq, st))) return rc;
+    if ((rc = upload(d.useq, s.useq, st))) return rc;
     if ((rc = upload(d.rowperm, s.rowperm_final, st))) return rc;
     if ((rc = upload(d.colperm_sol, c->an.colperm, st))) return rc;
     if ((rc = upload(d.Acp, s.Acp, st))) return rc;
@@ -218,10 +189,17 @@ int upload_all(cktlu_ctx *c) {
     }
     if (c->opt.precision == CKTLU_FP32_IR)
         LCHK(launch_f64_to_f32((const double *)d.Fx64.p, (float *)d.Fx32.p, nnzF(c), st));
-    // overflow work vectors for columns longer than the LDS capacity
+    // overflow work vectors for columns longer than the LDS capacity: one per wavefront of
+    // the widest level that holds such a column
     dfree(d.scratch);
-    if (s.max_col > 1024) {
-        const size_t waves = (size_t)d.grid_refactor * 4;
+    if (s.max_col > kLdsCap) {
+        int widest = 0;
+        for (int l = 0; l < s.nlevels; l++) {
+            bool big = false;
+            for (int t = s.lvl_ptr[l]; t < s.lvl_ptr[l + 1] && !big; t++) big = s.Dlen[s.seq[t]] > kLdsCap;
+            if (big) widest = std::max(widest, s.lvl_ptr[l + 1] - s.lvl_ptr[l]);
+        }
+        const size_t waves = ((size_t)widest * d.batch_cap + 3) / 4 * 4;
         if ((rc = dalloc(d.scratch, waves * (size_t)s.max_col * sizeof(double)))) return rc;
     }
     d.uploaded = true;
@@ -262,7 +240,8 @@ int factor_and_setup(cktlu_ctx *c, const double *values_host, const std::vector<
     int rc = host_gp_factor(c->an, values_host, c->opt.pivot_eps, init, keep ? &c->f : nullptr, keep, nf,
                             fail, nswaps);
     if (rc != CKTLU_OK) return rc;
-    const bool same = !c->f.Fi.empty() && nf.Fi == c->f.Fi && nf.Fp == c->f.Fp;
+    // same pattern and pivot sequence: the device schedule stays valid, only values change
+    const bool same = !c->f.Fi.empty() && nf.Fi == c->f.Fi && nf.Fp == c->f.Fp && nf.pivrow == c->f.pivrow;
     c->f = std::move(nf);
     if (!same || c->s.n != c->an.n) build_schedule(c->an, c->f, c->opt, c->s);
     fill_stats_pattern(c);
@@ -293,13 +272,14 @@ int ensure_device(cktlu_ctx *c) {
     return CKTLU_OK;
 }
 
-// One launch of the refactorization kernel over `batch` instances.
+// The level-by-level refactorization of `batch` instances (cluster mode):
+// one launch per dependency level.
 int run_refactor(cktlu_ctx *c, int batch, const double *values_dev, bool fp32, bool check, int force_col) {
     Device &d = c->dev;
     hipStream_t st = stream_of(c);
     d.epoch++;
-    if (d.epoch == 0 || d.epoch > 0x7ffffff0u) {   // keep flags distinct from the epoch after wrap
-        HIPCHK(hipMemsetAsync(d.ready.p, 0, d.ready.bytes, st));
+    if (d.epoch == 0 || d.epoch > 0x7ffffff0u) {   // keep completion epochs distinct after wrap
+        LCHK(launch_fill_i32((int *)d.done.p, (int64_t)c->an.n * d.batch_cap, 0, st));
         d.epoch = 1;
     }
     LCHK(launch_reset_ctrl((int *)d.ctrl.p, 1 + 2 * batch, INT_MAX, st));
@@ -318,7 +298,7 @@ int run_refactor(cktlu_ctx *c, int batch, const double *values_dev, bool fp32, b
     a.nnzA = c->an.nnz;
     a.nnzF = nnzF(c);
     a.Fx = fp32 ? d.Fx32.p : d.Fx64.p;
-    a.ready = (int *)d.ready.p;
+    a.done = (int *)d.done.p;
     a.ctrl = (int *)d.ctrl.p;
     a.eps = c->opt.pivot_eps;
     a.epoch = d.epoch;
@@ -327,12 +307,8 @@ int run_refactor(cktlu_ctx *c, int batch, const double *values_dev, bool fp32, b
     a.max_col = c->s.max_col;
     a.fp32 = fp32 ? 1 : 0;
     a.check = check ? 1 : 0;
-    a.err = err_word(c);
-    a.spin_limit = kSpinLimit;
-    int grid = d.grid_refactor;
-    const int64_t waves_needed = ((int64_t)a.n * batch + 3) / 4;
-    if (grid > waves_needed) grid = (int)std::max<int64_t>(1, waves_needed);
-    LCHK(launch_refactor(a, grid, st));
+    const Schedule &s = c->s;
+    for (int l = 0; l < s.nlevels; l++) LCHK(launch_refactor_level(a, s.lvl_ptr[l], s.lvl_ptr[l + 1], st));
     return CKTLU_OK;
 }
 
@@ -341,16 +317,16 @@ int run_refactor(cktlu_ctx *c, int batch, const double *values_dev, bool fp32, b
 int fallback(cktlu_ctx *c, const double *values_dev, cktlu_refactor_info *info) {
     const int n = c->an.n;
     hipStream_t st = stream_of(c);
-    std::vector<int> ready(n);
+    std::vector<int> done(n);
     std::vector<double> vals(c->an.nnz);
-    HIPCHK(hipMemcpyAsync(ready.data(), c->dev.ready.p, (size_t)n * sizeof(int), hipMemcpyDeviceToHost, st));
     std::vector<double> padded(nnzF(c));
+    HIPCHK(hipMemcpyAsync(done.data(), c->dev.done.p, (size_t)n * sizeof(int), hipMemcpyDeviceToHost, st));
     HIPCHK(hipMemcpyAsync(padded.data(), c->dev.Fx64.p, padded.size() * sizeof(double), hipMemcpyDeviceToHost, st));
     HIPCHK(hipMemcpyAsync(vals.data(), values_dev, vals.size() * sizeof(double), hipMemcpyDeviceToHost, st));
     HIPCHK(hipStreamSynchronize(st));
     unpad_values(c, padded.data(), c->f.Fx.data());
     std::vector<char> unfinished(n), in_set, keep(n);
-    for (int k = 0; k < n; k++) unfinished[k] = ready[k] != (int)c->dev.epoch;
+    for (int k = 0; k < n; k++) unfinished[k] = done[k] != (int)c->dev.epoch;
     restart_closure(c->an.parent, unfinished, in_set);
     int rsize = 0;
     for (int k = 0; k < n; k++) { keep[k] = !in_set[k]; rsize += in_set[k]; }
@@ -367,15 +343,23 @@ int fallback(cktlu_ctx *c, const double *values_dev, cktlu_refactor_info *info) 
     return CKTLU_OK;
 }
 
+int read_status(cktlu_ctx *c, int *h) {
+    hipStream_t st = stream_of(c);
+    HIPCHK(hipMemcpyAsync(h, c->dev.ctrl.p, 3 * sizeof(int), hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    return CKTLU_OK;
+}
+
 int refactor_single(cktlu_ctx *c, const double *values_dev, cktlu_refactor_info *info, bool check) {
-    if (!c || !values_dev) return CKTLU_E_ARG;
+    if (!c || (!values_dev && c->an.nnz > 0)) return CKTLU_E_ARG;
     if (c->state < 2) return CKTLU_E_STATE;
+    if (info) { info->repivoted = 0; info->first_fail_col = -1; info->restart_size = 0; info->pattern_changed = 0; }
+    if (c->an.n == 0) return CKTLU_OK;
     int rc = ensure_device(c);
     if (rc) return rc;
     if ((rc = ensure_batch(c, 1))) return rc;
     Device &d = c->dev;
     hipStream_t st = stream_of(c);
-    if (info) { info->repivoted = 0; info->first_fail_col = -1; info->restart_size = 0; info->pattern_changed = 0; }
     const bool fp32 = c->opt.precision == CKTLU_FP32_IR;
     const int force = check ? c->force_fail_pending : -1;
     c->force_fail_pending = -1;
@@ -387,22 +371,19 @@ int refactor_single(cktlu_ctx *c, const double *values_dev, cktlu_refactor_info 
     c->dev_values_newer = true;
     if (!check) return CKTLU_OK;
     int h[3];
-    HIPCHK(hipMemcpyAsync(h, d.ctrl.p, 3 * sizeof(int), hipMemcpyDeviceToHost, st));
-    if ((rc = check_watchdog(c))) return rc;
+    if ((rc = read_status(c, h))) return rc;
     if (!h[1]) return CKTLU_OK;
     int first = h[2];
     if (fp32) {
         // pivot decisions come from FP64: retry the check with FP64 arithmetic
         if ((rc = run_refactor(c, 1, values_dev, false, true, force))) return rc;
-        HIPCHK(hipMemcpyAsync(h, d.ctrl.p, 3 * sizeof(int), hipMemcpyDeviceToHost, st));
-        HIPCHK(hipStreamSynchronize(st));
+        if ((rc = read_status(c, h))) return rc;
         if (!h[1]) {
             LCHK(launch_f64_to_f32((const double *)d.Fx64.p, (float *)d.Fx32.p, nnzF(c), st));
             return CKTLU_OK;
         }
         first = h[2];
     }
-    if (info) info->first_fail_col = first;
     if ((rc = fallback(c, values_dev, info))) return rc;
     if (info) info->first_fail_col = first;
     return CKTLU_W_REPIVOTED;
@@ -416,7 +397,7 @@ int ensure_vec(cktlu_ctx *c, size_t doubles) {
     return CKTLU_OK;
 }
 
-// z (interleaved, n x nrhs, batch instances) <- (LU)^{-1} z, in place.
+// z (n rows of YS doubles per instance) <- (LU)^{-1} z, in place; level by level.
 int tri_solves(cktlu_ctx *c, int nrhs, int batch, double *z, bool fp32, const int *skip) {
     Device &d = c->dev;
     hipStream_t st = stream_of(c);
@@ -427,36 +408,29 @@ int tri_solves(cktlu_ctx *c, int nrhs, int batch, double *z, bool fp32, const in
     a.Lrp = (const int *)d.Lrp.p; a.Lrj = (const int *)d.Lrj.p; a.Lrsrc = (const int *)d.Lrsrc.p;
     a.Urp = (const int *)d.Urp.p; a.Urj = (const int *)d.Urj.p; a.Ursrc = (const int *)d.Ursrc.p;
     a.udiag = (const int *)d.udiag.p;
+    a.lseq = (const int *)d.lseq.p;
+    a.useq = (const int *)d.useq.p;
     a.Fx = fp32 ? d.Fx32.p : d.Fx64.p;
     a.nnzF = nnzF(c);
     a.fp32 = fp32 ? 1 : 0;
     a.y = z;
-    a.ready = (int *)d.sready.p;
-    a.ctrl = (int *)d.ctrl.p + 2 * d.batch_cap + 4;   // words after the refactor control block
     a.skip = skip;
-    a.err = err_word(c);
-    a.spin_limit = kSpinLimit;
-    int grid = d.grid_solve;
-    const int64_t waves = ((int64_t)a.n * batch + 3) / 4;
-    if (grid > waves) grid = (int)std::max<int64_t>(1, waves);
-    for (int pass = 0; pass < 2; pass++) {
-        d.sepoch++;
-        if (d.sepoch > 0x7ffffff0u) {
-            HIPCHK(hipMemsetAsync(d.sready.p, 0, d.sready.bytes, st));
-            d.sepoch = 1;
-        }
-        a.epoch = d.sepoch;
-        LCHK(launch_reset_ctrl(a.ctrl, 1, 0, st));
-        if (pass == 0) LCHK(launch_lsolve(a, grid, st));
-        else LCHK(launch_usolve(a, grid, st));
-    }
+    const Schedule &s = c->s;
+    for (int l = 0; l + 1 < (int)s.lsptr.size(); l++) LCHK(launch_lsolve_level(a, s.lsptr[l], s.lsptr[l + 1], st));
+    for (int l = 0; l + 1 < (int)s.usptr.size(); l++) LCHK(launch_usolve_level(a, s.usptr[l], s.usptr[l + 1], st));
     return CKTLU_OK;
+}
+
+// Device work vectors: z = n rows of YS doubles, then r = n x nrhs doubles, then
+// 3 x nrhs norms and one more word.
+size_t vec_need(const cktlu_ctx *c, int nrhs) {
+    return (size_t)c->an.n * YS + 64 + (size_t)c->an.n * nrhs + 3 * (size_t)nrhs + 8;
 }
 
 int solve_chunk(cktlu_ctx *c, int nrhs, const double *b, int64_t ldb, double *x, int64_t ldx, bool fp32,
                 bool accumulate) {
     const int n = c->an.n;
-    int rc = ensure_vec(c, (size_t)n * 8 * 2 + 64);
+    int rc = ensure_vec(c, vec_need(c, nrhs));
     if (rc) return rc;
     double *z = (double *)c->dev.vec.p;
     hipStream_t st = stream_of(c);
@@ -485,9 +459,9 @@ int solve_ir(cktlu_ctx *c, int nrhs, const double *b, int64_t ldb, double *x, in
              cktlu_solve_info *info, bool *converged) {
     const int n = c->an.n;
     hipStream_t st = stream_of(c);
-    int rc = ensure_vec(c, (size_t)n * 8 * 2 + 64 + (size_t)n * nrhs + 3 * (size_t)nrhs + 1);
+    int rc = ensure_vec(c, vec_need(c, nrhs));
     if (rc) return rc;
-    double *r = (double *)c->dev.vec.p + (size_t)n * 16 + 64;
+    double *r = (double *)c->dev.vec.p + (size_t)n * YS + 64;
     double *norms = r + (size_t)n * nrhs;
     for (int q = 0; q < nrhs; q++) HIPCHK(hipMemsetAsync(x + q * ldx, 0, (size_t)n * sizeof(double), st));
     const double *rhs = b;
@@ -619,9 +593,8 @@ int cktlu_factorize(cktlu_ctx *c, const double *values_dev) {
     int rc = factor_and_setup(c, v.data(), nullptr, true);
     if (rc != CKTLU_OK) return rc;
     c->stats.n_factorize++;
-    if (c->opt.precision == CKTLU_FP32_IR) {
-        rc = ensure_batch(c, 1);
-        if (rc) return rc;
+    if (c->an.nnz > 0) {
+        if ((rc = ensure_batch(c, 1))) return rc;
         LCHK(launch_copy_f64(values_dev, (double *)c->dev.Aval.p, c->an.nnz, st));
     }
     return CKTLU_OK;
@@ -647,9 +620,9 @@ int cktlu_solve(cktlu_ctx *c, int32_t nrhs, const double *b, int32_t ldb, double
     if (c->opt.precision == CKTLU_FP64) return solve_plain(c, nrhs, b, ldb, x, ldx, false, false);
     // FP32 factors + FP64 refinement
     hipStream_t st = stream_of(c);
-    if ((rc = ensure_vec(c, (size_t)c->an.n * 16 + 64 + (size_t)c->an.n * nrhs + 3 * (size_t)nrhs + 1))) return rc;
+    if ((rc = ensure_vec(c, vec_need(c, nrhs)))) return rc;
     {
-        double *an = (double *)c->dev.vec.p + (size_t)c->an.n * 16 + 64 + (size_t)c->an.n * nrhs + 3 * nrhs;
+        double *an = (double *)c->dev.vec.p + vec_need(c, nrhs) - 1;
         HIPCHK(hipMemsetAsync(an, 0, sizeof(double), st));
         LCHK(launch_anorm(c->an.n, (const int *)c->dev.Acp.p, (const int *)c->dev.Acsrc.p,
                           (const double *)c->dev.Aval.p, an, st));
@@ -674,11 +647,11 @@ int cktlu_refactorize_batched(cktlu_ctx *c, int32_t batch, const double *values_
     int rc = ensure_device(c);
     if (rc) return rc;
     if ((rc = ensure_batch(c, batch))) return rc;
+    if (c->s.max_col > kLdsCap) return CKTLU_E_LIMIT;   // overflow work vectors are sized for one instance
     const bool fp32 = c->opt.precision == CKTLU_FP32_IR;
     hipStream_t st = stream_of(c);
     LCHK(launch_copy_f64(values_dev, (double *)c->dev.Aval.p, c->an.nnz * (int64_t)batch, st));
     if ((rc = run_refactor(c, batch, values_dev, fp32, true, -1))) return rc;
-    // status: first failing column per instance, -1 when every check passed
     LCHK(launch_status_out((const int *)c->dev.ctrl.p + 1 + batch, status_dev, batch, st));
     c->last_batch = batch;
     c->stats.n_refactorize += batch;
@@ -688,11 +661,18 @@ int cktlu_refactorize_batched(cktlu_ctx *c, int32_t batch, const double *values_
 
 int cktlu_solve_batched(cktlu_ctx *c, int32_t batch, int32_t nrhs, const double *b, double *x,
                         const int32_t *status_dev) {
-    (void)status_dev;
-    if (!c || batch < 1 || nrhs < 1 || !b || !x) return CKTLU_E_ARG;
+    if (!c || batch < 1 || nrhs < 1 || nrhs > 8 || !b || !x) return CKTLU_E_ARG;
     if (c->state < 2 || c->last_batch < batch) return CKTLU_E_STATE;
-    (void)nrhs;
-    return CKTLU_E_LIMIT;   // batched solves: not yet available
+    const int n = c->an.n;
+    int rc = ensure_vec(c, (size_t)n * YS * batch + 64);
+    if (rc) return rc;
+    hipStream_t st = stream_of(c);
+    double *z = (double *)c->dev.vec.p;
+    const bool fp32 = c->opt.precision == CKTLU_FP32_IR;
+    LCHK(launch_gather_rhs(n, nrhs, batch, b, n, (const int *)c->dev.rowperm.p, z, st));
+    if ((rc = tri_solves(c, nrhs, batch, z, fp32, status_dev))) return rc;
+    LCHK(launch_scatter_sol(n, nrhs, batch, z, (const int *)c->dev.colperm_sol.p, x, n, 0, status_dev, st));
+    return CKTLU_OK;
 }
 
 int cktlu_get_perm(const cktlu_ctx *c, int32_t *rowperm, int32_t *colperm) {
@@ -732,27 +712,26 @@ int cktlu_get_factors(cktlu_ctx *c, int32_t instance, int32_t *Lp, int32_t *Li, 
     if (c->state < 2) return CKTLU_E_STATE;
     const int n = c->an.n;
     const int64_t F = nnzF(c);
-    std::vector<double> vals;
+    std::vector<double> compact;
     const double *src = c->f.Fx.data();
     if (c->dev.uploaded && (c->dev_values_newer || instance > 0)) {
         if (instance < 0 || instance >= std::max(1, c->dev.batch_cap)) return CKTLU_E_ARG;
-        vals.resize(F);
+        std::vector<double> padded(F);
         hipStream_t st = stream_of(c);
         if (c->opt.precision == CKTLU_FP32_IR) {
             std::vector<float> v32(F);
             HIPCHK(hipMemcpyAsync(v32.data(), (float *)c->dev.Fx32.p + (size_t)instance * F, F * sizeof(float),
                                   hipMemcpyDeviceToHost, st));
             HIPCHK(hipStreamSynchronize(st));
-            for (int64_t q = 0; q < F; q++) vals[q] = v32[q];
+            for (int64_t q = 0; q < F; q++) padded[q] = v32[q];
         } else {
-            HIPCHK(hipMemcpyAsync(vals.data(), (double *)c->dev.Fx64.p + (size_t)instance * F, F * sizeof(double),
-                                  hipMemcpyDeviceToHost, st));
+            HIPCHK(hipMemcpyAsync(padded.data(), (double *)c->dev.Fx64.p + (size_t)instance * F,
+                                  F * sizeof(double), hipMemcpyDeviceToHost, st));
             HIPCHK(hipStreamSynchronize(st));
         }
-        std::vector<double> compact(c->f.Fx.size());
-        unpad_values(c, vals.data(), compact.data());
-        vals.swap(compact);
-        src = vals.data();
+        compact.resize(c->f.Fx.size());
+        unpad_values(c, padded.data(), compact.data());
+        src = compact.data();
     } else if (instance != 0) {
         return CKTLU_E_ARG;
     }
@@ -790,19 +769,13 @@ int cktlu_get_stats(const cktlu_ctx *c, cktlu_stats *out) {
 
 size_t cktlu_footprint_bytes(const cktlu_ctx *c, int32_t batch) {
     if (!c) return 0;
-    const DevBuf *all[] = {&c->dev.seq, &c->dev.Dp, &c->dev.Dlen, &c->dev.Fi, &c->dev.nU, &c->dev.Ap, &c->dev.colperm,
-                           &c->dev.amap, &c->dev.Lrp, &c->dev.Lrj, &c->dev.Lrsrc, &c->dev.Urp, &c->dev.Urj,
-                           &c->dev.Ursrc, &c->dev.udiag, &c->dev.rowperm, &c->dev.colperm_sol, &c->dev.Acp,
-                           &c->dev.Acj, &c->dev.Acsrc, &c->dev.Fx64, &c->dev.Fx32, &c->dev.Aval,
-                           &c->dev.ready, &c->dev.sready, &c->dev.ctrl, &c->dev.scratch, &c->dev.vec};
+    Device &d = const_cast<Device &>(c->dev);
     size_t s = 0;
-    for (const DevBuf *b : all) s += b->bytes;
-    const int64_t F = c->f.Fp.empty() ? 0 : c->f.Fp[c->an.n];
+    for (int i = 0; DevBuf *b = all_buffers(d, i); i++) s += b->bytes;
+    const int64_t F = c->s.nnz_dev;
     const size_t per = (size_t)F * (c->opt.precision == CKTLU_FP32_IR ? 12 : 8) + (size_t)c->an.nnz * 8 +
-                       (size_t)c->an.n * 8;
-    if (!c->dev.uploaded) {
-        s += (size_t)F * 8 + (size_t)c->an.nnz * 12 + (size_t)c->an.n * 64;
-    }
+                       (size_t)c->an.n * (4 + 8 * YS);
+    if (!c->dev.uploaded) s += (size_t)F * 12 + (size_t)c->an.nnz * 12 + (size_t)c->an.n * 64;
     return s + (batch > 0 ? per * (size_t)batch : 0);
 }
 

@@ -61,23 +61,25 @@ void restart_closure(const std::vector<int> &parent, const std::vector<char> &un
 // ---------------------------------------------------------------- schedule
 struct Schedule {
     int n = 0;
-    std::vector<int> level, seq;              // level of each column; columns by (level, index)
+    // column dependency graph (column k depends on j when U(j,k) != 0): level of
+    // each column, columns ordered by (level, index), and the level boundaries
+    std::vector<int> level, seq, lvl_ptr;
     int nlevels = 0, max_width = 0;
     std::vector<int> amap;                    // user nonzero -> slot offset inside its column
     // device layout of the factor storage: column k occupies [Dp[k], Dp[k] + Dlen[k]);
-    // every column starts on a kColAlign-entry boundary so that no cache line holds
-    // entries of two columns
+    // every column starts on a kColAlign-entry boundary
     std::vector<int> Dp, Dlen, Fi_dev;        // Fi_dev: rows at device positions, padding = INT_MAX
     int64_t nnz_dev = 0;
     // CSR of strictly-lower L and strictly-upper U (position space) for the solves
     std::vector<int> Lrp, Lrj, Lrsrc, Urp, Urj, Ursrc, udiag;
+    // solve dependency graphs: rows by level (L: ascending dependencies, U: descending)
+    std::vector<int> lseq, lsptr, useq, usptr;
     std::vector<int> rowperm_final;           // position k <- user row
     // user-space CSR of A (for the FP64 residual of iterative refinement)
     std::vector<int> Acp, Acj, Acsrc;
     int max_col = 0;                          // longest column of F
     double macs = 0, flops = 0;
-    // dense trailing block [tail0, n)
-    int tail0 = 0;
+    int tail0 = 0;                            // first column of a densely factored tail (n = none)
 };
 
 void build_schedule(const Analysis &an, const Factor &f, const cktlu_options &opt, Schedule &s);
@@ -90,21 +92,19 @@ struct DevBuf {
 
 struct Device {
     bool uploaded = false;
-    int prec = CKTLU_FP64;
     int batch_cap = 0;                 // instances the value buffers hold
     // pattern / schedule
     DevBuf seq, Dp, Dlen, Fi, nU, Ap, colperm, amap;
-    DevBuf Lrp, Lrj, Lrsrc, Urp, Urj, Ursrc, udiag, rowperm, colperm_sol;
+    DevBuf Lrp, Lrj, Lrsrc, Urp, Urj, Ursrc, udiag, lseq, useq, rowperm, colperm_sol;
     DevBuf Acp, Acj, Acsrc;
-    // values and sync words
+    // values and status words
     DevBuf Fx64, Fx32;                 // factor values (FP64 always; FP32 in FP32_IR mode)
     DevBuf Aval;                       // copy of the last values (FP64) for residuals
-    DevBuf ready, sready, ctrl;        // per-column flags, per-row solve flags, control words
+    DevBuf done, ctrl;                 // per-column completion epochs, status words
     DevBuf scratch;                    // per-wave overflow work vectors
     DevBuf vec;                        // solve work vectors
     size_t vec_cap = 0;
-    unsigned epoch = 0, sepoch = 0;
-    int grid_refactor = 0, grid_solve = 0;
+    unsigned epoch = 0;
 };
 
 }  // namespace cktlu
@@ -115,6 +115,7 @@ namespace cktlu_dev {
 
 constexpr int kColAlign = 32;   // factor column alignment in entries (>= one 128-byte line)
 constexpr int YS = 16;          // doubles per solve-vector row (one 128-byte line); nrhs <= 8
+constexpr int kLdsCap = 1024;   // columns up to this length keep their work vector in LDS
 
 struct RefactorArgs {
     int n, batch;
@@ -122,44 +123,39 @@ struct RefactorArgs {
     const double *Aval;        // batch x nnzA
     int64_t nnzA, nnzF;
     void *Fx;                  // batch x nnzF (double or float)
-    int *ready;                // batch x n
-    int *ctrl;                 // [0] ticket, [1..] per-instance interrupt, then first-fail
+    int *done;                 // batch x n: epoch of the last successful computation of each column
+    int *ctrl;                 // [1, 1+batch) interrupt words, [1+batch, 1+2 batch) first failing column
     double eps;
     unsigned epoch;
     int force_fail_col;
-    void *scratch;             // per-wave work vectors of max_col entries
+    void *scratch;             // per-wave work vectors of max_col entries (columns longer than kLdsCap)
     int max_col;
     int fp32, check;
-    int *err;                  // watchdog word: set when a wait exceeds spin_limit
-    int spin_limit;
 };
 
-int launch_refactor(const RefactorArgs &a, int grid, void *stream);
+// Columns seq[lbeg, lend) (one dependency level) for every instance.
+int launch_refactor_level(const RefactorArgs &a, int lbeg, int lend, void *stream);
 int launch_reset_ctrl(int *ctrl, int nwords, int value, void *stream);
 // status[i] = firstfail[i] == INT_MAX ? -1 : firstfail[i]
 int launch_status_out(const int *firstfail, int *status, int batch, void *stream);
 
 struct SolveArgs {
     int n, nrhs, batch;
-    const int *Lrp, *Lrj, *Lrsrc, *Urp, *Urj, *Ursrc, *udiag;
+    const int *Lrp, *Lrj, *Lrsrc, *Urp, *Urj, *Ursrc, *udiag, *lseq, *useq;
     const void *Fx;            // factor values (double or float), batch x nnzF
     int64_t nnzF;
     int fp32;
-    double *y;                 // batch x n x nrhs work (interleaved by rhs)
-    int *ready;                // batch x n
-    int *ctrl;                 // ticket words
-    unsigned epoch;
+    double *y;                 // batch x n rows of YS doubles, rhs r in slot r
     const int *skip;           // per-instance status (-1 = solve), may be null
-    int *err;                  // watchdog word
-    int spin_limit;
 };
 
-int launch_lsolve(const SolveArgs &a, int grid, void *stream);
-int launch_usolve(const SolveArgs &a, int grid, void *stream);
-// y[(i*n + k)*nrhs + r] = b[(i*nrhs + r)*ldb + perm[k]]  (ldb = n for batched)
+// Rows lseq[lbeg, lend) / useq[lbeg, lend) (one level of the solve graph).
+int launch_lsolve_level(const SolveArgs &a, int lbeg, int lend, void *stream);
+int launch_usolve_level(const SolveArgs &a, int lbeg, int lend, void *stream);
+// y[((i*n + k)*YS + r] = b[(i*nrhs + r)*ldb + perm[k]]
 int launch_gather_rhs(int n, int nrhs, int batch, const double *b, int64_t ldb, const int *perm,
                       double *y, void *stream);
-// x[(i*nrhs + r)*ldx + perm[k]] (+)= z[(i*n + k)*nrhs + r]
+// x[(i*nrhs + r)*ldx + perm[k]] (+)= y[(i*n + k)*YS + r]
 int launch_scatter_sol(int n, int nrhs, int batch, const double *z, const int *perm, double *x,
                        int64_t ldx, int accumulate, const int *skip, void *stream);
 // r = b - A x (user space, FP64), per rhs; also writes |r|_inf, |x|_inf, |b|_inf maxima
@@ -170,6 +166,6 @@ int launch_anorm(int n, const int *Acp, const int *Acsrc, const double *Aval, do
                  void *stream);
 int launch_copy_f64(const double *src, double *dst, int64_t count, void *stream);
 int launch_f64_to_f32(const double *src, float *dst, int64_t count, void *stream);
-int occupancy_grid(int kind, int *grid);
+int launch_fill_i32(int *dst, int64_t count, int value, void *stream);
 
 }  // namespace cktlu_dev

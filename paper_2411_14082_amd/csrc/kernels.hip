@@ -1,32 +1,25 @@
 // Device kernels of the cktlu hot path (gfx950).
 //
-// refactor_kernel: fast factorization with pivot check (Section IV-B).  The
-//   paper's cluster mode (level by level) and pipeline mode (an atomic
-//   counter hands out the next node of a dependency-ordered sequence; a node
-//   waits until each predecessor has finished, watching a shared
-//   "interrupted" flag) become one persistent kernel: every wavefront takes
-//   the next column of the level-ordered sequence from a device counter,
-//   applies the left-looking updates of its predecessors in ascending order
-//   as they become ready, tests its pivot against eps times the largest entry
-//   of its L part, stores L and U and publishes a per-column ready flag.  A
-//   failed test records the column and raises the instance's interrupt flag;
-//   waiters see it and stop.  Because the counter hands out columns in
-//   topological order and only running wavefronts hold columns, every awaited
-//   column belongs to a running wavefront; a bounded wait (watchdog) turns any
-//   violation into an error instead of a hang.
+// refactor_level_kernel: fast factorization with pivot check (Section IV-B),
+//   cluster mode: one launch per dependency level of the column graph, one
+//   wavefront per (column, instance) of the level.  Every predecessor of a
+//   column sits in an earlier level, so it is complete when the launch starts
+//   and no wavefront ever waits on another.  A column applies the
+//   left-looking updates of its predecessors in ascending order on a work
+//   vector in LDS, tests its pivot against eps times the largest entry of its
+//   L part, stores U and L = x / pivot, and on failure records its index
+//   (atomic minimum) and raises the instance's interrupt word, which makes all
+//   later levels of that instance return at once (Algorithm 3: the level runs
+//   to its barrier, then the threads exit).
 //
-// trisolve_kernel: triangular solves (Section II-C, Section V) in the row
-//   ("pull") form with per-row ready flags: each wavefront takes the next row,
-//   waits for the solution entries it reads, reduces its dot product in a
-//   fixed order and publishes its own entry.  Deterministic.
+// trisolve_level_kernel: triangular solves (Section II-C, Algorithm 2) in the
+//   row ("pull") form, one launch per level of the solve dependency graph, one
+//   wavefront per (row, instance); each row reduces its dot product in a fixed
+//   order.  Deterministic.
 //
-// Cross-workgroup visibility on a multi-XCD MI355X: each XCD has its own L2,
-// and a plain store can stay in the writer's L2 until the kernel ends.  So
-// every flag is written with an atomic exchange and read with an atomic
-// compare-and-swap (both are performed at the device coherence point), data is
-// written back (release fence) before its flag is set, and every column of the
-// factor storage and every row of the solve vectors starts on its own cache
-// line, so no XCD can hold a line of data it has not yet been signalled for.
+// The level kernels keep all communication between wavefronts at kernel
+// boundaries, where the runtime makes device memory coherent across the
+// MI355X's eight XCDs (each has its own L2).
 #include <hip/hip_runtime.h>
 
 #include <climits>
@@ -40,13 +33,6 @@ constexpr int WAVE = 64;
 constexpr int WG = 256;
 constexpr int WAVES = WG / WAVE;
 constexpr int CAP = 1024;   // LDS work-vector slots per wavefront
-
-__device__ __forceinline__ int flag_read(int *p, int expect) {
-    return atomicCAS(p, expect, expect);   // an RMW: never served from a stale cache line
-}
-__device__ __forceinline__ void flag_write(int *p, int v) { atomicExch(p, v); }
-__device__ __forceinline__ void release_agent() { __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent"); }
-__device__ __forceinline__ void acquire_agent() { __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent"); }
 
 // Orders this wavefront's work-vector accesses (LDS or global) across lanes.
 __device__ __forceinline__ void wave_sync() {
@@ -75,93 +61,51 @@ __device__ __forceinline__ int find_slot(const int *rows, int len, int r) {
     return lo;
 }
 
-// Watchdog: the first wait that exceeds the limit records (waiter, awaited, ticket).
-__device__ __forceinline__ void watchdog_trip(int *err, int code, int waiter, int awaited, int ticket) {
-    if (atomicCAS(err, 0, code) == 0) {
-        atomicExch(err + 1, waiter);
-        atomicExch(err + 2, awaited);
-        atomicExch(err + 3, ticket);
-    }
-}
-
 // ------------------------------------------------------------ refactorize
 template <typename T, bool CHECK>
-__global__ __launch_bounds__(WG) void refactor_kernel(RefactorArgs a) {
+__global__ __launch_bounds__(WG) void refactor_level_kernel(RefactorArgs a, int lbeg, int lend) {
     __shared__ T xs_all[WAVES][CAP];
     __shared__ int rows_all[WAVES][CAP];
     const int lane = threadIdx.x & (WAVE - 1), wv = threadIdx.x / WAVE;
-    T *xl = xs_all[wv];
-    int *rl = rows_all[wv];
-    T *xg = a.scratch ? reinterpret_cast<T *>(a.scratch) + (size_t)(blockIdx.x * WAVES + wv) * a.max_col
-                      : nullptr;
+    const int64_t t = (int64_t)lbeg * a.batch + (int64_t)blockIdx.x * WAVES + wv;
+    if (t >= (int64_t)lend * a.batch) return;
+    const int inst = (int)(t % a.batch);
     int *interrupted = a.ctrl + 1;
     int *firstfail = a.ctrl + 1 + a.batch;
-    const int total = a.n * a.batch;
-    const int epoch = (int)a.epoch;
-    for (;;) {
-        int t = 0;
-        if (lane == 0) t = atomicAdd(a.ctrl, 1);
-        t = __shfl(t, 0);
-        if (t >= total) break;
-        const int inst = t % a.batch;
-        const int k = a.seq[t / a.batch];
-        const int base = a.Dp[k], len = a.Dlen[k], nu = a.nU[k];
-        const int *rowsg = a.Fi + base;
-        T *Fx = reinterpret_cast<T *>(a.Fx) + (size_t)inst * a.nnzF;
-        const double *Av = a.Aval + (size_t)inst * a.nnzA;
-        int *ready = a.ready + (size_t)inst * a.n;
-        const bool inlds = len <= CAP;
-        T *x = inlds ? xl : xg;
-        const int *rows = inlds ? rl : rowsg;
-        for (int i = lane; i < len; i += WAVE) {
-            x[i] = T(0);
-            if (inlds) rl[i] = rowsg[i];
+    if (CHECK && interrupted[inst]) return;          // an earlier level failed its check
+    const int k = a.seq[t / a.batch];
+    const int base = a.Dp[k], len = a.Dlen[k], nu = a.nU[k];
+    const int *rowsg = a.Fi + base;
+    T *Fx = reinterpret_cast<T *>(a.Fx) + (size_t)inst * a.nnzF;
+    const double *Av = a.Aval + (size_t)inst * a.nnzA;
+    const bool inlds = len <= CAP;
+    T *xl = xs_all[wv];
+    int *rl = rows_all[wv];
+    T *x = inlds ? xl : reinterpret_cast<T *>(a.scratch) + (size_t)(blockIdx.x * WAVES + wv) * a.max_col;
+    const int *rows = inlds ? rl : rowsg;
+    for (int i = lane; i < len; i += WAVE) {
+        x[i] = T(0);
+        if (inlds) rl[i] = rowsg[i];
+    }
+    wave_sync();
+    const int c = a.colperm[k];
+    for (int p = a.Ap[c] + lane; p < a.Ap[c + 1]; p += WAVE) x[a.amap[p]] = (T)Av[p];
+    wave_sync();
+    // left-looking update by every predecessor j (rows of U(:,k) above the diagonal), ascending
+    for (int u = 0; u < nu - 1; ++u) {
+        const int j = rows[u];
+        const T xj = x[u];
+        const int lb = a.Dp[j] + a.nU[j], le = a.Dp[j] + a.Dlen[j];
+        for (int q = lb + lane; q < le; q += WAVE) {
+            const int r = a.Fi[q];
+            const T l = Fx[q];
+            const int s = find_slot(rows, len, r);
+            if (s < len) x[s] -= l * xj;   // always found: struct(L(:,j)) is inside struct(col k)
         }
         wave_sync();
-        const int c = a.colperm[k];
-        for (int p = a.Ap[c] + lane; p < a.Ap[c + 1]; p += WAVE) x[a.amap[p]] = (T)Av[p];
-        wave_sync();
-        int abort = 0, ready_upto = 0;
-        for (int u = 0; u < nu - 1; ++u) {
-            if (u >= ready_upto) {
-                // poll the next 64 dependencies in parallel; proceed with the ready prefix
-                int spins = 0;
-                for (;;) {
-                    const int idx = u + lane;
-                    bool ok = true;
-                    if (idx < nu - 1) ok = flag_read(&ready[rows[idx]], epoch) == epoch;
-                    const unsigned long long notok = __ballot(!ok);
-                    const int prefix = notok ? __ffsll((long long)notok) - 1 : WAVE;
-                    if (prefix > 0) { ready_upto = u + prefix; break; }
-                    int stop = 0;
-                    if (lane == 0) {
-                        if (flag_read(&interrupted[inst], 1) != 0) stop = 1;
-                        else if (++spins > a.spin_limit) {
-                            watchdog_trip(a.err, 1, k, rows[u], t);
-                            flag_write(&interrupted[inst], 1);
-                            stop = 1;
-                        }
-                    }
-                    stop = __shfl(stop, 0);
-                    if (stop) { abort = 1; break; }
-                    __builtin_amdgcn_s_sleep(2);
-                }
-                if (abort) break;
-                acquire_agent();
-            }
-            const int j = rows[u];
-            const T xj = x[u];
-            const int lb = a.Dp[j] + a.nU[j], le = a.Dp[j] + a.Dlen[j];
-            for (int q = lb + lane; q < le; q += WAVE) {
-                const int r = a.Fi[q];
-                const T l = Fx[q];
-                const int s = find_slot(rows, len, r);
-                if (s < len) x[s] -= l * xj;   // always found: struct(L(:,j)) is inside struct(col k)
-            }
-            wave_sync();
-        }
-        if (abort) continue;
-        const T d = x[nu - 1];
+    }
+    const T d = x[nu - 1];
+    if (CHECK) {
         double m = 0.0;
         int bad = 0;
         for (int i = nu + lane; i < len; i += WAVE) {
@@ -169,35 +113,29 @@ __global__ __launch_bounds__(WG) void refactor_kernel(RefactorArgs a) {
             if (!isfinite(v)) bad = 1;
             m = fmax(m, fabs(v));
         }
-        bool fail = false;
-        if (CHECK) {
-            m = wave_max(m);
-            bad = __any(bad);
-            const double dd = (double)d;
-            fail = bad || !isfinite(dd) || dd == 0.0 || fabs(dd) < a.eps * m || k == a.force_fail_col;
-        }
-        if (fail) {
+        m = wave_max(m);
+        bad = __any(bad);
+        const double dd = (double)d;
+        if (bad || !isfinite(dd) || dd == 0.0 || fabs(dd) < a.eps * m || k == a.force_fail_col) {
             if (lane == 0) {
                 atomicMin(&firstfail[inst], k);
-                flag_write(&interrupted[inst], 1);
+                atomicExch(&interrupted[inst], 1);
             }
-            continue;
+            return;
         }
-        for (int i = lane; i < nu; i += WAVE) Fx[base + i] = x[i];
-        for (int i = nu + lane; i < len; i += WAVE) Fx[base + i] = x[i] / d;
-        release_agent();
-        if (lane == 0) flag_write(&ready[k], epoch);
     }
+    for (int i = lane; i < nu; i += WAVE) Fx[base + i] = x[i];
+    for (int i = nu + lane; i < len; i += WAVE) Fx[base + i] = x[i] / d;
+    if (CHECK && lane == 0) a.done[(size_t)inst * a.n + k] = (int)a.epoch;
 }
 
 __global__ void reset_ctrl_kernel(int *ctrl, int nwords, int value, int batch) {
-    // ctrl[0] = 0 (ticket); ctrl[1..batch] = 0 (interrupt); the rest = value
+    // ctrl[0] unused; ctrl[1..batch] = 0 (interrupt); the rest = value (first failing column)
     for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < nwords; i += gridDim.x * blockDim.x)
         ctrl[i] = (i == 0 || i <= batch) ? 0 : value;
 }
 
 int launch_reset_ctrl(int *ctrl, int nwords, int value, void *stream) {
-    // layout: [ticket][interrupt x batch][firstfail x batch]; batch = (nwords-1)/2
     const int batch = (nwords - 1) / 2;
     hipLaunchKernelGGL(reset_ctrl_kernel, dim3(1), dim3(256), 0, (hipStream_t)stream, ctrl, nwords,
                        value, batch);
@@ -215,14 +153,16 @@ int launch_status_out(const int *firstfail, int *status, int batch, void *stream
     return (int)hipGetLastError();
 }
 
-int launch_refactor(const RefactorArgs &a, int grid, void *stream) {
+int launch_refactor_level(const RefactorArgs &a, int lbeg, int lend, void *stream) {
     hipStream_t st = (hipStream_t)stream;
+    const int64_t waves = (int64_t)(lend - lbeg) * a.batch;
+    const dim3 grid((unsigned)((waves + WAVES - 1) / WAVES));
     if (a.fp32) {
-        if (a.check) hipLaunchKernelGGL((refactor_kernel<float, true>), dim3(grid), dim3(WG), 0, st, a);
-        else hipLaunchKernelGGL((refactor_kernel<float, false>), dim3(grid), dim3(WG), 0, st, a);
+        if (a.check) hipLaunchKernelGGL((refactor_level_kernel<float, true>), grid, dim3(WG), 0, st, a, lbeg, lend);
+        else hipLaunchKernelGGL((refactor_level_kernel<float, false>), grid, dim3(WG), 0, st, a, lbeg, lend);
     } else {
-        if (a.check) hipLaunchKernelGGL((refactor_kernel<double, true>), dim3(grid), dim3(WG), 0, st, a);
-        else hipLaunchKernelGGL((refactor_kernel<double, false>), dim3(grid), dim3(WG), 0, st, a);
+        if (a.check) hipLaunchKernelGGL((refactor_level_kernel<double, true>), grid, dim3(WG), 0, st, a, lbeg, lend);
+        else hipLaunchKernelGGL((refactor_level_kernel<double, false>), grid, dim3(WG), 0, st, a, lbeg, lend);
     }
     return (int)hipGetLastError();
 }
@@ -230,73 +170,51 @@ int launch_refactor(const RefactorArgs &a, int grid, void *stream) {
 // ----------------------------------------------------------------- solves
 // y holds one cache line (YS doubles) per row and instance: y[(inst*n + i)*YS + r].
 template <typename T, int NR, bool UPPER>
-__global__ __launch_bounds__(WG) void trisolve_kernel(SolveArgs a) {
-    const int lane = threadIdx.x & (WAVE - 1);
-    const int total = a.n * a.batch;
-    const int epoch = (int)a.epoch;
+__global__ __launch_bounds__(WG) void trisolve_level_kernel(SolveArgs a, int lbeg, int lend) {
+    const int lane = threadIdx.x & (WAVE - 1), wv = threadIdx.x / WAVE;
+    const int64_t t = (int64_t)lbeg * a.batch + (int64_t)blockIdx.x * WAVES + wv;
+    if (t >= (int64_t)lend * a.batch) return;
+    const int inst = (int)(t % a.batch);
+    if (a.skip && a.skip[inst] != -1) return;
+    const int i = (UPPER ? a.useq : a.lseq)[t / a.batch];
     const int *rp = UPPER ? a.Urp : a.Lrp;
     const int *rj = UPPER ? a.Urj : a.Lrj;
     const int *rs = UPPER ? a.Ursrc : a.Lrsrc;
-    for (;;) {
-        int t = 0;
-        if (lane == 0) t = atomicAdd(a.ctrl, 1);
-        t = __shfl(t, 0);
-        if (t >= total) break;
-        const int inst = t % a.batch;
-        const int i = UPPER ? a.n - 1 - t / a.batch : t / a.batch;
-        if (a.skip && a.skip[inst] != -1) continue;
-        const T *Fx = reinterpret_cast<const T *>(a.Fx) + (size_t)inst * a.nnzF;
-        double *y = a.y + (size_t)inst * a.n * YS;
-        int *ready = a.ready + (size_t)inst * a.n;
-        double acc[NR];
+    const T *Fx = reinterpret_cast<const T *>(a.Fx) + (size_t)inst * a.nnzF;
+    double *y = a.y + (size_t)inst * a.n * YS;
+    double acc[NR];
 #pragma unroll
-        for (int r = 0; r < NR; r++) acc[r] = 0.0;
-        for (int q0 = rp[i]; q0 < rp[i + 1]; q0 += WAVE) {
-            const int q = q0 + lane;
-            const bool act = q < rp[i + 1];
-            const int j = act ? rj[q] : 0;
-            const double l = act ? (double)Fx[rs[q]] : 0.0;
-            bool ok = !act || flag_read(&ready[j], epoch) == epoch;
-            int spins = 0;
-            while (!__all(ok)) {
-                if (!ok) ok = flag_read(&ready[j], epoch) == epoch;
-                if (++spins > a.spin_limit) {   // watchdog: never wait forever
-                    if (lane == 0) watchdog_trip(a.err, 2, i, j, t);
-                    break;
-                }
-                __builtin_amdgcn_s_sleep(2);
-            }
-            acquire_agent();
-            if (act) {
+    for (int r = 0; r < NR; r++) acc[r] = 0.0;
+    for (int q = rp[i] + lane; q < rp[i + 1]; q += WAVE) {
+        const int j = rj[q];
+        const double l = (double)Fx[rs[q]];
 #pragma unroll
-                for (int r = 0; r < NR; r++) acc[r] += l * y[(size_t)j * YS + r];
-            }
-        }
+        for (int r = 0; r < NR; r++) acc[r] += l * y[(size_t)j * YS + r];
+    }
 #pragma unroll
-        for (int r = 0; r < NR; r++) acc[r] = wave_sum(acc[r]);
-        double mine = acc[0];
+    for (int r = 0; r < NR; r++) acc[r] = wave_sum(acc[r]);
+    double mine = acc[0];
 #pragma unroll
-        for (int r = 1; r < NR; r++)
-            if (lane == r) mine = acc[r];
-        if (lane < NR) {
-            double v = y[(size_t)i * YS + lane] - mine;
-            if (UPPER) v = v / (double)Fx[a.udiag[i]];
-            y[(size_t)i * YS + lane] = v;
-        }
-        release_agent();
-        if (lane == 0) flag_write(&ready[i], epoch);
+    for (int r = 1; r < NR; r++)
+        if (lane == r) mine = acc[r];
+    if (lane < NR) {
+        double v = y[(size_t)i * YS + lane] - mine;
+        if (UPPER) v = v / (double)Fx[a.udiag[i]];
+        y[(size_t)i * YS + lane] = v;
     }
 }
 
 template <bool UPPER>
-static int launch_solve_impl(const SolveArgs &a, int grid, void *stream) {
+static int launch_solve_level_impl(const SolveArgs &a, int lbeg, int lend, void *stream) {
     hipStream_t st = (hipStream_t)stream;
-#define CKTLU_SOLVE_CASE(NRV)                                                                    \
-    case NRV:                                                                                    \
-        if (a.fp32)                                                                              \
-            hipLaunchKernelGGL((trisolve_kernel<float, NRV, UPPER>), dim3(grid), dim3(WG), 0, st, a); \
-        else                                                                                     \
-            hipLaunchKernelGGL((trisolve_kernel<double, NRV, UPPER>), dim3(grid), dim3(WG), 0, st, a); \
+    const int64_t waves = (int64_t)(lend - lbeg) * a.batch;
+    const dim3 grid((unsigned)((waves + WAVES - 1) / WAVES));
+#define CKTLU_SOLVE_CASE(NRV)                                                                          \
+    case NRV:                                                                                          \
+        if (a.fp32)                                                                                    \
+            hipLaunchKernelGGL((trisolve_level_kernel<float, NRV, UPPER>), grid, dim3(WG), 0, st, a, lbeg, lend); \
+        else                                                                                           \
+            hipLaunchKernelGGL((trisolve_level_kernel<double, NRV, UPPER>), grid, dim3(WG), 0, st, a, lbeg, lend); \
         break;
     switch (a.nrhs) {
         CKTLU_SOLVE_CASE(1)
@@ -309,8 +227,12 @@ static int launch_solve_impl(const SolveArgs &a, int grid, void *stream) {
     return (int)hipGetLastError();
 }
 
-int launch_lsolve(const SolveArgs &a, int grid, void *stream) { return launch_solve_impl<false>(a, grid, stream); }
-int launch_usolve(const SolveArgs &a, int grid, void *stream) { return launch_solve_impl<true>(a, grid, stream); }
+int launch_lsolve_level(const SolveArgs &a, int lbeg, int lend, void *stream) {
+    return launch_solve_level_impl<false>(a, lbeg, lend, stream);
+}
+int launch_usolve_level(const SolveArgs &a, int lbeg, int lend, void *stream) {
+    return launch_solve_level_impl<true>(a, lbeg, lend, stream);
+}
 
 // --------------------------------------------------------------- helpers
 __global__ void gather_rhs_kernel(int n, int nrhs, int batch, const double *b, int64_t ldb,
@@ -416,6 +338,11 @@ __global__ void f64_to_f32_kernel(const double *src, float *dst, int64_t count) 
         dst[i] = (float)src[i];
 }
 
+__global__ void fill_i32_kernel(int *dst, int64_t count, int value) {
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < count; i += (int64_t)gridDim.x * blockDim.x)
+        dst[i] = value;
+}
+
 int launch_copy_f64(const double *src, double *dst, int64_t count, void *stream) {
     hipLaunchKernelGGL(copy_f64_kernel, dim3(grid_for(count, 256)), dim3(256), 0, (hipStream_t)stream, src, dst,
                        count);
@@ -428,21 +355,10 @@ int launch_f64_to_f32(const double *src, float *dst, int64_t count, void *stream
     return (int)hipGetLastError();
 }
 
-// Resident workgroups of the persistent kernels (kind 0: refactorize, 1: solve).
-int occupancy_grid(int kind, int *grid) {
-    int dev = 0, cus = 0, per = 0;
-    hipError_t e = hipGetDevice(&dev);
-    if (e != hipSuccess) return (int)e;
-    e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
-    if (e != hipSuccess) return (int)e;
-    if (kind == 0)
-        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, refactor_kernel<double, true>, WG, 0);
-    else
-        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, trisolve_kernel<double, 1, false>, WG, 0);
-    if (e != hipSuccess) return (int)e;
-    if (per < 1) per = 1;
-    *grid = cus * per;
-    return 0;
+int launch_fill_i32(int *dst, int64_t count, int value, void *stream) {
+    hipLaunchKernelGGL(fill_i32_kernel, dim3(grid_for(count, 256)), dim3(256), 0, (hipStream_t)stream, dst, count,
+                       value);
+    return (int)hipGetLastError();
 }
 
 }  // namespace cktlu_dev

@@ -47,6 +47,7 @@ void build_schedule(const Analysis &an, const Factor &f, const cktlu_options &op
         s.max_width = std::max(s.max_width, cnt[l + 1]);
         cnt[l + 1] += cnt[l];
     }
+    s.lvl_ptr.assign(cnt.begin(), cnt.end());                    // level l = seq[lvl_ptr[l], lvl_ptr[l+1])
     s.seq.resize(n);
     for (int k = 0; k < n; k++) s.seq[cnt[s.level[k]]++] = k;   // ascending k inside a level
     // ---- value map: user nonzero p -> slot offset inside its factor column
@@ -89,6 +90,36 @@ void build_schedule(const Analysis &an, const Factor &f, const cktlu_options &op
             for (int64_t q = b; q < d; q++) { int i = f.Fi[q]; s.Urj[uf[i]] = k; s.Ursrc[uf[i]++] = dpos(k, q); }
             for (int64_t q = d + 1; q < e; q++) { int i = f.Fi[q]; s.Lrj[lf[i]] = k; s.Lrsrc[lf[i]++] = dpos(k, q); }
         }
+    }
+    // ---- solve levels: row i of L waits for every j with L(i,j) != 0; row i of U for j > i
+    auto order_by_level = [n](const std::vector<int> &lev, int nl, std::vector<int> &seq,
+                              std::vector<int> &ptr) {
+        std::vector<int> c(nl + 1, 0);
+        for (int i = 0; i < n; i++) c[lev[i] + 1]++;
+        for (int l = 0; l < nl; l++) c[l + 1] += c[l];
+        ptr.assign(c.begin(), c.end());
+        seq.resize(n);
+        for (int i = 0; i < n; i++) seq[c[lev[i]]++] = i;
+    };
+    {
+        std::vector<int> lev(n, 0);
+        int nl = n ? 1 : 0;
+        for (int i = 0; i < n; i++) {
+            int v = 0;
+            for (int q = s.Lrp[i]; q < s.Lrp[i + 1]; q++) v = std::max(v, lev[s.Lrj[q]] + 1);
+            lev[i] = v;
+            nl = std::max(nl, v + 1);
+        }
+        order_by_level(lev, nl, s.lseq, s.lsptr);
+        std::fill(lev.begin(), lev.end(), 0);
+        nl = n ? 1 : 0;
+        for (int i = n - 1; i >= 0; i--) {
+            int v = 0;
+            for (int q = s.Urp[i]; q < s.Urp[i + 1]; q++) v = std::max(v, lev[s.Urj[q]] + 1);
+            lev[i] = v;
+            nl = std::max(nl, v + 1);
+        }
+        order_by_level(lev, nl, s.useq, s.usptr);
     }
     s.rowperm_final.resize(n);
     for (int k = 0; k < n; k++) s.rowperm_final[k] = an.rowperm_pre[f.pivrow[k]];

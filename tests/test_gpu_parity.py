@@ -126,30 +126,49 @@ def test_forced_failure_fallback(ck, oracle_mod):
         ck.cktlu_destroy(ctx)
 
 
-def test_value_driven_repivot_matches_oracle(ck, oracle_mod):
-    """A value change that breaks the threshold test at a chosen column: the GPU
-    check fails, the fallback re-pivots, and pattern + pivots equal the oracle's
-    re-factorization from the previous sequence."""
-    c = mnagen.random_pattern(120, 0.03, 21)
-    eps = 0.1
-    s = ck.SparseLU(c.n, c.colptr, c.rowind, eps=eps)
+def _pivot_entry(c, a, k):
+    """Index of the user nonzero that holds the current pivot of column k."""
+    r = a["rowperm_pre"][a["pivrow"][k]]
+    col = a["colperm"][k]
+    lo, hi = c.colptr[col], c.colptr[col + 1]
+    p = lo + int(np.searchsorted(c.rowind[lo:hi], r))
+    assert c.rowind[p] == r
+    return p
+
+
+@pytest.mark.parametrize("nfail", [1, 3])
+def test_value_driven_repivot_matches_oracle(ck, oracle_mod, nfail):
+    """Pivots of level-0 columns shrunk by 1e-8: the GPU check must fail, the
+    fallback re-pivots, and pattern + pivot sequence equal the oracle's
+    re-factorization from the previous sequence; values within rounding."""
+    c = mnagen.mesh_transistor(30, 30, seed=21)
+    s = ck.SparseLU(c.n, c.colptr, c.rowind, eps=EPS)
     s.factorize(dev(c.values))
     a0 = s.analysis()
-    rng = np.random.default_rng(1)
-    hits = 0
-    for trial in range(12):
-        vh = c.values * rng.uniform(0.2, 5.0, c.values.shape)
-        lu = oracle_refactor(oracle_mod, c, vh, a0, eps, s.analysis()["pivrow"])
-        if lu.status != 0:
-            continue
-        rc, info = s.refactorize(dev(vh))
-        a = s.analysis()
-        assert np.array_equal(a["pivrow"], lu.pivrow), trial
-        compare_factors(s.factors(), lu, RTOL)
-        hits += int(lu.nswaps > 0)
-        if lu.nswaps > 0:
-            assert rc == ck.CKTLU_W_REPIVOTED
-    assert hits >= 1
+    lev = s.levels()
+    f0 = s.factors()
+    nl = np.diff(f0["Lp"])
+    cand = [k for k in range(c.n) if lev[k] == 0 and nl[k] > 0]
+    chosen = [cand[len(cand) * (i + 1) // (nfail + 1)] for i in range(nfail)]
+    vh = mnagen.perturb(c.values, 21, 0, 1)
+    for k in chosen:
+        vh[_pivot_entry(c, a0, k)] *= 1e-8
+    lu = oracle_refactor(oracle_mod, c, vh, a0, EPS, a0["pivrow"])
+    assert lu.status == 0 and lu.nswaps >= nfail
+    rc, info = s.refactorize(dev(vh))
+    assert rc == ck.CKTLU_W_REPIVOTED and info.repivoted == 1
+    assert info.first_fail_col == min(chosen)
+    a = s.analysis()
+    assert np.array_equal(a["pivrow"], lu.pivrow)
+    compare_factors(s.factors(), lu, RTOL)
+    # the next refactorization with the same values keeps the new sequence
+    rc2, info2 = s.refactorize(dev(vh))
+    assert rc2 == 0 and info2.repivoted == 0
+    compare_factors(s.factors(), lu, RTOL)
+    x = torch.zeros(c.n, dtype=torch.float64, device="cuda:0")
+    s.solve(dev(c.rhs[0]), x)
+    torch.cuda.synchronize()
+    assert oracle_mod.backward_error(c.colptr, c.rowind, vh, x.cpu().numpy(), c.rhs[0]) <= 1e-12
 
 
 @pytest.mark.parametrize("nrhs", [1, 3, 8])
@@ -171,9 +190,12 @@ def test_fp32_ir(ck, oracle_mod):
     c = mnagen.mesh_transistor(50, 50, seed=12)
     s = ck.SparseLU(c.n, c.colptr, c.rowind, eps=EPS, precision=ck.CKTLU_FP32_IR, ir_tol=1e-10)
     s.factorize(dev(c.values))
+    a0 = s.analysis()
     vh = mnagen.perturb(c.values, 12, 0, 1)
+    lu = oracle_refactor(oracle_mod, c, vh, a0, EPS, a0["pivrow"])
     rc, info = s.refactorize(dev(vh))
-    assert rc == 0
+    assert rc == (ck.CKTLU_W_REPIVOTED if lu.nswaps else 0)
+    assert np.array_equal(s.analysis()["pivrow"], lu.pivrow)
     b = c.rhs[0]
     x = torch.zeros(c.n, dtype=torch.float64, device="cuda:0")
     rc, sinfo = s.solve(dev(b), x)
@@ -181,9 +203,7 @@ def test_fp32_ir(ck, oracle_mod):
     xg = x.cpu().numpy()
     eta = oracle_mod.backward_error(c.colptr, c.rowind, vh, xg, b)
     assert eta <= 1e-10, (eta, sinfo.ir_iters, sinfo.used_fp64)
-    a = s.analysis()
-    lu = oracle_refactor(oracle_mod, c, vh, a, EPS, a["pivrow"])
-    xo = oracle_mod.solve(lu, a["rowperm_pre"], a["colperm"], b)
+    xo = oracle_mod.solve(lu, a0["rowperm_pre"], a0["colperm"], b)
     assert np.abs(xg - xo).max() <= 1e-6 * np.abs(xo).max()
 
 
