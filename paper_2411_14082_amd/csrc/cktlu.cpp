@@ -83,10 +83,11 @@ int upload(DevBuf &b, const std::vector<V> &v, hipStream_t st) {
 }
 
 DevBuf *all_buffers(Device &d, int i) {
-    DevBuf *all[] = {&d.seq, &d.Dp, &d.Dlen, &d.Fi, &d.nU, &d.Ap, &d.colperm, &d.amap, &d.Lrp, &d.Lrj,
+    DevBuf *all[] = {&d.seq, &d.Dp, &d.Dlen, &d.Fi, &d.nU, &d.Ap, &d.colperm, &d.amap, &d.task_tgt,
+                     &d.src_ptr, &d.src_col, &d.src_slot, &d.Lrp, &d.Lrj,
                      &d.Lrsrc, &d.Urp, &d.Urj, &d.Ursrc, &d.udiag, &d.lseq, &d.useq, &d.rowperm,
                      &d.colperm_sol, &d.Acp, &d.Acj, &d.Acsrc, &d.Fx64, &d.Fx32, &d.Aval, &d.done,
-                     &d.ctrl, &d.scratch, &d.vec};
+                     &d.ctrl, &d.vec};
     const int cnt = (int)(sizeof(all) / sizeof(all[0]));
     return i < cnt ? all[i] : nullptr;
 }
@@ -162,6 +163,10 @@ int upload_all(cktlu_ctx *c) {
     if ((rc = upload(d.Ap, c->an.Ap, st))) return rc;
     if ((rc = upload(d.colperm, c->an.colperm, st))) return rc;
     if ((rc = upload(d.amap, s.amap, st))) return rc;
+    if ((rc = upload(d.task_tgt, s.task_tgt, st))) return rc;
+    if ((rc = upload(d.src_ptr, s.src_ptr, st))) return rc;
+    if ((rc = upload(d.src_col, s.src_col, st))) return rc;
+    if ((rc = upload(d.src_slot, s.src_slot, st))) return rc;
     if ((rc = upload(d.Lrp, s.Lrp, st))) return rc;
     if ((rc = upload(d.Lrj, s.Lrj, st))) return rc;
     if ((rc = upload(d.Lrsrc, s.Lrsrc, st))) return rc;
@@ -189,19 +194,6 @@ int upload_all(cktlu_ctx *c) {
     }
     if (c->opt.precision == CKTLU_FP32_IR)
         LCHK(launch_f64_to_f32((const double *)d.Fx64.p, (float *)d.Fx32.p, nnzF(c), st));
-    // overflow work vectors for columns longer than the LDS capacity: one per wavefront of
-    // the widest level that holds such a column
-    dfree(d.scratch);
-    if (s.max_col > kLdsCap) {
-        int widest = 0;
-        for (int l = 0; l < s.nlevels; l++) {
-            bool big = false;
-            for (int t = s.lvl_ptr[l]; t < s.lvl_ptr[l + 1] && !big; t++) big = s.Dlen[s.seq[t]] > kLdsCap;
-            if (big) widest = std::max(widest, s.lvl_ptr[l + 1] - s.lvl_ptr[l]);
-        }
-        const size_t waves = ((size_t)widest * d.batch_cap + 3) / 4 * 4;
-        if ((rc = dalloc(d.scratch, waves * (size_t)s.max_col * sizeof(double)))) return rc;
-    }
     d.uploaded = true;
     c->dev_values_newer = false;
     return CKTLU_OK;
@@ -303,12 +295,21 @@ int run_refactor(cktlu_ctx *c, int batch, const double *values_dev, bool fp32, b
     a.eps = c->opt.pivot_eps;
     a.epoch = d.epoch;
     a.force_fail_col = force_col;
-    a.scratch = d.scratch.p;
-    a.max_col = c->s.max_col;
+    a.task_tgt = (const int *)d.task_tgt.p;
+    a.src_ptr = (const int *)d.src_ptr.p;
+    a.src_col = (const int *)d.src_col.p;
+    a.src_slot = (const int *)d.src_slot.p;
     a.fp32 = fp32 ? 1 : 0;
     a.check = check ? 1 : 0;
     const Schedule &s = c->s;
-    for (int l = 0; l < s.nlevels; l++) LCHK(launch_refactor_level(a, s.lvl_ptr[l], s.lvl_ptr[l + 1], st));
+    LCHK(launch_refactor_init(a, st));
+    // level l: check level l, normalise level l-1, update tasks of level l; then normalise the last
+    for (int l = 0; l <= s.n_rlevels; l++) {
+        const int cb = l < s.n_rlevels ? s.lvl_ptr[l] : 0, ce = l < s.n_rlevels ? s.lvl_ptr[l + 1] : 0;
+        const int pb = l > 0 ? s.lvl_ptr[l - 1] : 0, pe = l > 0 ? s.lvl_ptr[l] : 0;
+        const int tb = l < s.n_rlevels ? s.task_ptr[l] : 0, te = l < s.n_rlevels ? s.task_ptr[l + 1] : 0;
+        LCHK(launch_refactor_level(a, cb, ce, pb, pe, tb, te, st));
+    }
     return CKTLU_OK;
 }
 
@@ -647,7 +648,6 @@ int cktlu_refactorize_batched(cktlu_ctx *c, int32_t batch, const double *values_
     int rc = ensure_device(c);
     if (rc) return rc;
     if ((rc = ensure_batch(c, batch))) return rc;
-    if (c->s.max_col > kLdsCap) return CKTLU_E_LIMIT;   // overflow work vectors are sized for one instance
     const bool fp32 = c->opt.precision == CKTLU_FP32_IR;
     hipStream_t st = stream_of(c);
     LCHK(launch_copy_f64(values_dev, (double *)c->dev.Aval.p, c->an.nnz * (int64_t)batch, st));

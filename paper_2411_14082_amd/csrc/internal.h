@@ -61,10 +61,17 @@ void restart_closure(const std::vector<int> &parent, const std::vector<char> &un
 // ---------------------------------------------------------------- schedule
 struct Schedule {
     int n = 0;
-    // column dependency graph (column k depends on j when U(j,k) != 0): level of
-    // each column, columns ordered by (level, index), and the level boundaries
-    std::vector<int> level, seq, lvl_ptr;
+    // elimination graph (column k depends on j when U(j,k) != 0): level of each column
+    std::vector<int> level;
     int nlevels = 0, max_width = 0;
+    // right-looking schedule: columns by (rlevel, index) and the rlevel boundaries
+    std::vector<int> seq, lvl_ptr;
+    int n_rlevels = 0;
+    // right-looking update tasks: level l owns tasks [task_ptr[l], task_ptr[l+1]); task t
+    // updates target column task_tgt[t] with the sources src_col[src_ptr[t] .. src_ptr[t+1])
+    // (columns of level l, ascending); src_slot is the offset of the source's row in the
+    // target column (where the multiplier U(j,k) lives)
+    std::vector<int> task_ptr, task_tgt, src_ptr, src_col, src_slot;
     std::vector<int> amap;                    // user nonzero -> slot offset inside its column
     // device layout of the factor storage: column k occupies [Dp[k], Dp[k] + Dlen[k]);
     // every column starts on a kColAlign-entry boundary
@@ -95,13 +102,13 @@ struct Device {
     int batch_cap = 0;                 // instances the value buffers hold
     // pattern / schedule
     DevBuf seq, Dp, Dlen, Fi, nU, Ap, colperm, amap;
+    DevBuf task_tgt, src_ptr, src_col, src_slot;
     DevBuf Lrp, Lrj, Lrsrc, Urp, Urj, Ursrc, udiag, lseq, useq, rowperm, colperm_sol;
     DevBuf Acp, Acj, Acsrc;
     // values and status words
     DevBuf Fx64, Fx32;                 // factor values (FP64 always; FP32 in FP32_IR mode)
     DevBuf Aval;                       // copy of the last values (FP64) for residuals
     DevBuf done, ctrl;                 // per-column completion epochs, status words
-    DevBuf scratch;                    // per-wave overflow work vectors
     DevBuf vec;                        // solve work vectors
     size_t vec_cap = 0;
     unsigned epoch = 0;
@@ -115,11 +122,11 @@ namespace cktlu_dev {
 
 constexpr int kColAlign = 32;   // factor column alignment in entries (>= one 128-byte line)
 constexpr int YS = 16;          // doubles per solve-vector row (one 128-byte line); nrhs <= 8
-constexpr int kLdsCap = 1024;   // columns up to this length keep their work vector in LDS
 
 struct RefactorArgs {
     int n, batch;
     const int *seq, *Dp, *Dlen, *Fi, *nU, *Ap, *colperm, *amap;
+    const int *task_tgt, *src_ptr, *src_col, *src_slot;   // right-looking update tasks
     const double *Aval;        // batch x nnzA
     int64_t nnzA, nnzF;
     void *Fx;                  // batch x nnzF (double or float)
@@ -128,13 +135,15 @@ struct RefactorArgs {
     double eps;
     unsigned epoch;
     int force_fail_col;
-    void *scratch;             // per-wave work vectors of max_col entries (columns longer than kLdsCap)
-    int max_col;
     int fp32, check;
 };
 
-// Columns seq[lbeg, lend) (one dependency level) for every instance.
-int launch_refactor_level(const RefactorArgs &a, int lbeg, int lend, void *stream);
+// Zero every factor column and scatter the matrix values into it.
+int launch_refactor_init(const RefactorArgs &a, void *stream);
+// One right-looking level: pivot check of columns seq[cbeg, cend), normalisation of the
+// previous level seq[pbeg, pend) (L = x / pivot), and update tasks [tbeg, tend).
+int launch_refactor_level(const RefactorArgs &a, int cbeg, int cend, int pbeg, int pend, int tbeg,
+                          int tend, void *stream);
 int launch_reset_ctrl(int *ctrl, int nwords, int value, void *stream);
 // status[i] = firstfail[i] == INT_MAX ? -1 : firstfail[i]
 int launch_status_out(const int *firstfail, int *status, int batch, void *stream);

@@ -1,25 +1,30 @@
 // Device kernels of the cktlu hot path (gfx950).
 //
-// refactor_level_kernel: fast factorization with pivot check (Section IV-B),
-//   cluster mode: one launch per dependency level of the column graph, one
-//   wavefront per (column, instance) of the level.  Every predecessor of a
-//   column sits in an earlier level, so it is complete when the launch starts
-//   and no wavefront ever waits on another.  A column applies the
-//   left-looking updates of its predecessors in ascending order on a work
-//   vector in LDS, tests its pivot against eps times the largest entry of its
-//   L part, stores U and L = x / pivot, and on failure records its index
-//   (atomic minimum) and raises the instance's interrupt word, which makes all
-//   later levels of that instance return at once (Algorithm 3: the level runs
-//   to its barrier, then the threads exit).
+// Refactorization (fast factorization with pivot check, Section IV-B) runs as
+// right-looking sweeps over dependency levels, one launch per level:
+//   refactor_init_kernel   zeroes every factor column and scatters the matrix
+//                          values into it (one wavefront per column);
+//   refactor_level_kernel  for level l: (a) tests the pivot of every column of
+//                          level l against eps times the largest entry of its L
+//                          part (its values are final: every update came from an
+//                          earlier level); (b) divides the L part of every column
+//                          of level l-1 by its pivot; (c) runs the update tasks of
+//                          level l: a task owns one target column k and applies
+//                          x_k -= L(:,j) * U(j,k) for every source j of level l
+//                          with U(j,k) != 0, in ascending j, so no two wavefronts
+//                          write the same column and results are bit-reproducible.
+// This is the paper's cluster mode (Algorithm 3) with the left-looking column
+// update of the paper turned around: a column's updates are spread over the
+// levels of its sources, so the critical path is the number of levels, not the
+// length of a column's update list.  A failed test records the column (atomic
+// minimum) and raises the instance's interrupt word; later levels of that
+// instance return at once.
 //
-// trisolve_level_kernel: triangular solves (Section II-C, Algorithm 2) in the
-//   row ("pull") form, one launch per level of the solve dependency graph, one
-//   wavefront per (row, instance); each row reduces its dot product in a fixed
-//   order.  Deterministic.
+// Solves (Section II-C, Algorithm 2): trisolve_level_kernel, row ("pull") form,
+// one launch per level of the solve dependency graph, one wavefront per row.
 //
-// The level kernels keep all communication between wavefronts at kernel
-// boundaries, where the runtime makes device memory coherent across the
-// MI355X's eight XCDs (each has its own L2).
+// All communication between wavefronts happens at kernel boundaries, where the
+// runtime makes device memory coherent across the MI355X's eight XCDs.
 #include <hip/hip_runtime.h>
 
 #include <climits>
@@ -32,9 +37,8 @@ namespace cktlu_dev {
 constexpr int WAVE = 64;
 constexpr int WG = 256;
 constexpr int WAVES = WG / WAVE;
-constexpr int CAP = 1024;   // LDS work-vector slots per wavefront
 
-// Orders this wavefront's work-vector accesses (LDS or global) across lanes.
+// Orders this wavefront's global-memory accesses across its lanes.
 __device__ __forceinline__ void wave_sync() {
     __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "workgroup");
     __builtin_amdgcn_wave_barrier();
@@ -51,61 +55,44 @@ __device__ __forceinline__ double wave_sum(double v) {
     return v;
 }
 
-// first index in rows[0, len) with rows[idx] >= r
-__device__ __forceinline__ int find_slot(const int *rows, int len, int r) {
-    int lo = 0, hi = len;
-    while (lo < hi) {
-        int mid = (lo + hi) >> 1;
-        if (rows[mid] < r) lo = mid + 1; else hi = mid;
-    }
-    return lo;
-}
-
 // ------------------------------------------------------------ refactorize
-template <typename T, bool CHECK>
-__global__ __launch_bounds__(WG) void refactor_level_kernel(RefactorArgs a, int lbeg, int lend) {
-    __shared__ T xs_all[WAVES][CAP];
-    __shared__ int rows_all[WAVES][CAP];
+// one wavefront per (column, instance)
+template <typename T>
+__global__ __launch_bounds__(WG) void refactor_init_kernel(RefactorArgs a) {
     const int lane = threadIdx.x & (WAVE - 1), wv = threadIdx.x / WAVE;
-    const int64_t t = (int64_t)lbeg * a.batch + (int64_t)blockIdx.x * WAVES + wv;
-    if (t >= (int64_t)lend * a.batch) return;
-    const int inst = (int)(t % a.batch);
-    int *interrupted = a.ctrl + 1;
-    int *firstfail = a.ctrl + 1 + a.batch;
-    if (CHECK && interrupted[inst]) return;          // an earlier level failed its check
-    const int k = a.seq[t / a.batch];
-    const int base = a.Dp[k], len = a.Dlen[k], nu = a.nU[k];
-    const int *rowsg = a.Fi + base;
-    T *Fx = reinterpret_cast<T *>(a.Fx) + (size_t)inst * a.nnzF;
+    const int64_t w = (int64_t)blockIdx.x * WAVES + wv;
+    if (w >= (int64_t)a.n * a.batch) return;
+    const int inst = (int)(w % a.batch);
+    const int k = (int)(w / a.batch);
+    T *x = reinterpret_cast<T *>(a.Fx) + (size_t)inst * a.nnzF + a.Dp[k];
     const double *Av = a.Aval + (size_t)inst * a.nnzA;
-    const bool inlds = len <= CAP;
-    T *xl = xs_all[wv];
-    int *rl = rows_all[wv];
-    T *x = inlds ? xl : reinterpret_cast<T *>(a.scratch) + (size_t)(blockIdx.x * WAVES + wv) * a.max_col;
-    const int *rows = inlds ? rl : rowsg;
-    for (int i = lane; i < len; i += WAVE) {
-        x[i] = T(0);
-        if (inlds) rl[i] = rowsg[i];
-    }
+    const int len = a.Dlen[k];
+    for (int i = lane; i < len; i += WAVE) x[i] = T(0);
     wave_sync();
     const int c = a.colperm[k];
     for (int p = a.Ap[c] + lane; p < a.Ap[c + 1]; p += WAVE) x[a.amap[p]] = (T)Av[p];
-    wave_sync();
-    // left-looking update by every predecessor j (rows of U(:,k) above the diagonal), ascending
-    for (int u = 0; u < nu - 1; ++u) {
-        const int j = rows[u];
-        const T xj = x[u];
-        const int lb = a.Dp[j] + a.nU[j], le = a.Dp[j] + a.Dlen[j];
-        for (int q = lb + lane; q < le; q += WAVE) {
-            const int r = a.Fi[q];
-            const T l = Fx[q];
-            const int s = find_slot(rows, len, r);
-            if (s < len) x[s] -= l * xj;   // always found: struct(L(:,j)) is inside struct(col k)
-        }
-        wave_sync();
-    }
-    const T d = x[nu - 1];
-    if (CHECK) {
+}
+
+// one wavefront per (task, instance); tasks: [checks | normalisations | updates]
+template <typename T, bool CHECK>
+__global__ __launch_bounds__(WG) void refactor_level_kernel(RefactorArgs a, int cbeg, int cend, int pbeg,
+                                                             int pend, int tbeg, int tend) {
+    const int lane = threadIdx.x & (WAVE - 1), wv = threadIdx.x / WAVE;
+    const int64_t w = (int64_t)blockIdx.x * WAVES + wv;
+    const int nchk = cend - cbeg, nnorm = pend - pbeg, nupd = tend - tbeg;
+    if (w >= (int64_t)(nchk + nnorm + nupd) * a.batch) return;
+    const int inst = (int)(w % a.batch);
+    const int idx = (int)(w / a.batch);
+    int *interrupted = a.ctrl + 1;
+    int *firstfail = a.ctrl + 1 + a.batch;
+    if (CHECK && interrupted[inst]) return;          // an earlier level failed its check
+    T *Fx = reinterpret_cast<T *>(a.Fx) + (size_t)inst * a.nnzF;
+    if (idx < nchk) {
+        // (a) pivot check of a column of this level
+        if (!CHECK) return;
+        const int j = a.seq[cbeg + idx];
+        const T *x = Fx + a.Dp[j];
+        const int nu = a.nU[j], len = a.Dlen[j];
         double m = 0.0;
         int bad = 0;
         for (int i = nu + lane; i < len; i += WAVE) {
@@ -115,18 +102,49 @@ __global__ __launch_bounds__(WG) void refactor_level_kernel(RefactorArgs a, int 
         }
         m = wave_max(m);
         bad = __any(bad);
-        const double dd = (double)d;
-        if (bad || !isfinite(dd) || dd == 0.0 || fabs(dd) < a.eps * m || k == a.force_fail_col) {
+        const double d = (double)x[nu - 1];
+        if (bad || !isfinite(d) || d == 0.0 || fabs(d) < a.eps * m || j == a.force_fail_col) {
             if (lane == 0) {
-                atomicMin(&firstfail[inst], k);
+                atomicMin(&firstfail[inst], j);
                 atomicExch(&interrupted[inst], 1);
             }
-            return;
         }
+        return;
     }
-    for (int i = lane; i < nu; i += WAVE) Fx[base + i] = x[i];
-    for (int i = nu + lane; i < len; i += WAVE) Fx[base + i] = x[i] / d;
-    if (CHECK && lane == 0) a.done[(size_t)inst * a.n + k] = (int)a.epoch;
+    if (idx < nchk + nnorm) {
+        // (b) L(:,j) = x / pivot for a column of the previous level
+        const int j = a.seq[pbeg + idx - nchk];
+        T *x = Fx + a.Dp[j];
+        const int nu = a.nU[j], len = a.Dlen[j];
+        const T d = x[nu - 1];
+        for (int i = nu + lane; i < len; i += WAVE) x[i] = x[i] / d;
+        if (lane == 0) a.done[(size_t)inst * a.n + j] = (int)a.epoch;
+        return;
+    }
+    // (c) update task: target column k, sources j of this level in ascending order
+    const int t = tbeg + idx - nchk - nnorm;
+    const int k = a.task_tgt[t];
+    const int bk = a.Dp[k], lenk = a.Dlen[k];
+    const int *rowsk = a.Fi + bk;
+    T *xk = Fx + bk;
+    for (int s = a.src_ptr[t]; s < a.src_ptr[t + 1]; ++s) {
+        const int j = a.src_col[s];
+        const int sj = a.src_slot[s];
+        const T mult = xk[sj];                      // U(j,k): final, no source of this task updates it
+        const int bj = a.Dp[j], nuj = a.nU[j], lenj = a.Dlen[j];
+        const T inv = T(1) / Fx[bj + nuj - 1];      // the pivot of j (not yet divided into L(:,j))
+        for (int q = bj + nuj + lane; q < bj + lenj; q += WAVE) {
+            const int r = a.Fi[q];
+            const T l = Fx[q] * inv;
+            int lo = sj + 1, hi = lenk;             // rows of L(:,j) lie below row j in column k
+            while (lo < hi) {
+                const int mid = (lo + hi) >> 1;
+                if (rowsk[mid] < r) lo = mid + 1; else hi = mid;
+            }
+            if (lo < lenk) xk[lo] -= l * mult;     // always found: struct(L(:,j)) is inside struct(col k)
+        }
+        wave_sync();
+    }
 }
 
 __global__ void reset_ctrl_kernel(int *ctrl, int nwords, int value, int batch) {
@@ -153,17 +171,30 @@ int launch_status_out(const int *firstfail, int *status, int batch, void *stream
     return (int)hipGetLastError();
 }
 
-int launch_refactor_level(const RefactorArgs &a, int lbeg, int lend, void *stream) {
+int launch_refactor_init(const RefactorArgs &a, void *stream) {
     hipStream_t st = (hipStream_t)stream;
-    const int64_t waves = (int64_t)(lend - lbeg) * a.batch;
+    const int64_t waves = (int64_t)a.n * a.batch;
     const dim3 grid((unsigned)((waves + WAVES - 1) / WAVES));
+    if (waves == 0) return 0;
+    if (a.fp32) hipLaunchKernelGGL((refactor_init_kernel<float>), grid, dim3(WG), 0, st, a);
+    else hipLaunchKernelGGL((refactor_init_kernel<double>), grid, dim3(WG), 0, st, a);
+    return (int)hipGetLastError();
+}
+
+int launch_refactor_level(const RefactorArgs &a, int cbeg, int cend, int pbeg, int pend, int tbeg, int tend,
+                          void *stream) {
+    hipStream_t st = (hipStream_t)stream;
+    const int64_t waves = (int64_t)((cend - cbeg) + (pend - pbeg) + (tend - tbeg)) * a.batch;
+    if (waves == 0) return 0;
+    const dim3 grid((unsigned)((waves + WAVES - 1) / WAVES));
+#define CKTLU_LEVEL(T, C) \
+    hipLaunchKernelGGL((refactor_level_kernel<T, C>), grid, dim3(WG), 0, st, a, cbeg, cend, pbeg, pend, tbeg, tend)
     if (a.fp32) {
-        if (a.check) hipLaunchKernelGGL((refactor_level_kernel<float, true>), grid, dim3(WG), 0, st, a, lbeg, lend);
-        else hipLaunchKernelGGL((refactor_level_kernel<float, false>), grid, dim3(WG), 0, st, a, lbeg, lend);
+        if (a.check) CKTLU_LEVEL(float, true); else CKTLU_LEVEL(float, false);
     } else {
-        if (a.check) hipLaunchKernelGGL((refactor_level_kernel<double, true>), grid, dim3(WG), 0, st, a, lbeg, lend);
-        else hipLaunchKernelGGL((refactor_level_kernel<double, false>), grid, dim3(WG), 0, st, a, lbeg, lend);
+        if (a.check) CKTLU_LEVEL(double, true); else CKTLU_LEVEL(double, false);
     }
+#undef CKTLU_LEVEL
     return (int)hipGetLastError();
 }
 

@@ -47,9 +47,6 @@ void build_schedule(const Analysis &an, const Factor &f, const cktlu_options &op
         s.max_width = std::max(s.max_width, cnt[l + 1]);
         cnt[l + 1] += cnt[l];
     }
-    s.lvl_ptr.assign(cnt.begin(), cnt.end());                    // level l = seq[lvl_ptr[l], lvl_ptr[l+1])
-    s.seq.resize(n);
-    for (int k = 0; k < n; k++) s.seq[cnt[s.level[k]]++] = k;   // ascending k inside a level
     // ---- value map: user nonzero p -> slot offset inside its factor column
     s.amap.resize(an.nnz);
     for (int c = 0; c < n; c++) {
@@ -90,6 +87,60 @@ void build_schedule(const Analysis &an, const Factor &f, const cktlu_options &op
             for (int64_t q = b; q < d; q++) { int i = f.Fi[q]; s.Urj[uf[i]] = k; s.Ursrc[uf[i]++] = dpos(k, q); }
             for (int64_t q = d + 1; q < e; q++) { int i = f.Fi[q]; s.Lrj[lf[i]] = k; s.Lrsrc[lf[i]++] = dpos(k, q); }
         }
+    }
+    // ---- right-looking schedule.  Column k must follow every j with U(j,k) != 0 (its
+    // updates) and every j with L(k,j) != 0 (so that the multiplier U(k,m) that row k
+    // holds in any target m is final when k updates m).  rlevel = longest path.
+    {
+        std::vector<int> rlev(n, 0);
+        int nl = n ? 1 : 0;
+        for (int k = 0; k < n; k++) {
+            int v = 0;
+            for (int64_t q = f.Fp[k]; q < f.Fp[k] + f.nU[k] - 1; q++) v = std::max(v, rlev[f.Fi[q]] + 1);
+            for (int q = s.Lrp[k]; q < s.Lrp[k + 1]; q++) v = std::max(v, rlev[s.Lrj[q]] + 1);
+            rlev[k] = v;
+            nl = std::max(nl, v + 1);
+        }
+        s.n_rlevels = nl;
+        std::vector<int> c(nl + 1, 0);
+        for (int k = 0; k < n; k++) c[rlev[k] + 1]++;
+        for (int l = 0; l < nl; l++) c[l + 1] += c[l];
+        s.lvl_ptr.assign(c.begin(), c.end());
+        s.seq.resize(n);
+        for (int k = 0; k < n; k++) s.seq[c[rlev[k]]++] = k;
+        // update tasks: items (j -> k) for U(j,k) != 0, j < k, in (rlevel(j), k, j) order
+        // by a stable counting sort over the level (k and j already ascend in column order)
+        std::vector<int64_t> bucket(nl + 1, 0);
+        for (int k = 0; k < n; k++)
+            for (int64_t q = f.Fp[k]; q < f.Fp[k] + f.nU[k] - 1; q++) bucket[rlev[f.Fi[q]] + 1]++;
+        for (int l = 0; l < nl; l++) bucket[l + 1] += bucket[l];
+        const int64_t nitems = bucket[nl];
+        std::vector<int> it_k(nitems), it_j(nitems), it_slot(nitems);
+        std::vector<int64_t> fillp(bucket.begin(), bucket.end() - 1);
+        for (int k = 0; k < n; k++)
+            for (int64_t q = f.Fp[k]; q < f.Fp[k] + f.nU[k] - 1; q++) {
+                const int j = f.Fi[q];
+                const int64_t o = fillp[rlev[j]]++;
+                it_k[o] = k;
+                it_j[o] = j;
+                it_slot[o] = (int)(q - f.Fp[k]);
+            }
+        s.task_ptr.assign(nl + 1, 0);
+        s.task_tgt.clear();
+        s.src_ptr.assign(1, 0);
+        s.src_col.swap(it_j);
+        s.src_slot.swap(it_slot);
+        int l = 0;
+        for (int64_t i = 0; i < nitems; i++) {
+            while (i >= bucket[l + 1]) l++;
+            if (i == bucket[l] || it_k[i] != it_k[i - 1]) {
+                if (i > 0) s.src_ptr.push_back((int)i);
+                s.task_tgt.push_back(it_k[i]);
+                s.task_ptr[l + 1]++;
+            }
+        }
+        if (nitems > 0) s.src_ptr.push_back((int)nitems);
+        for (int q = 0; q < nl; q++) s.task_ptr[q + 1] += s.task_ptr[q];
     }
     // ---- solve levels: row i of L waits for every j with L(i,j) != 0; row i of U for j > i
     auto order_by_level = [n](const std::vector<int> &lev, int nl, std::vector<int> &seq,
