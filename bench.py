@@ -4,8 +4,9 @@
 A step is refactorize(values_t) (fast factorization with pivot check) plus
 solve(b) (plus iterative refinement in FP32+IR mode), on the post-layout RC
 mesh workload (3 layers x 300 x 300, vias, transistor stamps; n = 270,000),
-values perturbed +-5% per step, all value sets pre-staged in HBM before the
-timed region.  Prints one JSON line with steps/s, p50/p99 step latency for the
+every circuit element re-stamped with a +-5% factor per step (as a simulator
+re-stamps its devices in each Newton-Raphson iteration), all value sets
+pre-staged in HBM before the timed region.  Prints one JSON line with steps/s, p50/p99 step latency for the
 FP64 path (the headline value) and the FP32+IR path, the roofline of the
 refactorization phase and the CPU oracle baseline.
 """
@@ -98,6 +99,9 @@ def main():
     ap.add_argument("--workload", default="layered_rc_3x300", choices=sorted(WORKLOADS))
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp32", action="store_true")
+    ap.add_argument("--perturb", default="element", choices=["element", "nonzero"],
+                    help="element: every circuit element x U[0.95,1.05], re-assembled (NR re-stamping); "
+                         "nonzero: every assembled nonzero x U[0.95,1.05] (pivot stress)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
@@ -114,7 +118,10 @@ def main():
     c = wl["make"]()
     log("workload %s n=%d nnz=%d (%.1fs)" % (args.workload, c.n, c.nnz, time.time() - t0))
     nvals = 1 + args.warmup + args.steps
-    vals = [c.values] + [mnagen.perturb(c.values, 0, wl["cfg"], t) for t in range(1, nvals)]
+    if args.perturb == "element":
+        vals = [c.values] + [mnagen.restamp(c, 0, wl["cfg"], t) for t in range(1, nvals)]
+    else:
+        vals = [c.values] + [mnagen.perturb(c.values, 0, wl["cfg"], t) for t in range(1, nvals)]
     dev = torch.device("cuda:0")
     vals_dev = [torch.tensor(v, device=dev) for v in vals]       # staged in HBM before timing
     b = c.rhs[0]
@@ -164,7 +171,8 @@ def main():
         "ms_per_step": res64["wall"] * 1e3 / args.steps, "higher_is_better": True, "scaling": "weak",
         "vs_baseline": None, "dtype": "f64", "data": "synthetic",
         "config": {"workload": wl["desc"], "n": c.n, "nnz": c.nnz, "nnz_lu": st["nnz_l"] + st["nnz_u"],
-                   "flops_per_refactor": st["flops"], "levels": st["levels"], "value_perturbation": "+-5%"},
+                   "flops_per_refactor": st["flops"], "levels": st["levels"],
+                   "value_perturbation": "+-5% per %s" % args.perturb},
         "p50_ms": float(np.percentile(res64["step_ms"], 50)),
         "p99_ms": float(np.percentile(res64["step_ms"], 99)),
         "refactor_ms": float(res64["ref_ms"].mean()), "solve_ms": float(res64["sol_ms"].mean()),

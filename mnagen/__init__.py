@@ -24,7 +24,7 @@ import scipy.sparse as sp
 
 __all__ = [
     "Circuit", "assemble", "mesh_vsrc", "layered_rc", "mesh_transistor",
-    "power_grid", "perturb", "instance_values", "random_rhs", "step_rng",
+    "power_grid", "perturb", "restamp", "instance_values", "Stamping", "random_rhs", "step_rng",
     "random_pattern", "hand_pattern", "random_values", "serving_mix",
     "CONFIGS",
 ]
@@ -40,6 +40,7 @@ class Circuit:
     rhs: np.ndarray             # float64 [nrhs, n]
     name: str = ""
     meta: dict = field(default_factory=dict)
+    stamping: "Stamping | None" = None
 
     @property
     def nnz(self) -> int:
@@ -73,25 +74,77 @@ def _grid_edges(nx, ny, offset=0):
 
 
 class _Stamps:
-    """Triplet accumulator for MNA stamps."""
+    """Triplet accumulator for MNA stamps that remembers which element made each entry.
+
+    Every resistor, via, pad, capacitor companion or transistor stamp is one
+    element; ideal-source incidence entries are fixed elements (never scaled).
+    build() returns the CSC matrix and a Stamping that re-assembles the matrix
+    for any per-element scale factors.
+    """
 
     def __init__(self):
-        self.r, self.c, self.v = [], [], []
+        self.r, self.c, self.v, self.e = [], [], [], []
+        self.nelem = 0
+        self.fixed = []
+
+    def _ids(self, m, fixed=False):
+        ids = np.arange(self.nelem, self.nelem + m, dtype=np.int64)
+        self.nelem += m
+        if fixed:
+            self.fixed.append(ids)
+        return ids
 
     def conductance(self, a, b, g):
         a = np.asarray(a, np.int64); b = np.asarray(b, np.int64); g = np.asarray(g, np.float64)
-        self.r += [a, b, a, b]; self.c += [a, b, b, a]; self.v += [g, g, -g, -g]
+        ids = self._ids(a.size)
+        self.r += [a, b, a, b]; self.c += [a, b, b, a]; self.v += [g, g, -g, -g]; self.e += [ids] * 4
 
     def diag(self, a, g):
         a = np.asarray(a, np.int64)
         self.r.append(a); self.c.append(a); self.v.append(np.broadcast_to(np.asarray(g, np.float64), a.shape))
+        self.e.append(self._ids(a.size))
 
-    def entry(self, r, c, v):
+    def entry(self, r, c, v, group=1, fixed=False):
+        """Entries r, c, v; each run of `group` consecutive entries is one element."""
         r = np.asarray(r, np.int64); c = np.asarray(c, np.int64)
         self.r.append(r); self.c.append(c); self.v.append(np.broadcast_to(np.asarray(v, np.float64), r.shape))
+        ids = self._ids(r.size // group, fixed)
+        self.e.append(np.repeat(ids, group))
 
     def build(self, n):
-        return assemble(n, np.concatenate(self.r), np.concatenate(self.c), np.concatenate(self.v))
+        r = np.concatenate(self.r); c = np.concatenate(self.c)
+        v = np.concatenate(self.v).astype(np.float64); e = np.concatenate(self.e)
+        key = c * n + r                                     # column-major order = CSC order
+        ukey, pos = np.unique(key, return_inverse=True)
+        colptr = np.zeros(n + 1, dtype=np.int64)
+        np.add.at(colptr, (ukey // n) + 1, 1)
+        colptr = np.cumsum(colptr).astype(np.int32)
+        rowind = (ukey % n).astype(np.int32)
+        fixed = np.zeros(self.nelem, dtype=bool)
+        for ids in self.fixed:
+            fixed[ids] = True
+        st = Stamping(pos.astype(np.int64), v, e, self.nelem, fixed, int(ukey.size))
+        return colptr, rowind, st.values(), st
+
+
+@dataclass
+class Stamping:
+    """Per-entry provenance of an assembled MNA matrix."""
+    pos: np.ndarray        # nonzero index each triplet adds into
+    val: np.ndarray        # triplet value
+    elem: np.ndarray       # element id of each triplet
+    nelem: int
+    fixed: np.ndarray      # elements that are never scaled (ideal-source incidences)
+    nnz: int
+
+    def values(self, factors=None):
+        w = self.val if factors is None else self.val * factors[self.elem]
+        return np.bincount(self.pos, weights=w, minlength=self.nnz).astype(np.float64)
+
+    def factors(self, rng, lo, hi):
+        f = rng.uniform(lo, hi, self.nelem)
+        f[self.fixed] = 1.0
+        return f
 
 
 def _transistor_stamps(st, rng, nx, ny, layers, count, sigma=1e-2, diag=0.05):
@@ -105,7 +158,7 @@ def _transistor_stamps(st, rng, nx, ny, layers, count, sigma=1e-2, diag=0.05):
     cc = np.tile(nodes, (1, 4))
     vals = rng.normal(0.0, sigma, (count, 16))
     vals[:, [0, 5, 10, 15]] += diag
-    st.entry(rr.ravel(), cc.ravel(), vals.ravel())
+    st.entry(rr.ravel(), cc.ravel(), vals.ravel(), group=16)
 
 
 def random_rhs(rng, n, nrhs=1):
@@ -129,10 +182,10 @@ def mesh_vsrc(nx=32, ny=32, n_vsrc=4, seed=0, glo=1e-3, ghi=1e3, gmin=1e-12) -> 
     for s in range(n_vsrc):
         p = corners[s % 4] if s < 4 else int(rng.integers(0, nn))
         k = nn + s
-        st.entry([p, k], [k, p], [1.0, 1.0])
-    ap, ai, ax = st.build(n)
+        st.entry([p, k], [k, p], [1.0, 1.0], group=2, fixed=True)
+    ap, ai, ax, stp = st.build(n)
     return Circuit(n, ap, ai, ax, random_rhs(rng, n), name=f"mesh_vsrc_{nx}x{ny}",
-                   meta=dict(nx=nx, ny=ny, n_vsrc=n_vsrc, seed=seed))
+                   meta=dict(nx=nx, ny=ny, n_vsrc=n_vsrc, seed=seed), stamping=stp)
 
 
 def layered_rc(nx=300, ny=300, layers=3, via_frac=0.01, stamp_frac=0.1, seed=0,
@@ -151,9 +204,9 @@ def layered_rc(nx=300, ny=300, layers=3, via_frac=0.01, stamp_frac=0.1, seed=0,
         sites = rng.choice(nl, nvia, replace=False)
         st.conductance(l * nl + sites, (l + 1) * nl + sites, np.full(nvia, gvia))
     _transistor_stamps(st, rng, nx, ny, layers, int(stamp_frac * n))
-    ap, ai, ax = st.build(n)
+    ap, ai, ax, stp = st.build(n)
     return Circuit(n, ap, ai, ax, random_rhs(rng, n), name=f"layered_rc_{layers}x{nx}x{ny}",
-                   meta=dict(nx=nx, ny=ny, layers=layers, seed=seed))
+                   meta=dict(nx=nx, ny=ny, layers=layers, seed=seed), stamping=stp)
 
 
 def mesh_transistor(nx=141, ny=141, stamp_frac=0.1, seed=0, glo=1e-3, ghi=1e3,
@@ -175,13 +228,13 @@ def power_grid(nx=1000, ny=1000, pad_frac=0.005, n_src=1000, nrhs=8, seed=0,
     st.diag(np.arange(n), gmin)
     npad = max(1, int(round(pad_frac * n)))
     st.diag(rng.choice(n, npad, replace=False), gpad)
-    ap, ai, ax = st.build(n)
+    ap, ai, ax, stp = st.build(n)
     rhs = np.zeros((nrhs, n))
     for r in range(nrhs):
         nodes = rng.choice(n, min(n_src, n), replace=False)
         rhs[r, nodes] = rng.uniform(ilo, ihi, len(nodes))
     return Circuit(n, ap, ai, ax, rhs, name=f"power_grid_{nx}x{ny}",
-                   meta=dict(nx=nx, ny=ny, seed=seed))
+                   meta=dict(nx=nx, ny=ny, seed=seed), stamping=stp)
 
 
 def step_rng(seed, cfg, t):
@@ -189,15 +242,32 @@ def step_rng(seed, cfg, t):
     return np.random.default_rng(np.random.SeedSequence([seed, cfg, t]))
 
 
+def restamp(c, seed, cfg, t, rel=0.05):
+    """Per-step values of an NR iteration: every circuit element (resistor, via, pad,
+    capacitor companion, transistor stamp) scaled by its own U[1-rel, 1+rel] factor
+    and the matrix re-assembled, as a simulator re-stamps its devices (not cumulative;
+    ideal-source incidences stay fixed)."""
+    f = c.stamping.factors(step_rng(seed, cfg, t), 1.0 - rel, 1.0 + rel)
+    return c.stamping.values(f)
+
+
 def perturb(values, seed, cfg, t, rel=0.05):
-    """Per-step values: every assembled nonzero times U[1-rel, 1+rel] (not cumulative)."""
+    """Stress recipe: every assembled nonzero times an independent U[1-rel, 1+rel].
+
+    This breaks the element structure of the matrix (row sums no longer match the
+    element conductances), which makes pivots flip far more often than in an NR run."""
     return values * step_rng(seed, cfg, t).uniform(1.0 - rel, 1.0 + rel, values.shape)
 
 
-def instance_values(values, batch, sigma=0.3, seed=0):
-    """Monte-Carlo corners: per-instance, per-nonzero factor exp(sigma*N(0,1))."""
+def instance_values(c, batch, sigma=0.3, seed=0):
+    """Monte-Carlo corners: per-instance, per-element factor exp(sigma*N(0,1)), re-assembled."""
     rng = np.random.default_rng(np.random.SeedSequence([seed, 3, batch]))
-    return values[None, :] * np.exp(sigma * rng.standard_normal((batch, values.size)))
+    out = np.empty((batch, c.nnz))
+    for i in range(batch):
+        f = np.exp(sigma * rng.standard_normal(c.stamping.nelem))
+        f[c.stamping.fixed] = 1.0
+        out[i] = c.stamping.values(f)
+    return out
 
 
 def random_values(rng, nnz, lo=-1.0, hi=1.0):
@@ -250,8 +320,8 @@ def hand_pattern(kind, n, seed=0):
         e = _grid_edges(side, side)
         st.conductance(e[:, 0], e[:, 1], np.ones(len(e)))
         st.diag(np.arange(n), 0.5)
-        ap, ai, ax = st.build(n)
-        return Circuit(n, ap, ai, ax, random_rhs(rng, n), name=f"laplacian2d_{side}")
+        ap, ai, ax, stp = st.build(n)
+        return Circuit(n, ap, ai, ax, random_rhs(rng, n), name=f"laplacian2d_{side}", stamping=stp)
     else:
         raise ValueError(kind)
     ap, ai, ax = assemble(n, r, c, v)

@@ -55,8 +55,9 @@ def test_refactorize_and_solve_fp64(ck, oracle_mod, name, make):
     s.factorize(dev(c.values))
     a0 = s.analysis()
     prev = a0["pivrow"]
-    for t in range(1, 4):
-        vh = mnagen.perturb(c.values, 7, 0, t)
+    for t in range(1, 5):
+        # element re-stamping (NR-like) and the per-nonzero stress recipe, alternating
+        vh = mnagen.restamp(c, 7, 0, t) if t % 2 else mnagen.perturb(c.values, 7, 0, t)
         rc, info = s.refactorize(dev(vh))
         a = s.analysis()
         lu = oracle_refactor(oracle_mod, c, vh, a0, EPS, prev)
@@ -229,7 +230,7 @@ def test_tiny_and_degenerate(ck, oracle_mod):
 def test_batched_equals_single(ck):
     c = mnagen.mesh_transistor(30, 30, seed=13)
     batch = 5
-    V = mnagen.instance_values(c.values, batch, 0.3, seed=13)
+    V = mnagen.instance_values(c, batch, 0.3, seed=13)
     s = ck.SparseLU(c.n, c.colptr, c.rowind, eps=EPS)
     s.factorize(dev(c.values))
     status = torch.zeros(batch, dtype=torch.int32, device="cuda:0")
