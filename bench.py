@@ -172,7 +172,7 @@ def main():
         "vs_baseline": None, "dtype": "f64", "data": "synthetic",
         "config": {"workload": wl["desc"], "n": c.n, "nnz": c.nnz, "nnz_lu": st["nnz_l"] + st["nnz_u"],
                    "flops_per_refactor": st["flops"], "levels": st["levels"],
-                   "value_perturbation": "+-5% per %s" % args.perturb},
+                   "value_perturbation": "+-5%% per %s" % args.perturb},
         "p50_ms": float(np.percentile(res64["step_ms"], 50)),
         "p99_ms": float(np.percentile(res64["step_ms"], 99)),
         "refactor_ms": float(res64["ref_ms"].mean()), "solve_ms": float(res64["sol_ms"].mean()),

@@ -247,6 +247,8 @@ def restamp(c, seed, cfg, t, rel=0.05):
     capacitor companion, transistor stamp) scaled by its own U[1-rel, 1+rel] factor
     and the matrix re-assembled, as a simulator re-stamps its devices (not cumulative;
     ideal-source incidences stay fixed)."""
+    if c.stamping is None:          # no element provenance: every nonzero is its own element
+        return perturb(c.values, seed, cfg, t, rel)
     f = c.stamping.factors(step_rng(seed, cfg, t), 1.0 - rel, 1.0 + rel)
     return c.stamping.values(f)
 
