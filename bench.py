@@ -36,8 +36,8 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def run_leg(ck, torch, c, vals_dev, b_dev, precision, steps, warmup):
-    s = ck.SparseLU(c.n, c.colptr, c.rowind, eps=1e-3, precision=precision, ir_tol=1e-10)
+def run_leg(ck, torch, c, vals_dev, b_dev, precision, steps, warmup, tail_opts):
+    s = ck.SparseLU(c.n, c.colptr, c.rowind, eps=1e-3, precision=precision, ir_tol=1e-10, **tail_opts)
     t0 = time.time()
     s.factorize(vals_dev[0])
     t_setup = time.time() - t0
@@ -99,6 +99,10 @@ def main():
     ap.add_argument("--workload", default="layered_rc_3x300", choices=sorted(WORKLOADS))
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp32", action="store_true")
+    ap.add_argument("--dense-tail", type=int, default=None,
+                    help="order of the dense trailing block: 0 automatic (default), -1 none, >0 forced")
+    ap.add_argument("--dense-density", type=float, default=None,
+                    help="fill density threshold of the automatic dense-block choice")
     ap.add_argument("--perturb", default="element", choices=["element", "nonzero"],
                     help="element: every circuit element x U[0.95,1.05], re-assembled (NR re-stamping); "
                          "nonzero: every assembled nonzero x U[0.95,1.05] (pivot stress)")
@@ -128,9 +132,11 @@ def main():
     b_dev = torch.tensor(b, device=dev)
     torch.cuda.synchronize()
 
-    res64 = run_leg(ck, torch, c, vals_dev, b_dev, ck.CKTLU_FP64, args.steps, args.warmup)
-    log("fp64: %.3f steps/s, refactor %.2f ms, solve %.2f ms (setup %.1fs)" %
-        (args.steps / res64["wall"], res64["ref_ms"].mean(), res64["sol_ms"].mean(), res64["setup_s"]))
+    tail_opts = dict(dense_tail=args.dense_tail, dense_tail_density=args.dense_density)
+    res64 = run_leg(ck, torch, c, vals_dev, b_dev, ck.CKTLU_FP64, args.steps, args.warmup, tail_opts)
+    log("fp64: %.3f steps/s, refactor %.2f ms, solve %.2f ms (setup %.1fs), dense tail %d" %
+        (args.steps / res64["wall"], res64["ref_ms"].mean(), res64["sol_ms"].mean(), res64["setup_s"],
+         res64["stats"]["dense_tail"]))
     x64 = res64["x"].cpu().numpy()
     import scipy.sparse as sp
     A_last = sp.csc_matrix((vals[-1], c.rowind, c.colptr), shape=(c.n, c.n))
@@ -139,7 +145,7 @@ def main():
 
     out_fp32 = None
     if not args.no_fp32:
-        res32 = run_leg(ck, torch, c, vals_dev, b_dev, ck.CKTLU_FP32_IR, args.steps, args.warmup)
+        res32 = run_leg(ck, torch, c, vals_dev, b_dev, ck.CKTLU_FP32_IR, args.steps, args.warmup, tail_opts)
         iters = [i[0] for i in res32["infos"]]
         errs = [i[1] for i in res32["infos"]]
         out_fp32 = dict(steps_per_s=args.steps / res32["wall"],
@@ -171,7 +177,7 @@ def main():
         "ms_per_step": res64["wall"] * 1e3 / args.steps, "higher_is_better": True, "scaling": "weak",
         "vs_baseline": None, "dtype": "f64", "data": "synthetic",
         "config": {"workload": wl["desc"], "n": c.n, "nnz": c.nnz, "nnz_lu": st["nnz_l"] + st["nnz_u"],
-                   "flops_per_refactor": st["flops"], "levels": st["levels"],
+                   "flops_per_refactor": st["flops"], "levels": st["levels"], "dense_tail": st["dense_tail"],
                    "value_perturbation": "+-5%% per %s" % args.perturb},
         "p50_ms": float(np.percentile(res64["step_ms"], 50)),
         "p99_ms": float(np.percentile(res64["step_ms"], 99)),

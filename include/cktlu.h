@@ -65,8 +65,10 @@ typedef struct {
     int transversal;       /* 1 (default): structural maximum transversal before ordering */
     void *stream;          /* hipStream_t for all device work; NULL = the null stream */
     int force_fail_col;    /* test hook: >= 0 makes the pivot check of this column fail once */
-    int dense_tail_min;    /* schedule: smallest trailing block handled densely; 0 = automatic, -1 = never */
-    double dense_tail_density; /* schedule: minimum fill density of that block; default 0.3 */
+    int dense_tail_size;   /* schedule: order D of the trailing block factored densely (Section V-A);
+                              0 = automatic (largest multiple of 64 in [256, 8192] whose block of L+U
+                              reaches dense_tail_density), -1 = never, > 0 = exactly min(value, n) */
+    double dense_tail_density; /* schedule: minimum fill density for the automatic choice; default 0.3 */
 } cktlu_options;
 
 typedef struct {

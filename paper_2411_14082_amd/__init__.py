@@ -48,7 +48,7 @@ class cktlu_options(ctypes.Structure):
     _fields_ = [("pivot_eps", ctypes.c_double), ("precision", ctypes.c_int), ("ir_tol", ctypes.c_double),
                 ("ir_max_iter", ctypes.c_int), ("ordering", ctypes.c_int), ("transversal", ctypes.c_int),
                 ("stream", ctypes.c_void_p), ("force_fail_col", ctypes.c_int),
-                ("dense_tail_min", ctypes.c_int), ("dense_tail_density", ctypes.c_double)]
+                ("dense_tail_size", ctypes.c_int), ("dense_tail_density", ctypes.c_double)]
 
 
 class cktlu_refactor_info(ctypes.Structure):
@@ -236,8 +236,13 @@ class SparseLU:
     """
 
     def __init__(self, n, colptr, rowind, eps=1e-3, precision=CKTLU_FP64, ordering=CKTLU_ORDER_AMD,
-                 ir_tol=1e-10, ir_max_iter=10, stream=None, transversal=1):
+                 ir_tol=1e-10, ir_max_iter=10, stream=None, transversal=1, dense_tail=None,
+                 dense_tail_density=None):
         opt = cktlu_default_options()
+        if dense_tail is not None:
+            opt.dense_tail_size = int(dense_tail)
+        if dense_tail_density is not None:
+            opt.dense_tail_density = float(dense_tail_density)
         opt.pivot_eps = eps
         opt.precision = precision
         opt.ordering = ordering

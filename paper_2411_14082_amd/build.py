@@ -11,7 +11,7 @@ CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libcktlu.so")
 
 HOST_SOURCES = ["cktlu.cpp", "analyze.cpp", "factor_host.cpp", "schedule.cpp"]
-DEVICE_SOURCES = ["kernels.hip"]
+DEVICE_SOURCES = ["kernels.hip", "dense.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"
 

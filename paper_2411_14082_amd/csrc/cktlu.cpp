@@ -87,7 +87,7 @@ DevBuf *all_buffers(Device &d, int i) {
                      &d.src_ptr, &d.src_col, &d.src_slot, &d.Lrp, &d.Lrj,
                      &d.Lrsrc, &d.Urp, &d.Urj, &d.Ursrc, &d.udiag, &d.lseq, &d.useq, &d.rowperm,
                      &d.colperm_sol, &d.Acp, &d.Acj, &d.Acsrc, &d.Fx64, &d.Fx32, &d.Aval, &d.done,
-                     &d.ctrl, &d.vec};
+                     &d.ctrl, &d.vec, &d.S, &d.tail_rend};
     const int cnt = (int)(sizeof(all) / sizeof(all[0]));
     return i < cnt ? all[i] : nullptr;
 }
@@ -97,6 +97,7 @@ void free_device(Device &d) {
     d.uploaded = false;
     d.batch_cap = 0;
     d.vec_cap = 0;
+    d.S_prec = -1;
 }
 
 // entries of one instance of the (padded) device factor storage
@@ -145,6 +146,12 @@ int ensure_batch(cktlu_ctx *c, int batch) {
     dfree(d.ctrl);
     if ((rc = dalloc(d.ctrl, (size_t)(8 + 2 * batch) * sizeof(int)))) return rc;
     HIPCHK(hipMemsetAsync(d.ctrl.p, 0, (size_t)(8 + 2 * batch) * sizeof(int), st));
+    const size_t D = (size_t)(n - c->s.tail0);
+    if (D > 0) {
+        dfree(d.S);
+        if ((rc = dalloc(d.S, D * D * sizeof(double) * batch))) return rc;
+    }
+    d.S_prec = -1;
     d.batch_cap = batch;
     return CKTLU_OK;
 }
@@ -181,6 +188,7 @@ int upload_all(cktlu_ctx *c) {
     if ((rc = upload(d.Acp, s.Acp, st))) return rc;
     if ((rc = upload(d.Acj, s.Acj, st))) return rc;
     if ((rc = upload(d.Acsrc, s.Acsrc, st))) return rc;
+    if ((rc = upload(d.tail_rend, s.tail_rend, st))) return rc;
     // value buffers sized for the current batch capacity (at least one instance)
     const int batch = std::max(1, d.batch_cap);
     d.batch_cap = 0;
@@ -248,6 +256,7 @@ int factor_and_setup(cktlu_ctx *c, const double *values_host, const std::vector<
             if (c->opt.precision == CKTLU_FP32_IR)
                 LCHK(launch_f64_to_f32((const double *)c->dev.Fx64.p, (float *)c->dev.Fx32.p, nnzF(c), st));
             c->dev_values_newer = false;
+            c->dev.S_prec = -1;
         } else {
             rc = upload_all(c);
             if (rc) return rc;
@@ -264,8 +273,38 @@ int ensure_device(cktlu_ctx *c) {
     return CKTLU_OK;
 }
 
+// Arguments of the dense trailing-block kernels for `batch` instances.
+DenseArgs dense_args(cktlu_ctx *c, int batch, bool fp32) {
+    Device &d = c->dev;
+    DenseArgs a;
+    std::memset(&a, 0, sizeof(a));
+    a.n = c->an.n;
+    a.T = c->s.tail0;
+    a.D = c->an.n - c->s.tail0;
+    a.batch = batch;
+    a.Dp = (const int *)d.Dp.p;
+    a.Dlen = (const int *)d.Dlen.p;
+    a.Fi = (const int *)d.Fi.p;
+    a.Fx = fp32 ? d.Fx32.p : d.Fx64.p;
+    a.nnzF = nnzF(c);
+    a.S = d.S.p;
+    a.ctrl = (int *)d.ctrl.p;
+    a.done = (int *)d.done.p;
+    a.force_fail_col = -1;
+    a.fp32 = fp32 ? 1 : 0;
+    return a;
+}
+
+// Make S hold the dense block of the current factors of the given precision.
+int ensure_S(cktlu_ctx *c, bool fp32, int batch) {
+    if (c->s.tail0 >= c->an.n || c->dev.S_prec == (fp32 ? 1 : 0)) return CKTLU_OK;
+    LCHK(launch_dense_gather(dense_args(c, batch, fp32), stream_of(c)));
+    c->dev.S_prec = fp32 ? 1 : 0;
+    return CKTLU_OK;
+}
+
 // The level-by-level refactorization of `batch` instances (cluster mode):
-// one launch per dependency level.
+// one launch per dependency level of the sparse columns, then the dense block.
 int run_refactor(cktlu_ctx *c, int batch, const double *values_dev, bool fp32, bool check, int force_col) {
     Device &d = c->dev;
     hipStream_t st = stream_of(c);
@@ -309,6 +348,17 @@ int run_refactor(cktlu_ctx *c, int batch, const double *values_dev, bool fp32, b
         const int pb = l > 0 ? s.lvl_ptr[l - 1] : 0, pe = l > 0 ? s.lvl_ptr[l] : 0;
         const int tb = l < s.n_rlevels ? s.task_ptr[l] : 0, te = l < s.n_rlevels ? s.task_ptr[l + 1] : 0;
         LCHK(launch_refactor_level(a, cb, ce, pb, pe, tb, te, st));
+    }
+    if (s.tail0 < c->an.n) {
+        DenseArgs da = dense_args(c, batch, fp32);
+        da.ctrl = a.ctrl;
+        da.done = a.done;
+        da.eps = a.eps;
+        da.epoch = a.epoch;
+        da.force_fail_col = force_col;
+        da.check = a.check;
+        LCHK(launch_dense_refactor(da, st));
+        d.S_prec = fp32 ? 1 : 0;
     }
     return CKTLU_OK;
 }
@@ -381,6 +431,7 @@ int refactor_single(cktlu_ctx *c, const double *values_dev, cktlu_refactor_info 
         if ((rc = read_status(c, h))) return rc;
         if (!h[1]) {
             LCHK(launch_f64_to_f32((const double *)d.Fx64.p, (float *)d.Fx32.p, nnzF(c), st));
+            d.S_prec = -1;
             return CKTLU_OK;
         }
         first = h[2];
@@ -417,7 +468,17 @@ int tri_solves(cktlu_ctx *c, int nrhs, int batch, double *z, bool fp32, const in
     a.y = z;
     a.skip = skip;
     const Schedule &s = c->s;
+    a.tail0 = s.tail0;
+    a.tail_rend = (const int *)d.tail_rend.p;
+    // sparse L levels (the last one holds the dense rows: their entries in sparse columns)
     for (int l = 0; l + 1 < (int)s.lsptr.size(); l++) LCHK(launch_lsolve_level(a, s.lsptr[l], s.lsptr[l + 1], st));
+    if (s.tail0 < c->an.n) {
+        int rc = ensure_S(c, fp32, batch);
+        if (rc) return rc;
+        const DenseArgs da = dense_args(c, batch, fp32);
+        LCHK(launch_dense_solve(da, z, nrhs, skip, false, st));
+        LCHK(launch_dense_solve(da, z, nrhs, skip, true, st));
+    }
     for (int l = 0; l + 1 < (int)s.usptr.size(); l++) LCHK(launch_usolve_level(a, s.usptr[l], s.usptr[l + 1], st));
     return CKTLU_OK;
 }
@@ -511,7 +572,7 @@ void cktlu_default_options(cktlu_options *o) {
     o->transversal = 1;
     o->stream = nullptr;
     o->force_fail_col = -1;
-    o->dense_tail_min = 0;
+    o->dense_tail_size = 0;
     o->dense_tail_density = 0.3;
 }
 
@@ -773,8 +834,9 @@ size_t cktlu_footprint_bytes(const cktlu_ctx *c, int32_t batch) {
     size_t s = 0;
     for (int i = 0; DevBuf *b = all_buffers(d, i); i++) s += b->bytes;
     const int64_t F = c->s.nnz_dev;
+    const size_t Dt = (size_t)(c->an.n - c->s.tail0);
     const size_t per = (size_t)F * (c->opt.precision == CKTLU_FP32_IR ? 12 : 8) + (size_t)c->an.nnz * 8 +
-                       (size_t)c->an.n * (4 + 8 * YS);
+                       (size_t)c->an.n * (4 + 8 * YS) + Dt * Dt * 8;
     if (!c->dev.uploaded) s += (size_t)F * 12 + (size_t)c->an.nnz * 12 + (size_t)c->an.n * 64;
     return s + (batch > 0 ? per * (size_t)batch : 0);
 }

@@ -86,7 +86,8 @@ struct Schedule {
     std::vector<int> Acp, Acj, Acsrc;
     int max_col = 0;                          // longest column of F
     double macs = 0, flops = 0;
-    int tail0 = 0;                            // first column of a densely factored tail (n = none)
+    int tail0 = 0;                            // first column of the densely factored tail (n = none)
+    std::vector<int> tail_rend;               // rows i >= tail0: L entries of columns < tail0 end here
 };
 
 void build_schedule(const Analysis &an, const Factor &f, const cktlu_options &opt, Schedule &s);
@@ -110,8 +111,11 @@ struct Device {
     DevBuf Aval;                       // copy of the last values (FP64) for residuals
     DevBuf done, ctrl;                 // per-column completion epochs, status words
     DevBuf vec;                        // solve work vectors
+    DevBuf S;                          // dense trailing block, batch x D x D (8-byte slots)
+    DevBuf tail_rend;                  // per tail row: end of its L entries in front columns
     size_t vec_cap = 0;
     unsigned epoch = 0;
+    int S_prec = -1;                   // what S holds: -1 stale, 0 FP64 factors, 1 FP32 factors
 };
 
 }  // namespace cktlu
@@ -156,6 +160,8 @@ struct SolveArgs {
     int fp32;
     double *y;                 // batch x n rows of YS doubles, rhs r in slot r
     const int *skip;           // per-instance status (-1 = solve), may be null
+    int tail0;                 // rows >= tail0 of the L solve take only entries [Lrp[i], tail_rend[i - tail0])
+    const int *tail_rend;
 };
 
 // Rows lseq[lbeg, lend) / useq[lbeg, lend) (one level of the solve graph).
@@ -176,5 +182,27 @@ int launch_anorm(int n, const int *Acp, const int *Acsrc, const double *Aval, do
 int launch_copy_f64(const double *src, double *dst, int64_t count, void *stream);
 int launch_f64_to_f32(const double *src, float *dst, int64_t count, void *stream);
 int launch_fill_i32(int *dst, int64_t count, int value, void *stream);
+
+// Dense trailing block (dense.hip): columns and rows [T, n) of the factors,
+// D = n - T, held per instance as a column-major D x D matrix S.
+constexpr int kDenseBlock = 64;  // panel width of the blocked LU and of the block solves
+struct DenseArgs {
+    int n, T, D, batch;
+    const int *Dp, *Dlen, *Fi;
+    void *Fx;                  // factor values (double or float), batch x nnzF
+    int64_t nnzF;
+    void *S;                   // batch x D x D values of the factor type
+    int *ctrl, *done;          // status words and completion epochs (as RefactorArgs)
+    double eps;
+    unsigned epoch;
+    int force_fail_col;
+    int fp32, check;
+};
+// S <- rows >= T of the tail columns of Fx (zeros elsewhere)
+int launch_dense_gather(const DenseArgs &a, void *stream);
+// gather, blocked LU with the pivot test, scatter back into Fx
+int launch_dense_refactor(const DenseArgs &a, void *stream);
+// y rows [T, n): lower (unit) or upper triangular solve with the block in S
+int launch_dense_solve(const DenseArgs &a, double *y, int nrhs, const int *skip, bool upper, void *stream);
 
 }  // namespace cktlu_dev

@@ -216,7 +216,9 @@ __global__ __launch_bounds__(WG) void trisolve_level_kernel(SolveArgs a, int lbe
     double acc[NR];
 #pragma unroll
     for (int r = 0; r < NR; r++) acc[r] = 0.0;
-    for (int q = rp[i] + lane; q < rp[i + 1]; q += WAVE) {
+    // rows of the dense block take only their L entries in sparse columns here
+    const int qend = (!UPPER && i >= a.tail0) ? a.tail_rend[i - a.tail0] : rp[i + 1];
+    for (int q = rp[i] + lane; q < qend; q += WAVE) {
         const int j = rj[q];
         const double l = (double)Fx[rs[q]];
 #pragma unroll

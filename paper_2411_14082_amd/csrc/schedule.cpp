@@ -11,11 +11,35 @@
 
 namespace cktlu {
 
+// Order D of the trailing block factored densely (Section V-A).  Forced by a
+// positive option value, never with -1; otherwise the largest multiple of the
+// panel width (at least 256, at most 8192) whose block of L+U has a fill density
+// of at least dense_tail_density.  An entry (i,k) lies in the trailing block of
+// order D exactly when min(i,k) >= n - D.
+static int choose_tail(const Factor &f, const cktlu_options &opt) {
+    const int n = f.n;
+    if (opt.dense_tail_size < 0 || n == 0) return 0;
+    if (opt.dense_tail_size > 0) return std::min(opt.dense_tail_size, n);
+    const int nb = cktlu_dev::kDenseBlock, dmax = std::min(n, 8192) / nb * nb;
+    if (dmax < 256) return 0;
+    std::vector<double> cnt(dmax + 1, 0.0);
+    for (int k = n - dmax; k < n; k++)
+        for (int64_t q = f.Fp[k]; q < f.Fp[k + 1]; q++) {
+            const int m = std::min(f.Fi[q], k);
+            if (m >= n - dmax) cnt[n - m] += 1.0;
+        }
+    for (int d = 1; d <= dmax; d++) cnt[d] += cnt[d - 1];
+    for (int d = dmax; d >= 256; d -= nb)
+        if (cnt[d] >= opt.dense_tail_density * (double)d * (double)d) return d;
+    return 0;
+}
+
 void build_schedule(const Analysis &an, const Factor &f, const cktlu_options &opt, Schedule &s) {
-    (void)opt;
     const int n = an.n;
     s = Schedule();
     s.n = n;
+    const int T = n - choose_tail(f, opt);
+    s.tail0 = T;
     // ---- device layout: columns padded to whole cache lines
     const int al = cktlu_dev::kColAlign;
     s.Dp.assign(n + 1, 0);
@@ -88,13 +112,14 @@ void build_schedule(const Analysis &an, const Factor &f, const cktlu_options &op
             for (int64_t q = d + 1; q < e; q++) { int i = f.Fi[q]; s.Lrj[lf[i]] = k; s.Lrsrc[lf[i]++] = dpos(k, q); }
         }
     }
-    // ---- right-looking schedule.  Column k must follow every j with U(j,k) != 0 (its
-    // updates) and every j with L(k,j) != 0 (so that the multiplier U(k,m) that row k
-    // holds in any target m is final when k updates m).  rlevel = longest path.
+    // ---- right-looking schedule of the sparse columns [0, T).  Column k must follow
+    // every j with U(j,k) != 0 (its updates) and every j with L(k,j) != 0 (so that the
+    // multiplier U(k,m) that row k holds in any target m is final when k updates m).
+    // rlevel = longest path.  Columns [T, n) are update targets only (dense block).
     {
         std::vector<int> rlev(n, 0);
-        int nl = n ? 1 : 0;
-        for (int k = 0; k < n; k++) {
+        int nl = T ? 1 : 0;
+        for (int k = 0; k < T; k++) {
             int v = 0;
             for (int64_t q = f.Fp[k]; q < f.Fp[k] + f.nU[k] - 1; q++) v = std::max(v, rlev[f.Fi[q]] + 1);
             for (int q = s.Lrp[k]; q < s.Lrp[k + 1]; q++) v = std::max(v, rlev[s.Lrj[q]] + 1);
@@ -103,22 +128,23 @@ void build_schedule(const Analysis &an, const Factor &f, const cktlu_options &op
         }
         s.n_rlevels = nl;
         std::vector<int> c(nl + 1, 0);
-        for (int k = 0; k < n; k++) c[rlev[k] + 1]++;
+        for (int k = 0; k < T; k++) c[rlev[k] + 1]++;
         for (int l = 0; l < nl; l++) c[l + 1] += c[l];
         s.lvl_ptr.assign(c.begin(), c.end());
-        s.seq.resize(n);
-        for (int k = 0; k < n; k++) s.seq[c[rlev[k]]++] = k;
-        // update tasks: items (j -> k) for U(j,k) != 0, j < k, in (rlevel(j), k, j) order
-        // by a stable counting sort over the level (k and j already ascend in column order)
+        s.seq.resize(T);
+        for (int k = 0; k < T; k++) s.seq[c[rlev[k]]++] = k;
+        // update tasks: items (j -> k) for U(j,k) != 0, j < min(k, T), in (rlevel(j), k, j)
+        // order by a stable counting sort over the level (k and j ascend in column order)
         std::vector<int64_t> bucket(nl + 1, 0);
         for (int k = 0; k < n; k++)
-            for (int64_t q = f.Fp[k]; q < f.Fp[k] + f.nU[k] - 1; q++) bucket[rlev[f.Fi[q]] + 1]++;
+            for (int64_t q = f.Fp[k]; q < f.Fp[k] + f.nU[k] - 1 && f.Fi[q] < T; q++)
+                bucket[rlev[f.Fi[q]] + 1]++;
         for (int l = 0; l < nl; l++) bucket[l + 1] += bucket[l];
         const int64_t nitems = bucket[nl];
         std::vector<int> it_k(nitems), it_j(nitems), it_slot(nitems);
         std::vector<int64_t> fillp(bucket.begin(), bucket.end() - 1);
         for (int k = 0; k < n; k++)
-            for (int64_t q = f.Fp[k]; q < f.Fp[k] + f.nU[k] - 1; q++) {
+            for (int64_t q = f.Fp[k]; q < f.Fp[k] + f.nU[k] - 1 && f.Fi[q] < T; q++) {
                 const int j = f.Fi[q];
                 const int64_t o = fillp[rlev[j]]++;
                 it_k[o] = k;
@@ -142,35 +168,49 @@ void build_schedule(const Analysis &an, const Factor &f, const cktlu_options &op
         if (nitems > 0) s.src_ptr.push_back((int)nitems);
         for (int q = 0; q < nl; q++) s.task_ptr[q + 1] += s.task_ptr[q];
     }
-    // ---- solve levels: row i of L waits for every j with L(i,j) != 0; row i of U for j > i
-    auto order_by_level = [n](const std::vector<int> &lev, int nl, std::vector<int> &seq,
+    // ---- solve levels of the sparse rows [0, T): row i of L waits for every j with
+    // L(i,j) != 0, row i of U for every j > i with U(i,j) != 0 (rows >= T of U are
+    // solved densely before any sparse U row).  The L sequence ends with one more
+    // level holding the rows [T, n), which take only their entries in columns < T.
+    auto order_by_level = [T](const std::vector<int> &lev, int nl, std::vector<int> &seq,
                               std::vector<int> &ptr) {
         std::vector<int> c(nl + 1, 0);
-        for (int i = 0; i < n; i++) c[lev[i] + 1]++;
+        for (int i = 0; i < T; i++) c[lev[i] + 1]++;
         for (int l = 0; l < nl; l++) c[l + 1] += c[l];
         ptr.assign(c.begin(), c.end());
-        seq.resize(n);
-        for (int i = 0; i < n; i++) seq[c[lev[i]]++] = i;
+        seq.resize(T);
+        for (int i = 0; i < T; i++) seq[c[lev[i]]++] = i;
     };
     {
         std::vector<int> lev(n, 0);
-        int nl = n ? 1 : 0;
-        for (int i = 0; i < n; i++) {
+        int nl = T ? 1 : 0;
+        for (int i = 0; i < T; i++) {
             int v = 0;
             for (int q = s.Lrp[i]; q < s.Lrp[i + 1]; q++) v = std::max(v, lev[s.Lrj[q]] + 1);
             lev[i] = v;
             nl = std::max(nl, v + 1);
         }
         order_by_level(lev, nl, s.lseq, s.lsptr);
+        if (T < n) {
+            for (int i = T; i < n; i++) s.lseq.push_back(i);
+            s.lsptr.push_back(n);
+        }
         std::fill(lev.begin(), lev.end(), 0);
-        nl = n ? 1 : 0;
-        for (int i = n - 1; i >= 0; i--) {
+        nl = T ? 1 : 0;
+        for (int i = T - 1; i >= 0; i--) {
             int v = 0;
-            for (int q = s.Urp[i]; q < s.Urp[i + 1]; q++) v = std::max(v, lev[s.Urj[q]] + 1);
+            for (int q = s.Urp[i]; q < s.Urp[i + 1]; q++)
+                if (s.Urj[q] < T) v = std::max(v, lev[s.Urj[q]] + 1);
             lev[i] = v;
             nl = std::max(nl, v + 1);
         }
         order_by_level(lev, nl, s.useq, s.usptr);
+        s.tail_rend.resize(n - T);
+        for (int i = T; i < n; i++) {
+            int q = s.Lrp[i];
+            while (q < s.Lrp[i + 1] && s.Lrj[q] < T) q++;
+            s.tail_rend[i - T] = q;
+        }
     }
     s.rowperm_final.resize(n);
     for (int k = 0; k < n; k++) s.rowperm_final[k] = an.rowperm_pre[f.pivrow[k]];
@@ -189,7 +229,6 @@ void build_schedule(const Analysis &an, const Factor &f, const cktlu_options &op
                 s.Acsrc[fill[r]++] = p;
             }
     }
-    s.tail0 = n;
 }
 
 }  // namespace cktlu

@@ -5,6 +5,10 @@ Refactorization with pivot check must reproduce the oracle's re-factorization
 bit-exact, factor values within a rounding-level tolerance scaled by |L||U|.
 Solves must reach eta_inf <= 1e-12 in FP64 (1e-10 with FP32 factors and FP64
 refinement) and agree with the oracle's solution up to the conditioning.
+
+`tail` selects the order of the trailing block factored densely: -1 none
+(every column sparse), 64 one full panel, 100 a full and a ragged panel, 200
+three full panels and a ragged one, 10**6 every column dense.
 """
 import sys
 
@@ -47,11 +51,12 @@ SIZES = [
 ]
 
 
+@pytest.mark.parametrize("tail", [-1, 64, 100, 200])
 @pytest.mark.parametrize("name,make", SIZES, ids=[s[0] for s in SIZES])
-def test_refactorize_and_solve_fp64(ck, oracle_mod, name, make):
+def test_refactorize_and_solve_fp64(ck, oracle_mod, name, make, tail):
     c = make()
-    say("case", name, "n", c.n)
-    s = ck.SparseLU(c.n, c.colptr, c.rowind, eps=EPS)
+    say("case", name, "n", c.n, "tail", tail)
+    s = ck.SparseLU(c.n, c.colptr, c.rowind, eps=EPS, dense_tail=tail)
     s.factorize(dev(c.values))
     a0 = s.analysis()
     prev = a0["pivrow"]
@@ -74,15 +79,17 @@ def test_refactorize_and_solve_fp64(ck, oracle_mod, name, make):
         xg = x.cpu().numpy()
         eta = oracle_mod.backward_error(c.colptr, c.rowind, vh, xg, b)
         assert eta <= 1e-12, eta
+        assert s.stats()["dense_tail"] == (min(tail, c.n) if tail > 0 else 0)
         xo = oracle_mod.solve(lu, a0["rowperm_pre"], a0["colperm"], b)
         eta_o = oracle_mod.backward_error(c.colptr, c.rowind, vh, xo, b)
         assert eta_o <= 1e-12
         assert np.abs(xg - xo).max() <= 1e-6 * np.abs(xo).max()
 
 
-def test_refactorize_deterministic(ck):
+@pytest.mark.parametrize("tail", [-1, 200])
+def test_refactorize_deterministic(ck, tail):
     c = mnagen.mesh_transistor(40, 40, seed=5)
-    s = ck.SparseLU(c.n, c.colptr, c.rowind, eps=EPS)
+    s = ck.SparseLU(c.n, c.colptr, c.rowind, eps=EPS, dense_tail=tail)
     s.factorize(dev(c.values))
     v = dev(mnagen.perturb(c.values, 5, 0, 1))
     s.refactorize(v)
@@ -92,9 +99,10 @@ def test_refactorize_deterministic(ck):
     assert np.array_equal(f1["Lx"], f2["Lx"]) and np.array_equal(f1["Ux"], f2["Ux"])
 
 
-def test_refactorize_nocheck_equals_checked(ck):
+@pytest.mark.parametrize("tail", [-1, 100])
+def test_refactorize_nocheck_equals_checked(ck, tail):
     c = mnagen.layered_rc(20, 20, 3, seed=6)
-    s = ck.SparseLU(c.n, c.colptr, c.rowind, eps=EPS)
+    s = ck.SparseLU(c.n, c.colptr, c.rowind, eps=EPS, dense_tail=tail)
     s.factorize(dev(c.values))
     v = dev(mnagen.perturb(c.values, 6, 0, 1))
     s.refactorize(v)
@@ -104,27 +112,76 @@ def test_refactorize_nocheck_equals_checked(ck):
     assert np.array_equal(f1["Lx"], f2["Lx"]) and np.array_equal(f1["Ux"], f2["Ux"])
 
 
-def test_forced_failure_fallback(ck, oracle_mod):
-    """Pivot check forced to fail at one column: the fallback result equals a
-    fresh host factorization from the same sequence (nothing re-pivots)."""
+@pytest.mark.parametrize("where", ["sparse", "dense"])
+def test_forced_failure_fallback(ck, oracle_mod, where):
+    """Pivot check forced to fail at one column (a sparse one, or one inside the
+    dense trailing block): the fallback re-factors the restart set on the host
+    and the result equals the oracle's re-factorization (nothing re-pivots)."""
     c = mnagen.mesh_transistor(30, 30, seed=8)
+    tail = 100
+    col = c.n // 2 if where == "sparse" else c.n - tail + 37
     o = ck.cktlu_default_options()
     o.pivot_eps = EPS
-    o.force_fail_col = c.n // 2
+    o.force_fail_col = col
+    o.dense_tail_size = tail
     ctx = ck.cktlu_create(o)
     try:
         assert ck.cktlu_analyze(ctx, c.n, c.colptr, c.rowind) == 0
         assert ck.cktlu_factorize(ctx, dev(c.values)) == 0
+        n = c.n
+        rp, cp, pv, par = (np.zeros(n, np.int32) for _ in range(4))
+        assert ck.cktlu_get_analysis(ctx, rp, cp, pv, par) == 0
         vh = mnagen.perturb(c.values, 8, 0, 1)
         info = ck.cktlu_refactor_info()
         rc = ck.cktlu_refactorize(ctx, dev(vh), info)
         assert rc == ck.CKTLU_W_REPIVOTED and info.repivoted == 1
-        assert info.first_fail_col == c.n // 2
+        assert info.first_fail_col == col
         assert info.restart_size >= 1
         st = ck.cktlu_get_stats(ctx)
-        assert st.n_repivot == 1
+        assert st.n_repivot == 1 and st.dense_tail == tail
+        lu = oracle_refactor(oracle_mod, c, vh, dict(rowperm_pre=rp, colperm=cp), EPS, pv)
+        pv2 = np.zeros(n, np.int32)
+        assert ck.cktlu_get_analysis(ctx, None, None, pv2, None) == 0
+        assert np.array_equal(pv2, lu.pivrow)
+        x = torch.zeros(n, dtype=torch.float64, device="cuda:0")
+        sinfo = ck.cktlu_solve_info()
+        assert ck.cktlu_solve(ctx, 1, dev(c.rhs[0]), n, x, n, sinfo) == 0
+        torch.cuda.synchronize()
+        assert oracle_mod.backward_error(c.colptr, c.rowind, vh, x.cpu().numpy(), c.rhs[0]) <= 1e-12
     finally:
         ck.cktlu_destroy(ctx)
+
+
+def test_value_driven_repivot_in_dense_block(ck, oracle_mod):
+    """The pivot U(k,k) of a column inside the dense block shrunk to 1e-8 of its
+    value (through the diagonal entry of A, which only column k's pivot sees):
+    the dense pivot test fails at k, the fallback re-pivots, and pattern, pivot
+    sequence and values equal the oracle's re-factorization."""
+    c = mnagen.mesh_transistor(30, 30, seed=22)
+    tail = 100
+    s = ck.SparseLU(c.n, c.colptr, c.rowind, eps=EPS, dense_tail=tail)
+    s.factorize(dev(c.values))
+    a0 = s.analysis()
+    vh = mnagen.perturb(c.values, 22, 0, 1)
+    lu1 = oracle_refactor(oracle_mod, c, vh, a0, EPS, a0["pivrow"])
+    assert lu1.status == 0
+    k = c.n - tail + 30
+    assert np.array_equal(lu1.pivrow, a0["pivrow"])
+    ukk = lu1.Ux[lu1.Up[k + 1] - 1]                  # diagonal: last U entry of column k
+    assert lu1.Ui[lu1.Up[k + 1] - 1] == k
+    vh[_pivot_entry(c, a0, k)] -= ukk * (1 - 1e-8)
+    lu = oracle_refactor(oracle_mod, c, vh, a0, EPS, a0["pivrow"])
+    assert lu.status == 0 and lu.nswaps >= 1
+    rc, info = s.refactorize(dev(vh))
+    assert rc == ck.CKTLU_W_REPIVOTED and info.repivoted == 1
+    assert info.first_fail_col == k
+    a = s.analysis()
+    assert np.array_equal(a["pivrow"], lu.pivrow)
+    compare_factors(s.factors(), lu, RTOL)
+    x = torch.zeros(c.n, dtype=torch.float64, device="cuda:0")
+    s.solve(dev(c.rhs[0]), x)
+    torch.cuda.synchronize()
+    assert oracle_mod.backward_error(c.colptr, c.rowind, vh, x.cpu().numpy(), c.rhs[0]) <= 1e-12
 
 
 def _pivot_entry(c, a, k):
@@ -172,10 +229,11 @@ def test_value_driven_repivot_matches_oracle(ck, oracle_mod, nfail):
     assert oracle_mod.backward_error(c.colptr, c.rowind, vh, x.cpu().numpy(), c.rhs[0]) <= 1e-12
 
 
+@pytest.mark.parametrize("tail", [-1, 100])
 @pytest.mark.parametrize("nrhs", [1, 3, 8])
-def test_multi_rhs(ck, oracle_mod, nrhs):
+def test_multi_rhs(ck, oracle_mod, nrhs, tail):
     c = mnagen.power_grid(50, 50, n_src=40, nrhs=nrhs, seed=9)
-    s = ck.SparseLU(c.n, c.colptr, c.rowind, eps=EPS)
+    s = ck.SparseLU(c.n, c.colptr, c.rowind, eps=EPS, dense_tail=tail)
     s.factorize(dev(c.values))
     B = dev(c.rhs)              # [nrhs, n]: column r at r*n
     X = torch.zeros_like(B)
@@ -187,9 +245,11 @@ def test_multi_rhs(ck, oracle_mod, nrhs):
         assert eta <= 1e-12
 
 
-def test_fp32_ir(ck, oracle_mod):
+@pytest.mark.parametrize("tail", [-1, 200])
+def test_fp32_ir(ck, oracle_mod, tail):
     c = mnagen.mesh_transistor(50, 50, seed=12)
-    s = ck.SparseLU(c.n, c.colptr, c.rowind, eps=EPS, precision=ck.CKTLU_FP32_IR, ir_tol=1e-10)
+    s = ck.SparseLU(c.n, c.colptr, c.rowind, eps=EPS, precision=ck.CKTLU_FP32_IR, ir_tol=1e-10,
+                    dense_tail=tail)
     s.factorize(dev(c.values))
     a0 = s.analysis()
     vh = mnagen.perturb(c.values, 12, 0, 1)
@@ -206,14 +266,20 @@ def test_fp32_ir(ck, oracle_mod):
     assert eta <= 1e-10, (eta, sinfo.ir_iters, sinfo.used_fp64)
     xo = oracle_mod.solve(lu, a0["rowperm_pre"], a0["colperm"], b)
     assert np.abs(xg - xo).max() <= 1e-6 * np.abs(xo).max()
+    # a second solve with the same factors (the dense block is re-read, not re-factored)
+    x2 = torch.zeros(c.n, dtype=torch.float64, device="cuda:0")
+    s.solve(dev(b), x2)
+    torch.cuda.synchronize()
+    assert oracle_mod.backward_error(c.colptr, c.rowind, vh, x2.cpu().numpy(), b) <= 1e-10
 
 
-def test_tiny_and_degenerate(ck, oracle_mod):
+@pytest.mark.parametrize("tail", [-1, 10 ** 6])
+def test_tiny_and_degenerate(ck, oracle_mod, tail):
     for kind, n in [("diagonal", 1), ("diagonal", 7), ("dense", 12), ("tridiagonal", 200),
-                    ("arrow_first", 40), ("permutation", 9)]:
+                    ("arrow_first", 40), ("permutation", 9), ("dense", 130)]:
         c = mnagen.hand_pattern(kind, n, seed=3)
-        say("case", kind, n)
-        s = ck.SparseLU(c.n, c.colptr, c.rowind, eps=EPS)
+        say("case", kind, n, "tail", tail)
+        s = ck.SparseLU(c.n, c.colptr, c.rowind, eps=EPS, dense_tail=tail)
         s.factorize(dev(c.values))
         vh = mnagen.perturb(c.values, 3, 0, 1)
         rc, info = s.refactorize(dev(vh))
@@ -227,17 +293,18 @@ def test_tiny_and_degenerate(ck, oracle_mod):
         assert eta <= 1e-12, (kind, n, eta)
 
 
-def test_batched_equals_single(ck):
+@pytest.mark.parametrize("tail", [-1, 100])
+def test_batched_equals_single(ck, tail):
     c = mnagen.mesh_transistor(30, 30, seed=13)
     batch = 5
     V = mnagen.instance_values(c, batch, 0.3, seed=13)
-    s = ck.SparseLU(c.n, c.colptr, c.rowind, eps=EPS)
+    s = ck.SparseLU(c.n, c.colptr, c.rowind, eps=EPS, dense_tail=tail)
     s.factorize(dev(c.values))
     status = torch.zeros(batch, dtype=torch.int32, device="cuda:0")
     s.refactorize_batched(batch, dev(V), status)
     torch.cuda.synchronize()
     st = status.cpu().numpy()
-    single = ck.SparseLU(c.n, c.colptr, c.rowind, eps=EPS)
+    single = ck.SparseLU(c.n, c.colptr, c.rowind, eps=EPS, dense_tail=tail)
     single.factorize(dev(c.values))
     for i in range(batch):
         fb = s.factors(instance=i)
@@ -249,3 +316,31 @@ def test_batched_equals_single(ck):
         fs = single.factors()
         assert np.array_equal(fb["Lx"], fs["Lx"]) and np.array_equal(fb["Ux"], fs["Ux"]), i
     assert (st == -1).sum() >= 1
+
+
+@pytest.mark.parametrize("tail", [-1, 100])
+def test_solve_batched(ck, oracle_mod, tail):
+    """Batched solves after a batched refactorization: every instance that
+    passed its check is solved to eta <= 1e-12; failed instances are skipped."""
+    c = mnagen.mesh_transistor(30, 30, seed=14)
+    batch, nrhs = 4, 2
+    V = mnagen.instance_values(c, batch, 0.2, seed=14)
+    s = ck.SparseLU(c.n, c.colptr, c.rowind, eps=EPS, dense_tail=tail)
+    s.factorize(dev(c.values))
+    status = torch.zeros(batch, dtype=torch.int32, device="cuda:0")
+    s.refactorize_batched(batch, dev(V), status)
+    rng = np.random.default_rng(14)
+    B = rng.standard_normal((batch, nrhs, c.n))
+    X = torch.full((batch, nrhs, c.n), 7.0, dtype=torch.float64, device="cuda:0")
+    s.solve_batched(batch, nrhs, dev(B), X, status)
+    torch.cuda.synchronize()
+    st = status.cpu().numpy()
+    Xh = X.cpu().numpy()
+    assert (st == -1).sum() >= 1
+    for i in range(batch):
+        if st[i] != -1:
+            assert np.all(Xh[i] == 7.0)
+            continue
+        for r in range(nrhs):
+            eta = oracle_mod.backward_error(c.colptr, c.rowind, V[i], Xh[i, r], B[i, r])
+            assert eta <= 1e-12, (i, r, eta)

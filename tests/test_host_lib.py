@@ -156,3 +156,33 @@ def test_footprint_estimate_positive():
     s = _analysed(c)
     s.factorize_host(c.values)
     assert s.footprint_bytes(1) > 12 * (s.stats()["nnz_l"] + s.stats()["nnz_u"])
+
+
+def _trailing_density(f, n, D):
+    T = n - D
+    cnt = 0
+    for k in range(T, n):
+        cnt += int((f["Ui"][f["Up"][k]:f["Up"][k + 1]] >= T).sum())
+        cnt += int((f["Li"][f["Lp"][k]:f["Lp"][k + 1]] >= T).sum())
+    return cnt / float(D * D)
+
+
+def test_dense_tail_selection():
+    """Trailing dense block: forced sizes are clamped to n, -1 disables it, and
+    the automatic choice is the largest multiple of 64 in [256, 8192] whose
+    block of L+U reaches the density threshold."""
+    c = mnagen.mesh_transistor(60, 60, seed=4)
+    for tail, want in [(-1, 0), (100, 100), (10 ** 6, c.n)]:
+        s = ck.SparseLU(c.n, c.colptr, c.rowind, dense_tail=tail)
+        s.factorize_host(c.values)
+        assert s.stats()["dense_tail"] == want
+    for dens in (0.2, 0.3, 0.5):
+        s = ck.SparseLU(c.n, c.colptr, c.rowind, dense_tail=0, dense_tail_density=dens)
+        s.factorize_host(c.values)
+        D = s.stats()["dense_tail"]
+        f = s.factors()
+        if D:
+            assert D % 64 == 0 and 256 <= D <= min(8192, c.n)
+            assert _trailing_density(f, c.n, D) >= dens
+        for Dl in range(max(D + 64, 256), min(8192, c.n) // 64 * 64 + 1, 64):
+            assert _trailing_density(f, c.n, Dl) < dens, (dens, D, Dl)
