@@ -83,8 +83,8 @@ int upload(DevBuf &b, const std::vector<V> &v, hipStream_t st) {
 }
 
 DevBuf *all_buffers(Device &d, int i) {
-    DevBuf *all[] = {&d.seq, &d.Dp, &d.Dlen, &d.Fi, &d.nU, &d.Ap, &d.colperm, &d.amap, &d.task_tgt,
-                     &d.src_ptr, &d.src_col, &d.src_slot, &d.Lrp, &d.Lrj,
+    DevBuf *all[] = {&d.seq, &d.Dp, &d.Dlen, &d.Fi, &d.nU, &d.Ap, &d.colperm, &d.amap, &d.task4,
+                     &d.item4, &d.Lrp, &d.Lrj,
                      &d.Lrsrc, &d.Urp, &d.Urj, &d.Ursrc, &d.udiag, &d.lseq, &d.useq, &d.rowperm,
                      &d.colperm_sol, &d.Acp, &d.Acj, &d.Acsrc, &d.Fx64, &d.Fx32, &d.Aval, &d.done,
                      &d.ctrl, &d.vec, &d.S, &d.tail_rend};
@@ -170,10 +170,8 @@ int upload_all(cktlu_ctx *c) {
     if ((rc = upload(d.Ap, c->an.Ap, st))) return rc;
     if ((rc = upload(d.colperm, c->an.colperm, st))) return rc;
     if ((rc = upload(d.amap, s.amap, st))) return rc;
-    if ((rc = upload(d.task_tgt, s.task_tgt, st))) return rc;
-    if ((rc = upload(d.src_ptr, s.src_ptr, st))) return rc;
-    if ((rc = upload(d.src_col, s.src_col, st))) return rc;
-    if ((rc = upload(d.src_slot, s.src_slot, st))) return rc;
+    if ((rc = upload(d.task4, s.task4, st))) return rc;
+    if ((rc = upload(d.item4, s.item4, st))) return rc;
     if ((rc = upload(d.Lrp, s.Lrp, st))) return rc;
     if ((rc = upload(d.Lrj, s.Lrj, st))) return rc;
     if ((rc = upload(d.Lrsrc, s.Lrsrc, st))) return rc;
@@ -314,6 +312,7 @@ int run_refactor(cktlu_ctx *c, int batch, const double *values_dev, bool fp32, b
         d.epoch = 1;
     }
     LCHK(launch_reset_ctrl((int *)d.ctrl.p, 1 + 2 * batch, INT_MAX, st));
+    const Schedule &s = c->s;
     RefactorArgs a;
     a.n = c->an.n;
     a.batch = batch;
@@ -334,13 +333,13 @@ int run_refactor(cktlu_ctx *c, int batch, const double *values_dev, bool fp32, b
     a.eps = c->opt.pivot_eps;
     a.epoch = d.epoch;
     a.force_fail_col = force_col;
-    a.task_tgt = (const int *)d.task_tgt.p;
-    a.src_ptr = (const int *)d.src_ptr.p;
-    a.src_col = (const int *)d.src_col.p;
-    a.src_slot = (const int *)d.src_slot.p;
+    a.task4 = (const int *)d.task4.p;
+    a.item4 = (const int *)d.item4.p;
+    a.T = s.tail0;
+    a.D = c->an.n - s.tail0;
+    a.S = d.S.p;
     a.fp32 = fp32 ? 1 : 0;
     a.check = check ? 1 : 0;
-    const Schedule &s = c->s;
     LCHK(launch_refactor_init(a, st));
     // level l: check level l, normalise level l-1, update tasks of level l; then normalise the last
     for (int l = 0; l <= s.n_rlevels; l++) {
@@ -357,7 +356,7 @@ int run_refactor(cktlu_ctx *c, int batch, const double *values_dev, bool fp32, b
         da.epoch = a.epoch;
         da.force_fail_col = force_col;
         da.check = a.check;
-        LCHK(launch_dense_refactor(da, st));
+        LCHK(launch_dense_refactor(da, false, st));
         d.S_prec = fp32 ? 1 : 0;
     }
     return CKTLU_OK;

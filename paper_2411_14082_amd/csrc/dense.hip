@@ -375,13 +375,15 @@ int launch_dense_gather(const DenseArgs &a, void *stream) {
     return (int)hipGetLastError();
 }
 
-int launch_dense_refactor(const DenseArgs &a, void *stream) {
+int launch_dense_refactor(const DenseArgs &a, bool gather, void *stream) {
     hipStream_t st = (hipStream_t)stream;
     const int D = a.D;
     if (D <= 0) return 0;
     const dim3 gw = wave_grid((int64_t)D * a.batch);
-    int e = launch_dense_gather(a, stream);
-    if (e) return e;
+    if (gather) {
+        const int e = launch_dense_gather(a, stream);
+        if (e) return e;
+    }
     for (int p = 0; p < D; p += NB) {
         const int nb = D - p < NB ? D - p : NB;
         const int rest = D - p - nb;

@@ -72,6 +72,7 @@ struct Schedule {
     // (columns of level l, ascending); src_slot is the offset of the source's row in the
     // target column (where the multiplier U(j,k) lives)
     std::vector<int> task_ptr, task_tgt, src_ptr, src_col, src_slot;
+    std::vector<int> task4, item4;            // the same tasks packed for the device (4 ints each)
     std::vector<int> amap;                    // user nonzero -> slot offset inside its column
     // device layout of the factor storage: column k occupies [Dp[k], Dp[k] + Dlen[k]);
     // every column starts on a kColAlign-entry boundary
@@ -103,7 +104,7 @@ struct Device {
     int batch_cap = 0;                 // instances the value buffers hold
     // pattern / schedule
     DevBuf seq, Dp, Dlen, Fi, nU, Ap, colperm, amap;
-    DevBuf task_tgt, src_ptr, src_col, src_slot;
+    DevBuf task4, item4;
     DevBuf Lrp, Lrj, Lrsrc, Urp, Urj, Ursrc, udiag, lseq, useq, rowperm, colperm_sol;
     DevBuf Acp, Acj, Acsrc;
     // values and status words
@@ -130,10 +131,12 @@ constexpr int YS = 16;          // doubles per solve-vector row (one 128-byte li
 struct RefactorArgs {
     int n, batch;
     const int *seq, *Dp, *Dlen, *Fi, *nU, *Ap, *colperm, *amap;
-    const int *task_tgt, *src_ptr, *src_col, *src_slot;   // right-looking update tasks
+    const int *task4, *item4;  // right-looking update tasks and their items (int4 records)
     const double *Aval;        // batch x nnzA
     int64_t nnzA, nnzF;
     void *Fx;                  // batch x nnzF (double or float)
+    int T, D;                  // columns [T, n) form the dense block: their rows >= T live in S
+    void *S;                   // batch x D x D (factor type), column-major
     int *done;                 // batch x n: epoch of the last successful computation of each column
     int *ctrl;                 // [1, 1+batch) interrupt words, [1+batch, 1+2 batch) first failing column
     double eps;
@@ -200,8 +203,8 @@ struct DenseArgs {
 };
 // S <- rows >= T of the tail columns of Fx (zeros elsewhere)
 int launch_dense_gather(const DenseArgs &a, void *stream);
-// gather, blocked LU with the pivot test, scatter back into Fx
-int launch_dense_refactor(const DenseArgs &a, void *stream);
+// (gather if asked), blocked LU with the pivot test, scatter back into Fx
+int launch_dense_refactor(const DenseArgs &a, bool gather, void *stream);
 // y rows [T, n): lower (unit) or upper triangular solve with the block in S
 int launch_dense_solve(const DenseArgs &a, double *y, int nrhs, const int *skip, bool upper, void *stream);
 

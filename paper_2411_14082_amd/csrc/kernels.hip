@@ -37,6 +37,7 @@ namespace cktlu_dev {
 constexpr int WAVE = 64;
 constexpr int WG = 256;
 constexpr int WAVES = WG / WAVE;
+constexpr int kStageRows = 1024;   // target-column rows staged in LDS per wavefront
 
 // Orders this wavefront's global-memory accesses across its lanes.
 __device__ __forceinline__ void wave_sync() {
@@ -56,7 +57,8 @@ __device__ __forceinline__ double wave_sum(double v) {
 }
 
 // ------------------------------------------------------------ refactorize
-// one wavefront per (column, instance)
+// one wavefront per (column, instance).  Columns of the dense block keep their
+// rows >= T in S (column k at S + (k - T) D), so those rows are zeroed there.
 template <typename T>
 __global__ __launch_bounds__(WG) void refactor_init_kernel(RefactorArgs a) {
     const int lane = threadIdx.x & (WAVE - 1), wv = threadIdx.x / WAVE;
@@ -67,10 +69,24 @@ __global__ __launch_bounds__(WG) void refactor_init_kernel(RefactorArgs a) {
     T *x = reinterpret_cast<T *>(a.Fx) + (size_t)inst * a.nnzF + a.Dp[k];
     const double *Av = a.Aval + (size_t)inst * a.nnzA;
     const int len = a.Dlen[k];
-    for (int i = lane; i < len; i += WAVE) x[i] = T(0);
-    wave_sync();
     const int c = a.colperm[k];
-    for (int p = a.Ap[c] + lane; p < a.Ap[c + 1]; p += WAVE) x[a.amap[p]] = (T)Av[p];
+    if (k < a.T) {
+        for (int i = lane; i < len; i += WAVE) x[i] = T(0);
+        wave_sync();
+        for (int p = a.Ap[c] + lane; p < a.Ap[c + 1]; p += WAVE) x[a.amap[p]] = (T)Av[p];
+        return;
+    }
+    T *Sk = reinterpret_cast<T *>(a.S) + (size_t)inst * a.D * a.D + (size_t)(k - a.T) * a.D;
+    const int *rows = a.Fi + a.Dp[k];
+    for (int i = lane; i < len; i += WAVE) x[i] = T(0);
+    for (int i = lane; i < a.D; i += WAVE) Sk[i] = T(0);
+    wave_sync();
+    for (int p = a.Ap[c] + lane; p < a.Ap[c + 1]; p += WAVE) {
+        const int slot = a.amap[p];
+        const int r = rows[slot];
+        if (r >= a.T) Sk[r - a.T] = (T)Av[p];
+        else x[slot] = (T)Av[p];
+    }
 }
 
 // one wavefront per (task, instance); tasks: [checks | normalisations | updates]
@@ -121,29 +137,59 @@ __global__ __launch_bounds__(WG) void refactor_level_kernel(RefactorArgs a, int 
         if (lane == 0) a.done[(size_t)inst * a.n + j] = (int)a.epoch;
         return;
     }
-    // (c) update task: target column k, sources j of this level in ascending order
-    const int t = tbeg + idx - nchk - nnorm;
-    const int k = a.task_tgt[t];
-    const int bk = a.Dp[k], lenk = a.Dlen[k];
-    const int *rowsk = a.Fi + bk;
+    // (c) update task: target column k, sources j of this level in ascending order.
+    // Rows of the target are located by binary search in the searched part of column k,
+    // staged in LDS when it fits; rows >= T of a dense-block target are addressed in S.
+    const int4 tr = reinterpret_cast<const int4 *>(a.task4)[tbeg + idx - nchk - nnorm];
+    const int iend = reinterpret_cast<const int4 *>(a.task4)[tbeg + idx - nchk - nnorm + 1].w;
+    const int k = tr.x, bk = tr.y, slen = tr.z;
     T *xk = Fx + bk;
-    for (int s = a.src_ptr[t]; s < a.src_ptr[t + 1]; ++s) {
-        const int j = a.src_col[s];
-        const int sj = a.src_slot[s];
-        const T mult = xk[sj];                      // U(j,k): final, no source of this task updates it
-        const int bj = a.Dp[j], nuj = a.nU[j], lenj = a.Dlen[j];
-        const T inv = T(1) / Fx[bj + nuj - 1];      // the pivot of j (not yet divided into L(:,j))
-        for (int q = bj + nuj + lane; q < bj + lenj; q += WAVE) {
-            const int r = a.Fi[q];
-            const T l = Fx[q] * inv;
-            int lo = sj + 1, hi = lenk;             // rows of L(:,j) lie below row j in column k
-            while (lo < hi) {
-                const int mid = (lo + hi) >> 1;
-                if (rowsk[mid] < r) lo = mid + 1; else hi = mid;
-            }
-            if (lo < lenk) xk[lo] -= l * mult;     // always found: struct(L(:,j)) is inside struct(col k)
+    const int *rowsk = a.Fi + bk;
+    T *Sk = k >= a.T ? reinterpret_cast<T *>(a.S) + (size_t)inst * a.D * a.D + (size_t)(k - a.T) * a.D : nullptr;
+    __shared__ int srows[WAVES][kStageRows];
+    int *lrows = srows[wv];
+    const bool staged = slen <= kStageRows;
+    if (staged) {
+        for (int i = lane; i < slen; i += WAVE) lrows[i] = rowsk[i];
+    }
+    const int4 *items = reinterpret_cast<const int4 *>(a.item4);
+    for (int s0 = tr.w; s0 < iend; s0 += WAVE) {
+        // lane u holds item s0 + u: its record, the pivot of its source and its multiplier
+        int4 it = make_int4(0, 0, 0, 0);
+        T inv = T(0), mult = T(0);
+        if (s0 + lane < iend) {
+            it = items[s0 + lane];
+            inv = T(1) / Fx[it.x];                  // the pivot of j (not yet divided into L(:,j))
+            mult = xk[it.w];                        // U(j,k): final, no source of this level updates it
         }
-        wave_sync();
+        wave_sync();                                // staged rows and earlier updates visible
+        const int ns = min(WAVE, iend - s0);
+        for (int u = 0; u < ns; ++u) {
+            const int lb = __shfl(it.y, u), le = __shfl(it.z, u), lo0 = __shfl(it.w, u) + 1;
+            const T iv = __shfl(inv, u), m = __shfl(mult, u);
+            for (int q = lb + lane; q < le; q += WAVE) {
+                const int r = a.Fi[q];
+                const T l = Fx[q] * iv;
+                if (Sk && r >= a.T) {
+                    Sk[r - a.T] -= l * m;
+                    continue;
+                }
+                int lo = lo0, hi = slen;            // rows of L(:,j) lie below row j in column k
+                if (staged) {
+                    while (lo < hi) {
+                        const int mid = (lo + hi) >> 1;
+                        if (lrows[mid] < r) lo = mid + 1; else hi = mid;
+                    }
+                } else {
+                    while (lo < hi) {
+                        const int mid = (lo + hi) >> 1;
+                        if (rowsk[mid] < r) lo = mid + 1; else hi = mid;
+                    }
+                }
+                if (lo < slen) xk[lo] -= l * m;     // always found: struct(L(:,j)) is inside struct(col k)
+            }
+            wave_sync();
+        }
     }
 }
 

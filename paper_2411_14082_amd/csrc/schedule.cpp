@@ -167,6 +167,34 @@ void build_schedule(const Analysis &an, const Factor &f, const cktlu_options &op
         }
         if (nitems > 0) s.src_ptr.push_back((int)nitems);
         for (int q = 0; q < nl; q++) s.task_ptr[q + 1] += s.task_ptr[q];
+        // packed device records.  Task t: {target k, Dp[k], length of the part of column k
+        // that is searched for rows (all of it for k < T, its rows < T otherwise), first
+        // item}; one more record after the last task holds the item count.  Item i:
+        // {position of the pivot of its source j, begin and end of L(:,j), offset of row j
+        // in the target column (where the multiplier U(j,k) lives)}.
+        const int ntasks = (int)s.task_tgt.size();
+        s.task4.assign(4 * (size_t)(ntasks + 1), 0);
+        for (int t = 0; t < ntasks; t++) {
+            const int k = s.task_tgt[t];
+            int slen = s.Dlen[k];
+            if (k >= T) {
+                const int *b = f.Fi.data() + f.Fp[k], *e = f.Fi.data() + f.Fp[k + 1];
+                slen = (int)(std::lower_bound(b, e, T) - b);
+            }
+            s.task4[4 * (size_t)t + 0] = k;
+            s.task4[4 * (size_t)t + 1] = s.Dp[k];
+            s.task4[4 * (size_t)t + 2] = slen;
+            s.task4[4 * (size_t)t + 3] = s.src_ptr[t];
+        }
+        s.task4[4 * (size_t)ntasks + 3] = (int)nitems;
+        s.item4.resize(4 * (size_t)nitems);
+        for (int64_t i = 0; i < nitems; i++) {
+            const int j = s.src_col[i];
+            s.item4[4 * i + 0] = s.Dp[j] + f.nU[j] - 1;
+            s.item4[4 * i + 1] = s.Dp[j] + f.nU[j];
+            s.item4[4 * i + 2] = s.Dp[j] + s.Dlen[j];
+            s.item4[4 * i + 3] = s.src_slot[i];
+        }
     }
     // ---- solve levels of the sparse rows [0, T): row i of L waits for every j with
     // L(i,j) != 0, row i of U for every j > i with U(i,j) != 0 (rows >= T of U are
