@@ -6,11 +6,13 @@
 // trailing block S = A22 - L21 U12 (what the sweep left in those columns,
 // rows >= T) is gathered into a dense column-major D x D matrix per instance and
 // factored without pivoting by a blocked right-looking LU, panels of NB = 64:
-//   dlu_diag   one workgroup factors the NB x NB diagonal block in LDS;
-//   dlu_trsm   L21 = A21 U11^-1 (a thread per row) and U12 = L11^-1 A12 (a
-//              wavefront per column);
-//   dlu_gemm   A22 -= L21 U12 on the matrix cores: 64 x 64 output tiles, K = NB,
-//              v_mfma_f64_16x16x4 (v_mfma_f32_16x16x4 for FP32 factors).
+//   dlu_panel  every workgroup factors the NB x NB diagonal block in registers
+//              (one barrier per step), then computes its share of
+//              L21 = A21 U11^-1 (four lanes per row) or U12 = L11^-1 A12 (a
+//              wavefront per four columns);
+//   dlu_gemm   A22 -= L21 U12 on the matrix cores: 128 x 128 output tiles,
+//              K = NB in LDS-staged chunks, v_mfma_f64_16x16x4 (v_mfma_f32_16x16x4
+//              for FP32 factors).
 // dlu_check applies the pivot test of the sparse columns to every dense column
 // c (x = L(:,c) u_cc are its values before division):
 //   fail  <=>  u_cc not finite or zero, or max_{i>c} |x(i,c)| not finite, or
@@ -19,11 +21,12 @@
 // pivot-check fallback and the factor getters read).  The dense triangular
 // solves run one launch per NB-row block: the launch for block b applies block
 // b-1's solution to every row below it (the rectangle of the paper's trapezoid
-// slices, Section V-A) and then solves block b (the triangle).
+// slices, Section V-A) and then one wavefront solves block b (the triangle).
 #include <hip/hip_runtime.h>
 
 #include <climits>
 #include <cstdint>
+#include <type_traits>
 
 #include "internal.h"
 
@@ -93,145 +96,208 @@ __global__ __launch_bounds__(256) void tail_scatter_kernel(DenseArgs a) {
 }
 
 // ------------------------------------------------------------- blocked LU
-// One workgroup per instance factors the diagonal block [p, p+nb) in LDS.
-template <typename T>
-__global__ __launch_bounds__(256) void dlu_diag_kernel(DenseArgs a, int p) {
-    __shared__ T blk[NB][NB + 1];                     // blk[col][row]
-    const int inst = blockIdx.x;
-    if (sweep_failed(a, inst)) return;
-    T *S = inst_S<T>(a, inst);
-    const int nb = min(NB, a.D - p);
-    const int tid = threadIdx.x;
-    for (int e = tid; e < nb * nb; e += 256) {
-        const int cc = e / nb, rr = e % nb;
-        blk[cc][rr] = S[(size_t)(p + cc) * a.D + p + rr];
-    }
-    __syncthreads();
-    for (int kk = 0; kk < nb; kk++) {
-        const T piv = blk[kk][kk];
-        for (int i = kk + 1 + tid; i < nb; i += 256) blk[kk][i] = blk[kk][i] / piv;
-        __syncthreads();
-        const int m = nb - kk - 1;
-        for (int e = tid; e < m * m; e += 256) {
-            const int cc = kk + 1 + e / m, rr = kk + 1 + e % m;
-            blk[cc][rr] -= blk[kk][rr] * blk[cc][kk];
-        }
-        __syncthreads();
-    }
-    for (int e = tid; e < nb * nb; e += 256) {
-        const int cc = e / nb, rr = e % nb;
-        S[(size_t)(p + cc) * a.D + p + rr] = blk[cc][rr];
-    }
+__device__ __forceinline__ double readlane(double v, int l) {
+    const long long b = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_readlane((int)b, l);
+    const int hi = __builtin_amdgcn_readlane((int)(b >> 32), l);
+    return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+__device__ __forceinline__ float readlane(float v, int l) {
+    return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), l));
 }
 
-// Panel [p, p+NB) with rows/columns below/right of it (only launched for full
-// panels).  Workgroups [0, nrow_blocks) compute L21 = A21 U11^-1, a thread per
-// row; the others U12 = L11^-1 A12, a wavefront per column.
+// Factors the nb x nb diagonal block at (p, p) of S (padded to NB x NB with the
+// identity) without pivoting, in the registers of the workgroup's four
+// wavefronts: wavefront g holds rows 16g..16g+15, lane c column c.  Step kk
+// publishes row kk through LDS (double-buffered, one barrier per step); the
+// column-kk values come from lane kk by readlane.  L = x / u_kk is formed as
+// x * (1 / u_kk).  On return blk[col][row] holds unit L below the diagonal and U
+// on and above it, invd[k] = 1 / u_kk, and the workgroup is synchronised.
 template <typename T>
-__global__ __launch_bounds__(256) void dlu_trsm_kernel(DenseArgs a, int p, int nrow_blocks) {
-    __shared__ T blk[NB][NB + 1];                     // blk[col][row]: unit L11 below, U11 on and above
+__device__ void diag_factor(const T *S, int D, int p, int nb, T (*blk)[NB + 1], T *rowbuf, T *invd) {
+    const int lane = threadIdx.x & (WAVE - 1), g = threadIdx.x / WAVE;
+    T v[16];
+#pragma unroll
+    for (int e = 0; e < 16; e++) {
+        const int r = 16 * g + e;
+        v[e] = (lane < nb && r < nb) ? S[(size_t)(p + lane) * D + p + r] : (lane == r ? T(1) : T(0));
+    }
+#pragma unroll 1
+    for (int kb = 0; kb < 4; kb++) {
+#pragma unroll
+        for (int e0 = 0; e0 < 16; e0++) {
+            const int kk = 16 * kb + e0;
+            T *rb = rowbuf + (kk & 1) * NB;
+            if (g == kb) rb[lane] = v[e0];               // row kk: U(kk, c) for c >= kk
+            __syncthreads();
+            const T inv = T(1) / rb[kk];
+            if (threadIdx.x == 0) invd[kk] = inv;
+            // lanes c > kk subtract x * U(kk,c) / u_kk; lane kk keeps x / u_kk
+            const T w = lane > kk ? rb[lane] * inv : (lane == kk ? -inv : T(0));
+            const T keep = lane == kk ? T(0) : T(1);
+            if (g >= kb) {
+#pragma unroll
+                for (int e = 0; e < 16; e++) {
+                    if (16 * g + e > kk) {
+                        const T x = readlane(v[e], kk);
+                        v[e] = fma(-x, w, v[e] * keep);
+                    }
+                }
+            }
+        }
+    }
+#pragma unroll
+    for (int e = 0; e < 16; e++) blk[lane][16 * g + e] = v[e];
+    __syncthreads();
+}
+
+// One panel [p, p+nb): every workgroup factors the diagonal block (workgroup 0
+// writes it back); workgroups [1, 1+nrb) then compute L21 = A21 U11^-1 for 64
+// rows each (four lanes per row, sixteen columns per lane), the others
+// U12 = L11^-1 A12 for sixteen columns each (four per wavefront, lane m = row m).
+template <typename T>
+__global__ __launch_bounds__(256) void dlu_panel_kernel(DenseArgs a, int p, int nrb) {
+    __shared__ T blk[NB][NB + 1];
+    __shared__ T rowbuf[2 * NB];
+    __shared__ T invd[NB];
     const int inst = blockIdx.y;
     if (sweep_failed(a, inst)) return;
     T *S = inst_S<T>(a, inst);
-    const int tid = threadIdx.x;
-    for (int e = tid; e < NB * NB; e += 256) {
-        const int cc = e / NB, rr = e % NB;
-        blk[cc][rr] = S[(size_t)(p + cc) * a.D + p + rr];
-    }
-    __syncthreads();
-    if ((int)blockIdx.x < nrow_blocks) {
-        const int i = p + NB + blockIdx.x * 256 + tid;   // one row of A21
-        if (i >= a.D) return;
-        T l[NB];
-#pragma unroll
-        for (int m = 0; m < NB; m++) l[m] = S[(size_t)(p + m) * a.D + i];
-        // row-vector solve l U11 = a, right-looking: independent updates per step
-#pragma unroll
-        for (int kk = 0; kk < NB; kk++) {
-            l[kk] = l[kk] / blk[kk][kk];
-#pragma unroll
-            for (int m = kk + 1; m < NB; m++) l[m] -= l[kk] * blk[m][kk];
+    const int D = a.D;
+    const int nb = min(NB, D - p);
+    const int tid = threadIdx.x, lane = tid & (WAVE - 1);
+    diag_factor<T>(S, D, p, nb, blk, rowbuf, invd);
+    if (blockIdx.x == 0) {
+        for (int e = tid; e < nb * nb; e += 256) {
+            const int cc = e / nb, rr = e % nb;
+            S[(size_t)(p + cc) * D + p + rr] = blk[cc][rr];
         }
-#pragma unroll
-        for (int m = 0; m < NB; m++) S[(size_t)(p + m) * a.D + i] = l[m];
         return;
     }
-    const int lane = tid & (WAVE - 1);
-    const int j = p + NB + (blockIdx.x - nrow_blocks) * 4 + tid / WAVE;
-    if (j >= a.D) return;
-    T *col = S + (size_t)j * a.D + p;                 // lane m holds row p + m
-    T v = col[lane];
-    for (int kk = 0; kk < NB; kk++) {
-        const T u = __shfl(v, kk);
-        if (lane > kk) v -= blk[kk][lane] * u;
+    if ((int)blockIdx.x <= nrb) {
+        const int i = p + NB + ((int)blockIdx.x - 1) * 64 + tid / 4;
+        const int sub = tid & 3;
+        const bool act = i < D;
+        T l[16];
+#pragma unroll
+        for (int e = 0; e < 16; e++) l[e] = act ? S[(size_t)(p + 16 * sub + e) * D + i] : T(0);
+#pragma unroll 1
+        for (int kb = 0; kb < 4; kb++) {
+#pragma unroll
+            for (int e0 = 0; e0 < 16; e0++) {
+                const int kk = 16 * kb + e0;
+                if (sub == kb) l[e0] = l[e0] * invd[kk];
+                const T lk = __shfl(l[e0], (lane & ~3) | kb);
+#pragma unroll
+                for (int e = 0; e < 16; e++)
+                    if (16 * sub + e > kk) l[e] -= lk * blk[16 * sub + e][kk];
+            }
+        }
+        if (act) {
+#pragma unroll
+            for (int e = 0; e < 16; e++) S[(size_t)(p + 16 * sub + e) * D + i] = l[e];
+        }
+        return;
     }
-    col[lane] = v;
+    const int j0 = p + NB + (((int)blockIdx.x - 1 - nrb) * 4 + tid / WAVE) * 4;
+    T v[4];
+#pragma unroll
+    for (int q = 0; q < 4; q++) v[q] = j0 + q < D ? S[(size_t)(j0 + q) * D + p + lane] : T(0);
+    for (int kk = 0; kk < NB; kk++) {
+        const T lmk = lane > kk ? blk[kk][lane] : T(0);   // L(lane, kk)
+#pragma unroll
+        for (int q = 0; q < 4; q++) v[q] -= lmk * readlane(v[q], kk);
+    }
+#pragma unroll
+    for (int q = 0; q < 4; q++)
+        if (j0 + q < D) S[(size_t)(j0 + q) * D + p + lane] = v[q];
 }
 
-// A22 -= L21 U12 over the trailing block [p+NB, D)^2: a 64 x 64 output tile per
-// workgroup, each wavefront a 32 x 32 quadrant of 2 x 2 MFMA 16 x 16 tiles.
+// A22 -= L21 U12 over the trailing block [p+NB, D)^2: a 128 x 128 output tile
+// per workgroup, each wavefront 64 x 64 as 4 x 4 MFMA 16 x 16 tiles; K = NB in
+// chunks of 16 staged through LDS (double-buffered, prefetched in registers).
+// The MFMA computes the transposed tile (U12^T L21^T), so that a lane's results
+// run down a column of S and the read-modify-write of C is coalesced.
 // MFMA 16x16x4 operands: lane l holds A(l%16, l/16) and B(l/16, l%16).
 template <typename T>
 __global__ __launch_bounds__(256) void dlu_gemm_kernel(DenseArgs a, int p) {
-    __shared__ T As[NB][64 + 1];                      // As[k][row]
-    __shared__ T Bs[NB][64 + 1];                      // Bs[k][col]
+    constexpr int TM = 128, KC = 16, LD = TM + 4;
+    __shared__ T As[2][KC][LD];                       // [buf][k][row]
+    __shared__ T Bs[2][KC][LD];                       // [buf][k][col]
     const int inst = blockIdx.z;
     if (sweep_failed(a, inst)) return;
     T *S = inst_S<T>(a, inst);
-    const int base = p + NB;
-    const int r0 = base + blockIdx.x * 64, c0 = base + blockIdx.y * 64;
+    const int D = a.D;
+    const int r0 = p + NB + blockIdx.x * TM, c0 = p + NB + blockIdx.y * TM;
     const int tid = threadIdx.x;
-    for (int e = tid; e < NB * 64; e += 256) {
-        const int kk = e / 64, rr = e % 64;
-        As[kk][rr] = r0 + rr < a.D ? S[(size_t)(p + kk) * a.D + r0 + rr] : T(0);
-        const int kb = e % NB, cc = e / NB;
-        Bs[kb][cc] = c0 + cc < a.D ? S[(size_t)(c0 + cc) * a.D + p + kb] : T(0);
-    }
+    T ra[8], rb[8];
+    auto fetch = [&](int kc) {
+#pragma unroll
+        for (int u = 0; u < 8; u++) {
+            const int e = tid + 256 * u;
+            const int ka = e / TM, rr = e % TM;
+            ra[u] = r0 + rr < D ? S[(size_t)(p + kc + ka) * D + r0 + rr] : T(0);
+            const int kb = e % KC, cc = e / KC;
+            rb[u] = c0 + cc < D ? S[(size_t)(c0 + cc) * D + p + kc + kb] : T(0);
+        }
+    };
+    auto stash = [&](int buf) {
+#pragma unroll
+        for (int u = 0; u < 8; u++) {
+            const int e = tid + 256 * u;
+            As[buf][e / TM][e % TM] = ra[u];
+            Bs[buf][e % KC][e / KC] = rb[u];
+        }
+    };
+    fetch(0);
+    stash(0);
     __syncthreads();
     const int lane = tid & (WAVE - 1), wv = tid / WAVE;
     const int qr = wv >> 1, qc = wv & 1;
     const int li = lane & 15, lk = lane >> 4;
-    if constexpr (sizeof(T) == 8) {
-        d4 acc[2][2];
-        for (int ti = 0; ti < 2; ti++)
-            for (int tj = 0; tj < 2; tj++) acc[ti][tj] = d4{0, 0, 0, 0};
-        for (int s = 0; s < NB / 4; s++) {
-            const double a0 = As[4 * s + lk][32 * qr + li], a1 = As[4 * s + lk][32 * qr + 16 + li];
-            const double b0 = Bs[4 * s + lk][32 * qc + li], b1 = Bs[4 * s + lk][32 * qc + 16 + li];
-            acc[0][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b0, acc[0][0], 0, 0, 0);
-            acc[0][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b1, acc[0][1], 0, 0, 0);
-            acc[1][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b0, acc[1][0], 0, 0, 0);
-            acc[1][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b1, acc[1][1], 0, 0, 0);
-        }
-        // FP64 result: lane l, element q holds row 4q + l/16, column l%16
-        for (int ti = 0; ti < 2; ti++)
-            for (int tj = 0; tj < 2; tj++)
-                for (int q = 0; q < 4; q++) {
-                    const int row = r0 + 32 * qr + 16 * ti + 4 * q + lk;
-                    const int col = c0 + 32 * qc + 16 * tj + li;
-                    if (row < a.D && col < a.D) S[(size_t)col * a.D + row] -= acc[ti][tj][q];
+    typedef typename std::conditional<sizeof(T) == 8, d4, f4>::type acc_t;
+    acc_t acc[4][4];
+#pragma unroll
+    for (int ti = 0; ti < 4; ti++)
+#pragma unroll
+        for (int tj = 0; tj < 4; tj++) acc[ti][tj] = acc_t{0, 0, 0, 0};
+#pragma unroll 1
+    for (int ch = 0; ch < NB / KC; ch++) {
+        const int buf = ch & 1;
+        if (ch + 1 < NB / KC) fetch((ch + 1) * KC);
+#pragma unroll
+        for (int s = 0; s < KC / 4; s++) {
+            T av[4], bv[4];
+#pragma unroll
+            for (int t = 0; t < 4; t++) {
+                av[t] = As[buf][4 * s + lk][64 * qr + 16 * t + li];
+                bv[t] = Bs[buf][4 * s + lk][64 * qc + 16 * t + li];
+            }
+#pragma unroll
+            for (int ti = 0; ti < 4; ti++)
+#pragma unroll
+                for (int tj = 0; tj < 4; tj++) {
+                    if constexpr (sizeof(T) == 8)
+                        acc[ti][tj] = __builtin_amdgcn_mfma_f64_16x16x4f64(bv[tj], av[ti], acc[ti][tj], 0, 0, 0);
+                    else
+                        acc[ti][tj] = __builtin_amdgcn_mfma_f32_16x16x4f32(bv[tj], av[ti], acc[ti][tj], 0, 0, 0);
                 }
-    } else {
-        f4 acc[2][2];
-        for (int ti = 0; ti < 2; ti++)
-            for (int tj = 0; tj < 2; tj++) acc[ti][tj] = f4{0, 0, 0, 0};
-        for (int s = 0; s < NB / 4; s++) {
-            const float a0 = As[4 * s + lk][32 * qr + li], a1 = As[4 * s + lk][32 * qr + 16 + li];
-            const float b0 = Bs[4 * s + lk][32 * qc + li], b1 = Bs[4 * s + lk][32 * qc + 16 + li];
-            acc[0][0] = __builtin_amdgcn_mfma_f32_16x16x4f32(a0, b0, acc[0][0], 0, 0, 0);
-            acc[0][1] = __builtin_amdgcn_mfma_f32_16x16x4f32(a0, b1, acc[0][1], 0, 0, 0);
-            acc[1][0] = __builtin_amdgcn_mfma_f32_16x16x4f32(a1, b0, acc[1][0], 0, 0, 0);
-            acc[1][1] = __builtin_amdgcn_mfma_f32_16x16x4f32(a1, b1, acc[1][1], 0, 0, 0);
         }
-        // FP32 result: lane l, element q holds row 4(l/16) + q, column l%16
-        for (int ti = 0; ti < 2; ti++)
-            for (int tj = 0; tj < 2; tj++)
-                for (int q = 0; q < 4; q++) {
-                    const int row = r0 + 32 * qr + 16 * ti + 4 * lk + q;
-                    const int col = c0 + 32 * qc + 16 * tj + li;
-                    if (row < a.D && col < a.D) S[(size_t)col * a.D + row] -= acc[ti][tj][q];
-                }
+        if (ch + 1 < NB / KC) stash(buf ^ 1);
+        __syncthreads();
     }
+    // transposed tile: FP64 element q of lane l is C(row l%16, col 4q + l/16),
+    // FP32 element q is C(row l%16, col 4(l/16) + q)
+#pragma unroll
+    for (int ti = 0; ti < 4; ti++)
+#pragma unroll
+        for (int tj = 0; tj < 4; tj++)
+#pragma unroll
+            for (int q = 0; q < 4; q++) {
+                const int row = r0 + 64 * qr + 16 * ti + li;
+                const int col = c0 + 64 * qc + 16 * tj + (sizeof(T) == 8 ? 4 * q + lk : 4 * lk + q);
+                if (row < D && col < D) S[(size_t)col * D + row] -= acc[ti][tj][q];
+            }
 }
 
 // Pivot test of every dense column: one wavefront per (column, instance).
@@ -265,7 +331,7 @@ __global__ __launch_bounds__(256) void dlu_check_kernel(DenseArgs a) {
 template <typename T, int NR>
 __global__ __launch_bounds__(256) void dtrsv_lower_kernel(DenseArgs a, double *y, int b, const int *skip) {
     __shared__ double yb[NB][NR];
-    __shared__ double ys[NB][NR];
+    __shared__ double tri[NB][NB + 1];                // tri[col][row] of the diagonal block
     const int inst = blockIdx.y;
     if (skip && skip[inst] != -1) return;
     const T *S = inst_S<T>(a, inst);
@@ -291,16 +357,23 @@ __global__ __launch_bounds__(256) void dtrsv_lower_kernel(DenseArgs a, double *y
         __syncthreads();
     }
     if (blockIdx.x != 0) return;
+    // block b: stage L(p.., p..) in LDS, then one wavefront substitutes (lane i = row p + i)
     const int p = b * NB, nb = min(NB, D - p);
-    for (int e = tid; e < nb * NR; e += 256) ys[e / NR][e % NR] = yt[(size_t)(p + e / NR) * YS + e % NR];
+    for (int e = tid; e < nb * nb; e += 256) tri[e / nb][e % nb] = (double)S[(size_t)(p + e / nb) * D + p + e % nb];
     __syncthreads();
+    if (tid >= WAVE) return;
+    double yv[NR];
+#pragma unroll
+    for (int r = 0; r < NR; r++) yv[r] = tid < nb ? yt[(size_t)(p + tid) * YS + r] : 0.0;
     for (int kk = 0; kk < nb; kk++) {
-        const int r = tid % NR;
-        for (int ii = kk + 1 + tid / NR; ii < nb; ii += 256 / NR)
-            ys[ii][r] -= (double)S[(size_t)(p + kk) * D + p + ii] * ys[kk][r];
-        __syncthreads();
+        const double lik = tid > kk && tid < nb ? tri[kk][tid] : 0.0;
+#pragma unroll
+        for (int r = 0; r < NR; r++) yv[r] -= lik * readlane(yv[r], kk);
     }
-    for (int e = tid; e < nb * NR; e += 256) yt[(size_t)(p + e / NR) * YS + e % NR] = ys[e / NR][e % NR];
+    if (tid < nb) {
+#pragma unroll
+        for (int r = 0; r < NR; r++) yt[(size_t)(p + tid) * YS + r] = yv[r];
+    }
 }
 
 // Upper with its diagonal: launch b handles block blk = nblk-1-b: it applies
@@ -308,7 +381,7 @@ __global__ __launch_bounds__(256) void dtrsv_lower_kernel(DenseArgs a, double *y
 template <typename T, int NR>
 __global__ __launch_bounds__(256) void dtrsv_upper_kernel(DenseArgs a, double *y, int b, const int *skip) {
     __shared__ double yb[NB][NR];
-    __shared__ double ys[NB][NR];
+    __shared__ double tri[NB][NB + 1];                // tri[col][row] of the diagonal block
     const int inst = blockIdx.y;
     if (skip && skip[inst] != -1) return;
     const T *S = inst_S<T>(a, inst);
@@ -337,17 +410,25 @@ __global__ __launch_bounds__(256) void dtrsv_upper_kernel(DenseArgs a, double *y
         __syncthreads();
     }
     if (blockIdx.x != 0) return;
-    for (int e = tid; e < nb * NR; e += 256) ys[e / NR][e % NR] = yt[(size_t)(p + e / NR) * YS + e % NR];
+    for (int e = tid; e < nb * nb; e += 256) tri[e / nb][e % nb] = (double)S[(size_t)(p + e / nb) * D + p + e % nb];
     __syncthreads();
+    if (tid >= WAVE) return;
+    double yv[NR];
+#pragma unroll
+    for (int r = 0; r < NR; r++) yv[r] = tid < nb ? yt[(size_t)(p + tid) * YS + r] : 0.0;
     for (int kk = nb - 1; kk >= 0; kk--) {
-        if (tid < NR) ys[kk][tid] = ys[kk][tid] / (double)S[(size_t)(p + kk) * D + p + kk];
-        __syncthreads();
-        const int r = tid % NR;
-        for (int ii = tid / NR; ii < kk; ii += 256 / NR)
-            ys[ii][r] -= (double)S[(size_t)(p + kk) * D + p + ii] * ys[kk][r];
-        __syncthreads();
+        if (tid == kk) {
+#pragma unroll
+            for (int r = 0; r < NR; r++) yv[r] = yv[r] / tri[kk][kk];
+        }
+        const double uik = tid < kk ? tri[kk][tid] : 0.0;
+#pragma unroll
+        for (int r = 0; r < NR; r++) yv[r] -= uik * readlane(yv[r], kk);
     }
-    for (int e = tid; e < nb * NR; e += 256) yt[(size_t)(p + e / NR) * YS + e % NR] = ys[e / NR][e % NR];
+    if (tid < nb) {
+#pragma unroll
+        for (int r = 0; r < NR; r++) yt[(size_t)(p + tid) * YS + r] = yv[r];
+    }
 }
 
 template <typename T, int NR>
@@ -386,15 +467,13 @@ int launch_dense_refactor(const DenseArgs &a, bool gather, void *stream) {
     }
     for (int p = 0; p < D; p += NB) {
         const int nb = D - p < NB ? D - p : NB;
-        const int rest = D - p - nb;
-        if (a.fp32) hipLaunchKernelGGL((dlu_diag_kernel<float>), dim3(a.batch), dim3(256), 0, st, a, p);
-        else hipLaunchKernelGGL((dlu_diag_kernel<double>), dim3(a.batch), dim3(256), 0, st, a, p);
-        if (rest > 0) {   // nb == NB here
-            const int nrb = (rest + 255) / 256, ncb = (rest + 3) / 4;
-            const dim3 gt((unsigned)(nrb + ncb), (unsigned)a.batch);
-            if (a.fp32) hipLaunchKernelGGL((dlu_trsm_kernel<float>), gt, dim3(256), 0, st, a, p, nrb);
-            else hipLaunchKernelGGL((dlu_trsm_kernel<double>), gt, dim3(256), 0, st, a, p, nrb);
-            const dim3 gg((unsigned)((rest + 63) / 64), (unsigned)((rest + 63) / 64), (unsigned)a.batch);
+        const int rest = D - p - nb;   // > 0 only for full panels
+        const int nrb = (rest + 63) / 64, ncb = (rest + 15) / 16;
+        const dim3 gp((unsigned)(1 + nrb + ncb), (unsigned)a.batch);
+        if (a.fp32) hipLaunchKernelGGL((dlu_panel_kernel<float>), gp, dim3(256), 0, st, a, p, nrb);
+        else hipLaunchKernelGGL((dlu_panel_kernel<double>), gp, dim3(256), 0, st, a, p, nrb);
+        if (rest > 0) {
+            const dim3 gg((unsigned)((rest + 127) / 128), (unsigned)((rest + 127) / 128), (unsigned)a.batch);
             if (a.fp32) hipLaunchKernelGGL((dlu_gemm_kernel<float>), gg, dim3(256), 0, st, a, p);
             else hipLaunchKernelGGL((dlu_gemm_kernel<double>), gg, dim3(256), 0, st, a, p);
         }
