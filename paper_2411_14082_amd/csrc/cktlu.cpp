@@ -83,11 +83,11 @@ int upload(DevBuf &b, const std::vector<V> &v, hipStream_t st) {
 }
 
 DevBuf *all_buffers(Device &d, int i) {
-    DevBuf *all[] = {&d.seq, &d.Dp, &d.Dlen, &d.Fi, &d.nU, &d.Ap, &d.colperm, &d.amap, &d.task4,
-                     &d.item4, &d.Lrp, &d.Lrj,
-                     &d.Lrsrc, &d.Urp, &d.Urj, &d.Ursrc, &d.udiag, &d.lseq, &d.useq, &d.rowperm,
+    DevBuf *all[] = {&d.seq, &d.Dp, &d.Dlen, &d.Fi, &d.nU, &d.Ap, &d.colperm, &d.amap, &d.colrec, &d.task8,
+                     &d.item4, &d.lrec, &d.urec,
+                     &d.Lrjs, &d.Urjs, &d.rowperm,
                      &d.colperm_sol, &d.Acp, &d.Acj, &d.Acsrc, &d.Fx64, &d.Fx32, &d.Aval, &d.done,
-                     &d.ctrl, &d.vec, &d.S, &d.tail_rend};
+                     &d.ctrl, &d.vec, &d.S};
     const int cnt = (int)(sizeof(all) / sizeof(all[0]));
     return i < cnt ? all[i] : nullptr;
 }
@@ -170,23 +170,18 @@ int upload_all(cktlu_ctx *c) {
     if ((rc = upload(d.Ap, c->an.Ap, st))) return rc;
     if ((rc = upload(d.colperm, c->an.colperm, st))) return rc;
     if ((rc = upload(d.amap, s.amap, st))) return rc;
-    if ((rc = upload(d.task4, s.task4, st))) return rc;
+    if ((rc = upload(d.colrec, s.colrec, st))) return rc;
+    if ((rc = upload(d.task8, s.task8, st))) return rc;
     if ((rc = upload(d.item4, s.item4, st))) return rc;
-    if ((rc = upload(d.Lrp, s.Lrp, st))) return rc;
-    if ((rc = upload(d.Lrj, s.Lrj, st))) return rc;
-    if ((rc = upload(d.Lrsrc, s.Lrsrc, st))) return rc;
-    if ((rc = upload(d.Urp, s.Urp, st))) return rc;
-    if ((rc = upload(d.Urj, s.Urj, st))) return rc;
-    if ((rc = upload(d.Ursrc, s.Ursrc, st))) return rc;
-    if ((rc = upload(d.udiag, s.udiag, st))) return rc;
-    if ((rc = upload(d.lseq, s.lseq, st))) return rc;
-    if ((rc = upload(d.useq, s.useq, st))) return rc;
+    if ((rc = upload(d.lrec, s.lrec, st))) return rc;
+    if ((rc = upload(d.urec, s.urec, st))) return rc;
+    if ((rc = upload(d.Lrjs, s.Lrjs, st))) return rc;
+    if ((rc = upload(d.Urjs, s.Urjs, st))) return rc;
     if ((rc = upload(d.rowperm, s.rowperm_final, st))) return rc;
     if ((rc = upload(d.colperm_sol, c->an.colperm, st))) return rc;
     if ((rc = upload(d.Acp, s.Acp, st))) return rc;
     if ((rc = upload(d.Acj, s.Acj, st))) return rc;
     if ((rc = upload(d.Acsrc, s.Acsrc, st))) return rc;
-    if ((rc = upload(d.tail_rend, s.tail_rend, st))) return rc;
     // value buffers sized for the current batch capacity (at least one instance)
     const int batch = std::max(1, d.batch_cap);
     d.batch_cap = 0;
@@ -333,7 +328,8 @@ int run_refactor(cktlu_ctx *c, int batch, const double *values_dev, bool fp32, b
     a.eps = c->opt.pivot_eps;
     a.epoch = d.epoch;
     a.force_fail_col = force_col;
-    a.task4 = (const int *)d.task4.p;
+    a.colrec = (const int *)d.colrec.p;
+    a.task8 = (const int *)d.task8.p;
     a.item4 = (const int *)d.item4.p;
     a.T = s.tail0;
     a.D = c->an.n - s.tail0;
@@ -456,19 +452,16 @@ int tri_solves(cktlu_ctx *c, int nrhs, int batch, double *z, bool fp32, const in
     a.n = c->an.n;
     a.nrhs = nrhs;
     a.batch = batch;
-    a.Lrp = (const int *)d.Lrp.p; a.Lrj = (const int *)d.Lrj.p; a.Lrsrc = (const int *)d.Lrsrc.p;
-    a.Urp = (const int *)d.Urp.p; a.Urj = (const int *)d.Urj.p; a.Ursrc = (const int *)d.Ursrc.p;
-    a.udiag = (const int *)d.udiag.p;
-    a.lseq = (const int *)d.lseq.p;
-    a.useq = (const int *)d.useq.p;
+    a.lrec = (const int *)d.lrec.p;
+    a.urec = (const int *)d.urec.p;
+    a.Lrjs = (const int *)d.Lrjs.p;
+    a.Urjs = (const int *)d.Urjs.p;
     a.Fx = fp32 ? d.Fx32.p : d.Fx64.p;
     a.nnzF = nnzF(c);
     a.fp32 = fp32 ? 1 : 0;
     a.y = z;
     a.skip = skip;
     const Schedule &s = c->s;
-    a.tail0 = s.tail0;
-    a.tail_rend = (const int *)d.tail_rend.p;
     // sparse L levels (the last one holds the dense rows: their entries in sparse columns)
     for (int l = 0; l + 1 < (int)s.lsptr.size(); l++) LCHK(launch_lsolve_level(a, s.lsptr[l], s.lsptr[l + 1], st));
     if (s.tail0 < c->an.n) {

@@ -69,9 +69,18 @@ __global__ __launch_bounds__(256) void tail_gather_kernel(DenseArgs a) {
     for (int i = lane; i < a.D; i += WAVE) S[i] = T(0);
     __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "workgroup");
     __builtin_amdgcn_wave_barrier();
-    for (int q = lane; q < len; q += WAVE) {
-        const int r = rows[q];
-        if (r >= a.T) S[r - a.T] = Fx[q];
+    for (int q0 = 0; q0 < len; q0 += 4 * WAVE) {      // four loads in flight per lane
+        int r[4];
+        T x[4];
+#pragma unroll
+        for (int u = 0; u < 4; u++) {
+            const int q = q0 + u * WAVE + lane;
+            r[u] = q < len ? rows[q] : -1;
+            x[u] = q < len ? Fx[q] : T(0);
+        }
+#pragma unroll
+        for (int u = 0; u < 4; u++)
+            if (r[u] >= a.T) S[r[u] - a.T] = x[u];
     }
 }
 
@@ -87,9 +96,18 @@ __global__ __launch_bounds__(256) void tail_scatter_kernel(DenseArgs a) {
     T *Fx = reinterpret_cast<T *>(a.Fx) + (size_t)inst * a.nnzF + a.Dp[k];
     const int *rows = a.Fi + a.Dp[k];
     const int len = a.Dlen[k];
-    for (int q = lane; q < len; q += WAVE) {
-        const int r = rows[q];
-        if (r >= a.T) Fx[q] = S[r - a.T];
+    for (int q0 = 0; q0 < len; q0 += 4 * WAVE) {      // four loads in flight per lane
+        int r[4];
+        T x[4];
+#pragma unroll
+        for (int u = 0; u < 4; u++) {
+            const int q = q0 + u * WAVE + lane;
+            r[u] = q < len ? rows[q] : -1;
+            x[u] = r[u] >= a.T ? S[r[u] - a.T] : T(0);
+        }
+#pragma unroll
+        for (int u = 0; u < 4; u++)
+            if (r[u] >= a.T) Fx[q0 + u * WAVE + lane] = x[u];
     }
     // columns before the first failing one are final
     if (lane == 0 && k < a.ctrl[1 + a.batch + inst]) a.done[(size_t)inst * a.n + k] = (int)a.epoch;
@@ -107,58 +125,41 @@ __device__ __forceinline__ float readlane(float v, int l) {
 }
 
 // Factors the nb x nb diagonal block at (p, p) of S (padded to NB x NB with the
-// identity) without pivoting, in the registers of the workgroup's four
-// wavefronts: wavefront g holds rows 16g..16g+15, lane c column c.  Step kk
-// publishes row kk through LDS (double-buffered, one barrier per step); the
-// column-kk values come from lane kk by readlane.  L = x / u_kk is formed as
-// x * (1 / u_kk).  On return blk[col][row] holds unit L below the diagonal and U
-// on and above it, invd[k] = 1 / u_kk, and the workgroup is synchronised.
+// identity) without pivoting, in one wavefront: lane r holds row r, v[c] its
+// entry in column c, fully unrolled, so step kk reads row kk (U(kk, c)) from
+// lane kk by readlane and needs no barrier.  L = x / u_kk is formed as
+// x * (1 / u_kk).  The factors go to blk[col][row] (unit L below the diagonal, U
+// on and above it) and invd[k] = 1 / u_kk.
 template <typename T>
-__device__ void diag_factor(const T *S, int D, int p, int nb, T (*blk)[NB + 1], T *rowbuf, T *invd) {
-    const int lane = threadIdx.x & (WAVE - 1), g = threadIdx.x / WAVE;
-    T v[16];
+__device__ void diag_factor_wave(const T *S, int D, int p, int nb, T (*blk)[NB + 1], T *invd) {
+    const int lane = threadIdx.x & (WAVE - 1);
+    T v[NB];
 #pragma unroll
-    for (int e = 0; e < 16; e++) {
-        const int r = 16 * g + e;
-        v[e] = (lane < nb && r < nb) ? S[(size_t)(p + lane) * D + p + r] : (lane == r ? T(1) : T(0));
-    }
-#pragma unroll 1
-    for (int kb = 0; kb < 4; kb++) {
+    for (int c = 0; c < NB; c++)
+        v[c] = (lane < nb && c < nb) ? S[(size_t)(p + c) * D + p + lane] : (lane == c ? T(1) : T(0));
 #pragma unroll
-        for (int e0 = 0; e0 < 16; e0++) {
-            const int kk = 16 * kb + e0;
-            T *rb = rowbuf + (kk & 1) * NB;
-            if (g == kb) rb[lane] = v[e0];               // row kk: U(kk, c) for c >= kk
-            __syncthreads();
-            const T inv = T(1) / rb[kk];
-            if (threadIdx.x == 0) invd[kk] = inv;
-            // lanes c > kk subtract x * U(kk,c) / u_kk; lane kk keeps x / u_kk
-            const T w = lane > kk ? rb[lane] * inv : (lane == kk ? -inv : T(0));
-            const T keep = lane == kk ? T(0) : T(1);
-            if (g >= kb) {
+    for (int kk = 0; kk < NB; kk++) {
+        const T inv = T(1) / readlane(v[kk], kk);
+        if (lane == 0) invd[kk] = inv;
+        const T l = lane > kk ? v[kk] * inv : T(0);
+        v[kk] = lane > kk ? l : v[kk];
 #pragma unroll
-                for (int e = 0; e < 16; e++) {
-                    if (16 * g + e > kk) {
-                        const T x = readlane(v[e], kk);
-                        v[e] = fma(-x, w, v[e] * keep);
-                    }
-                }
-            }
-        }
+        for (int c = kk + 1; c < NB; c++) v[c] = fma(-l, readlane(v[c], kk), v[c]);
     }
 #pragma unroll
-    for (int e = 0; e < 16; e++) blk[lane][16 * g + e] = v[e];
-    __syncthreads();
+    for (int c = 0; c < NB; c++) blk[c][lane] = v[c];
 }
 
-// One panel [p, p+nb): every workgroup factors the diagonal block (workgroup 0
-// writes it back); workgroups [1, 1+nrb) then compute L21 = A21 U11^-1 for 64
-// rows each (four lanes per row, sixteen columns per lane), the others
-// U12 = L11^-1 A12 for sixteen columns each (four per wavefront, lane m = row m).
+// One panel [p, p+nb).  In every workgroup wavefront 0 factors the diagonal
+// block (workgroup 0 writes it back) while the others wait; then each
+// wavefront computes sixteen rows of L21 = A21 U11^-1 or sixteen columns of
+// U12 = L11^-1 A12: lane m holds element m of each of its rows (columns) and
+// step kk broadcasts element kk by readlane.  Workgroups [1, 1+nrb) take 64 rows
+// each, the rest 64 columns each.
 template <typename T>
 __global__ __launch_bounds__(256) void dlu_panel_kernel(DenseArgs a, int p, int nrb) {
+    constexpr int RW = 16;                            // rows (columns) per wavefront
     __shared__ T blk[NB][NB + 1];
-    __shared__ T rowbuf[2 * NB];
     __shared__ T invd[NB];
     const int inst = blockIdx.y;
     if (sweep_failed(a, inst)) return;
@@ -166,51 +167,53 @@ __global__ __launch_bounds__(256) void dlu_panel_kernel(DenseArgs a, int p, int 
     const int D = a.D;
     const int nb = min(NB, D - p);
     const int tid = threadIdx.x, lane = tid & (WAVE - 1);
-    diag_factor<T>(S, D, p, nb, blk, rowbuf, invd);
+    const int wv = __builtin_amdgcn_readfirstlane(tid / WAVE);
+    // loads of this wavefront's rows / columns, issued before the wait
+    const bool rows = (int)blockIdx.x <= nrb;
+    const int first = p + NB + (((int)blockIdx.x - 1 - (rows ? 0 : nrb)) * 4 + wv) * RW;
+    T x[RW];
+    if (blockIdx.x != 0) {
+#pragma unroll
+        for (int q = 0; q < RW; q++) {
+            const bool in = first + q < D;
+            x[q] = !in ? T(0) : rows ? S[(size_t)(p + lane) * D + first + q] : S[(size_t)(first + q) * D + p + lane];
+        }
+    }
+    if (wv == 0) diag_factor_wave<T>(S, D, p, nb, blk, invd);
+    __syncthreads();
     if (blockIdx.x == 0) {
-        for (int e = tid; e < nb * nb; e += 256) {
-            const int cc = e / nb, rr = e % nb;
-            S[(size_t)(p + cc) * D + p + rr] = blk[cc][rr];
+#pragma unroll
+        for (int e = 0; e < 16; e++) {
+            const int rr = 16 * wv + e;
+            if (lane < nb && rr < nb) S[(size_t)(p + lane) * D + p + rr] = blk[lane][rr];
         }
         return;
     }
-    if ((int)blockIdx.x <= nrb) {
-        const int i = p + NB + ((int)blockIdx.x - 1) * 64 + tid / 4;
-        const int sub = tid & 3;
-        const bool act = i < D;
-        T l[16];
+    if (rows) {
+        // rows of L21: x U11 = a, right-looking over kk
+        for (int kk = 0; kk < NB; kk++) {
+            const T inv = invd[kk];
+            const T ukm = blk[lane][kk];                  // U(kk, lane)
+            const T w = lane > kk ? ukm : (lane == kk ? T(-1) : T(0));
+            const T keep = lane == kk ? T(0) : T(1);
 #pragma unroll
-        for (int e = 0; e < 16; e++) l[e] = act ? S[(size_t)(p + 16 * sub + e) * D + i] : T(0);
-#pragma unroll 1
-        for (int kb = 0; kb < 4; kb++) {
-#pragma unroll
-            for (int e0 = 0; e0 < 16; e0++) {
-                const int kk = 16 * kb + e0;
-                if (sub == kb) l[e0] = l[e0] * invd[kk];
-                const T lk = __shfl(l[e0], (lane & ~3) | kb);
-#pragma unroll
-                for (int e = 0; e < 16; e++)
-                    if (16 * sub + e > kk) l[e] -= lk * blk[16 * sub + e][kk];
-            }
+            for (int q = 0; q < RW; q++) x[q] = fma(-(readlane(x[q], kk) * inv), w, x[q] * keep);
         }
-        if (act) {
 #pragma unroll
-            for (int e = 0; e < 16; e++) S[(size_t)(p + 16 * sub + e) * D + i] = l[e];
-        }
+        for (int q = 0; q < RW; q++)
+            if (first + q < D) S[(size_t)(p + lane) * D + first + q] = x[q];
         return;
     }
-    const int j0 = p + NB + (((int)blockIdx.x - 1 - nrb) * 4 + tid / WAVE) * 4;
-    T v[4];
-#pragma unroll
-    for (int q = 0; q < 4; q++) v[q] = j0 + q < D ? S[(size_t)(j0 + q) * D + p + lane] : T(0);
+    // columns of U12: L11 v = a, unit diagonal
     for (int kk = 0; kk < NB; kk++) {
-        const T lmk = lane > kk ? blk[kk][lane] : T(0);   // L(lane, kk)
+        const T lmk_ = blk[kk][lane];                     // L(lane, kk)
+        const T lmk = lane > kk ? lmk_ : T(0);
 #pragma unroll
-        for (int q = 0; q < 4; q++) v[q] -= lmk * readlane(v[q], kk);
+        for (int q = 0; q < RW; q++) x[q] = fma(-lmk, readlane(x[q], kk), x[q]);
     }
 #pragma unroll
-    for (int q = 0; q < 4; q++)
-        if (j0 + q < D) S[(size_t)(j0 + q) * D + p + lane] = v[q];
+    for (int q = 0; q < RW; q++)
+        if (first + q < D) S[(size_t)(first + q) * D + p + lane] = x[q];
 }
 
 // A22 -= L21 U12 over the trailing block [p+NB, D)^2: a 128 x 128 output tile
@@ -241,26 +244,35 @@ __global__ __launch_bounds__(256) void dlu_gemm_kernel(DenseArgs a, int p) {
             rb[u] = c0 + cc < D ? S[(size_t)(c0 + cc) * D + p + kc + kb] : T(0);
         }
     };
-    auto stash = [&](int buf) {
+    auto stash = [&](int buf) {                      // A is stored negated: acc = C + (-A) B
 #pragma unroll
         for (int u = 0; u < 8; u++) {
             const int e = tid + 256 * u;
-            As[buf][e / TM][e % TM] = ra[u];
+            As[buf][e / TM][e % TM] = -ra[u];
             Bs[buf][e % KC][e / KC] = rb[u];
         }
     };
-    fetch(0);
-    stash(0);
-    __syncthreads();
     const int lane = tid & (WAVE - 1), wv = tid / WAVE;
     const int qr = wv >> 1, qc = wv & 1;
     const int li = lane & 15, lk = lane >> 4;
+    // C(row, col) of accumulator element q (transposed tile, see the epilogue)
+    auto crow = [&](int ti) { return r0 + 64 * qr + 16 * ti + li; };
+    auto ccol = [&](int tj, int q) { return c0 + 64 * qc + 16 * tj + (sizeof(T) == 8 ? 4 * q + lk : 4 * lk + q); };
     typedef typename std::conditional<sizeof(T) == 8, d4, f4>::type acc_t;
     acc_t acc[4][4];
+    // the accumulators start from C, loaded before any store of this workgroup
 #pragma unroll
     for (int ti = 0; ti < 4; ti++)
 #pragma unroll
-        for (int tj = 0; tj < 4; tj++) acc[ti][tj] = acc_t{0, 0, 0, 0};
+        for (int tj = 0; tj < 4; tj++)
+#pragma unroll
+            for (int q = 0; q < 4; q++) {
+                const int row = crow(ti), col = ccol(tj, q);
+                acc[ti][tj][q] = (row < D && col < D) ? S[(size_t)col * D + row] : T(0);
+            }
+    fetch(0);
+    stash(0);
+    __syncthreads();
 #pragma unroll 1
     for (int ch = 0; ch < NB / KC; ch++) {
         const int buf = ch & 1;
@@ -294,9 +306,8 @@ __global__ __launch_bounds__(256) void dlu_gemm_kernel(DenseArgs a, int p) {
         for (int tj = 0; tj < 4; tj++)
 #pragma unroll
             for (int q = 0; q < 4; q++) {
-                const int row = r0 + 64 * qr + 16 * ti + li;
-                const int col = c0 + 64 * qc + 16 * tj + (sizeof(T) == 8 ? 4 * q + lk : 4 * lk + q);
-                if (row < D && col < D) S[(size_t)col * D + row] -= acc[ti][tj][q];
+                const int row = crow(ti), col = ccol(tj, q);
+                if (row < D && col < D) S[(size_t)col * D + row] = acc[ti][tj][q];
             }
 }
 
@@ -310,7 +321,13 @@ __global__ __launch_bounds__(256) void dlu_check_kernel(DenseArgs a) {
     if (sweep_failed(a, inst)) return;
     const T *col = inst_S<T>(a, inst) + (size_t)c * a.D;
     double m = 0.0;
-    for (int i = c + 1 + lane; i < a.D; i += WAVE) m = nanmax(m, fabs((double)col[i]));
+    for (int i0 = c + 1; i0 < a.D; i0 += 4 * WAVE) {
+        T x[4];
+#pragma unroll
+        for (int u = 0; u < 4; u++) x[u] = i0 + u * WAVE + lane < a.D ? col[i0 + u * WAVE + lane] : T(0);
+#pragma unroll
+        for (int u = 0; u < 4; u++) m = nanmax(m, fabs((double)x[u]));
+    }
 #pragma unroll
     for (int off = 32; off > 0; off >>= 1) m = nanmax(m, __shfl_xor(m, off));
     if (lane != 0) return;
@@ -339,7 +356,13 @@ __global__ __launch_bounds__(256) void dtrsv_lower_kernel(DenseArgs a, double *y
     const int D = a.D, tid = threadIdx.x;
     if (b > 0) {
         const int pb = (b - 1) * NB;
-        for (int e = tid; e < NB * NR; e += 256) yb[e / NR][e % NR] = yt[(size_t)(pb + e / NR) * YS + e % NR];
+        if (tid < NB * NR / 2) {                      // NB * NR <= 512: two loads per thread
+            const double y0 = yt[(size_t)(pb + tid / NR) * YS + tid % NR];
+            const int e1 = tid + NB * NR / 2;
+            const double y1 = yt[(size_t)(pb + e1 / NR) * YS + e1 % NR];
+            yb[tid / NR][tid % NR] = y0;
+            yb[e1 / NR][e1 % NR] = y1;
+        }
         __syncthreads();
         const int i = b * NB + blockIdx.x * 256 + tid;
         if (i < D) {
@@ -359,14 +382,24 @@ __global__ __launch_bounds__(256) void dtrsv_lower_kernel(DenseArgs a, double *y
     if (blockIdx.x != 0) return;
     // block b: stage L(p.., p..) in LDS, then one wavefront substitutes (lane i = row p + i)
     const int p = b * NB, nb = min(NB, D - p);
-    for (int e = tid; e < nb * nb; e += 256) tri[e / nb][e % nb] = (double)S[(size_t)(p + e / nb) * D + p + e % nb];
+    {
+        double t[16];                                 // column e/64, row e%64 of the block
+#pragma unroll
+        for (int u = 0; u < 16; u++) {
+            const int e = tid + 256 * u, cc = e / NB, rr = e % NB;
+            t[u] = (cc < nb && rr < nb) ? (double)S[(size_t)(p + cc) * D + p + rr] : 0.0;
+        }
+#pragma unroll
+        for (int u = 0; u < 16; u++) tri[(tid + 256 * u) / NB][(tid + 256 * u) % NB] = t[u];
+    }
     __syncthreads();
     if (tid >= WAVE) return;
     double yv[NR];
 #pragma unroll
     for (int r = 0; r < NR; r++) yv[r] = tid < nb ? yt[(size_t)(p + tid) * YS + r] : 0.0;
     for (int kk = 0; kk < nb; kk++) {
-        const double lik = tid > kk && tid < nb ? tri[kk][tid] : 0.0;
+        const double lik_ = tri[kk][tid];
+        const double lik = tid > kk ? lik_ : 0.0;
 #pragma unroll
         for (int r = 0; r < NR; r++) yv[r] -= lik * readlane(yv[r], kk);
     }
@@ -392,7 +425,13 @@ __global__ __launch_bounds__(256) void dtrsv_upper_kernel(DenseArgs a, double *y
     const int p = blk * NB, nb = min(NB, D - p);
     if (b > 0) {
         const int pb = (blk + 1) * NB, nbb = min(NB, D - pb);
-        for (int e = tid; e < nbb * NR; e += 256) yb[e / NR][e % NR] = yt[(size_t)(pb + e / NR) * YS + e % NR];
+        if (tid < NB * NR / 2) {                      // NB * NR <= 512: two loads per thread
+            const int e1 = tid + NB * NR / 2;
+            const double y0 = tid / NR < nbb ? yt[(size_t)(pb + tid / NR) * YS + tid % NR] : 0.0;
+            const double y1 = e1 / NR < nbb ? yt[(size_t)(pb + e1 / NR) * YS + e1 % NR] : 0.0;
+            yb[tid / NR][tid % NR] = y0;
+            yb[e1 / NR][e1 % NR] = y1;
+        }
         __syncthreads();
         const int i = pb - 1 - (int)(blockIdx.x * 256 + tid);   // rows above block blk+1, bottom up
         if (i >= 0) {
@@ -410,7 +449,16 @@ __global__ __launch_bounds__(256) void dtrsv_upper_kernel(DenseArgs a, double *y
         __syncthreads();
     }
     if (blockIdx.x != 0) return;
-    for (int e = tid; e < nb * nb; e += 256) tri[e / nb][e % nb] = (double)S[(size_t)(p + e / nb) * D + p + e % nb];
+    {
+        double t[16];                                 // column e/64, row e%64 of the block
+#pragma unroll
+        for (int u = 0; u < 16; u++) {
+            const int e = tid + 256 * u, cc = e / NB, rr = e % NB;
+            t[u] = (cc < nb && rr < nb) ? (double)S[(size_t)(p + cc) * D + p + rr] : 0.0;
+        }
+#pragma unroll
+        for (int u = 0; u < 16; u++) tri[(tid + 256 * u) / NB][(tid + 256 * u) % NB] = t[u];
+    }
     __syncthreads();
     if (tid >= WAVE) return;
     double yv[NR];
@@ -421,7 +469,8 @@ __global__ __launch_bounds__(256) void dtrsv_upper_kernel(DenseArgs a, double *y
 #pragma unroll
             for (int r = 0; r < NR; r++) yv[r] = yv[r] / tri[kk][kk];
         }
-        const double uik = tid < kk ? tri[kk][tid] : 0.0;
+        const double uik_ = tri[kk][tid];
+        const double uik = tid < kk ? uik_ : 0.0;
 #pragma unroll
         for (int r = 0; r < NR; r++) yv[r] -= uik * readlane(yv[r], kk);
     }
@@ -468,7 +517,7 @@ int launch_dense_refactor(const DenseArgs &a, bool gather, void *stream) {
     for (int p = 0; p < D; p += NB) {
         const int nb = D - p < NB ? D - p : NB;
         const int rest = D - p - nb;   // > 0 only for full panels
-        const int nrb = (rest + 63) / 64, ncb = (rest + 15) / 16;
+        const int nrb = (rest + 63) / 64, ncb = (rest + 63) / 64;
         const dim3 gp((unsigned)(1 + nrb + ncb), (unsigned)a.batch);
         if (a.fp32) hipLaunchKernelGGL((dlu_panel_kernel<float>), gp, dim3(256), 0, st, a, p, nrb);
         else hipLaunchKernelGGL((dlu_panel_kernel<double>), gp, dim3(256), 0, st, a, p, nrb);

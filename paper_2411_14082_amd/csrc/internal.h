@@ -72,7 +72,7 @@ struct Schedule {
     // (columns of level l, ascending); src_slot is the offset of the source's row in the
     // target column (where the multiplier U(j,k) lives)
     std::vector<int> task_ptr, task_tgt, src_ptr, src_col, src_slot;
-    std::vector<int> task4, item4;            // the same tasks packed for the device (4 ints each)
+    std::vector<int> colrec, task8, item4;    // the same schedule packed for the device
     std::vector<int> amap;                    // user nonzero -> slot offset inside its column
     // device layout of the factor storage: column k occupies [Dp[k], Dp[k] + Dlen[k]);
     // every column starts on a kColAlign-entry boundary
@@ -89,6 +89,7 @@ struct Schedule {
     double macs = 0, flops = 0;
     int tail0 = 0;                            // first column of the densely factored tail (n = none)
     std::vector<int> tail_rend;               // rows i >= tail0: L entries of columns < tail0 end here
+    std::vector<int> lrec, urec, Lrjs, Urjs;  // the solve levels packed for the device
 };
 
 void build_schedule(const Analysis &an, const Factor &f, const cktlu_options &opt, Schedule &s);
@@ -104,8 +105,8 @@ struct Device {
     int batch_cap = 0;                 // instances the value buffers hold
     // pattern / schedule
     DevBuf seq, Dp, Dlen, Fi, nU, Ap, colperm, amap;
-    DevBuf task4, item4;
-    DevBuf Lrp, Lrj, Lrsrc, Urp, Urj, Ursrc, udiag, lseq, useq, rowperm, colperm_sol;
+    DevBuf colrec, task8, item4;
+    DevBuf lrec, urec, Lrjs, Urjs, rowperm, colperm_sol;
     DevBuf Acp, Acj, Acsrc;
     // values and status words
     DevBuf Fx64, Fx32;                 // factor values (FP64 always; FP32 in FP32_IR mode)
@@ -113,7 +114,6 @@ struct Device {
     DevBuf done, ctrl;                 // per-column completion epochs, status words
     DevBuf vec;                        // solve work vectors
     DevBuf S;                          // dense trailing block, batch x D x D (8-byte slots)
-    DevBuf tail_rend;                  // per tail row: end of its L entries in front columns
     size_t vec_cap = 0;
     unsigned epoch = 0;
     int S_prec = -1;                   // what S holds: -1 stale, 0 FP64 factors, 1 FP32 factors
@@ -131,7 +131,8 @@ constexpr int YS = 16;          // doubles per solve-vector row (one 128-byte li
 struct RefactorArgs {
     int n, batch;
     const int *seq, *Dp, *Dlen, *Fi, *nU, *Ap, *colperm, *amap;
-    const int *task4, *item4;  // right-looking update tasks and their items (int4 records)
+    const int *colrec;         // {Dp, nU, Dlen, column} per position of seq
+    const int *task8, *item4;  // right-looking update tasks (two int4s each) and their extra items
     const double *Aval;        // batch x nnzA
     int64_t nnzA, nnzF;
     void *Fx;                  // batch x nnzF (double or float)
@@ -157,17 +158,16 @@ int launch_status_out(const int *firstfail, int *status, int batch, void *stream
 
 struct SolveArgs {
     int n, nrhs, batch;
-    const int *Lrp, *Lrj, *Lrsrc, *Urp, *Urj, *Ursrc, *udiag, *lseq, *useq;
+    const int *lrec, *urec;    // per solve position: {row, first entry, end, position of U(i,i)}
+    const int *Lrjs, *Urjs;    // per entry: {column, position of the value}
     const void *Fx;            // factor values (double or float), batch x nnzF
     int64_t nnzF;
     int fp32;
     double *y;                 // batch x n rows of YS doubles, rhs r in slot r
     const int *skip;           // per-instance status (-1 = solve), may be null
-    int tail0;                 // rows >= tail0 of the L solve take only entries [Lrp[i], tail_rend[i - tail0])
-    const int *tail_rend;
 };
 
-// Rows lseq[lbeg, lend) / useq[lbeg, lend) (one level of the solve graph).
+// Solve positions [lbeg, lend) of lrec / urec (one level of the solve graph).
 int launch_lsolve_level(const SolveArgs &a, int lbeg, int lend, void *stream);
 int launch_usolve_level(const SolveArgs &a, int lbeg, int lend, void *stream);
 // y[((i*n + k)*YS + r] = b[(i*nrhs + r)*ldb + perm[k]]

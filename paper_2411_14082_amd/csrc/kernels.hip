@@ -89,6 +89,94 @@ __global__ __launch_bounds__(WG) void refactor_init_kernel(RefactorArgs a) {
     }
 }
 
+constexpr int kItemChunk = 4;      // entries of a source column per lane per pass (longer sources)
+
+// x_k -= L(:,j) U(j,k) for one source j (item {pivot position, L begin, L end,
+// slot of row j}) of an update task, kItemChunk entries per lane per pass.  A pass
+// loads its entries, locates their rows in the target (rows >= T of a dense-block
+// target directly in Sk; others by a branch-free binary search over the searched
+// part of column k, the same range for every entry, run in lockstep, in LDS when
+// staged), loads every target value and only then stores: the rows of one source
+// are distinct, so no store of a pass can feed a load of the same pass.
+template <typename T, int U>
+__device__ __forceinline__ void apply_item_u(const RefactorArgs &a, const T *Fx, T *xk, T *Sk, const int *rowsk,
+                                             const int *lrows, bool staged, int slen, int lb, int le, int lo0,
+                                             T iv, T m, int lane, const int (&r0)[kItemChunk],
+                                             const T (&l0)[kItemChunk]) {
+    for (int q0 = lb; q0 < le; q0 += U * WAVE) {
+        int r[U];
+        T l[U];
+        if (q0 == lb) {                                   // the first pass was loaded by the caller
+#pragma unroll
+            for (int u = 0; u < U; u++) { r[u] = r0[u]; l[u] = l0[u]; }
+        } else {
+#pragma unroll
+            for (int u = 0; u < U; u++) {
+                const int q = q0 + u * WAVE + lane;
+                r[u] = q < le ? a.Fi[q] : -1;
+                l[u] = q < le ? Fx[q] : T(0);
+            }
+        }
+        // target slot of each entry: >= 0 in xk, < -1 as -(2 + offset) in Sk, -1 none
+        int pos[U];
+        int base[U];
+#pragma unroll
+        for (int u = 0; u < U; u++) base[u] = lo0;
+        int cnt = slen - lo0;                              // lower bound of r in rows [lo0, slen)
+        if (staged) {
+            while (cnt > 1) {
+                const int half = cnt >> 1;
+#pragma unroll
+                for (int u = 0; u < U; u++) base[u] = lrows[base[u] + half - 1] < r[u] ? base[u] + half : base[u];
+                cnt -= half;
+            }
+            if (cnt == 1) {
+#pragma unroll
+                for (int u = 0; u < U; u++) base[u] += lrows[base[u]] < r[u] ? 1 : 0;
+            }
+        } else {
+            while (cnt > 1) {
+                const int half = cnt >> 1;
+#pragma unroll
+                for (int u = 0; u < U; u++) base[u] = rowsk[base[u] + half - 1] < r[u] ? base[u] + half : base[u];
+                cnt -= half;
+            }
+            if (cnt == 1) {
+#pragma unroll
+                for (int u = 0; u < U; u++) base[u] += rowsk[base[u]] < r[u] ? 1 : 0;
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < U; u++) {
+            if (r[u] < 0) pos[u] = -1;
+            else if (Sk && r[u] >= a.T) pos[u] = -(2 + (r[u] - a.T));
+            else pos[u] = base[u] < slen ? base[u] : -1;  // always found: struct(L(:,j)) is inside struct(col k)
+        }
+        T tv[U];
+#pragma unroll
+        for (int u = 0; u < U; u++) tv[u] = pos[u] >= 0 ? xk[pos[u]] : (pos[u] < -1 ? Sk[-(pos[u] + 2)] : T(0));
+#pragma unroll
+        for (int u = 0; u < U; u++) {
+            const T v = tv[u] - l[u] * iv * m;
+            if (pos[u] >= 0) xk[pos[u]] = v;
+            else if (pos[u] < -1) Sk[-(pos[u] + 2)] = v;
+        }
+    }
+}
+
+// Sources of at most one entry per lane take the single-entry path (one search
+// per lane); longer ones kItemChunk entries per lane per pass.
+template <typename T>
+__device__ __forceinline__ void apply_item(const RefactorArgs &a, const T *Fx, T *xk, T *Sk, const int *rowsk,
+                                           const int *lrows, bool staged, int slen, int lb, int le, int lo0,
+                                           T iv, T m, int lane, const int (&r0)[kItemChunk],
+                                           const T (&l0)[kItemChunk]) {
+    if (le - lb <= WAVE)
+        apply_item_u<T, 1>(a, Fx, xk, Sk, rowsk, lrows, staged, slen, lb, le, lo0, iv, m, lane, r0, l0);
+    else
+        apply_item_u<T, kItemChunk>(a, Fx, xk, Sk, rowsk, lrows, staged, slen, lb, le, lo0, iv, m, lane, r0, l0);
+}
+
 // one wavefront per (task, instance); tasks: [checks | normalisations | updates]
 template <typename T, bool CHECK>
 __global__ __launch_bounds__(WG) void refactor_level_kernel(RefactorArgs a, int cbeg, int cend, int pbeg,
@@ -101,24 +189,31 @@ __global__ __launch_bounds__(WG) void refactor_level_kernel(RefactorArgs a, int 
     const int idx = (int)(w / a.batch);
     int *interrupted = a.ctrl + 1;
     int *firstfail = a.ctrl + 1 + a.batch;
-    if (CHECK && interrupted[inst]) return;          // an earlier level failed its check
     T *Fx = reinterpret_cast<T *>(a.Fx) + (size_t)inst * a.nnzF;
+    const int4 *colrec = reinterpret_cast<const int4 *>(a.colrec);
     if (idx < nchk) {
         // (a) pivot check of a column of this level
         if (!CHECK) return;
-        const int j = a.seq[cbeg + idx];
-        const T *x = Fx + a.Dp[j];
-        const int nu = a.nU[j], len = a.Dlen[j];
+        const int4 cr = colrec[cbeg + idx];
+        const int stop = interrupted[inst];
+        const int j = cr.w, nu = cr.y, len = cr.z;
+        const T *x = Fx + cr.x;
         double m = 0.0;
         int bad = 0;
-        for (int i = nu + lane; i < len; i += WAVE) {
-            const double v = (double)x[i];
-            if (!isfinite(v)) bad = 1;
-            m = fmax(m, fabs(v));
+        for (int i0 = nu; i0 < len; i0 += 4 * WAVE) {   // four loads in flight per lane
+            double v[4];
+#pragma unroll
+            for (int u = 0; u < 4; u++) v[u] = i0 + u * WAVE + lane < len ? (double)x[i0 + u * WAVE + lane] : 0.0;
+#pragma unroll
+            for (int u = 0; u < 4; u++) {
+                if (!isfinite(v[u])) bad = 1;
+                m = fmax(m, fabs(v[u]));
+            }
         }
+        const double d = (double)x[nu - 1];
+        if (stop) return;                                 // an earlier level failed its check
         m = wave_max(m);
         bad = __any(bad);
-        const double d = (double)x[nu - 1];
         if (bad || !isfinite(d) || d == 0.0 || fabs(d) < a.eps * m || j == a.force_fail_col) {
             if (lane == 0) {
                 atomicMin(&firstfail[inst], j);
@@ -129,67 +224,102 @@ __global__ __launch_bounds__(WG) void refactor_level_kernel(RefactorArgs a, int 
     }
     if (idx < nchk + nnorm) {
         // (b) L(:,j) = x / pivot for a column of the previous level
-        const int j = a.seq[pbeg + idx - nchk];
-        T *x = Fx + a.Dp[j];
-        const int nu = a.nU[j], len = a.Dlen[j];
+        const int4 cr = colrec[pbeg + idx - nchk];
+        const int stop = CHECK ? interrupted[inst] : 0;
+        const int j = cr.w, nu = cr.y, len = cr.z;
+        T *x = Fx + cr.x;
         const T d = x[nu - 1];
-        for (int i = nu + lane; i < len; i += WAVE) x[i] = x[i] / d;
+        T v[4];
+#pragma unroll
+        for (int u = 0; u < 4; u++) v[u] = nu + u * WAVE + lane < len ? x[nu + u * WAVE + lane] : T(0);
+        if (stop) return;
+        for (int i0 = nu; i0 < len; i0 += 4 * WAVE) {
+            if (i0 != nu) {
+#pragma unroll
+                for (int u = 0; u < 4; u++) v[u] = i0 + u * WAVE + lane < len ? x[i0 + u * WAVE + lane] : T(0);
+            }
+#pragma unroll
+            for (int u = 0; u < 4; u++)
+                if (i0 + u * WAVE + lane < len) x[i0 + u * WAVE + lane] = v[u] / d;
+        }
         if (lane == 0) a.done[(size_t)inst * a.n + j] = (int)a.epoch;
         return;
     }
     // (c) update task: target column k, sources j of this level in ascending order.
-    // Rows of the target are located by binary search in the searched part of column k,
-    // staged in LDS when it fits; rows >= T of a dense-block target are addressed in S.
-    const int4 tr = reinterpret_cast<const int4 *>(a.task4)[tbeg + idx - nchk - nnorm];
-    const int iend = reinterpret_cast<const int4 *>(a.task4)[tbeg + idx - nchk - nnorm + 1].w;
-    const int k = tr.x, bk = tr.y, slen = tr.z;
+    // Every load that does not depend on another is issued before the first wait:
+    // the task record, then the first item's pivot, multiplier and first entries,
+    // the extra items and the target rows to stage in LDS.
+    const int t = tbeg + idx - nchk - nnorm;
+    const int4 *task8 = reinterpret_cast<const int4 *>(a.task8);
+    const int4 h = task8[2 * t], it0 = task8[2 * t + 1];
+    const int xend = task8[2 * t + 2].w;
+    const int stop = CHECK ? interrupted[inst] : 0;
+    const int k = h.x, bk = h.y, slen = h.z, xbeg = h.w;
     T *xk = Fx + bk;
     const int *rowsk = a.Fi + bk;
     T *Sk = k >= a.T ? reinterpret_cast<T *>(a.S) + (size_t)inst * a.D * a.D + (size_t)(k - a.T) * a.D : nullptr;
+    const T piv0 = Fx[it0.x];                             // the pivot of j (not yet divided into L(:,j))
+    const T mult0 = xk[it0.w];                            // U(j,k): final, no source of this level updates it
+    int r0[kItemChunk];
+    T l0[kItemChunk];
+#pragma unroll
+    for (int u = 0; u < kItemChunk; u++) {
+        const int q = it0.y + u * WAVE + lane;
+        r0[u] = q < it0.z ? a.Fi[q] : -1;
+        l0[u] = q < it0.z ? Fx[q] : T(0);
+    }
+    int4 itx = make_int4(0, 0, 0, 0);
+    if (xbeg + lane < xend) itx = reinterpret_cast<const int4 *>(a.item4)[xbeg + lane];
     __shared__ int srows[WAVES][kStageRows];
     int *lrows = srows[wv];
     const bool staged = slen <= kStageRows;
     if (staged) {
-        for (int i = lane; i < slen; i += WAVE) lrows[i] = rowsk[i];
+        for (int i0 = 0; i0 < slen; i0 += 4 * WAVE) {
+            int rr[4];
+#pragma unroll
+            for (int u = 0; u < 4; u++) rr[u] = i0 + u * WAVE + lane < slen ? rowsk[i0 + u * WAVE + lane] : 0;
+#pragma unroll
+            for (int u = 0; u < 4; u++)
+                if (i0 + u * WAVE + lane < slen) lrows[i0 + u * WAVE + lane] = rr[u];
+        }
     }
-    const int4 *items = reinterpret_cast<const int4 *>(a.item4);
-    for (int s0 = tr.w; s0 < iend; s0 += WAVE) {
-        // lane u holds item s0 + u: its record, the pivot of its source and its multiplier
-        int4 it = make_int4(0, 0, 0, 0);
-        T inv = T(0), mult = T(0);
-        if (s0 + lane < iend) {
-            it = items[s0 + lane];
-            inv = T(1) / Fx[it.x];                  // the pivot of j (not yet divided into L(:,j))
-            mult = xk[it.w];                        // U(j,k): final, no source of this level updates it
+    if (stop) return;                                     // an earlier level failed its check
+    wave_sync();                                          // staged rows visible to the whole wavefront
+    apply_item<T>(a, Fx, xk, Sk, rowsk, lrows, staged, slen, it0.y, it0.z, it0.w + 1, T(1) / piv0, mult0, lane,
+                  r0, l0);
+    if (xend == xbeg) return;
+    // further sources of this task (lane u holds the record of the u-th)
+    T invx = T(0), multx = T(0);
+    const int nx = min(WAVE, xend - xbeg);
+    wave_sync();                                          // this item's updates visible before the next reads
+    if (lane < nx) {
+        invx = T(1) / Fx[itx.x];
+        multx = xk[itx.w];
+    }
+    for (int u = 0; u < nx; ++u) {
+        const int lb = __shfl(itx.y, u), le = __shfl(itx.z, u), lo0 = __shfl(itx.w, u) + 1;
+        const T iv = __shfl(invx, u), m = __shfl(multx, u);
+#pragma unroll
+        for (int v = 0; v < kItemChunk; v++) {
+            const int q = lb + v * WAVE + lane;
+            r0[v] = q < le ? a.Fi[q] : -1;
+            l0[v] = q < le ? Fx[q] : T(0);
         }
-        wave_sync();                                // staged rows and earlier updates visible
-        const int ns = min(WAVE, iend - s0);
-        for (int u = 0; u < ns; ++u) {
-            const int lb = __shfl(it.y, u), le = __shfl(it.z, u), lo0 = __shfl(it.w, u) + 1;
-            const T iv = __shfl(inv, u), m = __shfl(mult, u);
-            for (int q = lb + lane; q < le; q += WAVE) {
-                const int r = a.Fi[q];
-                const T l = Fx[q] * iv;
-                if (Sk && r >= a.T) {
-                    Sk[r - a.T] -= l * m;
-                    continue;
-                }
-                int lo = lo0, hi = slen;            // rows of L(:,j) lie below row j in column k
-                if (staged) {
-                    while (lo < hi) {
-                        const int mid = (lo + hi) >> 1;
-                        if (lrows[mid] < r) lo = mid + 1; else hi = mid;
-                    }
-                } else {
-                    while (lo < hi) {
-                        const int mid = (lo + hi) >> 1;
-                        if (rowsk[mid] < r) lo = mid + 1; else hi = mid;
-                    }
-                }
-                if (lo < slen) xk[lo] -= l * m;     // always found: struct(L(:,j)) is inside struct(col k)
-            }
-            wave_sync();
+        apply_item<T>(a, Fx, xk, Sk, rowsk, lrows, staged, slen, lb, le, lo0, iv, m, lane, r0, l0);
+        wave_sync();
+    }
+    // more than WAVE sources in one task: the rest one at a time
+    for (int i = xbeg + WAVE; i < xend; ++i) {
+        const int4 it = reinterpret_cast<const int4 *>(a.item4)[i];
+        const T iv = T(1) / Fx[it.x], m = xk[it.w];
+#pragma unroll
+        for (int v = 0; v < kItemChunk; v++) {
+            const int q = it.y + v * WAVE + lane;
+            r0[v] = q < it.z ? a.Fi[q] : -1;
+            l0[v] = q < it.z ? Fx[q] : T(0);
         }
+        apply_item<T>(a, Fx, xk, Sk, rowsk, lrows, staged, slen, it.y, it.z, it.w + 1, iv, m, lane, r0, l0);
+        wave_sync();
     }
 }
 
@@ -246,30 +376,40 @@ int launch_refactor_level(const RefactorArgs &a, int cbeg, int cend, int pbeg, i
 
 // ----------------------------------------------------------------- solves
 // y holds one cache line (YS doubles) per row and instance: y[(inst*n + i)*YS + r].
+// One wavefront per row: its record, then its entries {column, value position},
+// then the values and the y rows they multiply.
 template <typename T, int NR, bool UPPER>
 __global__ __launch_bounds__(WG) void trisolve_level_kernel(SolveArgs a, int lbeg, int lend) {
     const int lane = threadIdx.x & (WAVE - 1), wv = threadIdx.x / WAVE;
     const int64_t t = (int64_t)lbeg * a.batch + (int64_t)blockIdx.x * WAVES + wv;
     if (t >= (int64_t)lend * a.batch) return;
     const int inst = (int)(t % a.batch);
-    if (a.skip && a.skip[inst] != -1) return;
-    const int i = (UPPER ? a.useq : a.lseq)[t / a.batch];
-    const int *rp = UPPER ? a.Urp : a.Lrp;
-    const int *rj = UPPER ? a.Urj : a.Lrj;
-    const int *rs = UPPER ? a.Ursrc : a.Lrsrc;
+    const int4 rec = reinterpret_cast<const int4 *>(UPPER ? a.urec : a.lrec)[t / a.batch];
+    const int skipped = a.skip ? a.skip[inst] != -1 : 0;
+    const int2 *rjs = reinterpret_cast<const int2 *>(UPPER ? a.Urjs : a.Lrjs);
     const T *Fx = reinterpret_cast<const T *>(a.Fx) + (size_t)inst * a.nnzF;
     double *y = a.y + (size_t)inst * a.n * YS;
+    const int i = rec.x;
+    const double diag = UPPER ? (double)Fx[rec.w] : 1.0;
+    const double yi = lane < NR ? y[(size_t)i * YS + lane] : 0.0;
     double acc[NR];
 #pragma unroll
     for (int r = 0; r < NR; r++) acc[r] = 0.0;
-    // rows of the dense block take only their L entries in sparse columns here
-    const int qend = (!UPPER && i >= a.tail0) ? a.tail_rend[i - a.tail0] : rp[i + 1];
-    for (int q = rp[i] + lane; q < qend; q += WAVE) {
-        const int j = rj[q];
-        const double l = (double)Fx[rs[q]];
+    for (int q0 = rec.y; q0 < rec.z; q0 += 2 * WAVE) {   // two entries in flight per lane
+        int2 e[2];
 #pragma unroll
-        for (int r = 0; r < NR; r++) acc[r] += l * y[(size_t)j * YS + r];
+        for (int u = 0; u < 2; u++) e[u] = q0 + u * WAVE + lane < rec.z ? rjs[q0 + u * WAVE + lane] : make_int2(-1, 0);
+        double l[2];
+#pragma unroll
+        for (int u = 0; u < 2; u++) l[u] = e[u].x >= 0 ? (double)Fx[e[u].y] : 0.0;
+#pragma unroll
+        for (int u = 0; u < 2; u++)
+            if (e[u].x >= 0) {
+#pragma unroll
+                for (int r = 0; r < NR; r++) acc[r] += l[u] * y[(size_t)e[u].x * YS + r];
+            }
     }
+    if (skipped) return;
 #pragma unroll
     for (int r = 0; r < NR; r++) acc[r] = wave_sum(acc[r]);
     double mine = acc[0];
@@ -277,8 +417,8 @@ __global__ __launch_bounds__(WG) void trisolve_level_kernel(SolveArgs a, int lbe
     for (int r = 1; r < NR; r++)
         if (lane == r) mine = acc[r];
     if (lane < NR) {
-        double v = y[(size_t)i * YS + lane] - mine;
-        if (UPPER) v = v / (double)Fx[a.udiag[i]];
+        double v = yi - mine;
+        if (UPPER) v = v / diag;
         y[(size_t)i * YS + lane] = v;
     }
 }

@@ -167,13 +167,31 @@ void build_schedule(const Analysis &an, const Factor &f, const cktlu_options &op
         }
         if (nitems > 0) s.src_ptr.push_back((int)nitems);
         for (int q = 0; q < nl; q++) s.task_ptr[q + 1] += s.task_ptr[q];
-        // packed device records.  Task t: {target k, Dp[k], length of the part of column k
-        // that is searched for rows (all of it for k < T, its rows < T otherwise), first
-        // item}; one more record after the last task holds the item count.  Item i:
-        // {position of the pivot of its source j, begin and end of L(:,j), offset of row j
-        // in the target column (where the multiplier U(j,k) lives)}.
+        // packed device records.  colrec[i] = {Dp, nU, Dlen, column} of column seq[i].  Task t
+        // is two int4s: {target k, Dp[k], length of the part of column k that is searched for
+        // rows (all of it for k < T, its rows < T otherwise), first extra item} and its first
+        // item; a sentinel task after the last one holds the end of the extra items.  An item
+        // is {position of the pivot of its source j, begin and end of L(:,j), offset of row j
+        // in the target column (where the multiplier U(j,k) lives)}; a task's items after the
+        // first are item4[first extra item .. next task's first extra item).
+        s.colrec.resize(4 * (size_t)T);
+        for (int i = 0; i < T; i++) {
+            const int j = s.seq[i];
+            s.colrec[4 * (size_t)i + 0] = s.Dp[j];
+            s.colrec[4 * (size_t)i + 1] = f.nU[j];
+            s.colrec[4 * (size_t)i + 2] = s.Dlen[j];
+            s.colrec[4 * (size_t)i + 3] = j;
+        }
+        auto item_of = [&](int64_t i, int *dst) {
+            const int j = s.src_col[i];
+            dst[0] = s.Dp[j] + f.nU[j] - 1;
+            dst[1] = s.Dp[j] + f.nU[j];
+            dst[2] = s.Dp[j] + s.Dlen[j];
+            dst[3] = s.src_slot[i];
+        };
         const int ntasks = (int)s.task_tgt.size();
-        s.task4.assign(4 * (size_t)(ntasks + 1), 0);
+        s.task8.assign(8 * (size_t)(ntasks + 1), 0);
+        s.item4.clear();
         for (int t = 0; t < ntasks; t++) {
             const int k = s.task_tgt[t];
             int slen = s.Dlen[k];
@@ -181,20 +199,19 @@ void build_schedule(const Analysis &an, const Factor &f, const cktlu_options &op
                 const int *b = f.Fi.data() + f.Fp[k], *e = f.Fi.data() + f.Fp[k + 1];
                 slen = (int)(std::lower_bound(b, e, T) - b);
             }
-            s.task4[4 * (size_t)t + 0] = k;
-            s.task4[4 * (size_t)t + 1] = s.Dp[k];
-            s.task4[4 * (size_t)t + 2] = slen;
-            s.task4[4 * (size_t)t + 3] = s.src_ptr[t];
+            int *rec = s.task8.data() + 8 * (size_t)t;
+            rec[0] = k;
+            rec[1] = s.Dp[k];
+            rec[2] = slen;
+            rec[3] = (int)(s.item4.size() / 4);
+            item_of(s.src_ptr[t], rec + 4);
+            for (int i = s.src_ptr[t] + 1; i < s.src_ptr[t + 1]; i++) {
+                int it[4];
+                item_of(i, it);
+                s.item4.insert(s.item4.end(), it, it + 4);
+            }
         }
-        s.task4[4 * (size_t)ntasks + 3] = (int)nitems;
-        s.item4.resize(4 * (size_t)nitems);
-        for (int64_t i = 0; i < nitems; i++) {
-            const int j = s.src_col[i];
-            s.item4[4 * i + 0] = s.Dp[j] + f.nU[j] - 1;
-            s.item4[4 * i + 1] = s.Dp[j] + f.nU[j];
-            s.item4[4 * i + 2] = s.Dp[j] + s.Dlen[j];
-            s.item4[4 * i + 3] = s.src_slot[i];
-        }
+        s.task8[8 * (size_t)ntasks + 3] = (int)(s.item4.size() / 4);
     }
     // ---- solve levels of the sparse rows [0, T): row i of L waits for every j with
     // L(i,j) != 0, row i of U for every j > i with U(i,j) != 0 (rows >= T of U are
@@ -239,6 +256,28 @@ void build_schedule(const Analysis &an, const Factor &f, const cktlu_options &op
             while (q < s.Lrp[i + 1] && s.Lrj[q] < T) q++;
             s.tail_rend[i - T] = q;
         }
+        // packed device records: per solve position {row, first entry, end, position of the
+        // diagonal}; per entry {column, position of the value}
+        s.lrec.resize(4 * s.lseq.size());
+        for (size_t q = 0; q < s.lseq.size(); q++) {
+            const int i = s.lseq[q];
+            s.lrec[4 * q + 0] = i;
+            s.lrec[4 * q + 1] = s.Lrp[i];
+            s.lrec[4 * q + 2] = i >= T ? s.tail_rend[i - T] : s.Lrp[i + 1];
+            s.lrec[4 * q + 3] = s.udiag[i];
+        }
+        s.urec.resize(4 * s.useq.size());
+        for (size_t q = 0; q < s.useq.size(); q++) {
+            const int i = s.useq[q];
+            s.urec[4 * q + 0] = i;
+            s.urec[4 * q + 1] = s.Urp[i];
+            s.urec[4 * q + 2] = s.Urp[i + 1];
+            s.urec[4 * q + 3] = s.udiag[i];
+        }
+        s.Lrjs.resize(2 * s.Lrj.size());
+        for (size_t q = 0; q < s.Lrj.size(); q++) { s.Lrjs[2 * q] = s.Lrj[q]; s.Lrjs[2 * q + 1] = s.Lrsrc[q]; }
+        s.Urjs.resize(2 * s.Urj.size());
+        for (size_t q = 0; q < s.Urj.size(); q++) { s.Urjs[2 * q] = s.Urj[q]; s.Urjs[2 * q + 1] = s.Ursrc[q]; }
     }
     s.rowperm_final.resize(n);
     for (int k = 0; k < n; k++) s.rowperm_final[k] = an.rowperm_pre[f.pivrow[k]];
