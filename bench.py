@@ -11,8 +11,10 @@ FP64 path (the headline value) and the FP32+IR path, the roofline of the
 refactorization phase and the CPU oracle baseline.
 """
 import argparse
+import hashlib
 import json
 import os
+import re
 import sys
 import time
 
@@ -30,6 +32,26 @@ WORKLOADS = {
                          desc="mesh 32x32 + 4 ideal voltage sources"),
 }
 HBM_PEAK_GBS = 8000.0
+FP64_MFMA_PEAK_TFS = 78.6
+FP32_MFMA_PEAK_TFS = 157.3
+# measured HBM traffic of the sweep kernel: written from two rocprofv3 --pmc runs
+# (FETCH_SIZE, WRITE_SIZE) with the sha256 of the kernel source they were taken on
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "refactor_level_kernel_traffic_layered_rc_3x300.txt")
+KERNEL_SRC = os.path.join(ROOT, "paper_2411_14082_amd", "csrc", "kernels.hip")
+
+
+def measured_traffic():
+    """Bytes per sweep launch from the committed counter summary, or None when the
+    kernel source has changed since the counters were taken."""
+    if not os.path.exists(TRAFFIC_FILE):
+        return None
+    txt = open(TRAFFIC_FILE).read()
+    m_sha = re.search(r"kernels_hip_sha256:\s*([0-9a-f]{64})", txt)
+    m_b = re.search(r"hbm_bytes_per_launch:\s*([0-9.eE+]+)", txt)
+    if not m_sha or not m_b:
+        return None
+    cur = hashlib.sha256(open(KERNEL_SRC, "rb").read()).hexdigest()
+    return float(m_b.group(1)) if cur == m_sha.group(1) else None
 
 
 def log(*a):
@@ -37,7 +59,8 @@ def log(*a):
 
 
 def run_leg(ck, torch, c, vals_dev, b_dev, precision, steps, warmup, tail_opts):
-    s = ck.SparseLU(c.n, c.colptr, c.rowind, eps=1e-3, precision=precision, ir_tol=1e-10, **tail_opts)
+    s = ck.SparseLU(c.n, c.colptr, c.rowind, eps=1e-3, precision=precision, ir_tol=1e-10, timing=True,
+                    **tail_opts)
     t0 = time.time()
     s.factorize(vals_dev[0])
     t_setup = time.time() - t0
@@ -48,6 +71,7 @@ def run_leg(ck, torch, c, vals_dev, b_dev, precision, steps, warmup, tail_opts):
         nrep += info.repivoted
         s.solve(b_dev, x)
     torch.cuda.synchronize()
+    s.timing(reset=True)                         # phase times of the timed steps only
     ev = [[torch.cuda.Event(enable_timing=True) for _ in range(3)] for _ in range(steps)]
     infos = []
     torch.cuda.synchronize()
@@ -67,9 +91,10 @@ def run_leg(ck, torch, c, vals_dev, b_dev, precision, steps, warmup, tail_opts):
     ref_ms = np.array([ev[t][0].elapsed_time(ev[t][1]) for t in range(steps)])
     sol_ms = np.array([ev[t][1].elapsed_time(ev[t][2]) for t in range(steps)])
     st = s.stats()
+    tm = s.timing()
     s.close()
     return dict(wall=wall, step_ms=step_ms, ref_ms=ref_ms, sol_ms=sol_ms, stats=st, setup_s=t_setup,
-                repivots=int(nrep), infos=infos, x=x)
+                repivots=int(nrep), infos=infos, x=x, timing=tm)
 
 
 def cpu_baseline(c, vals, b):
@@ -157,13 +182,29 @@ def main():
         log("fp32+ir: %.3f steps/s" % out_fp32["steps_per_s"])
 
     st = res64["stats"]
-    b_ref = st["bytes_refactor"]
-    achieved = b_ref / (res64["ref_ms"].mean() * 1e-3) / 1e9
-    roofline = dict(bound="hbm", kernel="refactor_level_kernel (all level launches of one refactorization)",
-                    achieved=achieved, peak=HBM_PEAK_GBS, unit="GB/s", frac=achieved / HBM_PEAK_GBS,
-                    traffic=None, bytes_per_launch=b_ref / max(1, st["levels"]),
-                    launches_per_refactor=int(st["levels"]),
-                    avg_launch_us=res64["ref_ms"].mean() * 1e3 / max(1, st["levels"]))
+    tm = res64["timing"]
+    # dominant kernel: refactor_level_kernel (the sparse sweep); its launches run back to
+    # back on the library's stream, so the average launch lasts sweep_ms / launches
+    sweep_launch_s = tm["sweep_ms"] * 1e-3 / max(1, tm["sweep_launches"])
+    bytes_per_launch = st["bytes_sweep"] / max(1, st["sweep_launches"])
+    achieved = bytes_per_launch / sweep_launch_s / 1e9
+    traffic = measured_traffic()
+    roofline = dict(bound="hbm", kernel="refactor_level_kernel", achieved=achieved, peak=HBM_PEAK_GBS,
+                    unit="GB/s", frac=achieved / HBM_PEAK_GBS, traffic=traffic,
+                    algorithmic_bytes_per_launch=bytes_per_launch, avg_launch_us=sweep_launch_s * 1e6,
+                    launches_per_refactor=int(st["sweep_launches"]),
+                    bytes_model="28 B per sweep MAC + 24 B per L entry of a sparse column")
+    nref = max(1, tm["refactors"])
+    dense_s = tm["dense_ms"] * 1e-3 / nref
+    roofline_dense = None
+    if st["dense_tail"] > 0 and dense_s > 0:
+        tf = st["flops_dense"] / dense_s / 1e12
+        roofline_dense = dict(bound="mfma", kernel="dense block LU (dlu_panel_kernel + dlu_gemm_kernel)",
+                              achieved=tf, peak=FP64_MFMA_PEAK_TFS, unit="TFLOP/s", frac=tf / FP64_MFMA_PEAK_TFS,
+                              order=int(st["dense_tail"]))
+    npass = max(1, tm["solve_passes"])
+    phases = dict(init=tm["init_ms"] / nref, sweep=tm["sweep_ms"] / nref, dense=tm["dense_ms"] / nref,
+                  solve_sparse=tm["solve_sparse_ms"] / npass, solve_dense=tm["solve_dense_ms"] / npass)
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -172,7 +213,7 @@ def main():
 
     value = args.steps / res64["wall"]
     line = {
-        "metric": "NR refactor+solve steps/sec (FP64 path; FP32+IR alongside), 1 GPU",
+        "metric": "NR refactor+solve steps/sec + p50/p99 step latency, FP32+IR vs FP64, 1 GPU",
         "value": value, "unit": "steps/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
         "ms_per_step": res64["wall"] * 1e3 / args.steps, "higher_is_better": True, "scaling": "weak",
         "vs_baseline": None, "dtype": "f64", "data": "synthetic",
@@ -184,7 +225,9 @@ def main():
         "refactor_ms": float(res64["ref_ms"].mean()), "solve_ms": float(res64["sol_ms"].mean()),
         "backward_err": eta64, "repivots": res64["repivots"],
         "fp32_ir": out_fp32,
+        "phases_ms": phases,
         "roofline": roofline,
+        "roofline_dense": roofline_dense,
         "cpu_baseline": cpu,
     }
     print(json.dumps(line), flush=True)

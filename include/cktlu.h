@@ -69,6 +69,7 @@ typedef struct {
                               0 = automatic (largest multiple of 64 in [256, 8192] whose block of L+U
                               reaches dense_tail_density), -1 = never, > 0 = exactly min(value, n) */
     double dense_tail_density; /* schedule: minimum fill density for the automatic choice; default 0.3 */
+    int timing;            /* 1: record HIP events around each device phase (read by cktlu_get_timing) */
 } cktlu_options;
 
 typedef struct {
@@ -94,7 +95,28 @@ typedef struct {
     int64_t n_factorize, n_refactorize, n_repivot, n_restart_cols;
     int64_t n_fp64_fallback_solves;
     double bytes_refactor, bytes_solve;  /* algorithmic HBM bytes per refactorization / per RHS solve */
+    double macs_sweep;                /* multiply-adds of the sparse sweep's update tasks */
+    double bytes_sweep;               /* its algorithmic bytes: 28 per MAC (L value + row index
+                                         gathered, target read and written) + 24 per L entry of a
+                                         sparse column (pivot test read, division read and write) */
+    double flops_dense;               /* FLOPs of the dense trailing block's LU (2/3 D^3 + lower order) */
+    int64_t sweep_launches;           /* kernel launches of one sparse sweep */
+    int64_t dense_launches;           /* kernel launches of one dense-block factorization */
+    int64_t solve_launches;           /* kernel launches of one triangular solve pass (L and U) */
 } cktlu_stats;
+
+/* Device time of the phases, accumulated over the calls made with options.timing = 1
+ * (HIP events on the context's stream). */
+typedef struct {
+    double init_ms;        /* value scatter into the factor storage */
+    double sweep_ms;       /* right-looking level sweep over the sparse columns */
+    double dense_ms;       /* dense trailing block: panels, MFMA updates, pivot test, scatter */
+    double solve_sparse_ms;/* sparse levels of the L and U solves */
+    double solve_dense_ms; /* dense block solves */
+    int64_t refactors;     /* refactorizations timed */
+    int64_t solve_passes;  /* triangular solve passes timed (each covers up to 8 right-hand sides) */
+    int64_t sweep_launches, dense_launches, solve_sparse_launches, solve_dense_launches;
+} cktlu_timing;
 
 /* Fill *opt with defaults. */
 void cktlu_default_options(cktlu_options *opt);
@@ -218,6 +240,10 @@ int cktlu_get_levels(const cktlu_ctx *ctx, int32_t *level);
 
 /* Counters and sizes. */
 int cktlu_get_stats(const cktlu_ctx *ctx, cktlu_stats *out);
+
+/* Accumulated phase times (see cktlu_timing); synchronises the context's stream.
+ * reset != 0 clears the accumulators afterwards.  Errors: E_ARG. */
+int cktlu_get_timing(cktlu_ctx *ctx, cktlu_timing *out, int reset);
 
 /* Device memory the context holds now, plus what one batched instance would
  * add (for admission control). */

@@ -40,7 +40,7 @@ EXPORTS = [
     "cktlu_analyze", "cktlu_factorize", "cktlu_factorize_host", "cktlu_refactorize",
     "cktlu_refactorize_nocheck", "cktlu_solve", "cktlu_refactorize_batched", "cktlu_solve_batched",
     "cktlu_get_perm", "cktlu_get_analysis", "cktlu_get_factor_nnz", "cktlu_get_factors",
-    "cktlu_get_levels", "cktlu_get_stats", "cktlu_footprint_bytes",
+    "cktlu_get_levels", "cktlu_get_stats", "cktlu_get_timing", "cktlu_footprint_bytes",
 ]
 
 
@@ -48,7 +48,8 @@ class cktlu_options(ctypes.Structure):
     _fields_ = [("pivot_eps", ctypes.c_double), ("precision", ctypes.c_int), ("ir_tol", ctypes.c_double),
                 ("ir_max_iter", ctypes.c_int), ("ordering", ctypes.c_int), ("transversal", ctypes.c_int),
                 ("stream", ctypes.c_void_p), ("force_fail_col", ctypes.c_int),
-                ("dense_tail_size", ctypes.c_int), ("dense_tail_density", ctypes.c_double)]
+                ("dense_tail_size", ctypes.c_int), ("dense_tail_density", ctypes.c_double),
+                ("timing", ctypes.c_int)]
 
 
 class cktlu_refactor_info(ctypes.Structure):
@@ -67,7 +68,21 @@ class cktlu_stats(ctypes.Structure):
                 ("dense_tail", ctypes.c_int64), ("n_factorize", ctypes.c_int64),
                 ("n_refactorize", ctypes.c_int64), ("n_repivot", ctypes.c_int64),
                 ("n_restart_cols", ctypes.c_int64), ("n_fp64_fallback_solves", ctypes.c_int64),
-                ("bytes_refactor", ctypes.c_double), ("bytes_solve", ctypes.c_double)]
+                ("bytes_refactor", ctypes.c_double), ("bytes_solve", ctypes.c_double),
+                ("macs_sweep", ctypes.c_double), ("bytes_sweep", ctypes.c_double),
+                ("flops_dense", ctypes.c_double), ("sweep_launches", ctypes.c_int64),
+                ("dense_launches", ctypes.c_int64), ("solve_launches", ctypes.c_int64)]
+
+    def as_dict(self):
+        return {f: getattr(self, f) for f, _ in self._fields_}
+
+
+class cktlu_timing(ctypes.Structure):
+    _fields_ = [("init_ms", ctypes.c_double), ("sweep_ms", ctypes.c_double), ("dense_ms", ctypes.c_double),
+                ("solve_sparse_ms", ctypes.c_double), ("solve_dense_ms", ctypes.c_double),
+                ("refactors", ctypes.c_int64), ("solve_passes", ctypes.c_int64),
+                ("sweep_launches", ctypes.c_int64), ("dense_launches", ctypes.c_int64),
+                ("solve_sparse_launches", ctypes.c_int64), ("solve_dense_launches", ctypes.c_int64)]
 
     def as_dict(self):
         return {f: getattr(self, f) for f, _ in self._fields_}
@@ -102,6 +117,7 @@ def _load():
     lib.cktlu_get_factors.argtypes = [P, I32, P, P, P, P, P, P]
     lib.cktlu_get_levels.argtypes = [P, P]
     lib.cktlu_get_stats.argtypes = [P, ctypes.POINTER(cktlu_stats)]
+    lib.cktlu_get_timing.argtypes = [P, ctypes.POINTER(cktlu_timing), ctypes.c_int]
     lib.cktlu_footprint_bytes.argtypes = [P, I32]
     lib.cktlu_footprint_bytes.restype = ctypes.c_size_t
     for name in EXPORTS:
@@ -216,6 +232,12 @@ def cktlu_get_levels(ctx, level):
     return lib.cktlu_get_levels(ctx, _ptr(level))
 
 
+def cktlu_get_timing(ctx, reset=0) -> cktlu_timing:
+    t = cktlu_timing()
+    _check(lib.cktlu_get_timing(ctx, ctypes.byref(t), int(reset)), "cktlu_get_timing")
+    return t
+
+
 def cktlu_get_stats(ctx) -> cktlu_stats:
     s = cktlu_stats()
     _check(lib.cktlu_get_stats(ctx, ctypes.byref(s)), "cktlu_get_stats")
@@ -237,8 +259,9 @@ class SparseLU:
 
     def __init__(self, n, colptr, rowind, eps=1e-3, precision=CKTLU_FP64, ordering=CKTLU_ORDER_AMD,
                  ir_tol=1e-10, ir_max_iter=10, stream=None, transversal=1, dense_tail=None,
-                 dense_tail_density=None):
+                 dense_tail_density=None, timing=False):
         opt = cktlu_default_options()
+        opt.timing = 1 if timing else 0
         if dense_tail is not None:
             opt.dense_tail_size = int(dense_tail)
         if dense_tail_density is not None:
@@ -328,6 +351,9 @@ class SparseLU:
 
     def stats(self) -> dict:
         return cktlu_get_stats(self.ctx).as_dict()
+
+    def timing(self, reset=False) -> dict:
+        return cktlu_get_timing(self.ctx, 1 if reset else 0).as_dict()
 
     def footprint_bytes(self, batch=0) -> int:
         return cktlu_footprint_bytes(self.ctx, batch)

@@ -27,6 +27,11 @@ struct cktlu_ctx {
     int force_fail_pending = -1;
     int last_batch = 0;            // batch of the last batched refactorization
     double anorm_host = 0.0;
+    // options.timing: event pairs recorded around device phases, read by cktlu_get_timing
+    struct Pending { int phase; hipEvent_t a, b; int launches; };
+    std::vector<Pending> pending;
+    std::vector<hipEvent_t> event_pool;
+    cktlu_timing timing_acc;
 };
 
 namespace {
@@ -58,6 +63,62 @@ void debug_hip(int e, const char *what, int line) {
     } while (0)
 
 inline hipStream_t stream_of(const cktlu_ctx *c) { return (hipStream_t)c->opt.stream; }
+
+// ---- phase timing (options.timing)
+enum { PH_INIT, PH_SWEEP, PH_DENSE, PH_SOLVE_SPARSE, PH_SOLVE_DENSE };
+
+hipEvent_t take_event(cktlu_ctx *c) {
+    if (!c->event_pool.empty()) {
+        hipEvent_t e = c->event_pool.back();
+        c->event_pool.pop_back();
+        return e;
+    }
+    hipEvent_t e = nullptr;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    return e;
+}
+
+// Records the start event of a phase (nullptr when timing is off or no event).
+hipEvent_t phase_begin(cktlu_ctx *c) {
+    if (!c->opt.timing) return nullptr;
+    hipEvent_t e = take_event(c);
+    if (e && hipEventRecord(e, stream_of(c)) != hipSuccess) {
+        c->event_pool.push_back(e);
+        return nullptr;
+    }
+    return e;
+}
+
+void phase_end(cktlu_ctx *c, hipEvent_t start, int phase, int launches) {
+    if (!start) return;
+    hipEvent_t e = take_event(c);
+    if (!e || hipEventRecord(e, stream_of(c)) != hipSuccess) {
+        c->event_pool.push_back(start);
+        if (e) c->event_pool.push_back(e);
+        return;
+    }
+    c->pending.push_back({phase, start, e, launches});
+}
+
+int collect_timing(cktlu_ctx *c) {
+    for (const auto &p : c->pending) {
+        float ms = 0.f;
+        if (hipEventSynchronize(p.b) != hipSuccess || hipEventElapsedTime(&ms, p.a, p.b) != hipSuccess)
+            return CKTLU_E_HIP;
+        cktlu_timing &t = c->timing_acc;
+        switch (p.phase) {
+            case PH_INIT: t.init_ms += ms; break;
+            case PH_SWEEP: t.sweep_ms += ms; t.sweep_launches += p.launches; break;
+            case PH_DENSE: t.dense_ms += ms; t.dense_launches += p.launches; break;
+            case PH_SOLVE_SPARSE: t.solve_sparse_ms += ms; t.solve_sparse_launches += p.launches; break;
+            case PH_SOLVE_DENSE: t.solve_dense_ms += ms; t.solve_dense_launches += p.launches; break;
+        }
+        c->event_pool.push_back(p.a);
+        c->event_pool.push_back(p.b);
+    }
+    c->pending.clear();
+    return CKTLU_OK;
+}
 
 void dfree(DevBuf &b) {
     if (b.p) (void)hipFree(b.p);
@@ -218,6 +279,20 @@ void fill_stats_pattern(cktlu_ctx *c) {
     t.bytes_refactor = 12.0 * (double)t.nnz_a + (4.0 + fb) * nF;
     // factor values + indices read once, plus the solution vectors
     t.bytes_solve = (4.0 + fb) * nF + 24.0 * (double)t.n;
+    const Schedule &s = c->s;
+    t.macs_sweep = s.macs_sweep;
+    t.bytes_sweep = 28.0 * s.macs_sweep + 24.0 * s.lnz_front;
+    const double D = (double)(c->an.n - s.tail0);
+    t.flops_dense = 2.0 / 3.0 * D * D * D + D * D / 2.0;
+    t.sweep_launches = 0;
+    for (int l = 0; l <= s.n_rlevels; l++) {
+        const int64_t w = (l < s.n_rlevels ? (s.lvl_ptr[l + 1] - s.lvl_ptr[l]) + (s.task_ptr[l + 1] - s.task_ptr[l]) : 0) +
+                          (l > 0 ? s.lvl_ptr[l] - s.lvl_ptr[l - 1] : 0);
+        if (w > 0) t.sweep_launches++;
+    }
+    const int64_t panels = (int64_t)((D + kDenseBlock - 1) / kDenseBlock);
+    t.dense_launches = D > 0 ? 2 * panels - 1 + 2 : 0;        // panels, updates, pivot test, scatter
+    t.solve_launches = (int64_t)(s.lsptr.size() - 1) + (int64_t)(s.usptr.size() - 1) + (D > 0 ? 2 * panels : 0);
 }
 
 // Host factorization with pivoting (keep == nullptr: every column), then
@@ -336,14 +411,21 @@ int run_refactor(cktlu_ctx *c, int batch, const double *values_dev, bool fp32, b
     a.S = d.S.p;
     a.fp32 = fp32 ? 1 : 0;
     a.check = check ? 1 : 0;
+    hipEvent_t t0 = phase_begin(c);
     LCHK(launch_refactor_init(a, st));
+    phase_end(c, t0, PH_INIT, 1);
+    t0 = phase_begin(c);
+    int launches = 0;
     // level l: check level l, normalise level l-1, update tasks of level l; then normalise the last
     for (int l = 0; l <= s.n_rlevels; l++) {
         const int cb = l < s.n_rlevels ? s.lvl_ptr[l] : 0, ce = l < s.n_rlevels ? s.lvl_ptr[l + 1] : 0;
         const int pb = l > 0 ? s.lvl_ptr[l - 1] : 0, pe = l > 0 ? s.lvl_ptr[l] : 0;
         const int tb = l < s.n_rlevels ? s.task_ptr[l] : 0, te = l < s.n_rlevels ? s.task_ptr[l + 1] : 0;
         LCHK(launch_refactor_level(a, cb, ce, pb, pe, tb, te, st));
+        launches += (ce - cb) + (pe - pb) + (te - tb) > 0;
     }
+    phase_end(c, t0, PH_SWEEP, launches);
+    if (c->opt.timing) c->timing_acc.refactors++;
     if (s.tail0 < c->an.n) {
         DenseArgs da = dense_args(c, batch, fp32);
         da.ctrl = a.ctrl;
@@ -352,7 +434,9 @@ int run_refactor(cktlu_ctx *c, int batch, const double *values_dev, bool fp32, b
         da.epoch = a.epoch;
         da.force_fail_col = force_col;
         da.check = a.check;
+        t0 = phase_begin(c);
         LCHK(launch_dense_refactor(da, false, st));
+        phase_end(c, t0, PH_DENSE, (int)c->stats.dense_launches);
         d.S_prec = fp32 ? 1 : 0;
     }
     return CKTLU_OK;
@@ -463,15 +547,23 @@ int tri_solves(cktlu_ctx *c, int nrhs, int batch, double *z, bool fp32, const in
     a.skip = skip;
     const Schedule &s = c->s;
     // sparse L levels (the last one holds the dense rows: their entries in sparse columns)
+    hipEvent_t t0 = phase_begin(c);
     for (int l = 0; l + 1 < (int)s.lsptr.size(); l++) LCHK(launch_lsolve_level(a, s.lsptr[l], s.lsptr[l + 1], st));
+    phase_end(c, t0, PH_SOLVE_SPARSE, (int)s.lsptr.size() - 1);
     if (s.tail0 < c->an.n) {
         int rc = ensure_S(c, fp32, batch);
         if (rc) return rc;
         const DenseArgs da = dense_args(c, batch, fp32);
+        const int nblk = (da.D + kDenseBlock - 1) / kDenseBlock;
+        t0 = phase_begin(c);
         LCHK(launch_dense_solve(da, z, nrhs, skip, false, st));
         LCHK(launch_dense_solve(da, z, nrhs, skip, true, st));
+        phase_end(c, t0, PH_SOLVE_DENSE, 2 * nblk);
     }
+    t0 = phase_begin(c);
     for (int l = 0; l + 1 < (int)s.usptr.size(); l++) LCHK(launch_usolve_level(a, s.usptr[l], s.usptr[l + 1], st));
+    phase_end(c, t0, PH_SOLVE_SPARSE, (int)s.usptr.size() - 1);
+    if (c->opt.timing) c->timing_acc.solve_passes++;
     return CKTLU_OK;
 }
 
@@ -580,6 +672,7 @@ int cktlu_create(cktlu_ctx **out, const cktlu_options *opt) {
         return CKTLU_E_ARG;
     }
     std::memset(&c->stats, 0, sizeof(c->stats));
+    std::memset(&c->timing_acc, 0, sizeof(c->timing_acc));
     c->force_fail_pending = c->opt.force_fail_col;
     *out = c;
     return CKTLU_OK;
@@ -587,6 +680,9 @@ int cktlu_create(cktlu_ctx **out, const cktlu_options *opt) {
 
 void cktlu_destroy(cktlu_ctx *c) {
     if (!c) return;
+    if (!c->pending.empty()) (void)hipStreamSynchronize(stream_of(c));
+    for (auto &p : c->pending) { (void)hipEventDestroy(p.a); (void)hipEventDestroy(p.b); }
+    for (hipEvent_t e : c->event_pool) (void)hipEventDestroy(e);
     free_device(c->dev);
     delete c;
 }
@@ -817,6 +913,15 @@ int cktlu_get_levels(const cktlu_ctx *c, int32_t *level) {
 int cktlu_get_stats(const cktlu_ctx *c, cktlu_stats *out) {
     if (!c || !out) return CKTLU_E_ARG;
     *out = c->stats;
+    return CKTLU_OK;
+}
+
+int cktlu_get_timing(cktlu_ctx *c, cktlu_timing *out, int reset) {
+    if (!c || !out) return CKTLU_E_ARG;
+    int rc = collect_timing(c);
+    if (rc) return rc;
+    *out = c->timing_acc;
+    if (reset) std::memset(&c->timing_acc, 0, sizeof(c->timing_acc));
     return CKTLU_OK;
 }
 

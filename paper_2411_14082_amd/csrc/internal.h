@@ -87,6 +87,7 @@ struct Schedule {
     std::vector<int> Acp, Acj, Acsrc;
     int max_col = 0;                          // longest column of F
     double macs = 0, flops = 0;
+    double macs_sweep = 0, lnz_front = 0;     // MACs of the update tasks; L entries of sparse columns
     int tail0 = 0;                            // first column of the densely factored tail (n = none)
     std::vector<int> tail_rend;               // rows i >= tail0: L entries of columns < tail0 end here
     std::vector<int> lrec, urec, Lrjs, Urjs;  // the solve levels packed for the device

@@ -212,6 +212,13 @@ void build_schedule(const Analysis &an, const Factor &f, const cktlu_options &op
             }
         }
         s.task8[8 * (size_t)ntasks + 3] = (int)(s.item4.size() / 4);
+        s.macs_sweep = 0;
+        for (int64_t i = 0; i < nitems; i++) {
+            const int j = s.src_col[i];
+            s.macs_sweep += (double)(s.Dlen[j] - f.nU[j]);
+        }
+        s.lnz_front = 0;
+        for (int k = 0; k < T; k++) s.lnz_front += (double)(s.Dlen[k] - f.nU[k]);
     }
     // ---- solve levels of the sparse rows [0, T): row i of L waits for every j with
     // L(i,j) != 0, row i of U for every j > i with U(i,j) != 0 (rows >= T of U are
