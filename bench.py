@@ -40,18 +40,24 @@ TRAFFIC_FILE = os.path.join(ROOT, "profiles", "refactor_level_kernel_traffic_lay
 KERNEL_SRC = os.path.join(ROOT, "paper_2411_14082_amd", "csrc", "kernels.hip")
 
 
+def kernel_source_hash():
+    """sha256 of the sweep kernel's source (apply_item and refactor_level_kernel)."""
+    txt = open(KERNEL_SRC).read()
+    a, z = txt.find("constexpr int kItemChunk"), txt.find("__global__ void reset_ctrl_kernel")
+    return hashlib.sha256(txt[a:z].encode()).hexdigest() if 0 <= a < z else None
+
+
 def measured_traffic():
     """Bytes per sweep launch from the committed counter summary, or None when the
-    kernel source has changed since the counters were taken."""
+    sweep kernel's source has changed since the counters were taken."""
     if not os.path.exists(TRAFFIC_FILE):
         return None
     txt = open(TRAFFIC_FILE).read()
-    m_sha = re.search(r"kernels_hip_sha256:\s*([0-9a-f]{64})", txt)
+    m_sha = re.search(r"refactor_level_kernel_source_sha256:\s*([0-9a-f]{64})", txt)
     m_b = re.search(r"hbm_bytes_per_launch:\s*([0-9.eE+]+)", txt)
     if not m_sha or not m_b:
         return None
-    cur = hashlib.sha256(open(KERNEL_SRC, "rb").read()).hexdigest()
-    return float(m_b.group(1)) if cur == m_sha.group(1) else None
+    return float(m_b.group(1)) if kernel_source_hash() == m_sha.group(1) else None
 
 
 def log(*a):

@@ -204,14 +204,20 @@ int cktlu_refactorize_batched(cktlu_ctx *ctx, int32_t batch, const double *value
 
 /*
  * Solves with the resident factors of the last cktlu_refactorize_batched.
- * b_dev: device, batch x nrhs x n FP64 (instance i, rhs r at (i*nrhs + r)*n);
- * x_dev: same layout.  Instances whose status is not -1 are skipped (their x
- * is left unchanged).  In FP32_IR mode a fixed number of refinement steps
- * (ir_max_iter) runs without host synchronisation.  Errors: E_STATE, E_ARG,
- * E_HIP.
+ * b_dev: device, batch x nrhs x n FP64 (instance i, rhs r at (i*nrhs + r)*n),
+ * nrhs <= 8; x_dev: same layout.  status_dev: the status array of that call;
+ * instances whose status is not -1 are skipped (their x is left unchanged).
+ * FP32_IR mode: every instance is refined in FP64 (residual with its own
+ * values) until eta_inf <= ir_tol; converged instances leave the refinement,
+ * the host checks progress after each step (one synchronisation per step).
+ * Instances that reach ir_max_iter or stall are re-solved with FP64 factors
+ * of their values (all instances are re-factored in FP64 for that), and the
+ * call returns W_IR_FALLBACK.  eta_dev (device, double[batch], may be NULL)
+ * receives each instance's final eta_inf in FP32_IR mode (-1 if skipped or
+ * in FP64 mode).  Errors: E_STATE, E_ARG, E_NOMEM, E_HIP.
  */
 int cktlu_solve_batched(cktlu_ctx *ctx, int32_t batch, int32_t nrhs, const double *b_dev,
-                        double *x_dev, const int32_t *status_dev);
+                        double *x_dev, const int32_t *status_dev, double *eta_dev);
 
 /* Permutations (host out, int32[n] each): A(rowperm[k], colperm[j]) is the
  * (k, j) entry of the matrix that was factored, rowperm including pivoting. */

@@ -110,7 +110,7 @@ def _load():
     lib.cktlu_refactorize_nocheck.argtypes = [P, P]
     lib.cktlu_solve.argtypes = [P, I32, P, I32, P, I32, ctypes.POINTER(cktlu_solve_info)]
     lib.cktlu_refactorize_batched.argtypes = [P, I32, P, P]
-    lib.cktlu_solve_batched.argtypes = [P, I32, I32, P, P, P]
+    lib.cktlu_solve_batched.argtypes = [P, I32, I32, P, P, P, P]
     lib.cktlu_get_perm.argtypes = [P, P, P]
     lib.cktlu_get_analysis.argtypes = [P, P, P, P, P]
     lib.cktlu_get_factor_nnz.argtypes = [P, P, P]
@@ -208,8 +208,9 @@ def cktlu_refactorize_batched(ctx, batch, values_dev, status_dev):
     return lib.cktlu_refactorize_batched(ctx, int(batch), _ptr(values_dev), _ptr(status_dev))
 
 
-def cktlu_solve_batched(ctx, batch, nrhs, b_dev, x_dev, status_dev):
-    return lib.cktlu_solve_batched(ctx, int(batch), int(nrhs), _ptr(b_dev), _ptr(x_dev), _ptr(status_dev))
+def cktlu_solve_batched(ctx, batch, nrhs, b_dev, x_dev, status_dev, eta_dev=None):
+    return lib.cktlu_solve_batched(ctx, int(batch), int(nrhs), _ptr(b_dev), _ptr(x_dev), _ptr(status_dev),
+                                   _ptr(eta_dev))
 
 
 def cktlu_get_perm(ctx, rowperm, colperm):
@@ -316,8 +317,8 @@ class SparseLU:
         return _check(cktlu_refactorize_batched(self.ctx, batch, values_dev, status_dev),
                       "cktlu_refactorize_batched")
 
-    def solve_batched(self, batch, nrhs, b_dev, x_dev, status_dev):
-        return _check(cktlu_solve_batched(self.ctx, batch, nrhs, b_dev, x_dev, status_dev),
+    def solve_batched(self, batch, nrhs, b_dev, x_dev, status_dev, eta_dev=None):
+        return _check(cktlu_solve_batched(self.ctx, batch, nrhs, b_dev, x_dev, status_dev, eta_dev),
                       "cktlu_solve_batched")
 
     def analysis(self, with_pivots=True):

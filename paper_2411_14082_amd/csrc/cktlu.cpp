@@ -148,7 +148,7 @@ DevBuf *all_buffers(Device &d, int i) {
                      &d.item4, &d.lrec, &d.urec,
                      &d.Lrjs, &d.Urjs, &d.rowperm,
                      &d.colperm_sol, &d.Acp, &d.Acj, &d.Acsrc, &d.Fx64, &d.Fx32, &d.Aval, &d.done,
-                     &d.ctrl, &d.vec, &d.S};
+                     &d.ctrl, &d.vec, &d.S, &d.Dg};
     const int cnt = (int)(sizeof(all) / sizeof(all[0]));
     return i < cnt ? all[i] : nullptr;
 }
@@ -211,6 +211,8 @@ int ensure_batch(cktlu_ctx *c, int batch) {
     if (D > 0) {
         dfree(d.S);
         if ((rc = dalloc(d.S, D * D * sizeof(double) * batch))) return rc;
+        dfree(d.Dg);
+        if ((rc = dalloc(d.Dg, (size_t)kDenseBlock * kDenseBlock * sizeof(double) * batch))) return rc;
     }
     d.S_prec = -1;
     d.batch_cap = batch;
@@ -356,6 +358,7 @@ DenseArgs dense_args(cktlu_ctx *c, int batch, bool fp32) {
     a.Fx = fp32 ? d.Fx32.p : d.Fx64.p;
     a.nnzF = nnzF(c);
     a.S = d.S.p;
+    a.Dg = d.Dg.p;
     a.ctrl = (int *)d.ctrl.p;
     a.done = (int *)d.done.p;
     a.force_fail_col = -1;
@@ -809,19 +812,88 @@ int cktlu_refactorize_batched(cktlu_ctx *c, int32_t batch, const double *values_
 }
 
 int cktlu_solve_batched(cktlu_ctx *c, int32_t batch, int32_t nrhs, const double *b, double *x,
-                        const int32_t *status_dev) {
-    if (!c || batch < 1 || nrhs < 1 || nrhs > 8 || !b || !x) return CKTLU_E_ARG;
+                        const int32_t *status_dev, double *eta_dev) {
+    if (!c || batch < 1 || nrhs < 1 || nrhs > 8 || !b || !x || !status_dev) return CKTLU_E_ARG;
     if (c->state < 2 || c->last_batch < batch) return CKTLU_E_STATE;
     const int n = c->an.n;
-    int rc = ensure_vec(c, (size_t)n * YS * batch + 64);
+    const int64_t nnzA = c->an.nnz;
+    const size_t nv = (size_t)n * nrhs * batch;
+    // work vectors: z (batch x n rows of YS), r (nv), norms (3 nrhs per instance),
+    // |A| and eta per instance, then two int arrays of batch (refinement skip, FP64 skip)
+    const size_t zd = (size_t)n * YS * batch + 64;
+    const size_t need = zd + nv + 3 * (size_t)nrhs * batch + 2 * (size_t)batch + (size_t)batch + 64;
+    int rc = ensure_vec(c, need);
     if (rc) return rc;
     hipStream_t st = stream_of(c);
     double *z = (double *)c->dev.vec.p;
-    const bool fp32 = c->opt.precision == CKTLU_FP32_IR;
-    LCHK(launch_gather_rhs(n, nrhs, batch, b, n, (const int *)c->dev.rowperm.p, z, st));
-    if ((rc = tri_solves(c, nrhs, batch, z, fp32, status_dev))) return rc;
-    LCHK(launch_scatter_sol(n, nrhs, batch, z, (const int *)c->dev.colperm_sol.p, x, n, 0, status_dev, st));
-    return CKTLU_OK;
+    double *r = z + zd;
+    double *norms = r + nv;
+    double *anorm = norms + 3 * (size_t)nrhs * batch;
+    double *eta = anorm + batch;
+    int *skip = (int *)(eta + batch);
+    int *skip64 = skip + batch;
+    const int *rowperm = (const int *)c->dev.rowperm.p, *colperm = (const int *)c->dev.colperm_sol.p;
+    if (eta_dev) LCHK(launch_fill_f64(eta_dev, batch, -1.0, st));
+    if (c->opt.precision == CKTLU_FP64) {
+        LCHK(launch_gather_rhs(n, nrhs, batch, b, n, rowperm, z, st));
+        if ((rc = tri_solves(c, nrhs, batch, z, false, status_dev))) return rc;
+        LCHK(launch_scatter_sol(n, nrhs, batch, z, colperm, x, n, 0, status_dev, st));
+        return CKTLU_OK;
+    }
+    // FP32 factors with FP64 refinement per instance: x = 0; repeat d = (LU)^-1 r, x += d,
+    // r = b - A x, until eta <= ir_tol (instances leave as they converge) or the limit
+    const int *Acp = (const int *)c->dev.Acp.p, *Acj = (const int *)c->dev.Acj.p;
+    const int *Acsrc = (const int *)c->dev.Acsrc.p;
+    const double *Aval = (const double *)c->dev.Aval.p;
+    LCHK(launch_fill_f64(x, (int64_t)nv, 0.0, st));
+    LCHK(launch_fill_f64(anorm, batch, 0.0, st));
+    LCHK(launch_anorm_batched(n, batch, nnzA, Acp, Acsrc, Aval, anorm, st));
+    LCHK(launch_copy_i32(status_dev, skip, batch, st));
+    std::vector<int> hskip(batch), hstatus(batch);
+    std::vector<double> heta(batch), prev(batch, INFINITY);
+    std::vector<char> stalled(batch, 0);
+    HIPCHK(hipMemcpyAsync(hstatus.data(), status_dev, batch * sizeof(int), hipMemcpyDeviceToHost, st));
+    for (int it = 1; it <= c->opt.ir_max_iter; it++) {
+        LCHK(launch_gather_rhs(n, nrhs, batch, it == 1 ? b : r, n, rowperm, z, st));
+        if ((rc = tri_solves(c, nrhs, batch, z, true, skip))) return rc;
+        LCHK(launch_scatter_sol(n, nrhs, batch, z, colperm, x, n, 1, skip, st));
+        LCHK(launch_fill_f64(norms, 3 * (int64_t)nrhs * batch, 0.0, st));
+        LCHK(launch_residual_batched(n, nrhs, batch, nnzA, Acp, Acj, Acsrc, Aval, x, b, r, norms, skip, st));
+        LCHK(launch_ir_check(batch, nrhs, norms, anorm, c->opt.ir_tol, skip, eta, st));
+        HIPCHK(hipMemcpyAsync(hskip.data(), skip, batch * sizeof(int), hipMemcpyDeviceToHost, st));
+        HIPCHK(hipMemcpyAsync(heta.data(), eta, batch * sizeof(double), hipMemcpyDeviceToHost, st));
+        HIPCHK(hipStreamSynchronize(st));
+        int active = 0;
+        for (int i = 0; i < batch; i++) {
+            if (hskip[i] != -1) continue;
+            if (it >= 3 && heta[i] > 0.5 * prev[i]) { stalled[i] = 1; hskip[i] = 2; continue; }   // no progress
+            prev[i] = heta[i];
+            active++;
+        }
+        if (!active) break;
+        HIPCHK(hipMemcpyAsync(skip, hskip.data(), batch * sizeof(int), hipMemcpyHostToDevice, st));
+    }
+    if (eta_dev) LCHK(launch_copy_f64(eta, eta_dev, batch, st));
+    // instances that did not reach ir_tol: FP64 factors and an FP64 solve for them
+    std::vector<int> h64(batch, 1);
+    int nfb = 0;
+    for (int i = 0; i < batch; i++)
+        if (hstatus[i] == -1 && (hskip[i] == -1 || stalled[i])) { h64[i] = -1; nfb++; }
+    if (!nfb) return CKTLU_OK;
+    if ((rc = run_refactor(c, batch, Aval, false, false, -1))) return rc;
+    HIPCHK(hipMemcpyAsync(skip64, h64.data(), batch * sizeof(int), hipMemcpyHostToDevice, st));
+    LCHK(launch_gather_rhs(n, nrhs, batch, b, n, rowperm, z, st));
+    if ((rc = tri_solves(c, nrhs, batch, z, false, skip64))) return rc;
+    LCHK(launch_scatter_sol(n, nrhs, batch, z, colperm, x, n, 0, skip64, st));
+    if (eta_dev) {
+        LCHK(launch_fill_f64(norms, 3 * (int64_t)nrhs * batch, 0.0, st));
+        LCHK(launch_residual_batched(n, nrhs, batch, nnzA, Acp, Acj, Acsrc, Aval, x, b, r, norms, skip64, st));
+        LCHK(launch_ir_check(batch, nrhs, norms, anorm, 0.0, skip64, eta, st));
+        LCHK(launch_copy_f64(eta, eta_dev, batch, st));   // instances solved in FP64 get their eta
+    }
+    HIPCHK(hipStreamSynchronize(st));
+    c->stats.n_fp64_fallback_solves += nfb;
+    return CKTLU_W_IR_FALLBACK;
 }
 
 int cktlu_get_perm(const cktlu_ctx *c, int32_t *rowperm, int32_t *colperm) {

@@ -182,10 +182,15 @@ __global__ __launch_bounds__(256) void dlu_panel_kernel(DenseArgs a, int p, int 
     if (wv == 0) diag_factor_wave<T>(S, D, p, nb, blk, invd);
     __syncthreads();
     if (blockIdx.x == 0) {
+        // Other workgroups of this launch still read the unfactored block from S, so the
+        // factors go to the instance's scratch block, which the update launch of this panel
+        // copies into S; a panel without other workgroups (the last) writes S directly.
+        T *dst = gridDim.x == 1 ? S + (size_t)p * D + p : reinterpret_cast<T *>(a.Dg) + (size_t)inst * NB * NB;
+        const int ld = gridDim.x == 1 ? D : NB;
 #pragma unroll
         for (int e = 0; e < 16; e++) {
             const int rr = 16 * wv + e;
-            if (lane < nb && rr < nb) S[(size_t)(p + lane) * D + p + rr] = blk[lane][rr];
+            if (lane < nb && rr < nb) dst[(size_t)lane * ld + rr] = blk[lane][rr];
         }
         return;
     }
@@ -233,6 +238,18 @@ __global__ __launch_bounds__(256) void dlu_gemm_kernel(DenseArgs a, int p) {
     const int D = a.D;
     const int r0 = p + NB + blockIdx.x * TM, c0 = p + NB + blockIdx.y * TM;
     const int tid = threadIdx.x;
+    if (blockIdx.x == 0 && blockIdx.y == 0) {
+        // the factored diagonal block of this panel (full: the panel has a trailing part)
+        const T *src = reinterpret_cast<const T *>(a.Dg) + (size_t)inst * NB * NB;
+        T t[16];
+#pragma unroll
+        for (int u = 0; u < 16; u++) t[u] = src[tid + 256 * u];
+#pragma unroll
+        for (int u = 0; u < 16; u++) {
+            const int e = tid + 256 * u;
+            S[(size_t)(p + e / NB) * D + p + e % NB] = t[u];
+        }
+    }
     T ra[8], rb[8];
     auto fetch = [&](int kc) {
 #pragma unroll

@@ -115,6 +115,7 @@ struct Device {
     DevBuf done, ctrl;                 // per-column completion epochs, status words
     DevBuf vec;                        // solve work vectors
     DevBuf S;                          // dense trailing block, batch x D x D (8-byte slots)
+    DevBuf Dg;                         // batch x 64 x 64 (8-byte slots): a panel's diagonal block
     size_t vec_cap = 0;
     unsigned epoch = 0;
     int S_prec = -1;                   // what S holds: -1 stale, 0 FP64 factors, 1 FP32 factors
@@ -184,6 +185,17 @@ int launch_residual(int n, int nrhs, const int *Acp, const int *Acj, const int *
 int launch_anorm(int n, const int *Acp, const int *Acsrc, const double *Aval, double *out,
                  void *stream);
 int launch_copy_f64(const double *src, double *dst, int64_t count, void *stream);
+int launch_copy_i32(const int *src, int *dst, int64_t count, void *stream);
+int launch_fill_f64(double *dst, int64_t count, double value, void *stream);
+// batched refinement: per-instance residuals and their norms, |A|_inf per instance,
+// and the convergence test that takes converged instances out of skip
+int launch_residual_batched(int n, int nrhs, int batch, int64_t nnzA, const int *Acp, const int *Acj,
+                            const int *Acsrc, const double *Aval, const double *x, const double *b, double *r,
+                            double *norms, const int *skip, void *stream);
+int launch_anorm_batched(int n, int batch, int64_t nnzA, const int *Acp, const int *Acsrc, const double *Aval,
+                         double *out, void *stream);
+int launch_ir_check(int batch, int nrhs, const double *norms, const double *anorm, double tol, int *skip,
+                    double *eta, void *stream);
 int launch_f64_to_f32(const double *src, float *dst, int64_t count, void *stream);
 int launch_fill_i32(int *dst, int64_t count, int value, void *stream);
 
@@ -196,6 +208,7 @@ struct DenseArgs {
     void *Fx;                  // factor values (double or float), batch x nnzF
     int64_t nnzF;
     void *S;                   // batch x D x D values of the factor type
+    void *Dg;                  // batch x NB x NB: factored diagonal block of the current panel
     int *ctrl, *done;          // status words and completion epochs (as RefactorArgs)
     double eps;
     unsigned epoch;

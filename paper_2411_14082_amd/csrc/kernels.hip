@@ -547,6 +547,101 @@ int launch_anorm(int n, const int *Acp, const int *Acsrc, const double *Aval, do
     return (int)hipGetLastError();
 }
 
+// Batched refinement: instance i uses values Aval + i*nnzA and vectors at
+// (i*nrhs + r)*n; skip[i] != -1 leaves an instance out.
+__global__ void residual_batched_kernel(int n, int nrhs, int batch, int64_t nnzA, const int *Acp, const int *Acj,
+                                        const int *Acsrc, const double *Aval, const double *x, const double *b,
+                                        double *r, double *norms, const int *skip) {
+    const int64_t total = (int64_t)n * batch;
+    for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < total; t += (int64_t)gridDim.x * blockDim.x) {
+        const int inst = (int)(t / n), i = (int)(t % n);
+        if (skip[inst] != -1) continue;
+        const double *Av = Aval + (size_t)inst * nnzA;
+        for (int rr = 0; rr < nrhs; rr++) {
+            const size_t o = ((size_t)inst * nrhs + rr) * n;
+            double acc = b[o + i];
+            for (int p = Acp[i]; p < Acp[i + 1]; p++) acc -= Av[Acsrc[p]] * x[o + Acj[p]];
+            r[o + i] = acc;
+            double *nm = norms + ((size_t)inst * nrhs + rr) * 3;
+            atomic_max_nonneg(&nm[0], fabs(acc));
+            atomic_max_nonneg(&nm[1], fabs(x[o + i]));
+            atomic_max_nonneg(&nm[2], fabs(b[o + i]));
+        }
+    }
+}
+
+__global__ void anorm_batched_kernel(int n, int batch, int64_t nnzA, const int *Acp, const int *Acsrc,
+                                     const double *Aval, double *out) {
+    const int64_t total = (int64_t)n * batch;
+    for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < total; t += (int64_t)gridDim.x * blockDim.x) {
+        const int inst = (int)(t / n), i = (int)(t % n);
+        const double *Av = Aval + (size_t)inst * nnzA;
+        double s = 0.0;
+        for (int p = Acp[i]; p < Acp[i + 1]; p++) s += fabs(Av[Acsrc[p]]);
+        atomic_max_nonneg(&out[inst], s);
+    }
+}
+
+// eta[i] = max over right-hand sides of |r| / (|A| |x| + |b|); an instance whose
+// eta reaches tol leaves the refinement (skip = 1).
+__global__ void ir_check_kernel(int batch, int nrhs, const double *norms, const double *anorm, double tol,
+                                int *skip, double *eta) {
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < batch; i += gridDim.x * blockDim.x) {
+        if (skip[i] != -1) continue;
+        double e = 0.0;
+        for (int rr = 0; rr < nrhs; rr++) {
+            const double *nm = norms + ((size_t)i * nrhs + rr) * 3;
+            const double den = anorm[i] * nm[1] + nm[2];
+            e = fmax(e, den > 0.0 ? nm[0] / den : 0.0);
+        }
+        eta[i] = e;
+        if (e <= tol) skip[i] = 1;
+    }
+}
+
+int launch_residual_batched(int n, int nrhs, int batch, int64_t nnzA, const int *Acp, const int *Acj,
+                            const int *Acsrc, const double *Aval, const double *x, const double *b, double *r,
+                            double *norms, const int *skip, void *stream) {
+    hipLaunchKernelGGL(residual_batched_kernel, dim3(grid_for((int64_t)n * batch, 256)), dim3(256), 0,
+                       (hipStream_t)stream, n, nrhs, batch, nnzA, Acp, Acj, Acsrc, Aval, x, b, r, norms, skip);
+    return (int)hipGetLastError();
+}
+
+int launch_anorm_batched(int n, int batch, int64_t nnzA, const int *Acp, const int *Acsrc, const double *Aval,
+                         double *out, void *stream) {
+    hipLaunchKernelGGL(anorm_batched_kernel, dim3(grid_for((int64_t)n * batch, 256)), dim3(256), 0,
+                       (hipStream_t)stream, n, batch, nnzA, Acp, Acsrc, Aval, out);
+    return (int)hipGetLastError();
+}
+
+int launch_ir_check(int batch, int nrhs, const double *norms, const double *anorm, double tol, int *skip,
+                    double *eta, void *stream) {
+    hipLaunchKernelGGL(ir_check_kernel, dim3(grid_for(batch, 256)), dim3(256), 0, (hipStream_t)stream, batch, nrhs,
+                       norms, anorm, tol, skip, eta);
+    return (int)hipGetLastError();
+}
+
+__global__ void copy_i32_kernel(const int *src, int *dst, int64_t count) {
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < count; i += (int64_t)gridDim.x * blockDim.x)
+        dst[i] = src[i];
+}
+
+int launch_copy_i32(const int *src, int *dst, int64_t count, void *stream) {
+    hipLaunchKernelGGL(copy_i32_kernel, dim3(grid_for(count, 256)), dim3(256), 0, (hipStream_t)stream, src, dst, count);
+    return (int)hipGetLastError();
+}
+
+__global__ void fill_f64_kernel(double *dst, int64_t count, double value) {
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < count; i += (int64_t)gridDim.x * blockDim.x)
+        dst[i] = value;
+}
+
+int launch_fill_f64(double *dst, int64_t count, double value, void *stream) {
+    hipLaunchKernelGGL(fill_f64_kernel, dim3(grid_for(count, 256)), dim3(256), 0, (hipStream_t)stream, dst, count,
+                       value);
+    return (int)hipGetLastError();
+}
+
 __global__ void copy_f64_kernel(const double *src, double *dst, int64_t count) {
     for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < count; i += (int64_t)gridDim.x * blockDim.x)
         dst[i] = src[i];

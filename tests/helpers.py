@@ -46,3 +46,41 @@ def oracle_refactor(oracle_mod, c, values, an, eps, prev_pivrow):
     """The oracle's re-factorization: same pre-processing, previous pivot sequence."""
     return oracle_mod.gp_lu(c.n, c.colptr, c.rowind, values, an["rowperm_pre"], an["colperm"], eps,
                             init_pivrow=prev_pivrow)
+
+
+def compare_factors_sampled(f, lu, rtol, nsample=4000, seed=0):
+    """compare_factors for large factors: patterns compared in full (bit-exact),
+    values on nsample random entries of L and of U, each scaled by its own
+    (|L||U|)(i,k) = sum_j |L(i,j)| |U(j,k)|, formed from row i of L and column k
+    of U only."""
+    assert np.array_equal(f["Lp"], lu.Lp), "L column pointers differ"
+    assert np.array_equal(f["Li"], lu.Li), "L pattern differs"
+    assert np.array_equal(f["Up"], lu.Up), "U column pointers differ"
+    assert np.array_equal(f["Ui"], lu.Ui), "U pattern differs"
+    n = lu.n
+    rng = np.random.default_rng(seed)
+    # |L| with its unit diagonal, by rows; |U| by columns
+    Lr = (sp.csc_matrix((np.abs(lu.Lx), lu.Li, lu.Lp), shape=(n, n)) + sp.identity(n, format="csc")).tocsr()
+    Lr.sort_indices()
+    diag = lu.Ux[lu.Up[1:] - 1]
+
+    def scale(i, k):
+        cj = Lr.indices[Lr.indptr[i]:Lr.indptr[i + 1]]
+        cv = Lr.data[Lr.indptr[i]:Lr.indptr[i + 1]]
+        rj = lu.Ui[lu.Up[k]:lu.Up[k + 1]]
+        rv = np.abs(lu.Ux[lu.Up[k]:lu.Up[k + 1]])
+        _, a, b = np.intersect1d(cj, rj, assume_unique=True, return_indices=True)
+        return float((cv[a] * rv[b]).sum())
+
+    worst = 0.0
+    for Ap, Ai, Ax, Fx, is_l in ((lu.Up, lu.Ui, lu.Ux, f["Ux"], False), (lu.Lp, lu.Li, lu.Lx, f["Lx"], True)):
+        m = int(Ap[-1])
+        if m == 0:
+            continue
+        cols = np.repeat(np.arange(n), np.diff(Ap))
+        for q in rng.choice(m, size=min(nsample, m), replace=False):
+            i, k = int(Ai[q]), int(cols[q])
+            sc = scale(i, k) / (abs(diag[k]) if is_l else 1.0)
+            worst = max(worst, abs(Fx[q] - Ax[q]) / max(sc, np.finfo(float).tiny))
+    assert worst <= rtol, f"factor values differ: scaled error {worst:.3e} > {rtol:.1e}"
+    return worst
