@@ -219,6 +219,27 @@ int cktlu_refactorize_batched(cktlu_ctx *ctx, int32_t batch, const double *value
 int cktlu_solve_batched(cktlu_ctx *ctx, int32_t batch, int32_t nrhs, const double *b_dev,
                         double *x_dev, const int32_t *status_dev, double *eta_dev);
 
+/*
+ * One Newton-Raphson step of many same-pattern instances (Monte-Carlo corners)
+ * as a single captured HIP graph: the refactorization of cktlu_refactorize_batched
+ * (status_dev as there) followed by the solve of cktlu_solve_batched for nrhs
+ * right-hand sides (b_dev, x_dev as there).  FP64: a plain solve.  FP32_IR:
+ * FP32 factors and exactly ir_steps FP64 refinement steps (>= 1) decided on the
+ * device, each instance leaving once its eta_inf reaches ir_tol; eta_dev
+ * (device, double[batch], may be NULL) receives each instance's last eta_inf
+ * (-1 for instances that failed the pivot test, and in FP64 mode).  No host
+ * synchronisation: the caller reads status and eta afterwards and handles the
+ * instances that failed the pivot test or did not reach ir_tol (for instance
+ * with cktlu_solve_batched).  The graph is captured on the first call and
+ * replayed while batch, nrhs, ir_steps and every pointer stay the same and the
+ * library's device buffers have not moved; otherwise it is captured again (the
+ * capture synchronises the context's stream).  Errors: E_STATE, E_ARG, E_LIMIT,
+ * E_NOMEM, E_HIP.
+ */
+int cktlu_step_batched_graph(cktlu_ctx *ctx, int32_t batch, const double *values_dev, int32_t *status_dev,
+                             int32_t nrhs, const double *b_dev, double *x_dev, double *eta_dev,
+                             int32_t ir_steps);
+
 /* Permutations (host out, int32[n] each): A(rowperm[k], colperm[j]) is the
  * (k, j) entry of the matrix that was factored, rowperm including pivoting. */
 int cktlu_get_perm(const cktlu_ctx *ctx, int32_t *rowperm, int32_t *colperm);

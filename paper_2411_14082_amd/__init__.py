@@ -39,6 +39,7 @@ EXPORTS = [
     "cktlu_default_options", "cktlu_create", "cktlu_destroy", "cktlu_strerror", "cktlu_set_stream",
     "cktlu_analyze", "cktlu_factorize", "cktlu_factorize_host", "cktlu_refactorize",
     "cktlu_refactorize_nocheck", "cktlu_solve", "cktlu_refactorize_batched", "cktlu_solve_batched",
+    "cktlu_step_batched_graph",
     "cktlu_get_perm", "cktlu_get_analysis", "cktlu_get_factor_nnz", "cktlu_get_factors",
     "cktlu_get_levels", "cktlu_get_stats", "cktlu_get_timing", "cktlu_footprint_bytes",
 ]
@@ -111,6 +112,7 @@ def _load():
     lib.cktlu_solve.argtypes = [P, I32, P, I32, P, I32, ctypes.POINTER(cktlu_solve_info)]
     lib.cktlu_refactorize_batched.argtypes = [P, I32, P, P]
     lib.cktlu_solve_batched.argtypes = [P, I32, I32, P, P, P, P]
+    lib.cktlu_step_batched_graph.argtypes = [P, I32, P, P, I32, P, P, P, I32]
     lib.cktlu_get_perm.argtypes = [P, P, P]
     lib.cktlu_get_analysis.argtypes = [P, P, P, P, P]
     lib.cktlu_get_factor_nnz.argtypes = [P, P, P]
@@ -211,6 +213,11 @@ def cktlu_refactorize_batched(ctx, batch, values_dev, status_dev):
 def cktlu_solve_batched(ctx, batch, nrhs, b_dev, x_dev, status_dev, eta_dev=None):
     return lib.cktlu_solve_batched(ctx, int(batch), int(nrhs), _ptr(b_dev), _ptr(x_dev), _ptr(status_dev),
                                    _ptr(eta_dev))
+
+
+def cktlu_step_batched_graph(ctx, batch, values_dev, status_dev, nrhs, b_dev, x_dev, eta_dev=None, ir_steps=2):
+    return lib.cktlu_step_batched_graph(ctx, int(batch), _ptr(values_dev), _ptr(status_dev), int(nrhs), _ptr(b_dev),
+                                        _ptr(x_dev), _ptr(eta_dev), int(ir_steps))
 
 
 def cktlu_get_perm(ctx, rowperm, colperm):
@@ -320,6 +327,10 @@ class SparseLU:
     def solve_batched(self, batch, nrhs, b_dev, x_dev, status_dev, eta_dev=None):
         return _check(cktlu_solve_batched(self.ctx, batch, nrhs, b_dev, x_dev, status_dev, eta_dev),
                       "cktlu_solve_batched")
+
+    def step_batched_graph(self, batch, values_dev, status_dev, nrhs, b_dev, x_dev, eta_dev=None, ir_steps=2):
+        return _check(cktlu_step_batched_graph(self.ctx, batch, values_dev, status_dev, nrhs, b_dev, x_dev, eta_dev,
+                                               ir_steps), "cktlu_step_batched_graph")
 
     def analysis(self, with_pivots=True):
         n = self.n

@@ -32,6 +32,20 @@ struct cktlu_ctx {
     std::vector<Pending> pending;
     std::vector<hipEvent_t> event_pool;
     cktlu_timing timing_acc;
+    // captured batched step (cktlu_step_batched_graph): replayed while its key holds
+    struct GraphKey {
+        int batch = 0, nrhs = 0, ir_steps = 0;
+        const void *values = nullptr, *b = nullptr;
+        void *status = nullptr, *x = nullptr, *eta = nullptr;
+        uint64_t gen = 0;
+        bool operator==(const GraphKey &o) const {
+            return batch == o.batch && nrhs == o.nrhs && ir_steps == o.ir_steps && values == o.values &&
+                   b == o.b && status == o.status && x == o.x && eta == o.eta && gen == o.gen;
+        }
+    } graph_key;
+    hipGraphExec_t graph_exec = nullptr;
+    hipStream_t capture_stream = nullptr;
+    uint64_t buffers_gen = 1;      // bumped whenever device buffers may have moved
 };
 
 namespace {
@@ -183,6 +197,7 @@ void unpad_values(const cktlu_ctx *c, const double *padded, double *compact) {
 int ensure_batch(cktlu_ctx *c, int batch) {
     Device &d = c->dev;
     if (d.batch_cap >= batch) return CKTLU_OK;
+    c->buffers_gen++;                 // captured graphs hold the old pointers
     const int n = c->an.n;
     const int64_t F = nnzF(c);
     hipStream_t st = stream_of(c);
@@ -222,6 +237,7 @@ int ensure_batch(cktlu_ctx *c, int batch) {
 // Upload pattern, schedule and the host factor values (instance 0).
 int upload_all(cktlu_ctx *c) {
     Device &d = c->dev;
+    c->buffers_gen++;
     const Schedule &s = c->s;
     hipStream_t st = stream_of(c);
     int rc;
@@ -525,6 +541,7 @@ int refactor_single(cktlu_ctx *c, const double *values_dev, cktlu_refactor_info 
 
 int ensure_vec(cktlu_ctx *c, size_t doubles) {
     if (c->dev.vec_cap >= doubles) return CKTLU_OK;
+    c->buffers_gen++;
     int rc = dalloc(c->dev.vec, doubles * sizeof(double));
     if (rc) return rc;
     c->dev.vec_cap = doubles;
@@ -686,6 +703,8 @@ void cktlu_destroy(cktlu_ctx *c) {
     if (!c->pending.empty()) (void)hipStreamSynchronize(stream_of(c));
     for (auto &p : c->pending) { (void)hipEventDestroy(p.a); (void)hipEventDestroy(p.b); }
     for (hipEvent_t e : c->event_pool) (void)hipEventDestroy(e);
+    if (c->graph_exec) (void)hipGraphExecDestroy(c->graph_exec);
+    if (c->capture_stream) (void)hipStreamDestroy(c->capture_stream);
     free_device(c->dev);
     delete c;
 }
@@ -791,6 +810,96 @@ int cktlu_solve(cktlu_ctx *c, int32_t nrhs, const double *b, int32_t ldb, double
     c->stats.n_fp64_fallback_solves++;
     if (info) info->used_fp64 = 1;
     return CKTLU_W_IR_FALLBACK;
+}
+
+int cktlu_step_batched_graph(cktlu_ctx *c, int32_t batch, const double *values_dev, int32_t *status_dev,
+                             int32_t nrhs, const double *b, double *x, double *eta_dev, int32_t ir_steps) {
+    if (!c || batch < 1 || !values_dev || !status_dev || nrhs < 1 || nrhs > 8 || !b || !x) return CKTLU_E_ARG;
+    const bool fp32 = c->opt.precision == CKTLU_FP32_IR;
+    if (fp32 && ir_steps < 1) return CKTLU_E_ARG;
+    if (c->state < 2) return CKTLU_E_STATE;
+    if ((int64_t)batch * c->an.n >= INT_MAX) return CKTLU_E_LIMIT;
+    int rc = ensure_device(c);
+    if (rc) return rc;
+    if ((rc = ensure_batch(c, batch))) return rc;
+    const int n = c->an.n;
+    const int64_t nnzA = c->an.nnz;
+    const size_t nv = (size_t)n * nrhs * batch;
+    const size_t zd = (size_t)n * YS * batch + 64;
+    if ((rc = ensure_vec(c, zd + nv + 3 * (size_t)nrhs * batch + 3 * (size_t)batch + 64))) return rc;
+    // the dense block must hold factors of the precision the solve reads (set by the refactorization)
+    cktlu_ctx::GraphKey key;
+    key.batch = batch; key.nrhs = nrhs; key.ir_steps = fp32 ? ir_steps : 0;
+    key.values = values_dev; key.b = b; key.status = status_dev; key.x = x; key.eta = eta_dev;
+    key.gen = c->buffers_gen;
+    hipStream_t user = stream_of(c);
+    if (!c->graph_exec || !(key == c->graph_key)) {
+        if (c->graph_exec) { (void)hipGraphExecDestroy(c->graph_exec); c->graph_exec = nullptr; }
+        if (!c->capture_stream) HIPCHK(hipStreamCreateWithFlags(&c->capture_stream, hipStreamNonBlocking));
+        // everything below is enqueued on the capture stream and recorded, not run
+        HIPCHK(hipStreamSynchronize(user));
+        void *saved_stream = c->opt.stream;
+        const int saved_timing = c->opt.timing;
+        c->opt.stream = c->capture_stream;
+        c->opt.timing = 0;
+        hipStream_t st = c->capture_stream;
+        HIPCHK(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
+        auto body = [&]() -> int {
+            double *z = (double *)c->dev.vec.p;
+            double *r = z + zd;
+            double *norms = r + nv;
+            double *anorm = norms + 3 * (size_t)nrhs * batch;
+            double *eta = anorm + batch;
+            int *skip = (int *)(eta + batch);
+            const int *rowperm = (const int *)c->dev.rowperm.p, *colperm = (const int *)c->dev.colperm_sol.p;
+            LCHK(launch_copy_f64(values_dev, (double *)c->dev.Aval.p, nnzA * (int64_t)batch, st));
+            int e = run_refactor(c, batch, values_dev, fp32, true, -1);
+            if (e) return e;
+            LCHK(launch_status_out((const int *)c->dev.ctrl.p + 1 + batch, status_dev, batch, st));
+            if (!fp32) {
+                LCHK(launch_gather_rhs(n, nrhs, batch, b, n, rowperm, z, st));
+                if ((e = tri_solves(c, nrhs, batch, z, false, status_dev))) return e;
+                LCHK(launch_scatter_sol(n, nrhs, batch, z, colperm, x, n, 0, status_dev, st));
+                if (eta_dev) LCHK(launch_fill_f64(eta_dev, batch, -1.0, st));
+                return CKTLU_OK;
+            }
+            // FP32 factors, ir_steps FP64 refinement steps decided on the device
+            const int *Acp = (const int *)c->dev.Acp.p, *Acj = (const int *)c->dev.Acj.p;
+            const int *Acsrc = (const int *)c->dev.Acsrc.p;
+            const double *Aval = (const double *)c->dev.Aval.p;
+            LCHK(launch_fill_f64(x, (int64_t)nv, 0.0, st));
+            LCHK(launch_fill_f64(anorm, batch, 0.0, st));
+            LCHK(launch_fill_f64(eta, batch, -1.0, st));
+            LCHK(launch_anorm_batched(n, batch, nnzA, Acp, Acsrc, Aval, anorm, st));
+            LCHK(launch_copy_i32(status_dev, skip, batch, st));
+            for (int it = 1; it <= ir_steps; it++) {
+                LCHK(launch_gather_rhs(n, nrhs, batch, it == 1 ? b : r, n, rowperm, z, st));
+                if ((e = tri_solves(c, nrhs, batch, z, true, skip))) return e;
+                LCHK(launch_scatter_sol(n, nrhs, batch, z, colperm, x, n, 1, skip, st));
+                LCHK(launch_fill_f64(norms, 3 * (int64_t)nrhs * batch, 0.0, st));
+                LCHK(launch_residual_batched(n, nrhs, batch, nnzA, Acp, Acj, Acsrc, Aval, x, b, r, norms, skip, st));
+                LCHK(launch_ir_check(batch, nrhs, norms, anorm, c->opt.ir_tol, skip, eta, st));
+            }
+            if (eta_dev) LCHK(launch_copy_f64(eta, eta_dev, batch, st));
+            return CKTLU_OK;
+        };
+        const int brc = body();
+        hipGraph_t graph = nullptr;
+        const hipError_t ec = hipStreamEndCapture(st, &graph);
+        c->opt.stream = saved_stream;
+        c->opt.timing = saved_timing;
+        if (brc) { if (graph) (void)hipGraphDestroy(graph); return brc; }
+        if (ec != hipSuccess || !graph) { debug_hip((int)ec, "hipStreamEndCapture", __LINE__); return CKTLU_E_HIP; }
+        const hipError_t ei = hipGraphInstantiate(&c->graph_exec, graph, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(graph);
+        if (ei != hipSuccess) { c->graph_exec = nullptr; debug_hip((int)ei, "hipGraphInstantiate", __LINE__); return CKTLU_E_HIP; }
+        c->graph_key = key;
+    }
+    HIPCHK(hipGraphLaunch(c->graph_exec, user));
+    c->last_batch = batch;
+    c->stats.n_refactorize += batch;
+    c->dev_values_newer = true;
+    return CKTLU_OK;
 }
 
 int cktlu_refactorize_batched(cktlu_ctx *c, int32_t batch, const double *values_dev, int32_t *status_dev) {
