@@ -30,7 +30,79 @@ WORKLOADS = {
                                 desc="mesh 141x141 + transistor stamps"),
     "mesh_vsrc_32": dict(make=lambda: __import__("mnagen").mesh_vsrc(32, 32, 4, seed=0), cfg=1,
                          desc="mesh 32x32 + 4 ideal voltage sources"),
+    "corners_141_x256": dict(make=lambda: __import__("mnagen").mesh_transistor(141, 141, seed=0), cfg=3,
+                             batch=256, desc="256 corners of mesh 141x141 + transistor stamps, lognormal(0.3)"),
 }
+
+
+def run_batched(ck, torch, c, batch, steps, warmup, precision, graph, tail_opts):
+    """Batched NR steps: every step refactorizes all instances (new values in the same
+    buffer) and solves one right-hand side each; eager calls or one captured graph."""
+    import mnagen
+    s = ck.SparseLU(c.n, c.colptr, c.rowind, eps=1e-3, precision=precision, ir_tol=1e-10,
+                    **{k: v for k, v in tail_opts.items() if k != "autotune"})
+    dev = torch.device("cuda:0")
+    s.factorize(torch.tensor(c.values, device=dev))
+    nsets = 4
+    sets = [torch.tensor(mnagen.instance_values(c, batch, 0.3, seed=10 + i), device=dev) for i in range(nsets)]
+    tuned = s.autotune(batch, sets[0], reps=2) if tail_opts.get("autotune") else None
+    if tuned:
+        log("autotune:", tuned)
+    vals = torch.empty_like(sets[0])
+    status = torch.zeros(batch, dtype=torch.int32, device=dev)
+    B = torch.tensor(np.repeat(c.rhs[:1][None], batch, axis=0), device=dev)
+    X = torch.zeros_like(B)
+    eta = torch.zeros(batch, dtype=torch.float64, device=dev)
+
+    def step(t):
+        vals.copy_(sets[t % nsets])
+        if graph:
+            s.step_batched_graph(batch, vals, status, 1, B, X, eta, ir_steps=2)
+        else:
+            s.refactorize_batched(batch, vals, status)
+            s.solve_batched(batch, 1, B, X, status, eta)
+    for w in range(warmup):
+        step(w)
+    torch.cuda.synchronize()
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(steps)]
+    w0 = time.time()
+    for t in range(steps):
+        ev[t][0].record()
+        step(warmup + t)
+        ev[t][1].record()
+    torch.cuda.synchronize()
+    wall = time.time() - w0
+    ms = np.array([a.elapsed_time(b) for a, b in ev])
+    st = status.cpu().numpy()
+    e = eta.cpu().numpy()
+    s.close()
+    return dict(instance_steps_per_s=batch * steps / wall, p50_ms=float(np.percentile(ms, 50)),
+                p99_ms=float(np.percentile(ms, 99)), failed=int((st != -1).sum()),
+                eta_max=float(e[st == -1].max()) if precision == ck.CKTLU_FP32_IR else None,
+                dense_tail=tuned["best_dense_tail"] if tuned else None)
+
+
+def main_batched(args, wl):
+    import torch
+    import paper_2411_14082_amd as ck
+    c = wl["make"]()
+    batch = wl["batch"]
+    tail_opts = dict(dense_tail=args.dense_tail, dense_tail_density=args.dense_density, autotune=args.autotune)
+    legs = {}
+    for name, prec, graph in (("fp64_eager", ck.CKTLU_FP64, False), ("fp64_graph", ck.CKTLU_FP64, True),
+                              ("fp32_ir_eager", ck.CKTLU_FP32_IR, False), ("fp32_ir_graph", ck.CKTLU_FP32_IR, True)):
+        legs[name] = run_batched(ck, torch, c, batch, args.steps, args.warmup, prec, graph, tail_opts)
+        log(name, legs[name])
+    best = legs["fp64_graph"]
+    line = {
+        "metric": "NR refactor+solve steps/sec + p50/p99 step latency, FP32+IR vs FP64, 1 GPU",
+        "value": best["instance_steps_per_s"], "unit": "instance-steps/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": best["p50_ms"], "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": wl["desc"], "n": c.n, "nnz": c.nnz, "batch": batch},
+        "legs": legs,
+    }
+    print(json.dumps(line), flush=True)
 HBM_PEAK_GBS = 8000.0
 FP64_MFMA_PEAK_TFS = 78.6
 FP32_MFMA_PEAK_TFS = 157.3
@@ -66,10 +138,12 @@ def log(*a):
 
 def run_leg(ck, torch, c, vals_dev, b_dev, precision, steps, warmup, tail_opts):
     s = ck.SparseLU(c.n, c.colptr, c.rowind, eps=1e-3, precision=precision, ir_tol=1e-10, timing=True,
-                    **tail_opts)
+                    **{k: v for k, v in tail_opts.items() if k != "autotune"})
     t0 = time.time()
     s.factorize(vals_dev[0])
     t_setup = time.time() - t0
+    if tail_opts.get("autotune"):
+        log("autotune:", s.autotune(1, vals_dev[0], reps=2))
     x = torch.zeros_like(b_dev)
     nrep = 0
     for w in range(warmup):
@@ -134,6 +208,8 @@ def main():
                     help="order of the dense trailing block: 0 automatic (default), -1 none, >0 forced")
     ap.add_argument("--dense-density", type=float, default=None,
                     help="fill density threshold of the automatic dense-block choice")
+    ap.add_argument("--autotune", action="store_true",
+                    help="measure the dense-block candidates on the device first and keep the fastest")
     ap.add_argument("--perturb", default="element", choices=["element", "nonzero"],
                     help="element: every circuit element x U[0.95,1.05], re-assembled (NR re-stamping); "
                          "nonzero: every assembled nonzero x U[0.95,1.05] (pivot stress)")
@@ -149,6 +225,8 @@ def main():
     import paper_2411_14082_amd as ck
 
     wl = WORKLOADS[args.workload]
+    if "batch" in wl:
+        return main_batched(args, wl)
     t0 = time.time()
     c = wl["make"]()
     log("workload %s n=%d nnz=%d (%.1fs)" % (args.workload, c.n, c.nnz, time.time() - t0))
@@ -163,7 +241,7 @@ def main():
     b_dev = torch.tensor(b, device=dev)
     torch.cuda.synchronize()
 
-    tail_opts = dict(dense_tail=args.dense_tail, dense_tail_density=args.dense_density)
+    tail_opts = dict(dense_tail=args.dense_tail, dense_tail_density=args.dense_density, autotune=args.autotune)
     res64 = run_leg(ck, torch, c, vals_dev, b_dev, ck.CKTLU_FP64, args.steps, args.warmup, tail_opts)
     log("fp64: %.3f steps/s, refactor %.2f ms, solve %.2f ms (setup %.1fs), dense tail %d" %
         (args.steps / res64["wall"], res64["ref_ms"].mean(), res64["sol_ms"].mean(), res64["setup_s"],

@@ -240,6 +240,30 @@ int cktlu_step_batched_graph(cktlu_ctx *ctx, int32_t batch, const double *values
                              int32_t nrhs, const double *b_dev, double *x_dev, double *eta_dev,
                              int32_t ir_steps);
 
+/* Result of cktlu_autotune. */
+typedef struct {
+    int32_t n_tried;              /* schedules measured */
+    int32_t dense_tail[16];       /* order D of the dense trailing block of each (0 = none) */
+    double ms_per_step[16];       /* device time of one refactorization + solve of `batch` instances */
+    int32_t best;                 /* index of the fastest, now in use */
+} cktlu_tune_result;
+
+/*
+ * Schedule autotuner (the dense-part threshold the paper fixes for its CPUs,
+ * Section V-A, chosen here by measurement on the device): for each candidate
+ * order D of the dense trailing block (none, the density rule at 0.5, 0.3 and
+ * 0.2, and D = 512, 1024, 2048, 4096, 8192 up to n; duplicates skipped) the
+ * schedule is rebuilt and uploaded, and `reps` steps are timed with HIP events
+ * on the context's stream, a step being the refactorization of `batch`
+ * instances (values_dev: batch x nnz, as cktlu_refactorize_batched; batch 1
+ * uses cktlu_refactorize) plus a solve of one right-hand side each.  The
+ * fastest schedule stays in use (options.dense_tail_size is set to it).
+ * The factors on the device are those of the last timed step.  Errors:
+ * E_STATE, E_ARG, E_NOMEM, E_HIP.
+ */
+int cktlu_autotune(cktlu_ctx *ctx, int32_t batch, const double *values_dev, int32_t reps,
+                   cktlu_tune_result *out);
+
 /* Permutations (host out, int32[n] each): A(rowperm[k], colperm[j]) is the
  * (k, j) entry of the matrix that was factored, rowperm including pivoting. */
 int cktlu_get_perm(const cktlu_ctx *ctx, int32_t *rowperm, int32_t *colperm);

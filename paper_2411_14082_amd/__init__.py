@@ -39,7 +39,7 @@ EXPORTS = [
     "cktlu_default_options", "cktlu_create", "cktlu_destroy", "cktlu_strerror", "cktlu_set_stream",
     "cktlu_analyze", "cktlu_factorize", "cktlu_factorize_host", "cktlu_refactorize",
     "cktlu_refactorize_nocheck", "cktlu_solve", "cktlu_refactorize_batched", "cktlu_solve_batched",
-    "cktlu_step_batched_graph",
+    "cktlu_step_batched_graph", "cktlu_autotune",
     "cktlu_get_perm", "cktlu_get_analysis", "cktlu_get_factor_nnz", "cktlu_get_factors",
     "cktlu_get_levels", "cktlu_get_stats", "cktlu_get_timing", "cktlu_footprint_bytes",
 ]
@@ -78,6 +78,11 @@ class cktlu_stats(ctypes.Structure):
         return {f: getattr(self, f) for f, _ in self._fields_}
 
 
+class cktlu_tune_result(ctypes.Structure):
+    _fields_ = [("n_tried", ctypes.c_int32), ("dense_tail", ctypes.c_int32 * 16),
+                ("ms_per_step", ctypes.c_double * 16), ("best", ctypes.c_int32)]
+
+
 class cktlu_timing(ctypes.Structure):
     _fields_ = [("init_ms", ctypes.c_double), ("sweep_ms", ctypes.c_double), ("dense_ms", ctypes.c_double),
                 ("solve_sparse_ms", ctypes.c_double), ("solve_dense_ms", ctypes.c_double),
@@ -113,6 +118,7 @@ def _load():
     lib.cktlu_refactorize_batched.argtypes = [P, I32, P, P]
     lib.cktlu_solve_batched.argtypes = [P, I32, I32, P, P, P, P]
     lib.cktlu_step_batched_graph.argtypes = [P, I32, P, P, I32, P, P, P, I32]
+    lib.cktlu_autotune.argtypes = [P, I32, P, I32, ctypes.POINTER(cktlu_tune_result)]
     lib.cktlu_get_perm.argtypes = [P, P, P]
     lib.cktlu_get_analysis.argtypes = [P, P, P, P, P]
     lib.cktlu_get_factor_nnz.argtypes = [P, P, P]
@@ -218,6 +224,10 @@ def cktlu_solve_batched(ctx, batch, nrhs, b_dev, x_dev, status_dev, eta_dev=None
 def cktlu_step_batched_graph(ctx, batch, values_dev, status_dev, nrhs, b_dev, x_dev, eta_dev=None, ir_steps=2):
     return lib.cktlu_step_batched_graph(ctx, int(batch), _ptr(values_dev), _ptr(status_dev), int(nrhs), _ptr(b_dev),
                                         _ptr(x_dev), _ptr(eta_dev), int(ir_steps))
+
+
+def cktlu_autotune(ctx, batch, values_dev, reps, out: cktlu_tune_result):
+    return lib.cktlu_autotune(ctx, int(batch), _ptr(values_dev), int(reps), ctypes.byref(out))
 
 
 def cktlu_get_perm(ctx, rowperm, colperm):
@@ -331,6 +341,13 @@ class SparseLU:
     def step_batched_graph(self, batch, values_dev, status_dev, nrhs, b_dev, x_dev, eta_dev=None, ir_steps=2):
         return _check(cktlu_step_batched_graph(self.ctx, batch, values_dev, status_dev, nrhs, b_dev, x_dev, eta_dev,
                                                ir_steps), "cktlu_step_batched_graph")
+
+    def autotune(self, batch, values_dev, reps=3) -> dict:
+        r = cktlu_tune_result()
+        _check(cktlu_autotune(self.ctx, batch, values_dev, reps, r), "cktlu_autotune")
+        k = r.n_tried
+        return dict(dense_tail=list(r.dense_tail[:k]), ms_per_step=list(r.ms_per_step[:k]), best=r.best,
+                    best_dense_tail=r.dense_tail[r.best])
 
     def analysis(self, with_pivots=True):
         n = self.n

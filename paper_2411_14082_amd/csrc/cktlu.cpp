@@ -902,6 +902,92 @@ int cktlu_step_batched_graph(cktlu_ctx *c, int32_t batch, const double *values_d
     return CKTLU_OK;
 }
 
+int cktlu_autotune(cktlu_ctx *c, int32_t batch, const double *values_dev, int32_t reps, cktlu_tune_result *out) {
+    if (!c || !out || batch < 1 || reps < 1 || !values_dev) return CKTLU_E_ARG;
+    if (c->state < 2) return CKTLU_E_STATE;
+    std::memset(out, 0, sizeof(*out));
+    const int n = c->an.n;
+    struct Cand { int size; double density; };
+    std::vector<Cand> cands = {{-1, 0.3}, {0, 0.5}, {0, 0.3}, {0, 0.2}};
+    for (int d = 512; d <= 8192 && d <= n; d *= 2) cands.push_back({d, 0.3});
+    const cktlu_options saved = c->opt;
+    c->opt.timing = 0;
+    hipStream_t st = stream_of(c);
+    // work buffers: one right-hand side of ones per instance, solutions, status
+    DevBuf rhs, sol, status;
+    auto release = [&]() { dfree(rhs); dfree(sol); dfree(status); };
+    if (dalloc(rhs, (size_t)n * batch * sizeof(double)) || dalloc(sol, (size_t)n * batch * sizeof(double)) ||
+        dalloc(status, (size_t)batch * sizeof(int))) {
+        release();
+        return CKTLU_E_NOMEM;
+    }
+    if (launch_fill_f64((double *)rhs.p, (int64_t)n * batch, 1.0, st)) { release(); return CKTLU_E_HIP; }
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
+        if (e0) (void)hipEventDestroy(e0);
+        release();
+        return CKTLU_E_HIP;
+    }
+    auto step = [&]() -> int {
+        int rc;
+        if (batch == 1) {
+            rc = refactor_single(c, values_dev, nullptr, true);
+            if (rc < 0) return rc;
+            rc = cktlu_solve(c, 1, (const double *)rhs.p, n, (double *)sol.p, n, nullptr);
+            return rc < 0 ? rc : CKTLU_OK;
+        }
+        if ((rc = cktlu_refactorize_batched(c, batch, values_dev, (int *)status.p))) return rc;
+        rc = cktlu_solve_batched(c, batch, 1, (const double *)rhs.p, (double *)sol.p, (const int *)status.p, nullptr);
+        return rc < 0 ? rc : CKTLU_OK;
+    };
+    int rc = CKTLU_OK;
+    std::vector<int> seen;
+    double best_ms = INFINITY;
+    int best_size = saved.dense_tail_size;
+    double best_density = saved.dense_tail_density;
+    for (const Cand &cd : cands) {
+        if (out->n_tried >= 16) break;
+        c->opt.dense_tail_size = cd.size;
+        c->opt.dense_tail_density = cd.density;
+        Schedule trial;
+        build_schedule(c->an, c->f, c->opt, trial);
+        const int D = n - trial.tail0;
+        if (std::find(seen.begin(), seen.end(), D) != seen.end()) continue;
+        seen.push_back(D);
+        c->s = std::move(trial);
+        fill_stats_pattern(c);
+        if ((rc = upload_all(c))) break;
+        if ((rc = step())) break;                          // warm-up
+        HIPCHK(hipEventRecord(e0, st));
+        for (int r = 0; r < reps && !rc; r++) rc = step();
+        if (rc) break;
+        HIPCHK(hipEventRecord(e1, st));
+        HIPCHK(hipEventSynchronize(e1));
+        float ms = 0.f;
+        HIPCHK(hipEventElapsedTime(&ms, e0, e1));
+        const int k = out->n_tried++;
+        out->dense_tail[k] = D;
+        out->ms_per_step[k] = ms / reps;
+        if (ms / reps < best_ms) {
+            best_ms = ms / reps;
+            out->best = k;
+            best_size = D > 0 ? D : -1;
+            best_density = cd.density;
+        }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    release();
+    c->opt = saved;
+    if (rc) return rc;
+    // keep the fastest schedule
+    c->opt.dense_tail_size = best_size;
+    c->opt.dense_tail_density = best_density;
+    build_schedule(c->an, c->f, c->opt, c->s);
+    fill_stats_pattern(c);
+    return upload_all(c);
+}
+
 int cktlu_refactorize_batched(cktlu_ctx *c, int32_t batch, const double *values_dev, int32_t *status_dev) {
     if (!c || batch < 1 || !values_dev || !status_dev) return CKTLU_E_ARG;
     if (c->state < 2) return CKTLU_E_STATE;

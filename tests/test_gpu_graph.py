@@ -73,3 +73,26 @@ def test_graph_step_replays_match_eager(ck, oracle_mod, precision, tail):
             assert np.allclose(Xh[ok], Xe[ok], rtol=1e-9, atol=0)
     g.close()
     e.close()
+
+
+@pytest.mark.parametrize("batch", [1, 8])
+def test_autotune_keeps_fastest_schedule_and_results(ck, oracle_mod, batch):
+    """The autotuner measures several dense-block orders, keeps the fastest, and
+    the factors and solutions with the tuned schedule still meet the gates."""
+    c = mnagen.mesh_transistor(60, 60, seed=17)
+    s = ck.SparseLU(c.n, c.colptr, c.rowind, eps=EPS)
+    s.factorize(dev(c.values))
+    V = mnagen.instance_values(c, batch, 0.2, seed=17)
+    r = s.autotune(batch, dev(V if batch > 1 else V[0]), reps=2)
+    assert len(r["dense_tail"]) >= 3 and len(set(r["dense_tail"])) == len(r["dense_tail"])
+    assert r["ms_per_step"][r["best"]] == min(r["ms_per_step"])
+    assert s.stats()["dense_tail"] == r["best_dense_tail"]
+    status = torch.zeros(batch, dtype=torch.int32, device="cuda:0")
+    s.refactorize_batched(batch, dev(V), status)
+    B = np.repeat(c.rhs[:1][None], batch, axis=0)
+    X = torch.zeros((batch, 1, c.n), dtype=torch.float64, device="cuda:0")
+    s.solve_batched(batch, 1, dev(B), X, status)
+    torch.cuda.synchronize()
+    st, Xh = status.cpu().numpy(), X.cpu().numpy()
+    for i in np.flatnonzero(st == -1):
+        assert oracle_mod.backward_error(c.colptr, c.rowind, V[i], Xh[i, 0], B[i, 0]) <= 1e-12
