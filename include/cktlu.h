@@ -300,6 +300,64 @@ int cktlu_get_timing(cktlu_ctx *ctx, cktlu_timing *out, int reset);
  * add (for admission control). */
 size_t cktlu_footprint_bytes(const cktlu_ctx *ctx, int32_t batch);
 
+/* ------------------------------------------------------------------------
+ * Request loop (continuous serving of Newton-Raphson sequences).
+ * A server owns `slots` worker threads, each with a HIP stream of default
+ * priority.  Requests are taken in submission order; each is analysed and
+ * factored on the host (cktlu_analyze, cktlu_factorize_host with its first
+ * step's values), admitted once cktlu_footprint_bytes of it fits the HBM budget
+ * next to the requests already resident (a request larger than the budget runs
+ * alone), runs its steps (cktlu_refactorize + cktlu_solve per step) on its
+ * slot's stream, so the work of different requests overlaps on the device, and
+ * releases its memory.  A request computes exactly what a single context
+ * would, whatever else is in the mix.  For callers that serve many circuits.
+ * ---------------------------------------------------------------------- */
+typedef struct cktlu_server cktlu_server;
+
+typedef struct {
+    int slots;                /* requests on the device at once (worker threads); default 4, 1..64 */
+    double hbm_budget_bytes;  /* device bytes the resident requests may use together;
+                                 0 (default) = 80% of the free HBM at creation */
+    cktlu_options lu;         /* options of every request (precision, eps, ...); stream and timing ignored */
+} cktlu_server_options;
+
+typedef struct {
+    int32_t n;                /* order of the circuit matrix */
+    const int32_t *colptr;    /* host CSC pattern, colptr[n+1] and rowind[colptr[n]]; copied by submit */
+    const int32_t *rowind;
+    int32_t nsteps;           /* Newton-Raphson steps */
+    const double *values_dev; /* device, nsteps x nnz: values of step t at t * nnz (caller-owned) */
+    const double *b_dev;      /* device, n: right-hand side of every step */
+    double *x_dev;            /* device, nsteps x n: solution of step t at t * n (written) */
+    double arrival_s;         /* arrival time on the server clock (cktlu_server_now), for latencies */
+    int64_t tag;              /* caller's identifier, returned with the completion */
+} cktlu_request;
+
+typedef struct {
+    int64_t tag;
+    int status;               /* 0, the first warning of its calls, or the first error (then it stopped) */
+    double arrival_s;         /* server clock: arrival, taken by a slot, admitted to the device, finished */
+    double start_s, admit_s, end_s;
+    int32_t repivots;         /* steps whose pivot check failed (re-pivoted by the fallback) */
+    int32_t fp64_fallbacks;   /* FP32_IR solves that fell back to FP64 */
+    double backward_err;      /* FP32_IR: eta_inf of the last solve; -1 otherwise */
+    size_t footprint;         /* device bytes it was admitted with */
+} cktlu_request_done;
+
+void cktlu_server_default_options(cktlu_server_options *opt);
+/* Start the worker threads on the current HIP device.  Errors: E_ARG, E_NOMEM, E_HIP. */
+int cktlu_server_create(cktlu_server **out, const cktlu_server_options *opt);
+/* Queue a request (non-blocking).  Its device buffers must stay valid until its
+ * completion is polled.  Errors: E_ARG, E_STATE (server stopping). */
+int cktlu_server_submit(cktlu_server *srv, const cktlu_request *req);
+/* Move up to max completions into out, waiting up to wait_ms for the first;
+ * returns how many (>= 0) or E_ARG. */
+int cktlu_server_poll(cktlu_server *srv, cktlu_request_done *out, int32_t max, int32_t wait_ms);
+/* Seconds since the server was created (steady clock). */
+double cktlu_server_now(const cktlu_server *srv);
+/* Finish every queued request, stop the workers and release the server.  NULL is ignored. */
+void cktlu_server_destroy(cktlu_server *srv);
+
 #ifdef __cplusplus
 }
 #endif

@@ -25,7 +25,7 @@ import scipy.sparse as sp
 __all__ = [
     "Circuit", "assemble", "mesh_vsrc", "layered_rc", "mesh_transistor",
     "power_grid", "perturb", "restamp", "instance_values", "Stamping", "random_rhs", "step_rng",
-    "random_pattern", "hand_pattern", "random_values", "serving_mix",
+    "random_pattern", "hand_pattern", "random_values", "serving_mix", "mix_circuit",
     "CONFIGS",
 ]
 
@@ -336,6 +336,21 @@ def serving_mix(n_requests, seed=0, nmin=1000, nmax=200_000):
     ns = np.exp(rng.uniform(np.log(nmin), np.log(nmax), n_requests))
     kinds = rng.integers(0, 3, n_requests)
     return [(int(k), int(v)) for k, v in zip(kinds, ns)]
+
+
+def mix_circuit(kind, n, seed=0) -> Circuit:
+    """A circuit of the serving mix with about n unknowns: kind 0 a mesh with
+    ideal voltage sources, 1 a three-layer RC mesh, 2 a mesh with transistor
+    stamps, 3 a power grid."""
+    side = max(8, int(round(np.sqrt(n))))
+    if kind == 0:
+        return mesh_vsrc(side, side, 4, seed)
+    if kind == 1:
+        s3 = max(6, int(round(np.sqrt(n / 3.0))))
+        return layered_rc(s3, s3, 3, seed=seed)
+    if kind == 2:
+        return mesh_transistor(side, side, seed=seed)
+    return power_grid(side, side, n_src=max(10, n // 1000), nrhs=1, seed=seed)
 
 
 # Configurations: name -> factory(seed) at full size, and a reduced size that the

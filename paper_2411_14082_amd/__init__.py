@@ -40,6 +40,8 @@ EXPORTS = [
     "cktlu_analyze", "cktlu_factorize", "cktlu_factorize_host", "cktlu_refactorize",
     "cktlu_refactorize_nocheck", "cktlu_solve", "cktlu_refactorize_batched", "cktlu_solve_batched",
     "cktlu_step_batched_graph", "cktlu_autotune",
+    "cktlu_server_default_options", "cktlu_server_create", "cktlu_server_submit", "cktlu_server_poll",
+    "cktlu_server_now", "cktlu_server_destroy",
     "cktlu_get_perm", "cktlu_get_analysis", "cktlu_get_factor_nnz", "cktlu_get_factors",
     "cktlu_get_levels", "cktlu_get_stats", "cktlu_get_timing", "cktlu_footprint_bytes",
 ]
@@ -83,6 +85,26 @@ class cktlu_tune_result(ctypes.Structure):
                 ("ms_per_step", ctypes.c_double * 16), ("best", ctypes.c_int32)]
 
 
+class cktlu_server_options(ctypes.Structure):
+    _fields_ = [("slots", ctypes.c_int), ("hbm_budget_bytes", ctypes.c_double), ("lu", cktlu_options)]
+
+
+class cktlu_request(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int32), ("colptr", ctypes.c_void_p), ("rowind", ctypes.c_void_p),
+                ("nsteps", ctypes.c_int32), ("values_dev", ctypes.c_void_p), ("b_dev", ctypes.c_void_p),
+                ("x_dev", ctypes.c_void_p), ("arrival_s", ctypes.c_double), ("tag", ctypes.c_int64)]
+
+
+class cktlu_request_done(ctypes.Structure):
+    _fields_ = [("tag", ctypes.c_int64), ("status", ctypes.c_int), ("arrival_s", ctypes.c_double),
+                ("start_s", ctypes.c_double), ("admit_s", ctypes.c_double), ("end_s", ctypes.c_double),
+                ("repivots", ctypes.c_int32), ("fp64_fallbacks", ctypes.c_int32),
+                ("backward_err", ctypes.c_double), ("footprint", ctypes.c_size_t)]
+
+    def as_dict(self):
+        return {f: getattr(self, f) for f, _ in self._fields_}
+
+
 class cktlu_timing(ctypes.Structure):
     _fields_ = [("init_ms", ctypes.c_double), ("sweep_ms", ctypes.c_double), ("dense_ms", ctypes.c_double),
                 ("solve_sparse_ms", ctypes.c_double), ("solve_dense_ms", ctypes.c_double),
@@ -119,6 +141,15 @@ def _load():
     lib.cktlu_solve_batched.argtypes = [P, I32, I32, P, P, P, P]
     lib.cktlu_step_batched_graph.argtypes = [P, I32, P, P, I32, P, P, P, I32]
     lib.cktlu_autotune.argtypes = [P, I32, P, I32, ctypes.POINTER(cktlu_tune_result)]
+    lib.cktlu_server_default_options.argtypes = [ctypes.POINTER(cktlu_server_options)]
+    lib.cktlu_server_default_options.restype = None
+    lib.cktlu_server_create.argtypes = [ctypes.POINTER(P), ctypes.POINTER(cktlu_server_options)]
+    lib.cktlu_server_submit.argtypes = [P, ctypes.POINTER(cktlu_request)]
+    lib.cktlu_server_poll.argtypes = [P, ctypes.POINTER(cktlu_request_done), I32, I32]
+    lib.cktlu_server_now.argtypes = [P]
+    lib.cktlu_server_now.restype = ctypes.c_double
+    lib.cktlu_server_destroy.argtypes = [P]
+    lib.cktlu_server_destroy.restype = None
     lib.cktlu_get_perm.argtypes = [P, P, P]
     lib.cktlu_get_analysis.argtypes = [P, P, P, P, P]
     lib.cktlu_get_factor_nnz.argtypes = [P, P, P]
@@ -228,6 +259,75 @@ def cktlu_step_batched_graph(ctx, batch, values_dev, status_dev, nrhs, b_dev, x_
 
 def cktlu_autotune(ctx, batch, values_dev, reps, out: cktlu_tune_result):
     return lib.cktlu_autotune(ctx, int(batch), _ptr(values_dev), int(reps), ctypes.byref(out))
+
+
+def cktlu_server_default_options() -> cktlu_server_options:
+    o = cktlu_server_options()
+    lib.cktlu_server_default_options(ctypes.byref(o))
+    return o
+
+
+def cktlu_server_create(opt: cktlu_server_options | None = None):
+    h = ctypes.c_void_p()
+    _check(lib.cktlu_server_create(ctypes.byref(h), ctypes.byref(opt) if opt is not None else None),
+           "cktlu_server_create")
+    return h
+
+
+def cktlu_server_submit(srv, req: cktlu_request):
+    return lib.cktlu_server_submit(srv, ctypes.byref(req))
+
+
+def cktlu_server_poll(srv, max_done=64, wait_ms=0):
+    buf = (cktlu_request_done * max(1, max_done))()
+    k = _check(lib.cktlu_server_poll(srv, buf, int(max_done), int(wait_ms)), "cktlu_server_poll")
+    return [buf[i].as_dict() for i in range(k)]
+
+
+def cktlu_server_now(srv) -> float:
+    return float(lib.cktlu_server_now(srv))
+
+
+def cktlu_server_destroy(srv):
+    lib.cktlu_server_destroy(srv)
+
+
+class Server:
+    """Request loop over the C server: submit(circuit pattern + device buffers), poll()."""
+
+    def __init__(self, slots=4, hbm_budget_bytes=0.0, precision=CKTLU_FP64, eps=1e-3, ir_tol=1e-10):
+        o = cktlu_server_default_options()
+        o.slots = int(slots)
+        o.hbm_budget_bytes = float(hbm_budget_bytes)
+        o.lu.precision = precision
+        o.lu.pivot_eps = eps
+        o.lu.ir_tol = ir_tol
+        self.h = cktlu_server_create(o)
+        self._keep = {}
+
+    def now(self):
+        return cktlu_server_now(self.h)
+
+    def submit(self, tag, n, colptr, rowind, nsteps, values_dev, b_dev, x_dev, arrival_s=None):
+        cp = np.ascontiguousarray(colptr, dtype=np.int32)
+        ri = np.ascontiguousarray(rowind, dtype=np.int32)
+        r = cktlu_request(n=int(n), colptr=cp.ctypes.data, rowind=ri.ctypes.data, nsteps=int(nsteps),
+                          values_dev=_ptr(values_dev), b_dev=_ptr(b_dev), x_dev=_ptr(x_dev),
+                          arrival_s=self.now() if arrival_s is None else float(arrival_s), tag=int(tag))
+        self._keep[int(tag)] = (values_dev, b_dev, x_dev)
+        _check(cktlu_server_submit(self.h, r), "cktlu_server_submit")
+
+    def poll(self, wait_ms=0, max_done=64):
+        out = cktlu_server_poll(self.h, max_done, wait_ms)
+        for d in out:
+            self._keep.pop(d["tag"], None)
+        return out
+
+    def close(self):
+        if self.h:
+            cktlu_server_destroy(self.h)
+            self.h = None
+            self._keep.clear()
 
 
 def cktlu_get_perm(ctx, rowperm, colperm):

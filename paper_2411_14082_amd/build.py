@@ -10,7 +10,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libcktlu.so")
 
-HOST_SOURCES = ["cktlu.cpp", "analyze.cpp", "factor_host.cpp", "schedule.cpp"]
+HOST_SOURCES = ["cktlu.cpp", "analyze.cpp", "factor_host.cpp", "schedule.cpp", "server.cpp"]
 DEVICE_SOURCES = ["kernels.hip", "dense.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"
@@ -38,11 +38,11 @@ def build(verbose: bool = False) -> str:
         objs.append(obj)
     for src in HOST_SOURCES:
         obj = os.path.join(objdir, src + ".o")
-        _run([HIPCC, "-c", "-x", "c++", *COMMON, "-D__HIP_PLATFORM_AMD__", "-I", "/opt/rocm/include", "-o", obj,
+        _run([HIPCC, "-c", "-x", "c++", *COMMON, "-pthread", "-D__HIP_PLATFORM_AMD__", "-I", "/opt/rocm/include", "-o", obj,
               os.path.join(CSRC, src)])
         objs.append(obj)
     tmp = LIB + ".tmp%d" % os.getpid()
-    _run([HIPCC, "-shared", f"--offload-arch={ARCH}", "-o", tmp, *objs])
+    _run([HIPCC, "-shared", "-pthread", f"--offload-arch={ARCH}", "-o", tmp, *objs])
     os.replace(tmp, LIB)
     if verbose:
         print("built", LIB)
