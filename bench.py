@@ -30,6 +30,8 @@ WORKLOADS = {
                                 desc="mesh 141x141 + transistor stamps"),
     "mesh_vsrc_32": dict(make=lambda: __import__("mnagen").mesh_vsrc(32, 32, 4, seed=0), cfg=1,
                          desc="mesh 32x32 + 4 ideal voltage sources"),
+    "serving_mix": dict(make=None, cfg=5, serving=True,
+                        desc="Poisson arrivals of circuits n ~ logU[1k, 200k], 20 NR steps each"),
     "corners_141_x256": dict(make=lambda: __import__("mnagen").mesh_transistor(141, 141, seed=0), cfg=3,
                              batch=256, desc="256 corners of mesh 141x141 + transistor stamps, lognormal(0.3)"),
 }
@@ -80,6 +82,69 @@ def run_batched(ck, torch, c, batch, steps, warmup, precision, graph, tail_opts)
                 p99_ms=float(np.percentile(ms, 99)), failed=int((st != -1).sum()),
                 eta_max=float(e[st == -1].max()) if precision == ck.CKTLU_FP32_IR else None,
                 dense_tail=tuned["best_dense_tail"] if tuned else None)
+
+
+def main_serving(args, wl):
+    """Request loop: capacity with every request queued at once, then Poisson arrivals at
+    0.7 of that capacity; request latency = completion - arrival (host setup included)."""
+    import torch
+    import mnagen
+    import paper_2411_14082_amd as ck
+    nreq, nsteps = args.requests, 20
+    mix = mnagen.serving_mix(nreq, seed=0)
+    dev = torch.device("cuda:0")
+    reqs = []
+    for tag, (kind, n) in enumerate(mix):
+        c = mnagen.mix_circuit(kind, n, seed=tag)
+        vals = torch.tensor(np.stack([mnagen.restamp(c, tag, 5, t) for t in range(nsteps)]), device=dev)
+        reqs.append((tag, c, vals, torch.tensor(c.rhs[0], device=dev)))
+    log("serving mix: %d requests, n from %d to %d" % (nreq, min(r[1].n for r in reqs), max(r[1].n for r in reqs)))
+
+    def serve(precision, rate):
+        srv = ck.Server(slots=args.slots, precision=precision)
+        xs = [torch.zeros((nsteps, c.n), dtype=torch.float64, device=dev) for _, c, _, _ in reqs]
+        rng = np.random.default_rng(1)
+        arrivals = np.cumsum(rng.exponential(1.0 / rate, nreq)) if rate else np.zeros(nreq)
+        t0 = srv.now()
+        done, k = [], 0
+        while len(done) < nreq:
+            now = srv.now() - t0
+            while k < nreq and arrivals[k] <= now:
+                tag, c, vals, b = reqs[k]
+                srv.submit(tag, c.n, c.colptr, c.rowind, nsteps, vals, b, xs[k], arrival_s=t0 + arrivals[k])
+                k += 1
+            wait = 5 if k < nreq else 200
+            done += srv.poll(wait_ms=wait)
+        srv.close()
+        span = max(d["end_s"] for d in done) - t0
+        lat = np.array([d["end_s"] - d["arrival_s"] for d in done])
+        gpu = np.array([d["end_s"] - d["admit_s"] for d in done])
+        bad = [d for d in done if d["status"] < 0]
+        return dict(requests=nreq, span_s=span, requests_per_s=nreq / span, steps_per_s=nreq * nsteps / span,
+                    p50_latency_s=float(np.percentile(lat, 50)), p99_latency_s=float(np.percentile(lat, 99)),
+                    p50_device_s=float(np.percentile(gpu, 50)), p99_device_s=float(np.percentile(gpu, 99)),
+                    errors=len(bad), repivots=int(sum(d["repivots"] for d in done)),
+                    fp64_fallbacks=int(sum(d["fp64_fallbacks"] for d in done)))
+
+    legs = {}
+    for name, prec in (("fp64", ck.CKTLU_FP64), ("fp32_ir", ck.CKTLU_FP32_IR)):
+        cap = serve(prec, None)
+        log(name, "capacity", cap)
+        rate = 0.7 * cap["requests_per_s"]
+        run = serve(prec, rate)
+        run["offered_requests_per_s"] = rate
+        log(name, "poisson", run)
+        legs[name] = dict(capacity=cap, poisson_0_7=run)
+    best = legs["fp64"]["poisson_0_7"]
+    line = {
+        "metric": "NR refactor+solve steps/sec + p50/p99 step latency, FP32+IR vs FP64, 1 GPU",
+        "value": best["steps_per_s"], "unit": "steps/s", "n_gpus": 1, "steps": nsteps, "warmup": 0,
+        "ms_per_step": 1e3 / best["steps_per_s"], "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": wl["desc"], "requests": nreq, "slots": args.slots},
+        "legs": legs,
+    }
+    print(json.dumps(line), flush=True)
 
 
 def main_batched(args, wl):
@@ -208,6 +273,8 @@ def main():
                     help="order of the dense trailing block: 0 automatic (default), -1 none, >0 forced")
     ap.add_argument("--dense-density", type=float, default=None,
                     help="fill density threshold of the automatic dense-block choice")
+    ap.add_argument("--requests", type=int, default=16, help="serving_mix: number of requests")
+    ap.add_argument("--slots", type=int, default=4, help="serving_mix: requests on the device at once")
     ap.add_argument("--autotune", action="store_true",
                     help="measure the dense-block candidates on the device first and keep the fastest")
     ap.add_argument("--perturb", default="element", choices=["element", "nonzero"],
@@ -227,6 +294,8 @@ def main():
     wl = WORKLOADS[args.workload]
     if "batch" in wl:
         return main_batched(args, wl)
+    if wl.get("serving"):
+        return main_serving(args, wl)
     t0 = time.time()
     c = wl["make"]()
     log("workload %s n=%d nnz=%d (%.1fs)" % (args.workload, c.n, c.nnz, time.time() - t0))

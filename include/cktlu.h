@@ -185,8 +185,12 @@ int cktlu_refactorize_nocheck(cktlu_ctx *ctx, const double *values_dev);
  * x_dev: device, column r at x_dev + r*ldx (ldx >= n); b and x must not
  * overlap.  In FP32_IR mode the residual, the update and the stopping test run
  * in FP64 against the values of the last refactorization (backward error
- * eta_inf <= ir_tol), falling back to FP64 factors when refinement stalls.
- * info may be NULL.  Errors: E_STATE, E_ARG, E_HIP.
+ * eta_inf <= ir_tol), falling back to FP64 factors when refinement stalls
+ * (W_IR_FALLBACK).  After such a fallback the context keeps FP64 factors for
+ * its refactorizations and solves (info->used_fp64 = 1) until the next
+ * cktlu_factorize: a circuit too ill-conditioned for FP32 factors stays so
+ * while its values move by NR steps.  info may be NULL.  Errors: E_STATE,
+ * E_ARG, E_HIP.
  */
 int cktlu_solve(cktlu_ctx *ctx, int32_t nrhs, const double *b_dev, int32_t ldb,
                 double *x_dev, int32_t ldx, cktlu_solve_info *info);

@@ -24,6 +24,7 @@ struct cktlu_ctx {
     Device dev;
     cktlu_stats stats;
     bool dev_values_newer = false; // device factors hold values newer than f.Fx
+    bool fp64_sticky = false;      // FP32_IR: refinement fell back; FP64 until the next factorize
     int force_fail_pending = -1;
     int last_batch = 0;            // batch of the last batched refactorization
     double anorm_host = 0.0;
@@ -509,7 +510,7 @@ int refactor_single(cktlu_ctx *c, const double *values_dev, cktlu_refactor_info 
     if ((rc = ensure_batch(c, 1))) return rc;
     Device &d = c->dev;
     hipStream_t st = stream_of(c);
-    const bool fp32 = c->opt.precision == CKTLU_FP32_IR;
+    const bool fp32 = c->opt.precision == CKTLU_FP32_IR && !c->fp64_sticky;
     const int force = check ? c->force_fail_pending : -1;
     c->force_fail_pending = -1;
     // keep a copy of the values for residuals of iterative refinement
@@ -747,6 +748,7 @@ int cktlu_factorize_host(cktlu_ctx *c, const double *values_host) {
     if (!c || (!values_host && c->an.nnz > 0)) return CKTLU_E_ARG;
     if (c->state < 1) return CKTLU_E_STATE;
     c->f.pivrow.clear();
+    c->fp64_sticky = false;
     int rc = factor_and_setup(c, values_host, nullptr, false);
     if (rc == CKTLU_OK) c->stats.n_factorize++;
     return rc;
@@ -762,6 +764,7 @@ int cktlu_factorize(cktlu_ctx *c, const double *values_dev) {
         HIPCHK(hipStreamSynchronize(st));
     }
     c->f.pivrow.clear();
+    c->fp64_sticky = false;
     int rc = factor_and_setup(c, v.data(), nullptr, true);
     if (rc != CKTLU_OK) return rc;
     c->stats.n_factorize++;
@@ -790,6 +793,10 @@ int cktlu_solve(cktlu_ctx *c, int32_t nrhs, const double *b, int32_t ldb, double
     int rc = ensure_device(c);
     if (rc) return rc;
     if (c->opt.precision == CKTLU_FP64) return solve_plain(c, nrhs, b, ldb, x, ldx, false, false);
+    if (c->fp64_sticky) {                  // refinement failed on this circuit before: FP64 factors
+        if (info) info->used_fp64 = 1;
+        return solve_plain(c, nrhs, b, ldb, x, ldx, false, false);
+    }
     // FP32 factors + FP64 refinement
     hipStream_t st = stream_of(c);
     if ((rc = ensure_vec(c, vec_need(c, nrhs)))) return rc;
@@ -808,6 +815,7 @@ int cktlu_solve(cktlu_ctx *c, int32_t nrhs, const double *b, int32_t ldb, double
     if ((rc = run_refactor(c, 1, (const double *)c->dev.Aval.p, false, false, -1))) return rc;
     if ((rc = solve_plain(c, nrhs, b, ldb, x, ldx, false, false))) return rc;
     c->stats.n_fp64_fallback_solves++;
+    c->fp64_sticky = true;
     if (info) info->used_fp64 = 1;
     return CKTLU_W_IR_FALLBACK;
 }
