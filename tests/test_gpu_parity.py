@@ -389,3 +389,28 @@ def test_batched_many_instances_dense_block(ck, oracle_mod):
                 assert np.array_equal(fb["Lx"], fs["Lx"]) and np.array_equal(fb["Ux"], fs["Ux"]), i
                 checked += 1
     assert checked >= 4
+
+
+def test_fp32_ir_fallback_then_fp64(ck, oracle_mod):
+    """Refinement that cannot reach its target (ir_tol below FP64 rounding) falls
+    back to FP64 factors (W_IR_FALLBACK); the context then stays on FP64 factors
+    for the next steps, whose solves meet the FP64 gate, until factorize."""
+    c = mnagen.mesh_transistor(40, 40, seed=18)
+    s = ck.SparseLU(c.n, c.colptr, c.rowind, eps=EPS, precision=ck.CKTLU_FP32_IR, ir_tol=1e-30, ir_max_iter=3)
+    s.factorize(dev(c.values))
+    b = c.rhs[0]
+    for t in (1, 2):
+        v = mnagen.restamp(c, 18, 0, t)
+        s.refactorize(dev(v))
+        x = torch.zeros(c.n, dtype=torch.float64, device="cuda:0")
+        rc, info = s.solve(dev(b), x)
+        torch.cuda.synchronize()
+        assert info.used_fp64 == 1
+        assert rc == (ck.CKTLU_W_IR_FALLBACK if t == 1 else 0)
+        assert oracle_mod.backward_error(c.colptr, c.rowind, v, x.cpu().numpy(), b) <= 1e-12
+    assert s.stats()["n_fp64_fallback_solves"] == 1
+    s.factorize(dev(c.values))                     # back to FP32 factors
+    s.refactorize(dev(c.values))
+    x = torch.zeros(c.n, dtype=torch.float64, device="cuda:0")
+    rc, info = s.solve(dev(b), x)
+    assert info.used_fp64 == 1 and rc == ck.CKTLU_W_IR_FALLBACK   # the target is still out of reach
