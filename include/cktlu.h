@@ -100,6 +100,7 @@ typedef struct {
                                          gathered, target read and written) + 24 per L entry of a
                                          sparse column (pivot test read, division read and write) */
     double flops_dense;               /* FLOPs of the dense trailing block's LU (2/3 D^3 + lower order) */
+    double macs_schur;                /* multiply-adds of the dense block's update by the sparse columns */
     int64_t sweep_launches;           /* kernel launches of one sparse sweep */
     int64_t dense_launches;           /* kernel launches of one dense-block factorization */
     int64_t solve_launches;           /* kernel launches of one triangular solve pass (L and U) */

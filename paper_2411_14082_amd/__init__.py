@@ -73,7 +73,7 @@ class cktlu_stats(ctypes.Structure):
                 ("n_restart_cols", ctypes.c_int64), ("n_fp64_fallback_solves", ctypes.c_int64),
                 ("bytes_refactor", ctypes.c_double), ("bytes_solve", ctypes.c_double),
                 ("macs_sweep", ctypes.c_double), ("bytes_sweep", ctypes.c_double),
-                ("flops_dense", ctypes.c_double), ("sweep_launches", ctypes.c_int64),
+                ("flops_dense", ctypes.c_double), ("macs_schur", ctypes.c_double), ("sweep_launches", ctypes.c_int64),
                 ("dense_launches", ctypes.c_int64), ("solve_launches", ctypes.c_int64)]
 
     def as_dict(self):

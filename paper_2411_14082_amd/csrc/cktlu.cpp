@@ -160,7 +160,7 @@ int upload(DevBuf &b, const std::vector<V> &v, hipStream_t st) {
 
 DevBuf *all_buffers(Device &d, int i) {
     DevBuf *all[] = {&d.seq, &d.Dp, &d.Dlen, &d.Fi, &d.nU, &d.Ap, &d.colperm, &d.amap, &d.colrec, &d.task8,
-                     &d.item4, &d.lrec, &d.urec,
+                     &d.item4, &d.tail_nb, &d.l21, &d.lrec, &d.urec,
                      &d.Lrjs, &d.Urjs, &d.rowperm,
                      &d.colperm_sol, &d.Acp, &d.Acj, &d.Acsrc, &d.Fx64, &d.Fx32, &d.Aval, &d.done,
                      &d.ctrl, &d.vec, &d.S, &d.Dg};
@@ -252,6 +252,8 @@ int upload_all(cktlu_ctx *c) {
     if ((rc = upload(d.amap, s.amap, st))) return rc;
     if ((rc = upload(d.colrec, s.colrec, st))) return rc;
     if ((rc = upload(d.task8, s.task8, st))) return rc;
+    if ((rc = upload(d.tail_nb, s.tail_nb, st))) return rc;
+    if ((rc = upload(d.l21, s.l21, st))) return rc;
     if ((rc = upload(d.item4, s.item4, st))) return rc;
     if ((rc = upload(d.lrec, s.lrec, st))) return rc;
     if ((rc = upload(d.urec, s.urec, st))) return rc;
@@ -300,6 +302,7 @@ void fill_stats_pattern(cktlu_ctx *c) {
     t.bytes_solve = (4.0 + fb) * nF + 24.0 * (double)t.n;
     const Schedule &s = c->s;
     t.macs_sweep = s.macs_sweep;
+    t.macs_schur = s.macs_schur;
     t.bytes_sweep = 28.0 * s.macs_sweep + 24.0 * s.lnz_front;
     const double D = (double)(c->an.n - s.tail0);
     t.flops_dense = 2.0 / 3.0 * D * D * D + D * D / 2.0;
@@ -455,6 +458,7 @@ int run_refactor(cktlu_ctx *c, int batch, const double *values_dev, bool fp32, b
         da.force_fail_col = force_col;
         da.check = a.check;
         t0 = phase_begin(c);
+        LCHK(launch_schur(da, (const int *)d.tail_nb.p, (const int *)d.l21.p, st));
         LCHK(launch_dense_refactor(da, false, st));
         phase_end(c, t0, PH_DENSE, (int)c->stats.dense_launches);
         d.S_prec = fp32 ? 1 : 0;

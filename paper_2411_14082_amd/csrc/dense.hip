@@ -113,6 +113,85 @@ __global__ __launch_bounds__(256) void tail_scatter_kernel(DenseArgs a) {
     if (lane == 0 && k < a.ctrl[1 + a.batch + inst]) a.done[(size_t)inst * a.n + k] = (int)a.epoch;
 }
 
+// ------------------------------------------------------------- Schur update
+// S(:, c) -= sum over the bridge rows j of dense column T + c (its U entries in rows
+// < T, ascending) of L(rows >= T, j) U(j, T + c): the sparse columns' contribution to
+// the dense block, applied after the sweep (all of L21 and U12 final).  One wavefront
+// per (dense column, instance) applies the sources in ascending order: deterministic,
+// no atomics.  The L entries of four sources (up to 256 each) are loaded before
+// any of them is applied, and each source reads all its targets before storing.
+// IN_LDS: the column accumulates in LDS (D values), else in place.
+template <typename T, bool IN_LDS>
+__global__ __launch_bounds__(64) void schur_kernel(DenseArgs a, const int *tail_nb, const int *l21) {
+    extern __shared__ char schur_smem[];
+    constexpr int G = 4, CH = 4;                      // sources per group, 64-entry chunks loaded ahead
+    const int lane = threadIdx.x;
+    const int inst = (int)(blockIdx.x % (unsigned)a.batch), c = (int)(blockIdx.x / (unsigned)a.batch);
+    if (sweep_failed(a, inst)) return;
+    T *Sc = inst_S<T>(a, inst) + (size_t)c * a.D;
+    T *col = IN_LDS ? reinterpret_cast<T *>(schur_smem) : Sc;
+    if (IN_LDS) {
+        for (int i0 = 0; i0 < a.D; i0 += 4 * WAVE) {
+            T v[4];
+#pragma unroll
+            for (int u = 0; u < 4; u++) v[u] = i0 + u * WAVE + lane < a.D ? Sc[i0 + u * WAVE + lane] : T(0);
+#pragma unroll
+            for (int u = 0; u < 4; u++)
+                if (i0 + u * WAVE + lane < a.D) col[i0 + u * WAVE + lane] = v[u];
+        }
+        __syncthreads();
+    }
+    const T *Fx = reinterpret_cast<const T *>(a.Fx) + (size_t)inst * a.nnzF;
+    const int k = a.T + c;
+    const int bb = a.Dp[k], nb = tail_nb[c];
+    for (int s0 = 0; s0 < nb; s0 += WAVE) {
+        int rb = 0, re = 0;
+        T u = T(0);
+        if (s0 + lane < nb) {
+            const int j = a.Fi[bb + s0 + lane];
+            u = Fx[bb + s0 + lane];                       // U(j, k)
+            rb = l21[2 * j];
+            re = l21[2 * j + 1];
+        }
+        const int ns = min(WAVE, nb - s0);
+        for (int t = 0; t < ns; t += G) {
+            int rr[G][CH], beg[G], end[G];
+            T vv[G][CH], ug[G];
+#pragma unroll
+            for (int g = 0; g < G; g++) {
+                const int src = min(t + g, WAVE - 1);
+                beg[g] = __shfl(rb, src);
+                end[g] = t + g < ns ? __shfl(re, src) : beg[g];
+                ug[g] = __shfl(u, src);
+#pragma unroll
+                for (int h = 0; h < CH; h++) {
+                    const int q = beg[g] + h * WAVE + lane;
+                    rr[g][h] = q < end[g] ? a.Fi[q] : -1;
+                    vv[g][h] = q < end[g] ? Fx[q] : T(0);
+                }
+            }
+#pragma unroll
+            for (int g = 0; g < G; g++) {
+                // one source: its rows are distinct, so all its targets are read before any store
+                T tv[CH];
+#pragma unroll
+                for (int h = 0; h < CH; h++) tv[h] = rr[g][h] >= 0 ? col[rr[g][h] - a.T] : T(0);
+#pragma unroll
+                for (int h = 0; h < CH; h++)
+                    if (rr[g][h] >= 0) col[rr[g][h] - a.T] = tv[h] - vv[g][h] * ug[g];
+                for (int q0 = beg[g] + CH * WAVE; q0 < end[g]; q0 += WAVE) {   // very long sources
+                    const int q = q0 + lane;
+                    if (q < end[g]) col[a.Fi[q] - a.T] -= Fx[q] * ug[g];
+                }
+            }
+        }
+    }
+    if (IN_LDS) {
+        __syncthreads();
+        for (int i = lane; i < a.D; i += WAVE) Sc[i] = col[i];
+    }
+}
+
 // ------------------------------------------------------------- blocked LU
 __device__ __forceinline__ double readlane(double v, int l) {
     const long long b = __double_as_longlong(v);
@@ -519,6 +598,16 @@ int launch_dense_gather(const DenseArgs &a, void *stream) {
     const dim3 gw = wave_grid((int64_t)a.D * a.batch);
     if (a.fp32) hipLaunchKernelGGL((tail_gather_kernel<float>), gw, dim3(256), 0, st, a);
     else hipLaunchKernelGGL((tail_gather_kernel<double>), gw, dim3(256), 0, st, a);
+    return (int)hipGetLastError();
+}
+
+int launch_schur(const DenseArgs &a, const int *tail_nb, const int *l21, void *stream) {
+    hipStream_t st = (hipStream_t)stream;
+    if (a.D <= 0 || a.T <= 0) return 0;
+    // in place: a column in LDS limits the resident wavefronts more than the L2 traffic costs
+    const dim3 grid((unsigned)((int64_t)a.D * a.batch));
+    if (a.fp32) hipLaunchKernelGGL((schur_kernel<float, false>), grid, dim3(64), 0, st, a, tail_nb, l21);
+    else hipLaunchKernelGGL((schur_kernel<double, false>), grid, dim3(64), 0, st, a, tail_nb, l21);
     return (int)hipGetLastError();
 }
 

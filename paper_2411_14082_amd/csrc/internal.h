@@ -88,6 +88,9 @@ struct Schedule {
     int max_col = 0;                          // longest column of F
     double macs = 0, flops = 0;
     double macs_sweep = 0, lnz_front = 0;     // MACs of the update tasks; L entries of sparse columns
+    double macs_schur = 0;                    // MACs of the dense block's Schur update (S -= L21 U12)
+    std::vector<int> tail_nb;                 // per dense column: its U entries in rows < T (the bridge)
+    std::vector<int> l21;                     // per sparse column: device range of its L rows >= T
     int tail0 = 0;                            // first column of the densely factored tail (n = none)
     std::vector<int> tail_rend;               // rows i >= tail0: L entries of columns < tail0 end here
     std::vector<int> lrec, urec, Lrjs, Urjs;  // the solve levels packed for the device
@@ -106,7 +109,7 @@ struct Device {
     int batch_cap = 0;                 // instances the value buffers hold
     // pattern / schedule
     DevBuf seq, Dp, Dlen, Fi, nU, Ap, colperm, amap;
-    DevBuf colrec, task8, item4;
+    DevBuf colrec, task8, item4, tail_nb, l21;
     DevBuf lrec, urec, Lrjs, Urjs, rowperm, colperm_sol;
     DevBuf Acp, Acj, Acsrc;
     // values and status words
@@ -217,6 +220,8 @@ struct DenseArgs {
 };
 // S <- rows >= T of the tail columns of Fx (zeros elsewhere)
 int launch_dense_gather(const DenseArgs &a, void *stream);
+// S -= L21 U12: the sparse columns' contributions to the dense block, after the sweep
+int launch_schur(const DenseArgs &a, const int *tail_nb, const int *l21, void *stream);
 // (gather if asked), blocked LU with the pivot test, scatter back into Fx
 int launch_dense_refactor(const DenseArgs &a, bool gather, void *stream);
 // y rows [T, n): lower (unit) or upper triangular solve with the block in S

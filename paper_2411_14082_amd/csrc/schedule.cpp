@@ -133,12 +133,21 @@ void build_schedule(const Analysis &an, const Factor &f, const cktlu_options &op
         s.lvl_ptr.assign(c.begin(), c.end());
         s.seq.resize(T);
         for (int k = 0; k < T; k++) s.seq[c[rlev[k]]++] = k;
+        // L entries of each sparse column in rows < T (they come first: rows ascend)
+        std::vector<int> lo_cnt(T, 0);
+        for (int j = 0; j < T; j++) {
+            const int *b = f.Fi.data() + f.Fp[j] + f.nU[j], *e = f.Fi.data() + f.Fp[j + 1];
+            lo_cnt[j] = (int)(std::lower_bound(b, e, T) - b);
+        }
+        // an item (j -> k) of a dense-block target updates only its rows < T (the rest is the
+        // Schur update of the dense block, applied after the sweep); it exists if there are any
+        auto keep = [&](int j, int k) { return k < T || lo_cnt[j] > 0; };
         // update tasks: items (j -> k) for U(j,k) != 0, j < min(k, T), in (rlevel(j), k, j)
         // order by a stable counting sort over the level (k and j ascend in column order)
         std::vector<int64_t> bucket(nl + 1, 0);
         for (int k = 0; k < n; k++)
             for (int64_t q = f.Fp[k]; q < f.Fp[k] + f.nU[k] - 1 && f.Fi[q] < T; q++)
-                bucket[rlev[f.Fi[q]] + 1]++;
+                if (keep(f.Fi[q], k)) bucket[rlev[f.Fi[q]] + 1]++;
         for (int l = 0; l < nl; l++) bucket[l + 1] += bucket[l];
         const int64_t nitems = bucket[nl];
         std::vector<int> it_k(nitems), it_j(nitems), it_slot(nitems);
@@ -146,6 +155,7 @@ void build_schedule(const Analysis &an, const Factor &f, const cktlu_options &op
         for (int k = 0; k < n; k++)
             for (int64_t q = f.Fp[k]; q < f.Fp[k] + f.nU[k] - 1 && f.Fi[q] < T; q++) {
                 const int j = f.Fi[q];
+                if (!keep(j, k)) continue;
                 const int64_t o = fillp[rlev[j]]++;
                 it_k[o] = k;
                 it_j[o] = j;
@@ -182,11 +192,11 @@ void build_schedule(const Analysis &an, const Factor &f, const cktlu_options &op
             s.colrec[4 * (size_t)i + 2] = s.Dlen[j];
             s.colrec[4 * (size_t)i + 3] = j;
         }
-        auto item_of = [&](int64_t i, int *dst) {
+        auto item_of = [&](int64_t i, int k, int *dst) {
             const int j = s.src_col[i];
             dst[0] = s.Dp[j] + f.nU[j] - 1;
             dst[1] = s.Dp[j] + f.nU[j];
-            dst[2] = s.Dp[j] + s.Dlen[j];
+            dst[2] = k < T ? s.Dp[j] + s.Dlen[j] : s.Dp[j] + f.nU[j] + lo_cnt[j];
             dst[3] = s.src_slot[i];
         };
         const int ntasks = (int)s.task_tgt.size();
@@ -204,18 +214,37 @@ void build_schedule(const Analysis &an, const Factor &f, const cktlu_options &op
             rec[1] = s.Dp[k];
             rec[2] = slen;
             rec[3] = (int)(s.item4.size() / 4);
-            item_of(s.src_ptr[t], rec + 4);
+            item_of(s.src_ptr[t], k, rec + 4);
             for (int i = s.src_ptr[t] + 1; i < s.src_ptr[t + 1]; i++) {
                 int it[4];
-                item_of(i, it);
+                item_of(i, k, it);
                 s.item4.insert(s.item4.end(), it, it + 4);
             }
         }
         s.task8[8 * (size_t)ntasks + 3] = (int)(s.item4.size() / 4);
         s.macs_sweep = 0;
-        for (int64_t i = 0; i < nitems; i++) {
-            const int j = s.src_col[i];
-            s.macs_sweep += (double)(s.Dlen[j] - f.nU[j]);
+        for (int t = 0; t < ntasks; t++)
+            for (int i = s.src_ptr[t]; i < s.src_ptr[t + 1]; i++) {
+                const int j = s.src_col[i];
+                s.macs_sweep += (double)(s.task_tgt[t] < T ? s.Dlen[j] - f.nU[j] : lo_cnt[j]);
+            }
+        // Schur update of the dense block: per dense column, its U rows < T (the bridge) and,
+        // per sparse column, the range of its L entries in rows >= T
+        s.tail_nb.assign(n - T, 0);
+        s.l21.assign(2 * (size_t)T, 0);
+        s.macs_schur = 0;
+        for (int j = 0; j < T; j++) {
+            s.l21[2 * (size_t)j] = s.Dp[j] + f.nU[j] + lo_cnt[j];
+            s.l21[2 * (size_t)j + 1] = s.Dp[j] + s.Dlen[j];
+        }
+        for (int k = T; k < n; k++) {
+            const int *b = f.Fi.data() + f.Fp[k], *e = f.Fi.data() + f.Fp[k + 1];
+            const int nb = (int)(std::lower_bound(b, e, T) - b);
+            s.tail_nb[k - T] = nb;
+            for (int q = 0; q < nb; q++) {
+                const int j = b[q];
+                s.macs_schur += (double)(s.Dlen[j] - f.nU[j] - lo_cnt[j]);
+            }
         }
         s.lnz_front = 0;
         for (int k = 0; k < T; k++) s.lnz_front += (double)(s.Dlen[k] - f.nU[k]);
