@@ -152,7 +152,8 @@ def main_batched(args, wl):
     import paper_2411_14082_amd as ck
     c = wl["make"]()
     batch = wl["batch"]
-    tail_opts = dict(dense_tail=args.dense_tail, dense_tail_density=args.dense_density, autotune=args.autotune)
+    tail_opts = dict(dense_tail=args.dense_tail, dense_tail_density=args.dense_density, autotune=args.autotune,
+                     solve_chain_width=args.solve_chain, dense_panel_width=args.dense_panel_width)
     legs = {}
     for name, prec, graph in (("fp64_eager", ck.CKTLU_FP64, False), ("fp64_graph", ck.CKTLU_FP64, True),
                               ("fp32_ir_eager", ck.CKTLU_FP32_IR, False), ("fp32_ir_graph", ck.CKTLU_FP32_IR, True)):
@@ -273,6 +274,10 @@ def main():
                     help="order of the dense trailing block: 0 automatic (default), -1 none, >0 forced")
     ap.add_argument("--dense-density", type=float, default=None,
                     help="fill density threshold of the automatic dense-block choice")
+    ap.add_argument("--dense-panel-width", type=int, default=None,
+                    help="dense block: columns factored between trailing-block updates (64, 128, 256)")
+    ap.add_argument("--solve-chain", type=int, default=None,
+                    help="solve levels of at most this many rows chained in one launch (-1 = never)")
     ap.add_argument("--requests", type=int, default=16, help="serving_mix: number of requests")
     ap.add_argument("--slots", type=int, default=4, help="serving_mix: requests on the device at once")
     ap.add_argument("--autotune", action="store_true",
@@ -310,7 +315,8 @@ def main():
     b_dev = torch.tensor(b, device=dev)
     torch.cuda.synchronize()
 
-    tail_opts = dict(dense_tail=args.dense_tail, dense_tail_density=args.dense_density, autotune=args.autotune)
+    tail_opts = dict(dense_tail=args.dense_tail, dense_tail_density=args.dense_density, autotune=args.autotune,
+                     solve_chain_width=args.solve_chain, dense_panel_width=args.dense_panel_width)
     res64 = run_leg(ck, torch, c, vals_dev, b_dev, ck.CKTLU_FP64, args.steps, args.warmup, tail_opts)
     log("fp64: %.3f steps/s, refactor %.2f ms, solve %.2f ms (setup %.1fs), dense tail %d" %
         (args.steps / res64["wall"], res64["ref_ms"].mean(), res64["sol_ms"].mean(), res64["setup_s"],

@@ -70,6 +70,13 @@ typedef struct {
                               reaches dense_tail_density), -1 = never, > 0 = exactly min(value, n) */
     double dense_tail_density; /* schedule: minimum fill density for the automatic choice; default 0.3 */
     int timing;            /* 1: record HIP events around each device phase (read by cktlu_get_timing) */
+    int solve_chain_width; /* solves: consecutive levels of the solve graphs with at most this many rows run
+                              in one launch, one workgroup per instance stepping through them; 0 = automatic
+                              (currently one launch per level: chained levels run their rows one after another
+                              on one CU, which measured slower on long rows), -1 = one launch per level */
+    int dense_panel_width; /* dense block: columns factored between two updates of the whole trailing block
+                              (64, 128 or 256; panels of 64 inside update only the rest of their group);
+                              0 = automatic (256) */
 } cktlu_options;
 
 typedef struct {

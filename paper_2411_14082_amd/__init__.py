@@ -52,7 +52,8 @@ class cktlu_options(ctypes.Structure):
                 ("ir_max_iter", ctypes.c_int), ("ordering", ctypes.c_int), ("transversal", ctypes.c_int),
                 ("stream", ctypes.c_void_p), ("force_fail_col", ctypes.c_int),
                 ("dense_tail_size", ctypes.c_int), ("dense_tail_density", ctypes.c_double),
-                ("timing", ctypes.c_int)]
+                ("timing", ctypes.c_int), ("solve_chain_width", ctypes.c_int),
+                ("dense_panel_width", ctypes.c_int)]
 
 
 class cktlu_refactor_info(ctypes.Structure):
@@ -377,13 +378,17 @@ class SparseLU:
 
     def __init__(self, n, colptr, rowind, eps=1e-3, precision=CKTLU_FP64, ordering=CKTLU_ORDER_AMD,
                  ir_tol=1e-10, ir_max_iter=10, stream=None, transversal=1, dense_tail=None,
-                 dense_tail_density=None, timing=False):
+                 dense_tail_density=None, timing=False, solve_chain_width=None, dense_panel_width=None):
         opt = cktlu_default_options()
         opt.timing = 1 if timing else 0
         if dense_tail is not None:
             opt.dense_tail_size = int(dense_tail)
         if dense_tail_density is not None:
             opt.dense_tail_density = float(dense_tail_density)
+        if solve_chain_width is not None:
+            opt.solve_chain_width = int(solve_chain_width)
+        if dense_panel_width is not None:
+            opt.dense_panel_width = int(dense_panel_width)
         opt.pivot_eps = eps
         opt.precision = precision
         opt.ordering = ordering

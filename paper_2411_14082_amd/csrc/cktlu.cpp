@@ -161,7 +161,7 @@ int upload(DevBuf &b, const std::vector<V> &v, hipStream_t st) {
 DevBuf *all_buffers(Device &d, int i) {
     DevBuf *all[] = {&d.seq, &d.Dp, &d.Dlen, &d.Fi, &d.nU, &d.Ap, &d.colperm, &d.amap, &d.colrec, &d.task8,
                      &d.item4, &d.tail_nb, &d.l21, &d.lrec, &d.urec,
-                     &d.Lrjs, &d.Urjs, &d.rowperm,
+                     &d.Lrjs, &d.Urjs, &d.lsptr, &d.usptr, &d.rowperm,
                      &d.colperm_sol, &d.Acp, &d.Acj, &d.Acsrc, &d.Fx64, &d.Fx32, &d.Aval, &d.done,
                      &d.ctrl, &d.vec, &d.S, &d.Dg};
     const int cnt = (int)(sizeof(all) / sizeof(all[0]));
@@ -259,6 +259,8 @@ int upload_all(cktlu_ctx *c) {
     if ((rc = upload(d.urec, s.urec, st))) return rc;
     if ((rc = upload(d.Lrjs, s.Lrjs, st))) return rc;
     if ((rc = upload(d.Urjs, s.Urjs, st))) return rc;
+    if ((rc = upload(d.lsptr, s.lsptr, st))) return rc;
+    if ((rc = upload(d.usptr, s.usptr, st))) return rc;
     if ((rc = upload(d.rowperm, s.rowperm_final, st))) return rc;
     if ((rc = upload(d.colperm_sol, c->an.colperm, st))) return rc;
     if ((rc = upload(d.Acp, s.Acp, st))) return rc;
@@ -314,7 +316,7 @@ void fill_stats_pattern(cktlu_ctx *c) {
     }
     const int64_t panels = (int64_t)((D + kDenseBlock - 1) / kDenseBlock);
     t.dense_launches = D > 0 ? 2 * panels - 1 + 2 : 0;        // panels, updates, pivot test, scatter
-    t.solve_launches = (int64_t)(s.lsptr.size() - 1) + (int64_t)(s.usptr.size() - 1) + (D > 0 ? 2 * panels : 0);
+    t.solve_launches = (int64_t)(s.lseg.size() / 3) + (int64_t)(s.useg.size() / 3) + (D > 0 ? 2 * panels : 0);
 }
 
 // Host factorization with pivoting (keep == nullptr: every column), then
@@ -383,6 +385,7 @@ DenseArgs dense_args(cktlu_ctx *c, int batch, bool fp32) {
     a.done = (int *)d.done.p;
     a.force_fail_col = -1;
     a.fp32 = fp32 ? 1 : 0;
+    a.W = c->opt.dense_panel_width ? c->opt.dense_panel_width : 256;
     return a;
 }
 
@@ -557,6 +560,7 @@ int ensure_vec(cktlu_ctx *c, size_t doubles) {
 int tri_solves(cktlu_ctx *c, int nrhs, int batch, double *z, bool fp32, const int *skip) {
     Device &d = c->dev;
     hipStream_t st = stream_of(c);
+    nrhs = solve_slots(nrhs);     // the rows carry the padded slot count (zeros past the user's nrhs)
     SolveArgs a;
     a.n = c->an.n;
     a.nrhs = nrhs;
@@ -573,8 +577,12 @@ int tri_solves(cktlu_ctx *c, int nrhs, int batch, double *z, bool fp32, const in
     const Schedule &s = c->s;
     // sparse L levels (the last one holds the dense rows: their entries in sparse columns)
     hipEvent_t t0 = phase_begin(c);
-    for (int l = 0; l + 1 < (int)s.lsptr.size(); l++) LCHK(launch_lsolve_level(a, s.lsptr[l], s.lsptr[l + 1], st));
-    phase_end(c, t0, PH_SOLVE_SPARSE, (int)s.lsptr.size() - 1);
+    for (size_t g = 0; g < s.lseg.size(); g += 3) {
+        const int l0 = s.lseg[g], l1 = s.lseg[g + 1];
+        if (s.lseg[g + 2]) LCHK(launch_lsolve_chain(a, (const int *)d.lsptr.p, l0, l1, st));
+        else LCHK(launch_lsolve_level(a, s.lsptr[l0], s.lsptr[l1], st));
+    }
+    phase_end(c, t0, PH_SOLVE_SPARSE, (int)s.lseg.size() / 3);
     if (s.tail0 < c->an.n) {
         int rc = ensure_S(c, fp32, batch);
         if (rc) return rc;
@@ -586,8 +594,12 @@ int tri_solves(cktlu_ctx *c, int nrhs, int batch, double *z, bool fp32, const in
         phase_end(c, t0, PH_SOLVE_DENSE, 2 * nblk);
     }
     t0 = phase_begin(c);
-    for (int l = 0; l + 1 < (int)s.usptr.size(); l++) LCHK(launch_usolve_level(a, s.usptr[l], s.usptr[l + 1], st));
-    phase_end(c, t0, PH_SOLVE_SPARSE, (int)s.usptr.size() - 1);
+    for (size_t g = 0; g < s.useg.size(); g += 3) {
+        const int l0 = s.useg[g], l1 = s.useg[g + 1];
+        if (s.useg[g + 2]) LCHK(launch_usolve_chain(a, (const int *)d.usptr.p, l0, l1, st));
+        else LCHK(launch_usolve_level(a, s.usptr[l0], s.usptr[l1], st));
+    }
+    phase_end(c, t0, PH_SOLVE_SPARSE, (int)s.useg.size() / 3);
     if (c->opt.timing) c->timing_acc.solve_passes++;
     return CKTLU_OK;
 }
@@ -692,7 +704,10 @@ int cktlu_create(cktlu_ctx **out, const cktlu_options *opt) {
     if (!c) return CKTLU_E_NOMEM;
     if (opt) c->opt = *opt; else cktlu_default_options(&c->opt);
     if (!(c->opt.pivot_eps > 0.0 && c->opt.pivot_eps <= 1.0) ||
-        (c->opt.precision != CKTLU_FP64 && c->opt.precision != CKTLU_FP32_IR) || c->opt.ir_max_iter < 1) {
+        (c->opt.precision != CKTLU_FP64 && c->opt.precision != CKTLU_FP32_IR) || c->opt.ir_max_iter < 1 ||
+        c->opt.solve_chain_width < -1 ||
+        (c->opt.dense_panel_width != 0 && c->opt.dense_panel_width != 64 && c->opt.dense_panel_width != 128 &&
+         c->opt.dense_panel_width != 256)) {
         delete c;
         return CKTLU_E_ARG;
     }

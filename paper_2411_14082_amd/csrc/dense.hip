@@ -5,14 +5,18 @@
 // After the sparse right-looking sweep over the first T = n - D columns, the
 // trailing block S = A22 - L21 U12 (what the sweep left in those columns,
 // rows >= T) is gathered into a dense column-major D x D matrix per instance and
-// factored without pivoting by a blocked right-looking LU, panels of NB = 64:
+// factored without pivoting by a blocked right-looking LU, panels of NB = 64 in
+// groups of W (64, 128 or 256) columns:
 //   dlu_panel  every workgroup factors the NB x NB diagonal block in registers
-//              (one barrier per step), then computes its share of
-//              L21 = A21 U11^-1 (four lanes per row) or U12 = L11^-1 A12 (a
-//              wavefront per four columns);
-//   dlu_gemm   A22 -= L21 U12 on the matrix cores: 128 x 128 output tiles,
-//              K = NB in LDS-staged chunks, v_mfma_f64_16x16x4 (v_mfma_f32_16x16x4
-//              for FP32 factors).
+//              (a wavefront, lane = row), then computes its share of
+//              L21 = A21 U11^-1 or U12 = L11^-1 A12 (sixteen rows or columns
+//              per wavefront);
+//   dlu_gemm   C -= L21 U12 on the matrix cores: 128 x 128 output tiles, K in
+//              LDS-staged chunks, v_mfma_f64_16x16x4 (v_mfma_f32_16x16x4 for FP32
+//              factors).  After a panel it updates only the rest of its group
+//              (K = 64); after the group's last panel, the whole trailing block
+//              with K = W, so that the trailing block is read and written once
+//              per W columns instead of once per panel.
 // dlu_check applies the pivot test of the sparse columns to every dense column
 // c (x = L(:,c) u_cc are its values before division):
 //   fail  <=>  u_cc not finite or zero, or max_{i>c} |x(i,c)| not finite, or
@@ -300,14 +304,20 @@ __global__ __launch_bounds__(256) void dlu_panel_kernel(DenseArgs a, int p, int 
         if (first + q < D) S[(size_t)(first + q) * D + p + lane] = x[q];
 }
 
-// A22 -= L21 U12 over the trailing block [p+NB, D)^2: a 128 x 128 output tile
-// per workgroup, each wavefront 64 x 64 as 4 x 4 MFMA 16 x 16 tiles; K = NB in
+// C -= L(:, K) U(K, :) over up to two output rectangles of S, K = columns
+// [kp, kp + KW) (KW = 64, 128 or 256): the whole trailing block after a group of
+// panels, or the rest of the group after one of its panels.  A 128 x 128 output
+// tile per workgroup, each wavefront 64 x 64 as 4 x 4 MFMA 16 x 16 tiles; K in
 // chunks of 16 staged through LDS (double-buffered, prefetched in registers).
 // The MFMA computes the transposed tile (U12^T L21^T), so that a lane's results
 // run down a column of S and the read-modify-write of C is coalesced.
 // MFMA 16x16x4 operands: lane l holds A(l%16, l/16) and B(l/16, l%16).
-template <typename T>
-__global__ __launch_bounds__(256) void dlu_gemm_kernel(DenseArgs a, int p) {
+struct GemmRect {
+    int r0, r1, c0, c1;        // rows [r0, r1) x columns [c0, c1) of S
+    int ntx, nt;               // tiles down a tile column, tiles in all
+};
+template <typename T, int KW>
+__global__ __launch_bounds__(256) void dlu_gemm_kernel(DenseArgs a, int kp, GemmRect g0, GemmRect g1, int dgp) {
     constexpr int TM = 128, KC = 16, LD = TM + 4;
     __shared__ T As[2][KC][LD];                       // [buf][k][row]
     __shared__ T Bs[2][KC][LD];                       // [buf][k][col]
@@ -315,18 +325,23 @@ __global__ __launch_bounds__(256) void dlu_gemm_kernel(DenseArgs a, int p) {
     if (sweep_failed(a, inst)) return;
     T *S = inst_S<T>(a, inst);
     const int D = a.D;
-    const int r0 = p + NB + blockIdx.x * TM, c0 = p + NB + blockIdx.y * TM;
+    const bool first = (int)blockIdx.x < g0.nt;
+    const int t = first ? (int)blockIdx.x : (int)blockIdx.x - g0.nt;
+    const int ntx = first ? g0.ntx : g1.ntx;
+    const int r0 = (first ? g0.r0 : g1.r0) + (t % ntx) * TM, c0 = (first ? g0.c0 : g1.c0) + (t / ntx) * TM;
+    const int R1 = first ? g0.r1 : g1.r1, C1 = first ? g0.c1 : g1.c1;
     const int tid = threadIdx.x;
-    if (blockIdx.x == 0 && blockIdx.y == 0) {
-        // the factored diagonal block of this panel (full: the panel has a trailing part)
+    if (blockIdx.x == 0 && dgp >= 0) {
+        // the factored diagonal block of the panel at dgp (it had a trailing part, so its
+        // factors went to the scratch block while its other workgroups still read S)
         const T *src = reinterpret_cast<const T *>(a.Dg) + (size_t)inst * NB * NB;
-        T t[16];
+        T tv[16];
 #pragma unroll
-        for (int u = 0; u < 16; u++) t[u] = src[tid + 256 * u];
+        for (int u = 0; u < 16; u++) tv[u] = src[tid + 256 * u];
 #pragma unroll
         for (int u = 0; u < 16; u++) {
             const int e = tid + 256 * u;
-            S[(size_t)(p + e / NB) * D + p + e % NB] = t[u];
+            S[(size_t)(dgp + e / NB) * D + dgp + e % NB] = tv[u];
         }
     }
     T ra[8], rb[8];
@@ -335,9 +350,9 @@ __global__ __launch_bounds__(256) void dlu_gemm_kernel(DenseArgs a, int p) {
         for (int u = 0; u < 8; u++) {
             const int e = tid + 256 * u;
             const int ka = e / TM, rr = e % TM;
-            ra[u] = r0 + rr < D ? S[(size_t)(p + kc + ka) * D + r0 + rr] : T(0);
+            ra[u] = r0 + rr < R1 ? S[(size_t)(kp + kc + ka) * D + r0 + rr] : T(0);
             const int kb = e % KC, cc = e / KC;
-            rb[u] = c0 + cc < D ? S[(size_t)(c0 + cc) * D + p + kc + kb] : T(0);
+            rb[u] = c0 + cc < C1 ? S[(size_t)(c0 + cc) * D + kp + kc + kb] : T(0);
         }
     };
     auto stash = [&](int buf) {                      // A is stored negated: acc = C + (-A) B
@@ -364,15 +379,16 @@ __global__ __launch_bounds__(256) void dlu_gemm_kernel(DenseArgs a, int p) {
 #pragma unroll
             for (int q = 0; q < 4; q++) {
                 const int row = crow(ti), col = ccol(tj, q);
-                acc[ti][tj][q] = (row < D && col < D) ? S[(size_t)col * D + row] : T(0);
+                acc[ti][tj][q] = (row < R1 && col < C1) ? S[(size_t)col * D + row] : T(0);
             }
     fetch(0);
     stash(0);
     __syncthreads();
+    constexpr int nch = KW / KC;       // a compile-time trip count keeps the kernel at two waves per SIMD
 #pragma unroll 1
-    for (int ch = 0; ch < NB / KC; ch++) {
+    for (int ch = 0; ch < nch; ch++) {
         const int buf = ch & 1;
-        if (ch + 1 < NB / KC) fetch((ch + 1) * KC);
+        if (ch + 1 < nch) fetch((ch + 1) * KC);
 #pragma unroll
         for (int s = 0; s < KC / 4; s++) {
             T av[4], bv[4];
@@ -391,7 +407,7 @@ __global__ __launch_bounds__(256) void dlu_gemm_kernel(DenseArgs a, int p) {
                         acc[ti][tj] = __builtin_amdgcn_mfma_f32_16x16x4f32(bv[tj], av[ti], acc[ti][tj], 0, 0, 0);
                 }
         }
-        if (ch + 1 < NB / KC) stash(buf ^ 1);
+        if (ch + 1 < nch) stash(buf ^ 1);
         __syncthreads();
     }
     // transposed tile: FP64 element q of lane l is C(row l%16, col 4q + l/16),
@@ -403,7 +419,7 @@ __global__ __launch_bounds__(256) void dlu_gemm_kernel(DenseArgs a, int p) {
 #pragma unroll
             for (int q = 0; q < 4; q++) {
                 const int row = crow(ti), col = ccol(tj, q);
-                if (row < D && col < D) S[(size_t)col * D + row] = acc[ti][tj][q];
+                if (row < R1 && col < C1) S[(size_t)col * D + row] = acc[ti][tj][q];
             }
 }
 
@@ -620,18 +636,43 @@ int launch_dense_refactor(const DenseArgs &a, bool gather, void *stream) {
         const int e = launch_dense_gather(a, stream);
         if (e) return e;
     }
-    for (int p = 0; p < D; p += NB) {
-        const int nb = D - p < NB ? D - p : NB;
-        const int rest = D - p - nb;   // > 0 only for full panels
-        const int nrb = (rest + 63) / 64, ncb = (rest + 63) / 64;
-        const dim3 gp((unsigned)(1 + nrb + ncb), (unsigned)a.batch);
-        if (a.fp32) hipLaunchKernelGGL((dlu_panel_kernel<float>), gp, dim3(256), 0, st, a, p, nrb);
-        else hipLaunchKernelGGL((dlu_panel_kernel<double>), gp, dim3(256), 0, st, a, p, nrb);
-        if (rest > 0) {
-            const dim3 gg((unsigned)((rest + 127) / 128), (unsigned)((rest + 127) / 128), (unsigned)a.batch);
-            if (a.fp32) hipLaunchKernelGGL((dlu_gemm_kernel<float>), gg, dim3(256), 0, st, a, p);
-            else hipLaunchKernelGGL((dlu_gemm_kernel<double>), gg, dim3(256), 0, st, a, p);
+    // groups of W columns: each panel of 64 updates the rest of its group (the column strip
+    // below and right of it, the row strip right of the group); the whole trailing block
+    // is updated once per group with K = W
+    auto rect = [](int r0, int r1, int c0, int c1) {
+        GemmRect g;
+        g.r0 = r0; g.r1 = r1; g.c0 = c0; g.c1 = c1;
+        g.ntx = r1 > r0 && c1 > c0 ? (r1 - r0 + 127) / 128 : 0;
+        g.nt = g.ntx ? g.ntx * ((c1 - c0 + 127) / 128) : 0;
+        return g;
+    };
+    auto gemm = [&](int kp, int kw, const GemmRect &g0, const GemmRect &g1, int dgp) {
+        const dim3 gg((unsigned)(g0.nt + g1.nt), 1, (unsigned)a.batch);
+        if (kw == 64) {
+            if (a.fp32) hipLaunchKernelGGL((dlu_gemm_kernel<float, 64>), gg, dim3(256), 0, st, a, kp, g0, g1, dgp);
+            else hipLaunchKernelGGL((dlu_gemm_kernel<double, 64>), gg, dim3(256), 0, st, a, kp, g0, g1, dgp);
+        } else if (kw == 128) {
+            if (a.fp32) hipLaunchKernelGGL((dlu_gemm_kernel<float, 128>), gg, dim3(256), 0, st, a, kp, g0, g1, dgp);
+            else hipLaunchKernelGGL((dlu_gemm_kernel<double, 128>), gg, dim3(256), 0, st, a, kp, g0, g1, dgp);
+        } else {
+            if (a.fp32) hipLaunchKernelGGL((dlu_gemm_kernel<float, 256>), gg, dim3(256), 0, st, a, kp, g0, g1, dgp);
+            else hipLaunchKernelGGL((dlu_gemm_kernel<double, 256>), gg, dim3(256), 0, st, a, kp, g0, g1, dgp);
         }
+    };
+    const int W = a.W;
+    for (int p = 0; p < D; p += W) {
+        const int pe = D - p < W ? D : p + W;         // end of this group
+        for (int q = p; q < pe; q += NB) {
+            const int nb = D - q < NB ? D - q : NB;
+            const int rest = D - q - nb;               // > 0 only for full panels
+            const int nrb = (rest + 63) / 64, ncb = (rest + 63) / 64;
+            const dim3 gp((unsigned)(1 + nrb + ncb), (unsigned)a.batch);
+            if (a.fp32) hipLaunchKernelGGL((dlu_panel_kernel<float>), gp, dim3(256), 0, st, a, q, nrb);
+            else hipLaunchKernelGGL((dlu_panel_kernel<double>), gp, dim3(256), 0, st, a, q, nrb);
+            const int q1 = q + NB;
+            if (q1 < pe) gemm(q, NB, rect(q1, D, q1, pe), rect(q1, pe, pe, D), q);
+        }
+        if (pe < D) gemm(p, pe - p, rect(pe, D, pe, D), rect(0, 0, 0, 0), pe - NB);
     }
     if (a.check) {
         if (a.fp32) hipLaunchKernelGGL((dlu_check_kernel<float>), gw, dim3(256), 0, st, a);

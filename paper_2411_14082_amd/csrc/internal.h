@@ -82,6 +82,7 @@ struct Schedule {
     std::vector<int> Lrp, Lrj, Lrsrc, Urp, Urj, Ursrc, udiag;
     // solve dependency graphs: rows by level (L: ascending dependencies, U: descending)
     std::vector<int> lseq, lsptr, useq, usptr;
+    std::vector<int> lseg, useg;              // launch segments {first level, end level, chained}
     std::vector<int> rowperm_final;           // position k <- user row
     // user-space CSR of A (for the FP64 residual of iterative refinement)
     std::vector<int> Acp, Acj, Acsrc;
@@ -110,7 +111,7 @@ struct Device {
     // pattern / schedule
     DevBuf seq, Dp, Dlen, Fi, nU, Ap, colperm, amap;
     DevBuf colrec, task8, item4, tail_nb, l21;
-    DevBuf lrec, urec, Lrjs, Urjs, rowperm, colperm_sol;
+    DevBuf lrec, urec, Lrjs, Urjs, lsptr, usptr, rowperm, colperm_sol;
     DevBuf Acp, Acj, Acsrc;
     // values and status words
     DevBuf Fx64, Fx32;                 // factor values (FP64 always; FP32 in FP32_IR mode)
@@ -132,6 +133,8 @@ namespace cktlu_dev {
 
 constexpr int kColAlign = 32;   // factor column alignment in entries (>= one 128-byte line)
 constexpr int YS = 16;          // doubles per solve-vector row (one 128-byte line); nrhs <= 8
+// right-hand-side slots the solve kernels carry per row: nrhs rounded up to 1, 2, 4 or 8
+inline int solve_slots(int nrhs) { return nrhs <= 1 ? 1 : nrhs <= 2 ? 2 : nrhs <= 4 ? 4 : 8; }
 
 struct RefactorArgs {
     int n, batch;
@@ -175,7 +178,11 @@ struct SolveArgs {
 // Solve positions [lbeg, lend) of lrec / urec (one level of the solve graph).
 int launch_lsolve_level(const SolveArgs &a, int lbeg, int lend, void *stream);
 int launch_usolve_level(const SolveArgs &a, int lbeg, int lend, void *stream);
-// y[((i*n + k)*YS + r] = b[(i*nrhs + r)*ldb + perm[k]]
+// Levels [l0, l1) of the L / U solve graph in one launch: one workgroup per instance,
+// a barrier between levels; lvptr = level boundaries in solve positions (device).
+int launch_lsolve_chain(const SolveArgs &a, const int *lvptr, int l0, int l1, void *stream);
+int launch_usolve_chain(const SolveArgs &a, const int *lvptr, int l0, int l1, void *stream);
+// y[((i*n + k)*YS + r] = b[(i*nrhs + r)*ldb + perm[k]] for r < nrhs, 0 for r < solve_slots(nrhs)
 int launch_gather_rhs(int n, int nrhs, int batch, const double *b, int64_t ldb, const int *perm,
                       double *y, void *stream);
 // x[(i*nrhs + r)*ldx + perm[k]] (+)= y[(i*n + k)*YS + r]
@@ -217,6 +224,7 @@ struct DenseArgs {
     unsigned epoch;
     int force_fail_col;
     int fp32, check;
+    int W;                     // columns factored between two updates of the whole trailing block
 };
 // S <- rows >= T of the tail columns of Fx (zeros elsewhere)
 int launch_dense_gather(const DenseArgs &a, void *stream);

@@ -21,10 +21,12 @@
 // instance return at once.
 //
 // Solves (Section II-C, Algorithm 2): trisolve_level_kernel, row ("pull") form,
-// one launch per level of the solve dependency graph, one wavefront per row.
+// one launch per level of the solve dependency graph, one wavefront per row;
+// runs of narrow levels go to trisolve_chain_kernel, one workgroup per instance.
 //
-// All communication between wavefronts happens at kernel boundaries, where the
-// runtime makes device memory coherent across the MI355X's eight XCDs.
+// All communication between workgroups happens at kernel boundaries, where the
+// runtime makes device memory coherent across the MI355X's eight XCDs; inside
+// the chained solve only the wavefronts of one workgroup (one CU) communicate.
 #include <hip/hip_runtime.h>
 
 #include <climits>
@@ -376,16 +378,11 @@ int launch_refactor_level(const RefactorArgs &a, int cbeg, int cend, int pbeg, i
 
 // ----------------------------------------------------------------- solves
 // y holds one cache line (YS doubles) per row and instance: y[(inst*n + i)*YS + r].
-// One wavefront per row: its record, then its entries {column, value position},
-// then the values and the y rows they multiply.
+// One row of a triangular solve, by one wavefront: its record, then its entries
+// {column, value position}, then the values and the y rows they multiply.
 template <typename T, int NR, bool UPPER>
-__global__ __launch_bounds__(WG) void trisolve_level_kernel(SolveArgs a, int lbeg, int lend) {
-    const int lane = threadIdx.x & (WAVE - 1), wv = threadIdx.x / WAVE;
-    const int64_t t = (int64_t)lbeg * a.batch + (int64_t)blockIdx.x * WAVES + wv;
-    if (t >= (int64_t)lend * a.batch) return;
-    const int inst = (int)(t % a.batch);
-    const int4 rec = reinterpret_cast<const int4 *>(UPPER ? a.urec : a.lrec)[t / a.batch];
-    const int skipped = a.skip ? a.skip[inst] != -1 : 0;
+__device__ __forceinline__ void solve_row(const SolveArgs &a, int inst, int pos, int lane) {
+    const int4 rec = reinterpret_cast<const int4 *>(UPPER ? a.urec : a.lrec)[pos];
     const int2 *rjs = reinterpret_cast<const int2 *>(UPPER ? a.Urjs : a.Lrjs);
     const T *Fx = reinterpret_cast<const T *>(a.Fx) + (size_t)inst * a.nnzF;
     double *y = a.y + (size_t)inst * a.n * YS;
@@ -409,7 +406,6 @@ __global__ __launch_bounds__(WG) void trisolve_level_kernel(SolveArgs a, int lbe
                 for (int r = 0; r < NR; r++) acc[r] += l[u] * y[(size_t)e[u].x * YS + r];
             }
     }
-    if (skipped) return;
 #pragma unroll
     for (int r = 0; r < NR; r++) acc[r] = wave_sum(acc[r]);
     double mine = acc[0];
@@ -420,6 +416,35 @@ __global__ __launch_bounds__(WG) void trisolve_level_kernel(SolveArgs a, int lbe
         double v = yi - mine;
         if (UPPER) v = v / diag;
         y[(size_t)i * YS + lane] = v;
+    }
+}
+
+// One level: one wavefront per (row, instance).
+template <typename T, int NR, bool UPPER>
+__global__ __launch_bounds__(WG) void trisolve_level_kernel(SolveArgs a, int lbeg, int lend) {
+    const int lane = threadIdx.x & (WAVE - 1), wv = threadIdx.x / WAVE;
+    const int64_t t = (int64_t)lbeg * a.batch + (int64_t)blockIdx.x * WAVES + wv;
+    if (t >= (int64_t)lend * a.batch) return;
+    const int inst = (int)(t % a.batch);
+    if (a.skip && a.skip[inst] != -1) return;
+    solve_row<T, NR, UPPER>(a, inst, (int)(t / a.batch), lane);
+}
+
+// A run of narrow levels [l0, l1): one workgroup per instance takes the rows of a
+// level round-robin over its wavefronts, then waits at a barrier before the next
+// level (the barrier orders the workgroup's global stores before its later loads).
+constexpr int kChainWG = 1024;
+template <typename T, int NR, bool UPPER>
+__global__ __launch_bounds__(kChainWG) void trisolve_chain_kernel(SolveArgs a, const int *lvptr, int l0, int l1) {
+    const int lane = threadIdx.x & (WAVE - 1), wv = threadIdx.x / WAVE;
+    const int inst = blockIdx.x;
+    if (a.skip && a.skip[inst] != -1) return;          // the whole workgroup
+    int beg = lvptr[l0];
+    for (int l = l0; l < l1; l++) {
+        const int end = lvptr[l + 1];
+        for (int p = beg + wv; p < end; p += kChainWG / WAVE) solve_row<T, NR, UPPER>(a, inst, p, lane);
+        beg = end;
+        __syncthreads();
     }
 }
 
@@ -446,6 +471,35 @@ static int launch_solve_level_impl(const SolveArgs &a, int lbeg, int lend, void 
     return (int)hipGetLastError();
 }
 
+template <bool UPPER>
+static int launch_solve_chain_impl(const SolveArgs &a, const int *lvptr, int l0, int l1, void *stream) {
+    hipStream_t st = (hipStream_t)stream;
+    const dim3 grid((unsigned)a.batch);
+#define CKTLU_CHAIN_CASE(NRV)                                                                          \
+    case NRV:                                                                                          \
+        if (a.fp32)                                                                                    \
+            hipLaunchKernelGGL((trisolve_chain_kernel<float, NRV, UPPER>), grid, dim3(kChainWG), 0, st, a, lvptr, l0, l1); \
+        else                                                                                           \
+            hipLaunchKernelGGL((trisolve_chain_kernel<double, NRV, UPPER>), grid, dim3(kChainWG), 0, st, a, lvptr, l0, l1); \
+        break;
+    switch (a.nrhs) {
+        CKTLU_CHAIN_CASE(1)
+        CKTLU_CHAIN_CASE(2)
+        CKTLU_CHAIN_CASE(4)
+        CKTLU_CHAIN_CASE(8)
+        default: return (int)hipErrorInvalidValue;
+    }
+#undef CKTLU_CHAIN_CASE
+    return (int)hipGetLastError();
+}
+
+int launch_lsolve_chain(const SolveArgs &a, const int *lvptr, int l0, int l1, void *stream) {
+    return launch_solve_chain_impl<false>(a, lvptr, l0, l1, stream);
+}
+int launch_usolve_chain(const SolveArgs &a, const int *lvptr, int l0, int l1, void *stream) {
+    return launch_solve_chain_impl<true>(a, lvptr, l0, l1, stream);
+}
+
 int launch_lsolve_level(const SolveArgs &a, int lbeg, int lend, void *stream) {
     return launch_solve_level_impl<false>(a, lbeg, lend, stream);
 }
@@ -454,16 +508,17 @@ int launch_usolve_level(const SolveArgs &a, int lbeg, int lend, void *stream) {
 }
 
 // --------------------------------------------------------------- helpers
-__global__ void gather_rhs_kernel(int n, int nrhs, int batch, const double *b, int64_t ldb,
+// fills the solve slots [0, solve_slots(nrhs)) of each row; slots past nrhs get zeros
+__global__ void gather_rhs_kernel(int n, int nrhs, int nslots, int batch, const double *b, int64_t ldb,
                                   const int *perm, double *y) {
-    const int64_t total = (int64_t)n * nrhs * batch;
+    const int64_t total = (int64_t)n * nslots * batch;
     for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < total;
          t += (int64_t)gridDim.x * blockDim.x) {
-        const int r = (int)(t % nrhs);
-        const int64_t ik = t / nrhs;
+        const int r = (int)(t % nslots);
+        const int64_t ik = t / nslots;
         const int k = (int)(ik % n);
         const int64_t i = ik / n;
-        y[ik * YS + r] = b[(i * nrhs + r) * ldb + perm[k]];
+        y[ik * YS + r] = r < nrhs ? b[(i * nrhs + r) * ldb + perm[k]] : 0.0;
     }
 }
 
@@ -492,8 +547,9 @@ static inline int grid_for(int64_t total, int block) {
 
 int launch_gather_rhs(int n, int nrhs, int batch, const double *b, int64_t ldb, const int *perm,
                       double *y, void *stream) {
-    hipLaunchKernelGGL(gather_rhs_kernel, dim3(grid_for((int64_t)n * nrhs * batch, 256)), dim3(256), 0,
-                       (hipStream_t)stream, n, nrhs, batch, b, ldb, perm, y);
+    const int ns = solve_slots(nrhs);
+    hipLaunchKernelGGL(gather_rhs_kernel, dim3(grid_for((int64_t)n * ns * batch, 256)), dim3(256), 0,
+                       (hipStream_t)stream, n, nrhs, ns, batch, b, ldb, perm, y);
     return (int)hipGetLastError();
 }
 

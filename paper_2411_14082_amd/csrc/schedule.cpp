@@ -314,6 +314,26 @@ void build_schedule(const Analysis &an, const Factor &f, const cktlu_options &op
         for (size_t q = 0; q < s.Lrj.size(); q++) { s.Lrjs[2 * q] = s.Lrj[q]; s.Lrjs[2 * q + 1] = s.Lrsrc[q]; }
         s.Urjs.resize(2 * s.Urj.size());
         for (size_t q = 0; q < s.Urj.size(); q++) { s.Urjs[2 * q] = s.Urj[q]; s.Urjs[2 * q + 1] = s.Ursrc[q]; }
+        // launch segments: runs of two or more consecutive narrow levels go to one chained
+        // launch (a workgroup per instance steps through them with barriers in between)
+        const int cw = opt.solve_chain_width == 0 ? -1 : opt.solve_chain_width;
+        auto segments = [cw](const std::vector<int> &ptr, std::vector<int> &seg) {
+            seg.clear();
+            const int nl = (int)ptr.size() - 1;
+            for (int l = 0; l < nl;) {
+                int e = l;
+                while (cw > 0 && e < nl && ptr[e + 1] - ptr[e] <= cw) e++;
+                if (e - l >= 2) {
+                    seg.insert(seg.end(), {l, e, 1});
+                    l = e;
+                } else {
+                    seg.insert(seg.end(), {l, l + 1, 0});
+                    l++;
+                }
+            }
+        };
+        segments(s.lsptr, s.lseg);
+        segments(s.usptr, s.useg);
     }
     s.rowperm_final.resize(n);
     for (int k = 0; k < n; k++) s.rowperm_final[k] = an.rowperm_pre[f.pivrow[k]];

@@ -414,3 +414,77 @@ def test_fp32_ir_fallback_then_fp64(ck, oracle_mod):
     x = torch.zeros(c.n, dtype=torch.float64, device="cuda:0")
     rc, info = s.solve(dev(b), x)
     assert info.used_fp64 == 1 and rc == ck.CKTLU_W_IR_FALLBACK   # the target is still out of reach
+
+
+@pytest.mark.parametrize("tail", [-1, 100])
+@pytest.mark.parametrize("nrhs", [1, 3])
+def test_solve_chain_widths_identical(ck, oracle_mod, tail, nrhs):
+    """Chained solve launches (runs of narrow levels in one workgroup per
+    instance) compute every row exactly as the per-level launches do, so the
+    solutions are bit-identical for any chain width: -1 (no chains), 0 (the
+    default), 8 (short chains) and 10**9 (every level, the dense rows' level
+    included, chained); batched instances with one skipped instance too."""
+    c = mnagen.layered_rc(24, 24, 3, seed=21)
+    batch = 3
+    V = mnagen.instance_values(c, batch, 0.05, seed=21)
+    rng = np.random.default_rng(21)
+    B = rng.standard_normal((batch, nrhs, c.n))
+    B1 = rng.standard_normal((nrhs, c.n))
+    outs = {}
+    for w in (-1, 0, 8, 10 ** 9):
+        say("chain width", w, "tail", tail, "nrhs", nrhs)
+        s = ck.SparseLU(c.n, c.colptr, c.rowind, eps=EPS, dense_tail=tail, solve_chain_width=w)
+        s.factorize(dev(c.values))
+        X = torch.zeros((nrhs, c.n), dtype=torch.float64, device="cuda:0")
+        s.solve(dev(B1), X, nrhs=nrhs)
+        status = torch.tensor([-1, 5, -1], dtype=torch.int32, device="cuda:0")
+        Xb = torch.full((batch, nrhs, c.n), 7.0, dtype=torch.float64, device="cuda:0")
+        s.refactorize_batched(batch, dev(V), torch.zeros(batch, dtype=torch.int32, device="cuda:0"))
+        s.solve_batched(batch, nrhs, dev(B), Xb, status)
+        torch.cuda.synchronize()
+        outs[w] = (X.cpu().numpy(), Xb.cpu().numpy())
+    for w in (0, 8, 10 ** 9):
+        assert np.array_equal(outs[w][0], outs[-1][0]), w
+        assert np.array_equal(outs[w][1], outs[-1][1]), w
+    X, Xb = outs[0]
+    for r in range(nrhs):
+        assert oracle_mod.backward_error(c.colptr, c.rowind, c.values, X[r], B1[r]) <= 1e-12
+    assert np.all(Xb[1] == 7.0)
+    for i in (0, 2):
+        for r in range(nrhs):
+            assert oracle_mod.backward_error(c.colptr, c.rowind, V[i], Xb[i, r], B[i, r]) <= 1e-12
+
+
+@pytest.mark.parametrize("width", [64, 128, 256])
+@pytest.mark.parametrize("tail", [300, 520])
+def test_dense_panel_widths(ck, oracle_mod, width, tail):
+    """Groups of 64, 128 or 256 dense columns between updates of the whole trailing
+    block (full groups, a ragged last group, a ragged last panel): factors match
+    the oracle's, the solve reaches eta <= 1e-12, and a batch of instances gives
+    every instance's factors of the single-instance path."""
+    c = mnagen.mesh_transistor(40, 40, seed=23)
+    say("dense panel width", width, "tail", tail)
+    s = ck.SparseLU(c.n, c.colptr, c.rowind, eps=EPS, dense_tail=tail, dense_panel_width=width)
+    s.factorize(dev(c.values))
+    a0 = s.analysis()
+    vh = mnagen.restamp(c, 23, 0, 1)
+    rc, info = s.refactorize(dev(vh))
+    lu = oracle_refactor(oracle_mod, c, vh, a0, EPS, a0["pivrow"])
+    assert np.array_equal(s.analysis()["pivrow"], lu.pivrow)
+    f1 = s.factors()
+    compare_factors(f1, lu, RTOL)
+    x = torch.zeros(c.n, dtype=torch.float64, device="cuda:0")
+    s.solve(dev(c.rhs[0]), x)
+    torch.cuda.synchronize()
+    assert oracle_mod.backward_error(c.colptr, c.rowind, vh, x.cpu().numpy(), c.rhs[0]) <= 1e-12
+    if rc == 0:
+        batch = 3
+        V = np.stack([vh, mnagen.restamp(c, 23, 0, 2), vh])
+        st = torch.zeros(batch, dtype=torch.int32, device="cuda:0")
+        s.refactorize_batched(batch, dev(V), st)
+        torch.cuda.synchronize()
+        assert st.cpu().numpy()[0] == -1 and st.cpu().numpy()[2] == -1
+        for i in (0, 2):
+            fb = s.factors(instance=i)
+            for k in ("Lx", "Ux"):
+                assert np.array_equal(fb[k], f1[k]), (i, k)
