@@ -185,17 +185,21 @@ def kernel_source_hash():
     return hashlib.sha256(txt[a:z].encode()).hexdigest() if 0 <= a < z else None
 
 
-def measured_traffic():
+def measured_traffic(algorithmic_bytes_per_launch):
     """Bytes per sweep launch from the committed counter summary, or None when the
-    sweep kernel's source has changed since the counters were taken."""
+    sweep kernel's source or its work per launch (the schedule) has changed since
+    the counters were taken."""
     if not os.path.exists(TRAFFIC_FILE):
         return None
     txt = open(TRAFFIC_FILE).read()
     m_sha = re.search(r"refactor_level_kernel_source_sha256:\s*([0-9a-f]{64})", txt)
     m_b = re.search(r"hbm_bytes_per_launch:\s*([0-9.eE+]+)", txt)
-    if not m_sha or not m_b:
+    m_alg = re.search(r"algorithmic_bytes_per_launch:\s*([0-9.eE+]+)", txt)
+    if not m_sha or not m_b or not m_alg or kernel_source_hash() != m_sha.group(1):
         return None
-    return float(m_b.group(1)) if kernel_source_hash() == m_sha.group(1) else None
+    if abs(float(m_alg.group(1)) - algorithmic_bytes_per_launch) > 1e-3 * algorithmic_bytes_per_launch:
+        return None
+    return float(m_b.group(1))
 
 
 def log(*a):
@@ -347,7 +351,7 @@ def main():
     sweep_launch_s = tm["sweep_ms"] * 1e-3 / max(1, tm["sweep_launches"])
     bytes_per_launch = st["bytes_sweep"] / max(1, st["sweep_launches"])
     achieved = bytes_per_launch / sweep_launch_s / 1e9
-    traffic = measured_traffic()
+    traffic = measured_traffic(bytes_per_launch)
     roofline = dict(bound="hbm", kernel="refactor_level_kernel", achieved=achieved, peak=HBM_PEAK_GBS,
                     unit="GB/s", frac=achieved / HBM_PEAK_GBS, traffic=traffic,
                     algorithmic_bytes_per_launch=bytes_per_launch, avg_launch_us=sweep_launch_s * 1e6,
