@@ -153,7 +153,8 @@ def main_batched(args, wl):
     c = wl["make"]()
     batch = wl["batch"]
     tail_opts = dict(dense_tail=args.dense_tail, dense_tail_density=args.dense_density, autotune=args.autotune,
-                     solve_chain_width=args.solve_chain, dense_panel_width=args.dense_panel_width)
+                     solve_chain_width=args.solve_chain, dense_panel_width=args.dense_panel_width,
+                     dense_lookahead=args.dense_lookahead)
     legs = {}
     for name, prec, graph in (("fp64_eager", ck.CKTLU_FP64, False), ("fp64_graph", ck.CKTLU_FP64, True),
                               ("fp32_ir_eager", ck.CKTLU_FP32_IR, False), ("fp32_ir_graph", ck.CKTLU_FP32_IR, True)):
@@ -280,6 +281,8 @@ def main():
                     help="fill density threshold of the automatic dense-block choice")
     ap.add_argument("--dense-panel-width", type=int, default=None,
                     help="dense block: columns factored between trailing-block updates (64, 128, 256)")
+    ap.add_argument("--dense-lookahead", type=int, default=None,
+                    help="dense block: 1 panels of the next group on a second stream, 0 one stream")
     ap.add_argument("--solve-chain", type=int, default=None,
                     help="solve levels of at most this many rows chained in one launch (-1 = never)")
     ap.add_argument("--requests", type=int, default=16, help="serving_mix: number of requests")
@@ -320,7 +323,8 @@ def main():
     torch.cuda.synchronize()
 
     tail_opts = dict(dense_tail=args.dense_tail, dense_tail_density=args.dense_density, autotune=args.autotune,
-                     solve_chain_width=args.solve_chain, dense_panel_width=args.dense_panel_width)
+                     solve_chain_width=args.solve_chain, dense_panel_width=args.dense_panel_width,
+                     dense_lookahead=args.dense_lookahead)
     res64 = run_leg(ck, torch, c, vals_dev, b_dev, ck.CKTLU_FP64, args.steps, args.warmup, tail_opts)
     log("fp64: %.3f steps/s, refactor %.2f ms, solve %.2f ms (setup %.1fs), dense tail %d" %
         (args.steps / res64["wall"], res64["ref_ms"].mean(), res64["sol_ms"].mean(), res64["setup_s"],

@@ -77,6 +77,10 @@ typedef struct {
     int dense_panel_width; /* dense block: columns factored between two updates of the whole trailing block
                               (64, 128 or 256; panels of 64 inside update only the rest of their group);
                               0 = automatic (256) */
+    int dense_lookahead;   /* dense block: 1 runs the panels of the next group on a second stream of the
+                              context while the trailing update of the current group runs (same results);
+                              0 (default) = one stream, which measured faster: the update's workgroups fill
+                              the device and the panels waited for them */
 } cktlu_options;
 
 typedef struct {

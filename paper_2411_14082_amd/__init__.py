@@ -53,7 +53,7 @@ class cktlu_options(ctypes.Structure):
                 ("stream", ctypes.c_void_p), ("force_fail_col", ctypes.c_int),
                 ("dense_tail_size", ctypes.c_int), ("dense_tail_density", ctypes.c_double),
                 ("timing", ctypes.c_int), ("solve_chain_width", ctypes.c_int),
-                ("dense_panel_width", ctypes.c_int)]
+                ("dense_panel_width", ctypes.c_int), ("dense_lookahead", ctypes.c_int)]
 
 
 class cktlu_refactor_info(ctypes.Structure):
@@ -378,7 +378,8 @@ class SparseLU:
 
     def __init__(self, n, colptr, rowind, eps=1e-3, precision=CKTLU_FP64, ordering=CKTLU_ORDER_AMD,
                  ir_tol=1e-10, ir_max_iter=10, stream=None, transversal=1, dense_tail=None,
-                 dense_tail_density=None, timing=False, solve_chain_width=None, dense_panel_width=None):
+                 dense_tail_density=None, timing=False, solve_chain_width=None, dense_panel_width=None,
+                 dense_lookahead=None):
         opt = cktlu_default_options()
         opt.timing = 1 if timing else 0
         if dense_tail is not None:
@@ -389,6 +390,8 @@ class SparseLU:
             opt.solve_chain_width = int(solve_chain_width)
         if dense_panel_width is not None:
             opt.dense_panel_width = int(dense_panel_width)
+        if dense_lookahead is not None:
+            opt.dense_lookahead = int(dense_lookahead)
         opt.pivot_eps = eps
         opt.precision = precision
         opt.ordering = ordering

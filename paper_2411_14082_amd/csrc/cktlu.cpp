@@ -47,6 +47,9 @@ struct cktlu_ctx {
     hipGraphExec_t graph_exec = nullptr;
     hipStream_t capture_stream = nullptr;
     uint64_t buffers_gen = 1;      // bumped whenever device buffers may have moved
+    // dense-block look-ahead: a second stream (default priority) and its ordering events
+    hipStream_t side_stream = nullptr;
+    std::vector<hipEvent_t> la_events;
 };
 
 namespace {
@@ -389,6 +392,19 @@ DenseArgs dense_args(cktlu_ctx *c, int batch, bool fp32) {
     return a;
 }
 
+// The side stream and events of the dense-block look-ahead (created before any capture).
+int ensure_lookahead(cktlu_ctx *c, const DenseArgs &da) {
+    const int nev = dense_lookahead_events(da);
+    if (c->opt.dense_lookahead != 1 || nev == 0) return CKTLU_OK;
+    if (!c->side_stream) HIPCHK(hipStreamCreateWithFlags(&c->side_stream, hipStreamNonBlocking));
+    while ((int)c->la_events.size() < nev) {
+        hipEvent_t e = nullptr;
+        HIPCHK(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+        c->la_events.push_back(e);
+    }
+    return CKTLU_OK;
+}
+
 // Make S hold the dense block of the current factors of the given precision.
 int ensure_S(cktlu_ctx *c, bool fp32, int batch) {
     if (c->s.tail0 >= c->an.n || c->dev.S_prec == (fp32 ? 1 : 0)) return CKTLU_OK;
@@ -460,9 +476,17 @@ int run_refactor(cktlu_ctx *c, int batch, const double *values_dev, bool fp32, b
         da.epoch = a.epoch;
         da.force_fail_col = force_col;
         da.check = a.check;
+        DenseStreams la{nullptr, nullptr, 0};
+        int rc = ensure_lookahead(c, da);
+        if (rc) return rc;
+        if (c->side_stream && !c->la_events.empty()) {
+            la.side = c->side_stream;
+            la.ev = reinterpret_cast<void *const *>(c->la_events.data());
+            la.nev = (int)c->la_events.size();
+        }
         t0 = phase_begin(c);
         LCHK(launch_schur(da, (const int *)d.tail_nb.p, (const int *)d.l21.p, st));
-        LCHK(launch_dense_refactor(da, false, st));
+        LCHK(launch_dense_refactor(da, false, &la, st));
         phase_end(c, t0, PH_DENSE, (int)c->stats.dense_launches);
         d.S_prec = fp32 ? 1 : 0;
     }
@@ -705,7 +729,7 @@ int cktlu_create(cktlu_ctx **out, const cktlu_options *opt) {
     if (opt) c->opt = *opt; else cktlu_default_options(&c->opt);
     if (!(c->opt.pivot_eps > 0.0 && c->opt.pivot_eps <= 1.0) ||
         (c->opt.precision != CKTLU_FP64 && c->opt.precision != CKTLU_FP32_IR) || c->opt.ir_max_iter < 1 ||
-        c->opt.solve_chain_width < -1 ||
+        c->opt.solve_chain_width < -1 || (c->opt.dense_lookahead != 0 && c->opt.dense_lookahead != 1) ||
         (c->opt.dense_panel_width != 0 && c->opt.dense_panel_width != 64 && c->opt.dense_panel_width != 128 &&
          c->opt.dense_panel_width != 256)) {
         delete c;
@@ -725,6 +749,11 @@ void cktlu_destroy(cktlu_ctx *c) {
     for (hipEvent_t e : c->event_pool) (void)hipEventDestroy(e);
     if (c->graph_exec) (void)hipGraphExecDestroy(c->graph_exec);
     if (c->capture_stream) (void)hipStreamDestroy(c->capture_stream);
+    if (c->side_stream) {
+        (void)hipStreamSynchronize(c->side_stream);
+        (void)hipStreamDestroy(c->side_stream);
+    }
+    for (hipEvent_t e : c->la_events) (void)hipEventDestroy(e);
     free_device(c->dev);
     delete c;
 }
@@ -863,6 +892,7 @@ int cktlu_step_batched_graph(cktlu_ctx *c, int32_t batch, const double *values_d
     if (!c->graph_exec || !(key == c->graph_key)) {
         if (c->graph_exec) { (void)hipGraphExecDestroy(c->graph_exec); c->graph_exec = nullptr; }
         if (!c->capture_stream) HIPCHK(hipStreamCreateWithFlags(&c->capture_stream, hipStreamNonBlocking));
+        if (c->s.tail0 < c->an.n && (rc = ensure_lookahead(c, dense_args(c, batch, fp32)))) return rc;
         // everything below is enqueued on the capture stream and recorded, not run
         HIPCHK(hipStreamSynchronize(user));
         void *saved_stream = c->opt.stream;

@@ -627,7 +627,12 @@ int launch_schur(const DenseArgs &a, const int *tail_nb, const int *l21, void *s
     return (int)hipGetLastError();
 }
 
-int launch_dense_refactor(const DenseArgs &a, bool gather, void *stream) {
+int dense_lookahead_events(const DenseArgs &a) {
+    const int groups = (a.D + a.W - 1) / a.W;
+    return groups >= 2 ? 2 * (groups - 1) : 0;
+}
+
+int launch_dense_refactor(const DenseArgs &a, bool gather, const DenseStreams *la, void *stream) {
     hipStream_t st = (hipStream_t)stream;
     const int D = a.D;
     if (D <= 0) return 0;
@@ -646,33 +651,60 @@ int launch_dense_refactor(const DenseArgs &a, bool gather, void *stream) {
         g.nt = g.ntx ? g.ntx * ((c1 - c0 + 127) / 128) : 0;
         return g;
     };
-    auto gemm = [&](int kp, int kw, const GemmRect &g0, const GemmRect &g1, int dgp) {
+    auto gemm = [&](hipStream_t s, int kp, int kw, const GemmRect &g0, const GemmRect &g1, int dgp) {
         const dim3 gg((unsigned)(g0.nt + g1.nt), 1, (unsigned)a.batch);
         if (kw == 64) {
-            if (a.fp32) hipLaunchKernelGGL((dlu_gemm_kernel<float, 64>), gg, dim3(256), 0, st, a, kp, g0, g1, dgp);
-            else hipLaunchKernelGGL((dlu_gemm_kernel<double, 64>), gg, dim3(256), 0, st, a, kp, g0, g1, dgp);
+            if (a.fp32) hipLaunchKernelGGL((dlu_gemm_kernel<float, 64>), gg, dim3(256), 0, s, a, kp, g0, g1, dgp);
+            else hipLaunchKernelGGL((dlu_gemm_kernel<double, 64>), gg, dim3(256), 0, s, a, kp, g0, g1, dgp);
         } else if (kw == 128) {
-            if (a.fp32) hipLaunchKernelGGL((dlu_gemm_kernel<float, 128>), gg, dim3(256), 0, st, a, kp, g0, g1, dgp);
-            else hipLaunchKernelGGL((dlu_gemm_kernel<double, 128>), gg, dim3(256), 0, st, a, kp, g0, g1, dgp);
+            if (a.fp32) hipLaunchKernelGGL((dlu_gemm_kernel<float, 128>), gg, dim3(256), 0, s, a, kp, g0, g1, dgp);
+            else hipLaunchKernelGGL((dlu_gemm_kernel<double, 128>), gg, dim3(256), 0, s, a, kp, g0, g1, dgp);
         } else {
-            if (a.fp32) hipLaunchKernelGGL((dlu_gemm_kernel<float, 256>), gg, dim3(256), 0, st, a, kp, g0, g1, dgp);
-            else hipLaunchKernelGGL((dlu_gemm_kernel<double, 256>), gg, dim3(256), 0, st, a, kp, g0, g1, dgp);
+            if (a.fp32) hipLaunchKernelGGL((dlu_gemm_kernel<float, 256>), gg, dim3(256), 0, s, a, kp, g0, g1, dgp);
+            else hipLaunchKernelGGL((dlu_gemm_kernel<double, 256>), gg, dim3(256), 0, s, a, kp, g0, g1, dgp);
         }
     };
-    const int W = a.W;
-    for (int p = 0; p < D; p += W) {
-        const int pe = D - p < W ? D : p + W;         // end of this group
+    // the panels of the group [p, pe) and the updates inside the group
+    auto chain = [&](hipStream_t s, int p, int pe) {
         for (int q = p; q < pe; q += NB) {
             const int nb = D - q < NB ? D - q : NB;
             const int rest = D - q - nb;               // > 0 only for full panels
             const int nrb = (rest + 63) / 64, ncb = (rest + 63) / 64;
             const dim3 gp((unsigned)(1 + nrb + ncb), (unsigned)a.batch);
-            if (a.fp32) hipLaunchKernelGGL((dlu_panel_kernel<float>), gp, dim3(256), 0, st, a, q, nrb);
-            else hipLaunchKernelGGL((dlu_panel_kernel<double>), gp, dim3(256), 0, st, a, q, nrb);
+            if (a.fp32) hipLaunchKernelGGL((dlu_panel_kernel<float>), gp, dim3(256), 0, s, a, q, nrb);
+            else hipLaunchKernelGGL((dlu_panel_kernel<double>), gp, dim3(256), 0, s, a, q, nrb);
             const int q1 = q + NB;
-            if (q1 < pe) gemm(q, NB, rect(q1, D, q1, pe), rect(q1, pe, pe, D), q);
+            if (q1 < pe) gemm(s, q, NB, rect(q1, D, q1, pe), rect(q1, pe, pe, D), q);
         }
-        if (pe < D) gemm(p, pe - p, rect(pe, D, pe, D), rect(0, 0, 0, 0), pe - NB);
+    };
+    const int W = a.W;
+    const int nev = dense_lookahead_events(a);
+    if (!la || !la->side || nev == 0 || la->nev < nev) {
+        for (int p = 0; p < D; p += W) {
+            const int pe = D - p < W ? D : p + W;
+            chain(st, p, pe);
+            if (pe < D) gemm(st, p, pe - p, rect(pe, D, pe, D), rect(0, 0, 0, 0), pe - NB);
+        }
+    } else {
+        // look-ahead: after group g, its update of the next group's columns and rows comes
+        // first; the next group's panels then run on the side stream while the rest of
+        // the trailing block is updated here.  The two touch disjoint parts of S: the
+        // panels and in-group updates of group g+1 stay in its rows or columns, the rest
+        // of the update stays in rows and columns past it.
+        hipStream_t sd = (hipStream_t)la->side;
+        chain(st, 0, W);
+        for (int g = 0, p = 0; p + W < D; g++, p += W) {
+            const int pe = p + W, pe2 = D - pe < W ? D : pe + W;
+            gemm(st, p, W, rect(pe, D, pe, pe2), rect(pe, pe2, pe2, D), pe - NB);
+            hipEvent_t e0 = (hipEvent_t)la->ev[2 * g], e1 = (hipEvent_t)la->ev[2 * g + 1];
+            hipError_t err = hipEventRecord(e0, st);
+            if (err == hipSuccess) err = hipStreamWaitEvent(sd, e0, 0);
+            if (err != hipSuccess) return (int)err;
+            chain(sd, pe, pe2);
+            if ((err = hipEventRecord(e1, sd)) != hipSuccess) return (int)err;
+            if (pe2 < D) gemm(st, p, W, rect(pe2, D, pe2, D), rect(0, 0, 0, 0), -1);
+            if ((err = hipStreamWaitEvent(st, e1, 0)) != hipSuccess) return (int)err;
+        }
     }
     if (a.check) {
         if (a.fp32) hipLaunchKernelGGL((dlu_check_kernel<float>), gw, dim3(256), 0, st, a);

@@ -230,8 +230,18 @@ struct DenseArgs {
 int launch_dense_gather(const DenseArgs &a, void *stream);
 // S -= L21 U12: the sparse columns' contributions to the dense block, after the sweep
 int launch_schur(const DenseArgs &a, const int *tail_nb, const int *l21, void *stream);
+// Look-ahead resources of the dense LU: a second stream (default priority) on which the
+// panels of group g+1 run while the trailing update of group g runs on the main stream,
+// and events that order the two (2 per group boundary).  side == nullptr: one stream.
+struct DenseStreams {
+    void *side;
+    void *const *ev;
+    int nev;
+};
 // (gather if asked), blocked LU with the pivot test, scatter back into Fx
-int launch_dense_refactor(const DenseArgs &a, bool gather, void *stream);
+int launch_dense_refactor(const DenseArgs &a, bool gather, const DenseStreams *la, void *stream);
+// events the look-ahead needs for this dense block (0: it runs on one stream)
+int dense_lookahead_events(const DenseArgs &a);
 // y rows [T, n): lower (unit) or upper triangular solve with the block in S
 int launch_dense_solve(const DenseArgs &a, double *y, int nrhs, const int *skip, bool upper, void *stream);
 

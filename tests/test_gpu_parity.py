@@ -488,3 +488,31 @@ def test_dense_panel_widths(ck, oracle_mod, width, tail):
             fb = s.factors(instance=i)
             for k in ("Lx", "Ux"):
                 assert np.array_equal(fb[k], f1[k]), (i, k)
+
+
+@pytest.mark.parametrize("width", [64, 256])
+def test_dense_lookahead_identical(ck, width):
+    """The look-ahead (the next group's panels on a second stream while the trailing
+    update of the current group runs) performs the same operations on disjoint parts of
+    the dense block, so factors and solutions are bit-identical to one stream; a
+    batch of instances with one failing sweep included."""
+    c = mnagen.mesh_transistor(40, 40, seed=24)
+    batch = 3
+    V = mnagen.instance_values(c, batch, 0.1, seed=24)
+    out = {}
+    for la in (0, 1):
+        say("lookahead", la, "width", width)
+        s = ck.SparseLU(c.n, c.colptr, c.rowind, eps=EPS, dense_tail=600, dense_panel_width=width,
+                        dense_lookahead=la)
+        s.factorize(dev(c.values))
+        st = torch.zeros(batch, dtype=torch.int32, device="cuda:0")
+        s.refactorize_batched(batch, dev(V), st)
+        X = torch.zeros((batch, 1, c.n), dtype=torch.float64, device="cuda:0")
+        s.solve_batched(batch, 1, dev(np.repeat(c.rhs[:1][None], batch, axis=0)), X, st)
+        torch.cuda.synchronize()
+        out[la] = ([s.factors(instance=i) for i in range(batch)], X.cpu().numpy(), st.cpu().numpy())
+    assert np.array_equal(out[0][2], out[1][2])
+    assert np.array_equal(out[0][1], out[1][1])
+    for i in range(batch):
+        for k in ("Lx", "Ux"):
+            assert np.array_equal(out[0][0][i][k], out[1][0][i][k]), (i, k)
