@@ -28,6 +28,8 @@ WORKLOADS = {
                              desc="post-layout RC mesh 3x300x300 + vias + transistor stamps"),
     "mesh_transistor_141": dict(make=lambda: __import__("mnagen").mesh_transistor(141, 141, seed=0), cfg=3,
                                 desc="mesh 141x141 + transistor stamps"),
+    "power_grid_1000_8rhs": dict(make=lambda: __import__("mnagen").power_grid(1000, 1000, seed=0), cfg=4, nrhs=8,
+                                 desc="power grid 1000x1000 (n = 1M), pads and current loads, 8 right-hand sides"),
     "mesh_vsrc_32": dict(make=lambda: __import__("mnagen").mesh_vsrc(32, 32, 4, seed=0), cfg=1,
                          desc="mesh 32x32 + 4 ideal voltage sources"),
     "serving_mix": dict(make=None, cfg=5, serving=True,
@@ -208,6 +210,7 @@ def log(*a):
 
 
 def run_leg(ck, torch, c, vals_dev, b_dev, precision, steps, warmup, tail_opts):
+    nrhs = b_dev.shape[0] if b_dev.dim() == 2 else 1
     s = ck.SparseLU(c.n, c.colptr, c.rowind, eps=1e-3, precision=precision, ir_tol=1e-10, timing=True,
                     **{k: v for k, v in tail_opts.items() if k != "autotune"})
     t0 = time.time()
@@ -220,7 +223,7 @@ def run_leg(ck, torch, c, vals_dev, b_dev, precision, steps, warmup, tail_opts):
     for w in range(warmup):
         rc, info = s.refactorize(vals_dev[1 + w])
         nrep += info.repivoted
-        s.solve(b_dev, x)
+        s.solve(b_dev, x, nrhs=nrhs)
     torch.cuda.synchronize()
     s.timing(reset=True)                         # phase times of the timed steps only
     ev = [[torch.cuda.Event(enable_timing=True) for _ in range(3)] for _ in range(steps)]
@@ -232,7 +235,7 @@ def run_leg(ck, torch, c, vals_dev, b_dev, precision, steps, warmup, tail_opts):
         e0.record()
         rc, info = s.refactorize(vals_dev[1 + warmup + t])
         e1.record()
-        rc2, sinfo = s.solve(b_dev, x)
+        rc2, sinfo = s.solve(b_dev, x, nrhs=nrhs)
         e2.record()
         nrep += info.repivoted
         infos.append((sinfo.ir_iters, sinfo.backward_err, sinfo.used_fp64))
@@ -318,8 +321,9 @@ def main():
         vals = [c.values] + [mnagen.perturb(c.values, 0, wl["cfg"], t) for t in range(1, nvals)]
     dev = torch.device("cuda:0")
     vals_dev = [torch.tensor(v, device=dev) for v in vals]       # staged in HBM before timing
-    b = c.rhs[0]
-    b_dev = torch.tensor(b, device=dev)
+    nrhs = wl.get("nrhs", 1)
+    b = c.rhs[0] if nrhs == 1 else c.rhs[:nrhs]
+    b_dev = torch.tensor(np.ascontiguousarray(b), device=dev)
     torch.cuda.synchronize()
 
     tail_opts = dict(dense_tail=args.dense_tail, dense_tail_density=args.dense_density, autotune=args.autotune,
@@ -332,8 +336,9 @@ def main():
     x64 = res64["x"].cpu().numpy()
     import scipy.sparse as sp
     A_last = sp.csc_matrix((vals[-1], c.rowind, c.colptr), shape=(c.n, c.n))
-    eta64 = float(np.abs(b - A_last @ x64).max() /
-                  (abs(A_last).sum(axis=1).max() * np.abs(x64).max() + np.abs(b).max()))
+    anorm = abs(A_last).sum(axis=1).max()
+    eta64 = max(float(np.abs(bb - A_last @ xx).max() / (anorm * np.abs(xx).max() + np.abs(bb).max()))
+                for bb, xx in zip(np.atleast_2d(b), np.atleast_2d(x64)))
 
     out_fp32 = None
     if not args.no_fp32:
@@ -370,12 +375,13 @@ def main():
                               achieved=tf, peak=FP64_MFMA_PEAK_TFS, unit="TFLOP/s", frac=tf / FP64_MFMA_PEAK_TFS,
                               order=int(st["dense_tail"]))
     npass = max(1, tm["solve_passes"])
-    phases = dict(init=tm["init_ms"] / nref, sweep=tm["sweep_ms"] / nref, dense=tm["dense_ms"] / nref,
-                  solve_sparse=tm["solve_sparse_ms"] / npass, solve_dense=tm["solve_dense_ms"] / npass)
+    phases = dict(init=tm["init_ms"] / nref, sweep=tm["sweep_ms"] / nref, schur=tm["schur_ms"] / nref,
+                  dense=tm["dense_ms"] / nref, solve_sparse=tm["solve_sparse_ms"] / npass,
+                  solve_dense=tm["solve_dense_ms"] / npass)
 
     cpu = None
     if not args.no_cpu_baseline:
-        cpu, xo = cpu_baseline(c, vals, b)
+        cpu, xo = cpu_baseline(c, vals, np.atleast_2d(b)[0])
         log("cpu oracle: %.4f steps/s" % cpu["value"])
 
     value = args.steps / res64["wall"]
@@ -386,6 +392,7 @@ def main():
         "vs_baseline": None, "dtype": "f64", "data": "synthetic",
         "config": {"workload": wl["desc"], "n": c.n, "nnz": c.nnz, "nnz_lu": st["nnz_l"] + st["nnz_u"],
                    "flops_per_refactor": st["flops"], "levels": st["levels"], "dense_tail": st["dense_tail"],
+                   "nrhs": nrhs,
                    "value_perturbation": "+-5%% per %s" % args.perturb},
         "p50_ms": float(np.percentile(res64["step_ms"], 50)),
         "p99_ms": float(np.percentile(res64["step_ms"], 99)),

@@ -122,12 +122,13 @@ typedef struct {
 typedef struct {
     double init_ms;        /* value scatter into the factor storage */
     double sweep_ms;       /* right-looking level sweep over the sparse columns */
-    double dense_ms;       /* dense trailing block: panels, MFMA updates, pivot test, scatter */
+    double dense_ms;       /* dense trailing block LU: panels, MFMA updates, pivot test, scatter */
     double solve_sparse_ms;/* sparse levels of the L and U solves */
     double solve_dense_ms; /* dense block solves */
     int64_t refactors;     /* refactorizations timed */
     int64_t solve_passes;  /* triangular solve passes timed (each covers up to 8 right-hand sides) */
     int64_t sweep_launches, dense_launches, solve_sparse_launches, solve_dense_launches;
+    double schur_ms;       /* the sparse columns' update of the dense block, S -= L21 U12 (not in dense_ms) */
 } cktlu_timing;
 
 /* Fill *opt with defaults. */

@@ -111,7 +111,8 @@ class cktlu_timing(ctypes.Structure):
                 ("solve_sparse_ms", ctypes.c_double), ("solve_dense_ms", ctypes.c_double),
                 ("refactors", ctypes.c_int64), ("solve_passes", ctypes.c_int64),
                 ("sweep_launches", ctypes.c_int64), ("dense_launches", ctypes.c_int64),
-                ("solve_sparse_launches", ctypes.c_int64), ("solve_dense_launches", ctypes.c_int64)]
+                ("solve_sparse_launches", ctypes.c_int64), ("solve_dense_launches", ctypes.c_int64),
+                ("schur_ms", ctypes.c_double)]
 
     def as_dict(self):
         return {f: getattr(self, f) for f, _ in self._fields_}

@@ -83,7 +83,7 @@ void debug_hip(int e, const char *what, int line) {
 inline hipStream_t stream_of(const cktlu_ctx *c) { return (hipStream_t)c->opt.stream; }
 
 // ---- phase timing (options.timing)
-enum { PH_INIT, PH_SWEEP, PH_DENSE, PH_SOLVE_SPARSE, PH_SOLVE_DENSE };
+enum { PH_INIT, PH_SWEEP, PH_DENSE, PH_SOLVE_SPARSE, PH_SOLVE_DENSE, PH_SCHUR };
 
 hipEvent_t take_event(cktlu_ctx *c) {
     if (!c->event_pool.empty()) {
@@ -128,6 +128,7 @@ int collect_timing(cktlu_ctx *c) {
             case PH_INIT: t.init_ms += ms; break;
             case PH_SWEEP: t.sweep_ms += ms; t.sweep_launches += p.launches; break;
             case PH_DENSE: t.dense_ms += ms; t.dense_launches += p.launches; break;
+            case PH_SCHUR: t.schur_ms += ms; break;
             case PH_SOLVE_SPARSE: t.solve_sparse_ms += ms; t.solve_sparse_launches += p.launches; break;
             case PH_SOLVE_DENSE: t.solve_dense_ms += ms; t.solve_dense_launches += p.launches; break;
         }
@@ -486,6 +487,8 @@ int run_refactor(cktlu_ctx *c, int batch, const double *values_dev, bool fp32, b
         }
         t0 = phase_begin(c);
         LCHK(launch_schur(da, (const int *)d.tail_nb.p, (const int *)d.l21.p, st));
+        phase_end(c, t0, PH_SCHUR, 1);
+        t0 = phase_begin(c);
         LCHK(launch_dense_refactor(da, false, &la, st));
         phase_end(c, t0, PH_DENSE, (int)c->stats.dense_launches);
         d.S_prec = fp32 ? 1 : 0;
@@ -603,7 +606,8 @@ int tri_solves(cktlu_ctx *c, int nrhs, int batch, double *z, bool fp32, const in
     hipEvent_t t0 = phase_begin(c);
     for (size_t g = 0; g < s.lseg.size(); g += 3) {
         const int l0 = s.lseg[g], l1 = s.lseg[g + 1];
-        if (s.lseg[g + 2]) LCHK(launch_lsolve_chain(a, (const int *)d.lsptr.p, l0, l1, st));
+        if (s.lseg[g + 2] == 1) LCHK(launch_lsolve_chain(a, (const int *)d.lsptr.p, l0, l1, st));
+        else if (s.lseg[g + 2] == 2) LCHK(launch_lsolve_level_wg(a, s.lsptr[l0], s.lsptr[l1], st));
         else LCHK(launch_lsolve_level(a, s.lsptr[l0], s.lsptr[l1], st));
     }
     phase_end(c, t0, PH_SOLVE_SPARSE, (int)s.lseg.size() / 3);
@@ -620,7 +624,8 @@ int tri_solves(cktlu_ctx *c, int nrhs, int batch, double *z, bool fp32, const in
     t0 = phase_begin(c);
     for (size_t g = 0; g < s.useg.size(); g += 3) {
         const int l0 = s.useg[g], l1 = s.useg[g + 1];
-        if (s.useg[g + 2]) LCHK(launch_usolve_chain(a, (const int *)d.usptr.p, l0, l1, st));
+        if (s.useg[g + 2] == 1) LCHK(launch_usolve_chain(a, (const int *)d.usptr.p, l0, l1, st));
+        else if (s.useg[g + 2] == 2) LCHK(launch_usolve_level_wg(a, s.usptr[l0], s.usptr[l1], st));
         else LCHK(launch_usolve_level(a, s.usptr[l0], s.usptr[l1], st));
     }
     phase_end(c, t0, PH_SOLVE_SPARSE, (int)s.useg.size() / 3);
@@ -924,7 +929,6 @@ int cktlu_step_batched_graph(cktlu_ctx *c, int32_t batch, const double *values_d
             const int *Acp = (const int *)c->dev.Acp.p, *Acj = (const int *)c->dev.Acj.p;
             const int *Acsrc = (const int *)c->dev.Acsrc.p;
             const double *Aval = (const double *)c->dev.Aval.p;
-            LCHK(launch_fill_f64(x, (int64_t)nv, 0.0, st));
             LCHK(launch_fill_f64(anorm, batch, 0.0, st));
             LCHK(launch_fill_f64(eta, batch, -1.0, st));
             LCHK(launch_anorm_batched(n, batch, nnzA, Acp, Acsrc, Aval, anorm, st));
@@ -932,7 +936,8 @@ int cktlu_step_batched_graph(cktlu_ctx *c, int32_t batch, const double *values_d
             for (int it = 1; it <= ir_steps; it++) {
                 LCHK(launch_gather_rhs(n, nrhs, batch, it == 1 ? b : r, n, rowperm, z, st));
                 if ((e = tri_solves(c, nrhs, batch, z, true, skip))) return e;
-                LCHK(launch_scatter_sol(n, nrhs, batch, z, colperm, x, n, 1, skip, st));
+                // x = d on the first step (x of skipped instances is never written), then x += d
+                LCHK(launch_scatter_sol(n, nrhs, batch, z, colperm, x, n, it > 1 ? 1 : 0, skip, st));
                 LCHK(launch_fill_f64(norms, 3 * (int64_t)nrhs * batch, 0.0, st));
                 LCHK(launch_residual_batched(n, nrhs, batch, nnzA, Acp, Acj, Acsrc, Aval, x, b, r, norms, skip, st));
                 LCHK(launch_ir_check(batch, nrhs, norms, anorm, c->opt.ir_tol, skip, eta, st));
@@ -1097,7 +1102,6 @@ int cktlu_solve_batched(cktlu_ctx *c, int32_t batch, int32_t nrhs, const double 
     const int *Acp = (const int *)c->dev.Acp.p, *Acj = (const int *)c->dev.Acj.p;
     const int *Acsrc = (const int *)c->dev.Acsrc.p;
     const double *Aval = (const double *)c->dev.Aval.p;
-    LCHK(launch_fill_f64(x, (int64_t)nv, 0.0, st));
     LCHK(launch_fill_f64(anorm, batch, 0.0, st));
     LCHK(launch_anorm_batched(n, batch, nnzA, Acp, Acsrc, Aval, anorm, st));
     LCHK(launch_copy_i32(status_dev, skip, batch, st));
@@ -1108,7 +1112,8 @@ int cktlu_solve_batched(cktlu_ctx *c, int32_t batch, int32_t nrhs, const double 
     for (int it = 1; it <= c->opt.ir_max_iter; it++) {
         LCHK(launch_gather_rhs(n, nrhs, batch, it == 1 ? b : r, n, rowperm, z, st));
         if ((rc = tri_solves(c, nrhs, batch, z, true, skip))) return rc;
-        LCHK(launch_scatter_sol(n, nrhs, batch, z, colperm, x, n, 1, skip, st));
+        // x = d on the first step (x of skipped instances is never written), then x += d
+        LCHK(launch_scatter_sol(n, nrhs, batch, z, colperm, x, n, it > 1 ? 1 : 0, skip, st));
         LCHK(launch_fill_f64(norms, 3 * (int64_t)nrhs * batch, 0.0, st));
         LCHK(launch_residual_batched(n, nrhs, batch, nnzA, Acp, Acj, Acsrc, Aval, x, b, r, norms, skip, st));
         LCHK(launch_ir_check(batch, nrhs, norms, anorm, c->opt.ir_tol, skip, eta, st));

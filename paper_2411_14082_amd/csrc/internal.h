@@ -82,7 +82,7 @@ struct Schedule {
     std::vector<int> Lrp, Lrj, Lrsrc, Urp, Urj, Ursrc, udiag;
     // solve dependency graphs: rows by level (L: ascending dependencies, U: descending)
     std::vector<int> lseq, lsptr, useq, usptr;
-    std::vector<int> lseg, useg;              // launch segments {first level, end level, chained}
+    std::vector<int> lseg, useg;              // launch segments {first level, end level, kind}
     std::vector<int> rowperm_final;           // position k <- user row
     // user-space CSR of A (for the FP64 residual of iterative refinement)
     std::vector<int> Acp, Acj, Acsrc;
@@ -133,6 +133,7 @@ namespace cktlu_dev {
 
 constexpr int kColAlign = 32;   // factor column alignment in entries (>= one 128-byte line)
 constexpr int YS = 16;          // doubles per solve-vector row (one 128-byte line); nrhs <= 8
+constexpr int kSolveRowWG = 256; // solve rows longer than this get a workgroup of this many threads
 // right-hand-side slots the solve kernels carry per row: nrhs rounded up to 1, 2, 4 or 8
 inline int solve_slots(int nrhs) { return nrhs <= 1 ? 1 : nrhs <= 2 ? 2 : nrhs <= 4 ? 4 : 8; }
 
@@ -178,6 +179,9 @@ struct SolveArgs {
 // Solve positions [lbeg, lend) of lrec / urec (one level of the solve graph).
 int launch_lsolve_level(const SolveArgs &a, int lbeg, int lend, void *stream);
 int launch_usolve_level(const SolveArgs &a, int lbeg, int lend, void *stream);
+// Solve positions [lbeg, lend) with one workgroup of kSolveRowWG threads per (row, instance).
+int launch_lsolve_level_wg(const SolveArgs &a, int lbeg, int lend, void *stream);
+int launch_usolve_level_wg(const SolveArgs &a, int lbeg, int lend, void *stream);
 // Levels [l0, l1) of the L / U solve graph in one launch: one workgroup per instance,
 // a barrier between levels; lvptr = level boundaries in solve positions (device).
 int launch_lsolve_chain(const SolveArgs &a, const int *lvptr, int l0, int l1, void *stream);

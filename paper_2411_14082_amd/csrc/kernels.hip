@@ -22,7 +22,9 @@
 //
 // Solves (Section II-C, Algorithm 2): trisolve_level_kernel, row ("pull") form,
 // one launch per level of the solve dependency graph, one wavefront per row;
-// runs of narrow levels go to trisolve_chain_kernel, one workgroup per instance.
+// levels with long rows go to trisolve_rowwg_kernel (a workgroup per row), and
+// runs of narrow levels optionally to trisolve_chain_kernel (a workgroup per
+// instance).
 //
 // All communication between workgroups happens at kernel boundaries, where the
 // runtime makes device memory coherent across the MI355X's eight XCDs; inside
@@ -430,6 +432,59 @@ __global__ __launch_bounds__(WG) void trisolve_level_kernel(SolveArgs a, int lbe
     solve_row<T, NR, UPPER>(a, inst, (int)(t / a.batch), lane);
 }
 
+// One level of long rows: a workgroup of kSolveRowWG threads per (row, instance);
+// thread t takes entries t, t + kSolveRowWG, ... (four in flight), the wavefront
+// sums are added in wavefront order.
+template <typename T, int NR, bool UPPER>
+__global__ __launch_bounds__(kSolveRowWG) void trisolve_rowwg_kernel(SolveArgs a, int lbeg, int lend) {
+    constexpr int NW = kSolveRowWG / WAVE;
+    __shared__ double part[NW][NR];
+    const int tid = threadIdx.x, lane = tid & (WAVE - 1), wv = tid / WAVE;
+    const int64_t t = (int64_t)lbeg * a.batch + blockIdx.x;
+    const int inst = (int)(t % a.batch);
+    if (a.skip && a.skip[inst] != -1) return;            // the whole workgroup
+    const int4 rec = reinterpret_cast<const int4 *>(UPPER ? a.urec : a.lrec)[t / a.batch];
+    const int2 *rjs = reinterpret_cast<const int2 *>(UPPER ? a.Urjs : a.Lrjs);
+    const T *Fx = reinterpret_cast<const T *>(a.Fx) + (size_t)inst * a.nnzF;
+    double *y = a.y + (size_t)inst * a.n * YS;
+    double acc[NR];
+#pragma unroll
+    for (int r = 0; r < NR; r++) acc[r] = 0.0;
+    for (int q0 = rec.y; q0 < rec.z; q0 += 4 * kSolveRowWG) {
+        int2 e[4];
+#pragma unroll
+        for (int u = 0; u < 4; u++) {
+            const int q = q0 + u * kSolveRowWG + tid;
+            e[u] = q < rec.z ? rjs[q] : make_int2(-1, 0);
+        }
+        double l[4];
+#pragma unroll
+        for (int u = 0; u < 4; u++) l[u] = e[u].x >= 0 ? (double)Fx[e[u].y] : 0.0;
+#pragma unroll
+        for (int u = 0; u < 4; u++)
+            if (e[u].x >= 0) {
+#pragma unroll
+                for (int r = 0; r < NR; r++) acc[r] += l[u] * y[(size_t)e[u].x * YS + r];
+            }
+    }
+#pragma unroll
+    for (int r = 0; r < NR; r++) acc[r] = wave_sum(acc[r]);
+    if (lane == 0) {
+#pragma unroll
+        for (int r = 0; r < NR; r++) part[wv][r] = acc[r];
+    }
+    __syncthreads();
+    if (wv == 0 && lane < NR) {
+        double sum = part[0][lane];
+#pragma unroll
+        for (int w = 1; w < NW; w++) sum += part[w][lane];
+        const int i = rec.x;
+        double v = y[(size_t)i * YS + lane] - sum;
+        if (UPPER) v = v / (double)Fx[rec.w];
+        y[(size_t)i * YS + lane] = v;
+    }
+}
+
 // A run of narrow levels [l0, l1): one workgroup per instance takes the rows of a
 // level round-robin over its wavefronts, then waits at a barrier before the next
 // level (the barrier orders the workgroup's global stores before its later loads).
@@ -491,6 +546,35 @@ static int launch_solve_chain_impl(const SolveArgs &a, const int *lvptr, int l0,
     }
 #undef CKTLU_CHAIN_CASE
     return (int)hipGetLastError();
+}
+
+template <bool UPPER>
+static int launch_solve_rowwg_impl(const SolveArgs &a, int lbeg, int lend, void *stream) {
+    hipStream_t st = (hipStream_t)stream;
+    const dim3 grid((unsigned)((int64_t)(lend - lbeg) * a.batch));
+#define CKTLU_ROWWG_CASE(NRV)                                                                          \
+    case NRV:                                                                                          \
+        if (a.fp32)                                                                                    \
+            hipLaunchKernelGGL((trisolve_rowwg_kernel<float, NRV, UPPER>), grid, dim3(kSolveRowWG), 0, st, a, lbeg, lend); \
+        else                                                                                           \
+            hipLaunchKernelGGL((trisolve_rowwg_kernel<double, NRV, UPPER>), grid, dim3(kSolveRowWG), 0, st, a, lbeg, lend); \
+        break;
+    switch (a.nrhs) {
+        CKTLU_ROWWG_CASE(1)
+        CKTLU_ROWWG_CASE(2)
+        CKTLU_ROWWG_CASE(4)
+        CKTLU_ROWWG_CASE(8)
+        default: return (int)hipErrorInvalidValue;
+    }
+#undef CKTLU_ROWWG_CASE
+    return (int)hipGetLastError();
+}
+
+int launch_lsolve_level_wg(const SolveArgs &a, int lbeg, int lend, void *stream) {
+    return launch_solve_rowwg_impl<false>(a, lbeg, lend, stream);
+}
+int launch_usolve_level_wg(const SolveArgs &a, int lbeg, int lend, void *stream) {
+    return launch_solve_rowwg_impl<true>(a, lbeg, lend, stream);
 }
 
 int launch_lsolve_chain(const SolveArgs &a, const int *lvptr, int l0, int l1, void *stream) {

@@ -314,15 +314,27 @@ void build_schedule(const Analysis &an, const Factor &f, const cktlu_options &op
         for (size_t q = 0; q < s.Lrj.size(); q++) { s.Lrjs[2 * q] = s.Lrj[q]; s.Lrjs[2 * q + 1] = s.Lrsrc[q]; }
         s.Urjs.resize(2 * s.Urj.size());
         for (size_t q = 0; q < s.Urj.size(); q++) { s.Urjs[2 * q] = s.Urj[q]; s.Urjs[2 * q + 1] = s.Ursrc[q]; }
-        // launch segments: runs of two or more consecutive narrow levels go to one chained
-        // launch (a workgroup per instance steps through them with barriers in between)
+        // launch segments {first level, end level, kind}: kind 2 = a level with a row longer
+        // than kSolveRowWG entries (a workgroup per row); kind 1 = a run of two or more
+        // consecutive narrow levels of short rows (one chained launch, a workgroup per
+        // instance stepping through them); kind 0 = one level, a wavefront per row
         const int cw = opt.solve_chain_width == 0 ? -1 : opt.solve_chain_width;
-        auto segments = [cw](const std::vector<int> &ptr, std::vector<int> &seg) {
+        auto segments = [cw](const std::vector<int> &ptr, const std::vector<int> &rec, std::vector<int> &seg) {
             seg.clear();
             const int nl = (int)ptr.size() - 1;
+            auto long_rows = [&](int l) {
+                for (int q = ptr[l]; q < ptr[l + 1]; q++)
+                    if (rec[4 * q + 2] - rec[4 * q + 1] > cktlu_dev::kSolveRowWG) return true;
+                return false;
+            };
             for (int l = 0; l < nl;) {
+                if (long_rows(l)) {
+                    seg.insert(seg.end(), {l, l + 1, 2});
+                    l++;
+                    continue;
+                }
                 int e = l;
-                while (cw > 0 && e < nl && ptr[e + 1] - ptr[e] <= cw) e++;
+                while (cw > 0 && e < nl && ptr[e + 1] - ptr[e] <= cw && !long_rows(e)) e++;
                 if (e - l >= 2) {
                     seg.insert(seg.end(), {l, e, 1});
                     l = e;
@@ -332,8 +344,8 @@ void build_schedule(const Analysis &an, const Factor &f, const cktlu_options &op
                 }
             }
         };
-        segments(s.lsptr, s.lseg);
-        segments(s.usptr, s.useg);
+        segments(s.lsptr, s.lrec, s.lseg);
+        segments(s.usptr, s.urec, s.useg);
     }
     s.rowperm_final.resize(n);
     for (int k = 0; k < n; k++) s.rowperm_final[k] = an.rowperm_pre[f.pivrow[k]];

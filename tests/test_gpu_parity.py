@@ -516,3 +516,54 @@ def test_dense_lookahead_identical(ck, width):
     for i in range(batch):
         for k in ("Lx", "Ux"):
             assert np.array_equal(out[0][0][i][k], out[1][0][i][k]), (i, k)
+
+
+LONG_ROWS = [
+    ("power_grid_80", lambda: mnagen.power_grid(80, 80, n_src=50, seed=3)),      # L rows up to ~330
+    ("random_700", lambda: mnagen.random_pattern(700, 0.01, 6)),                 # L and U rows > 256
+    ("random_1400", lambda: mnagen.random_pattern(1400, 0.01, 8)),               # L rows > 1024 (two passes)
+]
+
+
+@pytest.mark.parametrize("nrhs", [1, 3])
+@pytest.mark.parametrize("name,make", LONG_ROWS, ids=[s[0] for s in LONG_ROWS])
+def test_solve_long_rows(ck, oracle_mod, name, make, nrhs):
+    """Levels holding a row longer than 256 entries run a workgroup per row; the
+    solutions reach eta <= 1e-12 and agree with the oracle's, single and batched
+    (one skipped instance), FP64 and FP32 factors with refinement."""
+    c = make()
+    say("long rows", name, "n", c.n, "nrhs", nrhs)
+    rng = np.random.default_rng(31)
+    B = rng.standard_normal((nrhs, c.n))
+    s = ck.SparseLU(c.n, c.colptr, c.rowind, eps=EPS, dense_tail=-1)
+    s.factorize(dev(c.values))
+    a0 = s.analysis()
+    X = torch.zeros((nrhs, c.n), dtype=torch.float64, device="cuda:0")
+    s.solve(dev(B), X, nrhs=nrhs)
+    torch.cuda.synchronize()
+    Xh = X.cpu().numpy()
+    lu = oracle_refactor(oracle_mod, c, c.values, a0, EPS, a0["pivrow"])
+    for r in range(nrhs):
+        assert oracle_mod.backward_error(c.colptr, c.rowind, c.values, Xh[r], B[r]) <= 1e-12
+        xo = oracle_mod.solve(lu, a0["rowperm_pre"], a0["colperm"], B[r])
+        assert np.abs(Xh[r] - xo).max() <= 1e-6 * np.abs(xo).max()
+    batch = 3
+    V = np.stack([mnagen.perturb(c.values, 31, 0, i) for i in range(batch)])
+    for prec, tol in ((ck.CKTLU_FP64, 1e-12), (ck.CKTLU_FP32_IR, 1e-10)):
+        sb = ck.SparseLU(c.n, c.colptr, c.rowind, eps=EPS, dense_tail=-1, precision=prec, ir_tol=1e-10)
+        sb.factorize(dev(c.values))
+        st = torch.zeros(batch, dtype=torch.int32, device="cuda:0")
+        sb.refactorize_batched(batch, dev(V), st)
+        st = torch.tensor(np.where(np.arange(batch) == 1, 4, st.cpu().numpy()), dtype=torch.int32, device="cuda:0")
+        Bb = rng.standard_normal((batch, nrhs, c.n))
+        Xb = torch.full((batch, nrhs, c.n), 7.0, dtype=torch.float64, device="cuda:0")
+        sb.solve_batched(batch, nrhs, dev(Bb), Xb, st)
+        torch.cuda.synchronize()
+        Xbh = Xb.cpu().numpy()
+        sth = st.cpu().numpy()
+        assert np.all(Xbh[1] == 7.0)
+        for i in (0, 2):
+            if sth[i] != -1:
+                continue
+            for r in range(nrhs):
+                assert oracle_mod.backward_error(c.colptr, c.rowind, V[i], Xbh[i, r], Bb[i, r]) <= tol, (prec, i, r)
