@@ -133,7 +133,9 @@ namespace cktlu_dev {
 
 constexpr int kColAlign = 32;   // factor column alignment in entries (>= one 128-byte line)
 constexpr int YS = 16;          // doubles per solve-vector row (one 128-byte line); nrhs <= 8
-constexpr int kSolveRowWG = 256; // solve rows longer than this get a workgroup of this many threads
+constexpr int kSolveRowWG = 256; // threads of the workgroup that solves one long row
+constexpr int kSolveLongRow = 64; // levels holding a longer row get a workgroup per row (64, 128 and
+                                  // 256 measured: 64 best on the RC mesh and the power grid)
 // right-hand-side slots the solve kernels carry per row: nrhs rounded up to 1, 2, 4 or 8
 inline int solve_slots(int nrhs) { return nrhs <= 1 ? 1 : nrhs <= 2 ? 2 : nrhs <= 4 ? 4 : 8; }
 

@@ -315,7 +315,7 @@ void build_schedule(const Analysis &an, const Factor &f, const cktlu_options &op
         s.Urjs.resize(2 * s.Urj.size());
         for (size_t q = 0; q < s.Urj.size(); q++) { s.Urjs[2 * q] = s.Urj[q]; s.Urjs[2 * q + 1] = s.Ursrc[q]; }
         // launch segments {first level, end level, kind}: kind 2 = a level with a row longer
-        // than kSolveRowWG entries (a workgroup per row); kind 1 = a run of two or more
+        // than kSolveLongRow entries (a workgroup per row); kind 1 = a run of two or more
         // consecutive narrow levels of short rows (one chained launch, a workgroup per
         // instance stepping through them); kind 0 = one level, a wavefront per row
         const int cw = opt.solve_chain_width == 0 ? -1 : opt.solve_chain_width;
@@ -324,7 +324,7 @@ void build_schedule(const Analysis &an, const Factor &f, const cktlu_options &op
             const int nl = (int)ptr.size() - 1;
             auto long_rows = [&](int l) {
                 for (int q = ptr[l]; q < ptr[l + 1]; q++)
-                    if (rec[4 * q + 2] - rec[4 * q + 1] > cktlu_dev::kSolveRowWG) return true;
+                    if (rec[4 * q + 2] - rec[4 * q + 1] > cktlu_dev::kSolveLongRow) return true;
                 return false;
             };
             for (int l = 0; l < nl;) {

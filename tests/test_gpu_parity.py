@@ -528,9 +528,10 @@ LONG_ROWS = [
 @pytest.mark.parametrize("nrhs", [1, 3])
 @pytest.mark.parametrize("name,make", LONG_ROWS, ids=[s[0] for s in LONG_ROWS])
 def test_solve_long_rows(ck, oracle_mod, name, make, nrhs):
-    """Levels holding a row longer than 256 entries run a workgroup per row; the
-    solutions reach eta <= 1e-12 and agree with the oracle's, single and batched
-    (one skipped instance), FP64 and FP32 factors with refinement."""
+    """Levels holding a row longer than 64 entries run a workgroup per row (rows past
+    1024 entries take several passes); the solutions reach eta <= 1e-12 and agree
+    with the oracle's, single and batched (one skipped instance), FP64 and FP32
+    factors with refinement."""
     c = make()
     say("long rows", name, "n", c.n, "nrhs", nrhs)
     rng = np.random.default_rng(31)
