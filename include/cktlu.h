@@ -81,6 +81,9 @@ typedef struct {
                               context while the trailing update of the current group runs (same results);
                               0 (default) = one stream, which measured faster: the update's workgroups fill
                               the device and the panels waited for them */
+    int dense_device_repivot; /* pivot-check fallback: 0 (default) re-factors the dense block on the device
+                              with the threshold pivot rule when every column to restart lies in it (the
+                              host then computes only the new pattern); -1 = always the host fallback */
 } cktlu_options;
 
 typedef struct {
@@ -115,6 +118,8 @@ typedef struct {
     int64_t sweep_launches;           /* kernel launches of one sparse sweep */
     int64_t dense_launches;           /* kernel launches of one dense-block factorization */
     int64_t solve_launches;           /* kernel launches of one triangular solve pass (L and U) */
+    int64_t n_device_repivot;         /* fallbacks whose restart set lay inside the dense block and were
+                                         re-factored on the device (pivoted dense LU) */
 } cktlu_stats;
 
 /* Device time of the phases, accumulated over the calls made with options.timing = 1

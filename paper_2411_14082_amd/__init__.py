@@ -53,7 +53,8 @@ class cktlu_options(ctypes.Structure):
                 ("stream", ctypes.c_void_p), ("force_fail_col", ctypes.c_int),
                 ("dense_tail_size", ctypes.c_int), ("dense_tail_density", ctypes.c_double),
                 ("timing", ctypes.c_int), ("solve_chain_width", ctypes.c_int),
-                ("dense_panel_width", ctypes.c_int), ("dense_lookahead", ctypes.c_int)]
+                ("dense_panel_width", ctypes.c_int), ("dense_lookahead", ctypes.c_int),
+                ("dense_device_repivot", ctypes.c_int)]
 
 
 class cktlu_refactor_info(ctypes.Structure):
@@ -75,7 +76,8 @@ class cktlu_stats(ctypes.Structure):
                 ("bytes_refactor", ctypes.c_double), ("bytes_solve", ctypes.c_double),
                 ("macs_sweep", ctypes.c_double), ("bytes_sweep", ctypes.c_double),
                 ("flops_dense", ctypes.c_double), ("macs_schur", ctypes.c_double), ("sweep_launches", ctypes.c_int64),
-                ("dense_launches", ctypes.c_int64), ("solve_launches", ctypes.c_int64)]
+                ("dense_launches", ctypes.c_int64), ("solve_launches", ctypes.c_int64),
+                ("n_device_repivot", ctypes.c_int64)]
 
     def as_dict(self):
         return {f: getattr(self, f) for f, _ in self._fields_}
@@ -380,7 +382,7 @@ class SparseLU:
     def __init__(self, n, colptr, rowind, eps=1e-3, precision=CKTLU_FP64, ordering=CKTLU_ORDER_AMD,
                  ir_tol=1e-10, ir_max_iter=10, stream=None, transversal=1, dense_tail=None,
                  dense_tail_density=None, timing=False, solve_chain_width=None, dense_panel_width=None,
-                 dense_lookahead=None):
+                 dense_lookahead=None, dense_device_repivot=None):
         opt = cktlu_default_options()
         opt.timing = 1 if timing else 0
         if dense_tail is not None:
@@ -393,6 +395,8 @@ class SparseLU:
             opt.dense_panel_width = int(dense_panel_width)
         if dense_lookahead is not None:
             opt.dense_lookahead = int(dense_lookahead)
+        if dense_device_repivot is not None:
+            opt.dense_device_repivot = int(dense_device_repivot)
         opt.pivot_eps = eps
         opt.precision = precision
         opt.ordering = ordering

@@ -3,6 +3,7 @@
 #include <hip/hip_runtime_api.h>
 
 #include <algorithm>
+#include <chrono>
 #include <climits>
 #include <cmath>
 #include <cstdio>
@@ -325,7 +326,8 @@ void fill_stats_pattern(cktlu_ctx *c) {
 
 // Host factorization with pivoting (keep == nullptr: every column), then
 // schedule and upload.
-int factor_and_setup(cktlu_ctx *c, const double *values_host, const std::vector<char> *keep, bool device) {
+int factor_and_setup(cktlu_ctx *c, const double *values_host, const std::vector<char> *keep, bool device,
+                     const DenseSource *dsrc = nullptr) {
     std::vector<int> init = c->f.pivrow;
     if ((int)init.size() != c->an.n) {
         init.resize(c->an.n);
@@ -334,7 +336,7 @@ int factor_and_setup(cktlu_ctx *c, const double *values_host, const std::vector<
     Factor nf;
     int fail = -1, nswaps = 0;
     int rc = host_gp_factor(c->an, values_host, c->opt.pivot_eps, init, keep ? &c->f : nullptr, keep, nf,
-                            fail, nswaps);
+                            fail, nswaps, dsrc);
     if (rc != CKTLU_OK) return rc;
     // same pattern and pivot sequence: the device schedule stays valid, only values change
     const bool same = !c->f.Fi.empty() && nf.Fi == c->f.Fi && nf.Fp == c->f.Fp && nf.pivrow == c->f.pivrow;
@@ -498,6 +500,71 @@ int run_refactor(cktlu_ctx *c, int batch, const double *values_dev, bool fp32, b
 
 // Pivot-check fallback (Sections IV-C, IV-D): restart set from the unfinished
 // columns, host re-factorization of that set with pivoting, re-setup.
+// Device re-factorization of the dense block with pivoting (instead of the host
+// fallback when every column to restart lies in the block): S = A22 - L21 U12 again, the
+// pivoted dense LU, then the host takes its pivots and values and computes only the
+// new pattern.  Returns 1 when the block had no usable pivot somewhere (the caller
+// then takes the host path), CKTLU_OK when done, or an error.
+int dense_pivot_refactor(cktlu_ctx *c, const std::vector<double> &vals, cktlu_refactor_info *info) {
+    const int n = c->an.n, T = c->s.tail0, D = n - T;
+    Device &d = c->dev;
+    hipStream_t st = stream_of(c);
+    RefactorArgs ra;
+    std::memset(&ra, 0, sizeof(ra));
+    ra.n = n; ra.batch = 1; ra.T = T; ra.D = D;
+    ra.Dp = (const int *)d.Dp.p; ra.Fi = (const int *)d.Fi.p; ra.Ap = (const int *)d.Ap.p;
+    ra.colperm = (const int *)d.colperm.p; ra.amap = (const int *)d.amap.p;
+    ra.Aval = (const double *)d.Aval.p; ra.S = d.S.p;
+    DenseArgs da = dense_args(c, 1, false);
+    da.ctrl = (int *)d.ctrl.p;
+    da.done = (int *)d.done.p;
+    da.eps = c->opt.pivot_eps;
+    DevBuf tmp;
+    int rc = dalloc(tmp, (size_t)(D + 1) * sizeof(int));
+    if (rc) return rc;
+    struct Free { DevBuf &b; ~Free() { dfree(b); } } guard{tmp};
+    int *swp = (int *)tmp.p, *dinfo = swp + D;
+    const auto t0 = std::chrono::steady_clock::now();
+    LCHK(launch_dense_reinit(ra, st));
+    LCHK(launch_schur(da, (const int *)d.tail_nb.p, (const int *)d.l21.p, st));
+    LCHK(launch_dense_pivoted_lu(da, swp, dinfo, st));
+    std::vector<double> Sh((size_t)D * D);
+    std::vector<int> sw(D + 1);
+    HIPCHK(hipMemcpyAsync(Sh.data(), d.S.p, Sh.size() * sizeof(double), hipMemcpyDeviceToHost, st));
+    HIPCHK(hipMemcpyAsync(sw.data(), swp, (size_t)(D + 1) * sizeof(int), hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    d.S_prec = -1;
+    if (sw[D] != 0) {
+        if (debug_on()) fprintf(stderr, "[cktlu] dense re-pivot: no usable pivot at block column %d\n", sw[D] - 1);
+        return 1;
+    }
+    std::vector<char> keep(n, 0);
+    for (int k = 0; k < T; k++) keep[k] = 1;
+    DenseSource ds;
+    ds.T = T; ds.D = D; ds.swap = sw.data(); ds.S = Sh.data();
+    std::vector<int> oldFi = c->f.Fi;
+    const auto t1 = std::chrono::steady_clock::now();
+    rc = factor_and_setup(c, vals.data(), &keep, true, &ds);
+    if (debug_on())
+        fprintf(stderr, "[cktlu] dense re-pivot: device LU and copy %.3f s, pattern and set-up %.3f s\n",
+                std::chrono::duration<double>(t1 - t0).count(),
+                std::chrono::duration<double>(std::chrono::steady_clock::now() - t1).count());
+    if (rc == CKTLU_E_STATE) {                              // the block disagreed with the pattern: host path
+        if (debug_on()) fprintf(stderr, "[cktlu] dense re-pivot: pattern disagreement, host fallback\n");
+        return 1;
+    }
+    if (rc != CKTLU_OK) return rc;
+    c->stats.n_repivot++;
+    c->stats.n_restart_cols += D;
+    c->stats.n_device_repivot++;
+    if (info) {
+        info->repivoted = 1;
+        info->restart_size = D;
+        info->pattern_changed = oldFi != c->f.Fi;
+    }
+    return CKTLU_OK;
+}
+
 int fallback(cktlu_ctx *c, const double *values_dev, cktlu_refactor_info *info) {
     const int n = c->an.n;
     hipStream_t st = stream_of(c);
@@ -512,10 +579,26 @@ int fallback(cktlu_ctx *c, const double *values_dev, cktlu_refactor_info *info) 
     std::vector<char> unfinished(n), in_set, keep(n);
     for (int k = 0; k < n; k++) unfinished[k] = done[k] != (int)c->dev.epoch;
     restart_closure(c->an.parent, unfinished, in_set);
-    int rsize = 0;
-    for (int k = 0; k < n; k++) { keep[k] = !in_set[k]; rsize += in_set[k]; }
+    int rsize = 0, first = n;
+    for (int k = 0; k < n; k++) {
+        keep[k] = !in_set[k];
+        rsize += in_set[k];
+        if (in_set[k] && k < first) first = k;
+    }
+    if (debug_on())
+        fprintf(stderr, "[cktlu] fallback: restart set %d columns from %d (dense block from %d)\n", rsize, first,
+                c->s.tail0);
+    // every column to restart inside the dense block: pivot it on the device
+    if (c->s.tail0 < n && first >= c->s.tail0 && c->opt.dense_device_repivot >= 0) {
+        int rc = dense_pivot_refactor(c, vals, info);
+        if (rc <= 0) return rc;
+    }
     std::vector<int> oldFi = c->f.Fi;
+    const auto t0 = std::chrono::steady_clock::now();
     int rc = factor_and_setup(c, vals.data(), &keep, true);
+    if (debug_on())
+        fprintf(stderr, "[cktlu] host fallback: factorization and set-up %.3f s\n",
+                std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count());
     if (rc != CKTLU_OK) return rc;
     c->stats.n_repivot++;
     c->stats.n_restart_cols += rsize;
@@ -735,6 +818,7 @@ int cktlu_create(cktlu_ctx **out, const cktlu_options *opt) {
     if (!(c->opt.pivot_eps > 0.0 && c->opt.pivot_eps <= 1.0) ||
         (c->opt.precision != CKTLU_FP64 && c->opt.precision != CKTLU_FP32_IR) || c->opt.ir_max_iter < 1 ||
         c->opt.solve_chain_width < -1 || (c->opt.dense_lookahead != 0 && c->opt.dense_lookahead != 1) ||
+        (c->opt.dense_device_repivot != 0 && c->opt.dense_device_repivot != -1) ||
         (c->opt.dense_panel_width != 0 && c->opt.dense_panel_width != 64 && c->opt.dense_panel_width != 128 &&
          c->opt.dense_panel_width != 256)) {
         delete c;

@@ -604,6 +604,162 @@ void dense_solve_impl(const DenseArgs &a, double *y, const int *skip, bool upper
     }
 }
 
+// ------------------------------------------------------- pivoted dense LU
+// The re-factorization of the dense block when its pivot test failed (the
+// sparse columns all passed, so only the block changes): the same blocked
+// right-looking LU in panels of NB, with the threshold pivot rule applied to
+// each column over the whole remaining height.  A step launch for column k
+// (every workgroup finds the same pivot from column k, which no workgroup of
+// that launch writes) exchanges rows k and p_k in the panel's later columns and
+// applies the rank-1 update to them; column k itself is completed (exchange,
+// division by the pivot) by the next step launch, which also carries the
+// exchanges into the panel's earlier columns.  After a panel, its exchanges are
+// applied to every other column, U12 = L11^-1 A12, and the trailing block gets
+// the K = NB update.  FP64, one instance.
+
+// pivot of column k over rows [k, D): returns the chosen row; *bad when no usable pivot
+__device__ int dpiv_choose(const double *col, int k, int D, double eps, bool *bad) {
+    __shared__ double s_best[256], s_oth[256];
+    __shared__ int s_bi[256], s_bad[256];
+    const int tid = threadIdx.x;
+    double best = -1.0, oth = 0.0;
+    int bi = INT_MAX, nf = 0;
+    for (int i = k + tid; i < D; i += 256) {            // ascending rows: ties keep the first
+        const double v = col[i], av = fabs(v);
+        if (!isfinite(v)) nf = 1;
+        if (i != k) oth = fmax(oth, av);
+        if (av > best) { best = av; bi = i; }
+    }
+    s_best[tid] = best; s_bi[tid] = bi; s_oth[tid] = oth; s_bad[tid] = nf;
+    __syncthreads();
+    for (int off = 128; off > 0; off >>= 1) {
+        if (tid < off) {
+            const double b2 = s_best[tid + off];
+            const int i2 = s_bi[tid + off];
+            if (b2 > s_best[tid] || (b2 == s_best[tid] && i2 < s_bi[tid])) { s_best[tid] = b2; s_bi[tid] = i2; }
+            s_oth[tid] = fmax(s_oth[tid], s_oth[tid + off]);
+            s_bad[tid] |= s_bad[tid + off];
+        }
+        __syncthreads();
+    }
+    const double xd = col[k];
+    int pk = k;
+    if (!(isfinite(xd) && xd != 0.0 && fabs(xd) >= eps * s_oth[0])) pk = s_bi[0];
+    *bad = s_bad[0] != 0 || pk >= D || col[pk] == 0.0;
+    const int r = pk < D ? pk : k;
+    __syncthreads();                                     // the shared arrays are reused by the caller
+    return r;
+}
+
+// blockIdx.x: 0 completes column k-1 (its exchange, its division, then this step's
+// exchange); 1 carries this step's exchange into columns [p, k-1); 2 + t updates
+// column k + 1 + t.  k == pe: only the completion of column pe - 1.
+__global__ __launch_bounds__(256) void dpiv_step_kernel(DenseArgs a, int p, int pe, int k, int *swp, int *info) {
+    double *S = reinterpret_cast<double *>(a.S);
+    const int D = a.D, tid = threadIdx.x, role = blockIdx.x;
+    int pk = -1;
+    double xp = 0.0;
+    if (k < pe) {
+        bool bad = false;
+        pk = dpiv_choose(S + (size_t)k * D, k, D, a.eps, &bad);
+        xp = S[(size_t)k * D + pk];
+        if (role == 0 && tid == 0) {
+            swp[k] = pk;
+            if (bad && *info == 0) *info = k + 1;
+        }
+    }
+    auto exch = [&](double *col, int r1, int r2) {
+        if (r1 != r2 && tid == 0) { const double t = col[r1]; col[r1] = col[r2]; col[r2] = t; }
+    };
+    if (role == 0) {
+        if (k > p) {
+            double *col = S + (size_t)(k - 1) * D;
+            const int q = swp[k - 1];
+            exch(col, k - 1, q);
+            __syncthreads();
+            const double u = col[k - 1];
+            for (int i = k + tid; i < D; i += 256) col[i] = col[i] / u;
+            __syncthreads();
+            if (k < pe) exch(col, k, pk);
+        }
+        return;
+    }
+    if (k >= pe) return;
+    if (role == 1) {
+        for (int c = p + tid; c < k - 1; c += 256) {
+            double *col = S + (size_t)c * D;
+            if (pk != k) { const double t = col[k]; col[k] = col[pk]; col[pk] = t; }
+        }
+        return;
+    }
+    const int j = k + 1 + (role - 2);
+    double *cj = S + (size_t)j * D;
+    const double *ck = S + (size_t)k * D;
+    exch(cj, k, pk);
+    __syncthreads();
+    const double ukj = cj[k];
+    const double xk = ck[k];
+    for (int i = k + 1 + tid; i < D; i += 256) {
+        const double xi = i == pk ? xk : ck[i];            // column k after the exchange
+        cj[i] -= (xi / xp) * ukj;
+    }
+}
+
+// the exchanges of panel [p, pe) applied to the columns outside it, 64 columns per
+// workgroup, the panel's rows staged in LDS
+__global__ __launch_bounds__(64) void dpiv_swap_rest_kernel(DenseArgs a, int p, int pe, const int *swp) {
+    __shared__ double rows[NB][NB + 1];
+    double *S = reinterpret_cast<double *>(a.S);
+    const int D = a.D, lane = threadIdx.x;
+    const int nleft = p, nright = D - pe;
+    const int c_idx = (int)blockIdx.x * NB + lane;
+    const bool valid = c_idx < nleft + nright;
+    const int c = c_idx < nleft ? c_idx : pe + (c_idx - nleft);
+    const int nb = pe - p;
+    double *col = S + (size_t)(valid ? c : 0) * D;
+    if (valid)
+        for (int r = 0; r < nb; r++) rows[r][lane] = col[p + r];
+    for (int k = p; k < pe; k++) {
+        const int q = swp[k];
+        if (!valid || q == k) continue;
+        if (q < pe) {
+            const double t = rows[k - p][lane];
+            rows[k - p][lane] = rows[q - p][lane];
+            rows[q - p][lane] = t;
+        } else {
+            const double t = col[q];
+            col[q] = rows[k - p][lane];
+            rows[k - p][lane] = t;
+        }
+    }
+    if (valid)
+        for (int r = 0; r < nb; r++) col[p + r] = rows[r][lane];
+}
+
+// U12 = L11^-1 A12 for the columns past the panel: the unit lower L11 staged in LDS,
+// a column per lane (64 rows in registers), 256 columns per workgroup
+__global__ __launch_bounds__(256) void dpiv_u12_kernel(DenseArgs a, int p) {
+    __shared__ double l11[NB][NB];                      // l11[col][row]
+    double *S = reinterpret_cast<double *>(a.S);
+    const int D = a.D, tid = threadIdx.x;
+    for (int e = tid; e < NB * NB; e += 256) l11[e / NB][e % NB] = S[(size_t)(p + e / NB) * D + p + e % NB];
+    __syncthreads();
+    const int j = p + NB + (int)blockIdx.x * 256 + tid;
+    if (j >= D) return;
+    double *col = S + (size_t)j * D + p;
+    double x[NB];
+#pragma unroll
+    for (int r = 0; r < NB; r++) x[r] = col[r];
+#pragma unroll
+    for (int kk = 0; kk < NB; kk++)
+#pragma unroll
+        for (int m = kk + 1; m < NB; m++) x[m] -= l11[kk][m] * x[kk];
+#pragma unroll
+    for (int r = 0; r < NB; r++) col[r] = x[r];
+}
+
+__global__ void zero_int_kernel(int *v) { *v = 0; }
+
 inline dim3 wave_grid(int64_t waves) { return dim3((unsigned)((waves + 3) / 4)); }
 
 }  // namespace
@@ -712,6 +868,38 @@ int launch_dense_refactor(const DenseArgs &a, bool gather, const DenseStreams *l
     }
     if (a.fp32) hipLaunchKernelGGL((tail_scatter_kernel<float>), gw, dim3(256), 0, st, a);
     else hipLaunchKernelGGL((tail_scatter_kernel<double>), gw, dim3(256), 0, st, a);
+    return (int)hipGetLastError();
+}
+
+int launch_dense_pivoted_lu(const DenseArgs &a, int *swp, int *info, void *stream) {
+    hipStream_t st = (hipStream_t)stream;
+    const int D = a.D;
+    if (D <= 0) return 0;
+    hipLaunchKernelGGL(zero_int_kernel, dim3(1), dim3(1), 0, st, info);
+    auto rect = [](int r0, int r1, int c0, int c1) {
+        GemmRect g;
+        g.r0 = r0; g.r1 = r1; g.c0 = c0; g.c1 = c1;
+        g.ntx = r1 > r0 && c1 > c0 ? (r1 - r0 + 127) / 128 : 0;
+        g.nt = g.ntx ? g.ntx * ((c1 - c0 + 127) / 128) : 0;
+        return g;
+    };
+    for (int p = 0; p < D; p += NB) {
+        const int pe = D - p < NB ? D : p + NB;
+        for (int k = p; k <= pe; k++) {
+            const int roles = k < pe ? 2 + (pe - k - 1) : 1;
+            hipLaunchKernelGGL(dpiv_step_kernel, dim3((unsigned)roles), dim3(256), 0, st, a, p, pe, k, swp, info);
+        }
+        const int nrest = p + (D - pe);
+        if (nrest > 0)
+            hipLaunchKernelGGL(dpiv_swap_rest_kernel, dim3((unsigned)((nrest + NB - 1) / NB)), dim3(NB), 0, st, a, p,
+                               pe, (const int *)swp);
+        if (pe < D) {
+            hipLaunchKernelGGL(dpiv_u12_kernel, dim3((unsigned)((D - pe + 255) / 256)), dim3(256), 0, st, a, p);
+            const GemmRect g0 = rect(pe, D, pe, D), g1 = rect(0, 0, 0, 0);
+            hipLaunchKernelGGL((dlu_gemm_kernel<double, 64>), dim3((unsigned)g0.nt, 1, 1), dim3(256), 0, st, a, p, g0,
+                               g1, -1);
+        }
+    }
     return (int)hipGetLastError();
 }
 

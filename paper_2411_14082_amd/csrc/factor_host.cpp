@@ -37,12 +37,22 @@ struct ColStore {
 
 int host_gp_factor(const Analysis &an, const double *values, double eps,
                    const std::vector<int> &init_pivrow, const Factor *prev,
-                   const std::vector<char> *keep, Factor &out, int &fail_col, int &nswaps) {
+                   const std::vector<char> *keep, Factor &out, int &fail_col, int &nswaps,
+                   const DenseSource *dsrc) {
     const int n = an.n;
     fail_col = -1;
     nswaps = 0;
     std::vector<int> pivrow(init_pivrow), posof(n);
     for (int k = 0; k < n; k++) posof[pivrow[k]] = k;
+    // dense source: final positions of every row after the block's exchanges
+    std::vector<int> fpos;
+    if (dsrc) {
+        if (!prev || dsrc->T + dsrc->D != n) return CKTLU_E_STATE;
+        std::vector<int> fr(pivrow);
+        for (int c = 0; c < dsrc->D; c++) std::swap(fr[dsrc->T + c], fr[dsrc->T + dsrc->swap[c]]);
+        fpos.resize(n);
+        for (int q = 0; q < n; q++) fpos[fr[q]] = q;
+    }
     std::vector<int> pivcol(n, -1);          // A_hat row -> column it is pivot of
     std::vector<int> stamp(n, -1), reach, deps, queue;
     std::vector<double> x(n, 0.0);
@@ -91,6 +101,45 @@ int host_gp_factor(const Analysis &an, const double *values, double eps,
             if (pivcol[r] >= 0) deps.push_back(pivcol[r]);
         }
         std::sort(deps.begin(), deps.end());
+        if (dsrc && k >= dsrc->T) {
+            // pivot and values from the dense source: the exchange it made at this step,
+            // U entries in rows < T from prev, the rest from the block in final positions
+            const int T = dsrc->T, D = dsrc->D;
+            const double *Sk = dsrc->S + (size_t)(k - T) * D;
+            const int d = pivrow[k], piv = pivrow[T + dsrc->swap[k - T]];
+            if (pivcol[piv] >= 0 || stamp[piv] != k) return CKTLU_E_STATE;   // not a candidate
+            if (piv != d) {
+                const int q = posof[piv];
+                pivrow[q] = d;  posof[d] = q;
+                pivrow[k] = piv; posof[piv] = k;
+                nswaps++;
+            }
+            const int64_t pb = prev->Fp[k];
+            const int pnu = prev->nU[k];
+            for (int j : deps) {
+                double v;
+                if (j < T) {
+                    const int *b = prev->Fi.data() + pb, *e = b + pnu - 1;
+                    const int *f = std::lower_bound(b, e, j);
+                    if (f == e || *f != j) return CKTLU_E_STATE;
+                    v = prev->Fx[pb + (f - b)];
+                } else {
+                    v = Sk[j - T];
+                }
+                cs.ucol.push_back(j);
+                cs.uval.push_back(v);
+            }
+            cs.diag[k] = Sk[k - T];
+            for (int r : reach)
+                if (pivcol[r] < 0 && r != piv) {
+                    cs.lrow.push_back(r);
+                    cs.lval.push_back(Sk[fpos[r] - T]);
+                }
+            pivcol[piv] = k;
+            cs.lptr.push_back((int64_t)cs.lrow.size());
+            cs.uptr.push_back((int64_t)cs.ucol.size());
+            continue;
+        }
         for (int p = an.Hp[k]; p < an.Hp[k + 1]; p++) x[an.Hi[p]] = values[an.Hsrc[p]];
         for (int j : deps) {
             const double xj = x[pivrow[j]];

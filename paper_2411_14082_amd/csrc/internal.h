@@ -46,13 +46,26 @@ struct Factor {
     int64_t nnz_u() const { int64_t s = 0; for (int v : nU) s += v; return s; }
 };
 
+// The trailing columns [T, n) factored elsewhere (the device's pivoted dense LU):
+// the position exchanged with each position at its step (swap[c] >= c, local to the
+// block) and the factors in final row positions (D x D, column-major, unit L below
+// the diagonal, U on and above).  Their rows < T (U entries) come from `prev`.
+struct DenseSource {
+    int T = 0, D = 0;
+    const int *swap = nullptr;
+    const double *S = nullptr;
+};
+
 // Host left-looking LU with threshold pivoting.  Columns with keep[k] != 0
 // are copied from `prev` (pattern and values) instead of being recomputed;
 // the others are factored with pivoting, the preferred row of column k being
-// the row in position k of init_pivrow.  Returns CKTLU_OK or an error code.
+// the row in position k of init_pivrow.  With dsrc, the columns >= dsrc->T that
+// are not kept take their pivots and values from dsrc (only their pattern is
+// computed here).  Returns CKTLU_OK or an error code.
 int host_gp_factor(const Analysis &an, const double *values, double eps,
                    const std::vector<int> &init_pivrow, const Factor *prev,
-                   const std::vector<char> *keep, Factor &out, int &fail_col, int &nswaps);
+                   const std::vector<char> *keep, Factor &out, int &fail_col, int &nswaps,
+                   const DenseSource *dsrc = nullptr);
 
 // Restart set: unfinished columns and their elimination-tree ancestors.
 void restart_closure(const std::vector<int> &parent, const std::vector<char> &unfinished,
@@ -159,6 +172,8 @@ struct RefactorArgs {
 
 // Zero every factor column and scatter the matrix values into it.
 int launch_refactor_init(const RefactorArgs &a, void *stream);
+// FP64, one instance: S = the dense columns' matrix values in rows >= T (their rows < T untouched).
+int launch_dense_reinit(const RefactorArgs &a, void *stream);
 // One right-looking level: pivot check of columns seq[cbeg, cend), normalisation of the
 // previous level seq[pbeg, pend) (L = x / pivot), and update tasks [tbeg, tend).
 int launch_refactor_level(const RefactorArgs &a, int cbeg, int cend, int pbeg, int pend, int tbeg,
@@ -248,6 +263,14 @@ struct DenseStreams {
 int launch_dense_refactor(const DenseArgs &a, bool gather, const DenseStreams *la, void *stream);
 // events the look-ahead needs for this dense block (0: it runs on one stream)
 int dense_lookahead_events(const DenseArgs &a);
+// FP64, one instance: LU of S with the threshold pivot rule (Section II-A): at column c
+// the row in position c stays unless its value is zero, not finite or below eps times
+// the largest other candidate; then the largest candidate (smallest position on ties)
+// is exchanged into position c.  Rows are exchanged across the whole block, so on
+// return S holds unit L below the diagonal and U on and above it in final row
+// positions; swap[c] (device, D ints) is the position exchanged with c at step c.
+// info (device int, zeroed here) receives 1 + the first column with no usable pivot.
+int launch_dense_pivoted_lu(const DenseArgs &a, int *swap, int *info, void *stream);
 // y rows [T, n): lower (unit) or upper triangular solve with the block in S
 int launch_dense_solve(const DenseArgs &a, double *y, int nrhs, const int *skip, bool upper, void *stream);
 

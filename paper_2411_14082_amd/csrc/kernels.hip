@@ -93,6 +93,31 @@ __global__ __launch_bounds__(WG) void refactor_init_kernel(RefactorArgs a) {
     }
 }
 
+// S = A22 (one instance): the dense columns' matrix values in rows >= T, zeros
+// elsewhere; their rows < T (already final) are not touched.  One wavefront per column.
+__global__ __launch_bounds__(WG) void dense_reinit_kernel(RefactorArgs a) {
+    const int lane = threadIdx.x & (WAVE - 1), wv = threadIdx.x / WAVE;
+    const int64_t w = (int64_t)blockIdx.x * WAVES + wv;
+    if (w >= a.D) return;
+    const int k = a.T + (int)w;
+    double *Sk = reinterpret_cast<double *>(a.S) + (size_t)w * a.D;
+    const int *rows = a.Fi + a.Dp[k];
+    const int c = a.colperm[k];
+    for (int i = lane; i < a.D; i += WAVE) Sk[i] = 0.0;
+    wave_sync();
+    for (int p = a.Ap[c] + lane; p < a.Ap[c + 1]; p += WAVE) {
+        const int r = rows[a.amap[p]];
+        if (r >= a.T) Sk[r - a.T] = a.Aval[p];
+    }
+}
+
+int launch_dense_reinit(const RefactorArgs &a, void *stream) {
+    if (a.D <= 0) return 0;
+    hipLaunchKernelGGL(dense_reinit_kernel, dim3((unsigned)((a.D + WAVES - 1) / WAVES)), dim3(WG), 0,
+                       (hipStream_t)stream, a);
+    return (int)hipGetLastError();
+}
+
 constexpr int kItemChunk = 4;      // entries of a source column per lane per pass (longer sources)
 
 // x_k -= L(:,j) U(j,k) for one source j (item {pivot position, L begin, L end,

@@ -84,3 +84,13 @@ def compare_factors_sampled(f, lu, rtol, nsample=4000, seed=0):
             worst = max(worst, abs(Fx[q] - Ax[q]) / max(sc, np.finfo(float).tiny))
     assert worst <= rtol, f"factor values differ: scaled error {worst:.3e} > {rtol:.1e}"
     return worst
+
+
+def pivot_entry(c, a, k):
+    """Index of the user nonzero that holds the current pivot of column k."""
+    r = a["rowperm_pre"][a["pivrow"][k]]
+    col = a["colperm"][k]
+    lo, hi = c.colptr[col], c.colptr[col + 1]
+    p = lo + int(np.searchsorted(c.rowind[lo:hi], r))
+    assert c.rowind[p] == r
+    return p

@@ -11,6 +11,9 @@
   oracle within rounding.
 - 1000 x 1000 power grid (n = 1,000,000) with FP32 factors, FP64 refinement and
   8 right-hand sides: eta_inf <= 1e-10 for every right-hand side.
+- The RC mesh with a pivot inside its dense block made to fail: the dense block
+  is re-factored on the device with the threshold pivot rule, and pattern and
+  pivot sequence equal the oracle's re-factorization, values within rounding.
 """
 import sys
 import time
@@ -20,7 +23,7 @@ import pytest
 import scipy.sparse as sp
 
 import mnagen
-from helpers import compare_factors, compare_factors_sampled, oracle_refactor
+from helpers import compare_factors, compare_factors_sampled, oracle_refactor, pivot_entry
 
 torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
@@ -90,6 +93,44 @@ def test_rc_mesh_3x300_full(ck, oracle_mod):
     assert e <= 1e-10
     xo = oracle_mod.solve(lu, a0["rowperm_pre"], a0["colperm"], b)
     assert np.abs(x.cpu().numpy() - xo).max() <= 1e-6 * np.abs(xo).max()
+
+
+@pytest.mark.timeout(900)
+@pytest.mark.parametrize("device", [0, -1], ids=["device", "host"])
+def test_rc_mesh_3x300_dense_repivot_full(ck, oracle_mod, device):
+    t0 = time.time()
+    c = mnagen.layered_rc(300, 300, 3, seed=0)
+    s = ck.SparseLU(c.n, c.colptr, c.rowind, eps=EPS, dense_device_repivot=device)
+    s.factorize(dev(c.values))
+    a0 = s.analysis()
+    D = s.stats()["dense_tail"]
+    say(t0, "factorized; dense tail", D)
+    v = mnagen.restamp(c, 0, 2, 1)
+    lu1 = oracle_refactor(oracle_mod, c, v, a0, EPS, a0["pivrow"])
+    assert lu1.status == 0 and lu1.nswaps == 0
+    k = c.n - D + 1000                                # a column of the block's 16th panel
+    assert lu1.Ui[lu1.Up[k + 1] - 1] == k
+    v[pivot_entry(c, a0, k)] -= lu1.Ux[lu1.Up[k + 1] - 1] * (1 - 1e-8)
+    lu = oracle_refactor(oracle_mod, c, v, a0, EPS, a0["pivrow"])
+    say(t0, "oracle re-factorizations done, swaps", lu.nswaps)
+    assert lu.status == 0 and lu.nswaps >= 1
+    torch.cuda.synchronize()
+    t1 = time.time()
+    rc, info = s.refactorize(dev(v))
+    torch.cuda.synchronize()
+    say(t0, "refactorize with the dense re-pivot: %.2f s" % (time.time() - t1), "rc", rc)
+    assert rc == ck.CKTLU_W_REPIVOTED and info.first_fail_col == k
+    assert s.stats()["n_device_repivot"] == (1 if device == 0 else 0)
+    assert np.array_equal(s.analysis()["pivrow"], lu.pivrow)
+    worst = compare_factors_sampled(s.factors(), lu, RTOL)
+    say(t0, "sampled scaled error", worst)
+    b = c.rhs[0]
+    x = torch.zeros(c.n, dtype=torch.float64, device="cuda:0")
+    s.solve(dev(b), x)
+    torch.cuda.synchronize()
+    assert eta_inf(c, v, x.cpu().numpy(), b) <= 1e-12
+    rc, info = s.refactorize(dev(v))                   # the new pivot sequence now passes its check
+    assert rc == 0 and info.repivoted == 0
 
 
 @pytest.mark.timeout(600)

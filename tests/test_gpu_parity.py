@@ -16,7 +16,7 @@ import numpy as np
 import pytest
 
 import mnagen
-from helpers import compare_factors, oracle_refactor
+from helpers import compare_factors, oracle_refactor, pivot_entry as _pivot_entry
 
 torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
@@ -152,29 +152,33 @@ def test_forced_failure_fallback(ck, oracle_mod, where):
         ck.cktlu_destroy(ctx)
 
 
-def test_value_driven_repivot_in_dense_block(ck, oracle_mod):
-    """The pivot U(k,k) of a column inside the dense block shrunk to 1e-8 of its
-    value (through the diagonal entry of A, which only column k's pivot sees):
-    the dense pivot test fails at k, the fallback re-pivots, and pattern, pivot
-    sequence and values equal the oracle's re-factorization."""
+@pytest.mark.parametrize("device", [0, -1], ids=["device", "host"])
+@pytest.mark.parametrize("tail,offs", [(100, (30,)), (300, (10, 150, 290))])
+def test_value_driven_repivot_in_dense_block(ck, oracle_mod, tail, offs, device):
+    """The pivots U(k,k) of columns inside the dense block shrunk to 1e-8 of their
+    values (through the diagonal entries of A, which only column k's pivot sees):
+    the dense pivot test fails at the first, the fallback re-pivots (the dense
+    block on the device with the threshold rule, or the host GP), and pattern,
+    pivot sequence and values equal the oracle's re-factorization."""
     c = mnagen.mesh_transistor(30, 30, seed=22)
-    tail = 100
-    s = ck.SparseLU(c.n, c.colptr, c.rowind, eps=EPS, dense_tail=tail)
+    s = ck.SparseLU(c.n, c.colptr, c.rowind, eps=EPS, dense_tail=tail, dense_device_repivot=device)
     s.factorize(dev(c.values))
     a0 = s.analysis()
     vh = mnagen.perturb(c.values, 22, 0, 1)
     lu1 = oracle_refactor(oracle_mod, c, vh, a0, EPS, a0["pivrow"])
     assert lu1.status == 0
-    k = c.n - tail + 30
     assert np.array_equal(lu1.pivrow, a0["pivrow"])
-    ukk = lu1.Ux[lu1.Up[k + 1] - 1]                  # diagonal: last U entry of column k
-    assert lu1.Ui[lu1.Up[k + 1] - 1] == k
-    vh[_pivot_entry(c, a0, k)] -= ukk * (1 - 1e-8)
+    for o in offs:
+        k = c.n - tail + o
+        ukk = lu1.Ux[lu1.Up[k + 1] - 1]              # diagonal: last U entry of column k
+        assert lu1.Ui[lu1.Up[k + 1] - 1] == k
+        vh[_pivot_entry(c, a0, k)] -= ukk * (1 - 1e-8)
     lu = oracle_refactor(oracle_mod, c, vh, a0, EPS, a0["pivrow"])
     assert lu.status == 0 and lu.nswaps >= 1
     rc, info = s.refactorize(dev(vh))
     assert rc == ck.CKTLU_W_REPIVOTED and info.repivoted == 1
-    assert info.first_fail_col == k
+    assert info.first_fail_col == c.n - tail + offs[0]
+    assert s.stats()["n_device_repivot"] == (1 if device == 0 else 0)
     a = s.analysis()
     assert np.array_equal(a["pivrow"], lu.pivrow)
     compare_factors(s.factors(), lu, RTOL)
@@ -182,16 +186,6 @@ def test_value_driven_repivot_in_dense_block(ck, oracle_mod):
     s.solve(dev(c.rhs[0]), x)
     torch.cuda.synchronize()
     assert oracle_mod.backward_error(c.colptr, c.rowind, vh, x.cpu().numpy(), c.rhs[0]) <= 1e-12
-
-
-def _pivot_entry(c, a, k):
-    """Index of the user nonzero that holds the current pivot of column k."""
-    r = a["rowperm_pre"][a["pivrow"][k]]
-    col = a["colperm"][k]
-    lo, hi = c.colptr[col], c.colptr[col + 1]
-    p = lo + int(np.searchsorted(c.rowind[lo:hi], r))
-    assert c.rowind[p] == r
-    return p
 
 
 @pytest.mark.parametrize("nfail", [1, 3])
