@@ -335,13 +335,19 @@ int factor_and_setup(cktlu_ctx *c, const double *values_host, const std::vector<
     }
     Factor nf;
     int fail = -1, nswaps = 0;
+    const auto t0 = std::chrono::steady_clock::now();
     int rc = host_gp_factor(c->an, values_host, c->opt.pivot_eps, init, keep ? &c->f : nullptr, keep, nf,
                             fail, nswaps, dsrc);
     if (rc != CKTLU_OK) return rc;
     // same pattern and pivot sequence: the device schedule stays valid, only values change
     const bool same = !c->f.Fi.empty() && nf.Fi == c->f.Fi && nf.Fp == c->f.Fp && nf.pivrow == c->f.pivrow;
     c->f = std::move(nf);
+    const auto t1 = std::chrono::steady_clock::now();
     if (!same || c->s.n != c->an.n) build_schedule(c->an, c->f, c->opt, c->s);
+    if (debug_on())
+        fprintf(stderr, "[cktlu] host factorization %.3f s, schedule %.3f s\n",
+                std::chrono::duration<double>(t1 - t0).count(),
+                std::chrono::duration<double>(std::chrono::steady_clock::now() - t1).count());
     fill_stats_pattern(c);
     c->state = 2;
     if (device) {
