@@ -274,7 +274,9 @@ typedef struct {
  * Schedule autotuner (the dense-part threshold the paper fixes for its CPUs,
  * Section V-A, chosen here by measurement on the device): for each candidate
  * order D of the dense trailing block (none, the density rule at 0.5, 0.3 and
- * 0.2, and D = 512, 1024, 2048, 4096, 8192 up to n; duplicates skipped) the
+ * 0.2, D = 512, 1024, 2048, 4096, 8192 up to n, and 10240, 12288, 16384 while
+ * batch blocks of that order fit a quarter of the free device memory;
+ * duplicates skipped) the
  * schedule is rebuilt and uploaded, and `reps` steps are timed with HIP events
  * on the context's stream, a step being the refactorization of `batch`
  * instances (values_dev: batch x nnz, as cktlu_refactorize_batched; batch 1

@@ -1062,6 +1062,11 @@ int cktlu_autotune(cktlu_ctx *c, int32_t batch, const double *values_dev, int32_
     struct Cand { int size; double density; };
     std::vector<Cand> cands = {{-1, 0.3}, {0, 0.5}, {0, 0.3}, {0, 0.2}};
     for (int d = 512; d <= 8192 && d <= n; d *= 2) cands.push_back({d, 0.3});
+    // larger blocks (fewer, longer levels traded for dense work) while they fit a quarter of free HBM
+    size_t hbm_free = 0, hbm_total = 0;
+    if (hipMemGetInfo(&hbm_free, &hbm_total) != hipSuccess) hbm_free = 0;
+    for (int d : {10240, 12288, 16384})
+        if (d <= n && (double)d * d * 8.0 * batch <= 0.25 * (double)hbm_free) cands.push_back({d, 0.3});
     const cktlu_options saved = c->opt;
     c->opt.timing = 0;
     hipStream_t st = stream_of(c);
