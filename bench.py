@@ -44,7 +44,7 @@ def run_batched(ck, torch, c, batch, steps, warmup, precision, graph, tail_opts)
     buffer) and solves one right-hand side each; eager calls or one captured graph."""
     import mnagen
     s = ck.SparseLU(c.n, c.colptr, c.rowind, eps=1e-3, precision=precision, ir_tol=1e-10,
-                    **{k: v for k, v in tail_opts.items() if k != "autotune"})
+                    **lu_options(ck, tail_opts))
     dev = torch.device("cuda:0")
     s.factorize(torch.tensor(c.values, device=dev))
     nsets = 4
@@ -156,7 +156,7 @@ def main_batched(args, wl):
     batch = wl["batch"]
     tail_opts = dict(dense_tail=args.dense_tail, dense_tail_density=args.dense_density, autotune=args.autotune,
                      solve_chain_width=args.solve_chain, dense_panel_width=args.dense_panel_width,
-                     dense_lookahead=args.dense_lookahead)
+                     dense_lookahead=args.dense_lookahead, ordering=args.ordering)
     legs = {}
     for name, prec, graph in (("fp64_eager", ck.CKTLU_FP64, False), ("fp64_graph", ck.CKTLU_FP64, True),
                               ("fp32_ir_eager", ck.CKTLU_FP32_IR, False), ("fp32_ir_graph", ck.CKTLU_FP32_IR, True)):
@@ -209,10 +209,19 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
+def lu_options(ck, tail_opts):
+    """SparseLU keyword arguments from the bench's schedule options."""
+    kw = {k: v for k, v in tail_opts.items() if k not in ("autotune", "ordering")}
+    if tail_opts.get("ordering"):
+        kw["ordering"] = {"amd": ck.CKTLU_ORDER_AMD, "amf": ck.CKTLU_ORDER_AMF, "auto": ck.CKTLU_ORDER_AUTO,
+                          "natural": ck.CKTLU_ORDER_NATURAL}[tail_opts["ordering"]]
+    return kw
+
+
 def run_leg(ck, torch, c, vals_dev, b_dev, precision, steps, warmup, tail_opts):
     nrhs = b_dev.shape[0] if b_dev.dim() == 2 else 1
     s = ck.SparseLU(c.n, c.colptr, c.rowind, eps=1e-3, precision=precision, ir_tol=1e-10, timing=True,
-                    **{k: v for k, v in tail_opts.items() if k != "autotune"})
+                    **lu_options(ck, tail_opts))
     t0 = time.time()
     s.factorize(vals_dev[0])
     t_setup = time.time() - t0
@@ -282,6 +291,8 @@ def main():
                     help="order of the dense trailing block: 0 automatic (default), -1 none, >0 forced")
     ap.add_argument("--dense-density", type=float, default=None,
                     help="fill density threshold of the automatic dense-block choice")
+    ap.add_argument("--ordering", default=None, choices=["amd", "amf", "auto", "natural"],
+                    help="fill-reducing ordering of analyze (default: the library's)")
     ap.add_argument("--dense-panel-width", type=int, default=None,
                     help="dense block: columns factored between trailing-block updates (64, 128, 256)")
     ap.add_argument("--dense-lookahead", type=int, default=None,
@@ -328,7 +339,7 @@ def main():
 
     tail_opts = dict(dense_tail=args.dense_tail, dense_tail_density=args.dense_density, autotune=args.autotune,
                      solve_chain_width=args.solve_chain, dense_panel_width=args.dense_panel_width,
-                     dense_lookahead=args.dense_lookahead)
+                     dense_lookahead=args.dense_lookahead, ordering=args.ordering)
     res64 = run_leg(ck, torch, c, vals_dev, b_dev, ck.CKTLU_FP64, args.steps, args.warmup, tail_opts)
     log("fp64: %.3f steps/s, refactor %.2f ms, solve %.2f ms (setup %.1fs), dense tail %d" %
         (args.steps / res64["wall"], res64["ref_ms"].mean(), res64["sol_ms"].mean(), res64["setup_s"],
@@ -392,7 +403,7 @@ def main():
         "vs_baseline": None, "dtype": "f64", "data": "synthetic",
         "config": {"workload": wl["desc"], "n": c.n, "nnz": c.nnz, "nnz_lu": st["nnz_l"] + st["nnz_u"],
                    "flops_per_refactor": st["flops"], "levels": st["levels"], "dense_tail": st["dense_tail"],
-                   "nrhs": nrhs,
+                   "nrhs": nrhs, "ordering": ["amd", "natural", "amf", "auto"][int(st.get("ordering_used", 0))],
                    "value_perturbation": "+-5%% per %s" % args.perturb},
         "p50_ms": float(np.percentile(res64["step_ms"], 50)),
         "p99_ms": float(np.percentile(res64["step_ms"], 99)),

@@ -53,6 +53,9 @@ extern "C" {
 /* fill-reducing ordering used by analyze */
 #define CKTLU_ORDER_AMD 0       /* approximate minimum degree on the pattern of B + B' */
 #define CKTLU_ORDER_NATURAL 1   /* keep the (transversal-permuted) natural order */
+#define CKTLU_ORDER_AMF 2       /* approximate minimum fill on the pattern of B + B' */
+#define CKTLU_ORDER_AUTO 3      /* both AMD and AMF; keep the one whose symbolic Cholesky of B + B' has
+                                   fewer entries (ties: AMD), the combined ordering of Section III-A */
 
 typedef struct cktlu_ctx cktlu_ctx;
 
@@ -61,7 +64,7 @@ typedef struct {
     int precision;         /* CKTLU_FP64 (default) or CKTLU_FP32_IR */
     double ir_tol;         /* FP32_IR: backward-error target; default 1e-10 */
     int ir_max_iter;       /* FP32_IR: refinement step limit; default 10 */
-    int ordering;          /* CKTLU_ORDER_*; default AMD */
+    int ordering;          /* CKTLU_ORDER_*; default AUTO (AMD and AMF, the one with less fill) */
     int transversal;       /* 1 (default): structural maximum transversal before ordering */
     void *stream;          /* hipStream_t for all device work; NULL = the null stream */
     int force_fail_col;    /* test hook: >= 0 makes the pivot check of this column fail once */
@@ -120,6 +123,9 @@ typedef struct {
     int64_t solve_launches;           /* kernel launches of one triangular solve pass (L and U) */
     int64_t n_device_repivot;         /* fallbacks whose restart set lay inside the dense block and were
                                          re-factored on the device (pivoted dense LU) */
+    int64_t ordering_used;            /* CKTLU_ORDER_* that analyze applied */
+    int64_t fill_amd, fill_amf;       /* CKTLU_ORDER_AUTO: entries of the symbolic Cholesky factor of B + B'
+                                         under each method (-1 when not run) */
 } cktlu_stats;
 
 /* Device time of the phases, accumulated over the calls made with options.timing = 1

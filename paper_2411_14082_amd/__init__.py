@@ -33,6 +33,8 @@ CKTLU_FP64 = 0
 CKTLU_FP32_IR = 1
 CKTLU_ORDER_AMD = 0
 CKTLU_ORDER_NATURAL = 1
+CKTLU_ORDER_AMF = 2
+CKTLU_ORDER_AUTO = 3
 
 # every symbol the header declares (checked by the CPU test-suite)
 EXPORTS = [
@@ -77,7 +79,8 @@ class cktlu_stats(ctypes.Structure):
                 ("macs_sweep", ctypes.c_double), ("bytes_sweep", ctypes.c_double),
                 ("flops_dense", ctypes.c_double), ("macs_schur", ctypes.c_double), ("sweep_launches", ctypes.c_int64),
                 ("dense_launches", ctypes.c_int64), ("solve_launches", ctypes.c_int64),
-                ("n_device_repivot", ctypes.c_int64)]
+                ("n_device_repivot", ctypes.c_int64), ("ordering_used", ctypes.c_int64),
+                ("fill_amd", ctypes.c_int64), ("fill_amf", ctypes.c_int64)]
 
     def as_dict(self):
         return {f: getattr(self, f) for f, _ in self._fields_}
@@ -379,7 +382,7 @@ class SparseLU:
     the non-negative status (0 or a warning code).
     """
 
-    def __init__(self, n, colptr, rowind, eps=1e-3, precision=CKTLU_FP64, ordering=CKTLU_ORDER_AMD,
+    def __init__(self, n, colptr, rowind, eps=1e-3, precision=CKTLU_FP64, ordering=CKTLU_ORDER_AUTO,
                  ir_tol=1e-10, ir_max_iter=10, stream=None, transversal=1, dense_tail=None,
                  dense_tail_density=None, timing=False, solve_chain_width=None, dense_panel_width=None,
                  dense_lookahead=None, dense_device_repivot=None):

@@ -11,6 +11,7 @@
 #include <cmath>
 #include <cstring>
 #include <numeric>
+#include <set>
 
 #include "internal.h"
 
@@ -112,8 +113,12 @@ enum : uint8_t { VAR = 0, ELEM = 1, ABSORBED = 2, MERGED = 3, DENSE = 4, DONE = 
 
 }  // namespace
 
-// Approximate minimum degree ordering of a symmetric pattern given by its
-// adjacency lists (no self loops).  perm[k] is the k-th eliminated node.
+// Minimum-priority ordering of a symmetric pattern given by its adjacency lists
+// (no self loops); perm[k] is the k-th eliminated node.  amf == false: approximate
+// minimum degree (AMD).  amf == true: approximate minimum fill, the priority of a
+// variable being the fill its elimination would add if its neighbours already formed
+// the largest clique it touches, d(d-1)/2 - c(c-1)/2 with d its approximate external
+// degree and c = max over its adjacent elements of |Le \ i|.
 //
 // Quotient-graph elimination: eliminating variable p turns it into element p
 // whose variable list Lp is the union of p's variable neighbours and the lists
@@ -124,10 +129,15 @@ enum : uint8_t { VAR = 0, ELEM = 1, ABSORBED = 2, MERGED = 3, DENSE = 4, DONE = 
 // element and variable lists are merged into supervariables.  Rows denser than
 // 10*sqrt(n) are ordered last.
 void amd_order(int n, const std::vector<int> &Sp, const std::vector<int> &Si,
-               std::vector<int> &perm) {
+               std::vector<int> &perm, bool amf) {
     perm.clear();
     perm.reserve(n);
     if (n == 0) return;
+    // AMF: (priority, node) in an ordered set; the AMD path keeps its degree lists
+    std::set<std::pair<int64_t, int>> pq;
+    std::vector<int64_t> key(amf ? n : 0, 0);
+    std::vector<int64_t> cmax(amf ? n : 0, 0);
+    auto fillkey = [](int64_t d, int64_t cl) { return d * (d - 1) / 2 - cl * (cl - 1) / 2; };
     std::vector<std::vector<int>> adjV(n), adjE(n), Le(n), members(n);
     std::vector<int> nv(n, 1), deg(n), mark(n, -1), wtag(n, -1);
     std::vector<int64_t> w(n, 0), esize(n, 0);
@@ -146,10 +156,21 @@ void amd_order(int n, const std::vector<int> &Sp, const std::vector<int> &Si,
             if (st[Si[p]] == VAR) adjV[i].push_back(Si[p]);
         deg[i] = (int)adjV[i].size();
     }
-    DegreeLists dl(n);
+    DegreeLists dl(amf ? 0 : n);
     int mindeg = n;
     for (int i = 0; i < n; i++)
-        if (st[i] == VAR) { dl.insert(i, deg[i]); mindeg = std::min(mindeg, deg[i]); }
+        if (st[i] == VAR) {
+            if (amf) {
+                key[i] = fillkey(deg[i], 0);
+                pq.insert({key[i], i});
+            } else {
+                dl.insert(i, deg[i]);
+                mindeg = std::min(mindeg, deg[i]);
+            }
+        }
+    auto q_remove = [&](int i) {
+        if (amf) pq.erase({key[i], i}); else dl.remove(i, deg[i]);
+    };
 
     int64_t k = 0;
     int tag = 0;
@@ -157,9 +178,15 @@ void amd_order(int n, const std::vector<int> &Sp, const std::vector<int> &Si,
     std::vector<uint64_t> hash(n, 0);
     std::vector<int> byhash;
     while (k < nlive) {
-        while (mindeg <= n && dl.head[mindeg] < 0) mindeg++;
-        int p = dl.head[mindeg];
-        dl.remove(p, mindeg);
+        int p;
+        if (amf) {
+            p = pq.begin()->second;
+            pq.erase(pq.begin());
+        } else {
+            while (mindeg <= n && dl.head[mindeg] < 0) mindeg++;
+            p = dl.head[mindeg];
+            dl.remove(p, mindeg);
+        }
         // ---- element p: Lp = A_p united with Le of adjacent elements
         ++tag;
         mark[p] = tag;
@@ -181,7 +208,7 @@ void amd_order(int n, const std::vector<int> &Sp, const std::vector<int> &Si,
         std::vector<int>().swap(members[p]);
         k += nv[p];
         int64_t degLp = 0;
-        for (int i : Lp) { degLp += nv[i]; dl.remove(i, deg[i]); }
+        for (int i : Lp) { degLp += nv[i]; q_remove(i); }
         esize[p] = degLp;
         // ---- |Le \ Lp| for every element adjacent to Lp
         for (int i : Lp)
@@ -193,7 +220,7 @@ void amd_order(int n, const std::vector<int> &Sp, const std::vector<int> &Si,
         // ---- degree update, list pruning, aggressive absorption
         int64_t left = nlive - k;
         for (int i : Lp) {
-            int64_t dsum = 0;
+            int64_t dsum = 0, cl = degLp - nv[i];
             std::vector<int> &E = adjE[i];
             size_t o = 0;
             for (int e : E) {
@@ -205,7 +232,9 @@ void amd_order(int n, const std::vector<int> &Sp, const std::vector<int> &Si,
                 }
                 E[o++] = e;
                 dsum += w[e];
+                cl = std::max(cl, esize[e] - nv[i]);
             }
+            if (amf) cmax[i] = cl;
             E.resize(o);
             E.push_back(p);
             std::vector<int> &V = adjV[i];
@@ -267,11 +296,47 @@ void amd_order(int n, const std::vector<int> &Sp, const std::vector<int> &Si,
             L.push_back(i);
             int d = std::min(deg[i], n);
             deg[i] = d;
-            dl.insert(i, d);
-            if (d < mindeg) mindeg = d;
+            if (amf) {
+                key[i] = fillkey(d, std::min<int64_t>(cmax[i], d));
+                pq.insert({key[i], i});
+            } else {
+                dl.insert(i, d);
+                if (d < mindeg) mindeg = d;
+            }
         }
     }
     for (int i : dense) perm.push_back(i);
+}
+
+int64_t symbolic_cholesky_nnz(int n, const std::vector<int> &Sp, const std::vector<int> &Si,
+                              const std::vector<int> &perm) {
+    std::vector<int> inv(n), parent(n, -1), ancestor(n, -1), mark(n, -1);
+    for (int k = 0; k < n; k++) inv[perm[k]] = k;
+    // elimination tree, ancestors path-compressed
+    for (int k = 0; k < n; k++) {
+        const int v = perm[k];
+        for (int p = Sp[v]; p < Sp[v + 1]; p++) {
+            int i = inv[Si[p]];
+            while (i != -1 && i < k) {
+                const int nxt = ancestor[i];
+                ancestor[i] = k;
+                if (nxt == -1) { parent[i] = k; break; }
+                i = nxt;
+            }
+        }
+    }
+    // row k of L: the union of the tree paths from its neighbours below k up to k
+    int64_t nnz = n;
+    for (int k = 0; k < n; k++) {
+        mark[k] = k;
+        const int v = perm[k];
+        for (int p = Sp[v]; p < Sp[v + 1]; p++) {
+            int i = inv[Si[p]];
+            if (i > k) continue;
+            while (mark[i] != k) { mark[i] = k; nnz++; i = parent[i]; }
+        }
+    }
+    return nnz;
 }
 
 // Column elimination tree of H (the elimination tree of H'H) without forming
@@ -315,7 +380,8 @@ int run_analysis(Analysis &an, int n, const int32_t *colptr, const int32_t *rowi
     for (int i = 0; i < n; i++) browof[match[i]] = i;
     // ordering of B + B'
     std::vector<int> q(n);
-    if (ordering == CKTLU_ORDER_AMD) {
+    an.ordering_used = CKTLU_ORDER_NATURAL;
+    if (ordering == CKTLU_ORDER_AMD || ordering == CKTLU_ORDER_AMF || ordering == CKTLU_ORDER_AUTO) {
         std::vector<int> cnt(n + 1, 0);
         for (int j = 0; j < n; j++)
             for (int p = an.Ap[j]; p < an.Ap[j + 1]; p++) {
@@ -339,8 +405,21 @@ int run_analysis(Analysis &an, int n, const int32_t *colptr, const int32_t *rowi
                 if (Si[p] != prevv) { Sd.push_back(Si[p]); prevv = Si[p]; }
             Sp[i + 1] = (int)Sd.size();
         }
-        amd_order(n, Sp, Sd, q);
-        if ((int)q.size() != n) return CKTLU_E_ARG;
+        // the combined ordering (Section III-A): each method, keep the one with less fill
+        std::vector<int> qa, qf;
+        if (ordering != CKTLU_ORDER_AMF) {
+            amd_order(n, Sp, Sd, qa, false);
+            if ((int)qa.size() != n) return CKTLU_E_ARG;
+            if (ordering == CKTLU_ORDER_AUTO) an.fill_amd = symbolic_cholesky_nnz(n, Sp, Sd, qa);
+        }
+        if (ordering != CKTLU_ORDER_AMD) {
+            amd_order(n, Sp, Sd, qf, true);
+            if ((int)qf.size() != n) return CKTLU_E_ARG;
+            if (ordering == CKTLU_ORDER_AUTO) an.fill_amf = symbolic_cholesky_nnz(n, Sp, Sd, qf);
+        }
+        const bool use_amf = ordering == CKTLU_ORDER_AMF || (ordering == CKTLU_ORDER_AUTO && an.fill_amf < an.fill_amd);
+        q = use_amf ? qf : qa;
+        an.ordering_used = use_amf ? CKTLU_ORDER_AMF : CKTLU_ORDER_AMD;
     } else {
         std::iota(q.begin(), q.end(), 0);
     }

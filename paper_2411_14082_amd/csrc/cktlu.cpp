@@ -300,6 +300,9 @@ void fill_stats_pattern(cktlu_ctx *c) {
     t.levels = c->s.nlevels;
     t.max_width = c->s.max_width;
     t.etree_height = c->an.etree_height;
+    t.ordering_used = c->an.ordering_used;
+    t.fill_amd = c->an.fill_amd;
+    t.fill_amf = c->an.fill_amf;
     t.dense_tail = c->an.n - c->s.tail0;
     const double fb = c->opt.precision == CKTLU_FP32_IR ? 4.0 : 8.0;
     const double nF = (double)(t.nnz_l + t.nnz_u);
@@ -807,7 +810,7 @@ void cktlu_default_options(cktlu_options *o) {
     o->precision = CKTLU_FP64;
     o->ir_tol = 1e-10;
     o->ir_max_iter = 10;
-    o->ordering = CKTLU_ORDER_AMD;
+    o->ordering = CKTLU_ORDER_AUTO;
     o->transversal = 1;
     o->stream = nullptr;
     o->force_fail_col = -1;
@@ -824,6 +827,7 @@ int cktlu_create(cktlu_ctx **out, const cktlu_options *opt) {
     if (!(c->opt.pivot_eps > 0.0 && c->opt.pivot_eps <= 1.0) ||
         (c->opt.precision != CKTLU_FP64 && c->opt.precision != CKTLU_FP32_IR) || c->opt.ir_max_iter < 1 ||
         c->opt.solve_chain_width < -1 || (c->opt.dense_lookahead != 0 && c->opt.dense_lookahead != 1) ||
+        c->opt.ordering < CKTLU_ORDER_AMD || c->opt.ordering > CKTLU_ORDER_AUTO ||
         (c->opt.dense_device_repivot != 0 && c->opt.dense_device_repivot != -1) ||
         (c->opt.dense_panel_width != 0 && c->opt.dense_panel_width != 64 && c->opt.dense_panel_width != 128 &&
          c->opt.dense_panel_width != 256)) {
@@ -1337,6 +1341,11 @@ int cktlu_get_levels(const cktlu_ctx *c, int32_t *level) {
 int cktlu_get_stats(const cktlu_ctx *c, cktlu_stats *out) {
     if (!c || !out) return CKTLU_E_ARG;
     *out = c->stats;
+    if (c->state >= 1) {                  // the ordering is known from analyze on
+        out->ordering_used = c->an.ordering_used;
+        out->fill_amd = c->an.fill_amd;
+        out->fill_amf = c->an.fill_amf;
+    }
     return CKTLU_OK;
 }
 

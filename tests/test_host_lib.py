@@ -186,3 +186,63 @@ def test_dense_tail_selection():
             assert _trailing_density(f, c.n, D) >= dens
         for Dl in range(max(D + 64, 256), min(8192, c.n) // 64 * 64 + 1, 64):
             assert _trailing_density(f, c.n, Dl) < dens, (dens, D, Dl)
+
+
+def _sym_pattern(c, a):
+    """Adjacency (no diagonal) of B + B' where B is the transversal-permuted matrix
+    in analyze's numbering (B(i, j) = A(rowperm_pre[i], colperm[j]) up to the
+    ordering, which is undone here to get back to B's own numbering)."""
+    rp, cp = a["rowperm_pre"], a["colperm"]
+    A = c.to_scipy().tocsc()
+    H = A[rp][:, cp]                                   # the ordered matrix
+    S = (abs(H) + abs(H.T)).tocsr()
+    S.setdiag(0)
+    S.eliminate_zeros()
+    return S
+
+
+def _chol_nnz_brute(S):
+    """nnz (with the diagonal) of the Cholesky factor of pattern S in its own order,
+    by elimination on boolean sets."""
+    n = S.shape[0]
+    adj = [set(S.indices[S.indptr[i]:S.indptr[i + 1]].tolist()) for i in range(n)]
+    nnz = n
+    for k in range(n):
+        higher = [j for j in adj[k] if j > k]
+        nnz += len(higher)
+        for a_ in higher:
+            for b_ in higher:
+                if a_ != b_:
+                    adj[a_].add(b_)
+    return nnz
+
+
+@pytest.mark.parametrize("name,make", CASES, ids=[c[0] for c in CASES])
+def test_combined_ordering_auto(oracle_mod, name, make):
+    """AMF and AUTO orderings: valid permutations; AUTO's symbolic fill counts
+    equal a brute-force elimination of B + B' under each method's order, and AUTO
+    keeps the method with the smaller count (ties: AMD); the host factorization
+    under the chosen order matches the oracle."""
+    c = make()
+    amd = _analysed(c, ordering=ck.CKTLU_ORDER_AMD)
+    amf = _analysed(c, ordering=ck.CKTLU_ORDER_AMF)
+    auto = _analysed(c, ordering=ck.CKTLU_ORDER_AUTO)
+    st = auto.stats()
+    assert amd.stats()["ordering_used"] == ck.CKTLU_ORDER_AMD
+    assert amf.stats()["ordering_used"] == ck.CKTLU_ORDER_AMF
+    for s in (amd, amf, auto):
+        a = s.analysis(with_pivots=False)
+        assert np.array_equal(np.sort(a["colperm"]), np.arange(c.n))
+    if c.n <= 1100:
+        fa = _chol_nnz_brute(_sym_pattern(c, amd.analysis(with_pivots=False)))
+        ff = _chol_nnz_brute(_sym_pattern(c, amf.analysis(with_pivots=False)))
+        assert st["fill_amd"] == fa and st["fill_amf"] == ff, (st["fill_amd"], fa, st["fill_amf"], ff)
+    want = ck.CKTLU_ORDER_AMF if st["fill_amf"] < st["fill_amd"] else ck.CKTLU_ORDER_AMD
+    assert st["ordering_used"] == want
+    same = amf if want == ck.CKTLU_ORDER_AMF else amd
+    assert np.array_equal(auto.analysis(with_pivots=False)["colperm"], same.analysis(with_pivots=False)["colperm"])
+    auto.factorize_host(c.values)
+    a = auto.analysis()
+    lu = oracle_mod.gp_lu(c.n, c.colptr, c.rowind, c.values, a["rowperm_pre"], a["colperm"], 1e-3)
+    assert lu.status == 0 and np.array_equal(a["pivrow"], lu.pivrow)
+    compare_factors(auto.factors(), lu, rtol=64 * c.n * 1.2e-16)
