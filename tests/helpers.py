@@ -94,3 +94,9 @@ def pivot_entry(c, a, k):
     p = lo + int(np.searchsorted(c.rowind[lo:hi], r))
     assert c.rowind[p] == r
     return p
+
+
+def kappa_inf(c, values):
+    """Infinity-norm condition number of A (dense; for small n only)."""
+    A = sp.csc_matrix((values, c.rowind, c.colptr), shape=(c.n, c.n)).toarray()
+    return float(np.linalg.norm(A, np.inf) * np.linalg.norm(np.linalg.inv(A), np.inf))
