@@ -168,7 +168,7 @@ DevBuf *all_buffers(Device &d, int i) {
                      &d.item4, &d.tail_nb, &d.l21, &d.lrec, &d.urec,
                      &d.Lrjs, &d.Urjs, &d.lsptr, &d.usptr, &d.rowperm,
                      &d.colperm_sol, &d.Acp, &d.Acj, &d.Acsrc, &d.Fx64, &d.Fx32, &d.Aval, &d.done,
-                     &d.ctrl, &d.vec, &d.S, &d.Dg};
+                     &d.ctrl, &d.vec, &d.S, &d.Dg, &d.Dinv};
     const int cnt = (int)(sizeof(all) / sizeof(all[0]));
     return i < cnt ? all[i] : nullptr;
 }
@@ -234,6 +234,9 @@ int ensure_batch(cktlu_ctx *c, int batch) {
         if ((rc = dalloc(d.S, D * D * sizeof(double) * batch))) return rc;
         dfree(d.Dg);
         if ((rc = dalloc(d.Dg, (size_t)kDenseBlock * kDenseBlock * sizeof(double) * batch))) return rc;
+        dfree(d.Dinv);
+        const size_t nblk = (D + kDenseBlock - 1) / kDenseBlock;
+        if ((rc = dalloc(d.Dinv, nblk * 2 * kDenseBlock * kDenseBlock * sizeof(double) * batch))) return rc;
     }
     d.S_prec = -1;
     d.batch_cap = batch;
@@ -396,6 +399,7 @@ DenseArgs dense_args(cktlu_ctx *c, int batch, bool fp32) {
     a.nnzF = nnzF(c);
     a.S = d.S.p;
     a.Dg = d.Dg.p;
+    a.Dinv = (double *)d.Dinv.p;
     a.ctrl = (int *)d.ctrl.p;
     a.done = (int *)d.done.p;
     a.force_fail_col = -1;
@@ -421,6 +425,7 @@ int ensure_lookahead(cktlu_ctx *c, const DenseArgs &da) {
 int ensure_S(cktlu_ctx *c, bool fp32, int batch) {
     if (c->s.tail0 >= c->an.n || c->dev.S_prec == (fp32 ? 1 : 0)) return CKTLU_OK;
     LCHK(launch_dense_gather(dense_args(c, batch, fp32), stream_of(c)));
+    LCHK(launch_dense_inverses(dense_args(c, batch, fp32), stream_of(c)));
     c->dev.S_prec = fp32 ? 1 : 0;
     return CKTLU_OK;
 }
@@ -1365,8 +1370,10 @@ size_t cktlu_footprint_bytes(const cktlu_ctx *c, int32_t batch) {
     for (int i = 0; DevBuf *b = all_buffers(d, i); i++) s += b->bytes;
     const int64_t F = c->s.nnz_dev;
     const size_t Dt = (size_t)(c->an.n - c->s.tail0);
+    const size_t nblk = (Dt + kDenseBlock - 1) / kDenseBlock;
     const size_t per = (size_t)F * (c->opt.precision == CKTLU_FP32_IR ? 12 : 8) + (size_t)c->an.nnz * 8 +
-                       (size_t)c->an.n * (4 + 8 * YS) + Dt * Dt * 8;
+                       (size_t)c->an.n * (4 + 8 * YS) + Dt * Dt * 8 +
+                       nblk * 2 * kDenseBlock * kDenseBlock * 8;
     if (!c->dev.uploaded) s += (size_t)F * 12 + (size_t)c->an.nnz * 12 + (size_t)c->an.n * 64;
     return s + (batch > 0 ? per * (size_t)batch : 0);
 }

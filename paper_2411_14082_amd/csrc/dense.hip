@@ -452,6 +452,49 @@ __global__ __launch_bounds__(256) void dlu_check_kernel(DenseArgs a) {
     }
 }
 
+// ------------------------------------------------- diagonal-block inverses
+// For the dense solves: the inverses of each 64 x 64 diagonal block's unit-lower and
+// upper triangles (the last block padded with the identity), FP64 whatever the factor
+// type.  One wavefront per (block, instance); lane j forms column j of each inverse
+// by substitution with the block read from LDS by broadcast.  Stored at
+// Dinv + ((inst * nblk + b) * 2 + {0: L, 1: U}) * 64 * 64, column-major.
+template <typename T>
+__global__ __launch_bounds__(64) void dlu_inverse_kernel(DenseArgs a) {
+    __shared__ double blk[NB][NB + 1];                // blk[col][row]
+    // no early exit for instances whose sweep failed: S may be re-gathered after a fallback
+    // while the status words still record the failure (a failed instance's solve is skipped)
+    const int b = blockIdx.x, inst = blockIdx.y, j = threadIdx.x;
+    const T *S = inst_S<T>(a, inst);
+    const int D = a.D, p = b * NB, nb = min(NB, D - p), nblk = (D + NB - 1) / NB;
+    for (int c = 0; c < NB; c++)
+        blk[c][j] = (c < nb && j < nb) ? (double)S[(size_t)(p + c) * D + p + j] : (c == j ? 1.0 : 0.0);
+    __syncthreads();
+    double *out = a.Dinv + ((size_t)inst * nblk + b) * 2 * NB * NB;
+    double x[NB];
+    // L x = e_j, unit diagonal
+#pragma unroll
+    for (int i = 0; i < NB; i++) {
+        double v = i == j ? 1.0 : 0.0;
+#pragma unroll
+        for (int k = 0; k < i; k++) v -= blk[k][i] * x[k];
+        x[i] = v;
+        asm volatile("" ::: "memory");                // each row's LDS reads stay with it
+    }
+#pragma unroll
+    for (int i = 0; i < NB; i++) out[(size_t)j * NB + i] = x[i];
+    // U x = e_j
+#pragma unroll
+    for (int i = NB - 1; i >= 0; i--) {
+        double v = i == j ? 1.0 : 0.0;
+#pragma unroll
+        for (int k = i + 1; k < NB; k++) v -= blk[k][i] * x[k];
+        x[i] = v / blk[i][i];
+        asm volatile("" ::: "memory");
+    }
+#pragma unroll
+    for (int i = 0; i < NB; i++) out[(size_t)NB * NB + (size_t)j * NB + i] = x[i];
+}
+
 // ------------------------------------------------------------- dense solves
 // y rows T.. of each instance hold the partial solution (YS doubles per row).
 // Lower, unit diagonal: launch b applies block b-1 to rows >= b*NB (a row per
@@ -466,6 +509,15 @@ __global__ __launch_bounds__(256) void dtrsv_lower_kernel(DenseArgs a, double *y
     const T *S = inst_S<T>(a, inst);
     double *yt = y + ((size_t)inst * a.n + a.T) * YS;
     const int D = a.D, tid = threadIdx.x;
+    const int p = b * NB, nb = min(NB, D - p);
+    // workgroup 0: the inverse of block b's unit-lower triangle (made at factorization time),
+    // loaded before the rectangle
+    const double *inv = a.Dinv + ((size_t)inst * ((D + NB - 1) / NB) + b) * 2 * NB * NB;   // [col][row]
+    double t[16];
+    if (blockIdx.x == 0) {
+#pragma unroll
+        for (int u = 0; u < 16; u++) t[u] = inv[tid + 256 * u];
+    }
     if (b > 0) {
         const int pb = (b - 1) * NB;
         if (tid < NB * NR / 2) {                      // NB * NR <= 512: two loads per thread
@@ -492,33 +544,28 @@ __global__ __launch_bounds__(256) void dtrsv_lower_kernel(DenseArgs a, double *y
         __syncthreads();
     }
     if (blockIdx.x != 0) return;
-    // block b: stage L(p.., p..) in LDS, then one wavefront substitutes (lane i = row p + i)
-    const int p = b * NB, nb = min(NB, D - p);
-    {
-        double t[16];                                 // column e/64, row e%64 of the block
-#pragma unroll
-        for (int u = 0; u < 16; u++) {
-            const int e = tid + 256 * u, cc = e / NB, rr = e % NB;
-            t[u] = (cc < nb && rr < nb) ? (double)S[(size_t)(p + cc) * D + p + rr] : 0.0;
-        }
-#pragma unroll
-        for (int u = 0; u < 16; u++) tri[(tid + 256 * u) / NB][(tid + 256 * u) % NB] = t[u];
+    // block b: y_b = L_bb^-1 y_b (a row per lane, the block's values read from LDS by broadcast)
+    if (tid < NB * NR / 2) {
+        const int e1 = tid + NB * NR / 2;
+        const double y0 = tid / NR < nb ? yt[(size_t)(p + tid / NR) * YS + tid % NR] : 0.0;
+        const double y1 = e1 / NR < nb ? yt[(size_t)(p + e1 / NR) * YS + e1 % NR] : 0.0;
+        yb[tid / NR][tid % NR] = y0;
+        yb[e1 / NR][e1 % NR] = y1;
     }
+#pragma unroll
+    for (int u = 0; u < 16; u++) tri[(tid + 256 * u) / NB][(tid + 256 * u) % NB] = t[u];
     __syncthreads();
-    if (tid >= WAVE) return;
-    double yv[NR];
+    if (tid >= nb) return;
+    double acc[NR];
 #pragma unroll
-    for (int r = 0; r < NR; r++) yv[r] = tid < nb ? yt[(size_t)(p + tid) * YS + r] : 0.0;
-    for (int kk = 0; kk < nb; kk++) {
-        const double lik_ = tri[kk][tid];
-        const double lik = tid > kk ? lik_ : 0.0;
+    for (int r = 0; r < NR; r++) acc[r] = 0.0;
+    for (int k = 0; k <= tid; k++) {                  // the unit-lower inverse is lower triangular
+        const double l = tri[k][tid];
 #pragma unroll
-        for (int r = 0; r < NR; r++) yv[r] -= lik * readlane(yv[r], kk);
+        for (int r = 0; r < NR; r++) acc[r] += l * yb[k][r];
     }
-    if (tid < nb) {
 #pragma unroll
-        for (int r = 0; r < NR; r++) yt[(size_t)(p + tid) * YS + r] = yv[r];
-    }
+    for (int r = 0; r < NR; r++) yt[(size_t)(p + tid) * YS + r] = acc[r];
 }
 
 // Upper with its diagonal: launch b handles block blk = nblk-1-b: it applies
@@ -535,6 +582,13 @@ __global__ __launch_bounds__(256) void dtrsv_upper_kernel(DenseArgs a, double *y
     const int nblk = (D + NB - 1) / NB;
     const int blk = nblk - 1 - b;
     const int p = blk * NB, nb = min(NB, D - p);
+    // workgroup 0: the inverse of block blk's upper triangle, loaded before the rectangle
+    const double *inv = a.Dinv + ((size_t)inst * nblk + blk) * 2 * NB * NB + NB * NB;   // [col][row]
+    double t[16];
+    if (blockIdx.x == 0) {
+#pragma unroll
+        for (int u = 0; u < 16; u++) t[u] = inv[tid + 256 * u];
+    }
     if (b > 0) {
         const int pb = (blk + 1) * NB, nbb = min(NB, D - pb);
         if (tid < NB * NR / 2) {                      // NB * NR <= 512: two loads per thread
@@ -561,35 +615,28 @@ __global__ __launch_bounds__(256) void dtrsv_upper_kernel(DenseArgs a, double *y
         __syncthreads();
     }
     if (blockIdx.x != 0) return;
-    {
-        double t[16];                                 // column e/64, row e%64 of the block
-#pragma unroll
-        for (int u = 0; u < 16; u++) {
-            const int e = tid + 256 * u, cc = e / NB, rr = e % NB;
-            t[u] = (cc < nb && rr < nb) ? (double)S[(size_t)(p + cc) * D + p + rr] : 0.0;
-        }
-#pragma unroll
-        for (int u = 0; u < 16; u++) tri[(tid + 256 * u) / NB][(tid + 256 * u) % NB] = t[u];
+    // block blk: x = U_bb^-1 y
+    if (tid < NB * NR / 2) {
+        const int e1 = tid + NB * NR / 2;
+        const double y0 = tid / NR < nb ? yt[(size_t)(p + tid / NR) * YS + tid % NR] : 0.0;
+        const double y1 = e1 / NR < nb ? yt[(size_t)(p + e1 / NR) * YS + e1 % NR] : 0.0;
+        yb[tid / NR][tid % NR] = y0;
+        yb[e1 / NR][e1 % NR] = y1;
     }
+#pragma unroll
+    for (int u = 0; u < 16; u++) tri[(tid + 256 * u) / NB][(tid + 256 * u) % NB] = t[u];
     __syncthreads();
-    if (tid >= WAVE) return;
-    double yv[NR];
+    if (tid >= nb) return;
+    double acc[NR];
 #pragma unroll
-    for (int r = 0; r < NR; r++) yv[r] = tid < nb ? yt[(size_t)(p + tid) * YS + r] : 0.0;
-    for (int kk = nb - 1; kk >= 0; kk--) {
-        if (tid == kk) {
+    for (int r = 0; r < NR; r++) acc[r] = 0.0;
+    for (int k = tid; k < nb; k++) {                  // the upper inverse is upper triangular
+        const double u = tri[k][tid];
 #pragma unroll
-            for (int r = 0; r < NR; r++) yv[r] = yv[r] / tri[kk][kk];
-        }
-        const double uik_ = tri[kk][tid];
-        const double uik = tid < kk ? uik_ : 0.0;
-#pragma unroll
-        for (int r = 0; r < NR; r++) yv[r] -= uik * readlane(yv[r], kk);
+        for (int r = 0; r < NR; r++) acc[r] += u * yb[k][r];
     }
-    if (tid < nb) {
 #pragma unroll
-        for (int r = 0; r < NR; r++) yt[(size_t)(p + tid) * YS + r] = yv[r];
-    }
+    for (int r = 0; r < NR; r++) yt[(size_t)(p + tid) * YS + r] = acc[r];
 }
 
 template <typename T, int NR>
@@ -868,7 +915,8 @@ int launch_dense_refactor(const DenseArgs &a, bool gather, const DenseStreams *l
     }
     if (a.fp32) hipLaunchKernelGGL((tail_scatter_kernel<float>), gw, dim3(256), 0, st, a);
     else hipLaunchKernelGGL((tail_scatter_kernel<double>), gw, dim3(256), 0, st, a);
-    return (int)hipGetLastError();
+    const int e = (int)hipGetLastError();
+    return e ? e : launch_dense_inverses(a, stream);
 }
 
 int launch_dense_pivoted_lu(const DenseArgs &a, int *swp, int *info, void *stream) {
@@ -900,6 +948,14 @@ int launch_dense_pivoted_lu(const DenseArgs &a, int *swp, int *info, void *strea
                                g1, -1);
         }
     }
+    return (int)hipGetLastError();
+}
+
+int launch_dense_inverses(const DenseArgs &a, void *stream) {
+    if (a.D <= 0) return 0;
+    const dim3 g((unsigned)((a.D + NB - 1) / NB), (unsigned)a.batch);
+    if (a.fp32) hipLaunchKernelGGL((dlu_inverse_kernel<float>), g, dim3(NB), 0, (hipStream_t)stream, a);
+    else hipLaunchKernelGGL((dlu_inverse_kernel<double>), g, dim3(NB), 0, (hipStream_t)stream, a);
     return (int)hipGetLastError();
 }
 

@@ -139,6 +139,7 @@ struct Device {
     DevBuf vec;                        // solve work vectors
     DevBuf S;                          // dense trailing block, batch x D x D (8-byte slots)
     DevBuf Dg;                         // batch x 64 x 64 (8-byte slots): a panel's diagonal block
+    DevBuf Dinv;                       // batch x nblk x 2 x 64 x 64 FP64: diagonal blocks' inverses
     size_t vec_cap = 0;
     unsigned epoch = 0;
     int S_prec = -1;                   // what S holds: -1 stale, 0 FP64 factors, 1 FP32 factors
@@ -246,6 +247,7 @@ struct DenseArgs {
     int64_t nnzF;
     void *S;                   // batch x D x D values of the factor type
     void *Dg;                  // batch x NB x NB: factored diagonal block of the current panel
+    double *Dinv;              // batch x nblk x 2 x NB x NB: inverses of the diagonal blocks' L and U
     int *ctrl, *done;          // status words and completion epochs (as RefactorArgs)
     double eps;
     unsigned epoch;
@@ -277,7 +279,9 @@ int dense_lookahead_events(const DenseArgs &a);
 // positions; swap[c] (device, D ints) is the position exchanged with c at step c.
 // info (device int, zeroed here) receives 1 + the first column with no usable pivot.
 int launch_dense_pivoted_lu(const DenseArgs &a, int *swap, int *info, void *stream);
-// y rows [T, n): lower (unit) or upper triangular solve with the block in S
+// Dinv <- inverses of the unit-lower and upper triangles of S's 64 x 64 diagonal blocks
+int launch_dense_inverses(const DenseArgs &a, void *stream);
+// y rows [T, n): lower (unit) or upper triangular solve with the block in S and Dinv
 int launch_dense_solve(const DenseArgs &a, double *y, int nrhs, const int *skip, bool upper, void *stream);
 
 }  // namespace cktlu_dev
