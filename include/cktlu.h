@@ -54,8 +54,9 @@ extern "C" {
 #define CKTLU_ORDER_AMD 0       /* approximate minimum degree on the pattern of B + B' */
 #define CKTLU_ORDER_NATURAL 1   /* keep the (transversal-permuted) natural order */
 #define CKTLU_ORDER_AMF 2       /* approximate minimum fill on the pattern of B + B' */
-#define CKTLU_ORDER_AUTO 3      /* both AMD and AMF; keep the one whose symbolic Cholesky of B + B' has
-                                   fewer entries (ties: AMD), the combined ordering of Section III-A */
+#define CKTLU_ORDER_AUTO 3      /* AMD, AMF and ND; keep the one whose symbolic Cholesky of B + B' has the
+                                   fewest entries (ties: the earlier), the combined ordering of Section III-A */
+#define CKTLU_ORDER_ND 4        /* nested dissection (level-set separators), AMD on parts of <= 4096 nodes */
 
 typedef struct cktlu_ctx cktlu_ctx;
 
@@ -64,7 +65,7 @@ typedef struct {
     int precision;         /* CKTLU_FP64 (default) or CKTLU_FP32_IR */
     double ir_tol;         /* FP32_IR: backward-error target; default 1e-10 */
     int ir_max_iter;       /* FP32_IR: refinement step limit; default 10 */
-    int ordering;          /* CKTLU_ORDER_*; default AUTO (AMD and AMF, the one with less fill) */
+    int ordering;          /* CKTLU_ORDER_*; default AUTO (AMD, AMF and ND, the one with the least fill) */
     int transversal;       /* 1 (default): structural maximum transversal before ordering */
     void *stream;          /* hipStream_t for all device work; NULL = the null stream */
     int force_fail_col;    /* test hook: >= 0 makes the pivot check of this column fail once */
@@ -124,8 +125,8 @@ typedef struct {
     int64_t n_device_repivot;         /* fallbacks whose restart set lay inside the dense block and were
                                          re-factored on the device (pivoted dense LU) */
     int64_t ordering_used;            /* CKTLU_ORDER_* that analyze applied */
-    int64_t fill_amd, fill_amf;       /* CKTLU_ORDER_AUTO: entries of the symbolic Cholesky factor of B + B'
-                                         under each method (-1 when not run) */
+    int64_t fill_amd, fill_amf, fill_nd;  /* CKTLU_ORDER_AUTO: entries of the symbolic Cholesky factor of
+                                         B + B' under each method (-1 when not run) */
 } cktlu_stats;
 
 /* Device time of the phases, accumulated over the calls made with options.timing = 1

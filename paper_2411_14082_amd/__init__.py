@@ -35,6 +35,7 @@ CKTLU_ORDER_AMD = 0
 CKTLU_ORDER_NATURAL = 1
 CKTLU_ORDER_AMF = 2
 CKTLU_ORDER_AUTO = 3
+CKTLU_ORDER_ND = 4
 
 # every symbol the header declares (checked by the CPU test-suite)
 EXPORTS = [
@@ -80,7 +81,7 @@ class cktlu_stats(ctypes.Structure):
                 ("flops_dense", ctypes.c_double), ("macs_schur", ctypes.c_double), ("sweep_launches", ctypes.c_int64),
                 ("dense_launches", ctypes.c_int64), ("solve_launches", ctypes.c_int64),
                 ("n_device_repivot", ctypes.c_int64), ("ordering_used", ctypes.c_int64),
-                ("fill_amd", ctypes.c_int64), ("fill_amf", ctypes.c_int64)]
+                ("fill_amd", ctypes.c_int64), ("fill_amf", ctypes.c_int64), ("fill_nd", ctypes.c_int64)]
 
     def as_dict(self):
         return {f: getattr(self, f) for f, _ in self._fields_}

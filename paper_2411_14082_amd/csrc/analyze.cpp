@@ -308,6 +308,97 @@ void amd_order(int n, const std::vector<int> &Sp, const std::vector<int> &Si,
     for (int i : dense) perm.push_back(i);
 }
 
+// Nested dissection of a symmetric pattern: a node set is split by the smallest
+// breadth-first level set near the middle of a level structure rooted at a
+// pseudo-peripheral node (two sweeps); both halves are ordered first, then the
+// separator.  Disconnected sets split into components; sets of at most `leaf` nodes
+// (or with fewer than three levels) are ordered by AMD on their induced subgraph.
+void nd_order(int n, const std::vector<int> &Sp, const std::vector<int> &Si, std::vector<int> &perm,
+              int leaf) {
+    perm.clear();
+    perm.reserve(n);
+    if (n == 0) return;
+    std::vector<int> inset(n, -1), lev(n, -1), local(n, -1);
+    int stamp = 0;
+    struct Task { std::vector<int> nodes; bool emit; };
+    std::vector<Task> stack;
+    std::vector<int> all(n);
+    std::iota(all.begin(), all.end(), 0);
+    stack.push_back({std::move(all), false});
+    std::vector<int> order, lptr;                       // BFS order and level pointers
+    auto bfs = [&](int root, int tag) {
+        order.clear();
+        lptr.assign(1, 0);
+        order.push_back(root);
+        lev[root] = tag;
+        size_t h = 0;
+        while (h < order.size()) {
+            const size_t e = order.size();
+            for (; h < e; h++) {
+                const int u = order[h];
+                for (int q = Sp[u]; q < Sp[u + 1]; q++) {
+                    const int v = Si[q];
+                    if (inset[v] == stamp && lev[v] != tag) { lev[v] = tag; order.push_back(v); }
+                }
+            }
+            lptr.push_back((int)e);
+        }
+        lptr.pop_back();
+        lptr.push_back((int)order.size());
+    };
+    std::vector<int> lSp, lSi, lperm;
+    int tag = 0;
+    while (!stack.empty()) {
+        Task t = std::move(stack.back());
+        stack.pop_back();
+        if (t.emit) { perm.insert(perm.end(), t.nodes.begin(), t.nodes.end()); continue; }
+        std::vector<int> &nodes = t.nodes;
+        ++stamp;
+        for (int v : nodes) inset[v] = stamp;
+        bool split = (int)nodes.size() > leaf;
+        if (split) {
+            bfs(nodes[0], ++tag);
+            if (order.size() < nodes.size()) {            // disconnected: this component, the rest
+                std::vector<int> rest;
+                for (int v : nodes) if (lev[v] != tag) rest.push_back(v);
+                std::vector<int> comp(order.begin(), order.end());
+                stack.push_back({std::move(rest), false});
+                stack.push_back({std::move(comp), false});
+                continue;
+            }
+            bfs(order.back(), ++tag);                     // from the farthest node
+            const int L = (int)lptr.size() - 1;
+            if (L < 3) split = false;
+            else {
+                const int mid = L / 2;
+                int m = std::max(1, mid - 3);
+                for (int i = m; i <= std::min(L - 2, mid + 3); i++)
+                    if (lptr[i + 1] - lptr[i] < lptr[m + 1] - lptr[m]) m = i;
+                std::vector<int> A(order.begin(), order.begin() + lptr[m]);
+                std::vector<int> sep(order.begin() + lptr[m], order.begin() + lptr[m + 1]);
+                std::vector<int> B(order.begin() + lptr[m + 1], order.end());
+                stack.push_back({std::move(sep), true});
+                stack.push_back({std::move(B), false});
+                stack.push_back({std::move(A), false});
+                continue;
+            }
+        }
+        // leaf: AMD on the induced subgraph
+        const int nl = (int)nodes.size();
+        for (int i = 0; i < nl; i++) local[nodes[i]] = i;
+        lSp.assign(nl + 1, 0);
+        lSi.clear();
+        for (int i = 0; i < nl; i++) {
+            const int u = nodes[i];
+            for (int q = Sp[u]; q < Sp[u + 1]; q++)
+                if (inset[Si[q]] == stamp) lSi.push_back(local[Si[q]]);
+            lSp[i + 1] = (int)lSi.size();
+        }
+        amd_order(nl, lSp, lSi, lperm, false);
+        for (int i = 0; i < nl; i++) perm.push_back(nodes[lperm[i]]);
+    }
+}
+
 int64_t symbolic_cholesky_nnz(int n, const std::vector<int> &Sp, const std::vector<int> &Si,
                               const std::vector<int> &perm) {
     std::vector<int> inv(n), parent(n, -1), ancestor(n, -1), mark(n, -1);
@@ -381,7 +472,7 @@ int run_analysis(Analysis &an, int n, const int32_t *colptr, const int32_t *rowi
     // ordering of B + B'
     std::vector<int> q(n);
     an.ordering_used = CKTLU_ORDER_NATURAL;
-    if (ordering == CKTLU_ORDER_AMD || ordering == CKTLU_ORDER_AMF || ordering == CKTLU_ORDER_AUTO) {
+    if (ordering != CKTLU_ORDER_NATURAL) {
         std::vector<int> cnt(n + 1, 0);
         for (int j = 0; j < n; j++)
             for (int p = an.Ap[j]; p < an.Ap[j + 1]; p++) {
@@ -406,20 +497,20 @@ int run_analysis(Analysis &an, int n, const int32_t *colptr, const int32_t *rowi
             Sp[i + 1] = (int)Sd.size();
         }
         // the combined ordering (Section III-A): each method, keep the one with less fill
-        std::vector<int> qa, qf;
-        if (ordering != CKTLU_ORDER_AMF) {
-            amd_order(n, Sp, Sd, qa, false);
-            if ((int)qa.size() != n) return CKTLU_E_ARG;
-            if (ordering == CKTLU_ORDER_AUTO) an.fill_amd = symbolic_cholesky_nnz(n, Sp, Sd, qa);
+        const bool autom = ordering == CKTLU_ORDER_AUTO;
+        std::vector<int> qm;
+        int64_t best = -1;
+        const int methods[3] = {CKTLU_ORDER_AMD, CKTLU_ORDER_AMF, CKTLU_ORDER_ND};
+        for (int m : methods) {
+            if (!autom && ordering != m) continue;
+            if (m == CKTLU_ORDER_ND) nd_order(n, Sp, Sd, qm, kNdLeaf);
+            else amd_order(n, Sp, Sd, qm, m == CKTLU_ORDER_AMF);
+            if ((int)qm.size() != n) return CKTLU_E_ARG;
+            if (!autom) { q.swap(qm); an.ordering_used = m; break; }
+            const int64_t f = symbolic_cholesky_nnz(n, Sp, Sd, qm);
+            (m == CKTLU_ORDER_AMD ? an.fill_amd : m == CKTLU_ORDER_AMF ? an.fill_amf : an.fill_nd) = f;
+            if (best < 0 || f < best) { best = f; q.swap(qm); an.ordering_used = m; }   // ties keep the earlier
         }
-        if (ordering != CKTLU_ORDER_AMD) {
-            amd_order(n, Sp, Sd, qf, true);
-            if ((int)qf.size() != n) return CKTLU_E_ARG;
-            if (ordering == CKTLU_ORDER_AUTO) an.fill_amf = symbolic_cholesky_nnz(n, Sp, Sd, qf);
-        }
-        const bool use_amf = ordering == CKTLU_ORDER_AMF || (ordering == CKTLU_ORDER_AUTO && an.fill_amf < an.fill_amd);
-        q = use_amf ? qf : qa;
-        an.ordering_used = use_amf ? CKTLU_ORDER_AMF : CKTLU_ORDER_AMD;
     } else {
         std::iota(q.begin(), q.end(), 0);
     }

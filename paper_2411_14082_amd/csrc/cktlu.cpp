@@ -306,6 +306,7 @@ void fill_stats_pattern(cktlu_ctx *c) {
     t.ordering_used = c->an.ordering_used;
     t.fill_amd = c->an.fill_amd;
     t.fill_amf = c->an.fill_amf;
+    t.fill_nd = c->an.fill_nd;
     t.dense_tail = c->an.n - c->s.tail0;
     const double fb = c->opt.precision == CKTLU_FP32_IR ? 4.0 : 8.0;
     const double nF = (double)(t.nnz_l + t.nnz_u);
@@ -832,7 +833,7 @@ int cktlu_create(cktlu_ctx **out, const cktlu_options *opt) {
     if (!(c->opt.pivot_eps > 0.0 && c->opt.pivot_eps <= 1.0) ||
         (c->opt.precision != CKTLU_FP64 && c->opt.precision != CKTLU_FP32_IR) || c->opt.ir_max_iter < 1 ||
         c->opt.solve_chain_width < -1 || (c->opt.dense_lookahead != 0 && c->opt.dense_lookahead != 1) ||
-        c->opt.ordering < CKTLU_ORDER_AMD || c->opt.ordering > CKTLU_ORDER_AUTO ||
+        c->opt.ordering < CKTLU_ORDER_AMD || c->opt.ordering > CKTLU_ORDER_ND ||
         (c->opt.dense_device_repivot != 0 && c->opt.dense_device_repivot != -1) ||
         (c->opt.dense_panel_width != 0 && c->opt.dense_panel_width != 64 && c->opt.dense_panel_width != 128 &&
          c->opt.dense_panel_width != 256)) {
@@ -1350,6 +1351,7 @@ int cktlu_get_stats(const cktlu_ctx *c, cktlu_stats *out) {
         out->ordering_used = c->an.ordering_used;
         out->fill_amd = c->an.fill_amd;
         out->fill_amf = c->an.fill_amf;
+        out->fill_nd = c->an.fill_nd;
     }
     return CKTLU_OK;
 }

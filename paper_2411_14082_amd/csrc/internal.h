@@ -21,7 +21,7 @@ struct Analysis {
     std::vector<int> parent;               // column elimination tree of A_hat
     int etree_height = 0;
     int ordering_used = 0;                 // CKTLU_ORDER_* that produced colperm
-    int64_t fill_amd = -1, fill_amf = -1;  // nnz of the symbolic Cholesky of B + B' under each (-1: not run)
+    int64_t fill_amd = -1, fill_amf = -1, fill_nd = -1;  // nnz of the symbolic Cholesky of B + B' under each
 };
 
 int validate_csc(int n, const int32_t *colptr, const int32_t *rowind);
@@ -29,6 +29,10 @@ bool max_transversal(int n, const std::vector<int> &Ap, const std::vector<int> &
                      std::vector<int> &match_of_col);
 void amd_order(int n, const std::vector<int> &Sp, const std::vector<int> &Si,
                std::vector<int> &perm, bool amf = false);
+// nested dissection with AMD on parts of at most `leaf` nodes
+constexpr int kNdLeaf = 4096;
+void nd_order(int n, const std::vector<int> &Sp, const std::vector<int> &Si, std::vector<int> &perm,
+              int leaf);
 // nnz (diagonal included) of the Cholesky factor of the symmetric pattern (Sp, Si)
 // eliminated in the order perm: elimination tree, then one row subtree per row
 int64_t symbolic_cholesky_nnz(int n, const std::vector<int> &Sp, const std::vector<int> &Si,

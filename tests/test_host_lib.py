@@ -246,3 +246,34 @@ def test_combined_ordering_auto(oracle_mod, name, make):
     lu = oracle_mod.gp_lu(c.n, c.colptr, c.rowind, c.values, a["rowperm_pre"], a["colperm"], 1e-3)
     assert lu.status == 0 and np.array_equal(a["pivrow"], lu.pivrow)
     compare_factors(auto.factors(), lu, rtol=64 * c.n * 1.2e-16)
+
+
+def test_nested_dissection_ordering(oracle_mod):
+    """ND ordering on a grid larger than its leaf size (so it dissects): a valid
+    permutation, its symbolic fill equals a brute-force elimination of B + B' in
+    that order, it beats the banded natural order's fill, AUTO keeps the least of
+    the three counts, and the host factorization under ND matches the oracle.  On
+    a matrix no larger than a leaf, ND is AMD itself."""
+    c = mnagen.power_grid(72, 72, seed=3)
+    assert c.n > 4096
+    nd = _analysed(c, ordering=ck.CKTLU_ORDER_ND)
+    assert nd.stats()["ordering_used"] == ck.CKTLU_ORDER_ND
+    a = nd.analysis(with_pivots=False)
+    assert np.array_equal(np.sort(a["colperm"]), np.arange(c.n))
+    fnd = _chol_nnz_brute(_sym_pattern(c, a))
+    nat = _analysed(c, ordering=ck.CKTLU_ORDER_NATURAL)
+    assert fnd < _chol_nnz_brute(_sym_pattern(c, nat.analysis(with_pivots=False)))
+    st = _analysed(c, ordering=ck.CKTLU_ORDER_AUTO).stats()
+    assert st["fill_nd"] == fnd
+    fills = {ck.CKTLU_ORDER_AMD: st["fill_amd"], ck.CKTLU_ORDER_AMF: st["fill_amf"], ck.CKTLU_ORDER_ND: st["fill_nd"]}
+    best = min(fills.values())
+    assert st["ordering_used"] == min(m for m, f in fills.items() if f == best)
+    nd.factorize_host(c.values)
+    a = nd.analysis()
+    lu = oracle_mod.gp_lu(c.n, c.colptr, c.rowind, c.values, a["rowperm_pre"], a["colperm"], 1e-3)
+    assert lu.status == 0 and np.array_equal(a["pivrow"], lu.pivrow)
+    compare_factors(nd.factors(), lu, rtol=64 * c.n * 1.2e-16)
+    small = mnagen.power_grid(30, 30, seed=1)
+    p_nd = _analysed(small, ordering=ck.CKTLU_ORDER_ND).analysis(with_pivots=False)["colperm"]
+    p_amd = _analysed(small, ordering=ck.CKTLU_ORDER_AMD).analysis(with_pivots=False)["colperm"]
+    assert np.array_equal(p_nd, p_amd)
