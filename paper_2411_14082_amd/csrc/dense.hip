@@ -10,7 +10,7 @@
 //   dlu_panel  every workgroup factors the NB x NB diagonal block in registers
 //              (a wavefront, lane = row), then computes its share of
 //              L21 = A21 U11^-1 or U12 = L11^-1 A12 (sixteen rows or columns
-//              per wavefront);
+//              per wavefront) by block substitution on the matrix cores;
 //   dlu_gemm   C -= L21 U12 on the matrix cores: 128 x 128 output tiles, K in
 //              LDS-staged chunks, v_mfma_f64_16x16x4 (v_mfma_f32_16x16x4 for FP32
 //              factors).  After a panel it updates only the rest of its group
@@ -207,6 +207,21 @@ __device__ __forceinline__ float readlane(float v, int l) {
     return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), l));
 }
 
+// 1 / u.  FP64: the hardware reciprocal refined by two Newton-Raphson steps
+// (r <- r + r (1 - u r)), each of which doubles the correct bits, for |u| in
+// [2^-1000, 2^1000] (no overflow or underflow on the way); elsewhere, and for FP32,
+// the division.  The branch is uniform: u comes from readlane.
+__device__ __forceinline__ double recip(double u) {
+    const double au = __builtin_fabs(u);
+    if (au >= 0x1p-1000 && au <= 0x1p1000) {
+        double r = __builtin_amdgcn_rcp(u);
+        r = fma(r, fma(-u, r, 1.0), r);
+        return fma(r, fma(-u, r, 1.0), r);
+    }
+    return 1.0 / u;
+}
+__device__ __forceinline__ float recip(float u) { return 1.0f / u; }
+
 // Factors the nb x nb diagonal block at (p, p) of S (padded to NB x NB with the
 // identity) without pivoting, in one wavefront: lane r holds row r, v[c] its
 // entry in column c, fully unrolled, so step kk reads row kk (U(kk, c)) from
@@ -222,7 +237,7 @@ __device__ void diag_factor_wave(const T *S, int D, int p, int nb, T (*blk)[NB +
         v[c] = (lane < nb && c < nb) ? S[(size_t)(p + c) * D + p + lane] : (lane == c ? T(1) : T(0));
 #pragma unroll
     for (int kk = 0; kk < NB; kk++) {
-        const T inv = T(1) / readlane(v[kk], kk);
+        const T inv = recip(readlane(v[kk], kk));
         if (lane == 0) invd[kk] = inv;
         const T l = lane > kk ? v[kk] * inv : T(0);
         v[kk] = lane > kk ? l : v[kk];
@@ -233,17 +248,33 @@ __device__ void diag_factor_wave(const T *S, int D, int p, int nb, T (*blk)[NB +
     for (int c = 0; c < NB; c++) blk[c][lane] = v[c];
 }
 
+// k of step s for lane group g (= lane / 16) in a 16 x 16 x 4 MFMA chain: the
+// accumulator's element s is then the B operand of step s.  FP64 accumulators hold
+// rows 4s + g, FP32 rows 4g + s (column lane % 16 in both).
+template <typename T>
+__device__ __forceinline__ int kidx(int s, int g) { return sizeof(T) == 8 ? 4 * s + g : 4 * g + s; }
+
+template <typename T>
+__device__ __forceinline__ auto mfma16(T a, T b, typename std::conditional<sizeof(T) == 8, d4, f4>::type c) {
+    if constexpr (sizeof(T) == 8) return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+    else return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+}
+
 // One panel [p, p+nb).  In every workgroup wavefront 0 factors the diagonal
-// block (workgroup 0 writes it back) while the others wait; then each
-// wavefront computes sixteen rows of L21 = A21 U11^-1 or sixteen columns of
-// U12 = L11^-1 A12: lane m holds element m of each of its rows (columns) and
-// step kk broadcasts element kk by readlane.  Workgroups [1, 1+nrb) take 64 rows
-// each, the rest 64 columns each.
+// block (workgroup 0 writes it back) while the others wait.  The other
+// workgroups compute L21 = A21 U11^-1 (the first nrb, 64 rows each) or
+// U12 = L11^-1 A12 (64 columns each), sixteen rows (columns) per wavefront, as a
+// block substitution over the four 16 x 16 diagonal blocks of U11 (L11):
+//   X_b = (A_b - sum_{b'<b} X_b' U_b'b) U_bb^-1,   Y_b = L_bb^-1 (A_b - sum_{b'<b} L_bb' Y_b'),
+// on the matrix cores; wavefront b first inverts diagonal block b (sixteen-step
+// substitution, lane = column).  The row case runs transposed (X^T = U^-T ...)
+// so that in both cases each product's accumulator is the next one's B operand.
 template <typename T>
 __global__ __launch_bounds__(256) void dlu_panel_kernel(DenseArgs a, int p, int nrb) {
-    constexpr int RW = 16;                            // rows (columns) per wavefront
+    typedef typename std::conditional<sizeof(T) == 8, d4, f4>::type acc_t;
     __shared__ T blk[NB][NB + 1];
     __shared__ T invd[NB];
+    __shared__ T winv[4][16][17];                     // [b][row][col] of U_bb^-1 or L_bb^-1
     const int inst = blockIdx.y;
     if (sweep_failed(a, inst)) return;
     T *S = inst_S<T>(a, inst);
@@ -251,16 +282,20 @@ __global__ __launch_bounds__(256) void dlu_panel_kernel(DenseArgs a, int p, int 
     const int nb = min(NB, D - p);
     const int tid = threadIdx.x, lane = tid & (WAVE - 1);
     const int wv = __builtin_amdgcn_readfirstlane(tid / WAVE);
-    // loads of this wavefront's rows / columns, issued before the wait
+    const int i16 = lane & 15, g = lane >> 4;
+    // loads of this wavefront's rows / columns (accumulator layout), issued before the wait
     const bool rows = (int)blockIdx.x <= nrb;
-    const int first = p + NB + (((int)blockIdx.x - 1 - (rows ? 0 : nrb)) * 4 + wv) * RW;
-    T x[RW];
+    const int first = p + NB + (((int)blockIdx.x - 1 - (rows ? 0 : nrb)) * 4 + wv) * 16;
+    const bool in = first + i16 < D;
+    acc_t t[4];
     if (blockIdx.x != 0) {
 #pragma unroll
-        for (int q = 0; q < RW; q++) {
-            const bool in = first + q < D;
-            x[q] = !in ? T(0) : rows ? S[(size_t)(p + lane) * D + first + q] : S[(size_t)(first + q) * D + p + lane];
-        }
+        for (int b = 0; b < 4; b++)
+#pragma unroll
+            for (int q = 0; q < 4; q++) {
+                const int k = p + 16 * b + kidx<T>(q, g);
+                t[b][q] = !in ? T(0) : rows ? S[(size_t)k * D + first + i16] : S[(size_t)(first + i16) * D + k];
+            }
     }
     if (wv == 0) diag_factor_wave<T>(S, D, p, nb, blk, invd);
     __syncthreads();
@@ -277,31 +312,66 @@ __global__ __launch_bounds__(256) void dlu_panel_kernel(DenseArgs a, int p, int 
         }
         return;
     }
-    if (rows) {
-        // rows of L21: x U11 = a, right-looking over kk
-        for (int kk = 0; kk < NB; kk++) {
-            const T inv = invd[kk];
-            const T ukm = blk[lane][kk];                  // U(kk, lane)
-            const T w = lane > kk ? ukm : (lane == kk ? T(-1) : T(0));
-            const T keep = lane == kk ? T(0) : T(1);
+    // (a full panel: nb = NB here) inverse of diagonal block b = wv, column i16
+    {
+        const int o = 16 * wv;
+        T x[16];
+        if (rows) {                                   // U_bb x = e_j, upper, from the bottom
 #pragma unroll
-            for (int q = 0; q < RW; q++) x[q] = fma(-(readlane(x[q], kk) * inv), w, x[q] * keep);
+            for (int i = 15; i >= 0; i--) {
+                T acc = i == i16 ? T(1) : T(0);
+#pragma unroll
+                for (int k = i + 1; k < 16; k++) acc = fma(-blk[o + k][o + i], x[k], acc);
+                x[i] = acc * invd[o + i];
+            }
+        } else {                                      // L_bb x = e_j, unit lower, from the top
+#pragma unroll
+            for (int i = 0; i < 16; i++) {
+                T acc = i == i16 ? T(1) : T(0);
+#pragma unroll
+                for (int k = 0; k < i; k++) acc = fma(-blk[o + k][o + i], x[k], acc);
+                x[i] = acc;
+            }
         }
+        if (lane < 16) {
 #pragma unroll
-        for (int q = 0; q < RW; q++)
-            if (first + q < D) S[(size_t)(p + lane) * D + first + q] = x[q];
-        return;
+            for (int i = 0; i < 16; i++) winv[wv][i][i16] = x[i];
+        }
     }
-    // columns of U12: L11 v = a, unit diagonal
-    for (int kk = 0; kk < NB; kk++) {
-        const T lmk_ = blk[kk][lane];                     // L(lane, kk)
-        const T lmk = lane > kk ? lmk_ : T(0);
+    __syncthreads();
+    if (first >= D) return;
+    acc_t x[4];
 #pragma unroll
-        for (int q = 0; q < RW; q++) x[q] = fma(-lmk, readlane(x[q], kk), x[q]);
+    for (int b = 0; b < 4; b++) {
+#pragma unroll
+        for (int bp = 0; bp < b; bp++)
+#pragma unroll
+            for (int s = 0; s < 4; s++) {
+                const int k = 16 * bp + kidx<T>(s, g);
+                // row case: (U_b'b)^T (i16, k) = U(k, 16b + i16); column case: L_bb'(i16, k) = L(16b + i16, k)
+                const T av = rows ? -blk[16 * b + i16][k] : -blk[k][16 * b + i16];
+                t[b] = mfma16<T>(av, x[bp][s], t[b]);
+            }
+        acc_t z = {};
+#pragma unroll
+        for (int s = 0; s < 4; s++) {
+            const int k = kidx<T>(s, g);
+            // row case: (U_bb^-1)^T (i16, k); column case: L_bb^-1 (i16, k)
+            const T av = rows ? winv[b][k][i16] : winv[b][i16][k];
+            z = mfma16<T>(av, t[b][s], z);
+        }
+        x[b] = z;
     }
+    if (in) {
 #pragma unroll
-    for (int q = 0; q < RW; q++)
-        if (first + q < D) S[(size_t)(first + q) * D + p + lane] = x[q];
+        for (int b = 0; b < 4; b++)
+#pragma unroll
+            for (int q = 0; q < 4; q++) {
+                const int k = p + 16 * b + kidx<T>(q, g);
+                if (rows) S[(size_t)k * D + first + i16] = x[b][q];
+                else S[(size_t)(first + i16) * D + k] = x[b][q];
+            }
+    }
 }
 
 // C -= L(:, K) U(K, :) over up to two output rectangles of S, K = columns
