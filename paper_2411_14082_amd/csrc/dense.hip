@@ -8,7 +8,7 @@
 // factored without pivoting by a blocked right-looking LU, panels of NB = 64 in
 // groups of W (64, 128 or 256) columns:
 //   dlu_panel  every workgroup factors the NB x NB diagonal block in registers
-//              (a wavefront, lane = row), then computes its share of
+//              (four wavefronts, lane = row), then computes its share of
 //              L21 = A21 U11^-1 or U12 = L11^-1 A12 (sixteen rows or columns
 //              per wavefront) by block substitution on the matrix cores;
 //   dlu_gemm   C -= L21 U12 on the matrix cores: 128 x 128 output tiles, K in
@@ -223,29 +223,50 @@ __device__ __forceinline__ double recip(double u) {
 __device__ __forceinline__ float recip(float u) { return 1.0f / u; }
 
 // Factors the nb x nb diagonal block at (p, p) of S (padded to NB x NB with the
-// identity) without pivoting, in one wavefront: lane r holds row r, v[c] its
-// entry in column c, fully unrolled, so step kk reads row kk (U(kk, c)) from
-// lane kk by readlane and needs no barrier.  L = x / u_kk is formed as
-// x * (1 / u_kk).  The factors go to blk[col][row] (unit L below the diagonal, U
-// on and above it) and invd[k] = 1 / u_kk.
-template <typename T>
-__device__ void diag_factor_wave(const T *S, int D, int p, int nb, T (*blk)[NB + 1], T *invd) {
+// identity) without pivoting, with the workgroup's four wavefronts: lane r holds
+// row r, wavefront W the columns c = 4j + W in v[j].  Step kk: the owner of
+// column kk (W = kk % 4) forms L(:, kk) = x * (1 / u_kk) and passes it through
+// LDS (two buffers, one barrier per step); every wavefront then updates its
+// columns c > kk, reading U(kk, c) from lane kk by readlane.  The factors go to
+// blk[col][row] (unit L below the diagonal, U on and above it) and
+// invd[k] = 1 / u_kk.
+template <typename T, int W>
+__device__ void diag_factor_part(const T *S, int D, int p, int nb, T (*blk)[NB + 1], T *invd, T (*lbuf)[WAVE]) {
     const int lane = threadIdx.x & (WAVE - 1);
-    T v[NB];
+    T v[NB / 4];
 #pragma unroll
-    for (int c = 0; c < NB; c++)
-        v[c] = (lane < nb && c < nb) ? S[(size_t)(p + c) * D + p + lane] : (lane == c ? T(1) : T(0));
-#pragma unroll
-    for (int kk = 0; kk < NB; kk++) {
-        const T inv = recip(readlane(v[kk], kk));
-        if (lane == 0) invd[kk] = inv;
-        const T l = lane > kk ? v[kk] * inv : T(0);
-        v[kk] = lane > kk ? l : v[kk];
-#pragma unroll
-        for (int c = kk + 1; c < NB; c++) v[c] = fma(-l, readlane(v[c], kk), v[c]);
+    for (int j = 0; j < NB / 4; j++) {
+        const int c = 4 * j + W;
+        v[j] = (lane < nb && c < nb) ? S[(size_t)(p + c) * D + p + lane] : (lane == c ? T(1) : T(0));
     }
 #pragma unroll
-    for (int c = 0; c < NB; c++) blk[c][lane] = v[c];
+    for (int kk = 0; kk < NB; kk++) {
+        T l;
+        if ((kk & 3) == W) {
+            const int jk = kk >> 2;
+            const T inv = recip(readlane(v[jk], kk));
+            if (lane == 0) invd[kk] = inv;
+            l = lane > kk ? v[jk] * inv : T(0);
+            v[jk] = lane > kk ? l : v[jk];
+            lbuf[kk & 1][lane] = l;
+        }
+        __syncthreads();
+        if ((kk & 3) != W) l = lbuf[kk & 1][lane];
+#pragma unroll
+        for (int j = 0; j < NB / 4; j++)
+            if (4 * j + W > kk) v[j] = fma(-l, readlane(v[j], kk), v[j]);
+    }
+#pragma unroll
+    for (int j = 0; j < NB / 4; j++) blk[4 * j + W][lane] = v[j];
+}
+template <typename T>
+__device__ void diag_factor(const T *S, int D, int p, int nb, T (*blk)[NB + 1], T *invd, T (*lbuf)[WAVE], int wv) {
+    switch (wv) {
+    case 0: diag_factor_part<T, 0>(S, D, p, nb, blk, invd, lbuf); break;
+    case 1: diag_factor_part<T, 1>(S, D, p, nb, blk, invd, lbuf); break;
+    case 2: diag_factor_part<T, 2>(S, D, p, nb, blk, invd, lbuf); break;
+    default: diag_factor_part<T, 3>(S, D, p, nb, blk, invd, lbuf); break;
+    }
 }
 
 // k of step s for lane group g (= lane / 16) in a 16 x 16 x 4 MFMA chain: the
@@ -260,8 +281,8 @@ __device__ __forceinline__ auto mfma16(T a, T b, typename std::conditional<sizeo
     else return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
 }
 
-// One panel [p, p+nb).  In every workgroup wavefront 0 factors the diagonal
-// block (workgroup 0 writes it back) while the others wait.  The other
+// One panel [p, p+nb).  Every workgroup factors the diagonal block (workgroup 0
+// writes it back).  The other
 // workgroups compute L21 = A21 U11^-1 (the first nrb, 64 rows each) or
 // U12 = L11^-1 A12 (64 columns each), sixteen rows (columns) per wavefront, as a
 // block substitution over the four 16 x 16 diagonal blocks of U11 (L11):
@@ -275,6 +296,7 @@ __global__ __launch_bounds__(256) void dlu_panel_kernel(DenseArgs a, int p, int 
     __shared__ T blk[NB][NB + 1];
     __shared__ T invd[NB];
     __shared__ T winv[4][16][17];                     // [b][row][col] of U_bb^-1 or L_bb^-1
+    __shared__ T lbuf[2][WAVE];
     const int inst = blockIdx.y;
     if (sweep_failed(a, inst)) return;
     T *S = inst_S<T>(a, inst);
@@ -288,7 +310,7 @@ __global__ __launch_bounds__(256) void dlu_panel_kernel(DenseArgs a, int p, int 
     const int first = p + NB + (((int)blockIdx.x - 1 - (rows ? 0 : nrb)) * 4 + wv) * 16;
     const bool in = first + i16 < D;
     acc_t t[4];
-    if (blockIdx.x != 0) {
+    auto load = [&]() {
 #pragma unroll
         for (int b = 0; b < 4; b++)
 #pragma unroll
@@ -296,8 +318,9 @@ __global__ __launch_bounds__(256) void dlu_panel_kernel(DenseArgs a, int p, int 
                 const int k = p + 16 * b + kidx<T>(q, g);
                 t[b][q] = !in ? T(0) : rows ? S[(size_t)k * D + first + i16] : S[(size_t)(first + i16) * D + k];
             }
-    }
-    if (wv == 0) diag_factor_wave<T>(S, D, p, nb, blk, invd);
+    };
+    if (blockIdx.x != 0) load();
+    diag_factor<T>(S, D, p, nb, blk, invd, lbuf, wv);
     __syncthreads();
     if (blockIdx.x == 0) {
         // Other workgroups of this launch still read the unfactored block from S, so the
@@ -379,6 +402,8 @@ __global__ __launch_bounds__(256) void dlu_panel_kernel(DenseArgs a, int p, int 
 // panels, or the rest of the group after one of its panels.  A 128 x 128 output
 // tile per workgroup, each wavefront 64 x 64 as 4 x 4 MFMA 16 x 16 tiles; K in
 // chunks of 16 staged through LDS (double-buffered, prefetched in registers).
+// TM = 64 (32 x 32 per wavefront) for the narrow in-group updates: four times as
+// many workgroups, so that several share a CU and overlap their loads and MFMAs.
 // The MFMA computes the transposed tile (U12^T L21^T), so that a lane's results
 // run down a column of S and the read-modify-write of C is coalesced.
 // MFMA 16x16x4 operands: lane l holds A(l%16, l/16) and B(l/16, l%16).
@@ -386,9 +411,10 @@ struct GemmRect {
     int r0, r1, c0, c1;        // rows [r0, r1) x columns [c0, c1) of S
     int ntx, nt;               // tiles down a tile column, tiles in all
 };
-template <typename T, int KW>
+template <typename T, int KW, int TM = 128>
 __global__ __launch_bounds__(256) void dlu_gemm_kernel(DenseArgs a, int kp, GemmRect g0, GemmRect g1, int dgp) {
-    constexpr int TM = 128, KC = 16, LD = TM + 4;
+    constexpr int KC = 16, LD = TM + 4;
+    constexpr int WT = TM / 2, NT = WT / 16, FE = KC * TM / 256;   // wave tile, MFMA tiles, staged per thread
     __shared__ T As[2][KC][LD];                       // [buf][k][row]
     __shared__ T Bs[2][KC][LD];                       // [buf][k][col]
     const int inst = blockIdx.z;
@@ -414,10 +440,10 @@ __global__ __launch_bounds__(256) void dlu_gemm_kernel(DenseArgs a, int kp, Gemm
             S[(size_t)(dgp + e / NB) * D + dgp + e % NB] = tv[u];
         }
     }
-    T ra[8], rb[8];
+    T ra[FE], rb[FE];
     auto fetch = [&](int kc) {
 #pragma unroll
-        for (int u = 0; u < 8; u++) {
+        for (int u = 0; u < FE; u++) {
             const int e = tid + 256 * u;
             const int ka = e / TM, rr = e % TM;
             ra[u] = r0 + rr < R1 ? S[(size_t)(kp + kc + ka) * D + r0 + rr] : T(0);
@@ -427,7 +453,7 @@ __global__ __launch_bounds__(256) void dlu_gemm_kernel(DenseArgs a, int kp, Gemm
     };
     auto stash = [&](int buf) {                      // A is stored negated: acc = C + (-A) B
 #pragma unroll
-        for (int u = 0; u < 8; u++) {
+        for (int u = 0; u < FE; u++) {
             const int e = tid + 256 * u;
             As[buf][e / TM][e % TM] = -ra[u];
             Bs[buf][e % KC][e / KC] = rb[u];
@@ -437,15 +463,15 @@ __global__ __launch_bounds__(256) void dlu_gemm_kernel(DenseArgs a, int kp, Gemm
     const int qr = wv >> 1, qc = wv & 1;
     const int li = lane & 15, lk = lane >> 4;
     // C(row, col) of accumulator element q (transposed tile, see the epilogue)
-    auto crow = [&](int ti) { return r0 + 64 * qr + 16 * ti + li; };
-    auto ccol = [&](int tj, int q) { return c0 + 64 * qc + 16 * tj + (sizeof(T) == 8 ? 4 * q + lk : 4 * lk + q); };
+    auto crow = [&](int ti) { return r0 + WT * qr + 16 * ti + li; };
+    auto ccol = [&](int tj, int q) { return c0 + WT * qc + 16 * tj + (sizeof(T) == 8 ? 4 * q + lk : 4 * lk + q); };
     typedef typename std::conditional<sizeof(T) == 8, d4, f4>::type acc_t;
-    acc_t acc[4][4];
+    acc_t acc[NT][NT];
     // the accumulators start from C, loaded before any store of this workgroup
 #pragma unroll
-    for (int ti = 0; ti < 4; ti++)
+    for (int ti = 0; ti < NT; ti++)
 #pragma unroll
-        for (int tj = 0; tj < 4; tj++)
+        for (int tj = 0; tj < NT; tj++)
 #pragma unroll
             for (int q = 0; q < 4; q++) {
                 const int row = crow(ti), col = ccol(tj, q);
@@ -461,16 +487,16 @@ __global__ __launch_bounds__(256) void dlu_gemm_kernel(DenseArgs a, int kp, Gemm
         if (ch + 1 < nch) fetch((ch + 1) * KC);
 #pragma unroll
         for (int s = 0; s < KC / 4; s++) {
-            T av[4], bv[4];
+            T av[NT], bv[NT];
 #pragma unroll
-            for (int t = 0; t < 4; t++) {
-                av[t] = As[buf][4 * s + lk][64 * qr + 16 * t + li];
-                bv[t] = Bs[buf][4 * s + lk][64 * qc + 16 * t + li];
+            for (int t = 0; t < NT; t++) {
+                av[t] = As[buf][4 * s + lk][WT * qr + 16 * t + li];
+                bv[t] = Bs[buf][4 * s + lk][WT * qc + 16 * t + li];
             }
 #pragma unroll
-            for (int ti = 0; ti < 4; ti++)
+            for (int ti = 0; ti < NT; ti++)
 #pragma unroll
-                for (int tj = 0; tj < 4; tj++) {
+                for (int tj = 0; tj < NT; tj++) {
                     if constexpr (sizeof(T) == 8)
                         acc[ti][tj] = __builtin_amdgcn_mfma_f64_16x16x4f64(bv[tj], av[ti], acc[ti][tj], 0, 0, 0);
                     else
@@ -483,9 +509,9 @@ __global__ __launch_bounds__(256) void dlu_gemm_kernel(DenseArgs a, int kp, Gemm
     // transposed tile: FP64 element q of lane l is C(row l%16, col 4q + l/16),
     // FP32 element q is C(row l%16, col 4(l/16) + q)
 #pragma unroll
-    for (int ti = 0; ti < 4; ti++)
+    for (int ti = 0; ti < NT; ti++)
 #pragma unroll
-        for (int tj = 0; tj < 4; tj++)
+        for (int tj = 0; tj < NT; tj++)
 #pragma unroll
             for (int q = 0; q < 4; q++) {
                 const int row = crow(ti), col = ccol(tj, q);
@@ -917,11 +943,11 @@ int launch_dense_refactor(const DenseArgs &a, bool gather, const DenseStreams *l
     // groups of W columns: each panel of 64 updates the rest of its group (the column strip
     // below and right of it, the row strip right of the group); the whole trailing block
     // is updated once per group with K = W
-    auto rect = [](int r0, int r1, int c0, int c1) {
+    auto rect = [](int r0, int r1, int c0, int c1, int tm = 128) {
         GemmRect g;
         g.r0 = r0; g.r1 = r1; g.c0 = c0; g.c1 = c1;
-        g.ntx = r1 > r0 && c1 > c0 ? (r1 - r0 + 127) / 128 : 0;
-        g.nt = g.ntx ? g.ntx * ((c1 - c0 + 127) / 128) : 0;
+        g.ntx = r1 > r0 && c1 > c0 ? (r1 - r0 + tm - 1) / tm : 0;
+        g.nt = g.ntx ? g.ntx * ((c1 - c0 + tm - 1) / tm) : 0;
         return g;
     };
     auto gemm = [&](hipStream_t s, int kp, int kw, const GemmRect &g0, const GemmRect &g1, int dgp) {
@@ -947,7 +973,12 @@ int launch_dense_refactor(const DenseArgs &a, bool gather, const DenseStreams *l
             if (a.fp32) hipLaunchKernelGGL((dlu_panel_kernel<float>), gp, dim3(256), 0, s, a, q, nrb);
             else hipLaunchKernelGGL((dlu_panel_kernel<double>), gp, dim3(256), 0, s, a, q, nrb);
             const int q1 = q + NB;
-            if (q1 < pe) gemm(s, q, NB, rect(q1, D, q1, pe), rect(q1, pe, pe, D), q);
+            if (q1 < pe) {                             // the in-group update: 64 x 64 tiles
+                const GemmRect g0 = rect(q1, D, q1, pe, 64), g1 = rect(q1, pe, pe, D, 64);
+                const dim3 gg((unsigned)(g0.nt + g1.nt), 1, (unsigned)a.batch);
+                if (a.fp32) hipLaunchKernelGGL((dlu_gemm_kernel<float, 64, 64>), gg, dim3(256), 0, s, a, q, g0, g1, q);
+                else hipLaunchKernelGGL((dlu_gemm_kernel<double, 64, 64>), gg, dim3(256), 0, s, a, q, g0, g1, q);
+            }
         }
     };
     const int W = a.W;
