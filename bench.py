@@ -299,6 +299,8 @@ def main():
                     help="dense block: 1 panels of the next group on a second stream, 0 one stream")
     ap.add_argument("--solve-chain", type=int, default=None,
                     help="solve levels of at most this many rows chained in one launch (-1 = never)")
+    ap.add_argument("--no-slot-map", action="store_true",
+                    help="sweep searches the target rows instead of loading the slot map")
     ap.add_argument("--requests", type=int, default=16, help="serving_mix: number of requests")
     ap.add_argument("--slots", type=int, default=4, help="serving_mix: requests on the device at once")
     ap.add_argument("--autotune", action="store_true",
@@ -339,7 +341,8 @@ def main():
 
     tail_opts = dict(dense_tail=args.dense_tail, dense_tail_density=args.dense_density, autotune=args.autotune,
                      solve_chain_width=args.solve_chain, dense_panel_width=args.dense_panel_width,
-                     dense_lookahead=args.dense_lookahead, ordering=args.ordering)
+                     dense_lookahead=args.dense_lookahead, ordering=args.ordering,
+                     sweep_slot_map=-1 if args.no_slot_map else None)
     res64 = run_leg(ck, torch, c, vals_dev, b_dev, ck.CKTLU_FP64, args.steps, args.warmup, tail_opts)
     log("fp64: %.3f steps/s, refactor %.2f ms, solve %.2f ms (setup %.1fs), dense tail %d" %
         (args.steps / res64["wall"], res64["ref_ms"].mean(), res64["sol_ms"].mean(), res64["setup_s"],
@@ -404,6 +407,7 @@ def main():
         "config": {"workload": wl["desc"], "n": c.n, "nnz": c.nnz, "nnz_lu": st["nnz_l"] + st["nnz_u"],
                    "flops_per_refactor": st["flops"], "levels": st["levels"], "dense_tail": st["dense_tail"],
                    "nrhs": nrhs, "ordering": ["amd", "natural", "amf", "auto", "nd"][int(st.get("ordering_used", 0))],
+                   "slot_map_entries": int(st.get("slot_map_entries", 0)),
                    "value_perturbation": "+-5%% per %s" % args.perturb},
         "p50_ms": float(np.percentile(res64["step_ms"], 50)),
         "p99_ms": float(np.percentile(res64["step_ms"], 99)),

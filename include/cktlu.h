@@ -88,6 +88,10 @@ typedef struct {
     int dense_device_repivot; /* pivot-check fallback: 0 (default) re-factors the dense block on the device
                               with the threshold pivot rule when every column to restart lies in it (the
                               host then computes only the new pattern); -1 = always the host fallback */
+    int sweep_slot_map;    /* 0 (default): the analysis records, for every entry of every update task's
+                              sources, its slot in the target column (4 bytes per multiply-add of the sweep,
+                              kept on the device when it takes at most a quarter of the free HBM), so the
+                              sweep loads the slot instead of searching the target's rows; -1 = never */
 } cktlu_options;
 
 typedef struct {
@@ -127,6 +131,8 @@ typedef struct {
     int64_t ordering_used;            /* CKTLU_ORDER_* that analyze applied */
     int64_t fill_amd, fill_amf, fill_nd;  /* CKTLU_ORDER_AUTO: entries of the symbolic Cholesky factor of
                                          B + B' under each method (-1 when not run) */
+    int64_t slot_map_entries;         /* entries of the sweep's slot map on the device (0: none, the sweep
+                                         searches the target rows) */
 } cktlu_stats;
 
 /* Device time of the phases, accumulated over the calls made with options.timing = 1

@@ -57,7 +57,7 @@ class cktlu_options(ctypes.Structure):
                 ("dense_tail_size", ctypes.c_int), ("dense_tail_density", ctypes.c_double),
                 ("timing", ctypes.c_int), ("solve_chain_width", ctypes.c_int),
                 ("dense_panel_width", ctypes.c_int), ("dense_lookahead", ctypes.c_int),
-                ("dense_device_repivot", ctypes.c_int)]
+                ("dense_device_repivot", ctypes.c_int), ("sweep_slot_map", ctypes.c_int)]
 
 
 class cktlu_refactor_info(ctypes.Structure):
@@ -81,7 +81,8 @@ class cktlu_stats(ctypes.Structure):
                 ("flops_dense", ctypes.c_double), ("macs_schur", ctypes.c_double), ("sweep_launches", ctypes.c_int64),
                 ("dense_launches", ctypes.c_int64), ("solve_launches", ctypes.c_int64),
                 ("n_device_repivot", ctypes.c_int64), ("ordering_used", ctypes.c_int64),
-                ("fill_amd", ctypes.c_int64), ("fill_amf", ctypes.c_int64), ("fill_nd", ctypes.c_int64)]
+                ("fill_amd", ctypes.c_int64), ("fill_amf", ctypes.c_int64), ("fill_nd", ctypes.c_int64),
+                ("slot_map_entries", ctypes.c_int64)]
 
     def as_dict(self):
         return {f: getattr(self, f) for f, _ in self._fields_}
@@ -386,7 +387,7 @@ class SparseLU:
     def __init__(self, n, colptr, rowind, eps=1e-3, precision=CKTLU_FP64, ordering=CKTLU_ORDER_AUTO,
                  ir_tol=1e-10, ir_max_iter=10, stream=None, transversal=1, dense_tail=None,
                  dense_tail_density=None, timing=False, solve_chain_width=None, dense_panel_width=None,
-                 dense_lookahead=None, dense_device_repivot=None):
+                 dense_lookahead=None, dense_device_repivot=None, sweep_slot_map=None):
         opt = cktlu_default_options()
         opt.timing = 1 if timing else 0
         if dense_tail is not None:
@@ -401,6 +402,8 @@ class SparseLU:
             opt.dense_lookahead = int(dense_lookahead)
         if dense_device_repivot is not None:
             opt.dense_device_repivot = int(dense_device_repivot)
+        if sweep_slot_map is not None:
+            opt.sweep_slot_map = int(sweep_slot_map)
         opt.pivot_eps = eps
         opt.precision = precision
         opt.ordering = ordering

@@ -165,7 +165,7 @@ int upload(DevBuf &b, const std::vector<V> &v, hipStream_t st) {
 
 DevBuf *all_buffers(Device &d, int i) {
     DevBuf *all[] = {&d.seq, &d.Dp, &d.Dlen, &d.Fi, &d.nU, &d.Ap, &d.colperm, &d.amap, &d.colrec, &d.task8,
-                     &d.item4, &d.tail_nb, &d.l21, &d.lrec, &d.urec,
+                     &d.item4, &d.smap, &d.tmoff, &d.tail_nb, &d.l21, &d.lrec, &d.urec,
                      &d.Lrjs, &d.Urjs, &d.lsptr, &d.usptr, &d.rowperm,
                      &d.colperm_sol, &d.Acp, &d.Acj, &d.Acsrc, &d.Fx64, &d.Fx32, &d.Aval, &d.done,
                      &d.ctrl, &d.vec, &d.S, &d.Dg, &d.Dinv};
@@ -263,6 +263,19 @@ int upload_all(cktlu_ctx *c) {
     if ((rc = upload(d.tail_nb, s.tail_nb, st))) return rc;
     if ((rc = upload(d.l21, s.l21, st))) return rc;
     if ((rc = upload(d.item4, s.item4, st))) return rc;
+    {
+        // the sweep's slot map, when it takes at most a quarter of the free HBM
+        dfree(d.smap);
+        dfree(d.tmoff);
+        size_t fr = 0, tot = 0;
+        if (hipMemGetInfo(&fr, &tot) != hipSuccess) fr = 0;
+        const double mb = (double)s.smap.size() * sizeof(int);
+        if (!s.smap.empty() && mb <= 0.25 * (double)fr) {
+            if ((rc = upload(d.smap, s.smap, st))) return rc;
+            if ((rc = upload(d.tmoff, s.tmoff, st))) return rc;
+        }
+        c->stats.slot_map_entries = d.smap.p ? (int64_t)s.smap.size() : 0;
+    }
     if ((rc = upload(d.lrec, s.lrec, st))) return rc;
     if ((rc = upload(d.urec, s.urec, st))) return rc;
     if ((rc = upload(d.Lrjs, s.Lrjs, st))) return rc;
@@ -466,6 +479,8 @@ int run_refactor(cktlu_ctx *c, int batch, const double *values_dev, bool fp32, b
     a.colrec = (const int *)d.colrec.p;
     a.task8 = (const int *)d.task8.p;
     a.item4 = (const int *)d.item4.p;
+    a.smap = d.smap.p ? (const int *)d.smap.p : nullptr;
+    a.tmoff = d.smap.p ? (const int *)d.tmoff.p : nullptr;
     a.T = s.tail0;
     a.D = c->an.n - s.tail0;
     a.S = d.S.p;
@@ -835,6 +850,7 @@ int cktlu_create(cktlu_ctx **out, const cktlu_options *opt) {
         c->opt.solve_chain_width < -1 || (c->opt.dense_lookahead != 0 && c->opt.dense_lookahead != 1) ||
         c->opt.ordering < CKTLU_ORDER_AMD || c->opt.ordering > CKTLU_ORDER_ND ||
         (c->opt.dense_device_repivot != 0 && c->opt.dense_device_repivot != -1) ||
+        (c->opt.sweep_slot_map != 0 && c->opt.sweep_slot_map != -1) ||
         (c->opt.dense_panel_width != 0 && c->opt.dense_panel_width != 64 && c->opt.dense_panel_width != 128 &&
          c->opt.dense_panel_width != 256)) {
         delete c;

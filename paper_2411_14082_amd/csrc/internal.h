@@ -96,6 +96,9 @@ struct Schedule {
     // target column (where the multiplier U(j,k) lives)
     std::vector<int> task_ptr, task_tgt, src_ptr, src_col, src_slot;
     std::vector<int> colrec, task8, item4;    // the same schedule packed for the device
+    // slot map: for task t, the slots in its target column of the entries of its items
+    // (first item, then the extra ones, each its L range in order) from smap[tmoff[t]]
+    std::vector<int> smap, tmoff;
     std::vector<int> amap;                    // user nonzero -> slot offset inside its column
     // device layout of the factor storage: column k occupies [Dp[k], Dp[k] + Dlen[k]);
     // every column starts on a kColAlign-entry boundary
@@ -133,7 +136,7 @@ struct Device {
     int batch_cap = 0;                 // instances the value buffers hold
     // pattern / schedule
     DevBuf seq, Dp, Dlen, Fi, nU, Ap, colperm, amap;
-    DevBuf colrec, task8, item4, tail_nb, l21;
+    DevBuf colrec, task8, item4, smap, tmoff, tail_nb, l21;
     DevBuf lrec, urec, Lrjs, Urjs, lsptr, usptr, rowperm, colperm_sol;
     DevBuf Acp, Acj, Acsrc;
     // values and status words
@@ -168,6 +171,8 @@ struct RefactorArgs {
     const int *seq, *Dp, *Dlen, *Fi, *nU, *Ap, *colperm, *amap;
     const int *colrec;         // {Dp, nU, Dlen, column} per position of seq
     const int *task8, *item4;  // right-looking update tasks (two int4s each) and their extra items
+    const int *smap, *tmoff;   // slot map (target slot of every source entry) and its offset per task,
+                               // or nullptr: the tasks search the target rows
     const double *Aval;        // batch x nnzA
     int64_t nnzA, nnzF;
     void *Fx;                  // batch x nnzF (double or float)

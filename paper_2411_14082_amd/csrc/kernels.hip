@@ -127,11 +127,13 @@ constexpr int kItemChunk = 4;      // entries of a source column per lane per pa
 // part of column k, the same range for every entry, run in lockstep, in LDS when
 // staged), loads every target value and only then stores: the rows of one source
 // are distinct, so no store of a pass can feed a load of the same pass.
-template <typename T, int U>
+// With the slot map (MAP) the caller's r0 and the entries loaded here are the slots
+// themselves (mp: the map of this item) and there is no search.
+template <typename T, int U, bool MAP>
 __device__ __forceinline__ void apply_item_u(const RefactorArgs &a, const T *Fx, T *xk, T *Sk, const int *rowsk,
                                              const int *lrows, bool staged, int slen, int lb, int le, int lo0,
                                              T iv, T m, int lane, const int (&r0)[kItemChunk],
-                                             const T (&l0)[kItemChunk]) {
+                                             const T (&l0)[kItemChunk], const int *mp) {
     for (int q0 = lb; q0 < le; q0 += U * WAVE) {
         int r[U];
         T l[U];
@@ -142,12 +144,16 @@ __device__ __forceinline__ void apply_item_u(const RefactorArgs &a, const T *Fx,
 #pragma unroll
             for (int u = 0; u < U; u++) {
                 const int q = q0 + u * WAVE + lane;
-                r[u] = q < le ? a.Fi[q] : -1;
+                r[u] = q < le ? (MAP ? mp[q - lb] : a.Fi[q]) : -1;
                 l[u] = q < le ? Fx[q] : T(0);
             }
         }
         // target slot of each entry: >= 0 in xk, < -1 as -(2 + offset) in Sk, -1 none
         int pos[U];
+        if constexpr (MAP) {
+#pragma unroll
+            for (int u = 0; u < U; u++) pos[u] = r[u];
+        } else {
         int base[U];
 #pragma unroll
         for (int u = 0; u < U; u++) base[u] = lo0;
@@ -181,6 +187,7 @@ __device__ __forceinline__ void apply_item_u(const RefactorArgs &a, const T *Fx,
             else if (Sk && r[u] >= a.T) pos[u] = -(2 + (r[u] - a.T));
             else pos[u] = base[u] < slen ? base[u] : -1;  // always found: struct(L(:,j)) is inside struct(col k)
         }
+        }
         T tv[U];
 #pragma unroll
         for (int u = 0; u < U; u++) tv[u] = pos[u] >= 0 ? xk[pos[u]] : (pos[u] < -1 ? Sk[-(pos[u] + 2)] : T(0));
@@ -195,19 +202,20 @@ __device__ __forceinline__ void apply_item_u(const RefactorArgs &a, const T *Fx,
 
 // Sources of at most one entry per lane take the single-entry path (one search
 // per lane); longer ones kItemChunk entries per lane per pass.
-template <typename T>
+template <typename T, bool MAP>
 __device__ __forceinline__ void apply_item(const RefactorArgs &a, const T *Fx, T *xk, T *Sk, const int *rowsk,
                                            const int *lrows, bool staged, int slen, int lb, int le, int lo0,
                                            T iv, T m, int lane, const int (&r0)[kItemChunk],
-                                           const T (&l0)[kItemChunk]) {
+                                           const T (&l0)[kItemChunk], const int *mp) {
     if (le - lb <= WAVE)
-        apply_item_u<T, 1>(a, Fx, xk, Sk, rowsk, lrows, staged, slen, lb, le, lo0, iv, m, lane, r0, l0);
+        apply_item_u<T, 1, MAP>(a, Fx, xk, Sk, rowsk, lrows, staged, slen, lb, le, lo0, iv, m, lane, r0, l0, mp);
     else
-        apply_item_u<T, kItemChunk>(a, Fx, xk, Sk, rowsk, lrows, staged, slen, lb, le, lo0, iv, m, lane, r0, l0);
+        apply_item_u<T, kItemChunk, MAP>(a, Fx, xk, Sk, rowsk, lrows, staged, slen, lb, le, lo0, iv, m, lane, r0,
+                                         l0, mp);
 }
 
 // one wavefront per (task, instance); tasks: [checks | normalisations | updates]
-template <typename T, bool CHECK>
+template <typename T, bool CHECK, bool MAP>
 __global__ __launch_bounds__(WG) void refactor_level_kernel(RefactorArgs a, int cbeg, int cend, int pbeg,
                                                              int pend, int tbeg, int tend) {
     const int lane = threadIdx.x & (WAVE - 1), wv = threadIdx.x / WAVE;
@@ -289,19 +297,20 @@ __global__ __launch_bounds__(WG) void refactor_level_kernel(RefactorArgs a, int 
     T *Sk = k >= a.T ? reinterpret_cast<T *>(a.S) + (size_t)inst * a.D * a.D + (size_t)(k - a.T) * a.D : nullptr;
     const T piv0 = Fx[it0.x];                             // the pivot of j (not yet divided into L(:,j))
     const T mult0 = xk[it0.w];                            // U(j,k): final, no source of this level updates it
+    const int *mp = MAP ? a.smap + a.tmoff[t] : nullptr;   // slots of this task's entries, item by item
     int r0[kItemChunk];
     T l0[kItemChunk];
 #pragma unroll
     for (int u = 0; u < kItemChunk; u++) {
         const int q = it0.y + u * WAVE + lane;
-        r0[u] = q < it0.z ? a.Fi[q] : -1;
+        r0[u] = q < it0.z ? (MAP ? mp[q - it0.y] : a.Fi[q]) : -1;
         l0[u] = q < it0.z ? Fx[q] : T(0);
     }
     int4 itx = make_int4(0, 0, 0, 0);
     if (xbeg + lane < xend) itx = reinterpret_cast<const int4 *>(a.item4)[xbeg + lane];
-    __shared__ int srows[WAVES][kStageRows];
-    int *lrows = srows[wv];
-    const bool staged = slen <= kStageRows;
+    __shared__ int srows[MAP ? 1 : WAVES][MAP ? 1 : kStageRows];
+    int *lrows = srows[MAP ? 0 : wv];
+    const bool staged = !MAP && slen <= kStageRows;
     if (staged) {
         for (int i0 = 0; i0 < slen; i0 += 4 * WAVE) {
             int rr[4];
@@ -314,9 +323,10 @@ __global__ __launch_bounds__(WG) void refactor_level_kernel(RefactorArgs a, int 
     }
     if (stop) return;                                     // an earlier level failed its check
     wave_sync();                                          // staged rows visible to the whole wavefront
-    apply_item<T>(a, Fx, xk, Sk, rowsk, lrows, staged, slen, it0.y, it0.z, it0.w + 1, T(1) / piv0, mult0, lane,
-                  r0, l0);
+    apply_item<T, MAP>(a, Fx, xk, Sk, rowsk, lrows, staged, slen, it0.y, it0.z, it0.w + 1, T(1) / piv0, mult0,
+                       lane, r0, l0, mp);
     if (xend == xbeg) return;
+    if (MAP) mp += it0.z - it0.y;
     // further sources of this task (lane u holds the record of the u-th)
     T invx = T(0), multx = T(0);
     const int nx = min(WAVE, xend - xbeg);
@@ -331,10 +341,11 @@ __global__ __launch_bounds__(WG) void refactor_level_kernel(RefactorArgs a, int 
 #pragma unroll
         for (int v = 0; v < kItemChunk; v++) {
             const int q = lb + v * WAVE + lane;
-            r0[v] = q < le ? a.Fi[q] : -1;
+            r0[v] = q < le ? (MAP ? mp[q - lb] : a.Fi[q]) : -1;
             l0[v] = q < le ? Fx[q] : T(0);
         }
-        apply_item<T>(a, Fx, xk, Sk, rowsk, lrows, staged, slen, lb, le, lo0, iv, m, lane, r0, l0);
+        apply_item<T, MAP>(a, Fx, xk, Sk, rowsk, lrows, staged, slen, lb, le, lo0, iv, m, lane, r0, l0, mp);
+        if (MAP) mp += le - lb;
         wave_sync();
     }
     // more than WAVE sources in one task: the rest one at a time
@@ -344,10 +355,12 @@ __global__ __launch_bounds__(WG) void refactor_level_kernel(RefactorArgs a, int 
 #pragma unroll
         for (int v = 0; v < kItemChunk; v++) {
             const int q = it.y + v * WAVE + lane;
-            r0[v] = q < it.z ? a.Fi[q] : -1;
+            r0[v] = q < it.z ? (MAP ? mp[q - it.y] : a.Fi[q]) : -1;
             l0[v] = q < it.z ? Fx[q] : T(0);
         }
-        apply_item<T>(a, Fx, xk, Sk, rowsk, lrows, staged, slen, it.y, it.z, it.w + 1, iv, m, lane, r0, l0);
+        apply_item<T, MAP>(a, Fx, xk, Sk, rowsk, lrows, staged, slen, it.y, it.z, it.w + 1, iv, m, lane, r0, l0,
+                           mp);
+        if (MAP) mp += it.z - it.y;
         wave_sync();
     }
 }
@@ -392,8 +405,15 @@ int launch_refactor_level(const RefactorArgs &a, int cbeg, int cend, int pbeg, i
     const int64_t waves = (int64_t)((cend - cbeg) + (pend - pbeg) + (tend - tbeg)) * a.batch;
     if (waves == 0) return 0;
     const dim3 grid((unsigned)((waves + WAVES - 1) / WAVES));
-#define CKTLU_LEVEL(T, C) \
-    hipLaunchKernelGGL((refactor_level_kernel<T, C>), grid, dim3(WG), 0, st, a, cbeg, cend, pbeg, pend, tbeg, tend)
+#define CKTLU_LEVEL(T, C)                                                                                     \
+    do {                                                                                                      \
+        if (a.smap)                                                                                           \
+            hipLaunchKernelGGL((refactor_level_kernel<T, C, true>), grid, dim3(WG), 0, st, a, cbeg, cend, pbeg, \
+                               pend, tbeg, tend);                                                            \
+        else                                                                                                  \
+            hipLaunchKernelGGL((refactor_level_kernel<T, C, false>), grid, dim3(WG), 0, st, a, cbeg, cend, pbeg,\
+                               pend, tbeg, tend);                                                            \
+    } while (0)
     if (a.fp32) {
         if (a.check) CKTLU_LEVEL(float, true); else CKTLU_LEVEL(float, false);
     } else {

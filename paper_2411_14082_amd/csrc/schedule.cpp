@@ -5,6 +5,7 @@
 // of L and U used by the triangular solves.
 #include <algorithm>
 #include <climits>
+#include <thread>
 #include <numeric>
 
 #include "internal.h"
@@ -222,6 +223,61 @@ void build_schedule(const Analysis &an, const Factor &f, const cktlu_options &op
             }
         }
         s.task8[8 * (size_t)ntasks + 3] = (int)(s.item4.size() / 4);
+        // slot map: the slot in column k of every entry of every item, so that the device
+        // loads it instead of searching column k's rows; items in the order the task
+        // applies them, entries in L order; built in parallel over tasks
+        s.smap.clear();
+        s.tmoff.clear();
+        if (opt.sweep_slot_map == 0 && ntasks > 0) {
+            std::vector<int64_t> off(ntasks + 1, 0);
+            for (int t = 0; t < ntasks; t++) {
+                int64_t len = 0;
+                for (int i = s.src_ptr[t]; i < s.src_ptr[t + 1]; i++) {
+                    int it[4];
+                    item_of(i, s.task_tgt[t], it);
+                    len += it[2] - it[1];
+                }
+                off[t + 1] = off[t] + len;
+            }
+            if (off[ntasks] <= (int64_t)INT_MAX) {
+                s.tmoff.resize(ntasks + 1);
+                for (int t = 0; t <= ntasks; t++) s.tmoff[t] = (int)off[t];
+                s.smap.resize((size_t)off[ntasks]);
+                auto fill = [&](int t0, int t1) {
+                    for (int t = t0; t < t1; t++) {
+                        const int k = s.task_tgt[t];
+                        const int *rk = s.Fi_dev.data() + s.Dp[k];
+                        const int slen = s.task8[8 * (size_t)t + 2];
+                        int64_t o = off[t];
+                        for (int i = s.src_ptr[t]; i < s.src_ptr[t + 1]; i++) {
+                            int it[4];
+                            item_of(i, k, it);
+                            int pos = it[3] + 1;               // rows of L(:,j) lie below row j in column k
+                            for (int q = it[1]; q < it[2]; q++) {
+                                pos = (int)(std::lower_bound(rk + pos, rk + slen, s.Fi_dev[q]) - rk);
+                                s.smap[(size_t)o++] = pos;   // struct(L(:,j)) is inside struct(column k)
+                            }
+                        }
+                    }
+                };
+                const unsigned hw = std::max(1u, std::min(16u, std::thread::hardware_concurrency()));
+                if (hw == 1 || off[ntasks] < (1 << 20)) fill(0, ntasks);
+                else {
+                    // split by map entries so that the threads get similar work
+                    std::vector<std::thread> th;
+                    int t0 = 0;
+                    for (unsigned w = 1; w <= hw; w++) {
+                        const int64_t goal = off[ntasks] * (int64_t)w / hw;
+                        int t1 = (int)(std::lower_bound(off.begin(), off.end(), goal) - off.begin());
+                        t1 = std::min(std::max(t1, t0), ntasks);
+                        if (w == hw) t1 = ntasks;
+                        if (t1 > t0) th.emplace_back(fill, t0, t1);
+                        t0 = t1;
+                    }
+                    for (auto &x : th) x.join();
+                }
+            }
+        }
         s.macs_sweep = 0;
         for (int t = 0; t < ntasks; t++)
             for (int i = s.src_ptr[t]; i < s.src_ptr[t + 1]; i++) {

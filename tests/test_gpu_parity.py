@@ -515,6 +515,51 @@ def test_dense_lookahead_identical(ck, width):
             assert np.array_equal(out[0][0][i][k], out[1][0][i][k]), (i, k)
 
 
+SLOT_MAP_CASES = [
+    ("mesh_transistor_40", lambda: mnagen.mesh_transistor(40, 40, seed=31), 600),
+    ("random_1400", lambda: mnagen.random_pattern(1400, 0.01, 8), -1),         # no dense block; columns > 1024 rows
+]
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32_ir"])
+@pytest.mark.parametrize("name,make,tail", SLOT_MAP_CASES, ids=[s[0] for s in SLOT_MAP_CASES])
+def test_slot_map_identical(ck, name, make, tail, precision):
+    """The sweep's slot map replaces the search of the target rows by a load of the
+    slot; the updates and their order are the same, so factors, solutions and statuses
+    are bit-identical to the search path, single and batched (one instance failing its
+    pivot check)."""
+    c = make()
+    batch = 3
+    V = np.stack([mnagen.perturb(c.values, 31, 0, t) for t in range(batch)])
+    prec = ck.CKTLU_FP64 if precision == "fp64" else ck.CKTLU_FP32_IR
+    h = ck.SparseLU(c.n, c.colptr, c.rowind, eps=EPS, dense_tail=tail)
+    h.factorize_host(c.values)
+    lev, nl = h.levels(), np.diff(h.factors()["Lp"])
+    kf = [k for k in range(c.n) if lev[k] == 1 and nl[k] > 0][0]
+    V[1, _pivot_entry(c, h.analysis(), kf)] *= 1e-8       # instance 1 fails its pivot check
+    out = {}
+    for m in (-1, 0):
+        say(name, precision, "slot map", m)
+        s = ck.SparseLU(c.n, c.colptr, c.rowind, eps=EPS, dense_tail=tail, sweep_slot_map=m, precision=prec)
+        s.factorize(dev(c.values))
+        assert (s.stats()["slot_map_entries"] > 0) == (m == 0)
+        s.refactorize(dev(V[0]))
+        f1 = s.factors()
+        st = torch.zeros(batch, dtype=torch.int32, device="cuda:0")
+        s.refactorize_batched(batch, dev(V), st)
+        X = torch.zeros((batch, 1, c.n), dtype=torch.float64, device="cuda:0")
+        s.solve_batched(batch, 1, dev(np.repeat(c.rhs[:1][None], batch, axis=0)), X, st)
+        torch.cuda.synchronize()
+        out[m] = (f1, [s.factors(instance=i) for i in (0, 2)], X.cpu().numpy(), st.cpu().numpy())
+    assert np.array_equal(out[-1][3], out[0][3])
+    assert 0 <= out[0][3][1] <= kf and out[0][3][0] == -1 and out[0][3][2] == -1
+    assert np.array_equal(out[-1][2][[0, 2]], out[0][2][[0, 2]])
+    for k in ("Lx", "Ux"):
+        assert np.array_equal(out[-1][0][k], out[0][0][k]), k
+        for i in range(2):
+            assert np.array_equal(out[-1][1][i][k], out[0][1][i][k]), (i, k)
+
+
 LONG_ROWS = [
     ("power_grid_80", lambda: mnagen.power_grid(80, 80, n_src=50, seed=3)),      # L rows up to ~330
     ("random_700", lambda: mnagen.random_pattern(700, 0.01, 6)),                 # L and U rows > 256
