@@ -480,7 +480,7 @@ int run_refactor(cktlu_ctx *c, int batch, const double *values_dev, bool fp32, b
     a.task8 = (const int *)d.task8.p;
     a.item4 = (const int *)d.item4.p;
     a.smap = d.smap.p ? (const int *)d.smap.p : nullptr;
-    a.tmoff = d.smap.p ? (const int *)d.tmoff.p : nullptr;
+    a.tmoff = d.smap.p ? (const int64_t *)d.tmoff.p : nullptr;
     a.T = s.tail0;
     a.D = c->an.n - s.tail0;
     a.S = d.S.p;
@@ -1133,7 +1133,11 @@ int cktlu_autotune(cktlu_ctx *c, int32_t batch, const double *values_dev, int32_
         c->opt.dense_tail_size = cd.size;
         c->opt.dense_tail_density = cd.density;
         Schedule trial;
-        build_schedule(c->an, c->f, c->opt, trial);
+        // trials build a slot map of at most 2^30 entries (a few seconds); the kept schedule
+        // gets the full one
+        size_t fr = 0, tot = 0;
+        const int64_t cap = hipMemGetInfo(&fr, &tot) == hipSuccess ? (int64_t)(0.25 * (double)fr / sizeof(int)) : 0;
+        build_schedule(c->an, c->f, c->opt, trial, std::min<int64_t>(cap, (int64_t)1 << 30));
         const int D = n - trial.tail0;
         if (std::find(seen.begin(), seen.end(), D) != seen.end()) continue;
         seen.push_back(D);

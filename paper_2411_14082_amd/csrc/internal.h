@@ -98,7 +98,8 @@ struct Schedule {
     std::vector<int> colrec, task8, item4;    // the same schedule packed for the device
     // slot map: for task t, the slots in its target column of the entries of its items
     // (first item, then the extra ones, each its L range in order) from smap[tmoff[t]]
-    std::vector<int> smap, tmoff;
+    std::vector<int> smap;
+    std::vector<int64_t> tmoff;
     std::vector<int> amap;                    // user nonzero -> slot offset inside its column
     // device layout of the factor storage: column k occupies [Dp[k], Dp[k] + Dlen[k]);
     // every column starts on a kColAlign-entry boundary
@@ -123,7 +124,10 @@ struct Schedule {
     std::vector<int> lrec, urec, Lrjs, Urjs;  // the solve levels packed for the device
 };
 
-void build_schedule(const Analysis &an, const Factor &f, const cktlu_options &opt, Schedule &s);
+// map_cap: most slot-map entries to build (-1: what a quarter of the device's free memory
+// holds; none without a device)
+void build_schedule(const Analysis &an, const Factor &f, const cktlu_options &opt, Schedule &s,
+                    int64_t map_cap = -1);
 
 // ------------------------------------------------------------------ device
 struct DevBuf {
@@ -171,8 +175,8 @@ struct RefactorArgs {
     const int *seq, *Dp, *Dlen, *Fi, *nU, *Ap, *colperm, *amap;
     const int *colrec;         // {Dp, nU, Dlen, column} per position of seq
     const int *task8, *item4;  // right-looking update tasks (two int4s each) and their extra items
-    const int *smap, *tmoff;   // slot map (target slot of every source entry) and its offset per task,
-                               // or nullptr: the tasks search the target rows
+    const int *smap;           // slot map (target slot of every source entry), or nullptr: the tasks
+    const int64_t *tmoff;      // search the target rows; its offset per task
     const double *Aval;        // batch x nnzA
     int64_t nnzA, nnzF;
     void *Fx;                  // batch x nnzF (double or float)

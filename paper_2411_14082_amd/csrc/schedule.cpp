@@ -8,6 +8,8 @@
 #include <thread>
 #include <numeric>
 
+#include <hip/hip_runtime.h>
+
 #include "internal.h"
 
 namespace cktlu {
@@ -35,7 +37,7 @@ static int choose_tail(const Factor &f, const cktlu_options &opt) {
     return 0;
 }
 
-void build_schedule(const Analysis &an, const Factor &f, const cktlu_options &opt, Schedule &s) {
+void build_schedule(const Analysis &an, const Factor &f, const cktlu_options &opt, Schedule &s, int64_t map_cap) {
     const int n = an.n;
     s = Schedule();
     s.n = n;
@@ -228,7 +230,11 @@ void build_schedule(const Analysis &an, const Factor &f, const cktlu_options &op
         // applies them, entries in L order; built in parallel over tasks
         s.smap.clear();
         s.tmoff.clear();
-        if (opt.sweep_slot_map == 0 && ntasks > 0) {
+        if (map_cap < 0) {
+            size_t fr = 0, tot = 0;
+            map_cap = hipMemGetInfo(&fr, &tot) == hipSuccess ? (int64_t)(0.25 * (double)fr / sizeof(int)) : 0;
+        }
+        if (opt.sweep_slot_map == 0 && ntasks > 0 && map_cap > 0) {
             std::vector<int64_t> off(ntasks + 1, 0);
             for (int t = 0; t < ntasks; t++) {
                 int64_t len = 0;
@@ -239,9 +245,8 @@ void build_schedule(const Analysis &an, const Factor &f, const cktlu_options &op
                 }
                 off[t + 1] = off[t] + len;
             }
-            if (off[ntasks] <= (int64_t)INT_MAX) {
-                s.tmoff.resize(ntasks + 1);
-                for (int t = 0; t <= ntasks; t++) s.tmoff[t] = (int)off[t];
+            if (off[ntasks] <= map_cap) {
+                s.tmoff.assign(off.begin(), off.end());
                 s.smap.resize((size_t)off[ntasks]);
                 auto fill = [&](int t0, int t1) {
                     for (int t = t0; t < t1; t++) {
