@@ -355,7 +355,9 @@ typedef struct {
     int slots;                /* requests on the device at once (worker threads); default 4, 1..64 */
     double hbm_budget_bytes;  /* device bytes the resident requests may use together;
                                  0 (default) = 80% of the free HBM at creation */
-    cktlu_options lu;         /* options of every request (precision, eps, ...); stream and timing ignored */
+    cktlu_options lu;         /* options of every request (precision, eps, ...); stream, timing and
+                                 sweep_slot_map ignored (requests run without the slot map: their few
+                                 steps do not repay building it) */
 } cktlu_server_options;
 
 typedef struct {

@@ -1396,7 +1396,9 @@ size_t cktlu_footprint_bytes(const cktlu_ctx *c, int32_t batch) {
     const size_t per = (size_t)F * (c->opt.precision == CKTLU_FP32_IR ? 12 : 8) + (size_t)c->an.nnz * 8 +
                        (size_t)c->an.n * (4 + 8 * YS) + Dt * Dt * 8 +
                        nblk * 2 * kDenseBlock * kDenseBlock * 8;
-    if (!c->dev.uploaded) s += (size_t)F * 12 + (size_t)c->an.nnz * 12 + (size_t)c->an.n * 64;
+    if (!c->dev.uploaded)
+        s += (size_t)F * 12 + (size_t)c->an.nnz * 12 + (size_t)c->an.n * 64 + c->s.smap.size() * sizeof(int) +
+             c->s.tmoff.size() * sizeof(int64_t);
     return s + (batch > 0 ? per * (size_t)batch : 0);
 }
 

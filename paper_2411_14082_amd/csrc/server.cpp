@@ -52,6 +52,9 @@ int serve_one(cktlu_server *srv, cktlu_server::Req &q, hipStream_t st, cktlu_req
     cktlu_options o = srv->opt.lu;
     o.stream = st;
     o.timing = 0;
+    // no slot map: a request's few steps do not repay building it on the host, and the
+    // slots' requests would each size it against the same free memory
+    o.sweep_slot_map = -1;
     cktlu_ctx *ctx = nullptr;
     int rc = cktlu_create(&ctx, &o);
     if (rc) return rc;
