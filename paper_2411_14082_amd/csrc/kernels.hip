@@ -154,39 +154,39 @@ __device__ __forceinline__ void apply_item_u(const RefactorArgs &a, const T *Fx,
 #pragma unroll
             for (int u = 0; u < U; u++) pos[u] = r[u];
         } else {
-        int base[U];
+            int base[U];
 #pragma unroll
-        for (int u = 0; u < U; u++) base[u] = lo0;
-        int cnt = slen - lo0;                              // lower bound of r in rows [lo0, slen)
-        if (staged) {
-            while (cnt > 1) {
-                const int half = cnt >> 1;
+            for (int u = 0; u < U; u++) base[u] = lo0;
+            int cnt = slen - lo0;                              // lower bound of r in rows [lo0, slen)
+            if (staged) {
+                while (cnt > 1) {
+                    const int half = cnt >> 1;
 #pragma unroll
-                for (int u = 0; u < U; u++) base[u] = lrows[base[u] + half - 1] < r[u] ? base[u] + half : base[u];
-                cnt -= half;
+                    for (int u = 0; u < U; u++) base[u] = lrows[base[u] + half - 1] < r[u] ? base[u] + half : base[u];
+                    cnt -= half;
+                }
+                if (cnt == 1) {
+#pragma unroll
+                    for (int u = 0; u < U; u++) base[u] += lrows[base[u]] < r[u] ? 1 : 0;
+                }
+            } else {
+                while (cnt > 1) {
+                    const int half = cnt >> 1;
+#pragma unroll
+                    for (int u = 0; u < U; u++) base[u] = rowsk[base[u] + half - 1] < r[u] ? base[u] + half : base[u];
+                    cnt -= half;
+                }
+                if (cnt == 1) {
+#pragma unroll
+                    for (int u = 0; u < U; u++) base[u] += rowsk[base[u]] < r[u] ? 1 : 0;
+                }
             }
-            if (cnt == 1) {
 #pragma unroll
-                for (int u = 0; u < U; u++) base[u] += lrows[base[u]] < r[u] ? 1 : 0;
+            for (int u = 0; u < U; u++) {
+                if (r[u] < 0) pos[u] = -1;
+                else if (Sk && r[u] >= a.T) pos[u] = -(2 + (r[u] - a.T));
+                else pos[u] = base[u] < slen ? base[u] : -1;  // always found: struct(L(:,j)) is inside struct(col k)
             }
-        } else {
-            while (cnt > 1) {
-                const int half = cnt >> 1;
-#pragma unroll
-                for (int u = 0; u < U; u++) base[u] = rowsk[base[u] + half - 1] < r[u] ? base[u] + half : base[u];
-                cnt -= half;
-            }
-            if (cnt == 1) {
-#pragma unroll
-                for (int u = 0; u < U; u++) base[u] += rowsk[base[u]] < r[u] ? 1 : 0;
-            }
-        }
-#pragma unroll
-        for (int u = 0; u < U; u++) {
-            if (r[u] < 0) pos[u] = -1;
-            else if (Sk && r[u] >= a.T) pos[u] = -(2 + (r[u] - a.T));
-            else pos[u] = base[u] < slen ? base[u] : -1;  // always found: struct(L(:,j)) is inside struct(col k)
-        }
         }
         T tv[U];
 #pragma unroll
