@@ -88,10 +88,12 @@ typedef struct {
     int dense_device_repivot; /* pivot-check fallback: 0 (default) re-factors the dense block on the device
                               with the threshold pivot rule when every column to restart lies in it (the
                               host then computes only the new pattern); -1 = always the host fallback */
-    int sweep_slot_map;    /* 0 (default): the analysis records, for every entry of every update task's
-                              sources, its slot in the target column (4 bytes per multiply-add of the sweep,
-                              kept on the device when it takes at most a quarter of the free HBM), so the
-                              sweep loads the slot instead of searching the target's rows; -1 = never */
+    int sweep_slot_map;    /* 0 (default): the schedule (built by the factorizations) records, for every
+                              entry of every update task's sources, its slot in the target column: 4 bytes
+                              per multiply-add of the sweep, built on the host only when a device is present
+                              and the map takes at most a quarter of its free HBM (autotuner trials: at most
+                              2^30 entries).  The sweep then loads the slot instead of searching the target's
+                              rows; results are bit-identical.  -1 = never */
 } cktlu_options;
 
 typedef struct {
