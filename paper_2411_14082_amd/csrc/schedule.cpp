@@ -6,6 +6,7 @@
 #include <algorithm>
 #include <climits>
 #include <thread>
+#include <new>
 #include <numeric>
 
 #include <hip/hip_runtime.h>
@@ -230,7 +231,7 @@ void build_schedule(const Analysis &an, const Factor &f, const cktlu_options &op
         // applies them, entries in L order; built in parallel over tasks
         s.smap.clear();
         s.tmoff.clear();
-        if (map_cap < 0) {
+        if (map_cap < 0 && opt.sweep_slot_map == 0) {
             size_t fr = 0, tot = 0;
             map_cap = hipMemGetInfo(&fr, &tot) == hipSuccess ? (int64_t)(0.25 * (double)fr / sizeof(int)) : 0;
         }
@@ -245,9 +246,18 @@ void build_schedule(const Analysis &an, const Factor &f, const cktlu_options &op
                 }
                 off[t + 1] = off[t] + len;
             }
-            if (off[ntasks] <= map_cap) {
-                s.tmoff.assign(off.begin(), off.end());
-                s.smap.resize((size_t)off[ntasks]);
+            bool fits = off[ntasks] <= map_cap;
+            if (fits) {
+                try {                                  // host memory for the map: none, no map
+                    s.tmoff.assign(off.begin(), off.end());
+                    s.smap.resize((size_t)off[ntasks]);
+                } catch (const std::bad_alloc &) {
+                    std::vector<int>().swap(s.smap);
+                    std::vector<int64_t>().swap(s.tmoff);
+                    fits = false;
+                }
+            }
+            if (fits) {
                 auto fill = [&](int t0, int t1) {
                     for (int t = t0; t < t1; t++) {
                         const int k = s.task_tgt[t];
@@ -268,7 +278,8 @@ void build_schedule(const Analysis &an, const Factor &f, const cktlu_options &op
                 const unsigned hw = std::max(1u, std::min(16u, std::thread::hardware_concurrency()));
                 if (hw == 1 || off[ntasks] < (1 << 20)) fill(0, ntasks);
                 else {
-                    // split by map entries so that the threads get similar work
+                    // split by map entries so that the threads get similar work; a range whose
+                    // thread cannot be started is filled here
                     std::vector<std::thread> th;
                     int t0 = 0;
                     for (unsigned w = 1; w <= hw; w++) {
@@ -276,7 +287,13 @@ void build_schedule(const Analysis &an, const Factor &f, const cktlu_options &op
                         int t1 = (int)(std::lower_bound(off.begin(), off.end(), goal) - off.begin());
                         t1 = std::min(std::max(t1, t0), ntasks);
                         if (w == hw) t1 = ntasks;
-                        if (t1 > t0) th.emplace_back(fill, t0, t1);
+                        if (t1 > t0) {
+                            try {
+                                th.emplace_back(fill, t0, t1);
+                            } catch (...) {
+                                fill(t0, t1);
+                            }
+                        }
                         t0 = t1;
                     }
                     for (auto &x : th) x.join();
