@@ -135,6 +135,8 @@ typedef struct {
                                          B + B' under each method (-1 when not run) */
     int64_t slot_map_entries;         /* entries of the sweep's slot map on the device (0: none, the sweep
                                          searches the target rows) */
+    int64_t schur_parts, schur_scratch_cols;  /* the dense block's Schur update: parts (wavefronts per
+                                         instance) and scratch columns of the parts after a column's first */
 } cktlu_stats;
 
 /* Device time of the phases, accumulated over the calls made with options.timing = 1

@@ -82,7 +82,8 @@ class cktlu_stats(ctypes.Structure):
                 ("dense_launches", ctypes.c_int64), ("solve_launches", ctypes.c_int64),
                 ("n_device_repivot", ctypes.c_int64), ("ordering_used", ctypes.c_int64),
                 ("fill_amd", ctypes.c_int64), ("fill_amf", ctypes.c_int64), ("fill_nd", ctypes.c_int64),
-                ("slot_map_entries", ctypes.c_int64)]
+                ("slot_map_entries", ctypes.c_int64), ("schur_parts", ctypes.c_int64),
+                ("schur_scratch_cols", ctypes.c_int64)]
 
     def as_dict(self):
         return {f: getattr(self, f) for f, _ in self._fields_}

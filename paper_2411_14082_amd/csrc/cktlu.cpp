@@ -165,7 +165,8 @@ int upload(DevBuf &b, const std::vector<V> &v, hipStream_t st) {
 
 DevBuf *all_buffers(Device &d, int i) {
     DevBuf *all[] = {&d.seq, &d.Dp, &d.Dlen, &d.Fi, &d.nU, &d.Ap, &d.colperm, &d.amap, &d.colrec, &d.task8,
-                     &d.item4, &d.smap, &d.tmoff, &d.tail_nb, &d.l21, &d.lrec, &d.urec,
+                     &d.item4, &d.smap, &d.tmoff, &d.tail_nb, &d.schur_parts, &d.schur_add, &d.schur_scr,
+                     &d.l21, &d.lrec, &d.urec,
                      &d.Lrjs, &d.Urjs, &d.lsptr, &d.usptr, &d.rowperm,
                      &d.colperm_sol, &d.Acp, &d.Acj, &d.Acsrc, &d.Fx64, &d.Fx32, &d.Aval, &d.done,
                      &d.ctrl, &d.vec, &d.S, &d.Dg, &d.Dinv};
@@ -237,6 +238,10 @@ int ensure_batch(cktlu_ctx *c, int batch) {
         dfree(d.Dinv);
         const size_t nblk = (D + kDenseBlock - 1) / kDenseBlock;
         if ((rc = dalloc(d.Dinv, nblk * 2 * kDenseBlock * kDenseBlock * sizeof(double) * batch))) return rc;
+        dfree(d.schur_scr);
+        if (c->s.schur_nscr > 0 &&
+            (rc = dalloc(d.schur_scr, (size_t)c->s.schur_nscr * D * sizeof(double) * batch)))
+            return rc;
     }
     d.S_prec = -1;
     d.batch_cap = batch;
@@ -261,6 +266,8 @@ int upload_all(cktlu_ctx *c) {
     if ((rc = upload(d.colrec, s.colrec, st))) return rc;
     if ((rc = upload(d.task8, s.task8, st))) return rc;
     if ((rc = upload(d.tail_nb, s.tail_nb, st))) return rc;
+    if ((rc = upload(d.schur_parts, s.schur_parts, st))) return rc;
+    if ((rc = upload(d.schur_add, s.schur_add, st))) return rc;
     if ((rc = upload(d.l21, s.l21, st))) return rc;
     if ((rc = upload(d.item4, s.item4, st))) return rc;
     {
@@ -320,6 +327,8 @@ void fill_stats_pattern(cktlu_ctx *c) {
     t.fill_amd = c->an.fill_amd;
     t.fill_amf = c->an.fill_amf;
     t.fill_nd = c->an.fill_nd;
+    t.schur_parts = (int64_t)(c->s.schur_parts.size() / 4);
+    t.schur_scratch_cols = c->s.schur_nscr;
     t.dense_tail = c->an.n - c->s.tail0;
     const double fb = c->opt.precision == CKTLU_FP32_IR ? 4.0 : 8.0;
     const double nF = (double)(t.nnz_l + t.nnz_u);
@@ -419,6 +428,8 @@ DenseArgs dense_args(cktlu_ctx *c, int batch, bool fp32) {
     a.force_fail_col = -1;
     a.fp32 = fp32 ? 1 : 0;
     a.W = c->opt.dense_panel_width ? c->opt.dense_panel_width : 256;
+    a.scr = d.schur_scr.p;
+    a.nscr = c->s.schur_nscr;
     return a;
 }
 
@@ -518,8 +529,9 @@ int run_refactor(cktlu_ctx *c, int batch, const double *values_dev, bool fp32, b
             la.nev = (int)c->la_events.size();
         }
         t0 = phase_begin(c);
-        LCHK(launch_schur(da, (const int *)d.tail_nb.p, (const int *)d.l21.p, st));
-        phase_end(c, t0, PH_SCHUR, 1);
+        LCHK(launch_schur(da, (const int *)d.schur_parts.p, (int)(c->s.schur_parts.size() / 4),
+                          (const int *)d.schur_add.p, (int)(c->s.schur_add.size() / 4), (const int *)d.l21.p, st));
+        phase_end(c, t0, PH_SCHUR, c->s.schur_add.empty() ? 1 : 2);
         t0 = phase_begin(c);
         LCHK(launch_dense_refactor(da, false, &la, st));
         phase_end(c, t0, PH_DENSE, (int)c->stats.dense_launches);
@@ -556,7 +568,8 @@ int dense_pivot_refactor(cktlu_ctx *c, const std::vector<double> &vals, cktlu_re
     int *swp = (int *)tmp.p, *dinfo = swp + D;
     const auto t0 = std::chrono::steady_clock::now();
     LCHK(launch_dense_reinit(ra, st));
-    LCHK(launch_schur(da, (const int *)d.tail_nb.p, (const int *)d.l21.p, st));
+    LCHK(launch_schur(da, (const int *)d.schur_parts.p, (int)(c->s.schur_parts.size() / 4),
+                      (const int *)d.schur_add.p, (int)(c->s.schur_add.size() / 4), (const int *)d.l21.p, st));
     LCHK(launch_dense_pivoted_lu(da, swp, dinfo, st));
     std::vector<double> Sh((size_t)D * D);
     std::vector<int> sw(D + 1);
@@ -1395,7 +1408,7 @@ size_t cktlu_footprint_bytes(const cktlu_ctx *c, int32_t batch) {
     const size_t nblk = (Dt + kDenseBlock - 1) / kDenseBlock;
     const size_t per = (size_t)F * (c->opt.precision == CKTLU_FP32_IR ? 12 : 8) + (size_t)c->an.nnz * 8 +
                        (size_t)c->an.n * (4 + 8 * YS) + Dt * Dt * 8 +
-                       nblk * 2 * kDenseBlock * kDenseBlock * 8;
+                       nblk * 2 * kDenseBlock * kDenseBlock * 8 + (size_t)c->s.schur_nscr * Dt * 8;
     if (!c->dev.uploaded)
         s += (size_t)F * 12 + (size_t)c->an.nnz * 12 + (size_t)c->an.n * 64 + c->s.smap.size() * sizeof(int) +
              c->s.tmoff.size() * sizeof(int64_t);

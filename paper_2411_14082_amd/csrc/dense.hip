@@ -120,35 +120,34 @@ __global__ __launch_bounds__(256) void tail_scatter_kernel(DenseArgs a) {
 // ------------------------------------------------------------- Schur update
 // S(:, c) -= sum over the bridge rows j of dense column T + c (its U entries in rows
 // < T, ascending) of L(rows >= T, j) U(j, T + c): the sparse columns' contribution to
-// the dense block, applied after the sweep (all of L21 and U12 final).  One wavefront
-// per (dense column, instance) applies the sources in ascending order: deterministic,
-// no atomics.  The L entries of four sources (up to 256 each) are loaded before
-// any of them is applied, and each source reads all its targets before storing.
-// IN_LDS: the column accumulates in LDS (D values), else in place.
-template <typename T, bool IN_LDS>
-__global__ __launch_bounds__(64) void schur_kernel(DenseArgs a, const int *tail_nb, const int *l21) {
-    extern __shared__ char schur_smem[];
+// the dense block, applied after the sweep (all of L21 and U12 final).  A column's
+// sources are cut into parts of similar cost (no column's chain then sets the time
+// alone); one wavefront per (part, instance) applies its sources in ascending order,
+// part 0 in place and each later part into a zeroed scratch column, which
+// schur_add_kernel then adds to S in part order: deterministic, no atomics.  The L
+// entries of four sources (up to 256 each) are loaded before any of them is applied,
+// and each source reads all its targets before storing.
+template <typename T>
+__global__ __launch_bounds__(64) void schur_kernel(DenseArgs a, const int *parts, const int *l21) {
     constexpr int G = 4, CH = 4;                      // sources per group, 64-entry chunks loaded ahead
     const int lane = threadIdx.x;
-    const int inst = (int)(blockIdx.x % (unsigned)a.batch), c = (int)(blockIdx.x / (unsigned)a.batch);
+    const int inst = (int)(blockIdx.x % (unsigned)a.batch);
+    const int4 pr = reinterpret_cast<const int4 *>(parts)[blockIdx.x / (unsigned)a.batch];
+    const int c = pr.x;
     if (sweep_failed(a, inst)) return;
-    T *Sc = inst_S<T>(a, inst) + (size_t)c * a.D;
-    T *col = IN_LDS ? reinterpret_cast<T *>(schur_smem) : Sc;
-    if (IN_LDS) {
-        for (int i0 = 0; i0 < a.D; i0 += 4 * WAVE) {
-            T v[4];
-#pragma unroll
-            for (int u = 0; u < 4; u++) v[u] = i0 + u * WAVE + lane < a.D ? Sc[i0 + u * WAVE + lane] : T(0);
-#pragma unroll
-            for (int u = 0; u < 4; u++)
-                if (i0 + u * WAVE + lane < a.D) col[i0 + u * WAVE + lane] = v[u];
-        }
-        __syncthreads();
+    // part 0 of a column updates it in place; a later part accumulates into its zeroed
+    // scratch column, which the add pass folds into S
+    T *col = pr.w < 0 ? inst_S<T>(a, inst) + (size_t)c * a.D
+                      : reinterpret_cast<T *>(a.scr) + ((size_t)inst * a.nscr + pr.w) * a.D;
+    if (pr.w >= 0) {
+        for (int i = lane; i < a.D; i += WAVE) col[i] = T(0);
+        __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "workgroup");
+        __builtin_amdgcn_wave_barrier();
     }
     const T *Fx = reinterpret_cast<const T *>(a.Fx) + (size_t)inst * a.nnzF;
     const int k = a.T + c;
-    const int bb = a.Dp[k], nb = tail_nb[c];
-    for (int s0 = 0; s0 < nb; s0 += WAVE) {
+    const int bb = a.Dp[k], nb = pr.z;                // bridge sources [pr.y, pr.z) of column k
+    for (int s0 = pr.y; s0 < nb; s0 += WAVE) {
         int rb = 0, re = 0;
         T u = T(0);
         if (s0 + lane < nb) {
@@ -190,9 +189,32 @@ __global__ __launch_bounds__(64) void schur_kernel(DenseArgs a, const int *tail_
             }
         }
     }
-    if (IN_LDS) {
-        __syncthreads();
-        for (int i = lane; i < a.D; i += WAVE) Sc[i] = col[i];
+}
+
+// S(:, c) += the scratch columns of c's later parts, in part order: one wavefront per
+// (split column, instance), four rows in flight per lane
+template <typename T>
+__global__ __launch_bounds__(256) void schur_add_kernel(DenseArgs a, const int *add, int nadd) {
+    const int lane = threadIdx.x & (WAVE - 1);
+    const int64_t w = (int64_t)blockIdx.x * 4 + threadIdx.x / WAVE;
+    if (w >= (int64_t)nadd * a.batch) return;
+    const int inst = (int)(w % a.batch);
+    const int4 r = reinterpret_cast<const int4 *>(add)[w / a.batch];
+    if (sweep_failed(a, inst)) return;
+    T *col = inst_S<T>(a, inst) + (size_t)r.x * a.D;
+    const T *scr = reinterpret_cast<const T *>(a.scr) + ((size_t)inst * a.nscr + r.y) * a.D;
+    for (int i0 = 0; i0 < a.D; i0 += 4 * WAVE) {
+        T v[4];
+#pragma unroll
+        for (int u = 0; u < 4; u++) v[u] = i0 + u * WAVE + lane < a.D ? col[i0 + u * WAVE + lane] : T(0);
+        for (int p = 0; p < r.z; p++) {
+#pragma unroll
+            for (int u = 0; u < 4; u++)
+                if (i0 + u * WAVE + lane < a.D) v[u] += scr[(size_t)p * a.D + i0 + u * WAVE + lane];
+        }
+#pragma unroll
+        for (int u = 0; u < 4; u++)
+            if (i0 + u * WAVE + lane < a.D) col[i0 + u * WAVE + lane] = v[u];
     }
 }
 
@@ -916,13 +938,19 @@ int launch_dense_gather(const DenseArgs &a, void *stream) {
     return (int)hipGetLastError();
 }
 
-int launch_schur(const DenseArgs &a, const int *tail_nb, const int *l21, void *stream) {
+int launch_schur(const DenseArgs &a, const int *parts, int nparts, const int *add, int nadd, const int *l21,
+                 void *stream) {
     hipStream_t st = (hipStream_t)stream;
-    if (a.D <= 0 || a.T <= 0) return 0;
-    // in place: a column in LDS limits the resident wavefronts more than the L2 traffic costs
-    const dim3 grid((unsigned)((int64_t)a.D * a.batch));
-    if (a.fp32) hipLaunchKernelGGL((schur_kernel<float, false>), grid, dim3(64), 0, st, a, tail_nb, l21);
-    else hipLaunchKernelGGL((schur_kernel<double, false>), grid, dim3(64), 0, st, a, tail_nb, l21);
+    if (a.D <= 0 || a.T <= 0 || nparts <= 0) return 0;
+    // in place (part 0) or in scratch: a column in LDS would limit the resident wavefronts
+    const dim3 grid((unsigned)((int64_t)nparts * a.batch));
+    if (a.fp32) hipLaunchKernelGGL((schur_kernel<float>), grid, dim3(64), 0, st, a, parts, l21);
+    else hipLaunchKernelGGL((schur_kernel<double>), grid, dim3(64), 0, st, a, parts, l21);
+    if (nadd > 0) {
+        const dim3 ga((unsigned)(((int64_t)nadd * a.batch + 3) / 4));
+        if (a.fp32) hipLaunchKernelGGL((schur_add_kernel<float>), ga, dim3(256), 0, st, a, add, nadd);
+        else hipLaunchKernelGGL((schur_add_kernel<double>), ga, dim3(256), 0, st, a, add, nadd);
+    }
     return (int)hipGetLastError();
 }
 

@@ -118,6 +118,10 @@ struct Schedule {
     double macs_sweep = 0, lnz_front = 0;     // MACs of the update tasks; L entries of sparse columns
     double macs_schur = 0;                    // MACs of the dense block's Schur update (S -= L21 U12)
     std::vector<int> tail_nb;                 // per dense column: its U entries in rows < T (the bridge)
+    // Schur update parts {dense column, first and end bridge source, scratch column or -1}
+    // and the add pass {dense column, first scratch column, count, 0}
+    std::vector<int> schur_parts, schur_add;
+    int schur_nscr = 0;
     std::vector<int> l21;                     // per sparse column: device range of its L rows >= T
     int tail0 = 0;                            // first column of the densely factored tail (n = none)
     std::vector<int> tail_rend;               // rows i >= tail0: L entries of columns < tail0 end here
@@ -140,7 +144,7 @@ struct Device {
     int batch_cap = 0;                 // instances the value buffers hold
     // pattern / schedule
     DevBuf seq, Dp, Dlen, Fi, nU, Ap, colperm, amap;
-    DevBuf colrec, task8, item4, smap, tmoff, tail_nb, l21;
+    DevBuf colrec, task8, item4, smap, tmoff, tail_nb, l21, schur_parts, schur_add, schur_scr;
     DevBuf lrec, urec, Lrjs, Urjs, lsptr, usptr, rowperm, colperm_sol;
     DevBuf Acp, Acj, Acsrc;
     // values and status words
@@ -267,11 +271,16 @@ struct DenseArgs {
     int force_fail_col;
     int fp32, check;
     int W;                     // columns factored between two updates of the whole trailing block
+    void *scr;                 // batch x nscr x D Schur scratch columns (factor type, 8-byte slots)
+    int nscr;
 };
 // S <- rows >= T of the tail columns of Fx (zeros elsewhere)
 int launch_dense_gather(const DenseArgs &a, void *stream);
-// S -= L21 U12: the sparse columns' contributions to the dense block, after the sweep
-int launch_schur(const DenseArgs &a, const int *tail_nb, const int *l21, void *stream);
+// S -= L21 U12: the sparse columns' contributions to the dense block, after the sweep, in
+// nparts parts (int4 {dense column, first and end bridge source, scratch column or -1}),
+// then the scratch columns added into S (nadd records {column, first scratch, count, 0})
+int launch_schur(const DenseArgs &a, const int *parts, int nparts, const int *add, int nadd, const int *l21,
+                 void *stream);
 // Look-ahead resources of the dense LU: a second stream (default priority) on which the
 // panels of group g+1 run while the trailing update of group g runs on the main stream,
 // and events that order the two (2 per group boundary).  side == nullptr: one stream.

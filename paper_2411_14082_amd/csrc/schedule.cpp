@@ -324,6 +324,39 @@ void build_schedule(const Analysis &an, const Factor &f, const cktlu_options &op
                 s.macs_schur += (double)(s.Dlen[j] - f.nU[j] - lo_cnt[j]);
             }
         }
+        // Schur parts: each dense column's bridge sources, in order, cut into parts of
+        // similar cost (a source costs one round trip plus one per 64 entries), so that no
+        // column's chain sets the kernel's time alone; part 0 updates S in place, each later
+        // part a zeroed scratch column that the add pass folds into S in part order
+        {
+            const int Dn = n - T;
+            std::vector<double> ccost(Dn, 0.0);
+            auto scost = [&](int j) { return 1.0 + (double)(s.Dlen[j] - f.nU[j] - lo_cnt[j]) / 64.0; };
+            double tot = 0.0;
+            for (int c = 0; c < Dn; c++) {
+                const int *b = f.Fi.data() + f.Fp[T + c];
+                for (int q = 0; q < s.tail_nb[c]; q++) ccost[c] += scost(b[q]);
+                tot += ccost[c];
+            }
+            const double budget = Dn > 0 ? std::max(1.0, 1.5 * tot / Dn) : 1.0;
+            s.schur_parts.clear();
+            s.schur_add.clear();
+            s.schur_nscr = 0;
+            for (int c = 0; c < Dn; c++) {
+                const int *b = f.Fi.data() + f.Fp[T + c];
+                const int nb = s.tail_nb[c];
+                const int scr0 = s.schur_nscr;
+                for (int q0 = 0, part = 0; q0 < nb; part++) {   // no part for a column without bridge
+                    double acc = 0.0;
+                    int q1 = q0;
+                    while (q1 < nb && (q1 == q0 || acc + scost(b[q1]) <= budget)) acc += scost(b[q1++]);
+                    const int scr = part == 0 ? -1 : s.schur_nscr++;
+                    s.schur_parts.insert(s.schur_parts.end(), {c, q0, q1, scr});
+                    q0 = q1;
+                }
+                if (s.schur_nscr > scr0) s.schur_add.insert(s.schur_add.end(), {c, scr0, s.schur_nscr - scr0, 0});
+            }
+        }
         s.lnz_front = 0;
         for (int k = 0; k < T; k++) s.lnz_front += (double)(s.Dlen[k] - f.nU[k]);
     }
