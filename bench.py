@@ -311,7 +311,7 @@ def main():
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
-              "(instances and requests shard across GPUs without communication; see DESIGN.md)",
+              "(instances and requests shard across GPUs without communication)",
               file=sys.stderr)
         sys.exit(2)
 
