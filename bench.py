@@ -310,7 +310,7 @@ def main():
                          "nonzero: every assembled nonzero x U[0.95,1.05] (pivot stress)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py measures one GPU only: this build has no multi-GPU path "
+        print("bench.py measures one GPU only: the library has no multi-GPU path "
               "(instances and requests shard across GPUs without communication)",
               file=sys.stderr)
         sys.exit(2)
