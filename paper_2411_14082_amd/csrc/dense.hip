@@ -245,41 +245,61 @@ __device__ __forceinline__ double recip(double u) {
 __device__ __forceinline__ float recip(float u) { return 1.0f / u; }
 
 // Factors the nb x nb diagonal block at (p, p) of S (padded to NB x NB with the
-// identity) without pivoting, with the workgroup's four wavefronts: lane r holds
-// row r, wavefront W the columns c = 4j + W in v[j].  Step kk: the owner of
-// column kk (W = kk % 4) forms L(:, kk) = x * (1 / u_kk) and passes it through
-// LDS (two buffers, one barrier per step); every wavefront then updates its
-// columns c > kk, reading U(kk, c) from lane kk by readlane.  The factors go to
-// blk[col][row] (unit L below the diagonal, U on and above it) and
-// invd[k] = 1 / u_kk.
+// identity) without pivoting, with the workgroup's four wavefronts, two columns per
+// step: lane r holds row r, wavefront W the column pairs (8a + 2W, 8a + 2W + 1) in
+// v[2a], v[2a + 1].  Step (kk, kk+1): the owner of the pair (W = kk/2 % 4) forms
+// L(:, kk) = x * (1 / u_kk), applies it to column kk+1 and forms L(:, kk+1), and
+// passes both through LDS (two buffers, one barrier per step); every wavefront then
+// updates its columns c > kk+1 with both, U(kk, c) read from lane kk by readlane and
+// U(kk+1, c) = x(kk+1, c) - L(kk+1, kk) U(kk, c) formed as lane kk+1 would, so the
+// result equals two single steps bit for bit.  The factors go to blk[col][row] (unit
+// L below the diagonal, U on and above it) and invd[k] = 1 / u_kk.
 template <typename T, int W>
 __device__ void diag_factor_part(const T *S, int D, int p, int nb, T (*blk)[NB + 1], T *invd, T (*lbuf)[WAVE]) {
     const int lane = threadIdx.x & (WAVE - 1);
     T v[NB / 4];
 #pragma unroll
     for (int j = 0; j < NB / 4; j++) {
-        const int c = 4 * j + W;
+        const int c = 8 * (j / 2) + 2 * W + (j % 2);
         v[j] = (lane < nb && c < nb) ? S[(size_t)(p + c) * D + p + lane] : (lane == c ? T(1) : T(0));
     }
 #pragma unroll
-    for (int kk = 0; kk < NB; kk++) {
-        T l;
-        if ((kk & 3) == W) {
-            const int jk = kk >> 2;
-            const T inv = recip(readlane(v[jk], kk));
-            if (lane == 0) invd[kk] = inv;
-            l = lane > kk ? v[jk] * inv : T(0);
-            v[jk] = lane > kk ? l : v[jk];
-            lbuf[kk & 1][lane] = l;
+    for (int kk = 0; kk < NB; kk += 2) {
+        const int buf = 2 * ((kk / 2) & 1);
+        T l0, l1;
+        if (((kk / 2) & 3) == W) {
+            const int jk = 2 * (kk / 8);
+            const T inv0 = recip(readlane(v[jk], kk));
+            l0 = lane > kk ? v[jk] * inv0 : T(0);
+            v[jk] = lane > kk ? l0 : v[jk];
+            v[jk + 1] = fma(-l0, readlane(v[jk + 1], kk), v[jk + 1]);
+            const T inv1 = recip(readlane(v[jk + 1], kk + 1));
+            l1 = lane > kk + 1 ? v[jk + 1] * inv1 : T(0);
+            v[jk + 1] = lane > kk + 1 ? l1 : v[jk + 1];
+            if (lane == 0) {
+                invd[kk] = inv0;
+                invd[kk + 1] = inv1;
+            }
+            lbuf[buf][lane] = l0;
+            lbuf[buf + 1][lane] = l1;
         }
         __syncthreads();
-        if ((kk & 3) != W) l = lbuf[kk & 1][lane];
+        if (((kk / 2) & 3) != W) {
+            l0 = lbuf[buf][lane];
+            l1 = lbuf[buf + 1][lane];
+        }
+        const T l0n = readlane(l0, kk + 1);            // L(kk+1, kk)
 #pragma unroll
-        for (int j = 0; j < NB / 4; j++)
-            if (4 * j + W > kk) v[j] = fma(-l, readlane(v[j], kk), v[j]);
+        for (int j = 0; j < NB / 4; j++) {
+            if (8 * (j / 2) + 2 * W + (j % 2) > kk + 1) {
+                const T u0 = readlane(v[j], kk);
+                const T u1 = fma(-l0n, u0, readlane(v[j], kk + 1));
+                v[j] = fma(-l1, u1, fma(-l0, u0, v[j]));
+            }
+        }
     }
 #pragma unroll
-    for (int j = 0; j < NB / 4; j++) blk[4 * j + W][lane] = v[j];
+    for (int j = 0; j < NB / 4; j++) blk[8 * (j / 2) + 2 * W + (j % 2)][lane] = v[j];
 }
 template <typename T>
 __device__ void diag_factor(const T *S, int D, int p, int nb, T (*blk)[NB + 1], T *invd, T (*lbuf)[WAVE], int wv) {
@@ -318,7 +338,7 @@ __global__ __launch_bounds__(256) void dlu_panel_kernel(DenseArgs a, int p, int 
     __shared__ T blk[NB][NB + 1];
     __shared__ T invd[NB];
     __shared__ T winv[4][16][17];                     // [b][row][col] of U_bb^-1 or L_bb^-1
-    __shared__ T lbuf[2][WAVE];
+    __shared__ T lbuf[4][WAVE];
     const int inst = blockIdx.y;
     if (sweep_failed(a, inst)) return;
     T *S = inst_S<T>(a, inst);
