@@ -277,3 +277,24 @@ def test_nested_dissection_ordering(oracle_mod):
     p_nd = _analysed(small, ordering=ck.CKTLU_ORDER_ND).analysis(with_pivots=False)["colperm"]
     p_amd = _analysed(small, ordering=ck.CKTLU_ORDER_AMD).analysis(with_pivots=False)["colperm"]
     assert np.array_equal(p_nd, p_amd)
+
+
+def test_schur_parts_bookkeeping():
+    """The dense block's Schur update is cut into parts: every dense column with
+    bridge entries (U entries in rows < T) gets exactly one in-place part, every
+    further part a scratch column, and columns without bridge entries get none.
+    Without a device no slot map is built."""
+    c = mnagen.mesh_transistor(40, 40, seed=31)
+    s = ck.SparseLU(c.n, c.colptr, c.rowind, dense_tail=600)
+    s.factorize_host(c.values)
+    st = s.stats()
+    D = st["dense_tail"]
+    assert D >= 600
+    T = c.n - D
+    f = s.factors()
+    Up, Ui = f["Up"], f["Ui"]
+    bridged = sum(1 for k in range(T, c.n) if np.any(Ui[Up[k]:Up[k + 1]] < T))
+    assert bridged > 0
+    assert st["schur_parts"] >= bridged
+    assert st["schur_scratch_cols"] == st["schur_parts"] - bridged
+    assert st["slot_map_entries"] == 0
