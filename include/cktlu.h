@@ -190,7 +190,8 @@ int cktlu_analyze(cktlu_ctx *ctx, int32_t n, const int32_t *colptr, const int32_
 int cktlu_factorize(cktlu_ctx *ctx, const double *values_dev);
 
 /* Same as cktlu_factorize with host values (no device work until the next
- * device call).  Usable without a GPU. */
+ * device call, which uploads the factors and these values: an FP32_IR solve
+ * right after it refines against them).  Usable without a GPU. */
 int cktlu_factorize_host(cktlu_ctx *ctx, const double *values_host);
 
 /*
@@ -304,6 +305,28 @@ typedef struct {
  */
 int cktlu_autotune(cktlu_ctx *ctx, int32_t batch, const double *values_dev, int32_t reps,
                    cktlu_tune_result *out);
+
+/*
+ * Restart set of the pivot-check fallback (Section IV-C), host only: in_set[k]
+ * = 1 for every column k with unfinished[k] != 0 and for every ancestor of such
+ * a column in the column elimination tree, 0 for the others.  parent: host
+ * int32[n], the tree (-1 = root; every other entry satisfies k < parent[k] < n,
+ * as cktlu_get_analysis returns it); unfinished, in_set: host int32[n].
+ * Errors: E_ARG (NULL pointer with n > 0, n < 0, a parent out of range).
+ */
+int cktlu_restart_closure(int32_t n, const int32_t *parent, const int32_t *unfinished, int32_t *in_set);
+
+/*
+ * The sets of this context's last pivot-check fallback (Section IV-C), host
+ * out, int32[n] each, either may be NULL: unfinished[k] = 1 for the columns
+ * the device had not finished when the check failed (every column of the
+ * level whose check failed first and of later levels, and the dense-block
+ * columns from the first failing one on), in_set the restart set computed
+ * from them.  Which columns are unfinished depends only on the values, not on
+ * the order in which the device ran its work.  Errors: E_ARG, E_STATE (no
+ * fallback since the last cktlu_analyze).
+ */
+int cktlu_get_last_restart(const cktlu_ctx *ctx, int32_t *unfinished, int32_t *in_set);
 
 /* Permutations (host out, int32[n] each): A(rowperm[k], colperm[j]) is the
  * (k, j) entry of the matrix that was factored, rowperm including pivoting. */

@@ -60,6 +60,8 @@ def _load():
         lib.or_lu_free.argtypes = [ctypes.POINTER(_OrLu)]
         lib.or_lsolve.argtypes = [ctypes.c_int, ip, ip, dp, dp, dp]
         lib.or_usolve.argtypes = [ctypes.c_int, ip, ip, dp, dp, dp]
+        lib.or_utsolve.argtypes = [ctypes.c_int, ip, ip, dp, dp, dp]
+        lib.or_ltsolve.argtypes = [ctypes.c_int, ip, ip, dp, dp, dp]
         lib.or_levels.argtypes = [ctypes.c_int, ip, ip, ip]
         lib.or_coletree.argtypes = [ctypes.c_int, ip, ip, ip]
         lib.or_coletree.restype = ctypes.c_int
@@ -136,6 +138,32 @@ def usolve(lu: LU, y):
     x = _f64(y).copy()
     _load().or_usolve(lu.n, lu.Up, lu.Ui, lu.Ux, x, x)
     return x
+
+
+def utsolve(lu: LU, c):
+    """z = U^{-T} c."""
+    z = _f64(c).copy()
+    _load().or_utsolve(lu.n, lu.Up, lu.Ui, lu.Ux, z, z)
+    return z
+
+
+def ltsolve(lu: LU, z):
+    """w = L^{-T} z (unit diagonal)."""
+    w = _f64(z).copy()
+    _load().or_ltsolve(lu.n, lu.Lp, lu.Li, lu.Lx, w, w)
+    return w
+
+
+def solve_transposed(lu: LU, rowperm, colperm, c):
+    """Solve A' y = c given A-hat = A(rowperm, colperm) and A-hat(pivrow,:) = L U.
+
+    With B = A(rowperm[pivrow], colperm) = L U, B' = A'(colperm, rowperm[pivrow]),
+    so y(rowperm[pivrow]) = L^{-T} U^{-T} c(colperm)."""
+    rowperm = np.asarray(rowperm); colperm = np.asarray(colperm)
+    w = ltsolve(lu, utsolve(lu, _f64(c)[colperm]))
+    y = np.empty_like(w)
+    y[rowperm[lu.pivrow]] = w
+    return y
 
 
 def solve(lu: LU, rowperm, colperm, b):

@@ -410,3 +410,32 @@ double or_mac_count(int n, const int *Lp, const int *Up, const int *Ui) {
         }
     return macs;
 }
+
+/* Transposed solves, used only by the condition estimate of the tests
+ * (Section II-C's two substitutions applied to U' and L').
+ * or_utsolve: U' z = c with U in CSC (diagonal last in each column): U' is
+ * lower triangular and column j of U is row j of U', so z(j) is
+ * (c(j) - sum_{i<j} U(i,j) z(i)) / U(j,j), j ascending.  c and z may alias. */
+void or_utsolve(int n, const int *Up, const int *Ui, const double *Ux,
+                const double *c, double *z) {
+    if (z != c) memcpy(z, c, (size_t)n * sizeof(double));
+    for (int j = 0; j < n; j++) {
+        int dpos = Up[j + 1] - 1;
+        double s = z[j];
+        for (int p = Up[j]; p < dpos; p++) s -= Ux[p] * z[Ui[p]];
+        z[j] = s / Ux[dpos];
+    }
+}
+
+/* or_ltsolve: L' w = z with unit-diagonal L in CSC: L' is unit upper
+ * triangular and column j of L is row j of L', so w(j) is
+ * z(j) - sum_{i>j} L(i,j) w(i), j descending.  z and w may alias. */
+void or_ltsolve(int n, const int *Lp, const int *Li, const double *Lx,
+                const double *z, double *w) {
+    if (w != z) memcpy(w, z, (size_t)n * sizeof(double));
+    for (int j = n - 1; j >= 0; j--) {
+        double s = w[j];
+        for (int p = Lp[j]; p < Lp[j + 1]; p++) s -= Lx[p] * w[Li[p]];
+        w[j] = s;
+    }
+}

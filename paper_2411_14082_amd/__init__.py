@@ -47,6 +47,7 @@ EXPORTS = [
     "cktlu_server_now", "cktlu_server_destroy",
     "cktlu_get_perm", "cktlu_get_analysis", "cktlu_get_factor_nnz", "cktlu_get_factors",
     "cktlu_get_levels", "cktlu_get_stats", "cktlu_get_timing", "cktlu_footprint_bytes",
+    "cktlu_restart_closure", "cktlu_get_last_restart",
 ]
 
 
@@ -165,6 +166,8 @@ def _load():
     lib.cktlu_get_factor_nnz.argtypes = [P, P, P]
     lib.cktlu_get_factors.argtypes = [P, I32, P, P, P, P, P, P]
     lib.cktlu_get_levels.argtypes = [P, P]
+    lib.cktlu_restart_closure.argtypes = [I32, P, P, P]
+    lib.cktlu_get_last_restart.argtypes = [P, P, P]
     lib.cktlu_get_stats.argtypes = [P, ctypes.POINTER(cktlu_stats)]
     lib.cktlu_get_timing.argtypes = [P, ctypes.POINTER(cktlu_timing), ctypes.c_int]
     lib.cktlu_footprint_bytes.argtypes = [P, I32]
@@ -360,6 +363,14 @@ def cktlu_get_levels(ctx, level):
     return lib.cktlu_get_levels(ctx, _ptr(level))
 
 
+def cktlu_restart_closure(n, parent, unfinished, in_set):
+    return lib.cktlu_restart_closure(int(n), _ptr(parent), _ptr(unfinished), _ptr(in_set))
+
+
+def cktlu_get_last_restart(ctx, unfinished, in_set):
+    return lib.cktlu_get_last_restart(ctx, _ptr(unfinished), _ptr(in_set))
+
+
 def cktlu_get_timing(ctx, reset=0) -> cktlu_timing:
     t = cktlu_timing()
     _check(lib.cktlu_get_timing(ctx, ctypes.byref(t), int(reset)), "cktlu_get_timing")
@@ -493,6 +504,13 @@ class SparseLU:
         _check(cktlu_get_factors(self.ctx, instance, Lp, Li, Lx, Up, Ui, Ux), "cktlu_get_factors")
         k = int(nl[0]); m = int(nu[0])
         return dict(Lp=Lp, Li=Li[:k], Lx=Lx[:k], Up=Up, Ui=Ui[:m], Ux=Ux[:m])
+
+    def last_restart(self):
+        """(unfinished, restart set) of the last pivot-check fallback, boolean arrays."""
+        unf = np.zeros(self.n, np.int32)
+        rs = np.zeros(self.n, np.int32)
+        _check(cktlu_get_last_restart(self.ctx, unf, rs), "cktlu_get_last_restart")
+        return unf.astype(bool), rs.astype(bool)
 
     def levels(self):
         lev = np.zeros(self.n, np.int32)

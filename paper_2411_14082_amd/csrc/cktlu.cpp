@@ -29,6 +29,10 @@ struct cktlu_ctx {
     int force_fail_pending = -1;
     int last_batch = 0;            // batch of the last batched refactorization
     double anorm_host = 0.0;
+    // the last pivot-check fallback: columns the device had not finished, and the restart set
+    std::vector<char> last_unfinished, last_restart;
+    // cktlu_factorize_host: the values, uploaded with the factors (FP32_IR residuals read them)
+    std::vector<double> host_values;
     // options.timing: event pairs recorded around device phases, read by cktlu_get_timing
     struct Pending { int phase; hipEvent_t a, b; int launches; };
     std::vector<Pending> pending;
@@ -307,6 +311,13 @@ int upload_all(cktlu_ctx *c) {
     }
     if (c->opt.precision == CKTLU_FP32_IR)
         LCHK(launch_f64_to_f32((const double *)d.Fx64.p, (float *)d.Fx32.p, nnzF(c), st));
+    if (!c->host_values.empty()) {
+        // values of cktlu_factorize_host: the matrix of these factors, for residuals
+        HIPCHK(hipMemcpyAsync(d.Aval.p, c->host_values.data(), c->host_values.size() * sizeof(double),
+                              hipMemcpyHostToDevice, st));
+        HIPCHK(hipStreamSynchronize(st));
+        c->host_values.clear();
+    }
     d.uploaded = true;
     c->dev_values_newer = false;
     return CKTLU_OK;
@@ -507,7 +518,7 @@ int run_refactor(cktlu_ctx *c, int batch, const double *values_dev, bool fp32, b
         const int cb = l < s.n_rlevels ? s.lvl_ptr[l] : 0, ce = l < s.n_rlevels ? s.lvl_ptr[l + 1] : 0;
         const int pb = l > 0 ? s.lvl_ptr[l - 1] : 0, pe = l > 0 ? s.lvl_ptr[l] : 0;
         const int tb = l < s.n_rlevels ? s.task_ptr[l] : 0, te = l < s.n_rlevels ? s.task_ptr[l + 1] : 0;
-        LCHK(launch_refactor_level(a, cb, ce, pb, pe, tb, te, st));
+        LCHK(launch_refactor_level(a, cb, ce, pb, pe, tb, te, l, st));
         launches += (ce - cb) + (pe - pb) + (te - tb) > 0;
     }
     phase_end(c, t0, PH_SWEEP, launches);
@@ -622,6 +633,8 @@ int fallback(cktlu_ctx *c, const double *values_dev, cktlu_refactor_info *info) 
     std::vector<char> unfinished(n), in_set, keep(n);
     for (int k = 0; k < n; k++) unfinished[k] = done[k] != (int)c->dev.epoch;
     restart_closure(c->an.parent, unfinished, in_set);
+    c->last_unfinished = unfinished;
+    c->last_restart = in_set;
     int rsize = 0, first = n;
     for (int k = 0; k < n; k++) {
         keep[k] = !in_set[k];
@@ -920,6 +933,9 @@ int cktlu_analyze(cktlu_ctx *c, int32_t n, const int32_t *colptr, const int32_t 
     free_device(c->dev);
     c->f = Factor();
     c->s = Schedule();
+    c->last_unfinished.clear();
+    c->last_restart.clear();
+    c->host_values.clear();
     int rc = run_analysis(c->an, n, colptr, rowind, c->opt.ordering, c->opt.transversal);
     if (rc != CKTLU_OK) { c->state = 0; return rc; }
     c->state = 1;
@@ -932,7 +948,10 @@ int cktlu_factorize_host(cktlu_ctx *c, const double *values_host) {
     c->f.pivrow.clear();
     c->fp64_sticky = false;
     int rc = factor_and_setup(c, values_host, nullptr, false);
-    if (rc == CKTLU_OK) c->stats.n_factorize++;
+    if (rc == CKTLU_OK) {
+        c->stats.n_factorize++;
+        c->host_values.assign(values_host, values_host + c->an.nnz);
+    }
     return rc;
 }
 
@@ -947,6 +966,7 @@ int cktlu_factorize(cktlu_ctx *c, const double *values_dev) {
     }
     c->f.pivrow.clear();
     c->fp64_sticky = false;
+    c->host_values.clear();
     int rc = factor_and_setup(c, v.data(), nullptr, true);
     if (rc != CKTLU_OK) return rc;
     c->stats.n_factorize++;
@@ -1289,6 +1309,29 @@ int cktlu_solve_batched(cktlu_ctx *c, int32_t batch, int32_t nrhs, const double 
     HIPCHK(hipStreamSynchronize(st));
     c->stats.n_fp64_fallback_solves += nfb;
     return CKTLU_W_IR_FALLBACK;
+}
+
+int cktlu_restart_closure(int32_t n, const int32_t *parent, const int32_t *unfinished, int32_t *in_set) {
+    if (n < 0 || (n > 0 && (!parent || !unfinished || !in_set))) return CKTLU_E_ARG;
+    std::vector<int> par(parent, parent + n);
+    std::vector<char> unf(n), set;
+    for (int k = 0; k < n; k++) {
+        if (par[k] != -1 && (par[k] <= k || par[k] >= n)) return CKTLU_E_ARG;
+        unf[k] = unfinished[k] != 0;
+    }
+    restart_closure(par, unf, set);
+    for (int k = 0; k < n; k++) in_set[k] = set[k];
+    return CKTLU_OK;
+}
+
+int cktlu_get_last_restart(const cktlu_ctx *c, int32_t *unfinished, int32_t *in_set) {
+    if (!c) return CKTLU_E_ARG;
+    if (c->last_restart.empty() || (int)c->last_restart.size() != c->an.n) return CKTLU_E_STATE;
+    for (int k = 0; k < c->an.n; k++) {
+        if (unfinished) unfinished[k] = c->last_unfinished[k];
+        if (in_set) in_set[k] = c->last_restart[k];
+    }
+    return CKTLU_OK;
 }
 
 int cktlu_get_perm(const cktlu_ctx *c, int32_t *rowperm, int32_t *colperm) {

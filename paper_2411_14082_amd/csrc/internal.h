@@ -187,7 +187,9 @@ struct RefactorArgs {
     int T, D;                  // columns [T, n) form the dense block: their rows >= T live in S
     void *S;                   // batch x D x D (factor type), column-major
     int *done;                 // batch x n: epoch of the last successful computation of each column
-    int *ctrl;                 // [1, 1+batch) interrupt words, [1+batch, 1+2 batch) first failing column
+    int *ctrl;                 // [1, 1+batch) interrupt words (1 + the level whose check failed, any
+                               // nonzero value after the dense block's test), [1+batch, 1+2 batch) first
+                               // failing column
     double eps;
     unsigned epoch;
     int force_fail_col;
@@ -198,10 +200,10 @@ struct RefactorArgs {
 int launch_refactor_init(const RefactorArgs &a, void *stream);
 // FP64, one instance: S = the dense columns' matrix values in rows >= T (their rows < T untouched).
 int launch_dense_reinit(const RefactorArgs &a, void *stream);
-// One right-looking level: pivot check of columns seq[cbeg, cend), normalisation of the
-// previous level seq[pbeg, pend) (L = x / pivot), and update tasks [tbeg, tend).
+// One right-looking level `lev`: pivot check of columns seq[cbeg, cend), normalisation of
+// the previous level seq[pbeg, pend) (L = x / pivot), and update tasks [tbeg, tend).
 int launch_refactor_level(const RefactorArgs &a, int cbeg, int cend, int pbeg, int pend, int tbeg,
-                          int tend, void *stream);
+                          int tend, int lev, void *stream);
 int launch_reset_ctrl(int *ctrl, int nwords, int value, void *stream);
 // status[i] = firstfail[i] == INT_MAX ? -1 : firstfail[i]
 int launch_status_out(const int *firstfail, int *status, int batch, void *stream);

@@ -214,10 +214,15 @@ __device__ __forceinline__ void apply_item(const RefactorArgs &a, const T *Fx, T
                                          l0, mp);
 }
 
-// one wavefront per (task, instance); tasks: [checks | normalisations | updates]
+// one wavefront per (task, instance); tasks: [checks | normalisations | updates].
+// The interrupt word of an instance holds 1 + the level whose check failed first (0:
+// none).  Every part of launch `lev` stops only for a failure of an earlier level, never
+// for one of its own level, so which columns finish does not depend on the order in
+// which the launch's wavefronts run: after a failure at level f the columns of levels
+// below f are final and normalised, those of levels >= f are not.
 template <typename T, bool CHECK, bool MAP>
 __global__ __launch_bounds__(WG) void refactor_level_kernel(RefactorArgs a, int cbeg, int cend, int pbeg,
-                                                             int pend, int tbeg, int tend) {
+                                                             int pend, int tbeg, int tend, int lev) {
     const int lane = threadIdx.x & (WAVE - 1), wv = threadIdx.x / WAVE;
     const int64_t w = (int64_t)blockIdx.x * WAVES + wv;
     const int nchk = cend - cbeg, nnorm = pend - pbeg, nupd = tend - tbeg;
@@ -248,13 +253,13 @@ __global__ __launch_bounds__(WG) void refactor_level_kernel(RefactorArgs a, int 
             }
         }
         const double d = (double)x[nu - 1];
-        if (stop) return;                                 // an earlier level failed its check
+        if (stop && stop <= lev) return;                  // an earlier level failed its check
         m = wave_max(m);
         bad = __any(bad);
         if (bad || !isfinite(d) || d == 0.0 || fabs(d) < a.eps * m || j == a.force_fail_col) {
             if (lane == 0) {
                 atomicMin(&firstfail[inst], j);
-                atomicExch(&interrupted[inst], 1);
+                atomicExch(&interrupted[inst], lev + 1);  // every writer of this launch writes the same
             }
         }
         return;
@@ -269,7 +274,7 @@ __global__ __launch_bounds__(WG) void refactor_level_kernel(RefactorArgs a, int 
         T v[4];
 #pragma unroll
         for (int u = 0; u < 4; u++) v[u] = nu + u * WAVE + lane < len ? x[nu + u * WAVE + lane] : T(0);
-        if (stop) return;
+        if (stop && stop <= lev) return;                  // level lev-1 passed: normalised whatever lev does
         for (int i0 = nu; i0 < len; i0 += 4 * WAVE) {
             if (i0 != nu) {
 #pragma unroll
@@ -321,7 +326,7 @@ __global__ __launch_bounds__(WG) void refactor_level_kernel(RefactorArgs a, int 
                 if (i0 + u * WAVE + lane < slen) lrows[i0 + u * WAVE + lane] = rr[u];
         }
     }
-    if (stop) return;                                     // an earlier level failed its check
+    if (stop && stop <= lev) return;                      // an earlier level failed its check
     wave_sync();                                          // staged rows visible to the whole wavefront
     apply_item<T, MAP>(a, Fx, xk, Sk, rowsk, lrows, staged, slen, it0.y, it0.z, it0.w + 1, T(1) / piv0, mult0,
                        lane, r0, l0, mp);
@@ -400,7 +405,7 @@ int launch_refactor_init(const RefactorArgs &a, void *stream) {
 }
 
 int launch_refactor_level(const RefactorArgs &a, int cbeg, int cend, int pbeg, int pend, int tbeg, int tend,
-                          void *stream) {
+                          int lev, void *stream) {
     hipStream_t st = (hipStream_t)stream;
     const int64_t waves = (int64_t)((cend - cbeg) + (pend - pbeg) + (tend - tbeg)) * a.batch;
     if (waves == 0) return 0;
@@ -409,10 +414,10 @@ int launch_refactor_level(const RefactorArgs &a, int cbeg, int cend, int pbeg, i
     do {                                                                                                      \
         if (a.smap)                                                                                           \
             hipLaunchKernelGGL((refactor_level_kernel<T, C, true>), grid, dim3(WG), 0, st, a, cbeg, cend, pbeg, \
-                               pend, tbeg, tend);                                                            \
+                               pend, tbeg, tend, lev);                                                       \
         else                                                                                                  \
             hipLaunchKernelGGL((refactor_level_kernel<T, C, false>), grid, dim3(WG), 0, st, a, cbeg, cend, pbeg,\
-                               pend, tbeg, tend);                                                            \
+                               pend, tbeg, tend, lev);                                                       \
     } while (0)
     if (a.fp32) {
         if (a.check) CKTLU_LEVEL(float, true); else CKTLU_LEVEL(float, false);

@@ -136,19 +136,38 @@ def test_errors_and_state():
         assert ck.strerror(s)
 
 
-def test_restart_closure_via_etree(oracle_mod):
-    """The fallback's restart set equals the oracle's closure on the library's etree."""
+def test_restart_closure_vs_oracle(oracle_mod):
+    """The library's restart closure (Section IV-C), called through the C ABI on the
+    library's own elimination tree, equals the oracle's BFS closure for random
+    unfinished sets; the golden example of Section IV-C too; bad trees are refused."""
     c = mnagen.mesh_vsrc(10, 10, 4, seed=5)
     s = _analysed(c)
     par = s.analysis(with_pivots=False)["parent"]
     rng = np.random.default_rng(0)
-    for _ in range(5):
-        unf = rng.uniform(size=c.n) < 0.05
-        got = oracle_mod.restart_set(par, unf)
-        # closure property: members' parents are members, and it contains unf
-        assert got[unf].all()
-        idx = np.nonzero(got)[0]
-        assert all(par[i] < 0 or got[par[i]] for i in idx)
+    for frac in (0.0, 0.01, 0.05, 0.3, 1.0):
+        unf = rng.uniform(size=c.n) < frac
+        got = np.zeros(c.n, np.int32)
+        assert ck.cktlu_restart_closure(c.n, par, unf.astype(np.int32), got) == 0
+        assert np.array_equal(got.astype(bool), oracle_mod.restart_set(par, unf)), frac
+    rec = {}
+    with open(os.path.join(os.path.dirname(__file__), "golden", "restart_example.txt")) as f:
+        for line in f:
+            if line.startswith("#") or not line.strip():
+                continue
+            key, vals = line.split(":")
+            rec[key] = [int(v) for v in vals.split()]
+    gpar = np.array([p - 1 for p in rec["parent"]], np.int32)
+    unf = np.zeros(10, np.int32)
+    unf[np.array(rec["unfinished"]) - 1] = 1
+    got = np.zeros(10, np.int32)
+    assert ck.cktlu_restart_closure(10, gpar, unf, got) == 0
+    assert list(np.nonzero(got)[0] + 1) == rec["restart"]
+    bad = gpar.copy()
+    bad[3] = 1                                     # parent below its child
+    assert ck.cktlu_restart_closure(10, bad, unf, got) == ck.CKTLU_E_ARG
+    assert ck.cktlu_restart_closure(10, None, unf, got) == ck.CKTLU_E_ARG
+    # no fallback yet: the last-restart getter refuses
+    assert ck.cktlu_get_last_restart(s.ctx, None, None) == ck.CKTLU_E_STATE
 
 
 def test_footprint_estimate_positive():

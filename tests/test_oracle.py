@@ -287,3 +287,180 @@ def test_oracle_singular_cases(oracle_mod):
     A = sp.csc_matrix(np.array([[np.nan, 1.0], [1.0, 1.0]]))
     lu = oracle_mod.gp_lu(2, A.indptr, A.indices, A.data)
     assert lu.status == oracle_mod.NUM_SINGULAR and lu.fail_col == 0
+
+
+# ---------------------------------------------------------------- MAC count
+def _dense_macs(n):
+    """Multiply-adds of a dense n x n LU: sum over pivot j of (n-1-j)^2."""
+    return (n - 1) * n * (2 * n - 1) // 6
+
+
+def test_oracle_mac_count_closed_forms(oracle_mod):
+    """or_mac_count against closed forms: dense (and arrow with its hub first, which
+    fills completely) sum_{m<n} m^2; tridiagonal and arrow-last n-1; diagonal 0."""
+    for n in (1, 2, 3, 7, 12, 20):
+        for kind, want in (("dense", _dense_macs(n)), ("arrow_first", _dense_macs(n)),
+                           ("tridiagonal", n - 1), ("arrow_last", n - 1), ("diagonal", 0)):
+            c = mnagen.hand_pattern(kind, n)
+            lu = oracle_mod.gp_lu(c.n, c.colptr, c.rowind, c.values)
+            assert lu.status == 0
+            assert oracle_mod.mac_count(lu) == want, (kind, n)
+
+
+def _triple_count(Lb, Ub):
+    """#{(i, j, k): L(i,j) != 0, i > j, U(j,k) != 0, k > j} by explicit loops."""
+    n = Lb.shape[0]
+    cnt = 0
+    for j in range(n):
+        for i in range(j + 1, n):
+            if not Lb[i, j]:
+                continue
+            for k in range(j + 1, n):
+                if Ub[j, k]:
+                    cnt += 1
+    return cnt
+
+
+@pytest.mark.parametrize("eps", [1.0, 0.1, 1e-3])
+def test_oracle_mac_count_bruteforce(oracle_mod, eps):
+    """or_mac_count equals a brute-force triple count over the fill pattern that a
+    dense boolean elimination with the dense checker's pivots produces: every
+    (i, j, k) with L(i,j) and U(j,k) structurally nonzero is one multiply-add of
+    the update of column k by column j."""
+    for seed in range(30):
+        n = 3 + seed % 14
+        c = mnagen.random_pattern(n, 0.3, 4000 + seed)
+        A = c.to_scipy().toarray()
+        piv, _, _ = dense_threshold_lu(A, eps)
+        S = symbolic_pattern(A != 0, piv)
+        Lb, Ub = np.tril(S, -1), np.triu(S, 1)
+        lu = oracle_mod.gp_lu(n, c.colptr, c.rowind, c.values, eps=eps)
+        assert lu.status == 0
+        assert oracle_mod.mac_count(lu) == _triple_count(Lb, Ub), seed
+
+
+# ------------------------------------------------- initial pivot sequence
+@pytest.mark.parametrize("eps", [1.0, 0.1, 1e-3])
+def test_oracle_init_pivrow_vs_dense_bruteforce(oracle_mod, eps):
+    """Re-factorization from a given pivot sequence p0 (Section II-A: the preferred
+    row of column k is the row in position k): the oracle must equal the dense
+    checker run on A(p0, :) from the identity, composed with p0 -- pivots exactly,
+    values to rounding, pattern by boolean elimination.  Random p0 put rows with
+    small or structurally zero entries in preferred positions, so exchanges happen."""
+    rng = np.random.default_rng(17)
+    swaps = cases_with_swaps = 0
+    for seed in range(60):
+        n = 3 + seed % 14
+        c = mnagen.random_pattern(n, 0.3, 3000 + seed)
+        A = c.to_scipy().toarray()
+        p0 = rng.permutation(n).astype(np.int32)
+        lu = oracle_mod.gp_lu(n, c.colptr, c.rowind, c.values, eps=eps, init_pivrow=p0)
+        try:
+            piv, L, U = dense_threshold_lu(A[p0], eps)
+        except ZeroDivisionError:
+            assert lu.status != 0
+            continue
+        assert lu.status == 0
+        assert np.array_equal(lu.pivrow, p0[piv]), (seed, lu.pivrow, p0[piv])
+        Ls, Us = _lu_dense(lu)
+        assert np.abs(Ls - L).max() <= 1e-13 * max(1.0, np.abs(L).max())
+        assert np.abs(Us - U).max() <= 1e-13 * max(1.0, np.abs(L).max() * np.abs(U).max())
+        assert np.array_equal(_pattern(lu), symbolic_pattern(A[p0] != 0, piv))
+        swaps += lu.nswaps
+        cases_with_swaps += lu.nswaps > 0
+    assert cases_with_swaps >= 30, cases_with_swaps
+
+
+def test_oracle_refactor_exchange_vs_dense(oracle_mod):
+    """A re-factorization whose check fails: factor, shrink the pivot of one column
+    so its previous pivot row fails the threshold test, re-factor from the previous
+    sequence; the exchange and every later column must equal the dense checker's
+    elimination of A_new(previous sequence, :)."""
+    eps = 0.1
+    done = 0
+    for seed in range(40):
+        n = 6 + seed % 10
+        c = mnagen.random_pattern(n, 0.35, 5000 + seed)
+        A = c.to_scipy().toarray()
+        lu0 = oracle_mod.gp_lu(n, c.colptr, c.rowind, c.values, eps=eps)
+        if lu0.status != 0:
+            continue
+        # scale the entry that holds the pivot of a middle column down by 1e6
+        k = n // 2
+        r = lu0.pivrow[k]
+        v = c.values.copy()
+        lo, hi = c.colptr[k], c.colptr[k + 1]
+        hit = np.nonzero(c.rowind[lo:hi] == r)[0]
+        if hit.size == 0:
+            continue
+        v[lo + hit[0]] *= 1e-6
+        A1 = A.copy()
+        A1[r, k] *= 1e-6
+        lu1 = oracle_mod.gp_lu(n, c.colptr, c.rowind, v, eps=eps, init_pivrow=lu0.pivrow)
+        try:
+            piv, L, U = dense_threshold_lu(A1[lu0.pivrow], eps)
+        except ZeroDivisionError:
+            assert lu1.status != 0
+            continue
+        assert lu1.status == 0
+        assert np.array_equal(lu1.pivrow, lu0.pivrow[piv])
+        Ls, Us = _lu_dense(lu1)
+        assert np.abs(Ls - L).max() <= 1e-12 * max(1.0, np.abs(L).max())
+        assert np.abs(Us - U).max() <= 1e-12 * max(1.0, np.abs(L).max() * np.abs(U).max())
+        done += lu1.nswaps > 0
+    assert done >= 10, done
+
+
+# ------------------------------------------------------ transposed solves
+def test_oracle_transposed_solves_exact_integer(oracle_mod):
+    """U' z = c and L' w = z on exact integer unit/±1-diagonal factors (exact in FP64)."""
+    rng = np.random.default_rng(5)
+    n = 30
+    L = np.tril(rng.integers(-2, 3, (n, n)) * (rng.uniform(size=(n, n)) < 0.2), -1) + np.eye(n)
+    U = np.triu(rng.integers(-2, 3, (n, n)) * (rng.uniform(size=(n, n)) < 0.2), 1) + \
+        np.diag(rng.choice([-1.0, 1.0], n))
+    w = rng.integers(-3, 4, n).astype(float)
+    z = L.T @ w
+    cvec = U.T @ z
+    assert np.abs(cvec).max() < 2 ** 40
+    Ls = sp.csc_matrix(np.tril(L, -1)); Us = sp.csc_matrix(U)
+    lu = oracle_mod.LU(n, 0, -1, 0, np.arange(n, dtype=np.int32),
+                       Ls.indptr.astype(np.int32), Ls.indices.astype(np.int32), Ls.data,
+                       Us.indptr.astype(np.int32), Us.indices.astype(np.int32), Us.data)
+    assert np.array_equal(oracle_mod.utsolve(lu, cvec), z)
+    assert np.array_equal(oracle_mod.ltsolve(lu, z), w)
+
+
+def test_oracle_solve_transposed_vs_numpy(oracle_mod):
+    c = mnagen.mesh_vsrc(8, 8, 4, seed=3)
+    rng = np.random.default_rng(1)
+    rp = rng.permutation(c.n); cp = rng.permutation(c.n)
+    lu = oracle_mod.gp_lu(c.n, c.colptr, c.rowind, c.values, rp, cp, eps=1e-3)
+    assert lu.status == 0
+    y = oracle_mod.solve_transposed(lu, rp, cp, c.rhs[0])
+    yr = np.linalg.solve(c.to_scipy().toarray().T, c.rhs[0])
+    assert np.abs(y - yr).max() <= 1e-8 * np.abs(yr).max()
+
+
+def test_condest_vs_exact_inverse_norm(oracle_mod):
+    """Hager's estimate of ||A^{-1}||_inf from the oracle's solves is a lower bound of
+    the exact value (dense inverse), within a factor 3 of it on these matrices, and
+    exact on at least half of them."""
+    from oracle.condest import kappa_inf
+    exact_hits = 0
+    cases = 0
+    for seed in range(24):
+        c = (mnagen.random_pattern(20 + seed, 0.15, 6000 + seed) if seed % 2 else
+             mnagen.mesh_vsrc(5 + seed % 4, 5 + seed % 4, 4, seed=seed))
+        lu = oracle_mod.gp_lu(c.n, c.colptr, c.rowind, c.values, eps=1e-3)
+        if lu.status != 0:
+            continue
+        idn = np.arange(c.n)
+        k_est = kappa_inf(oracle_mod, lu, c.colptr, c.rowind, c.values, idn, idn)
+        A = c.to_scipy().toarray()
+        k_ex = np.linalg.norm(A, np.inf) * np.linalg.norm(np.linalg.inv(A), np.inf)
+        assert k_est <= k_ex * (1 + 1e-8), (seed, k_est, k_ex)
+        assert k_est >= k_ex / 3, (seed, k_est, k_ex)
+        exact_hits += k_est >= k_ex * (1 - 1e-8)
+        cases += 1
+    assert cases >= 20 and exact_hits >= cases * 0.5, (exact_hits, cases)
