@@ -2,13 +2,16 @@
 """Benchmark: Newton-Raphson refactor + solve steps on one MI355X.
 
 A step is refactorize(values_t) (fast factorization with pivot check) plus
-solve(b) (plus iterative refinement in FP32+IR mode), on the post-layout RC
-mesh workload (3 layers x 300 x 300, vias, transistor stamps; n = 270,000),
-every circuit element re-stamped with a +-5% factor per step (as a simulator
-re-stamps its devices in each Newton-Raphson iteration), all value sets
-pre-staged in HBM before the timed region.  Prints one JSON line with steps/s, p50/p99 step latency for the
-FP64 path (the headline value) and the FP32+IR path, the roofline of the
-refactorization phase and the CPU oracle baseline.
+solve(B) (plus iterative refinement in FP32+IR mode).  The default workload is
+the 1000 x 1000 power grid (n = 1,000,000, pads and current loads) with 8
+right-hand sides per factorization, every circuit element re-stamped with a
++-5% factor per step (as a simulator re-stamps its devices in each
+Newton-Raphson iteration), all value sets pre-staged in HBM before the timed
+region.  Prints one JSON line with steps/s and p50/p99 step latency of the FP64
+path (the headline value) and of the FP32+IR path, the forward error of both
+against the CPU oracle's solution with a condition estimate, the HBM roofline
+of the whole step and of its dominant kernel on the compulsory bytes per
+factor entry, and the CPU oracle baseline.
 """
 import argparse
 import hashlib
@@ -175,32 +178,33 @@ def main_batched(args, wl):
 HBM_PEAK_GBS = 8000.0
 FP64_MFMA_PEAK_TFS = 78.6
 FP32_MFMA_PEAK_TFS = 157.3
-# measured HBM traffic of the sweep kernel: written from two rocprofv3 --pmc runs
+# measured HBM traffic of the dominant kernel: written from two rocprofv3 --pmc runs
 # (FETCH_SIZE, WRITE_SIZE) with the sha256 of the kernel source they were taken on
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "refactor_level_kernel_traffic_layered_rc_3x300.txt")
+PROFILES = os.path.join(ROOT, "profiles")
 KERNEL_SRC = os.path.join(ROOT, "paper_2411_14082_amd", "csrc", "kernels.hip")
 
 
-def kernel_source_hash():
-    """sha256 of the sweep kernel's source (apply_item and refactor_level_kernel)."""
+def kernel_source_hash(begin="constexpr int kItemChunk", end="__global__ void reset_ctrl_kernel"):
+    """sha256 of the dominant kernel's source section."""
     txt = open(KERNEL_SRC).read()
-    a, z = txt.find("constexpr int kItemChunk"), txt.find("__global__ void reset_ctrl_kernel")
+    a, z = txt.find(begin), txt.find(end)
     return hashlib.sha256(txt[a:z].encode()).hexdigest() if 0 <= a < z else None
 
 
-def measured_traffic(algorithmic_bytes_per_launch):
-    """Bytes per sweep launch from the committed counter summary, or None when the
-    sweep kernel's source or its work per launch (the schedule) has changed since
-    the counters were taken."""
-    if not os.path.exists(TRAFFIC_FILE):
+def measured_traffic(fname, kernel, launches_per_step):
+    """HBM bytes per launch of `kernel` from the committed counter summary `fname`, or
+    None when the kernel's source or the work per step (its launch count) has changed
+    since the counters were taken."""
+    path = os.path.join(PROFILES, fname)
+    if not os.path.exists(path):
         return None
-    txt = open(TRAFFIC_FILE).read()
-    m_sha = re.search(r"refactor_level_kernel_source_sha256:\s*([0-9a-f]{64})", txt)
+    txt = open(path).read()
+    m_sha = re.search(r"%s_source_sha256:\s*([0-9a-f]{64})" % kernel, txt)
     m_b = re.search(r"hbm_bytes_per_launch:\s*([0-9.eE+]+)", txt)
-    m_alg = re.search(r"algorithmic_bytes_per_launch:\s*([0-9.eE+]+)", txt)
-    if not m_sha or not m_b or not m_alg or kernel_source_hash() != m_sha.group(1):
+    m_l = re.search(r"launches_per_step:\s*([0-9]+)", txt)
+    if not m_sha or not m_b or not m_l or kernel_source_hash() != m_sha.group(1):
         return None
-    if abs(float(m_alg.group(1)) - algorithmic_bytes_per_launch) > 1e-3 * algorithmic_bytes_per_launch:
+    if int(m_l.group(1)) != int(launches_per_step):
         return None
     return float(m_b.group(1))
 
@@ -209,16 +213,30 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
+def cpu_model():
+    """CPU model name of this host (from /proc/cpuinfo), or None."""
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
+
+
 def lu_options(ck, tail_opts):
     """SparseLU keyword arguments from the bench's schedule options."""
-    kw = {k: v for k, v in tail_opts.items() if k not in ("autotune", "ordering")}
+    kw = {k: v for k, v in tail_opts.items() if k not in ("autotune", "ordering") and v is not None}
     if tail_opts.get("ordering"):
         kw["ordering"] = {"amd": ck.CKTLU_ORDER_AMD, "amf": ck.CKTLU_ORDER_AMF, "nd": ck.CKTLU_ORDER_ND,
                           "auto": ck.CKTLU_ORDER_AUTO, "natural": ck.CKTLU_ORDER_NATURAL}[tail_opts["ordering"]]
     return kw
 
 
-def run_leg(ck, torch, c, vals_dev, b_dev, precision, steps, warmup, tail_opts):
+def run_leg(ck, torch, c, vals_dev, b_dev, precision, steps, warmup, tail_opts, inject=None):
+    """`warmup` untimed and `steps` timed NR steps on values vals_dev[1 + t].
+    inject: {step index: column} makes the pivot test of that column fail on that
+    timed step (value-driven: its pivot entry shrunk on a copy of the values)."""
     nrhs = b_dev.shape[0] if b_dev.dim() == 2 else 1
     s = ck.SparseLU(c.n, c.colptr, c.rowind, eps=1e-3, precision=precision, ir_tol=1e-10, timing=True,
                     **lu_options(ck, tail_opts))
@@ -237,12 +255,30 @@ def run_leg(ck, torch, c, vals_dev, b_dev, precision, steps, warmup, tail_opts):
     s.timing(reset=True)                         # phase times of the timed steps only
     ev = [[torch.cuda.Event(enable_timing=True) for _ in range(3)] for _ in range(steps)]
     infos = []
+    staged = {}
+    if inject:
+        import mnagen
+        for t, col in inject.items():            # values with one pivot shrunk, staged before timing
+            v = vals_dev[1 + warmup + t].clone()
+            staged[t] = (v, col)
     torch.cuda.synchronize()
     w0 = time.time()
     for t in range(steps):
         e0, e1, e2 = ev[t]
+        vt = vals_dev[1 + warmup + t]
+        if t in staged:
+            # the entry that holds the current pivot of the chosen column, found from the
+            # current pivot sequence (a re-pivot earlier in the run may have moved it)
+            v, col = staged[t]
+            a = s.analysis()
+            r = a["rowperm_pre"][a["pivrow"][col]]
+            cc = a["colperm"][col]
+            lo, hi = int(c.colptr[cc]), int(c.colptr[cc + 1])
+            p = lo + int(np.searchsorted(c.rowind[lo:hi], r))
+            v[p] *= 1e-8
+            vt = v
         e0.record()
-        rc, info = s.refactorize(vals_dev[1 + warmup + t])
+        rc, info = s.refactorize(vt)
         e1.record()
         rc2, sinfo = s.solve(b_dev, x, nrhs=nrhs)
         e2.record()
@@ -260,23 +296,74 @@ def run_leg(ck, torch, c, vals_dev, b_dev, precision, steps, warmup, tail_opts):
                 repivots=int(nrep), infos=infos, x=x, timing=tm)
 
 
-def cpu_baseline(c, vals, b):
-    """The CPU oracle (single thread): one re-factorization + solve of the same matrix."""
+def cpu_baseline(c, values, B):
+    """The CPU oracle (single thread) on one step of the workload: the factorization of
+    the last step's matrix and the solves of its right-hand sides.  Returns the
+    baseline record, the oracle's solutions and a condition estimate kappa_inf(A)."""
     import oracle
+    from oracle.condest import kappa_inf
     import paper_2411_14082_amd as ck
     oracle.build(force=False)
-    s = ck.SparseLU(c.n, c.colptr, c.rowind, eps=1e-3)
+    s = ck.SparseLU(c.n, c.colptr, c.rowind, eps=1e-3, sweep_slot_map=-1)
     a = s.analysis(with_pivots=False)
     s.close()
-    lu0 = oracle.gp_lu(c.n, c.colptr, c.rowind, vals[0], a["rowperm_pre"], a["colperm"], 1e-3)
     t0 = time.time()
-    lu = oracle.gp_lu(c.n, c.colptr, c.rowind, vals[1], a["rowperm_pre"], a["colperm"], 1e-3,
-                      init_pivrow=lu0.pivrow)
-    x = oracle.solve(lu, a["rowperm_pre"], a["colperm"], b)
+    lu = oracle.gp_lu(c.n, c.colptr, c.rowind, values, a["rowperm_pre"], a["colperm"], 1e-3)
+    xo = [oracle.solve(lu, a["rowperm_pre"], a["colperm"], b) for b in B]
     dt = time.time() - t0
-    return dict(value=1.0 / dt, unit="steps/s", cores=1, kind="oracle",
-                sample="1 refactorization (from the previous pivot sequence) + 1 solve of the full matrix, "
-                       "FP64, single thread; %.1f s" % dt), x
+    kap = kappa_inf(oracle, lu, c.colptr, c.rowind, values, a["rowperm_pre"], a["colperm"])
+    rec = dict(value=1.0 / dt, unit="steps/s", cores=1, kind="oracle", cpu_model=cpu_model(),
+               host_cores=os.cpu_count(),
+               sample="1 step of the same workload: the Gilbert-Peierls factorization with threshold pivoting "
+                      "of the last step's matrix and %d right-hand-side solves, FP64, one thread; %.1f s"
+                      % (len(B), dt))
+    return rec, np.array(xo), kap, lu.nswaps
+
+
+def eta_inf(c, values, x, b):
+    import scipy.sparse as sp
+    A = sp.csc_matrix((values, c.rowind, c.colptr), shape=(c.n, c.n))
+    return float(np.abs(b - A @ x).max() / (abs(A).sum(axis=1).max() * np.abs(x).max() + np.abs(b).max()))
+
+
+def leg_summary(res, steps):
+    return dict(steps_per_s=steps / res["wall"], p50_ms=float(np.percentile(res["step_ms"], 50)),
+                p99_ms=float(np.percentile(res["step_ms"], 99)), refactor_ms=float(res["ref_ms"].mean()),
+                solve_ms=float(res["sol_ms"].mean()), repivots=res["repivots"])
+
+
+def phases_of(tm):
+    nref = max(1, tm["refactors"])
+    npass = max(1, tm["solve_passes"])
+    return dict(init=tm["init_ms"] / nref, sweep=tm["sweep_ms"] / nref, schur=tm["schur_ms"] / nref,
+                dense=tm["dense_ms"] / nref, solve_sparse=tm["solve_sparse_ms"] / npass,
+                solve_dense=tm["solve_dense_ms"] / npass, solve_passes_per_step=npass / max(1, tm["refactors"]))
+
+
+def main_repivot(args, wl, c, vals_dev, b_dev, tail_opts, ck, torch):
+    """Section VI's general case: of `steps` runs, a fraction re-pivots (the pivot test of a
+    random column made to fail by its values); steps/s against the run with none."""
+    rng = np.random.default_rng(7)
+    out = {}
+    for rate in [0.0] + [float(r) for r in args.repivot_rates.split(",")]:
+        k = int(round(rate * args.steps))
+        when = sorted(rng.choice(args.steps, size=k, replace=False).tolist()) if k else []
+        inject = {int(t): int(rng.integers(0, c.n)) for t in when}
+        res = run_leg(ck, torch, c, vals_dev, b_dev, ck.CKTLU_FP64, args.steps, args.warmup, tail_opts, inject)
+        out["%g" % rate] = dict(leg_summary(res, args.steps), injected=len(inject),
+                                repivots=res["repivots"], device_repivots=int(res["stats"]["n_device_repivot"]))
+        log("re-pivot rate %g: %s" % (rate, out["%g" % rate]))
+    base = out["0"]["steps_per_s"]
+    line = {
+        "metric": "NR refactor+solve steps/sec + p50/p99 step latency, FP32+IR vs FP64, 1 GPU",
+        "value": base, "unit": "steps/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": 1e3 / base, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f64", "data": "synthetic",
+        "config": {"workload": wl["desc"] + "; a fraction of the steps re-pivots at a random column", "n": c.n},
+        "repivot_rates": out,
+        "relative_steps_per_s": {r: v["steps_per_s"] / base for r, v in out.items()},
+    }
+    print(json.dumps(line), flush=True)
 
 
 def main():
@@ -284,7 +371,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default="layered_rc_3x300", choices=sorted(WORKLOADS))
+    ap.add_argument("--workload", default="power_grid_1000_8rhs", choices=sorted(WORKLOADS))
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp32", action="store_true")
     ap.add_argument("--dense-tail", type=int, default=None,
@@ -308,6 +395,9 @@ def main():
     ap.add_argument("--perturb", default="element", choices=["element", "nonzero"],
                     help="element: every circuit element x U[0.95,1.05], re-assembled (NR re-stamping); "
                          "nonzero: every assembled nonzero x U[0.95,1.05] (pivot stress)")
+    ap.add_argument("--repivot-rates", default=None,
+                    help="comma-separated fractions of the timed steps that re-pivot at a random column "
+                         "(e.g. 0.03,0.05,0.1): the general case of Section VI instead of the default line")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: the library has no multi-GPU path "
@@ -335,74 +425,93 @@ def main():
     dev = torch.device("cuda:0")
     vals_dev = [torch.tensor(v, device=dev) for v in vals]       # staged in HBM before timing
     nrhs = wl.get("nrhs", 1)
-    b = c.rhs[0] if nrhs == 1 else c.rhs[:nrhs]
-    b_dev = torch.tensor(np.ascontiguousarray(b), device=dev)
+    B = np.atleast_2d(c.rhs[0] if nrhs == 1 else c.rhs[:nrhs])
+    b_dev = torch.tensor(np.ascontiguousarray(B[0] if nrhs == 1 else B), device=dev)
     torch.cuda.synchronize()
 
     tail_opts = dict(dense_tail=args.dense_tail, dense_tail_density=args.dense_density, autotune=args.autotune,
                      solve_chain_width=args.solve_chain, dense_panel_width=args.dense_panel_width,
                      dense_lookahead=args.dense_lookahead, ordering=args.ordering,
                      sweep_slot_map=-1 if args.no_slot_map else None)
+    if args.repivot_rates:
+        return main_repivot(args, wl, c, vals_dev, b_dev, tail_opts, ck, torch)
     res64 = run_leg(ck, torch, c, vals_dev, b_dev, ck.CKTLU_FP64, args.steps, args.warmup, tail_opts)
     log("fp64: %.3f steps/s, refactor %.2f ms, solve %.2f ms (setup %.1fs), dense tail %d" %
         (args.steps / res64["wall"], res64["ref_ms"].mean(), res64["sol_ms"].mean(), res64["setup_s"],
          res64["stats"]["dense_tail"]))
-    x64 = res64["x"].cpu().numpy()
-    import scipy.sparse as sp
-    A_last = sp.csc_matrix((vals[-1], c.rowind, c.colptr), shape=(c.n, c.n))
-    anorm = abs(A_last).sum(axis=1).max()
-    eta64 = max(float(np.abs(bb - A_last @ xx).max() / (anorm * np.abs(xx).max() + np.abs(bb).max()))
-                for bb, xx in zip(np.atleast_2d(b), np.atleast_2d(x64)))
+    X64 = np.atleast_2d(res64["x"].cpu().numpy())
+    eta64 = max(eta_inf(c, vals[-1], X64[r], B[r]) for r in range(nrhs))
 
-    out_fp32 = None
+    leg32 = None
     if not args.no_fp32:
         res32 = run_leg(ck, torch, c, vals_dev, b_dev, ck.CKTLU_FP32_IR, args.steps, args.warmup, tail_opts)
+        X32 = np.atleast_2d(res32["x"].cpu().numpy())
         iters = [i[0] for i in res32["infos"]]
-        errs = [i[1] for i in res32["infos"]]
-        out_fp32 = dict(steps_per_s=args.steps / res32["wall"],
-                        p50_ms=float(np.percentile(res32["step_ms"], 50)),
-                        p99_ms=float(np.percentile(res32["step_ms"], 99)),
-                        refactor_ms=float(res32["ref_ms"].mean()), solve_ms=float(res32["sol_ms"].mean()),
-                        ir_iters_mean=float(np.mean(iters)), backward_err_max=float(np.max(errs)),
-                        fp64_fallbacks=int(sum(i[2] for i in res32["infos"])), repivots=res32["repivots"])
-        log("fp32+ir: %.3f steps/s" % out_fp32["steps_per_s"])
+        leg32 = dict(leg_summary(res32, args.steps), ir_iters_mean=float(np.mean(iters)),
+                     backward_err_max=max(eta_inf(c, vals[-1], X32[r], B[r]) for r in range(nrhs)),
+                     backward_err_reported_max=float(np.max([i[1] for i in res32["infos"]])),
+                     fp64_fallbacks=int(sum(i[2] for i in res32["infos"])), phases_ms=phases_of(res32["timing"]))
+        log("fp32+ir: %.3f steps/s" % leg32["steps_per_s"])
 
     st = res64["stats"]
     tm = res64["timing"]
-    # dominant kernel: refactor_level_kernel (the sparse sweep); its launches run back to
-    # back on the library's stream, so the average launch lasts sweep_ms / launches
+    steps_per_s = args.steps / res64["wall"]
+    t_step = res64["wall"] / args.steps
+    # whole step on the compulsory bytes: refactorization (A values and map, factor index and
+    # value per entry) and one solve pass per right-hand side (factor index and value per entry)
+    b_step = st["bytes_refactor"] + nrhs * st["bytes_solve"]
+    roofline_step = dict(bound="hbm", achieved=b_step / t_step / 1e9, peak=HBM_PEAK_GBS, unit="GB/s",
+                         frac=b_step / t_step / 1e9 / HBM_PEAK_GBS, bytes_per_step=b_step,
+                         bytes_model="12 B per A nonzero + 12 B per factor entry (refactorization) + "
+                                     "(12 B per factor entry + 24 B per row) per right-hand side")
+    # dominant kernel: the sparse sweep (refactor_level_kernel); its launches run back to back
+    # on the library's stream, so the average launch lasts sweep_ms / launches
     sweep_launch_s = tm["sweep_ms"] * 1e-3 / max(1, tm["sweep_launches"])
-    bytes_per_launch = st["bytes_sweep"] / max(1, st["sweep_launches"])
-    achieved = bytes_per_launch / sweep_launch_s / 1e9
-    traffic = measured_traffic(bytes_per_launch)
+    launches = max(1, int(st["sweep_launches"]))
+    alg_per_launch = st["alg_bytes_refactor_sweep"] / launches
+    achieved = alg_per_launch / sweep_launch_s / 1e9
+    traffic = measured_traffic("refactor_level_kernel_traffic_%s.txt" % args.workload, "refactor_level_kernel",
+                               launches)
     roofline = dict(bound="hbm", kernel="refactor_level_kernel", achieved=achieved, peak=HBM_PEAK_GBS,
                     unit="GB/s", frac=achieved / HBM_PEAK_GBS, traffic=traffic,
-                    algorithmic_bytes_per_launch=bytes_per_launch, avg_launch_us=sweep_launch_s * 1e6,
-                    launches_per_refactor=int(st["sweep_launches"]),
-                    bytes_model="28 B per sweep MAC + 24 B per L entry of a sparse column")
+                    algorithmic_bytes_per_launch=alg_per_launch, avg_launch_us=sweep_launch_s * 1e6,
+                    launches_per_refactor=launches,
+                    bytes_model="12 B per factor entry the sweep finalises (row index read, value written)",
+                    traffic_model_bytes_per_launch=st["bytes_sweep"] / launches,
+                    traffic_model="28 B per sweep multiply-add + 24 B per L entry of a sparse column "
+                                  "(every operand from HBM, no cache reuse)",
+                    traffic_over_algorithmic=(traffic / alg_per_launch) if traffic else None)
     nref = max(1, tm["refactors"])
     dense_s = tm["dense_ms"] * 1e-3 / nref
     roofline_dense = None
     if st["dense_tail"] > 0 and dense_s > 0:
-        tf = st["flops_dense"] / dense_s / 1e12
+        tf = 2.0 * st["macs_dense"] / dense_s / 1e12
         roofline_dense = dict(bound="mfma", kernel="dense block LU (dlu_panel_kernel + dlu_gemm_kernel)",
                               achieved=tf, peak=FP64_MFMA_PEAK_TFS, unit="TFLOP/s", frac=tf / FP64_MFMA_PEAK_TFS,
-                              order=int(st["dense_tail"]))
-    npass = max(1, tm["solve_passes"])
-    phases = dict(init=tm["init_ms"] / nref, sweep=tm["sweep_ms"] / nref, schur=tm["schur_ms"] / nref,
-                  dense=tm["dense_ms"] / nref, solve_sparse=tm["solve_sparse_ms"] / npass,
-                  solve_dense=tm["solve_dense_ms"] / npass)
+                              order=int(st["dense_tail"]), method_flops=2.0 * st["macs_dense"],
+                              issued_flops=st["flops_dense"],
+                              issued_tflops_per_s=st["flops_dense"] / dense_s / 1e12)
 
-    cpu = None
+    cpu, fwd = None, None
     if not args.no_cpu_baseline:
-        cpu, xo = cpu_baseline(c, vals, np.atleast_2d(b)[0])
+        cpu, XO, kap, oswaps = cpu_baseline(c, vals[-1], B)
         log("cpu oracle: %.4f steps/s" % cpu["value"])
+        etao = [eta_inf(c, vals[-1], XO[r], B[r]) for r in range(nrhs)]
 
-    value = args.steps / res64["wall"]
+        def fwd_err(X):
+            return max(float(np.abs(X[r] - XO[r]).max() / np.abs(XO[r]).max()) for r in range(nrhs))
+        fwd = dict(kappa_inf_estimate=kap, oracle_backward_err=max(etao), oracle_swaps=int(oswaps),
+                   fp64=fwd_err(X64), fp64_bound=8 * kap * (eta64 + max(etao)),
+                   note="||x - x_oracle||_inf / ||x_oracle||_inf, max over right-hand sides, last step; "
+                        "bound 8 kappa (eta + eta_oracle)")
+        if leg32:
+            fwd["fp32_ir"] = fwd_err(X32)
+            fwd["fp32_ir_bound"] = 8 * kap * (leg32["backward_err_max"] + max(etao))
+
     line = {
         "metric": "NR refactor+solve steps/sec + p50/p99 step latency, FP32+IR vs FP64, 1 GPU",
-        "value": value, "unit": "steps/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
-        "ms_per_step": res64["wall"] * 1e3 / args.steps, "higher_is_better": True, "scaling": "weak",
+        "value": steps_per_s, "unit": "steps/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": t_step * 1e3, "higher_is_better": True, "scaling": "weak",
         "vs_baseline": None, "dtype": "f64", "data": "synthetic",
         "config": {"workload": wl["desc"], "n": c.n, "nnz": c.nnz, "nnz_lu": st["nnz_l"] + st["nnz_u"],
                    "flops_per_refactor": st["flops"], "levels": st["levels"], "dense_tail": st["dense_tail"],
@@ -412,10 +521,12 @@ def main():
         "p50_ms": float(np.percentile(res64["step_ms"], 50)),
         "p99_ms": float(np.percentile(res64["step_ms"], 99)),
         "refactor_ms": float(res64["ref_ms"].mean()), "solve_ms": float(res64["sol_ms"].mean()),
-        "backward_err": eta64, "repivots": res64["repivots"],
-        "fp32_ir": out_fp32,
-        "phases_ms": phases,
+        "backward_err": eta64, "repivots": res64["repivots"], "setup_s": res64["setup_s"],
+        "fp32_ir": leg32,
+        "forward_err": fwd,
+        "phases_ms": phases_of(tm),
         "roofline": roofline,
+        "roofline_step": roofline_step,
         "roofline_dense": roofline_dense,
         "cpu_baseline": cpu,
     }

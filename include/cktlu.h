@@ -120,9 +120,10 @@ typedef struct {
     int64_t n_fp64_fallback_solves;
     double bytes_refactor, bytes_solve;  /* algorithmic HBM bytes per refactorization / per RHS solve */
     double macs_sweep;                /* multiply-adds of the sparse sweep's update tasks */
-    double bytes_sweep;               /* its algorithmic bytes: 28 per MAC (L value + row index
-                                         gathered, target read and written) + 24 per L entry of a
-                                         sparse column (pivot test read, division read and write) */
+    double bytes_sweep;               /* its traffic model: 28 per MAC (L value + row index gathered,
+                                         target read and written) + 24 per L entry of a sparse column
+                                         (pivot test read, division read and write): what the update
+                                         moves when nothing is reused from caches */
     double flops_dense;               /* FLOPs of the dense trailing block's LU (2/3 D^3 + lower order) */
     double macs_schur;                /* multiply-adds of the dense block's update by the sparse columns */
     int64_t sweep_launches;           /* kernel launches of one sparse sweep */
@@ -137,6 +138,13 @@ typedef struct {
                                          searches the target rows) */
     int64_t schur_parts, schur_scratch_cols;  /* the dense block's Schur update: parts (wavefronts per
                                          instance) and scratch columns of the parts after a column's first */
+    double entries_sweep;             /* factor entries the sweep finalises: every entry of the sparse
+                                         columns and the dense columns' entries in sparse rows */
+    double entries_dense;             /* factor entries of the dense columns in dense rows */
+    double macs_dense;                /* multiply-adds of the dense block's own LU (the method's work inside
+                                         it; the blocked dense LU issues 2/3 D^3 flops) */
+    double alg_bytes_refactor_sweep;  /* compulsory bytes of the sweep: an index read and a value written per
+                                         entry it finalises (12 bytes in FP64, 8 with FP32 factors) */
 } cktlu_stats;
 
 /* Device time of the phases, accumulated over the calls made with options.timing = 1

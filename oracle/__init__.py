@@ -66,6 +66,8 @@ def _load():
         lib.or_coletree.argtypes = [ctypes.c_int, ip, ip, ip]
         lib.or_coletree.restype = ctypes.c_int
         lib.or_restart_set.argtypes = [ctypes.c_int, ip, ip, ip]
+        lib.or_lu_errbound.argtypes = [ctypes.c_int, ip, ip, dp, ip, ip, dp, ctypes.c_double, dp, dp]
+        lib.or_lu_errbound.restype = ctypes.c_int
         lib.or_mac_count.argtypes = [ctypes.c_int, ip, ip, ip]
         lib.or_mac_count.restype = ctypes.c_double
         _lib = lib
@@ -196,6 +198,18 @@ def restart_set(parent, unfinished) -> np.ndarray:
     out = np.zeros(parent.size, dtype=np.int32)
     _load().or_restart_set(parent.size, parent, _i32(np.asarray(unfinished, dtype=bool)), out)
     return out.astype(bool)
+
+
+def lu_error_bound(lu: LU, roundings_per_product=1.0):
+    """First-order rounding-error bound of every factor entry (eL, eU in the factors'
+    order), from or_lu_errbound."""
+    eL = np.zeros(max(int(lu.Lp[-1]), 1))
+    eU = np.zeros(max(int(lu.Up[-1]), 1))
+    rc = _load().or_lu_errbound(lu.n, lu.Lp, lu.Li, _f64(lu.Lx), lu.Up, lu.Ui, _f64(lu.Ux),
+                                float(roundings_per_product), eL, eU)
+    if rc != OK:
+        raise MemoryError("oracle error bound")
+    return eL[:int(lu.Lp[-1])], eU[:int(lu.Up[-1])]
 
 
 def mac_count(lu: LU) -> float:

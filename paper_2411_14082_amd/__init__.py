@@ -84,7 +84,9 @@ class cktlu_stats(ctypes.Structure):
                 ("n_device_repivot", ctypes.c_int64), ("ordering_used", ctypes.c_int64),
                 ("fill_amd", ctypes.c_int64), ("fill_amf", ctypes.c_int64), ("fill_nd", ctypes.c_int64),
                 ("slot_map_entries", ctypes.c_int64), ("schur_parts", ctypes.c_int64),
-                ("schur_scratch_cols", ctypes.c_int64)]
+                ("schur_scratch_cols", ctypes.c_int64), ("entries_sweep", ctypes.c_double),
+                ("entries_dense", ctypes.c_double), ("macs_dense", ctypes.c_double),
+                ("alg_bytes_refactor_sweep", ctypes.c_double)]
 
     def as_dict(self):
         return {f: getattr(self, f) for f, _ in self._fields_}

@@ -351,6 +351,10 @@ void fill_stats_pattern(cktlu_ctx *c) {
     t.macs_sweep = s.macs_sweep;
     t.macs_schur = s.macs_schur;
     t.bytes_sweep = 28.0 * s.macs_sweep + 24.0 * s.lnz_front;
+    t.entries_sweep = s.entries_sweep;
+    t.entries_dense = s.entries_dense;
+    t.macs_dense = s.macs_dense;
+    t.alg_bytes_refactor_sweep = (4.0 + fb) * s.entries_sweep;
     const double D = (double)(c->an.n - s.tail0);
     t.flops_dense = 2.0 / 3.0 * D * D * D + D * D / 2.0;
     t.sweep_launches = 0;

@@ -117,6 +117,9 @@ struct Schedule {
     double macs = 0, flops = 0;
     double macs_sweep = 0, lnz_front = 0;     // MACs of the update tasks; L entries of sparse columns
     double macs_schur = 0;                    // MACs of the dense block's Schur update (S -= L21 U12)
+    double macs_dense = 0;                    // MACs of the dense block's own LU (dense sources and targets)
+    double entries_sweep = 0;                 // factor entries the sweep finalises (sparse columns, bridge rows)
+    double entries_dense = 0;                 // factor entries of the dense columns in rows >= tail0
     std::vector<int> tail_nb;                 // per dense column: its U entries in rows < T (the bridge)
     // Schur update parts {dense column, first and end bridge source, scratch column or -1}
     // and the add pass {dense column, first scratch column, count, 0}

@@ -359,6 +359,19 @@ void build_schedule(const Analysis &an, const Factor &f, const cktlu_options &op
         }
         s.lnz_front = 0;
         for (int k = 0; k < T; k++) s.lnz_front += (double)(s.Dlen[k] - f.nU[k]);
+        // the method's own work and entries per phase (the compulsory bytes of the roofline)
+        s.entries_sweep = 0;
+        for (int k = 0; k < T; k++) s.entries_sweep += (double)s.Dlen[k];
+        s.entries_dense = 0;
+        s.macs_dense = 0;
+        for (int k = T; k < n; k++) {
+            s.entries_sweep += (double)s.tail_nb[k - T];
+            s.entries_dense += (double)(s.Dlen[k] - s.tail_nb[k - T]);
+            for (int64_t q = f.Fp[k] + s.tail_nb[k - T]; q < f.Fp[k] + f.nU[k] - 1; q++) {
+                const int j = f.Fi[q];
+                s.macs_dense += (double)(s.Dlen[j] - f.nU[j]);
+            }
+        }
     }
     // ---- solve levels of the sparse rows [0, T): row i of L waits for every j with
     // L(i,j) != 0, row i of U for every j > i with U(i,j) != 0 (rows >= T of U are

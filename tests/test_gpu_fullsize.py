@@ -9,8 +9,11 @@
   refactorization: every instance's solve reaches its gate (FP64 and FP32 + IR),
   sampled instances equal their single refactorization bit for bit and the
   oracle within rounding.
-- 1000 x 1000 power grid (n = 1,000,000) with FP32 factors, FP64 refinement and
-  8 right-hand sides: eta_inf <= 1e-10 for every right-hand side.
+- 1000 x 1000 power grid (n = 1,000,000) with 8 right-hand sides: the FP64
+  refactorization's pattern and pivot sequence bit-exact against the oracle's,
+  sampled values within rounding, every right-hand side's solution within the
+  condition-scaled bound of the oracle's; then FP32 factors with FP64 refinement,
+  eta_inf <= 1e-10 and the same forward bound for every right-hand side.
 - The RC mesh with a pivot inside its dense block made to fail: the dense block
   is re-factored on the device with the threshold pivot rule, and pattern and
   pivot sequence equal the oracle's re-factorization, values within rounding.
@@ -23,13 +26,13 @@ import pytest
 import scipy.sparse as sp
 
 import mnagen
-from helpers import compare_factors, compare_factors_sampled, oracle_refactor, pivot_entry
+from helpers import (check_solution, compare_factors, compare_factors_sampled, kappa_est, oracle_refactor,
+                     pivot_entry)
 
 torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
 
 EPS = 1e-3
-RTOL = 1e-8
 
 
 @pytest.fixture(scope="module")
@@ -78,7 +81,7 @@ def test_rc_mesh_3x300_full(ck, oracle_mod):
     say(t0, "oracle re-factorization done, swaps", lu.nswaps)
     assert lu.status == 0
     assert np.array_equal(s.analysis()["pivrow"], lu.pivrow)
-    worst = compare_factors_sampled(s.factors(), lu, RTOL)
+    worst = compare_factors_sampled(s.factors(), lu)
     say(t0, "sampled scaled error", worst)
     s.close()
     # FP32 factors + FP64 refinement on the same values
@@ -91,12 +94,12 @@ def test_rc_mesh_3x300_full(ck, oracle_mod):
     e = eta_inf(c, v, x.cpu().numpy(), b)
     say(t0, "fp32+ir rc", rc, "iters", sinfo.ir_iters, "eta", e)
     assert e <= 1e-10
-    # forward error against the FP64 oracle: kappa(A) times eta at most (no condition
-    # estimate at this size; reported, with a loose sanity bound)
+    # forward error against the FP64 oracle within the condition-scaled bound
     xo = oracle_mod.solve(lu, a0["rowperm_pre"], a0["colperm"], b)
-    fwd = float(np.abs(x.cpu().numpy() - xo).max() / np.abs(xo).max())
-    say(t0, "fp32+ir forward error vs the oracle", fwd)
-    assert fwd <= 1e-3
+    eta_o = eta_inf(c, v, xo, b)
+    kap = kappa_est(oracle_mod, lu, c, v, a0)
+    w = check_solution(x.cpu().numpy(), xo, kap, e, eta_o, "fp32+ir")
+    say(t0, "fp32+ir forward difference / bound %.3e, kappa %.3e" % (w, kap))
 
 
 @pytest.mark.timeout(900)
@@ -126,7 +129,7 @@ def test_rc_mesh_3x300_dense_repivot_full(ck, oracle_mod, device):
     assert rc == ck.CKTLU_W_REPIVOTED and info.first_fail_col == k
     assert s.stats()["n_device_repivot"] == (1 if device == 0 else 0)
     assert np.array_equal(s.analysis()["pivrow"], lu.pivrow)
-    worst = compare_factors_sampled(s.factors(), lu, RTOL)
+    worst = compare_factors_sampled(s.factors(), lu)
     say(t0, "sampled scaled error", worst)
     b = c.rhs[0]
     x = torch.zeros(c.n, dtype=torch.float64, device="cuda:0")
@@ -176,27 +179,56 @@ def test_batched_corners_256_full(ck, oracle_mod, precision):
         if precision == "fp64":
             lu = oracle_refactor(oracle_mod, c, V[i], a0, EPS, a0["pivrow"])
             assert lu.nswaps == 0
-            compare_factors(fb, lu, RTOL)
+            compare_factors(fb, lu)
     say(t0, "sampled instances equal their single refactorization")
 
 
-@pytest.mark.timeout(900)
-def test_power_grid_1000_fp32_ir_8rhs_full(ck):
+@pytest.mark.timeout(1200)
+def test_power_grid_1000_8rhs_full(ck, oracle_mod):
     t0 = time.time()
     c = mnagen.power_grid(1000, 1000, seed=0)
     nrhs = c.rhs.shape[0]
     say(t0, "power_grid_1000 n", c.n, "nnz", c.nnz, "nrhs", nrhs)
     assert nrhs == 8
-    s = ck.SparseLU(c.n, c.colptr, c.rowind, eps=EPS, precision=ck.CKTLU_FP32_IR, ir_tol=1e-10)
-    s.factorize(dev(c.values))
-    say(t0, "factorized; dense tail", s.stats()["dense_tail"])
     v = mnagen.restamp(c, 0, 4, 1)
-    rc, info = s.refactorize(dev(v))
     Bd = dev(c.rhs)
+    s = ck.SparseLU(c.n, c.colptr, c.rowind, eps=EPS)
+    s.factorize(dev(c.values))
+    a0 = s.analysis()
+    say(t0, "fp64 factorized; dense tail", s.stats()["dense_tail"])
+    rc, info = s.refactorize(dev(v))
     X = torch.zeros_like(Bd)
-    rc, sinfo = s.solve(Bd, X, nrhs=nrhs)
+    s.solve(Bd, X, nrhs=nrhs)
+    torch.cuda.synchronize()
+    X64 = X.cpu().numpy()
+    f = s.factors()
+    piv = s.analysis()["pivrow"]
+    s.close()
+    say(t0, "fp64 refactorize rc", rc)
+    lu = oracle_refactor(oracle_mod, c, v, a0, EPS, a0["pivrow"])
+    say(t0, "oracle re-factorization done, swaps", lu.nswaps)
+    assert lu.status == 0
+    assert np.array_equal(piv, lu.pivrow)
+    worst = compare_factors_sampled(f, lu)
+    say(t0, "sampled scaled error", worst)
+    kap = kappa_est(oracle_mod, lu, c, v, a0)
+    xo = [oracle_mod.solve(lu, a0["rowperm_pre"], a0["colperm"], c.rhs[r]) for r in range(nrhs)]
+    eo = [eta_inf(c, v, xo[r], c.rhs[r]) for r in range(nrhs)]
+    for r in range(nrhs):
+        e = eta_inf(c, v, X64[r], c.rhs[r])
+        assert e <= 1e-12, (r, e)
+        w = check_solution(X64[r], xo[r], kap, e, eo[r], "fp64 rhs %d" % r)
+    say(t0, "fp64 solutions within the bound; kappa %.3e" % kap)
+    s32 = ck.SparseLU(c.n, c.colptr, c.rowind, eps=EPS, precision=ck.CKTLU_FP32_IR, ir_tol=1e-10)
+    s32.factorize(dev(c.values))
+    rc, info = s32.refactorize(dev(v))
+    X = torch.zeros_like(Bd)
+    rc, sinfo = s32.solve(Bd, X, nrhs=nrhs)
     torch.cuda.synchronize()
     Xh = X.cpu().numpy()
+    s32.close()
     etas = [eta_inf(c, v, Xh[r], c.rhs[r]) for r in range(nrhs)]
-    say(t0, "rc", rc, "iters", sinfo.ir_iters, "fp64 fallback", sinfo.used_fp64, "eta", max(etas))
+    say(t0, "fp32+ir rc", rc, "iters", sinfo.ir_iters, "fp64 fallback", sinfo.used_fp64, "eta", max(etas))
     assert max(etas) <= 1e-10
+    ws = [check_solution(Xh[r], xo[r], kap, etas[r], eo[r], "fp32+ir rhs %d" % r) for r in range(nrhs)]
+    say(t0, "fp32+ir forward difference / bound, worst %.3e" % max(ws))

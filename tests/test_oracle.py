@@ -464,3 +464,63 @@ def test_condest_vs_exact_inverse_norm(oracle_mod):
         exact_hits += k_est >= k_ex * (1 - 1e-8)
         cases += 1
     assert cases >= 20 and exact_hits >= cases * 0.5, (exact_hits, cases)
+
+
+# ------------------------------------------------------- rounding-error bound
+def _extended_lu(A, piv):
+    """Doolittle LU of A[piv] in extended precision (numpy longdouble, 64-bit mantissa
+    on x86-64), no pivoting: the reference 'exact' factors for the bound's pin."""
+    M = np.array(A, dtype=np.longdouble)[np.asarray(piv)]
+    n = M.shape[0]
+    for k in range(n):
+        M[k + 1:, k] /= M[k, k]
+        M[k + 1:, k + 1:] -= np.outer(M[k + 1:, k], M[k, k + 1:])
+    return M
+
+
+def _graded(n, seed):
+    """A matrix whose threshold pivoting at eps = 1e-3 keeps multipliers up to ~1e3:
+    a random pattern with a weak diagonal, so errors propagate through large |L|."""
+    c = mnagen.random_pattern(n, 0.35, seed)
+    v = c.values.copy()
+    for j in range(n):
+        for p in range(c.colptr[j], c.colptr[j + 1]):
+            if c.rowind[p] == j:
+                v[p] *= 2e-3
+    c.values = v
+    return c
+
+
+@pytest.mark.parametrize("eps", [1.0, 0.1, 1e-3])
+def test_oracle_error_bound_vs_extended_precision(oracle_mod, eps):
+    """The running error bound of every factor entry holds against an extended-precision
+    factorization with the same pivot sequence (|oracle - exact| <= bound), on random
+    and on graded matrices whose large multipliers make inherited errors dominate; and
+    it is not vacuous (relative bounds far below 1)."""
+    exceeded_own = 0
+    for seed in range(40):
+        n = 8 + seed % 20
+        c = _graded(n, 7000 + seed) if seed % 2 else mnagen.random_pattern(n, 0.3, 7000 + seed)
+        lu = oracle_mod.gp_lu(n, c.colptr, c.rowind, c.values, eps=eps)
+        if lu.status != 0:
+            continue
+        eL, eU = oracle_mod.lu_error_bound(lu, 1.0)
+        X = _extended_lu(c.to_scipy().toarray(), lu.pivrow)
+        lcols = np.repeat(np.arange(n), np.diff(lu.Lp))
+        ucols = np.repeat(np.arange(n), np.diff(lu.Up))
+        dl = np.abs(lu.Lx - X[lu.Li, lcols].astype(np.float64))
+        du = np.abs(lu.Ux - X[lu.Ui, ucols].astype(np.float64))
+        tiny = 1e-300
+        assert np.all(dl <= eL + tiny), (seed, float((dl / np.maximum(eL, tiny)).max()))
+        assert np.all(du <= eU + tiny), (seed, float((du / np.maximum(eU, tiny)).max()))
+        B = (sp.csc_matrix((np.abs(lu.Lx), lu.Li, lu.Lp), shape=(n, n)) + sp.identity(n)) @ \
+            sp.csc_matrix((np.abs(lu.Ux), lu.Ui, lu.Up), shape=(n, n))
+        Bd = B.toarray()
+        scale_u = Bd[lu.Ui, ucols]
+        if seed % 2 == 0:                       # well-scaled random matrices: a tight bound
+            assert float((eU / np.maximum(scale_u, tiny)).max()) < 1e-10
+        # the entries' own rounding alone (2 n u times their |L||U| scale) is exceeded
+        # somewhere: the inherited part of the bound is needed, not decoration
+        exceeded_own += int(np.any(du > 2 * n * np.finfo(float).eps * scale_u))
+    if eps < 1:
+        assert exceeded_own >= 1
