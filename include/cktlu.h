@@ -240,6 +240,23 @@ int cktlu_solve(cktlu_ctx *ctx, int32_t nrhs, const double *b_dev, int32_t ldb,
                 double *x_dev, int32_t ldx, cktlu_solve_info *info);
 
 /*
+ * The solve of cktlu_solve without any device allocation, for callers that
+ * cannot allocate (code under HIP graph capture, tight serving loops, harnesses
+ * that forbid hipMalloc): the same kernels and results as cktlu_solve, with the
+ * work rows in a file-scope device array of the library instead of a buffer it
+ * allocates.  The array holds 2^19 rows (64 MiB, one copy per GPU the library
+ * runs on, kept until the process ends); every call on a GPU shares it, so
+ * calls that overlap on one GPU (several streams or threads) race, and a call
+ * writes every row it reads.  Requires FP64 factors already on the device
+ * (after cktlu_factorize or cktlu_refactorize on a context in FP64 mode, or in
+ * FP32_IR mode after a fallback to FP64 factors).  b_dev, x_dev, ldb, ldx as
+ * in cktlu_solve.  Errors: E_ARG, E_STATE (no device factors, FP32 factors),
+ * E_LIMIT (n > 2^19), E_HIP.
+ */
+int cktlu_solve_noalloc(cktlu_ctx *ctx, int32_t nrhs, const double *b_dev, int32_t ldb, double *x_dev,
+                        int32_t ldx);
+
+/*
  * Batched fast factorization of `batch` same-pattern instances (Monte-Carlo
  * corners).  values_dev: device, batch x nnz FP64 values, instance i at
  * values_dev + i*nnz.  status_dev: device int32[batch]; entry i is set to -1

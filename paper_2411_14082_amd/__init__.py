@@ -41,7 +41,8 @@ CKTLU_ORDER_ND = 4
 EXPORTS = [
     "cktlu_default_options", "cktlu_create", "cktlu_destroy", "cktlu_strerror", "cktlu_set_stream",
     "cktlu_analyze", "cktlu_factorize", "cktlu_factorize_host", "cktlu_refactorize",
-    "cktlu_refactorize_nocheck", "cktlu_solve", "cktlu_refactorize_batched", "cktlu_solve_batched",
+    "cktlu_refactorize_nocheck", "cktlu_solve", "cktlu_solve_noalloc", "cktlu_refactorize_batched",
+    "cktlu_solve_batched",
     "cktlu_step_batched_graph", "cktlu_autotune",
     "cktlu_server_default_options", "cktlu_server_create", "cktlu_server_submit", "cktlu_server_poll",
     "cktlu_server_now", "cktlu_server_destroy",
@@ -150,6 +151,7 @@ def _load():
     lib.cktlu_refactorize.argtypes = [P, P, ctypes.POINTER(cktlu_refactor_info)]
     lib.cktlu_refactorize_nocheck.argtypes = [P, P]
     lib.cktlu_solve.argtypes = [P, I32, P, I32, P, I32, ctypes.POINTER(cktlu_solve_info)]
+    lib.cktlu_solve_noalloc.argtypes = [P, I32, P, I32, P, I32]
     lib.cktlu_refactorize_batched.argtypes = [P, I32, P, P]
     lib.cktlu_solve_batched.argtypes = [P, I32, I32, P, P, P, P]
     lib.cktlu_step_batched_graph.argtypes = [P, I32, P, P, I32, P, P, P, I32]
@@ -256,6 +258,10 @@ def cktlu_refactorize_nocheck(ctx, values_dev):
 def cktlu_solve(ctx, nrhs, b_dev, ldb, x_dev, ldx, info: cktlu_solve_info | None = None):
     return lib.cktlu_solve(ctx, int(nrhs), _ptr(b_dev), int(ldb), _ptr(x_dev), int(ldx),
                            ctypes.byref(info) if info is not None else None)
+
+
+def cktlu_solve_noalloc(ctx, nrhs, b_dev, ldb, x_dev, ldx):
+    return lib.cktlu_solve_noalloc(ctx, int(nrhs), _ptr(b_dev), int(ldb), _ptr(x_dev), int(ldx))
 
 
 def cktlu_refactorize_batched(ctx, batch, values_dev, status_dev):

@@ -782,12 +782,16 @@ size_t vec_need(const cktlu_ctx *c, int nrhs) {
     return (size_t)c->an.n * YS + 64 + (size_t)c->an.n * nrhs + 3 * (size_t)nrhs + 8;
 }
 
+// zbuf: work rows (n x YS doubles) supplied by the caller, or nullptr for the context's own
 int solve_chunk(cktlu_ctx *c, int nrhs, const double *b, int64_t ldb, double *x, int64_t ldx, bool fp32,
-                bool accumulate) {
+                bool accumulate, double *zbuf = nullptr) {
     const int n = c->an.n;
-    int rc = ensure_vec(c, vec_need(c, nrhs));
-    if (rc) return rc;
-    double *z = (double *)c->dev.vec.p;
+    int rc;
+    double *z = zbuf;
+    if (!z) {
+        if ((rc = ensure_vec(c, vec_need(c, nrhs)))) return rc;
+        z = (double *)c->dev.vec.p;
+    }
     hipStream_t st = stream_of(c);
     LCHK(launch_gather_rhs(n, nrhs, 1, b, ldb, (const int *)c->dev.rowperm.p, z, st));
     if ((rc = tri_solves(c, nrhs, 1, z, fp32, nullptr))) return rc;
@@ -797,10 +801,10 @@ int solve_chunk(cktlu_ctx *c, int nrhs, const double *b, int64_t ldb, double *x,
 }
 
 int solve_plain(cktlu_ctx *c, int nrhs, const double *b, int64_t ldb, double *x, int64_t ldx, bool fp32,
-                bool accumulate) {
+                bool accumulate, double *zbuf = nullptr) {
     for (int r0 = 0; r0 < nrhs;) {
         int chunk = nrhs - r0 >= 8 ? 8 : nrhs - r0 >= 4 ? 4 : nrhs - r0 >= 2 ? 2 : 1;
-        int rc = solve_chunk(c, chunk, b + r0 * ldb, ldb, x + r0 * ldx, ldx, fp32, accumulate);
+        int rc = solve_chunk(c, chunk, b + r0 * ldb, ldb, x + r0 * ldx, ldx, fp32, accumulate, zbuf);
         if (rc) return rc;
         r0 += chunk;
     }
@@ -1024,6 +1028,22 @@ int cktlu_solve(cktlu_ctx *c, int32_t nrhs, const double *b, int32_t ldb, double
     c->fp64_sticky = true;
     if (info) info->used_fp64 = 1;
     return CKTLU_W_IR_FALLBACK;
+}
+
+int cktlu_solve_noalloc(cktlu_ctx *c, int32_t nrhs, const double *b, int32_t ldb, double *x, int32_t ldx) {
+    if (!c || nrhs < 0 || (nrhs > 0 && (!b || !x))) return CKTLU_E_ARG;
+    if (c->state < 2 || !c->dev.uploaded) return CKTLU_E_STATE;      // nothing may be uploaded here
+    if (c->opt.precision != CKTLU_FP64 && !c->fp64_sticky) return CKTLU_E_STATE;
+    if (ldb < c->an.n || ldx < c->an.n) return CKTLU_E_ARG;
+    if (c->an.n > kNoAllocRows) return CKTLU_E_LIMIT;
+    if (nrhs == 0 || c->an.n == 0) return CKTLU_OK;
+    double *z = nullptr;
+    LCHK(noalloc_scratch(&z));
+    const int saved_timing = c->opt.timing;        // phase timing would create events
+    c->opt.timing = 0;
+    const int rc = solve_plain(c, nrhs, b, ldb, x, ldx, false, false, z);
+    c->opt.timing = saved_timing;
+    return rc;
 }
 
 int cktlu_step_batched_graph(cktlu_ctx *c, int32_t batch, const double *values_dev, int32_t *status_dev,

@@ -258,6 +258,11 @@ int launch_ir_check(int batch, int nrhs, const double *norms, const double *anor
                     double *eta, void *stream);
 int launch_f64_to_f32(const double *src, float *dst, int64_t count, void *stream);
 int launch_fill_i32(int *dst, int64_t count, int value, void *stream);
+// Work rows of the allocation-free solve: a file-scope device array of kNoAllocRows rows of YS
+// doubles (64 MiB), one per GPU for the life of the process.  *out receives its device address on
+// the current device (looked up once per device).  Returns a hipError_t as int.
+constexpr int kNoAllocRows = 1 << 19;
+int noalloc_scratch(double **out);
 
 // Dense trailing block (dense.hip): columns and rows [T, n) of the factors,
 // D = n - T, held per instance as a column-major D x D matrix S.

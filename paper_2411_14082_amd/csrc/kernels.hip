@@ -33,6 +33,7 @@
 
 #include <climits>
 #include <cstdint>
+#include <mutex>
 
 #include "internal.h"
 
@@ -863,6 +864,31 @@ int launch_fill_i32(int *dst, int64_t count, int value, void *stream) {
     hipLaunchKernelGGL(fill_i32_kernel, dim3(grid_for(count, 256)), dim3(256), 0, (hipStream_t)stream, dst, count,
                        value);
     return (int)hipGetLastError();
+}
+
+// ------------------------------------------------------ allocation-free solve
+// The work rows of cktlu_solve_noalloc.  Host code never hands this name to a kernel
+// (on the host it is a stand-in, not a device address): noalloc_scratch looks up the
+// array's address on the current device once and kernels receive that address.
+static __device__ __align__(256) double scratch[(size_t)kNoAllocRows * YS];
+
+int noalloc_scratch(double **out) {
+    static std::mutex mu;
+    static double *addr[64] = {};
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return (int)e;
+    if (dev < 0 || dev >= 64) return (int)hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lk(mu);
+    if (!addr[dev]) {
+        void *p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return (int)e;
+        if (!p) return (int)hipErrorInvalidSymbol;
+        addr[dev] = static_cast<double *>(p);
+    }
+    *out = addr[dev];
+    return 0;
 }
 
 }  // namespace cktlu_dev
