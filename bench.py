@@ -229,6 +229,7 @@ def lu_options(ck, tail_opts):
     kw = {k: v for k, v in tail_opts.items() if k not in ("autotune", "ordering") and v is not None}
     if tail_opts.get("ordering"):
         kw["ordering"] = {"amd": ck.CKTLU_ORDER_AMD, "amf": ck.CKTLU_ORDER_AMF, "nd": ck.CKTLU_ORDER_ND,
+                          "ndc": ck.CKTLU_ORDER_ND_CAMD,
                           "auto": ck.CKTLU_ORDER_AUTO, "natural": ck.CKTLU_ORDER_NATURAL}[tail_opts["ordering"]]
     return kw
 
@@ -378,7 +379,7 @@ def main():
                     help="order of the dense trailing block: 0 automatic (default), -1 none, >0 forced")
     ap.add_argument("--dense-density", type=float, default=None,
                     help="fill density threshold of the automatic dense-block choice")
-    ap.add_argument("--ordering", default=None, choices=["amd", "amf", "nd", "auto", "natural"],
+    ap.add_argument("--ordering", default=None, choices=["amd", "amf", "nd", "ndc", "auto", "natural"],
                     help="fill-reducing ordering of analyze (default: the library's)")
     ap.add_argument("--dense-panel-width", type=int, default=None,
                     help="dense block: columns factored between trailing-block updates (64, 128, 256)")
@@ -515,7 +516,7 @@ def main():
         "vs_baseline": None, "dtype": "f64", "data": "synthetic",
         "config": {"workload": wl["desc"], "n": c.n, "nnz": c.nnz, "nnz_lu": st["nnz_l"] + st["nnz_u"],
                    "flops_per_refactor": st["flops"], "levels": st["levels"], "dense_tail": st["dense_tail"],
-                   "nrhs": nrhs, "ordering": ["amd", "natural", "amf", "auto", "nd"][int(st.get("ordering_used", 0))],
+                   "nrhs": nrhs, "ordering": ["amd", "natural", "amf", "auto", "nd", "nd+camd"][int(st.get("ordering_used", 0))],
                    "slot_map_entries": int(st.get("slot_map_entries", 0)),
                    "value_perturbation": "+-5%% per %s" % args.perturb},
         "p50_ms": float(np.percentile(res64["step_ms"], 50)),

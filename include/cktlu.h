@@ -54,9 +54,13 @@ extern "C" {
 #define CKTLU_ORDER_AMD 0       /* approximate minimum degree on the pattern of B + B' */
 #define CKTLU_ORDER_NATURAL 1   /* keep the (transversal-permuted) natural order */
 #define CKTLU_ORDER_AMF 2       /* approximate minimum fill on the pattern of B + B' */
-#define CKTLU_ORDER_AUTO 3      /* AMD, AMF and ND; keep the one whose symbolic Cholesky of B + B' has the
-                                   fewest entries (ties: the earlier), the combined ordering of Section III-A */
+#define CKTLU_ORDER_AUTO 3      /* AMD, AMF, ND and ND + constrained AMD; keep the one whose symbolic Cholesky of
+                                   B + B' has the fewest entries (ties: the earlier), the combined ordering of
+                                   Section III-A */
 #define CKTLU_ORDER_ND 4        /* nested dissection (level-set separators), AMD on parts of <= 4096 nodes */
+#define CKTLU_ORDER_ND_CAMD 5   /* the same dissection stopped at its parts, then one constrained minimum degree
+                                   over the whole pattern that eliminates the parts in the dissection's order
+                                   (Section III-A) */
 
 typedef struct cktlu_ctx cktlu_ctx;
 
@@ -94,6 +98,17 @@ typedef struct {
                               and the map takes at most a quarter of its free HBM (autotuner trials: at most
                               2^30 entries).  The sweep then loads the slot instead of searching the target's
                               rows; results are bit-identical.  -1 = never */
+    int sweep_supernodes;  /* 0 (default): the sweep runs on supernodes of up to 64 columns (runs of columns
+                              with a dense diagonal block and shared rows below it): per dependency level of
+                              the supernodes, one launch factors their diagonal blocks and panels densely and
+                              one applies them to their target columns; -1: the column sweep (one launch per
+                              right-looking level of single columns, with the slot map above) */
+    int static_pivoting;   /* pre-processing with values (cktlu_analyze_values; Section III-A): 0 (default) the
+                              structural transversal only; 1 the row permutation P that maximises the product
+                              of the diagonal magnitudes (maximum-weight matching); 2 that P and scalings S_r,
+                              S_c with |diagonal| = 1 and every other entry at most 1 in magnitude: the library
+                              then factors S_r P A S_c (its factors, pivot tests and getters refer to that
+                              matrix) while values, right-hand sides and solutions stay the caller's */
 } cktlu_options;
 
 typedef struct {
@@ -145,6 +160,9 @@ typedef struct {
                                          it; the blocked dense LU issues 2/3 D^3 flops) */
     double alg_bytes_refactor_sweep;  /* compulsory bytes of the sweep: an index read and a value written per
                                          entry it finalises (12 bytes in FP64, 8 with FP32 factors) */
+    int64_t sweep_supernodes;         /* supernodes of the supernodal sweep (0: the column sweep runs) */
+    int64_t sweep_levels;             /* dependency levels of the sweep (supernodal or right-looking) */
+    int64_t fill_ndc;                 /* CKTLU_ORDER_AUTO: the same count under ND + constrained AMD */
 } cktlu_stats;
 
 /* Device time of the phases, accumulated over the calls made with options.timing = 1
@@ -185,6 +203,23 @@ int cktlu_set_stream(cktlu_ctx *ctx, void *stream);
  * Errors: E_ARG, E_STRUCT_SINGULAR, E_NOMEM.
  */
 int cktlu_analyze(cktlu_ctx *ctx, int32_t n, const int32_t *colptr, const int32_t *rowind);
+
+/*
+ * cktlu_analyze with the matrix values (host, nnz FP64 in the CSC order): with
+ * options.static_pivoting = 1 or 2 the transversal is the maximum-product
+ * matching of the values (and 2 computes the scaling), so that large entries
+ * sit on the diagonal before the ordering (Section III-A); when the nonzero
+ * values admit no perfect matching the structural transversal is used and no
+ * scaling.  With static_pivoting = 0 it equals cktlu_analyze.  Errors: those
+ * of cktlu_analyze, and E_ARG for NULL values with static_pivoting > 0.
+ */
+int cktlu_analyze_values(cktlu_ctx *ctx, int32_t n, const int32_t *colptr, const int32_t *rowind,
+                         const double *values);
+
+/* The static scaling of the last analyze (host out, double[n] each, either may be
+ * NULL): the factored matrix is rscale[i] A(i, j) cscale[j] (all ones without
+ * scaling).  Errors: E_ARG, E_STATE. */
+int cktlu_get_scaling(const cktlu_ctx *ctx, double *rscale, double *cscale);
 
 /*
  * Factorization with pivoting (Section II-A, Algorithm 1): threshold partial

@@ -36,6 +36,7 @@ CKTLU_ORDER_NATURAL = 1
 CKTLU_ORDER_AMF = 2
 CKTLU_ORDER_AUTO = 3
 CKTLU_ORDER_ND = 4
+CKTLU_ORDER_ND_CAMD = 5
 
 # every symbol the header declares (checked by the CPU test-suite)
 EXPORTS = [
@@ -48,7 +49,7 @@ EXPORTS = [
     "cktlu_server_now", "cktlu_server_destroy",
     "cktlu_get_perm", "cktlu_get_analysis", "cktlu_get_factor_nnz", "cktlu_get_factors",
     "cktlu_get_levels", "cktlu_get_stats", "cktlu_get_timing", "cktlu_footprint_bytes",
-    "cktlu_restart_closure", "cktlu_get_last_restart",
+    "cktlu_restart_closure", "cktlu_get_last_restart", "cktlu_analyze_values", "cktlu_get_scaling",
 ]
 
 
@@ -59,7 +60,8 @@ class cktlu_options(ctypes.Structure):
                 ("dense_tail_size", ctypes.c_int), ("dense_tail_density", ctypes.c_double),
                 ("timing", ctypes.c_int), ("solve_chain_width", ctypes.c_int),
                 ("dense_panel_width", ctypes.c_int), ("dense_lookahead", ctypes.c_int),
-                ("dense_device_repivot", ctypes.c_int), ("sweep_slot_map", ctypes.c_int)]
+                ("dense_device_repivot", ctypes.c_int), ("sweep_slot_map", ctypes.c_int),
+                ("sweep_supernodes", ctypes.c_int), ("static_pivoting", ctypes.c_int)]
 
 
 class cktlu_refactor_info(ctypes.Structure):
@@ -87,7 +89,8 @@ class cktlu_stats(ctypes.Structure):
                 ("slot_map_entries", ctypes.c_int64), ("schur_parts", ctypes.c_int64),
                 ("schur_scratch_cols", ctypes.c_int64), ("entries_sweep", ctypes.c_double),
                 ("entries_dense", ctypes.c_double), ("macs_dense", ctypes.c_double),
-                ("alg_bytes_refactor_sweep", ctypes.c_double)]
+                ("alg_bytes_refactor_sweep", ctypes.c_double), ("sweep_supernodes", ctypes.c_int64),
+                ("sweep_levels", ctypes.c_int64), ("fill_ndc", ctypes.c_int64)]
 
     def as_dict(self):
         return {f: getattr(self, f) for f, _ in self._fields_}
@@ -146,6 +149,8 @@ def _load():
     lib.cktlu_strerror.restype = ctypes.c_char_p
     lib.cktlu_set_stream.argtypes = [P, P]
     lib.cktlu_analyze.argtypes = [P, I32, P, P]
+    lib.cktlu_analyze_values.argtypes = [P, I32, P, P, P]
+    lib.cktlu_get_scaling.argtypes = [P, P, P]
     lib.cktlu_factorize.argtypes = [P, P]
     lib.cktlu_factorize_host.argtypes = [P, P]
     lib.cktlu_refactorize.argtypes = [P, P, ctypes.POINTER(cktlu_refactor_info)]
@@ -371,6 +376,14 @@ def cktlu_get_levels(ctx, level):
     return lib.cktlu_get_levels(ctx, _ptr(level))
 
 
+def cktlu_analyze_values(ctx, n, colptr, rowind, values):
+    return lib.cktlu_analyze_values(ctx, int(n), _ptr(colptr), _ptr(rowind), _ptr(values))
+
+
+def cktlu_get_scaling(ctx, rscale, cscale):
+    return lib.cktlu_get_scaling(ctx, _ptr(rscale), _ptr(cscale))
+
+
 def cktlu_restart_closure(n, parent, unfinished, in_set):
     return lib.cktlu_restart_closure(int(n), _ptr(parent), _ptr(unfinished), _ptr(in_set))
 
@@ -407,7 +420,8 @@ class SparseLU:
     def __init__(self, n, colptr, rowind, eps=1e-3, precision=CKTLU_FP64, ordering=CKTLU_ORDER_AUTO,
                  ir_tol=1e-10, ir_max_iter=10, stream=None, transversal=1, dense_tail=None,
                  dense_tail_density=None, timing=False, solve_chain_width=None, dense_panel_width=None,
-                 dense_lookahead=None, dense_device_repivot=None, sweep_slot_map=None):
+                 dense_lookahead=None, dense_device_repivot=None, sweep_slot_map=None, sweep_supernodes=None,
+                 static_pivoting=None, values=None):
         opt = cktlu_default_options()
         opt.timing = 1 if timing else 0
         if dense_tail is not None:
@@ -424,6 +438,10 @@ class SparseLU:
             opt.dense_device_repivot = int(dense_device_repivot)
         if sweep_slot_map is not None:
             opt.sweep_slot_map = int(sweep_slot_map)
+        if sweep_supernodes is not None:
+            opt.sweep_supernodes = int(sweep_supernodes)
+        if static_pivoting is not None:
+            opt.static_pivoting = int(static_pivoting)
         opt.pivot_eps = eps
         opt.precision = precision
         opt.ordering = ordering
@@ -436,7 +454,12 @@ class SparseLU:
         self._colptr = np.ascontiguousarray(colptr, dtype=np.int32)
         self._rowind = np.ascontiguousarray(rowind, dtype=np.int32)
         self.nnz = int(self._colptr[-1])
-        _check(cktlu_analyze(self.ctx, self.n, self._colptr, self._rowind), "cktlu_analyze")
+        if values is None:
+            _check(cktlu_analyze(self.ctx, self.n, self._colptr, self._rowind), "cktlu_analyze")
+        else:
+            self._values0 = np.ascontiguousarray(values, dtype=np.float64)
+            _check(cktlu_analyze_values(self.ctx, self.n, self._colptr, self._rowind, self._values0),
+                   "cktlu_analyze_values")
 
     def close(self):
         if self.ctx:
@@ -512,6 +535,13 @@ class SparseLU:
         _check(cktlu_get_factors(self.ctx, instance, Lp, Li, Lx, Up, Ui, Ux), "cktlu_get_factors")
         k = int(nl[0]); m = int(nu[0])
         return dict(Lp=Lp, Li=Li[:k], Lx=Lx[:k], Up=Up, Ui=Ui[:m], Ux=Ux[:m])
+
+    def scaling(self):
+        """(rscale, cscale): the factored matrix is rscale[i] A(i, j) cscale[j]."""
+        r = np.zeros(self.n)
+        c = np.zeros(self.n)
+        _check(cktlu_get_scaling(self.ctx, r, c), "cktlu_get_scaling")
+        return r, c
 
     def last_restart(self):
         """(unfinished, restart set) of the last pivot-check fallback, boolean arrays."""

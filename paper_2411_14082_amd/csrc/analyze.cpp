@@ -11,7 +11,11 @@
 #include <cmath>
 #include <cstring>
 #include <numeric>
+#include <climits>
 #include <set>
+#include <limits>
+#include <queue>
+#include <tuple>
 
 #include "internal.h"
 
@@ -129,20 +133,25 @@ enum : uint8_t { VAR = 0, ELEM = 1, ABSORBED = 2, MERGED = 3, DENSE = 4, DONE = 
 // element and variable lists are merged into supervariables.  Rows denser than
 // 10*sqrt(n) are ordered last.
 void amd_order(int n, const std::vector<int> &Sp, const std::vector<int> &Si,
-               std::vector<int> &perm, bool amf) {
+               std::vector<int> &perm, bool amf, const std::vector<int> *group) {
     perm.clear();
     perm.reserve(n);
     if (n == 0) return;
-    // AMF: (priority, node) in an ordered set; the AMD path keeps its degree lists
-    std::set<std::pair<int64_t, int>> pq;
-    std::vector<int64_t> key(amf ? n : 0, 0);
+    // AMF and the constrained form: (group, priority, node) in an ordered set, so that a node
+    // of a later group is never eliminated while one of an earlier group is left; the
+    // unconstrained AMD path keeps its degree lists
+    const bool useset = amf || group;
+    auto grp = [&](int i) { return group ? (int64_t)(*group)[i] : (int64_t)0; };
+    std::set<std::tuple<int64_t, int64_t, int>> pq;
+    std::vector<int64_t> key(useset ? n : 0, 0);
     std::vector<int64_t> cmax(amf ? n : 0, 0);
     auto fillkey = [](int64_t d, int64_t cl) { return d * (d - 1) / 2 - cl * (cl - 1) / 2; };
     std::vector<std::vector<int>> adjV(n), adjE(n), Le(n), members(n);
     std::vector<int> nv(n, 1), deg(n), mark(n, -1), wtag(n, -1);
     std::vector<int64_t> w(n, 0), esize(n, 0);
     std::vector<uint8_t> st(n, VAR);
-    const int dense_thr = std::max(16, (int)(10.0 * std::sqrt((double)n)));
+    // (no dense rows in the constrained form: they would leave their group)
+    const int dense_thr = group ? INT_MAX : std::max(16, (int)(10.0 * std::sqrt((double)n)));
     std::vector<int> dense;
     for (int i = 0; i < n; i++) {
         int d = Sp[i + 1] - Sp[i];
@@ -156,20 +165,20 @@ void amd_order(int n, const std::vector<int> &Sp, const std::vector<int> &Si,
             if (st[Si[p]] == VAR) adjV[i].push_back(Si[p]);
         deg[i] = (int)adjV[i].size();
     }
-    DegreeLists dl(amf ? 0 : n);
+    DegreeLists dl(useset ? 0 : n);
     int mindeg = n;
     for (int i = 0; i < n; i++)
         if (st[i] == VAR) {
-            if (amf) {
-                key[i] = fillkey(deg[i], 0);
-                pq.insert({key[i], i});
+            if (useset) {
+                key[i] = amf ? fillkey(deg[i], 0) : deg[i];
+                pq.insert({grp(i), key[i], i});
             } else {
                 dl.insert(i, deg[i]);
                 mindeg = std::min(mindeg, deg[i]);
             }
         }
     auto q_remove = [&](int i) {
-        if (amf) pq.erase({key[i], i}); else dl.remove(i, deg[i]);
+        if (useset) pq.erase({grp(i), key[i], i}); else dl.remove(i, deg[i]);
     };
 
     int64_t k = 0;
@@ -179,8 +188,8 @@ void amd_order(int n, const std::vector<int> &Sp, const std::vector<int> &Si,
     std::vector<int> byhash;
     while (k < nlive) {
         int p;
-        if (amf) {
-            p = pq.begin()->second;
+        if (useset) {
+            p = std::get<2>(*pq.begin());
             pq.erase(pq.begin());
         } else {
             while (mindeg <= n && dl.head[mindeg] < 0) mindeg++;
@@ -248,7 +257,7 @@ void amd_order(int n, const std::vector<int> &Sp, const std::vector<int> &Si,
             int64_t ext = degLp - nv[i];
             int64_t d = std::min<int64_t>({(int64_t)deg[i] + ext, dsum + ext, left - nv[i]});
             deg[i] = (int)std::max<int64_t>(0, d);
-            uint64_t h = 0;
+            uint64_t h = (uint64_t)grp(i) * 0x94D049BB133111EBull;   // supervariables stay inside a group
             for (int e : E) h += (uint64_t)e * 0x9E3779B97F4A7C15ull;
             for (int j : V) h += (uint64_t)(j + 1) * 0xC2B2AE3D27D4EB4Full;
             hash[i] = h ^ ((uint64_t)E.size() << 48) ^ ((uint64_t)V.size() << 32);
@@ -273,7 +282,7 @@ void amd_order(int n, const std::vector<int> &Sp, const std::vector<int> &Si,
                     for (size_t y = x + 1; y < b; y++) {
                         int j = byhash[y];
                         if (st[j] != VAR) continue;
-                        if (adjE[i] == adjE[j] && adjV[i] == adjV[j]) {
+                        if (grp(i) == grp(j) && adjE[i] == adjE[j] && adjV[i] == adjV[j]) {
                             deg[i] = std::max(0, deg[i] - nv[j]);
                             nv[i] += nv[j];
                             nv[j] = 0;
@@ -296,9 +305,9 @@ void amd_order(int n, const std::vector<int> &Sp, const std::vector<int> &Si,
             L.push_back(i);
             int d = std::min(deg[i], n);
             deg[i] = d;
-            if (amf) {
-                key[i] = fillkey(d, std::min<int64_t>(cmax[i], d));
-                pq.insert({key[i], i});
+            if (useset) {
+                key[i] = amf ? fillkey(d, std::min<int64_t>(cmax[i], d)) : d;
+                pq.insert({grp(i), key[i], i});
             } else {
                 dl.insert(i, d);
                 if (d < mindeg) mindeg = d;
@@ -314,9 +323,11 @@ void amd_order(int n, const std::vector<int> &Sp, const std::vector<int> &Si,
 // separator.  Disconnected sets split into components; sets of at most `leaf` nodes
 // (or with fewer than three levels) are ordered by AMD on their induced subgraph.
 void nd_order(int n, const std::vector<int> &Sp, const std::vector<int> &Si, std::vector<int> &perm,
-              int leaf) {
+              int leaf, std::vector<int> *groups) {
     perm.clear();
     perm.reserve(n);
+    if (groups) groups->assign(n, 0);
+    int ngroups = 0;
     if (n == 0) return;
     std::vector<int> inset(n, -1), lev(n, -1), local(n, -1);
     int stamp = 0;
@@ -351,7 +362,11 @@ void nd_order(int n, const std::vector<int> &Sp, const std::vector<int> &Si, std
     while (!stack.empty()) {
         Task t = std::move(stack.back());
         stack.pop_back();
-        if (t.emit) { perm.insert(perm.end(), t.nodes.begin(), t.nodes.end()); continue; }
+        if (t.emit) {
+            perm.insert(perm.end(), t.nodes.begin(), t.nodes.end());
+            if (groups) { for (int v : t.nodes) (*groups)[v] = ngroups; ngroups++; }
+            continue;
+        }
         std::vector<int> &nodes = t.nodes;
         ++stamp;
         for (int v : nodes) inset[v] = stamp;
@@ -383,6 +398,12 @@ void nd_order(int n, const std::vector<int> &Sp, const std::vector<int> &Si, std
                 continue;
             }
         }
+        if (groups) {                                     // incomplete dissection: the leaf is a group
+            perm.insert(perm.end(), nodes.begin(), nodes.end());
+            for (int v : nodes) (*groups)[v] = ngroups;
+            ngroups++;
+            continue;
+        }
         // leaf: AMD on the induced subgraph
         const int nl = (int)nodes.size();
         for (int i = 0; i < nl; i++) local[nodes[i]] = i;
@@ -397,6 +418,18 @@ void nd_order(int n, const std::vector<int> &Sp, const std::vector<int> &Si, std
         amd_order(nl, lSp, lSi, lperm, false);
         for (int i = 0; i < nl; i++) perm.push_back(nodes[lperm[i]]);
     }
+}
+
+// Nested dissection followed by a constrained minimum degree (Section III-A): the
+// dissection stops at its leaves and numbers its parts (the leaves and separators) in the
+// order it would emit them; one AMD over the whole pattern then eliminates the parts in
+// that order, each by approximate degree, so that the ordering inside a part sees the fill
+// it causes in the separators that border it.
+void nd_camd_order(int n, const std::vector<int> &Sp, const std::vector<int> &Si, std::vector<int> &perm,
+                   int leaf) {
+    std::vector<int> groups, nd;
+    nd_order(n, Sp, Si, nd, leaf, &groups);
+    amd_order(n, Sp, Si, perm, false, &groups);
 }
 
 int64_t symbolic_cholesky_nnz(int n, const std::vector<int> &Sp, const std::vector<int> &Si,
@@ -451,8 +484,112 @@ void column_etree(int n, const std::vector<int> &Hp, const std::vector<int> &Hi,
     }
 }
 
+// Static pivoting (Section III-A): the row matched to each column that maximises the
+// product of the matched magnitudes, and the scaling that makes every matched entry 1 in
+// magnitude and every other entry at most 1.  With column maxima a_j = max_i |A(i,j)| and
+// costs c_ij = ln a_j - ln |A(i,j)| >= 0 (entries with A(i,j) = 0 are left out), the
+// matching is a minimum-cost perfect matching, found by successive shortest augmenting
+// paths: each unmatched column starts a Dijkstra search over reduced costs c_ij + pc_j -
+// pr_i >= 0 (column j to row i; a matched row leads on to its column at reduced cost 0),
+// stops at the nearest unmatched row, augments, and raises every potential by the
+// distance found (capped at the path length), which keeps all reduced costs non-negative
+// and the matched ones zero.  Columns whose maximum sits on a free row are matched first.
+// At the end u_i = pr_i, v_j = -pc_j satisfy c_ij >= u_i + v_j with equality on the
+// matching, so ln of the row scale is u_i and of the column scale v_j - ln a_j.
+// Returns false when the nonzero entries admit no perfect matching.
+bool max_product_matching(int n, const std::vector<int> &Ap, const std::vector<int> &Ai, const double *Ax,
+                          std::vector<int> &match_of_col, std::vector<double> &lnr, std::vector<double> &lnc) {
+    const double INF = std::numeric_limits<double>::infinity();
+    std::vector<double> cost(Ap[n]), lnmax(n, -INF);
+    for (int j = 0; j < n; j++) {
+        for (int p = Ap[j]; p < Ap[j + 1]; p++)
+            if (Ax[p] != 0.0 && std::isfinite(Ax[p])) lnmax[j] = std::max(lnmax[j], std::log(std::fabs(Ax[p])));
+        if (lnmax[j] == -INF) return false;                  // a column without a usable entry
+        for (int p = Ap[j]; p < Ap[j + 1]; p++)
+            cost[p] = (Ax[p] != 0.0 && std::isfinite(Ax[p])) ? lnmax[j] - std::log(std::fabs(Ax[p])) : INF;
+    }
+    std::vector<int> col_of_row(n, -1);
+    match_of_col.assign(n, -1);
+    std::vector<double> pr(n, 0.0), pc(n, 0.0);
+    // greedy start: a column's maximum (reduced cost 0) on a free row
+    for (int j = 0; j < n; j++)
+        for (int p = Ap[j]; p < Ap[j + 1]; p++)
+            if (cost[p] == 0.0 && col_of_row[Ai[p]] < 0) {
+                col_of_row[Ai[p]] = j;
+                match_of_col[j] = Ai[p];
+                break;
+            }
+    std::vector<double> dr(n, INF);                     // distance of each row in the current search
+    std::vector<int> via(n, -1), seen(n, -1), touched;
+    std::vector<int> done_cols;
+    typedef std::pair<double, int> QE;
+    for (int j0 = 0; j0 < n; j0++) {
+        if (match_of_col[j0] >= 0) continue;
+        std::priority_queue<QE, std::vector<QE>, std::greater<QE>> pq;
+        touched.clear();
+        done_cols.clear();
+        // relax the rows of column j at distance dj
+        auto relax = [&](int j, double dj) {
+            for (int p = Ap[j]; p < Ap[j + 1]; p++) {
+                if (cost[p] == INF) continue;
+                const int i = Ai[p];
+                if (seen[i] == j0) continue;                 // finalised
+                // reduced costs are >= 0 up to rounding (the potentials keep them so)
+                const double d = dj + std::max(0.0, cost[p] + pc[j] - pr[i]);
+                if (d < dr[i]) {
+                    if (dr[i] == INF) touched.push_back(i);
+                    dr[i] = d;
+                    via[i] = j;
+                    pq.push({d, i});
+                }
+            }
+        };
+        std::vector<std::pair<int, double>> fin;             // finalised rows and their distances
+        std::vector<double> dcol;                            // distances of the columns reached
+        done_cols.push_back(j0);
+        dcol.push_back(0.0);
+        relax(j0, 0.0);
+        int ifree = -1;
+        double delta = INF;
+        while (!pq.empty()) {
+            const QE t = pq.top();
+            pq.pop();
+            const int i = t.second;
+            if (seen[i] == j0 || t.first > dr[i]) continue;
+            seen[i] = j0;
+            fin.push_back({i, t.first});
+            if (col_of_row[i] < 0) { ifree = i; delta = t.first; break; }
+            const int jn = col_of_row[i];
+            done_cols.push_back(jn);
+            dcol.push_back(t.first);
+            relax(jn, t.first);
+        }
+        if (ifree < 0) return false;                         // no augmenting path: no perfect matching
+        // potentials pi += min(d, delta) (Johnson's rule, truncated at the path length), shifted
+        // by -delta: nodes reached at d < delta move by d - delta, the others stay
+        for (auto &f : fin) if (f.second < delta) pr[f.first] -= delta - f.second;
+        for (size_t q = 0; q < done_cols.size(); q++) if (dcol[q] < delta) pc[done_cols[q]] -= delta - dcol[q];
+        // augment along via[]
+        int i = ifree;
+        while (true) {
+            const int j = via[i];
+            const int iprev = match_of_col[j];
+            match_of_col[j] = i;
+            col_of_row[i] = j;
+            if (j == j0) break;
+            i = iprev;
+        }
+        for (int r : touched) dr[r] = INF;
+    }
+    lnr.resize(n);
+    lnc.resize(n);
+    for (int i = 0; i < n; i++) lnr[i] = pr[i];
+    for (int j = 0; j < n; j++) lnc[j] = -pc[j] - lnmax[j];
+    return true;
+}
+
 int run_analysis(Analysis &an, int n, const int32_t *colptr, const int32_t *rowind,
-                 int ordering, int transversal) {
+                 int ordering, int transversal, const double *values, int static_pivoting) {
     int rc = validate_csc(n, colptr, rowind);
     if (rc != CKTLU_OK) return rc;
     an = Analysis();
@@ -460,12 +597,29 @@ int run_analysis(Analysis &an, int n, const int32_t *colptr, const int32_t *rowi
     an.nnz = colptr[n];
     an.Ap.assign(colptr, colptr + n + 1);
     an.Ai.assign(rowind, rowind + an.nnz);
-    // structural transversal: B(i, j) = A(match[i], j) has a zero-free diagonal
+    // transversal: B(i, j) = A(match[i], j) has a zero-free diagonal; with values and static
+    // pivoting, the one that maximises the product of the diagonal magnitudes (and the scaling)
     std::vector<int> match(n);
-    if (transversal) {
-        if (!max_transversal(n, an.Ap, an.Ai, match)) return CKTLU_E_STRUCT_SINGULAR;
-    } else {
-        std::iota(match.begin(), match.end(), 0);
+    an.rscale.clear();
+    an.cscale.clear();
+    bool matched = false;
+    if (values && static_pivoting > 0) {
+        std::vector<double> lnr, lnc;
+        matched = max_product_matching(n, an.Ap, an.Ai, values, match, lnr, lnc);
+        an.static_pivoting_used = matched ? static_pivoting : 0;
+        if (matched && static_pivoting == 2) {
+            an.rscale.resize(n);
+            an.cscale.resize(n);
+            for (int i = 0; i < n; i++) an.rscale[i] = std::exp(lnr[i]);
+            for (int j = 0; j < n; j++) an.cscale[j] = std::exp(lnc[j]);
+        }
+    }
+    if (!matched) {
+        if (transversal) {
+            if (!max_transversal(n, an.Ap, an.Ai, match)) return CKTLU_E_STRUCT_SINGULAR;
+        } else {
+            std::iota(match.begin(), match.end(), 0);
+        }
     }
     std::vector<int> browof(n);            // A row -> B row
     for (int i = 0; i < n; i++) browof[match[i]] = i;
@@ -500,15 +654,17 @@ int run_analysis(Analysis &an, int n, const int32_t *colptr, const int32_t *rowi
         const bool autom = ordering == CKTLU_ORDER_AUTO;
         std::vector<int> qm;
         int64_t best = -1;
-        const int methods[3] = {CKTLU_ORDER_AMD, CKTLU_ORDER_AMF, CKTLU_ORDER_ND};
+        const int methods[4] = {CKTLU_ORDER_AMD, CKTLU_ORDER_AMF, CKTLU_ORDER_ND, CKTLU_ORDER_ND_CAMD};
         for (int m : methods) {
             if (!autom && ordering != m) continue;
             if (m == CKTLU_ORDER_ND) nd_order(n, Sp, Sd, qm, kNdLeaf);
+            else if (m == CKTLU_ORDER_ND_CAMD) nd_camd_order(n, Sp, Sd, qm, kNdLeaf);
             else amd_order(n, Sp, Sd, qm, m == CKTLU_ORDER_AMF);
             if ((int)qm.size() != n) return CKTLU_E_ARG;
             if (!autom) { q.swap(qm); an.ordering_used = m; break; }
             const int64_t f = symbolic_cholesky_nnz(n, Sp, Sd, qm);
-            (m == CKTLU_ORDER_AMD ? an.fill_amd : m == CKTLU_ORDER_AMF ? an.fill_amf : an.fill_nd) = f;
+            (m == CKTLU_ORDER_AMD ? an.fill_amd : m == CKTLU_ORDER_AMF ? an.fill_amf
+                                              : m == CKTLU_ORDER_ND ? an.fill_nd : an.fill_ndc) = f;
             if (best < 0 || f < best) { best = f; q.swap(qm); an.ordering_used = m; }   // ties keep the earlier
         }
     } else {

@@ -173,7 +173,9 @@ DevBuf *all_buffers(Device &d, int i) {
                      &d.l21, &d.lrec, &d.urec,
                      &d.Lrjs, &d.Urjs, &d.lsptr, &d.usptr, &d.rowperm,
                      &d.colperm_sol, &d.Acp, &d.Acj, &d.Acsrc, &d.Fx64, &d.Fx32, &d.Aval, &d.done,
-                     &d.ctrl, &d.vec, &d.S, &d.Dg, &d.Dinv};
+                     &d.ctrl, &d.vec, &d.S, &d.Dg, &d.Dinv, &d.sn_rec, &d.sn_cb, &d.sn_seq, &d.sn_task,
+                     &d.sn_item, &d.sn_moff, &d.sn_map, &d.snl_seq, &d.snu_seq, &d.Lrp, &d.Urp,
+                     &d.ascale, &d.gscale, &d.sscale};
     const int cnt = (int)(sizeof(all) / sizeof(all[0]));
     return i < cnt ? all[i] : nullptr;
 }
@@ -287,6 +289,36 @@ int upload_all(cktlu_ctx *c) {
         }
         c->stats.slot_map_entries = d.smap.p ? (int64_t)s.smap.size() : 0;
     }
+    if ((rc = upload(d.sn_rec, s.sn_rec, st))) return rc;
+    if ((rc = upload(d.sn_cb, s.sn_cb, st))) return rc;
+    if ((rc = upload(d.sn_seq, s.sn_seq, st))) return rc;
+    if ((rc = upload(d.sn_task, s.sn_task, st))) return rc;
+    if ((rc = upload(d.sn_item, s.sn_item, st))) return rc;
+    if ((rc = upload(d.sn_moff, s.sn_moff, st))) return rc;
+    if ((rc = upload(d.sn_map, s.sn_map, st))) return rc;
+    if (!c->an.rscale.empty()) {
+        // static scaling A' = S_r P A S_c: per nonzero of A, per solve row and per solve column
+        const Analysis &an = c->an;
+        std::vector<double> as(an.nnz), gs(an.n), ss(an.n);
+        for (int j = 0; j < an.n; j++)
+            for (int p = an.Ap[j]; p < an.Ap[j + 1]; p++) as[p] = an.rscale[an.Ai[p]] * an.cscale[j];
+        for (int k = 0; k < an.n; k++) {
+            gs[k] = an.rscale[s.rowperm_final[k]];
+            ss[k] = an.cscale[an.colperm[k]];
+        }
+        if ((rc = upload(d.ascale, as, st))) return rc;
+        if ((rc = upload(d.gscale, gs, st))) return rc;
+        if ((rc = upload(d.sscale, ss, st))) return rc;
+        HIPCHK(hipStreamSynchronize(st));
+    } else {
+        dfree(d.ascale);
+        dfree(d.gscale);
+        dfree(d.sscale);
+    }
+    if ((rc = upload(d.snl_seq, s.snl_seq, st))) return rc;
+    if ((rc = upload(d.snu_seq, s.snu_seq, st))) return rc;
+    if ((rc = upload(d.Lrp, s.Lrp, st))) return rc;
+    if ((rc = upload(d.Urp, s.Urp, st))) return rc;
     if ((rc = upload(d.lrec, s.lrec, st))) return rc;
     if ((rc = upload(d.urec, s.urec, st))) return rc;
     if ((rc = upload(d.Lrjs, s.Lrjs, st))) return rc;
@@ -338,6 +370,7 @@ void fill_stats_pattern(cktlu_ctx *c) {
     t.fill_amd = c->an.fill_amd;
     t.fill_amf = c->an.fill_amf;
     t.fill_nd = c->an.fill_nd;
+    t.fill_ndc = c->an.fill_ndc;
     t.schur_parts = (int64_t)(c->s.schur_parts.size() / 4);
     t.schur_scratch_cols = c->s.schur_nscr;
     t.dense_tail = c->an.n - c->s.tail0;
@@ -350,7 +383,12 @@ void fill_stats_pattern(cktlu_ctx *c) {
     const Schedule &s = c->s;
     t.macs_sweep = s.macs_sweep;
     t.macs_schur = s.macs_schur;
-    t.bytes_sweep = 28.0 * s.macs_sweep + 24.0 * s.lnz_front;
+    // traffic models: column sweep 28 B per multiply-add (L value and slot gathered, target read and
+    // written) + 24 B per L entry; supernodal sweep 8 B per multiply-add (the panel's L entry) + 20 B
+    // per row of R applied to a target (slot, target read and written) + 24 B per L entry (panel)
+    t.bytes_sweep = s.sn_count ? 8.0 * s.sn_macs + 20.0 * (double)(s.sn_moff.empty() ? 0 : s.sn_moff.back()) +
+                                     24.0 * s.lnz_front
+                               : 28.0 * s.macs_sweep + 24.0 * s.lnz_front;
     t.entries_sweep = s.entries_sweep;
     t.entries_dense = s.entries_dense;
     t.macs_dense = s.macs_dense;
@@ -363,9 +401,15 @@ void fill_stats_pattern(cktlu_ctx *c) {
                           (l > 0 ? s.lvl_ptr[l] - s.lvl_ptr[l - 1] : 0);
         if (w > 0) t.sweep_launches++;
     }
+    for (int l = 0; l < s.sn_levels; l++)
+        t.sweep_launches += (s.sn_lvl_single[l] > s.sn_lvl[l]) + (s.sn_lvl[l + 1] > s.sn_lvl_single[l]) +
+                            (s.sn_task_lvl[l + 1] > s.sn_task_lvl[l]);
+    t.sweep_supernodes = s.sn_count;
+    t.sweep_levels = s.sn_count ? s.sn_levels : s.n_rlevels;
     const int64_t panels = (int64_t)((D + kDenseBlock - 1) / kDenseBlock);
     t.dense_launches = D > 0 ? 2 * panels - 1 + 2 : 0;        // panels, updates, pivot test, scatter
-    t.solve_launches = (int64_t)(s.lseg.size() / 3) + (int64_t)(s.useg.size() / 3) + (D > 0 ? 2 * panels : 0);
+    t.solve_launches = s.sn_count ? (int64_t)s.snl_levels + s.snu_levels + (D > 0 ? 1 + 2 * panels : 0)
+                                  : (int64_t)(s.lseg.size() / 3) + (int64_t)(s.useg.size() / 3) + (D > 0 ? 2 * panels : 0);
 }
 
 // Host factorization with pivoting (keep == nullptr: every column), then
@@ -380,6 +424,15 @@ int factor_and_setup(cktlu_ctx *c, const double *values_host, const std::vector<
     Factor nf;
     int fail = -1, nswaps = 0;
     const auto t0 = std::chrono::steady_clock::now();
+    std::vector<double> scaled;
+    if (!c->an.rscale.empty()) {          // the factored matrix is S_r P A S_c
+        const Analysis &an = c->an;
+        scaled.resize(an.nnz);
+        for (int j = 0; j < an.n; j++)
+            for (int p = an.Ap[j]; p < an.Ap[j + 1]; p++)
+                scaled[p] = values_host[p] * an.rscale[an.Ai[p]] * an.cscale[j];
+        values_host = scaled.data();
+    }
     int rc = host_gp_factor(c->an, values_host, c->opt.pivot_eps, init, keep ? &c->f : nullptr, keep, nf,
                             fail, nswaps, dsrc);
     if (rc != CKTLU_OK) return rc;
@@ -502,6 +555,7 @@ int run_refactor(cktlu_ctx *c, int batch, const double *values_dev, bool fp32, b
     a.eps = c->opt.pivot_eps;
     a.epoch = d.epoch;
     a.force_fail_col = force_col;
+    a.ascale = (const double *)d.ascale.p;
     a.colrec = (const int *)d.colrec.p;
     a.task8 = (const int *)d.task8.p;
     a.item4 = (const int *)d.item4.p;
@@ -517,8 +571,23 @@ int run_refactor(cktlu_ctx *c, int batch, const double *values_dev, bool fp32, b
     phase_end(c, t0, PH_INIT, 1);
     t0 = phase_begin(c);
     int launches = 0;
-    // level l: check level l, normalise level l-1, update tasks of level l; then normalise the last
-    for (int l = 0; l <= s.n_rlevels; l++) {
+    a.sn_rec = (const int *)d.sn_rec.p;
+    a.sn_cb = (const int *)d.sn_cb.p;
+    a.sn_seq = (const int *)d.sn_seq.p;
+    a.sn_task = (const int *)d.sn_task.p;
+    a.sn_item = (const int *)d.sn_item.p;
+    a.sn_map = (const int *)d.sn_map.p;
+    a.sn_moff = (const int64_t *)d.sn_moff.p;
+    // supernodal sweep: per level, the supernodes' panels, then the updates they apply
+    for (int l = 0; l < s.sn_levels; l++) {
+        LCHK(launch_sn_panels(a, l, s.sn_lvl[l], s.sn_lvl_single[l], s.sn_lvl[l + 1], st));
+        LCHK(launch_sn_updates(a, l, s.sn_task_lvl[l], s.sn_task_lvl[l + 1], st));
+        launches += (s.sn_lvl_single[l] > s.sn_lvl[l]) + (s.sn_lvl[l + 1] > s.sn_lvl_single[l]) +
+                    (s.sn_task_lvl[l + 1] > s.sn_task_lvl[l]);
+    }
+    // column sweep: level l checks level l, normalises level l-1, runs the update tasks of
+    // level l; then the last level is normalised
+    for (int l = 0; l <= s.n_rlevels && s.n_rlevels > 0; l++) {
         const int cb = l < s.n_rlevels ? s.lvl_ptr[l] : 0, ce = l < s.n_rlevels ? s.lvl_ptr[l + 1] : 0;
         const int pb = l > 0 ? s.lvl_ptr[l - 1] : 0, pe = l > 0 ? s.lvl_ptr[l] : 0;
         const int tb = l < s.n_rlevels ? s.task_ptr[l] : 0, te = l < s.n_rlevels ? s.task_ptr[l + 1] : 0;
@@ -572,6 +641,7 @@ int dense_pivot_refactor(cktlu_ctx *c, const std::vector<double> &vals, cktlu_re
     ra.Dp = (const int *)d.Dp.p; ra.Fi = (const int *)d.Fi.p; ra.Ap = (const int *)d.Ap.p;
     ra.colperm = (const int *)d.colperm.p; ra.amap = (const int *)d.amap.p;
     ra.Aval = (const double *)d.Aval.p; ra.S = d.S.p;
+    ra.ascale = (const double *)d.ascale.p;
     DenseArgs da = dense_args(c, 1, false);
     da.ctrl = (int *)d.ctrl.p;
     da.done = (int *)d.done.p;
@@ -744,16 +814,29 @@ int tri_solves(cktlu_ctx *c, int nrhs, int batch, double *z, bool fp32, const in
     a.fp32 = fp32 ? 1 : 0;
     a.y = z;
     a.skip = skip;
+    a.sn_rec = (const int *)d.sn_rec.p;
+    a.sn_cb = (const int *)d.sn_cb.p;
+    a.Lrp = (const int *)d.Lrp.p;
+    a.Urp = (const int *)d.Urp.p;
     const Schedule &s = c->s;
-    // sparse L levels (the last one holds the dense rows: their entries in sparse columns)
+    const bool snodal = s.sn_count > 0;
+    // sparse L levels (the last one holds the dense rows: their entries in sparse columns); with
+    // supernodes, the rows < T by supernode levels and then only that last level
     hipEvent_t t0 = phase_begin(c);
+    int launches = 0;
+    for (int l = 0; snodal && l < s.snl_levels; l++, launches++)
+        LCHK(launch_sn_lsolve(a, (const int *)d.snl_seq.p, s.snl_lvl[l], s.snl_single[l], s.snl_lvl[l + 1], st));
+    const int ldense = s.tail0 < c->an.n ? (int)s.lsptr.size() - 2 : -1;   // level of the dense rows
     for (size_t g = 0; g < s.lseg.size(); g += 3) {
         const int l0 = s.lseg[g], l1 = s.lseg[g + 1];
-        if (s.lseg[g + 2] == 1) LCHK(launch_lsolve_chain(a, (const int *)d.lsptr.p, l0, l1, st));
-        else if (s.lseg[g + 2] == 2) LCHK(launch_lsolve_level_wg(a, s.lsptr[l0], s.lsptr[l1], st));
-        else LCHK(launch_lsolve_level(a, s.lsptr[l0], s.lsptr[l1], st));
+        if (snodal && !(l0 <= ldense && ldense < l1)) continue;
+        const int a0 = snodal ? ldense : l0, a1 = snodal ? ldense + 1 : l1;
+        if (s.lseg[g + 2] == 1 && !snodal) LCHK(launch_lsolve_chain(a, (const int *)d.lsptr.p, l0, l1, st));
+        else if (s.lseg[g + 2] == 2) LCHK(launch_lsolve_level_wg(a, s.lsptr[a0], s.lsptr[a1], st));
+        else LCHK(launch_lsolve_level(a, s.lsptr[a0], s.lsptr[a1], st));
+        launches++;
     }
-    phase_end(c, t0, PH_SOLVE_SPARSE, (int)s.lseg.size() / 3);
+    phase_end(c, t0, PH_SOLVE_SPARSE, launches);
     if (s.tail0 < c->an.n) {
         int rc = ensure_S(c, fp32, batch);
         if (rc) return rc;
@@ -765,13 +848,16 @@ int tri_solves(cktlu_ctx *c, int nrhs, int batch, double *z, bool fp32, const in
         phase_end(c, t0, PH_SOLVE_DENSE, 2 * nblk);
     }
     t0 = phase_begin(c);
-    for (size_t g = 0; g < s.useg.size(); g += 3) {
+    launches = 0;
+    for (int l = 0; snodal && l < s.snu_levels; l++, launches++)
+        LCHK(launch_sn_usolve(a, (const int *)d.snu_seq.p, s.snu_lvl[l], s.snu_single[l], s.snu_lvl[l + 1], st));
+    for (size_t g = 0; !snodal && g < s.useg.size(); g += 3, launches++) {
         const int l0 = s.useg[g], l1 = s.useg[g + 1];
         if (s.useg[g + 2] == 1) LCHK(launch_usolve_chain(a, (const int *)d.usptr.p, l0, l1, st));
         else if (s.useg[g + 2] == 2) LCHK(launch_usolve_level_wg(a, s.usptr[l0], s.usptr[l1], st));
         else LCHK(launch_usolve_level(a, s.usptr[l0], s.usptr[l1], st));
     }
-    phase_end(c, t0, PH_SOLVE_SPARSE, (int)s.useg.size() / 3);
+    phase_end(c, t0, PH_SOLVE_SPARSE, launches);
     if (c->opt.timing) c->timing_acc.solve_passes++;
     return CKTLU_OK;
 }
@@ -793,10 +879,10 @@ int solve_chunk(cktlu_ctx *c, int nrhs, const double *b, int64_t ldb, double *x,
         z = (double *)c->dev.vec.p;
     }
     hipStream_t st = stream_of(c);
-    LCHK(launch_gather_rhs(n, nrhs, 1, b, ldb, (const int *)c->dev.rowperm.p, z, st));
+    LCHK(launch_gather_rhs(n, nrhs, 1, b, ldb, (const int *)c->dev.rowperm.p, z, st, (const double *)c->dev.gscale.p));
     if ((rc = tri_solves(c, nrhs, 1, z, fp32, nullptr))) return rc;
     LCHK(launch_scatter_sol(n, nrhs, 1, z, (const int *)c->dev.colperm_sol.p, x, ldx, accumulate ? 1 : 0,
-                            nullptr, st));
+                            nullptr, st, (const double *)c->dev.sscale.p));
     return CKTLU_OK;
 }
 
@@ -882,9 +968,11 @@ int cktlu_create(cktlu_ctx **out, const cktlu_options *opt) {
     if (!(c->opt.pivot_eps > 0.0 && c->opt.pivot_eps <= 1.0) ||
         (c->opt.precision != CKTLU_FP64 && c->opt.precision != CKTLU_FP32_IR) || c->opt.ir_max_iter < 1 ||
         c->opt.solve_chain_width < -1 || (c->opt.dense_lookahead != 0 && c->opt.dense_lookahead != 1) ||
-        c->opt.ordering < CKTLU_ORDER_AMD || c->opt.ordering > CKTLU_ORDER_ND ||
+        c->opt.ordering < CKTLU_ORDER_AMD || c->opt.ordering > CKTLU_ORDER_ND_CAMD ||
         (c->opt.dense_device_repivot != 0 && c->opt.dense_device_repivot != -1) ||
         (c->opt.sweep_slot_map != 0 && c->opt.sweep_slot_map != -1) ||
+        c->opt.sweep_supernodes < -1 || c->opt.sweep_supernodes > 64 ||
+        c->opt.static_pivoting < 0 || c->opt.static_pivoting > 2 ||
         (c->opt.dense_panel_width != 0 && c->opt.dense_panel_width != 64 && c->opt.dense_panel_width != 128 &&
          c->opt.dense_panel_width != 256)) {
         delete c;
@@ -932,6 +1020,34 @@ const char *cktlu_strerror(int s) {
 int cktlu_set_stream(cktlu_ctx *c, void *stream) {
     if (!c) return CKTLU_E_ARG;
     c->opt.stream = stream;
+    return CKTLU_OK;
+}
+
+int cktlu_analyze_values(cktlu_ctx *c, int32_t n, const int32_t *colptr, const int32_t *rowind,
+                         const double *values) {
+    if (!c || (n > 0 && !values && c->opt.static_pivoting > 0)) return CKTLU_E_ARG;
+    if (n > (1 << 28)) return CKTLU_E_LIMIT;
+    free_device(c->dev);
+    c->f = Factor();
+    c->s = Schedule();
+    c->last_unfinished.clear();
+    c->last_restart.clear();
+    c->host_values.clear();
+    int rc = run_analysis(c->an, n, colptr, rowind, c->opt.ordering, c->opt.transversal, values,
+                          c->opt.static_pivoting);
+    if (rc != CKTLU_OK) { c->state = 0; return rc; }
+    c->state = 1;
+    return CKTLU_OK;
+}
+
+int cktlu_get_scaling(const cktlu_ctx *c, double *rscale, double *cscale) {
+    if (!c) return CKTLU_E_ARG;
+    if (c->state < 1) return CKTLU_E_STATE;
+    const bool sc = !c->an.rscale.empty();
+    for (int i = 0; i < c->an.n; i++) {
+        if (rscale) rscale[i] = sc ? c->an.rscale[i] : 1.0;
+        if (cscale) cscale[i] = sc ? c->an.cscale[i] : 1.0;
+    }
     return CKTLU_OK;
 }
 
@@ -1092,9 +1208,9 @@ int cktlu_step_batched_graph(cktlu_ctx *c, int32_t batch, const double *values_d
             if (e) return e;
             LCHK(launch_status_out((const int *)c->dev.ctrl.p + 1 + batch, status_dev, batch, st));
             if (!fp32) {
-                LCHK(launch_gather_rhs(n, nrhs, batch, b, n, rowperm, z, st));
+                LCHK(launch_gather_rhs(n, nrhs, batch, b, n, rowperm, z, st, (const double *)c->dev.gscale.p));
                 if ((e = tri_solves(c, nrhs, batch, z, false, status_dev))) return e;
-                LCHK(launch_scatter_sol(n, nrhs, batch, z, colperm, x, n, 0, status_dev, st));
+                LCHK(launch_scatter_sol(n, nrhs, batch, z, colperm, x, n, 0, status_dev, st, (const double *)c->dev.sscale.p));
                 if (eta_dev) LCHK(launch_fill_f64(eta_dev, batch, -1.0, st));
                 return CKTLU_OK;
             }
@@ -1107,10 +1223,10 @@ int cktlu_step_batched_graph(cktlu_ctx *c, int32_t batch, const double *values_d
             LCHK(launch_anorm_batched(n, batch, nnzA, Acp, Acsrc, Aval, anorm, st));
             LCHK(launch_copy_i32(status_dev, skip, batch, st));
             for (int it = 1; it <= ir_steps; it++) {
-                LCHK(launch_gather_rhs(n, nrhs, batch, it == 1 ? b : r, n, rowperm, z, st));
+                LCHK(launch_gather_rhs(n, nrhs, batch, it == 1 ? b : r, n, rowperm, z, st, (const double *)c->dev.gscale.p));
                 if ((e = tri_solves(c, nrhs, batch, z, true, skip))) return e;
                 // x = d on the first step (x of skipped instances is never written), then x += d
-                LCHK(launch_scatter_sol(n, nrhs, batch, z, colperm, x, n, it > 1 ? 1 : 0, skip, st));
+                LCHK(launch_scatter_sol(n, nrhs, batch, z, colperm, x, n, it > 1 ? 1 : 0, skip, st, (const double *)c->dev.sscale.p));
                 LCHK(launch_fill_f64(norms, 3 * (int64_t)nrhs * batch, 0.0, st));
                 LCHK(launch_residual_batched(n, nrhs, batch, nnzA, Acp, Acj, Acsrc, Aval, x, b, r, norms, skip, st));
                 LCHK(launch_ir_check(batch, nrhs, norms, anorm, c->opt.ir_tol, skip, eta, st));
@@ -1274,9 +1390,9 @@ int cktlu_solve_batched(cktlu_ctx *c, int32_t batch, int32_t nrhs, const double 
     const int *rowperm = (const int *)c->dev.rowperm.p, *colperm = (const int *)c->dev.colperm_sol.p;
     if (eta_dev) LCHK(launch_fill_f64(eta_dev, batch, -1.0, st));
     if (c->opt.precision == CKTLU_FP64) {
-        LCHK(launch_gather_rhs(n, nrhs, batch, b, n, rowperm, z, st));
+        LCHK(launch_gather_rhs(n, nrhs, batch, b, n, rowperm, z, st, (const double *)c->dev.gscale.p));
         if ((rc = tri_solves(c, nrhs, batch, z, false, status_dev))) return rc;
-        LCHK(launch_scatter_sol(n, nrhs, batch, z, colperm, x, n, 0, status_dev, st));
+        LCHK(launch_scatter_sol(n, nrhs, batch, z, colperm, x, n, 0, status_dev, st, (const double *)c->dev.sscale.p));
         return CKTLU_OK;
     }
     // FP32 factors with FP64 refinement per instance: x = 0; repeat d = (LU)^-1 r, x += d,
@@ -1292,10 +1408,10 @@ int cktlu_solve_batched(cktlu_ctx *c, int32_t batch, int32_t nrhs, const double 
     std::vector<char> stalled(batch, 0);
     HIPCHK(hipMemcpyAsync(hstatus.data(), status_dev, batch * sizeof(int), hipMemcpyDeviceToHost, st));
     for (int it = 1; it <= c->opt.ir_max_iter; it++) {
-        LCHK(launch_gather_rhs(n, nrhs, batch, it == 1 ? b : r, n, rowperm, z, st));
+        LCHK(launch_gather_rhs(n, nrhs, batch, it == 1 ? b : r, n, rowperm, z, st, (const double *)c->dev.gscale.p));
         if ((rc = tri_solves(c, nrhs, batch, z, true, skip))) return rc;
         // x = d on the first step (x of skipped instances is never written), then x += d
-        LCHK(launch_scatter_sol(n, nrhs, batch, z, colperm, x, n, it > 1 ? 1 : 0, skip, st));
+        LCHK(launch_scatter_sol(n, nrhs, batch, z, colperm, x, n, it > 1 ? 1 : 0, skip, st, (const double *)c->dev.sscale.p));
         LCHK(launch_fill_f64(norms, 3 * (int64_t)nrhs * batch, 0.0, st));
         LCHK(launch_residual_batched(n, nrhs, batch, nnzA, Acp, Acj, Acsrc, Aval, x, b, r, norms, skip, st));
         LCHK(launch_ir_check(batch, nrhs, norms, anorm, c->opt.ir_tol, skip, eta, st));
@@ -1321,9 +1437,9 @@ int cktlu_solve_batched(cktlu_ctx *c, int32_t batch, int32_t nrhs, const double 
     if (!nfb) return CKTLU_OK;
     if ((rc = run_refactor(c, batch, Aval, false, false, -1))) return rc;
     HIPCHK(hipMemcpyAsync(skip64, h64.data(), batch * sizeof(int), hipMemcpyHostToDevice, st));
-    LCHK(launch_gather_rhs(n, nrhs, batch, b, n, rowperm, z, st));
+    LCHK(launch_gather_rhs(n, nrhs, batch, b, n, rowperm, z, st, (const double *)c->dev.gscale.p));
     if ((rc = tri_solves(c, nrhs, batch, z, false, skip64))) return rc;
-    LCHK(launch_scatter_sol(n, nrhs, batch, z, colperm, x, n, 0, skip64, st));
+    LCHK(launch_scatter_sol(n, nrhs, batch, z, colperm, x, n, 0, skip64, st, (const double *)c->dev.sscale.p));
     if (eta_dev) {
         LCHK(launch_fill_f64(norms, 3 * (int64_t)nrhs * batch, 0.0, st));
         LCHK(launch_residual_batched(n, nrhs, batch, nnzA, Acp, Acj, Acsrc, Aval, x, b, r, norms, skip64, st));
@@ -1452,6 +1568,7 @@ int cktlu_get_stats(const cktlu_ctx *c, cktlu_stats *out) {
         out->fill_amd = c->an.fill_amd;
         out->fill_amf = c->an.fill_amf;
         out->fill_nd = c->an.fill_nd;
+        out->fill_ndc = c->an.fill_ndc;
     }
     return CKTLU_OK;
 }

@@ -254,14 +254,16 @@ __device__ __forceinline__ float recip(float u) { return 1.0f / u; }
 // U(kk+1, c) = x(kk+1, c) - L(kk+1, kk) U(kk, c) formed as lane kk+1 would, so the
 // result equals two single steps bit for bit.  The factors go to blk[col][row] (unit
 // L below the diagonal, U on and above it) and invd[k] = 1 / u_kk.
-template <typename T, int W>
-__device__ void diag_factor_part(const T *S, int D, int p, int nb, T (*blk)[NB + 1], T *invd, T (*lbuf)[WAVE]) {
+// The block's element (row r, column c) comes from elem(c, r), which returns the identity's
+// element outside the nb x nb block.
+template <typename T, int W, typename Elem>
+__device__ void diag_factor_part(Elem elem, T (*blk)[NB + 1], T *invd, T (*lbuf)[WAVE]) {
     const int lane = threadIdx.x & (WAVE - 1);
     T v[NB / 4];
 #pragma unroll
     for (int j = 0; j < NB / 4; j++) {
         const int c = 8 * (j / 2) + 2 * W + (j % 2);
-        v[j] = (lane < nb && c < nb) ? S[(size_t)(p + c) * D + p + lane] : (lane == c ? T(1) : T(0));
+        v[j] = elem(c, lane);
     }
 #pragma unroll
     for (int kk = 0; kk < NB; kk += 2) {
@@ -301,14 +303,22 @@ __device__ void diag_factor_part(const T *S, int D, int p, int nb, T (*blk)[NB +
 #pragma unroll
     for (int j = 0; j < NB / 4; j++) blk[8 * (j / 2) + 2 * W + (j % 2)][lane] = v[j];
 }
+template <typename T, typename Elem>
+__device__ void diag_factor_elem(Elem elem, T (*blk)[NB + 1], T *invd, T (*lbuf)[WAVE], int wv) {
+    switch (wv) {
+    case 0: diag_factor_part<T, 0>(elem, blk, invd, lbuf); break;
+    case 1: diag_factor_part<T, 1>(elem, blk, invd, lbuf); break;
+    case 2: diag_factor_part<T, 2>(elem, blk, invd, lbuf); break;
+    default: diag_factor_part<T, 3>(elem, blk, invd, lbuf); break;
+    }
+}
+// the nb x nb diagonal block at (p, p) of S (column-major, leading dimension D)
 template <typename T>
 __device__ void diag_factor(const T *S, int D, int p, int nb, T (*blk)[NB + 1], T *invd, T (*lbuf)[WAVE], int wv) {
-    switch (wv) {
-    case 0: diag_factor_part<T, 0>(S, D, p, nb, blk, invd, lbuf); break;
-    case 1: diag_factor_part<T, 1>(S, D, p, nb, blk, invd, lbuf); break;
-    case 2: diag_factor_part<T, 2>(S, D, p, nb, blk, invd, lbuf); break;
-    default: diag_factor_part<T, 3>(S, D, p, nb, blk, invd, lbuf); break;
-    }
+    auto elem = [=](int c, int r) -> T {
+        return (r < nb && c < nb) ? S[(size_t)(p + c) * D + p + r] : (r == c ? T(1) : T(0));
+    };
+    diag_factor_elem<T>(elem, blk, invd, lbuf, wv);
 }
 
 // k of step s for lane group g (= lane / 16) in a 16 x 16 x 4 MFMA chain: the
@@ -947,6 +957,244 @@ __global__ void zero_int_kernel(int *v) { *v = 0; }
 
 inline dim3 wave_grid(int64_t waves) { return dim3((unsigned)((waves + 3) / 4)); }
 
+// ------------------------------------------------------------- supernodal sweep
+// A supernode is a run of sparse columns [s0, s0 + w) with a dense diagonal block and the
+// same rows R (m of them) below it; column s0 + c keeps rows s0 .. s0 + w - 1 and then R
+// contiguously from offset sn_cb[s0 + c] of its storage.  The interrupt word of an
+// instance holds 1 + the level whose pivot test failed first: a level's work stops only
+// for failures of earlier levels, so which columns finish does not depend on timing.
+__device__ __forceinline__ bool sn_stopped(const RefactorArgs &a, int inst, int lev) {
+    if (!a.check) return false;
+    const int st = a.ctrl[1 + inst];
+    return st != 0 && st <= lev;
+}
+__device__ __forceinline__ void sn_fail(const RefactorArgs &a, int inst, int lev, int col) {
+    atomicMin(&a.ctrl[1 + a.batch + inst], col);
+    atomicExch(&a.ctrl[1 + inst], lev + 1);          // every writer of this launch writes the same
+}
+
+// Singleton supernodes (one column j): the pivot test on its values before division
+// (Section II-A: fail when x(j) is zero or not finite, or |x(j)| < eps max |L part|),
+// then L(:,j) = x / x(j).  One wavefront per (column, instance), four loads in flight.
+template <typename T>
+__global__ __launch_bounds__(256) void sn_single_kernel(RefactorArgs a, int lev, int sbeg, int send) {
+    const int lane = threadIdx.x & (WAVE - 1);
+    const int64_t w = (int64_t)blockIdx.x * 4 + threadIdx.x / WAVE;
+    if (w >= (int64_t)(send - sbeg) * a.batch) return;
+    const int inst = (int)(w % a.batch);
+    const int j = a.sn_rec[4 * a.sn_seq[sbeg + (int)(w / a.batch)]];
+    if (sn_stopped(a, inst, lev)) return;
+    T *x = reinterpret_cast<T *>(a.Fx) + (size_t)inst * a.nnzF + a.Dp[j];
+    const int nu = a.nU[j], len = a.Dlen[j];
+    const T d = x[nu - 1];
+    double m = 0.0;
+    for (int i0 = nu; i0 < len; i0 += 4 * WAVE) {
+        T v[4];
+#pragma unroll
+        for (int u = 0; u < 4; u++) v[u] = i0 + u * WAVE + lane < len ? x[i0 + u * WAVE + lane] : T(0);
+#pragma unroll
+        for (int u = 0; u < 4; u++) {
+            m = nanmax(m, fabs((double)v[u]));
+            if (i0 + u * WAVE + lane < len) x[i0 + u * WAVE + lane] = v[u] / d;
+        }
+    }
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) m = nanmax(m, __shfl_xor(m, off));
+    if (lane != 0) return;
+    const double dd = (double)d;
+    if (a.check && (!isfinite(dd) || dd == 0.0 || !isfinite(m) || fabs(dd) < a.eps * m || j == a.force_fail_col))
+        sn_fail(a, inst, lev, j);
+    else
+        a.done[(size_t)inst * a.n + j] = (int)a.epoch;
+}
+
+// Supernode panels (w >= 2): one workgroup per (supernode, instance).  The w x w diagonal
+// block (padded with the identity) is factored without pivoting by the dense block's
+// four-wavefront step (diag_factor_part) and written back; then L21 = A21 U11^-1 for the
+// m rows of R, sixteen rows per wavefront per pass, by the block substitution of
+// dlu_panel_kernel (X_b = (A_b - sum X_b' U_b'b) U_bb^-1 on the matrix cores).  The pivot
+// test of column c is the dense block's: |u_cc| >= eps |u_cc| max_{i>c} |L(i,c)|, i.e. on
+// the values L(i,c) u_cc before division.
+template <typename T>
+__global__ __launch_bounds__(256) void sn_panel_kernel(RefactorArgs a, int lev, int pbeg) {
+    typedef typename std::conditional<sizeof(T) == 8, d4, f4>::type acc_t;
+    __shared__ T blk[NB][NB + 1];
+    __shared__ T invd[NB];
+    __shared__ T winv[4][16][17];
+    __shared__ T lbuf[4][WAVE];
+    __shared__ double cmax[4][NB];
+    const int inst = blockIdx.y;
+    if (sn_stopped(a, inst, lev)) return;                 // uniform over the workgroup
+    const int tid = threadIdx.x, lane = tid & (WAVE - 1);
+    const int wv = __builtin_amdgcn_readfirstlane(tid / WAVE);
+    const int i16 = lane & 15, g = lane >> 4;
+    const int4 rec = reinterpret_cast<const int4 *>(a.sn_rec)[a.sn_seq[pbeg + (int)blockIdx.x]];
+    const int s0 = rec.x, w = rec.y, m = rec.z;
+    const int *cb = a.sn_cb + s0;
+    T *Fx = reinterpret_cast<T *>(a.Fx) + (size_t)inst * a.nnzF;
+    auto elem = [=](int c, int r) -> T { return (r < w && c < w) ? Fx[cb[c] + r] : (r == c ? T(1) : T(0)); };
+    diag_factor_elem<T>(elem, blk, invd, lbuf, wv);
+    __syncthreads();
+    for (int e = tid; e < w * w; e += 256) {
+        const int c = e / w, r = e - c * w;
+        Fx[cb[c] + r] = blk[c][r];
+    }
+    {
+        // inverse of U11's diagonal block b = wv (upper, from the bottom), column i16
+        const int o = 16 * wv;
+        T x[16];
+#pragma unroll
+        for (int i = 15; i >= 0; i--) {
+            T acc = i == i16 ? T(1) : T(0);
+#pragma unroll
+            for (int k = i + 1; k < 16; k++) acc = fma(-blk[o + k][o + i], x[k], acc);
+            x[i] = acc * invd[o + i];
+        }
+        if (lane < 16) {
+#pragma unroll
+            for (int i = 0; i < 16; i++) winv[wv][i][i16] = x[i];
+        }
+    }
+    __syncthreads();
+    double mx[4][4];
+#pragma unroll
+    for (int b = 0; b < 4; b++)
+#pragma unroll
+        for (int q = 0; q < 4; q++) mx[b][q] = 0.0;
+    for (int r0 = 16 * wv; r0 < m; r0 += 64) {           // uniform per wavefront
+        const int row = r0 + i16;
+        const bool in = row < m;
+        acc_t t[4];
+#pragma unroll
+        for (int b = 0; b < 4; b++)
+#pragma unroll
+            for (int q = 0; q < 4; q++) {
+                const int k = 16 * b + kidx<T>(q, g);
+                t[b][q] = (in && k < w) ? Fx[cb[k] + w + row] : T(0);
+            }
+        acc_t x[4];
+#pragma unroll
+        for (int b = 0; b < 4; b++) {
+#pragma unroll
+            for (int bp = 0; bp < b; bp++)
+#pragma unroll
+                for (int s = 0; s < 4; s++) {
+                    const int k = 16 * bp + kidx<T>(s, g);
+                    t[b] = mfma16<T>(-blk[16 * b + i16][k], x[bp][s], t[b]);   // (U_b'b)^T (i16, k)
+                }
+            acc_t z = {};
+#pragma unroll
+            for (int s = 0; s < 4; s++) z = mfma16<T>(winv[b][kidx<T>(s, g)][i16], t[b][s], z);
+            x[b] = z;
+        }
+#pragma unroll
+        for (int b = 0; b < 4; b++)
+#pragma unroll
+            for (int q = 0; q < 4; q++) {
+                const int k = 16 * b + kidx<T>(q, g);
+                if (in && k < w) {
+                    Fx[cb[k] + w + row] = x[b][q];
+                    mx[b][q] = nanmax(mx[b][q], fabs((double)x[b][q]));
+                }
+            }
+    }
+    // column maxima over the rows of R: across the sixteen lanes of a group, then wavefronts
+#pragma unroll
+    for (int b = 0; b < 4; b++)
+#pragma unroll
+        for (int q = 0; q < 4; q++) {
+            double v = mx[b][q];
+#pragma unroll
+            for (int off = 1; off < 16; off <<= 1) v = nanmax(v, __shfl_xor(v, off));
+            if (i16 == 0) cmax[wv][16 * b + kidx<T>(q, g)] = v;
+        }
+    __syncthreads();
+    if (tid < w) {
+        const int c = tid;
+        double M = nanmax(nanmax(cmax[0][c], cmax[1][c]), nanmax(cmax[2][c], cmax[3][c]));
+        for (int r = c + 1; r < w; r++) M = nanmax(M, fabs((double)blk[c][r]));
+        const double piv = (double)blk[c][c];
+        const double xmax = fabs(piv) * M;
+        const int col = s0 + c;
+        if (a.check && (!isfinite(piv) || piv == 0.0 || !isfinite(xmax) || fabs(piv) < a.eps * xmax ||
+                        col == a.force_fail_col))
+            sn_fail(a, inst, lev, col);
+        else
+            a.done[(size_t)inst * a.n + col] = (int)a.epoch;
+    }
+}
+
+// Update tasks of a level: one wavefront per (target column k, instance) applies the level's
+// supernodes S with U(S, k) != 0 in ascending order.  Per supernode, on the suffix of S's
+// rows present in k (len rows, lane c holds row c): U(S, k) = L11^-1 x_k(S) by substitution
+// (eight L11 loads in flight), written to k; then x_k(R) -= L21 U(S, k), a wavefront of rows
+// of R at a time (rows < T only for a dense-block target: its rows >= T are the Schur
+// update's), their slots in k from sn_map.  Rows of one supernode are distinct, so the
+// stores of one pass never feed its own loads.
+template <typename T>
+__global__ __launch_bounds__(256) void sn_update_kernel(RefactorArgs a, int lev, int tbeg, int tend) {
+    const int lane = threadIdx.x & (WAVE - 1);
+    const int64_t wid = (int64_t)blockIdx.x * 4 + threadIdx.x / WAVE;
+    if (wid >= (int64_t)(tend - tbeg) * a.batch) return;
+    const int inst = (int)(wid % a.batch);
+    const int t = tbeg + (int)(wid / a.batch);
+    if (sn_stopped(a, inst, lev)) return;
+    T *Fx = reinterpret_cast<T *>(a.Fx) + (size_t)inst * a.nnzF;
+    const int4 tk = reinterpret_cast<const int4 *>(a.sn_task)[t];
+    T *xk = Fx + tk.y;
+    for (int it = tk.z; it < tk.w; it++) {
+        const int4 item = reinterpret_cast<const int4 *>(a.sn_item)[it];
+        const int4 rec = reinterpret_cast<const int4 *>(a.sn_rec)[item.x];
+        const int w = rec.y, len = item.z, off = w - len, mcnt = item.w;
+        const int *cb = a.sn_cb + rec.x + off;           // the suffix's columns
+        const int *mp = a.sn_map + a.sn_moff[it];
+        T xv = lane < len ? xk[item.y + lane] : T(0);
+        for (int c0 = 0; c0 < len; c0 += 8) {
+            T lv[8];
+#pragma unroll
+            for (int u = 0; u < 8; u++) {
+                const int c = c0 + u;
+                lv[u] = (c < len && lane > c && lane < len) ? Fx[cb[c] + off + lane] : T(0);
+            }
+#pragma unroll
+            for (int u = 0; u < 8; u++) {
+                const int c = c0 + u;
+                if (c < len) {
+                    const T uc = readlane(xv, c);
+                    if (lane > c) xv = fma(-lv[u], uc, xv);
+                }
+            }
+        }
+        if (lane < len) xk[item.y + lane] = xv;
+        for (int r0 = 0; r0 < mcnt; r0 += 2 * WAVE) {      // two rows per lane: 16 loads in flight
+            const int ra = r0 + lane, rb = r0 + WAVE + lane;
+            const bool ina = ra < mcnt, inb = rb < mcnt;
+            const int sla = ina ? mp[ra] : 0, slb = inb ? mp[rb] : 0;
+            T acca = T(0), accb = T(0);
+            for (int c0 = 0; c0 < len; c0 += 8) {
+                T la[8], lb[8];
+#pragma unroll
+                for (int u = 0; u < 8; u++) {
+                    const int c = c0 + u;
+                    la[u] = (ina && c < len) ? Fx[cb[c] + w + ra] : T(0);
+                    lb[u] = (inb && c < len) ? Fx[cb[c] + w + rb] : T(0);
+                }
+#pragma unroll
+                for (int u = 0; u < 8; u++)
+                    if (c0 + u < len) {
+                        const T uc = readlane(xv, c0 + u);
+                        acca = fma(la[u], uc, acca);
+                        accb = fma(lb[u], uc, accb);
+                    }
+            }
+            if (ina) xk[sla] -= acca;
+            if (inb) xk[slb] -= accb;
+        }
+        __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "workgroup");
+        __builtin_amdgcn_wave_barrier();
+    }
+}
+
 }  // namespace
 
 int launch_dense_gather(const DenseArgs &a, void *stream) {
@@ -1124,6 +1372,33 @@ int launch_dense_solve(const DenseArgs &a, double *y, int nrhs, const int *skip,
         default: return (int)hipErrorInvalidValue;
     }
 #undef CKTLU_DS
+    return (int)hipGetLastError();
+}
+
+int launch_sn_panels(const RefactorArgs &a, int lev, int sbeg, int smid, int send, void *stream) {
+    hipStream_t st = (hipStream_t)stream;
+    const int64_t waves = (int64_t)(smid - sbeg) * a.batch;
+    if (waves > 0) {
+        const dim3 grid((unsigned)((waves + 3) / 4));
+        if (a.fp32) hipLaunchKernelGGL(sn_single_kernel<float>, grid, dim3(256), 0, st, a, lev, sbeg, smid);
+        else hipLaunchKernelGGL(sn_single_kernel<double>, grid, dim3(256), 0, st, a, lev, sbeg, smid);
+        const hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return (int)e;
+    }
+    if (send > smid) {
+        const dim3 grid((unsigned)(send - smid), (unsigned)a.batch);
+        if (a.fp32) hipLaunchKernelGGL(sn_panel_kernel<float>, grid, dim3(256), 0, st, a, lev, smid);
+        else hipLaunchKernelGGL(sn_panel_kernel<double>, grid, dim3(256), 0, st, a, lev, smid);
+    }
+    return (int)hipGetLastError();
+}
+
+int launch_sn_updates(const RefactorArgs &a, int lev, int tbeg, int tend, void *stream) {
+    const int64_t waves = (int64_t)(tend - tbeg) * a.batch;
+    if (waves == 0) return 0;
+    const dim3 grid((unsigned)((waves + 3) / 4));
+    if (a.fp32) hipLaunchKernelGGL(sn_update_kernel<float>, grid, dim3(256), 0, (hipStream_t)stream, a, lev, tbeg, tend);
+    else hipLaunchKernelGGL(sn_update_kernel<double>, grid, dim3(256), 0, (hipStream_t)stream, a, lev, tbeg, tend);
     return (int)hipGetLastError();
 }
 

@@ -22,25 +22,37 @@ struct Analysis {
     int etree_height = 0;
     int ordering_used = 0;                 // CKTLU_ORDER_* that produced colperm
     int64_t fill_amd = -1, fill_amf = -1, fill_nd = -1;  // nnz of the symbolic Cholesky of B + B' under each
+    int64_t fill_ndc = -1;                 // ... under ND + constrained AMD
+    int static_pivoting_used = 0;          // 0 structural transversal, 1 max-product matching, 2 and scaling
+    std::vector<double> rscale, cscale;    // static scaling of A's rows and columns (empty: none)
 };
 
 int validate_csc(int n, const int32_t *colptr, const int32_t *rowind);
 bool max_transversal(int n, const std::vector<int> &Ap, const std::vector<int> &Ai,
                      std::vector<int> &match_of_col);
+// group != nullptr: constrained minimum degree, the nodes eliminated in ascending group
 void amd_order(int n, const std::vector<int> &Sp, const std::vector<int> &Si,
-               std::vector<int> &perm, bool amf = false);
-// nested dissection with AMD on parts of at most `leaf` nodes
+               std::vector<int> &perm, bool amf = false, const std::vector<int> *group = nullptr);
+// nested dissection with AMD on parts of at most `leaf` nodes; with groups, the leaves are not
+// ordered and every node receives the number of its part in the dissection's order instead
 constexpr int kNdLeaf = 4096;
 void nd_order(int n, const std::vector<int> &Sp, const std::vector<int> &Si, std::vector<int> &perm,
-              int leaf);
+              int leaf, std::vector<int> *groups = nullptr);
+// nested dissection to parts of at most `leaf` nodes, then constrained AMD over the parts
+void nd_camd_order(int n, const std::vector<int> &Sp, const std::vector<int> &Si, std::vector<int> &perm,
+                   int leaf);
 // nnz (diagonal included) of the Cholesky factor of the symmetric pattern (Sp, Si)
 // eliminated in the order perm: elimination tree, then one row subtree per row
 int64_t symbolic_cholesky_nnz(int n, const std::vector<int> &Sp, const std::vector<int> &Si,
                               const std::vector<int> &perm);
 void column_etree(int n, const std::vector<int> &Hp, const std::vector<int> &Hi,
                   std::vector<int> &parent);
+// values (may be null) and static_pivoting (0, 1 matching, 2 matching and scaling) select the
+// value-based static pivoting of Section III-A instead of the structural transversal
+bool max_product_matching(int n, const std::vector<int> &Ap, const std::vector<int> &Ai, const double *Ax,
+                          std::vector<int> &match_of_col, std::vector<double> &lnr, std::vector<double> &lnc);
 int run_analysis(Analysis &an, int n, const int32_t *colptr, const int32_t *rowind,
-                 int ordering, int transversal);
+                 int ordering, int transversal, const double *values = nullptr, int static_pivoting = 0);
 
 // ------------------------------------------------------------------ factor
 // Factors in position space.  Column k of the combined storage F holds the
@@ -129,6 +141,36 @@ struct Schedule {
     int tail0 = 0;                            // first column of the densely factored tail (n = none)
     std::vector<int> tail_rend;               // rows i >= tail0: L entries of columns < tail0 end here
     std::vector<int> lrec, urec, Lrjs, Urjs;  // the solve levels packed for the device
+    // ---- supernodal sweep (options.sweep_supernodes >= 0).  A supernode is a run of sparse
+    // columns [s0, s0 + w) (w <= 64) whose diagonal block is dense and whose L columns share the
+    // rows R below it (L(:,j) = {j+1} u L(:,j+1)).  Level = longest path over the supernodes
+    // whose columns update its columns (U entries) or whose rows feed its rows (L entries).
+    // Level l runs two launches: the panels of its supernodes (dense LU of the diagonal block,
+    // L21 = A21 U11^-1, the pivot test), then update tasks: a task owns one target column k and
+    // applies every supernode S of level l with U(S, k) != 0 in ascending order: U(S, k) =
+    // L11^-1 x_k(S) on the suffix of S's rows present in k, then x_k(R) -= L21 U(S, k).
+    int sn_count = 0, sn_levels = 0;
+    std::vector<int> sn_rec;                  // int4 per supernode {s0, w, m = |R|, 0}
+    std::vector<int> sn_cb;                   // per sparse column j: device offset of row s0(j) in column j
+    std::vector<int> sn_lvl;                  // [sn_levels+1] supernodes of level l: sn_seq[sn_lvl[l] ..]
+    std::vector<int> sn_seq;                  // supernode ids by level: singletons first, then panels
+    std::vector<int> sn_lvl_single;           // [sn_levels] singletons of level l: sn_seq[sn_lvl[l] ..
+                                              // sn_lvl_single[l]), panels after
+    std::vector<int> sn_task_lvl;             // [sn_levels+1] tasks of level l
+    std::vector<int> sn_task;                 // int4 per task {k, Dp[k], first item, end item}
+    std::vector<int> sn_item;                 // int4 per item {supernode, slot of its first row in k, rows
+                                              // of S present in k (the suffix), rows of R updated}
+    std::vector<int64_t> sn_moff;             // per item: its slots of R's rows in column k in sn_map
+    std::vector<int> sn_map;
+    int64_t sn_items = 0;
+    double sn_macs = 0;                       // multiply-adds of the supernodal updates and panels
+    // supernodal solves of the rows [0, T): a supernode's rows first pull their entries outside
+    // its diagonal block (L: columns < s0; U: columns >= s0 + w), then its dense triangle is
+    // solved.  Level = longest path over the supernodes those entries reach.  Per level of the
+    // L (U) solve: its supernodes in snl_seq (snu_seq) [snl_lvl[l], snl_lvl[l+1]), singletons
+    // first up to snl_single[l].
+    int snl_levels = 0, snu_levels = 0;
+    std::vector<int> snl_lvl, snl_single, snl_seq, snu_lvl, snu_single, snu_seq;
 };
 
 // map_cap: most slot-map entries to build (-1: what a quarter of the device's free memory
@@ -150,6 +192,9 @@ struct Device {
     DevBuf colrec, task8, item4, smap, tmoff, tail_nb, l21, schur_parts, schur_add, schur_scr;
     DevBuf lrec, urec, Lrjs, Urjs, lsptr, usptr, rowperm, colperm_sol;
     DevBuf Acp, Acj, Acsrc;
+    DevBuf sn_rec, sn_cb, sn_seq, sn_task, sn_item, sn_moff, sn_map;   // supernodal sweep
+    DevBuf snl_seq, snu_seq, Lrp, Urp;                                 // supernodal solves
+    DevBuf ascale, gscale, sscale;     // static scaling: per nonzero of A, per solve row, per solve column
     // values and status words
     DevBuf Fx64, Fx32;                 // factor values (FP64 always; FP32 in FP32_IR mode)
     DevBuf Aval;                       // copy of the last values (FP64) for residuals
@@ -197,6 +242,11 @@ struct RefactorArgs {
     unsigned epoch;
     int force_fail_col;
     int fp32, check;
+    // supernodal sweep (see Schedule): supernode records, per-column offset of the supernode's
+    // first row, supernodes by level, update tasks, their items and the rows' slots
+    const int *sn_rec, *sn_cb, *sn_seq, *sn_task, *sn_item, *sn_map;
+    const int64_t *sn_moff;
+    const double *ascale;      // static scaling per nonzero of A (row scale x column scale), or null
 };
 
 // Zero every factor column and scatter the matrix values into it.
@@ -207,6 +257,11 @@ int launch_dense_reinit(const RefactorArgs &a, void *stream);
 // the previous level seq[pbeg, pend) (L = x / pivot), and update tasks [tbeg, tend).
 int launch_refactor_level(const RefactorArgs &a, int cbeg, int cend, int pbeg, int pend, int tbeg,
                           int tend, int lev, void *stream);
+// Supernodal sweep, level `lev` (dense.hip): the singleton supernodes sn_seq[sbeg, smid) (pivot test
+// and L = x / pivot, a wavefront each) and the panels sn_seq[smid, send) (a workgroup each: dense
+// LU of the diagonal block, L21 = A21 U11^-1, pivot test); then the level's update tasks [tbeg, tend).
+int launch_sn_panels(const RefactorArgs &a, int lev, int sbeg, int smid, int send, void *stream);
+int launch_sn_updates(const RefactorArgs &a, int lev, int tbeg, int tend, void *stream);
 int launch_reset_ctrl(int *ctrl, int nwords, int value, void *stream);
 // status[i] = firstfail[i] == INT_MAX ? -1 : firstfail[i]
 int launch_status_out(const int *firstfail, int *status, int batch, void *stream);
@@ -220,7 +275,15 @@ struct SolveArgs {
     int fp32;
     double *y;                 // batch x n rows of YS doubles, rhs r in slot r
     const int *skip;           // per-instance status (-1 = solve), may be null
+    // supernodal solves: supernode records and first-row offsets (as RefactorArgs), and the row
+    // pointers of the strictly lower L and strictly upper U (entries in Lrjs / Urjs)
+    const int *sn_rec, *sn_cb, *Lrp, *Urp;
 };
+
+// One level of the supernodal L (U) solve: the singleton supernodes seq[sbeg, smid) and the
+// panel supernodes seq[smid, send).
+int launch_sn_lsolve(const SolveArgs &a, const int *seq, int sbeg, int smid, int send, void *stream);
+int launch_sn_usolve(const SolveArgs &a, const int *seq, int sbeg, int smid, int send, void *stream);
 
 // Solve positions [lbeg, lend) of lrec / urec (one level of the solve graph).
 int launch_lsolve_level(const SolveArgs &a, int lbeg, int lend, void *stream);
@@ -234,10 +297,10 @@ int launch_lsolve_chain(const SolveArgs &a, const int *lvptr, int l0, int l1, vo
 int launch_usolve_chain(const SolveArgs &a, const int *lvptr, int l0, int l1, void *stream);
 // y[((i*n + k)*YS + r] = b[(i*nrhs + r)*ldb + perm[k]] for r < nrhs, 0 for r < solve_slots(nrhs)
 int launch_gather_rhs(int n, int nrhs, int batch, const double *b, int64_t ldb, const int *perm,
-                      double *y, void *stream);
+                      double *y, void *stream, const double *scale = nullptr);
 // x[(i*nrhs + r)*ldx + perm[k]] (+)= y[(i*n + k)*YS + r]
 int launch_scatter_sol(int n, int nrhs, int batch, const double *z, const int *perm, double *x,
-                       int64_t ldx, int accumulate, const int *skip, void *stream);
+                       int64_t ldx, int accumulate, const int *skip, void *stream, const double *scale = nullptr);
 // r = b - A x (user space, FP64), per rhs; also writes |r|_inf, |x|_inf, |b|_inf maxima
 int launch_residual(int n, int nrhs, const int *Acp, const int *Acj, const int *Acsrc,
                     const double *Aval, const double *x, int64_t ldx, const double *b,

@@ -78,7 +78,7 @@ __global__ __launch_bounds__(WG) void refactor_init_kernel(RefactorArgs a) {
     if (k < a.T) {
         for (int i = lane; i < len; i += WAVE) x[i] = T(0);
         wave_sync();
-        for (int p = a.Ap[c] + lane; p < a.Ap[c + 1]; p += WAVE) x[a.amap[p]] = (T)Av[p];
+        for (int p = a.Ap[c] + lane; p < a.Ap[c + 1]; p += WAVE) x[a.amap[p]] = (T)(a.ascale ? Av[p] * a.ascale[p] : Av[p]);
         return;
     }
     T *Sk = reinterpret_cast<T *>(a.S) + (size_t)inst * a.D * a.D + (size_t)(k - a.T) * a.D;
@@ -89,8 +89,9 @@ __global__ __launch_bounds__(WG) void refactor_init_kernel(RefactorArgs a) {
     for (int p = a.Ap[c] + lane; p < a.Ap[c + 1]; p += WAVE) {
         const int slot = a.amap[p];
         const int r = rows[slot];
-        if (r >= a.T) Sk[r - a.T] = (T)Av[p];
-        else x[slot] = (T)Av[p];
+        const double v = a.ascale ? Av[p] * a.ascale[p] : Av[p];
+        if (r >= a.T) Sk[r - a.T] = (T)v;
+        else x[slot] = (T)v;
     }
 }
 
@@ -108,7 +109,7 @@ __global__ __launch_bounds__(WG) void dense_reinit_kernel(RefactorArgs a) {
     wave_sync();
     for (int p = a.Ap[c] + lane; p < a.Ap[c + 1]; p += WAVE) {
         const int r = rows[a.amap[p]];
-        if (r >= a.T) Sk[r - a.T] = a.Aval[p];
+        if (r >= a.T) Sk[r - a.T] = a.ascale ? a.Aval[p] * a.ascale[p] : a.Aval[p];
     }
 }
 
@@ -433,22 +434,17 @@ int launch_refactor_level(const RefactorArgs &a, int cbeg, int cend, int pbeg, i
 // y holds one cache line (YS doubles) per row and instance: y[(inst*n + i)*YS + r].
 // One row of a triangular solve, by one wavefront: its record, then its entries
 // {column, value position}, then the values and the y rows they multiply.
-template <typename T, int NR, bool UPPER>
-__device__ __forceinline__ void solve_row(const SolveArgs &a, int inst, int pos, int lane) {
-    const int4 rec = reinterpret_cast<const int4 *>(UPPER ? a.urec : a.lrec)[pos];
-    const int2 *rjs = reinterpret_cast<const int2 *>(UPPER ? a.Urjs : a.Lrjs);
-    const T *Fx = reinterpret_cast<const T *>(a.Fx) + (size_t)inst * a.nnzF;
-    double *y = a.y + (size_t)inst * a.n * YS;
-    const int i = rec.x;
-    const double diag = UPPER ? (double)Fx[rec.w] : 1.0;
-    const double yi = lane < NR ? y[(size_t)i * YS + lane] : 0.0;
-    double acc[NR];
+// sum over the row entries [beg, end) of value * y(column), per right-hand side, over the
+// wavefront (two entries in flight per lane), totals in every lane
+template <typename T, int NR>
+__device__ __forceinline__ void row_pull(const int2 *rjs, const T *Fx, const double *y, int beg, int end, int lane,
+                                         double (&acc)[NR]) {
 #pragma unroll
     for (int r = 0; r < NR; r++) acc[r] = 0.0;
-    for (int q0 = rec.y; q0 < rec.z; q0 += 2 * WAVE) {   // two entries in flight per lane
+    for (int q0 = beg; q0 < end; q0 += 2 * WAVE) {
         int2 e[2];
 #pragma unroll
-        for (int u = 0; u < 2; u++) e[u] = q0 + u * WAVE + lane < rec.z ? rjs[q0 + u * WAVE + lane] : make_int2(-1, 0);
+        for (int u = 0; u < 2; u++) e[u] = q0 + u * WAVE + lane < end ? rjs[q0 + u * WAVE + lane] : make_int2(-1, 0);
         double l[2];
 #pragma unroll
         for (int u = 0; u < 2; u++) l[u] = e[u].x >= 0 ? (double)Fx[e[u].y] : 0.0;
@@ -461,6 +457,18 @@ __device__ __forceinline__ void solve_row(const SolveArgs &a, int inst, int pos,
     }
 #pragma unroll
     for (int r = 0; r < NR; r++) acc[r] = wave_sum(acc[r]);
+}
+
+template <typename T, int NR, bool UPPER>
+__device__ __forceinline__ void solve_row_rec(const SolveArgs &a, int inst, int4 rec, int lane) {
+    const int2 *rjs = reinterpret_cast<const int2 *>(UPPER ? a.Urjs : a.Lrjs);
+    const T *Fx = reinterpret_cast<const T *>(a.Fx) + (size_t)inst * a.nnzF;
+    double *y = a.y + (size_t)inst * a.n * YS;
+    const int i = rec.x;
+    const double diag = UPPER ? (double)Fx[rec.w] : 1.0;
+    const double yi = lane < NR ? y[(size_t)i * YS + lane] : 0.0;
+    double acc[NR];
+    row_pull<T, NR>(rjs, Fx, y, rec.y, rec.z, lane, acc);
     double mine = acc[0];
 #pragma unroll
     for (int r = 1; r < NR; r++)
@@ -470,6 +478,11 @@ __device__ __forceinline__ void solve_row(const SolveArgs &a, int inst, int pos,
         if (UPPER) v = v / diag;
         y[(size_t)i * YS + lane] = v;
     }
+}
+
+template <typename T, int NR, bool UPPER>
+__device__ __forceinline__ void solve_row(const SolveArgs &a, int inst, int pos, int lane) {
+    solve_row_rec<T, NR, UPPER>(a, inst, reinterpret_cast<const int4 *>(UPPER ? a.urec : a.lrec)[pos], lane);
 }
 
 // One level: one wavefront per (row, instance).
@@ -534,6 +547,146 @@ __global__ __launch_bounds__(kSolveRowWG) void trisolve_rowwg_kernel(SolveArgs a
         if (UPPER) v = v / (double)Fx[rec.w];
         y[(size_t)i * YS + lane] = v;
     }
+}
+
+// ------------------------------------------------------------ supernodal solves
+__device__ __forceinline__ double readlane_f64(double v, int l) {
+    const long long b = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_readlane((int)b, l);
+    const int hi = __builtin_amdgcn_readlane((int)(b >> 32), l);
+    return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+
+// One level of the supernodal L (U) solve.  Singleton supernodes (one row i) are solved by a
+// wavefront per (row, instance) as in the row kernel; a panel supernode [s0, s0 + w) by a
+// workgroup per (supernode, instance): its wavefronts pull the rows' entries outside the
+// diagonal block (L: columns < s0, the row's first entries; U: columns >= s0 + w, its last
+// entries) into LDS, then one wavefront solves the dense triangle, lane c holding row s0 + c:
+// L: y_c -= L(c, c') y_c' for c' < c in ascending c' (unit diagonal); U: x_c = t_c / U(c, c)
+// in descending c, then t_c'' -= U(c'', c) x_c for c'' < c.  The triangle's entries come from
+// the factor columns (sn_cb: offset of the supernode's first row in each column).
+template <typename T, int NR, bool UPPER>
+__global__ __launch_bounds__(WG) void sn_solve_kernel(SolveArgs a, const int *seq, int sbeg, int smid, int send) {
+    __shared__ double tv[64][8];
+    const int lane = threadIdx.x & (WAVE - 1), wv = threadIdx.x / WAVE;
+    const int64_t nsingle = (int64_t)(smid - sbeg) * a.batch;
+    const int64_t nsw = (nsingle + WAVES - 1) / WAVES;
+    const int *rp = UPPER ? a.Urp : a.Lrp;
+    if ((int64_t)blockIdx.x < nsw) {
+        const int64_t w = (int64_t)blockIdx.x * WAVES + wv;
+        if (w >= nsingle) return;
+        const int inst = (int)(w % a.batch);
+        if (a.skip && a.skip[inst] != -1) return;
+        const int i = a.sn_rec[4 * seq[sbeg + (int)(w / a.batch)]];
+        solve_row_rec<T, NR, UPPER>(a, inst, make_int4(i, rp[i], rp[i + 1], a.sn_cb[i]), lane);
+        return;
+    }
+    const int64_t pu = (int64_t)blockIdx.x - nsw;
+    const int inst = (int)(pu % a.batch);
+    if (a.skip && a.skip[inst] != -1) return;            // the whole workgroup
+    const int4 rec = reinterpret_cast<const int4 *>(a.sn_rec)[seq[smid + (int)(pu / a.batch)]];
+    const int s0 = rec.x, w = rec.y;
+    const int2 *rjs = reinterpret_cast<const int2 *>(UPPER ? a.Urjs : a.Lrjs);
+    const T *Fx = reinterpret_cast<const T *>(a.Fx) + (size_t)inst * a.nnzF;
+    double *y = a.y + (size_t)inst * a.n * YS;
+    for (int c = wv; c < w; c += WAVES) {
+        const int i = s0 + c;
+        const int beg = UPPER ? rp[i] + (w - 1 - c) : rp[i];
+        const int end = UPPER ? rp[i + 1] : rp[i + 1] - c;
+        const double yi = lane < NR ? y[(size_t)i * YS + lane] : 0.0;
+        double acc[NR];
+        row_pull<T, NR>(rjs, Fx, y, beg, end, lane, acc);
+        double mine = acc[0];
+#pragma unroll
+        for (int r = 1; r < NR; r++)
+            if (lane == r) mine = acc[r];
+        if (lane < NR) tv[c][lane] = yi - mine;
+    }
+    __syncthreads();
+    if (wv != 0) return;
+    const int *cb = a.sn_cb + s0;
+    double t[NR];
+#pragma unroll
+    for (int r = 0; r < NR; r++) t[r] = lane < w ? tv[lane][r] : 0.0;
+    if (!UPPER) {
+        for (int c0 = 0; c0 < w; c0 += 8) {
+            double lv[8];
+#pragma unroll
+            for (int u = 0; u < 8; u++) {
+                const int c = c0 + u;
+                lv[u] = (c < w && lane > c && lane < w) ? (double)Fx[cb[c] + lane] : 0.0;
+            }
+#pragma unroll
+            for (int u = 0; u < 8; u++) {
+                const int c = c0 + u;
+                if (c < w) {
+#pragma unroll
+                    for (int r = 0; r < NR; r++) {
+                        const double uc = readlane_f64(t[r], c);
+                        if (lane > c) t[r] = fma(-lv[u], uc, t[r]);
+                    }
+                }
+            }
+        }
+    } else {
+        for (int c0 = w - 1; c0 >= 0; c0 -= 8) {
+            double lv[8], dg[8];
+#pragma unroll
+            for (int u = 0; u < 8; u++) {
+                const int c = c0 - u;
+                lv[u] = (c >= 0 && lane < c) ? (double)Fx[cb[c] + lane] : 0.0;
+                dg[u] = c >= 0 ? (double)Fx[cb[c] + c] : 1.0;
+            }
+#pragma unroll
+            for (int u = 0; u < 8; u++) {
+                const int c = c0 - u;
+                if (c >= 0) {
+#pragma unroll
+                    for (int r = 0; r < NR; r++) {
+                        if (lane == c) t[r] = t[r] / dg[u];
+                        const double xc = readlane_f64(t[r], c);
+                        if (lane < c) t[r] = fma(-lv[u], xc, t[r]);
+                    }
+                }
+            }
+        }
+    }
+    if (lane < w) {
+#pragma unroll
+        for (int r = 0; r < NR; r++) y[(size_t)(s0 + lane) * YS + r] = t[r];
+    }
+}
+
+template <bool UPPER>
+static int launch_sn_solve_impl(const SolveArgs &a, const int *seq, int sbeg, int smid, int send, void *stream) {
+    const int64_t nsw = ((int64_t)(smid - sbeg) * a.batch + WAVES - 1) / WAVES;
+    const int64_t units = nsw + (int64_t)(send - smid) * a.batch;
+    if (units == 0) return 0;
+    const dim3 grid((unsigned)units);
+    hipStream_t st = (hipStream_t)stream;
+#define CKTLU_SNS_CASE(NRV)                                                                             \
+    case NRV:                                                                                           \
+        if (a.fp32)                                                                                     \
+            hipLaunchKernelGGL((sn_solve_kernel<float, NRV, UPPER>), grid, dim3(WG), 0, st, a, seq, sbeg, smid, send); \
+        else                                                                                            \
+            hipLaunchKernelGGL((sn_solve_kernel<double, NRV, UPPER>), grid, dim3(WG), 0, st, a, seq, sbeg, smid, send); \
+        break;
+    switch (a.nrhs) {
+        CKTLU_SNS_CASE(1)
+        CKTLU_SNS_CASE(2)
+        CKTLU_SNS_CASE(4)
+        CKTLU_SNS_CASE(8)
+        default: return (int)hipErrorInvalidValue;
+    }
+#undef CKTLU_SNS_CASE
+    return (int)hipGetLastError();
+}
+
+int launch_sn_lsolve(const SolveArgs &a, const int *seq, int sbeg, int smid, int send, void *stream) {
+    return launch_sn_solve_impl<false>(a, seq, sbeg, smid, send, stream);
+}
+int launch_sn_usolve(const SolveArgs &a, const int *seq, int sbeg, int smid, int send, void *stream) {
+    return launch_sn_solve_impl<true>(a, seq, sbeg, smid, send, stream);
 }
 
 // A run of narrow levels [l0, l1): one workgroup per instance takes the rows of a
@@ -644,8 +797,9 @@ int launch_usolve_level(const SolveArgs &a, int lbeg, int lend, void *stream) {
 
 // --------------------------------------------------------------- helpers
 // fills the solve slots [0, solve_slots(nrhs)) of each row; slots past nrhs get zeros
+// scale (may be null): per solve position, the static row scaling of its user row
 __global__ void gather_rhs_kernel(int n, int nrhs, int nslots, int batch, const double *b, int64_t ldb,
-                                  const int *perm, double *y) {
+                                  const int *perm, double *y, const double *scale) {
     const int64_t total = (int64_t)n * nslots * batch;
     for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < total;
          t += (int64_t)gridDim.x * blockDim.x) {
@@ -653,12 +807,14 @@ __global__ void gather_rhs_kernel(int n, int nrhs, int nslots, int batch, const 
         const int64_t ik = t / nslots;
         const int k = (int)(ik % n);
         const int64_t i = ik / n;
-        y[ik * YS + r] = r < nrhs ? b[(i * nrhs + r) * ldb + perm[k]] : 0.0;
+        const double v = r < nrhs ? b[(i * nrhs + r) * ldb + perm[k]] : 0.0;
+        y[ik * YS + r] = scale ? v * scale[k] : v;
     }
 }
 
+// scale (may be null): per solve position, the static column scaling of its user column
 __global__ void scatter_sol_kernel(int n, int nrhs, int batch, const double *z, const int *perm,
-                                   double *x, int64_t ldx, int accumulate, const int *skip) {
+                                   double *x, int64_t ldx, int accumulate, const int *skip, const double *scale) {
     const int64_t total = (int64_t)n * nrhs * batch;
     for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < total;
          t += (int64_t)gridDim.x * blockDim.x) {
@@ -668,7 +824,7 @@ __global__ void scatter_sol_kernel(int n, int nrhs, int batch, const double *z, 
         const int64_t i = ik / n;
         if (skip && skip[i] != -1) continue;
         double *dst = x + (i * nrhs + r) * ldx + perm[k];
-        const double v = z[ik * YS + r];
+        const double v = scale ? z[ik * YS + r] * scale[k] : z[ik * YS + r];
         *dst = accumulate ? *dst + v : v;
     }
 }
@@ -681,17 +837,17 @@ static inline int grid_for(int64_t total, int block) {
 }
 
 int launch_gather_rhs(int n, int nrhs, int batch, const double *b, int64_t ldb, const int *perm,
-                      double *y, void *stream) {
+                      double *y, void *stream, const double *scale) {
     const int ns = solve_slots(nrhs);
     hipLaunchKernelGGL(gather_rhs_kernel, dim3(grid_for((int64_t)n * ns * batch, 256)), dim3(256), 0,
-                       (hipStream_t)stream, n, nrhs, ns, batch, b, ldb, perm, y);
+                       (hipStream_t)stream, n, nrhs, ns, batch, b, ldb, perm, y, scale);
     return (int)hipGetLastError();
 }
 
 int launch_scatter_sol(int n, int nrhs, int batch, const double *z, const int *perm, double *x,
-                       int64_t ldx, int accumulate, const int *skip, void *stream) {
+                       int64_t ldx, int accumulate, const int *skip, void *stream, const double *scale) {
     hipLaunchKernelGGL(scatter_sol_kernel, dim3(grid_for((int64_t)n * nrhs * batch, 256)), dim3(256), 0,
-                       (hipStream_t)stream, n, nrhs, batch, z, perm, x, ldx, accumulate, skip);
+                       (hipStream_t)stream, n, nrhs, batch, z, perm, x, ldx, accumulate, skip, scale);
     return (int)hipGetLastError();
 }
 

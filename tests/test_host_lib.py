@@ -256,9 +256,11 @@ def test_combined_ordering_auto(oracle_mod, name, make):
         fa = _chol_nnz_brute(_sym_pattern(c, amd.analysis(with_pivots=False)))
         ff = _chol_nnz_brute(_sym_pattern(c, amf.analysis(with_pivots=False)))
         assert st["fill_amd"] == fa and st["fill_amf"] == ff, (st["fill_amd"], fa, st["fill_amf"], ff)
-    want = ck.CKTLU_ORDER_AMF if st["fill_amf"] < st["fill_amd"] else ck.CKTLU_ORDER_AMD
+    fills = {ck.CKTLU_ORDER_AMD: st["fill_amd"], ck.CKTLU_ORDER_AMF: st["fill_amf"], ck.CKTLU_ORDER_ND: st["fill_nd"],
+             ck.CKTLU_ORDER_ND_CAMD: st["fill_ndc"]}
+    want = min(m for m, f in fills.items() if f == min(fills.values()))   # ties: the earlier method
     assert st["ordering_used"] == want
-    same = amf if want == ck.CKTLU_ORDER_AMF else amd
+    same = _analysed(c, ordering=want)
     assert np.array_equal(auto.analysis(with_pivots=False)["colperm"], same.analysis(with_pivots=False)["colperm"])
     auto.factorize_host(c.values)
     a = auto.analysis()
@@ -284,7 +286,8 @@ def test_nested_dissection_ordering(oracle_mod):
     assert fnd < _chol_nnz_brute(_sym_pattern(c, nat.analysis(with_pivots=False)))
     st = _analysed(c, ordering=ck.CKTLU_ORDER_AUTO).stats()
     assert st["fill_nd"] == fnd
-    fills = {ck.CKTLU_ORDER_AMD: st["fill_amd"], ck.CKTLU_ORDER_AMF: st["fill_amf"], ck.CKTLU_ORDER_ND: st["fill_nd"]}
+    fills = {ck.CKTLU_ORDER_AMD: st["fill_amd"], ck.CKTLU_ORDER_AMF: st["fill_amf"], ck.CKTLU_ORDER_ND: st["fill_nd"],
+             ck.CKTLU_ORDER_ND_CAMD: st["fill_ndc"]}
     best = min(fills.values())
     assert st["ordering_used"] == min(m for m, f in fills.items() if f == best)
     nd.factorize_host(c.values)
@@ -342,3 +345,125 @@ def test_phase_work_counts_vs_oracle(oracle_mod):
     st = got[200]
     assert st["entries_sweep"] + st["entries_dense"] == nlu
     assert st["macs_sweep"] + st["macs_schur"] + st["macs_dense"] == macs
+
+
+def test_nd_constrained_amd_ordering(oracle_mod):
+    """ND followed by constrained AMD (Section III-A): a valid permutation whose parts keep
+    the dissection's order (the separators of the plain ND order stay after the leaves they
+    split, so the first node of the last separator is placed no earlier than in ND), its
+    symbolic fill equals a brute-force elimination in that order, it does not exceed plain
+    ND's fill on this grid, and the host factorization under it matches the oracle."""
+    c = mnagen.power_grid(72, 72, seed=3)
+    ndc = _analysed(c, ordering=ck.CKTLU_ORDER_ND_CAMD)
+    assert ndc.stats()["ordering_used"] == ck.CKTLU_ORDER_ND_CAMD
+    a = ndc.analysis(with_pivots=False)
+    assert np.array_equal(np.sort(a["colperm"]), np.arange(c.n))
+    f = _chol_nnz_brute(_sym_pattern(c, a))
+    st = _analysed(c, ordering=ck.CKTLU_ORDER_AUTO).stats()
+    assert st["fill_ndc"] == f
+    assert f <= st["fill_nd"], (f, st["fill_nd"])
+    # the top separator of the dissection is the same node set, eliminated last in both
+    nd = _analysed(c, ordering=ck.CKTLU_ORDER_ND).analysis(with_pivots=False)["colperm"]
+    pos_nd = np.empty(c.n, np.int64); pos_nd[nd] = np.arange(c.n)
+    pos_c = np.empty(c.n, np.int64); pos_c[a["colperm"]] = np.arange(c.n)
+    m = 60                                              # the top separator's nodes are among the last ones
+    tail_nd = set(nd[-m:].tolist())
+    assert all(pos_c[v] >= c.n - 2 * m for v in tail_nd)
+    ndc.factorize_host(c.values)
+    a = ndc.analysis()
+    lu = oracle_mod.gp_lu(c.n, c.colptr, c.rowind, c.values, a["rowperm_pre"], a["colperm"], 1e-3)
+    assert lu.status == 0 and np.array_equal(a["pivrow"], lu.pivrow)
+    compare_factors(ndc.factors(), lu)
+
+
+def _matched_log_product(c, a):
+    """sum_j ln |A(rowperm_pre[j], colperm[j])|: the log of the product of the diagonal
+    magnitudes after the transversal."""
+    A = c.to_scipy().tocsc()
+    return float(sum(np.log(abs(A[a["rowperm_pre"][j], a["colperm"][j]])) for j in range(c.n)))
+
+
+def _dominant_rows(c, seed, k=2, f=100.0):
+    """The values of c with k random rows scaled by f: most column maxima then share
+    a row, so the matching needs augmenting paths and potentials beyond a greedy start."""
+    rng = np.random.default_rng(seed)
+    rows = rng.choice(c.n, size=min(k, c.n), replace=False)
+    v = c.values.copy()
+    v[np.isin(c.rowind, rows)] *= f
+    c.values = v
+    return c
+
+
+def test_static_pivoting_matching_bruteforce():
+    """Maximum-product matching (Section III-A) against brute force over all permutations
+    on small matrices, half of them with dominant rows (the greedy start fails there)."""
+    import itertools
+    checked = 0
+    for seed in range(60):
+        n = 3 + seed % 5
+        c = mnagen.random_pattern(n, 0.5, 8000 + seed)
+        if seed % 2:
+            c = _dominant_rows(c, seed, k=1 + seed % 2)
+        A = c.to_scipy().toarray()
+        best = -np.inf
+        for perm in itertools.permutations(range(n)):
+            v = A[list(perm), range(n)]
+            if np.all(v != 0):
+                best = max(best, float(np.sum(np.log(np.abs(v)))))
+        if not np.isfinite(best):
+            continue
+        s = ck.SparseLU(c.n, c.colptr, c.rowind, static_pivoting=1, values=c.values)
+        got = _matched_log_product(c, s.analysis(with_pivots=False))
+        assert abs(got - best) <= 1e-12 * max(1.0, abs(best)), (seed, got, best)
+        checked += 1
+    assert checked >= 45
+
+
+def test_static_pivoting_matching_vs_assignment_and_scaling():
+    """The matching's log-product equals scipy's linear_sum_assignment optimum on the
+    costs -ln|a_ij| (zeros excluded); the scaling makes every matched entry 1 in
+    magnitude and every entry at most 1."""
+    from scipy.optimize import linear_sum_assignment
+    for seed in range(16):
+        c = mnagen.random_pattern(40 + 10 * seed, 0.05, 9000 + seed)
+        if seed % 2:
+            c = _dominant_rows(c, seed, k=3 + seed % 4)
+        A = c.to_scipy().toarray()
+        cost = np.where(A != 0, -np.log(np.abs(np.where(A != 0, A, 1.0))), 1e6)
+        r, col = linear_sum_assignment(cost)
+        if np.any(A[r, col] == 0):
+            continue
+        best = -float(cost[r, col].sum())
+        s = ck.SparseLU(c.n, c.colptr, c.rowind, static_pivoting=2, values=c.values)
+        a = s.analysis(with_pivots=False)
+        got = _matched_log_product(c, a)
+        assert abs(got - best) <= 1e-10 * max(1.0, abs(best)), (seed, got, best)
+        rs, cs = s.scaling()
+        As = np.abs(rs[:, None] * A * cs[None, :])
+        assert As.max() <= 1 + 1e-12
+        diag = As[a["rowperm_pre"], a["colperm"]]
+        assert np.abs(diag - 1).max() <= 1e-12
+
+
+def test_static_pivoting_factorization_vs_oracle(oracle_mod):
+    """With matching and scaling the library factors S_r P A S_c: the host factorization
+    equals the oracle's on that matrix (pattern and pivots exact, values within the
+    per-entry bound), and a mesh with voltage sources (zero diagonal entries) needs no
+    exchange any more."""
+    for c in (mnagen.mesh_vsrc(12, 12, 4, seed=3), mnagen.mesh_transistor(20, 20, seed=4)):
+        s = ck.SparseLU(c.n, c.colptr, c.rowind, static_pivoting=2, values=c.values)
+        s.factorize_host(c.values)
+        a = s.analysis()
+        rs, cs = s.scaling()
+        cols = np.repeat(np.arange(c.n), np.diff(c.colptr))
+        vs = c.values * rs[c.rowind] * cs[cols]
+        lu = oracle_mod.gp_lu(c.n, c.colptr, c.rowind, vs, a["rowperm_pre"], a["colperm"], 1e-3)
+        assert lu.status == 0 and np.array_equal(a["pivrow"], lu.pivrow)
+        compare_factors(s.factors(), lu)
+    c = mnagen.mesh_vsrc(12, 12, 4, seed=3)
+    plain = oracle_mod.gp_lu(c.n, c.colptr, c.rowind, c.values, None, None, 1e-3)
+    assert plain.nswaps > 0                         # the zero diagonals of the sources force exchanges
+    s = ck.SparseLU(c.n, c.colptr, c.rowind, static_pivoting=1, values=c.values)
+    a = s.analysis(with_pivots=False)
+    lu = oracle_mod.gp_lu(c.n, c.colptr, c.rowind, c.values, a["rowperm_pre"], a["colperm"], 1e-3)
+    assert lu.status == 0 and lu.nswaps == 0
