@@ -181,13 +181,20 @@ FP32_MFMA_PEAK_TFS = 157.3
 # measured HBM traffic of the dominant kernel: written from two rocprofv3 --pmc runs
 # (FETCH_SIZE, WRITE_SIZE) with the sha256 of the kernel source they were taken on
 PROFILES = os.path.join(ROOT, "profiles")
-KERNEL_SRC = os.path.join(ROOT, "paper_2411_14082_amd", "csrc", "kernels.hip")
+CSRC = os.path.join(ROOT, "paper_2411_14082_amd", "csrc")
+# kernel -> (source file, first line of its section, first line after it)
+KERNEL_SECTIONS = {
+    "sn_sweep": ("dense.hip", "// ------------------------------------------------------------- supernodal sweep", None),
+    "refactor_level_kernel": ("kernels.hip", "constexpr int kItemChunk", "__global__ void reset_ctrl_kernel"),
+}
 
 
-def kernel_source_hash(begin="constexpr int kItemChunk", end="__global__ void reset_ctrl_kernel"):
-    """sha256 of the dominant kernel's source section."""
-    txt = open(KERNEL_SRC).read()
-    a, z = txt.find(begin), txt.find(end)
+def kernel_source_hash(kernel):
+    """sha256 of the source section of `kernel` (see KERNEL_SECTIONS)."""
+    fname, begin, end = KERNEL_SECTIONS[kernel]
+    txt = open(os.path.join(CSRC, fname)).read()
+    a = txt.find(begin)
+    z = txt.find(end, a + 1) if end else len(txt)
     return hashlib.sha256(txt[a:z].encode()).hexdigest() if 0 <= a < z else None
 
 
@@ -202,11 +209,20 @@ def measured_traffic(fname, kernel, launches_per_step):
     m_sha = re.search(r"%s_source_sha256:\s*([0-9a-f]{64})" % kernel, txt)
     m_b = re.search(r"hbm_bytes_per_launch:\s*([0-9.eE+]+)", txt)
     m_l = re.search(r"launches_per_step:\s*([0-9]+)", txt)
-    if not m_sha or not m_b or not m_l or kernel_source_hash() != m_sha.group(1):
+    if not m_sha or not m_b or not m_l or kernel_source_hash(kernel) != m_sha.group(1):
         return None
     if int(m_l.group(1)) != int(launches_per_step):
         return None
     return float(m_b.group(1))
+
+
+def solve_passes(nrhs):
+    """Solve passes of the library for nrhs right-hand sides (chunks of 8, 4, 2, 1)."""
+    k = 0
+    while nrhs > 0:
+        nrhs -= 8 if nrhs >= 8 else 4 if nrhs >= 4 else 2 if nrhs >= 2 else 1
+        k += 1
+    return k
 
 
 def log(*a):
@@ -459,28 +475,39 @@ def main():
     steps_per_s = args.steps / res64["wall"]
     t_step = res64["wall"] / args.steps
     # whole step on the compulsory bytes: refactorization (A values and map, factor index and
-    # value per entry) and one solve pass per right-hand side (factor index and value per entry)
-    b_step = st["bytes_refactor"] + nrhs * st["bytes_solve"]
+    # value per entry); each solve pass (up to eight right-hand sides) reads the factor once and
+    # every right-hand side adds its rows (b read, x written, permutations)
+    passes = solve_passes(nrhs)
+    fac_read = st["bytes_solve"] - 24.0 * c.n
+    b_step = st["bytes_refactor"] + passes * fac_read + nrhs * 24.0 * c.n
     roofline_step = dict(bound="hbm", achieved=b_step / t_step / 1e9, peak=HBM_PEAK_GBS, unit="GB/s",
                          frac=b_step / t_step / 1e9 / HBM_PEAK_GBS, bytes_per_step=b_step,
                          bytes_model="12 B per A nonzero + 12 B per factor entry (refactorization) + "
-                                     "(12 B per factor entry + 24 B per row) per right-hand side")
-    # dominant kernel: the sparse sweep (refactor_level_kernel); its launches run back to back
-    # on the library's stream, so the average launch lasts sweep_ms / launches
+                                     "12 B per factor entry per solve pass of up to 8 right-hand sides + "
+                                     "24 B per row per right-hand side")
+    # dominant kernel: the sparse sweep.  Supernodal: sn_panel_kernel and sn_update_kernel, one of
+    # each per level; column sweep: refactor_level_kernel, one per level.  Its launches run back
+    # to back on the library's stream, so the average launch lasts sweep_ms / launches
+    snodal = int(st.get("sweep_supernodes", 0)) > 0
+    kname = "sn_sweep" if snodal else "refactor_level_kernel"
+    kdesc = ("sn_panel_kernel + sn_update_kernel (supernodal sweep, one of each per level)" if snodal
+             else "refactor_level_kernel")
     sweep_launch_s = tm["sweep_ms"] * 1e-3 / max(1, tm["sweep_launches"])
     launches = max(1, int(st["sweep_launches"]))
     alg_per_launch = st["alg_bytes_refactor_sweep"] / launches
     achieved = alg_per_launch / sweep_launch_s / 1e9
-    traffic = measured_traffic("refactor_level_kernel_traffic_%s.txt" % args.workload, "refactor_level_kernel",
-                               launches)
-    roofline = dict(bound="hbm", kernel="refactor_level_kernel", achieved=achieved, peak=HBM_PEAK_GBS,
+    traffic = measured_traffic("%s_traffic_%s.txt" % (kname, args.workload), kname, launches)
+    roofline = dict(bound="hbm", kernel=kdesc, achieved=achieved, peak=HBM_PEAK_GBS,
                     unit="GB/s", frac=achieved / HBM_PEAK_GBS, traffic=traffic,
                     algorithmic_bytes_per_launch=alg_per_launch, avg_launch_us=sweep_launch_s * 1e6,
                     launches_per_refactor=launches,
                     bytes_model="12 B per factor entry the sweep finalises (row index read, value written)",
                     traffic_model_bytes_per_launch=st["bytes_sweep"] / launches,
-                    traffic_model="28 B per sweep multiply-add + 24 B per L entry of a sparse column "
-                                  "(every operand from HBM, no cache reuse)",
+                    traffic_model=("8 B per panel and update multiply-add + 20 B per row of R updated + "
+                                   "24 B per L entry of a sparse column (every operand from HBM, no cache reuse)"
+                                   if snodal else
+                                   "28 B per sweep multiply-add + 24 B per L entry of a sparse column "
+                                   "(every operand from HBM, no cache reuse)"),
                     traffic_over_algorithmic=(traffic / alg_per_launch) if traffic else None)
     nref = max(1, tm["refactors"])
     dense_s = tm["dense_ms"] * 1e-3 / nref

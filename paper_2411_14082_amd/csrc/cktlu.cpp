@@ -175,7 +175,8 @@ DevBuf *all_buffers(Device &d, int i) {
                      &d.colperm_sol, &d.Acp, &d.Acj, &d.Acsrc, &d.Fx64, &d.Fx32, &d.Aval, &d.done,
                      &d.ctrl, &d.vec, &d.S, &d.Dg, &d.Dinv, &d.sn_rec, &d.sn_cb, &d.sn_seq, &d.sn_task,
                      &d.sn_item, &d.sn_moff, &d.sn_map, &d.snl_seq, &d.snu_seq, &d.Lrp, &d.Urp,
-                     &d.ascale, &d.gscale, &d.sscale};
+                     &d.ascale, &d.gscale, &d.sscale, &d.schur_sn_items,
+                     &d.snl_unit, &d.snu_unit, &d.sn_part, &d.sn_cnt, &d.sn_punit, &d.sn_sunit};
     const int cnt = (int)(sizeof(all) / sizeof(all[0]));
     return i < cnt ? all[i] : nullptr;
 }
@@ -249,6 +250,19 @@ int ensure_batch(cktlu_ctx *c, int batch) {
             (rc = dalloc(d.schur_scr, (size_t)c->s.schur_nscr * D * sizeof(double) * batch)))
             return rc;
     }
+    // split supernodal solves: partial sums (512 doubles per scratch block and instance) and one
+    // arrival counter per supernode, direction and instance (zero between launches)
+    dfree(d.sn_part);
+    dfree(d.sn_cnt);
+    // (also the column maxima of split wide panels in the sweep, 64 doubles per block, and their
+    // counters after the solves' two segments)
+    const size_t part = std::max((size_t)std::max(c->s.snl_nscr, c->s.snu_nscr) * 512, (size_t)c->s.sn_pnscr * 64);
+    if (part > 0) {
+        if ((rc = dalloc(d.sn_part, part * batch * sizeof(double)))) return rc;
+        const size_t cb = (size_t)3 * c->s.sn_count * batch * sizeof(int);
+        if ((rc = dalloc(d.sn_cnt, cb))) return rc;
+        HIPCHK(hipMemsetAsync(d.sn_cnt.p, 0, cb, st));
+    }
     d.S_prec = -1;
     d.batch_cap = batch;
     return CKTLU_OK;
@@ -296,6 +310,7 @@ int upload_all(cktlu_ctx *c) {
     if ((rc = upload(d.sn_item, s.sn_item, st))) return rc;
     if ((rc = upload(d.sn_moff, s.sn_moff, st))) return rc;
     if ((rc = upload(d.sn_map, s.sn_map, st))) return rc;
+    if ((rc = upload(d.schur_sn_items, s.schur_sn_items, st))) return rc;
     if (!c->an.rscale.empty()) {
         // static scaling A' = S_r P A S_c: per nonzero of A, per solve row and per solve column
         const Analysis &an = c->an;
@@ -317,6 +332,10 @@ int upload_all(cktlu_ctx *c) {
     }
     if ((rc = upload(d.snl_seq, s.snl_seq, st))) return rc;
     if ((rc = upload(d.snu_seq, s.snu_seq, st))) return rc;
+    if ((rc = upload(d.snl_unit, s.snl_unit, st))) return rc;
+    if ((rc = upload(d.sn_punit, s.sn_punit, st))) return rc;
+    if ((rc = upload(d.sn_sunit, s.sn_sunit, st))) return rc;
+    if ((rc = upload(d.snu_unit, s.snu_unit, st))) return rc;
     if ((rc = upload(d.Lrp, s.Lrp, st))) return rc;
     if ((rc = upload(d.Urp, s.Urp, st))) return rc;
     if ((rc = upload(d.lrec, s.lrec, st))) return rc;
@@ -354,6 +373,13 @@ int upload_all(cktlu_ctx *c) {
     c->dev_values_newer = false;
     return CKTLU_OK;
 }
+
+// Launches of supernodal sweep level l: singletons, small panels, panels, update tasks.
+int sn_level_launches(const Schedule &s, int l) {
+    return (s.sn_lvl_single[l] > s.sn_lvl[l]) + (s.sn_lvl_small[l] > s.sn_lvl_single[l]) +
+           (s.sn_pulvl[l + 1] > s.sn_pulvl[l]) + (s.sn_task_lvl[l + 1] > s.sn_task_lvl[l]);
+}
+
 
 void fill_stats_pattern(cktlu_ctx *c) {
     cktlu_stats &t = c->stats;
@@ -401,9 +427,7 @@ void fill_stats_pattern(cktlu_ctx *c) {
                           (l > 0 ? s.lvl_ptr[l] - s.lvl_ptr[l - 1] : 0);
         if (w > 0) t.sweep_launches++;
     }
-    for (int l = 0; l < s.sn_levels; l++)
-        t.sweep_launches += (s.sn_lvl_single[l] > s.sn_lvl[l]) + (s.sn_lvl[l + 1] > s.sn_lvl_single[l]) +
-                            (s.sn_task_lvl[l + 1] > s.sn_task_lvl[l]);
+    for (int l = 0; l < s.sn_levels; l++) t.sweep_launches += sn_level_launches(s, l);
     t.sweep_supernodes = s.sn_count;
     t.sweep_levels = s.sn_count ? s.sn_levels : s.n_rlevels;
     const int64_t panels = (int64_t)((D + kDenseBlock - 1) / kDenseBlock);
@@ -523,6 +547,18 @@ int ensure_S(cktlu_ctx *c, bool fp32, int batch) {
     return CKTLU_OK;
 }
 
+// S -= L21 U12: by supernodes when the sweep is supernodal, by bridge columns otherwise
+// (the schedule builds the parts of the matching kind).  Returns the launch's error code.
+int schur_update(cktlu_ctx *c, const DenseArgs &da, hipStream_t st) {
+    const Device &d = c->dev;
+    const Schedule &s = c->s;
+    const int np = (int)(s.schur_parts.size() / 4), na = (int)(s.schur_add.size() / 4);
+    if (s.sn_count > 0)
+        return launch_schur_sn(da, (const int *)d.schur_parts.p, np, (const int *)d.schur_add.p, na,
+                               (const int *)d.schur_sn_items.p, (const int *)d.sn_rec.p, (const int *)d.sn_cb.p, st);
+    return launch_schur(da, (const int *)d.schur_parts.p, np, (const int *)d.schur_add.p, na, (const int *)d.l21.p, st);
+}
+
 // The level-by-level refactorization of `batch` instances (cluster mode):
 // one launch per dependency level of the sparse columns, then the dense block.
 int run_refactor(cktlu_ctx *c, int batch, const double *values_dev, bool fp32, bool check, int force_col) {
@@ -536,6 +572,7 @@ int run_refactor(cktlu_ctx *c, int batch, const double *values_dev, bool fp32, b
     LCHK(launch_reset_ctrl((int *)d.ctrl.p, 1 + 2 * batch, INT_MAX, st));
     const Schedule &s = c->s;
     RefactorArgs a;
+    std::memset(&a, 0, sizeof(a));
     a.n = c->an.n;
     a.batch = batch;
     a.seq = (const int *)d.seq.p;
@@ -578,12 +615,17 @@ int run_refactor(cktlu_ctx *c, int batch, const double *values_dev, bool fp32, b
     a.sn_item = (const int *)d.sn_item.p;
     a.sn_map = (const int *)d.sn_map.p;
     a.sn_moff = (const int64_t *)d.sn_moff.p;
+    a.sn_punit = (const int *)d.sn_punit.p;
+    a.sn_sunit = (const int *)d.sn_sunit.p;
+    a.sn_pmax = (double *)d.sn_part.p;
+    a.sn_pcnt = d.sn_cnt.p ? (int *)d.sn_cnt.p + (size_t)2 * s.sn_count * batch : nullptr;
     // supernodal sweep: per level, the supernodes' panels, then the updates they apply
     for (int l = 0; l < s.sn_levels; l++) {
-        LCHK(launch_sn_panels(a, l, s.sn_lvl[l], s.sn_lvl_single[l], s.sn_lvl[l + 1], st));
-        LCHK(launch_sn_updates(a, l, s.sn_task_lvl[l], s.sn_task_lvl[l + 1], st));
-        launches += (s.sn_lvl_single[l] > s.sn_lvl[l]) + (s.sn_lvl[l + 1] > s.sn_lvl_single[l]) +
-                    (s.sn_task_lvl[l + 1] > s.sn_task_lvl[l]);
+        LCHK(launch_sn_panels(a, l, s.sn_lvl[l], s.sn_lvl_single[l], s.sn_sulvl[l], s.sn_sulvl[l + 1], s.sn_pulvl[l],
+                              s.sn_pulvl[l + 1], st));
+        LCHK(launch_sn_updates(a, l, s.sn_task_lvl[l], s.sn_task_heavy[l], s.sn_task_tiny[l], s.sn_task_lvl[l + 1],
+                               st));
+        launches += sn_level_launches(s, l);
     }
     // column sweep: level l checks level l, normalises level l-1, runs the update tasks of
     // level l; then the last level is normalised
@@ -613,8 +655,7 @@ int run_refactor(cktlu_ctx *c, int batch, const double *values_dev, bool fp32, b
             la.nev = (int)c->la_events.size();
         }
         t0 = phase_begin(c);
-        LCHK(launch_schur(da, (const int *)d.schur_parts.p, (int)(c->s.schur_parts.size() / 4),
-                          (const int *)d.schur_add.p, (int)(c->s.schur_add.size() / 4), (const int *)d.l21.p, st));
+        LCHK(schur_update(c, da, st));
         phase_end(c, t0, PH_SCHUR, c->s.schur_add.empty() ? 1 : 2);
         t0 = phase_begin(c);
         LCHK(launch_dense_refactor(da, false, &la, st));
@@ -653,8 +694,7 @@ int dense_pivot_refactor(cktlu_ctx *c, const std::vector<double> &vals, cktlu_re
     int *swp = (int *)tmp.p, *dinfo = swp + D;
     const auto t0 = std::chrono::steady_clock::now();
     LCHK(launch_dense_reinit(ra, st));
-    LCHK(launch_schur(da, (const int *)d.schur_parts.p, (int)(c->s.schur_parts.size() / 4),
-                      (const int *)d.schur_add.p, (int)(c->s.schur_add.size() / 4), (const int *)d.l21.p, st));
+    LCHK(schur_update(c, da, st));
     LCHK(launch_dense_pivoted_lu(da, swp, dinfo, st));
     std::vector<double> Sh((size_t)D * D);
     std::vector<int> sw(D + 1);
@@ -818,6 +858,7 @@ int tri_solves(cktlu_ctx *c, int nrhs, int batch, double *z, bool fp32, const in
     a.sn_cb = (const int *)d.sn_cb.p;
     a.Lrp = (const int *)d.Lrp.p;
     a.Urp = (const int *)d.Urp.p;
+    a.sn_part = (double *)d.sn_part.p;
     const Schedule &s = c->s;
     const bool snodal = s.sn_count > 0;
     // sparse L levels (the last one holds the dense rows: their entries in sparse columns); with
@@ -825,7 +866,8 @@ int tri_solves(cktlu_ctx *c, int nrhs, int batch, double *z, bool fp32, const in
     hipEvent_t t0 = phase_begin(c);
     int launches = 0;
     for (int l = 0; snodal && l < s.snl_levels; l++, launches++)
-        LCHK(launch_sn_lsolve(a, (const int *)d.snl_seq.p, s.snl_lvl[l], s.snl_single[l], s.snl_lvl[l + 1], st));
+        LCHK(launch_sn_lsolve(a, (const int *)d.snl_seq.p, (const int *)d.snl_unit.p, s.snl_lvl[l], s.snl_single[l],
+                              s.snl_ulvl[l], s.snl_ulvl[l + 1], (int *)d.sn_cnt.p, st));
     const int ldense = s.tail0 < c->an.n ? (int)s.lsptr.size() - 2 : -1;   // level of the dense rows
     for (size_t g = 0; g < s.lseg.size(); g += 3) {
         const int l0 = s.lseg[g], l1 = s.lseg[g + 1];
@@ -850,7 +892,9 @@ int tri_solves(cktlu_ctx *c, int nrhs, int batch, double *z, bool fp32, const in
     t0 = phase_begin(c);
     launches = 0;
     for (int l = 0; snodal && l < s.snu_levels; l++, launches++)
-        LCHK(launch_sn_usolve(a, (const int *)d.snu_seq.p, s.snu_lvl[l], s.snu_single[l], s.snu_lvl[l + 1], st));
+        LCHK(launch_sn_usolve(a, (const int *)d.snu_seq.p, (const int *)d.snu_unit.p, s.snu_lvl[l], s.snu_single[l],
+                              s.snu_ulvl[l], s.snu_ulvl[l + 1],
+                              d.sn_cnt.p ? (int *)d.sn_cnt.p + (size_t)s.sn_count * batch : nullptr, st));
     for (size_t g = 0; !snodal && g < s.useg.size(); g += 3, launches++) {
         const int l0 = s.useg[g], l1 = s.useg[g + 1];
         if (s.useg[g + 2] == 1) LCHK(launch_usolve_chain(a, (const int *)d.usptr.p, l0, l1, st));

@@ -57,6 +57,25 @@ __device__ __forceinline__ bool sweep_failed(const DenseArgs &a, int inst) {
 // maximum that keeps a NaN
 __device__ __forceinline__ double nanmax(double a, double b) { return (a != a || a > b) ? a : b; }
 
+// Workgroups are dispatched to the eight XCDs (each with its own L2) round-robin by index:
+// renumber the n workgroups of a range so that each XCD gets a contiguous block of it, and
+// neighbouring work items (which often read the same source columns) share an L2.
+__device__ __forceinline__ unsigned xcd_contiguous(unsigned i, unsigned n) {
+    const unsigned q = n / 8, r = n % 8, x = i % 8;
+    return x * q + (x < r ? x : r) + i / 8;
+}
+
+// lane l's value (l uniform)
+__device__ __forceinline__ double readlane(double v, int l) {
+    const long long b = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_readlane((int)b, l);
+    const int hi = __builtin_amdgcn_readlane((int)(b >> 32), l);
+    return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+__device__ __forceinline__ float readlane(float v, int l) {
+    return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), l));
+}
+
 // ------------------------------------------------------------- gather / scatter
 // one wavefront per (tail column, instance)
 template <typename T>
@@ -191,6 +210,66 @@ __global__ __launch_bounds__(64) void schur_kernel(DenseArgs a, const int *parts
     }
 }
 
+// The Schur update by supernodes: a part of dense column c applies its items in order; item
+// {S, c0, g, q} is the product of the rows >= T of columns s0 + c0 .. s0 + c0 + g - 1 of
+// supernode S (shared rows, m - mlo of them, in every column after the block and the rows < T)
+// with U(those columns, k), which sit at positions q .. q + g - 1 of column k = T + c.  Two rows
+// per lane and up to sixteen loads in flight; each item reads all its targets before storing,
+// and its rows are distinct.  Part 0 works in place, later parts in zeroed scratch columns
+// that schur_add_kernel adds in part order.
+template <typename T>
+__global__ __launch_bounds__(64) void schur_sn_kernel(DenseArgs a, const int *parts, const int *items,
+                                                      const int *sn_rec, const int *sn_cb) {
+    const int lane = threadIdx.x;
+    const int inst = (int)(blockIdx.x % (unsigned)a.batch);
+    const int4 pr = reinterpret_cast<const int4 *>(parts)[blockIdx.x / (unsigned)a.batch];
+    if (sweep_failed(a, inst)) return;
+    T *col = pr.w < 0 ? inst_S<T>(a, inst) + (size_t)pr.x * a.D
+                      : reinterpret_cast<T *>(a.scr) + ((size_t)inst * a.nscr + pr.w) * a.D;
+    if (pr.w >= 0) {
+        for (int i = lane; i < a.D; i += WAVE) col[i] = T(0);
+        __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "workgroup");
+        __builtin_amdgcn_wave_barrier();
+    }
+    const T *Fx = reinterpret_cast<const T *>(a.Fx) + (size_t)inst * a.nnzF;
+    const int bb = a.Dp[a.T + pr.x];
+    for (int it = pr.y; it < pr.z; it++) {
+        const int4 item = reinterpret_cast<const int4 *>(items)[it];
+        const int4 rec = reinterpret_cast<const int4 *>(sn_rec)[item.x];
+        const int w = rec.y, mlo = rec.w, mhi = rec.z - rec.w, g = item.z;
+        const int *cb = sn_cb + rec.x + item.y;
+        const int *rows = a.Fi + sn_cb[rec.x + w - 1] + w + mlo;   // R's rows >= T
+        const T uv = lane < g ? Fx[bb + item.w + lane] : T(0);
+        for (int r0 = 0; r0 < mhi; r0 += 2 * WAVE) {
+            const int ra = r0 + lane, rb = r0 + WAVE + lane;
+            const bool ina = ra < mhi, inb = rb < mhi;
+            const int ia = ina ? rows[ra] - a.T : 0, ib = inb ? rows[rb] - a.T : 0;
+            T acca = T(0), accb = T(0);
+            for (int c0 = 0; c0 < g; c0 += 8) {
+                T la[8], lb[8];
+#pragma unroll
+                for (int u = 0; u < 8; u++) {
+                    const int cc = c0 + u;
+                    la[u] = (ina && cc < g) ? Fx[cb[cc] + w + mlo + ra] : T(0);
+                    lb[u] = (inb && cc < g) ? Fx[cb[cc] + w + mlo + rb] : T(0);
+                }
+#pragma unroll
+                for (int u = 0; u < 8; u++)
+                    if (c0 + u < g) {
+                        const T uc = readlane(uv, c0 + u);
+                        acca = fma(la[u], uc, acca);
+                        accb = fma(lb[u], uc, accb);
+                    }
+            }
+            const T ta = ina ? col[ia] : T(0), tb = inb ? col[ib] : T(0);
+            if (ina) col[ia] = ta - acca;
+            if (inb) col[ib] = tb - accb;
+        }
+        __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "workgroup");
+        __builtin_amdgcn_wave_barrier();
+    }
+}
+
 // S(:, c) += the scratch columns of c's later parts, in part order: one wavefront per
 // (split column, instance), four rows in flight per lane
 template <typename T>
@@ -219,15 +298,6 @@ __global__ __launch_bounds__(256) void schur_add_kernel(DenseArgs a, const int *
 }
 
 // ------------------------------------------------------------- blocked LU
-__device__ __forceinline__ double readlane(double v, int l) {
-    const long long b = __double_as_longlong(v);
-    const int lo = __builtin_amdgcn_readlane((int)b, l);
-    const int hi = __builtin_amdgcn_readlane((int)(b >> 32), l);
-    return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
-}
-__device__ __forceinline__ float readlane(float v, int l) {
-    return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), l));
-}
 
 // 1 / u.  FP64: the hardware reciprocal refined by two Newton-Raphson steps
 // (r <- r + r (1 - u r)), each of which doubles the correct bits, for |u| in
@@ -973,9 +1043,128 @@ __device__ __forceinline__ void sn_fail(const RefactorArgs &a, int inst, int lev
     atomicExch(&a.ctrl[1 + inst], lev + 1);          // every writer of this launch writes the same
 }
 
-// Singleton supernodes (one column j): the pivot test on its values before division
-// (Section II-A: fail when x(j) is zero or not finite, or |x(j)| < eps max |L part|),
-// then L(:,j) = x / x(j).  One wavefront per (column, instance), four loads in flight.
+// Small supernodes (w <= kSnSmallW columns): one wavefront per (supernode, instance).
+// A singleton (one column j): the pivot test on its values before division (Section II-A: fail
+// when x(j) is zero or not finite, or |x(j)| < eps max |L part|), then L(:,j) = x / x(j), four
+// loads in flight.  A small panel: lane r < w holds row r of the diagonal block, factored by
+// right-looking steps (column c: L(r, c) = x(r, c) / u_cc below the diagonal, then
+// x(r, c') -= L(r, c) U(c, c') for c' > c); the rows of R, 64 at a time (a row per lane), by
+// the same steps with U11 read from the block's lanes.  The pivot test of column c is taken
+// on its values before division: the block rows below c and every row of R.
+template <typename T>
+__device__ void sn_small_panel(const RefactorArgs &a, int inst, int lev, int s0, int w, int m, int4 un, int lane) {
+    T *Fx = reinterpret_cast<T *>(a.Fx) + (size_t)inst * a.nnzF;
+    const int *cb = a.sn_cb + s0;
+    // this unit's rows of R: slice un.y of un.z
+    const int rb = (int)((int64_t)m * un.y / un.z), re = (int)((int64_t)m * (un.y + 1) / un.z);
+    T bv[kSnSmallW];
+    double mx[kSnSmallW];
+#pragma unroll
+    for (int c = 0; c < kSnSmallW; c++) {
+        bv[c] = (c < w && lane < w) ? Fx[cb[c] + lane] : T(0);
+        mx[c] = 0.0;
+    }
+#pragma unroll
+    for (int c = 0; c < kSnSmallW; c++) {
+        if (c < w) {                                       // uniform
+            const T inv = recip(readlane(bv[c], c));
+            const bool below = lane > c && lane < w;
+            if (below) {
+                mx[c] = nanmax(mx[c], fabs((double)bv[c]));
+                bv[c] = bv[c] * inv;
+            }
+#pragma unroll
+            for (int c2 = c + 1; c2 < kSnSmallW; c2++)
+                if (c2 < w) {
+                    const T u = readlane(bv[c2], c);
+                    if (below) bv[c2] = fma(-bv[c], u, bv[c2]);
+                }
+        }
+    }
+    // the factored block goes back here when the panel is one unit, else by the last unit to
+    // finish (the others may still be reading the original block)
+    if (un.z == 1) {
+#pragma unroll
+        for (int c = 0; c < kSnSmallW; c++)
+            if (c < w && lane < w) Fx[cb[c] + lane] = bv[c];
+    }
+    for (int r0 = rb; r0 < re; r0 += WAVE) {
+        const int row = r0 + lane;
+        const bool in = row < re;
+        T x[kSnSmallW];
+#pragma unroll
+        for (int c = 0; c < kSnSmallW; c++) x[c] = (in && c < w) ? Fx[cb[c] + w + row] : T(0);
+#pragma unroll
+        for (int c = 0; c < kSnSmallW; c++) {
+            if (c < w) {
+                mx[c] = nanmax(mx[c], fabs((double)x[c]));
+                x[c] = x[c] * recip(readlane(bv[c], c));
+#pragma unroll
+                for (int c2 = c + 1; c2 < kSnSmallW; c2++)
+                    if (c2 < w) x[c2] = fma(-x[c], readlane(bv[c2], c), x[c2]);
+            }
+        }
+#pragma unroll
+        for (int c = 0; c < kSnSmallW; c++)
+            if (in && c < w) Fx[cb[c] + w + row] = x[c];
+    }
+    // column maxima over the wavefront: lane c keeps column c's
+    double M = 0.0;
+#pragma unroll
+    for (int c = 0; c < kSnSmallW; c++) {
+        if (c >= w) continue;
+        double v = mx[c];
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) v = nanmax(v, __shfl_xor(v, off));
+        if (lane == c) M = v;
+    }
+    if (un.z > 1) {
+        // slices meet as in the wide panels: the last unit to arrive takes the maxima of all
+        // slices, writes the block back and runs the test
+        double *pm = a.sn_pmax + ((size_t)un.w * a.batch + inst) * NB;
+        const size_t pstride = (size_t)a.batch * NB;
+        if (lane < w) pm[un.y * pstride + lane] = M;
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+        int prev = 0;
+        int *ctr = a.sn_pcnt + (size_t)un.x * a.batch + inst;
+        if (lane == 0) prev = __hip_atomic_fetch_add(ctr, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        prev = __shfl(prev, 0);
+        if (prev != un.z - 1) return;
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+        if (lane == 0) __hip_atomic_store(ctr, 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if (lane < w)
+            for (int p = 0; p < un.z; p++) M = nanmax(M, pm[p * pstride + lane]);
+#pragma unroll
+        for (int c = 0; c < kSnSmallW; c++)
+            if (c < w && lane < w) Fx[cb[c] + lane] = bv[c];
+    }
+    if (lane < w) {
+        // lane c holds u_cc in bv[c]
+        double piv = 0.0;
+#pragma unroll
+        for (int c = 0; c < kSnSmallW; c++)
+            if (c == lane) piv = (double)bv[c];
+        const int col = s0 + lane;
+        if (a.check && (!isfinite(piv) || piv == 0.0 || !isfinite(M) || fabs(piv) < a.eps * M ||
+                        col == a.force_fail_col))
+            sn_fail(a, inst, lev, col);
+        else
+            a.done[(size_t)inst * a.n + col] = (int)a.epoch;
+    }
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void sn_small_kernel(RefactorArgs a, int lev, int ubeg, int uend) {
+    const int lane = threadIdx.x & (WAVE - 1);
+    const int64_t w = (int64_t)blockIdx.x * 4 + threadIdx.x / WAVE;
+    if (w >= (int64_t)(uend - ubeg) * a.batch) return;
+    const int inst = (int)(w % a.batch);
+    const int4 un = reinterpret_cast<const int4 *>(a.sn_sunit)[ubeg + (int)(w / a.batch)];
+    const int4 rec = reinterpret_cast<const int4 *>(a.sn_rec)[a.sn_seq[un.x]];
+    if (sn_stopped(a, inst, lev)) return;
+    sn_small_panel<T>(a, inst, lev, rec.x, rec.y, rec.z, un, lane);
+}
+
 template <typename T>
 __global__ __launch_bounds__(256) void sn_single_kernel(RefactorArgs a, int lev, int sbeg, int send) {
     const int lane = threadIdx.x & (WAVE - 1);
@@ -1008,38 +1197,51 @@ __global__ __launch_bounds__(256) void sn_single_kernel(RefactorArgs a, int lev,
         a.done[(size_t)inst * a.n + j] = (int)a.epoch;
 }
 
-// Supernode panels (w >= 2): one workgroup per (supernode, instance).  The w x w diagonal
-// block (padded with the identity) is factored without pivoting by the dense block's
-// four-wavefront step (diag_factor_part) and written back; then L21 = A21 U11^-1 for the
-// m rows of R, sixteen rows per wavefront per pass, by the block substitution of
+// Supernode panels (w > kSnSmallW): one workgroup of eight wavefronts per (supernode, instance).
+// The w x w diagonal block (padded with the identity) is factored without pivoting by the dense
+// block's four-wavefront step (diag_factor_part; the other wavefronts wait at the same barriers)
+// and written back; then L21 = A21 U11^-1 for the m rows of R, sixteen rows per wavefront per
+// pass, by the block substitution of
 // dlu_panel_kernel (X_b = (A_b - sum X_b' U_b'b) U_bb^-1 on the matrix cores).  The pivot
 // test of column c is the dense block's: |u_cc| >= eps |u_cc| max_{i>c} |L(i,c)|, i.e. on
 // the values L(i,c) u_cc before division.
+constexpr int kSnPanelWaves = 8;                     // wavefronts of a panel workgroup (16 would spill)
 template <typename T>
-__global__ __launch_bounds__(256) void sn_panel_kernel(RefactorArgs a, int lev, int pbeg) {
+__global__ __launch_bounds__(kSnPanelWaves * WAVE) void sn_panel_kernel(RefactorArgs a, int lev, int ubeg) {
     typedef typename std::conditional<sizeof(T) == 8, d4, f4>::type acc_t;
     __shared__ T blk[NB][NB + 1];
     __shared__ T invd[NB];
     __shared__ T winv[4][16][17];
     __shared__ T lbuf[4][WAVE];
-    __shared__ double cmax[4][NB];
+    __shared__ double cmax[kSnPanelWaves][NB];
+    __shared__ int arrived;
     const int inst = blockIdx.y;
     if (sn_stopped(a, inst, lev)) return;                 // uniform over the workgroup
     const int tid = threadIdx.x, lane = tid & (WAVE - 1);
     const int wv = __builtin_amdgcn_readfirstlane(tid / WAVE);
     const int i16 = lane & 15, g = lane >> 4;
-    const int4 rec = reinterpret_cast<const int4 *>(a.sn_rec)[a.sn_seq[pbeg + (int)blockIdx.x]];
+    const int4 un = reinterpret_cast<const int4 *>(a.sn_punit)[ubeg + (int)blockIdx.x];
+    const int4 rec = reinterpret_cast<const int4 *>(a.sn_rec)[a.sn_seq[un.x]];
     const int s0 = rec.x, w = rec.y, m = rec.z;
+    // this unit's rows of R: slice un.y of un.z
+    const int rb = (int)((int64_t)m * un.y / un.z), re = (int)((int64_t)m * (un.y + 1) / un.z);
     const int *cb = a.sn_cb + s0;
     T *Fx = reinterpret_cast<T *>(a.Fx) + (size_t)inst * a.nnzF;
     auto elem = [=](int c, int r) -> T { return (r < w && c < w) ? Fx[cb[c] + r] : (r == c ? T(1) : T(0)); };
-    diag_factor_elem<T>(elem, blk, invd, lbuf, wv);
-    __syncthreads();
-    for (int e = tid; e < w * w; e += 256) {
-        const int c = e / w, r = e - c * w;
-        Fx[cb[c] + r] = blk[c][r];
+    if (wv < 4) {
+        diag_factor_elem<T>(elem, blk, invd, lbuf, wv);
+    } else {
+        for (int kk = 0; kk < NB; kk += 2) __syncthreads();   // the factorization's barriers, one per step
     }
-    {
+    __syncthreads();
+    // the factored block goes back to the factor storage here when the panel is one unit, else
+    // by the last unit to finish (the others may still be reading the original block)
+    if (un.z == 1)
+        for (int e = tid; e < w * w; e += kSnPanelWaves * WAVE) {
+            const int c = e / w, r = e - c * w;
+            Fx[cb[c] + r] = blk[c][r];
+        }
+    if (wv < 4) {
         // inverse of U11's diagonal block b = wv (upper, from the bottom), column i16
         const int o = 16 * wv;
         T x[16];
@@ -1061,9 +1263,9 @@ __global__ __launch_bounds__(256) void sn_panel_kernel(RefactorArgs a, int lev, 
     for (int b = 0; b < 4; b++)
 #pragma unroll
         for (int q = 0; q < 4; q++) mx[b][q] = 0.0;
-    for (int r0 = 16 * wv; r0 < m; r0 += 64) {           // uniform per wavefront
+    for (int r0 = rb + 16 * wv; r0 < re; r0 += 16 * kSnPanelWaves) {   // uniform per wavefront
         const int row = r0 + i16;
-        const bool in = row < m;
+        const bool in = row < re;
         acc_t t[4];
 #pragma unroll
         for (int b = 0; b < 4; b++)
@@ -1109,9 +1311,36 @@ __global__ __launch_bounds__(256) void sn_panel_kernel(RefactorArgs a, int lev, 
             if (i16 == 0) cmax[wv][16 * b + kidx<T>(q, g)] = v;
         }
     __syncthreads();
+    double M = 0.0;
+    if (tid < w)
+        for (int q = 0; q < kSnPanelWaves; q++) M = nanmax(M, cmax[q][tid]);
+    if (un.z > 1) {
+        // slices meet: each stores its column maxima and counts its arrival; the last one to
+        // arrive takes the maxima of all slices (a maximum does not depend on their order),
+        // writes the block back and runs the test
+        double *pm = a.sn_pmax + ((size_t)un.w * a.batch + inst) * NB;
+        const size_t pstride = (size_t)a.batch * NB;
+        if (tid < w) pm[un.y * pstride + tid] = M;
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+        __syncthreads();
+        if (tid == 0) {
+            int *ctr = a.sn_pcnt + (size_t)un.x * a.batch + inst;
+            const int prev = __hip_atomic_fetch_add(ctr, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            arrived = prev == un.z - 1;
+            if (arrived) __hip_atomic_store(ctr, 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        }
+        __syncthreads();
+        if (!arrived) return;                            // uniform: read after the barrier
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+        if (tid < w)
+            for (int p = 0; p < un.z; p++) M = nanmax(M, pm[p * pstride + tid]);
+        for (int e = tid; e < w * w; e += kSnPanelWaves * WAVE) {
+            const int c = e / w, r = e - c * w;
+            Fx[cb[c] + r] = blk[c][r];
+        }
+    }
     if (tid < w) {
         const int c = tid;
-        double M = nanmax(nanmax(cmax[0][c], cmax[1][c]), nanmax(cmax[2][c], cmax[3][c]));
         for (int r = c + 1; r < w; r++) M = nanmax(M, fabs((double)blk[c][r]));
         const double piv = (double)blk[c][c];
         const double xmax = fabs(piv) * M;
@@ -1124,21 +1353,128 @@ __global__ __launch_bounds__(256) void sn_panel_kernel(RefactorArgs a, int lev, 
     }
 }
 
-// Update tasks of a level: one wavefront per (target column k, instance) applies the level's
-// supernodes S with U(S, k) != 0 in ascending order.  Per supernode, on the suffix of S's
-// rows present in k (len rows, lane c holds row c): U(S, k) = L11^-1 x_k(S) by substitution
-// (eight L11 loads in flight), written to k; then x_k(R) -= L21 U(S, k), a wavefront of rows
-// of R at a time (rows < T only for a dense-block target: its rows >= T are the Schur
-// update's), their slots in k from sn_map.  Rows of one supernode are distinct, so the
-// stores of one pass never feed its own loads.
+// U(S, k) = L11^-1 x_k(S) on the suffix of S's rows present in k (len rows; lane c holds row
+// c), eight L11 loads in flight; returns this lane's value.
 template <typename T>
-__global__ __launch_bounds__(256) void sn_update_kernel(RefactorArgs a, int lev, int tbeg, int tend) {
-    const int lane = threadIdx.x & (WAVE - 1);
-    const int64_t wid = (int64_t)blockIdx.x * 4 + threadIdx.x / WAVE;
-    if (wid >= (int64_t)(tend - tbeg) * a.batch) return;
-    const int inst = (int)(wid % a.batch);
-    const int t = tbeg + (int)(wid / a.batch);
-    if (sn_stopped(a, inst, lev)) return;
+__device__ __forceinline__ T sn_suffix_solve(const T *Fx, const T *xk, const int *cb, int slot0, int off, int len,
+                                             int lane) {
+    T xv = lane < len ? xk[slot0 + lane] : T(0);
+    for (int c0 = 0; c0 < len; c0 += 8) {
+        T lv[8];
+#pragma unroll
+        for (int u = 0; u < 8; u++) {
+            const int c = c0 + u;
+            lv[u] = (c < len && lane > c && lane < len) ? Fx[cb[c] + off + lane] : T(0);
+        }
+#pragma unroll
+        for (int u = 0; u < 8; u++) {
+            const int c = c0 + u;
+            if (c < len) {
+                const T uc = readlane(xv, c);
+                if (lane > c) xv = fma(-lv[u], uc, xv);
+            }
+        }
+    }
+    return xv;
+}
+
+// x_k(R rows [r0, r0 + 128) of the item) -= L21 u: two rows per lane, sixteen loads in flight.
+// u(c) comes from get(c) (a readlane or an LDS read), the same for every lane.
+template <typename T, typename GetU>
+__device__ __forceinline__ void sn_rows_update(const T *Fx, T *xk, const int *cb, const int *mp, int w, int len,
+                                               int mcnt, int r0, int lane, GetU get) {
+    const int ra = r0 + lane, rb = r0 + WAVE + lane;
+    const bool ina = ra < mcnt, inb = rb < mcnt;
+    const int sla = ina ? mp[ra] : 0, slb = inb ? mp[rb] : 0;
+    T acca = T(0), accb = T(0);
+    for (int c0 = 0; c0 < len; c0 += 8) {
+        T la[8], lb[8];
+#pragma unroll
+        for (int u = 0; u < 8; u++) {
+            const int c = c0 + u;
+            la[u] = (ina && c < len) ? Fx[cb[c] + w + ra] : T(0);
+            lb[u] = (inb && c < len) ? Fx[cb[c] + w + rb] : T(0);
+        }
+#pragma unroll
+        for (int u = 0; u < 8; u++)
+            if (c0 + u < len) {
+                const T uc = get(c0 + u);
+                acca = fma(la[u], uc, acca);
+                accb = fma(lb[u], uc, accb);
+            }
+    }
+    if (ina) xk[sla] -= acca;
+    if (inb) xk[slb] -= accb;
+}
+
+// Update tasks of a level: a task owns one target column k and applies the level's
+// supernodes S with U(S, k) != 0 in ascending order.  Per supernode: U(S, k) = L11^-1 x_k(S)
+// on the suffix of S's rows present in k, written to k; then x_k(R) -= L21 U(S, k) on R's
+// rows (rows < T only for a dense-block target: its rows >= T are the Schur update's), their
+// slots in k from sn_map.  Rows of one supernode are distinct, so the stores of one pass
+// never feed its own loads.  Tasks [tbeg, theavy) are heavy: a workgroup per (task,
+// instance), wavefront 0 solving the suffix and passing U(S, k) through LDS, the four
+// wavefronts then splitting R's rows, a barrier between supernodes; tasks [theavy, tend) get
+// a wavefront per (task, instance).  Either way every row of k receives the same operations
+// in the same order.
+template <typename T>
+__global__ __launch_bounds__(256) void sn_update_kernel(RefactorArgs a, int lev, int tbeg, int theavy, int ttiny,
+                                                        int tend) {
+    __shared__ T us[WAVE];
+    const int lane = threadIdx.x & (WAVE - 1), wv = threadIdx.x / WAVE;
+    // grid sizes fit 32 bits (one dimension of a launch)
+    const unsigned nheavy = (unsigned)(theavy - tbeg) * (unsigned)a.batch;
+    const unsigned nlight = ((unsigned)(ttiny - theavy) * (unsigned)a.batch + 3) / 4;
+    const unsigned bid = blockIdx.x, batch = (unsigned)a.batch;
+    int t, inst;
+    const bool heavy = bid < nheavy;
+    if (heavy) {
+        const unsigned b = xcd_contiguous(bid, nheavy);
+        inst = (int)(b % batch);
+        t = tbeg + (int)(b / batch);
+    } else if (bid < nheavy + nlight) {
+        const unsigned wid = xcd_contiguous(bid - nheavy, nlight) * 4 + wv;
+        if (wid >= (unsigned)(ttiny - theavy) * batch) return;
+        inst = (int)(wid % batch);
+        t = theavy + (int)(wid / batch);
+    } else {
+        // tiny tasks (every item at most kTinyRows suffix rows and rows of R): sixteen lanes
+        // each, the same operations in the same order as a wavefront's: the suffix solve with
+        // lane c holding suffix row c, then a row of R per lane
+        const unsigned ntiny = gridDim.x - nheavy - nlight;
+        const unsigned gid = xcd_contiguous(bid - nheavy - nlight, ntiny) * 16 + threadIdx.x / 16;
+        if (gid >= (unsigned)(tend - ttiny) * batch) return;
+        inst = (int)(gid % batch);
+        if (sn_stopped(a, inst, lev)) return;
+        const int l16 = lane & 15;
+        T *Fx = reinterpret_cast<T *>(a.Fx) + (size_t)inst * a.nnzF;
+        const int4 tk = reinterpret_cast<const int4 *>(a.sn_task)[ttiny + (int)(gid / batch)];
+        T *xk = Fx + tk.y;
+        for (int it = tk.z; it < tk.w; it++) {
+            const int4 item = reinterpret_cast<const int4 *>(a.sn_item)[it];
+            const int4 rec = reinterpret_cast<const int4 *>(a.sn_rec)[item.x];
+            const int w = rec.y, len = item.z, off = w - len, mcnt = item.w;
+            const int *cb = a.sn_cb + rec.x + off;        // the suffix's columns
+            T xv = l16 < len ? xk[item.y + l16] : T(0);
+            for (int c = 0; c < len - 1; c++) {
+                const T uc = __shfl(xv, c, 16);
+                if (l16 > c && l16 < len) xv = fma(-Fx[cb[c] + off + l16], uc, xv);
+            }
+            if (l16 < len) xk[item.y + l16] = xv;
+            // every lane of the group takes part in the shuffles (a shuffle reads active lanes)
+            T acc = T(0);
+            for (int c = 0; c < len; c++) {
+                const T uc = __shfl(xv, c, 16);
+                const T lv = l16 < mcnt ? Fx[cb[c] + w + l16] : T(0);
+                acc = fma(lv, uc, acc);
+            }
+            if (l16 < mcnt) xk[a.sn_map[a.sn_moff[it] + l16]] -= acc;
+            __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "workgroup");
+            __builtin_amdgcn_wave_barrier();
+        }
+        return;
+    }
+    if (sn_stopped(a, inst, lev)) return;                // uniform over a heavy task's workgroup
     T *Fx = reinterpret_cast<T *>(a.Fx) + (size_t)inst * a.nnzF;
     const int4 tk = reinterpret_cast<const int4 *>(a.sn_task)[t];
     T *xk = Fx + tk.y;
@@ -1148,50 +1484,26 @@ __global__ __launch_bounds__(256) void sn_update_kernel(RefactorArgs a, int lev,
         const int w = rec.y, len = item.z, off = w - len, mcnt = item.w;
         const int *cb = a.sn_cb + rec.x + off;           // the suffix's columns
         const int *mp = a.sn_map + a.sn_moff[it];
-        T xv = lane < len ? xk[item.y + lane] : T(0);
-        for (int c0 = 0; c0 < len; c0 += 8) {
-            T lv[8];
-#pragma unroll
-            for (int u = 0; u < 8; u++) {
-                const int c = c0 + u;
-                lv[u] = (c < len && lane > c && lane < len) ? Fx[cb[c] + off + lane] : T(0);
-            }
-#pragma unroll
-            for (int u = 0; u < 8; u++) {
-                const int c = c0 + u;
-                if (c < len) {
-                    const T uc = readlane(xv, c);
-                    if (lane > c) xv = fma(-lv[u], uc, xv);
+        if (!heavy) {
+            const T xv = sn_suffix_solve<T>(Fx, xk, cb, item.y, off, len, lane);
+            if (lane < len) xk[item.y + lane] = xv;
+            for (int r0 = 0; r0 < mcnt; r0 += 2 * WAVE)
+                sn_rows_update<T>(Fx, xk, cb, mp, w, len, mcnt, r0, lane, [&](int c) { return readlane(xv, c); });
+            __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "workgroup");
+            __builtin_amdgcn_wave_barrier();
+        } else {
+            if (wv == 0) {
+                const T xv = sn_suffix_solve<T>(Fx, xk, cb, item.y, off, len, lane);
+                if (lane < len) {
+                    xk[item.y + lane] = xv;
+                    us[lane] = xv;
                 }
             }
+            __syncthreads();
+            for (int r0 = 2 * WAVE * wv; r0 < mcnt; r0 += 8 * WAVE)
+                sn_rows_update<T>(Fx, xk, cb, mp, w, len, mcnt, r0, lane, [&](int c) { return us[c]; });
+            __syncthreads();
         }
-        if (lane < len) xk[item.y + lane] = xv;
-        for (int r0 = 0; r0 < mcnt; r0 += 2 * WAVE) {      // two rows per lane: 16 loads in flight
-            const int ra = r0 + lane, rb = r0 + WAVE + lane;
-            const bool ina = ra < mcnt, inb = rb < mcnt;
-            const int sla = ina ? mp[ra] : 0, slb = inb ? mp[rb] : 0;
-            T acca = T(0), accb = T(0);
-            for (int c0 = 0; c0 < len; c0 += 8) {
-                T la[8], lb[8];
-#pragma unroll
-                for (int u = 0; u < 8; u++) {
-                    const int c = c0 + u;
-                    la[u] = (ina && c < len) ? Fx[cb[c] + w + ra] : T(0);
-                    lb[u] = (inb && c < len) ? Fx[cb[c] + w + rb] : T(0);
-                }
-#pragma unroll
-                for (int u = 0; u < 8; u++)
-                    if (c0 + u < len) {
-                        const T uc = readlane(xv, c0 + u);
-                        acca = fma(la[u], uc, acca);
-                        accb = fma(lb[u], uc, accb);
-                    }
-            }
-            if (ina) xk[sla] -= acca;
-            if (inb) xk[slb] -= accb;
-        }
-        __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "workgroup");
-        __builtin_amdgcn_wave_barrier();
     }
 }
 
@@ -1214,6 +1526,21 @@ int launch_schur(const DenseArgs &a, const int *parts, int nparts, const int *ad
     const dim3 grid((unsigned)((int64_t)nparts * a.batch));
     if (a.fp32) hipLaunchKernelGGL((schur_kernel<float>), grid, dim3(64), 0, st, a, parts, l21);
     else hipLaunchKernelGGL((schur_kernel<double>), grid, dim3(64), 0, st, a, parts, l21);
+    if (nadd > 0) {
+        const dim3 ga((unsigned)(((int64_t)nadd * a.batch + 3) / 4));
+        if (a.fp32) hipLaunchKernelGGL((schur_add_kernel<float>), ga, dim3(256), 0, st, a, add, nadd);
+        else hipLaunchKernelGGL((schur_add_kernel<double>), ga, dim3(256), 0, st, a, add, nadd);
+    }
+    return (int)hipGetLastError();
+}
+
+int launch_schur_sn(const DenseArgs &a, const int *parts, int nparts, const int *add, int nadd, const int *sn_items,
+                    const int *sn_rec, const int *sn_cb, void *stream) {
+    hipStream_t st = (hipStream_t)stream;
+    if (a.D <= 0 || a.T <= 0 || nparts <= 0) return 0;
+    const dim3 grid((unsigned)((int64_t)nparts * a.batch));
+    if (a.fp32) hipLaunchKernelGGL((schur_sn_kernel<float>), grid, dim3(64), 0, st, a, parts, sn_items, sn_rec, sn_cb);
+    else hipLaunchKernelGGL((schur_sn_kernel<double>), grid, dim3(64), 0, st, a, parts, sn_items, sn_rec, sn_cb);
     if (nadd > 0) {
         const dim3 ga((unsigned)(((int64_t)nadd * a.batch + 3) / 4));
         if (a.fp32) hipLaunchKernelGGL((schur_add_kernel<float>), ga, dim3(256), 0, st, a, add, nadd);
@@ -1375,30 +1702,45 @@ int launch_dense_solve(const DenseArgs &a, double *y, int nrhs, const int *skip,
     return (int)hipGetLastError();
 }
 
-int launch_sn_panels(const RefactorArgs &a, int lev, int sbeg, int smid, int send, void *stream) {
+int launch_sn_panels(const RefactorArgs &a, int lev, int sbeg, int s1, int sub, int sue, int ubeg, int uend,
+                     void *stream) {
     hipStream_t st = (hipStream_t)stream;
-    const int64_t waves = (int64_t)(smid - sbeg) * a.batch;
+    const int64_t waves = (int64_t)(s1 - sbeg) * a.batch;
     if (waves > 0) {
         const dim3 grid((unsigned)((waves + 3) / 4));
-        if (a.fp32) hipLaunchKernelGGL(sn_single_kernel<float>, grid, dim3(256), 0, st, a, lev, sbeg, smid);
-        else hipLaunchKernelGGL(sn_single_kernel<double>, grid, dim3(256), 0, st, a, lev, sbeg, smid);
+        if (a.fp32) hipLaunchKernelGGL(sn_single_kernel<float>, grid, dim3(256), 0, st, a, lev, sbeg, s1);
+        else hipLaunchKernelGGL(sn_single_kernel<double>, grid, dim3(256), 0, st, a, lev, sbeg, s1);
         const hipError_t e = hipGetLastError();
         if (e != hipSuccess) return (int)e;
     }
-    if (send > smid) {
-        const dim3 grid((unsigned)(send - smid), (unsigned)a.batch);
-        if (a.fp32) hipLaunchKernelGGL(sn_panel_kernel<float>, grid, dim3(256), 0, st, a, lev, smid);
-        else hipLaunchKernelGGL(sn_panel_kernel<double>, grid, dim3(256), 0, st, a, lev, smid);
+    const int64_t swaves = (int64_t)(sue - sub) * a.batch;
+    if (swaves > 0) {
+        const dim3 grid((unsigned)((swaves + 3) / 4));
+        if (a.fp32) hipLaunchKernelGGL(sn_small_kernel<float>, grid, dim3(256), 0, st, a, lev, sub, sue);
+        else hipLaunchKernelGGL(sn_small_kernel<double>, grid, dim3(256), 0, st, a, lev, sub, sue);
+        const hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return (int)e;
+    }
+    if (uend > ubeg) {
+        const dim3 grid((unsigned)(uend - ubeg), (unsigned)a.batch);
+        const dim3 block(kSnPanelWaves * WAVE);
+        if (a.fp32) hipLaunchKernelGGL(sn_panel_kernel<float>, grid, block, 0, st, a, lev, ubeg);
+        else hipLaunchKernelGGL(sn_panel_kernel<double>, grid, block, 0, st, a, lev, ubeg);
     }
     return (int)hipGetLastError();
 }
 
-int launch_sn_updates(const RefactorArgs &a, int lev, int tbeg, int tend, void *stream) {
-    const int64_t waves = (int64_t)(tend - tbeg) * a.batch;
-    if (waves == 0) return 0;
-    const dim3 grid((unsigned)((waves + 3) / 4));
-    if (a.fp32) hipLaunchKernelGGL(sn_update_kernel<float>, grid, dim3(256), 0, (hipStream_t)stream, a, lev, tbeg, tend);
-    else hipLaunchKernelGGL(sn_update_kernel<double>, grid, dim3(256), 0, (hipStream_t)stream, a, lev, tbeg, tend);
+int launch_sn_updates(const RefactorArgs &a, int lev, int tbeg, int theavy, int ttiny, int tend, void *stream) {
+    const int64_t heavy = (int64_t)(theavy - tbeg) * a.batch;
+    const int64_t light = ((int64_t)(ttiny - theavy) * a.batch + 3) / 4;
+    const int64_t tiny = ((int64_t)(tend - ttiny) * a.batch + 15) / 16;
+    if (heavy + light + tiny == 0) return 0;
+    if (heavy + light + tiny > INT_MAX || (int64_t)(tend - tbeg) * a.batch > INT_MAX) return (int)hipErrorInvalidValue;
+    const dim3 grid((unsigned)(heavy + light + tiny));
+    if (a.fp32) hipLaunchKernelGGL(sn_update_kernel<float>, grid, dim3(256), 0, (hipStream_t)stream, a, lev, tbeg,
+                                   theavy, ttiny, tend);
+    else hipLaunchKernelGGL(sn_update_kernel<double>, grid, dim3(256), 0, (hipStream_t)stream, a, lev, tbeg, theavy,
+                            ttiny, tend);
     return (int)hipGetLastError();
 }
 

@@ -150,13 +150,25 @@ struct Schedule {
     // applies every supernode S of level l with U(S, k) != 0 in ascending order: U(S, k) =
     // L11^-1 x_k(S) on the suffix of S's rows present in k, then x_k(R) -= L21 U(S, k).
     int sn_count = 0, sn_levels = 0;
-    std::vector<int> sn_rec;                  // int4 per supernode {s0, w, m = |R|, 0}
+    std::vector<int> sn_rec;                  // int4 per supernode {s0, w, m = |R|, rows of R below tail0}
+    // Schur update by supernodes (with sn_count > 0, schur_parts index these items instead of
+    // bridge rows): {supernode, first column in it, columns, position of the first row in k}
+    std::vector<int> schur_sn_items;
     std::vector<int> sn_cb;                   // per sparse column j: device offset of row s0(j) in column j
     std::vector<int> sn_lvl;                  // [sn_levels+1] supernodes of level l: sn_seq[sn_lvl[l] ..]
-    std::vector<int> sn_seq;                  // supernode ids by level: singletons first, then panels
+    std::vector<int> sn_seq;                  // supernode ids by level: singletons, small panels, panels
     std::vector<int> sn_lvl_single;           // [sn_levels] singletons of level l: sn_seq[sn_lvl[l] ..
-                                              // sn_lvl_single[l]), panels after
+                                              // sn_lvl_single[l])
+    std::vector<int> sn_lvl_small;            // [sn_levels] then panels at most kSnSmallW wide (a
+                                              // wavefront each) up to sn_lvl_small[l], wider ones after
+    std::vector<int> sn_punit;                // wide panels as units: int4 {position in sn_seq, slice p,
+                                              // slices P, first scratch block (-1 when P = 1)}
+    std::vector<int> sn_pulvl;                // [sn_levels+1] units of level l
+    std::vector<int> sn_sunit, sn_sulvl;      // the same for the small panels
+    int sn_pnscr = 0;                         // scratch blocks a launch uses at most
     std::vector<int> sn_task_lvl;             // [sn_levels+1] tasks of level l
+    std::vector<int> sn_task_heavy;           // [sn_levels] its heavy tasks (a workgroup each) end here
+    std::vector<int> sn_task_tiny;            // [sn_levels] its tiny tasks (sixteen lanes each) start here
     std::vector<int> sn_task;                 // int4 per task {k, Dp[k], first item, end item}
     std::vector<int> sn_item;                 // int4 per item {supernode, slot of its first row in k, rows
                                               // of S present in k (the suffix), rows of R updated}
@@ -168,9 +180,14 @@ struct Schedule {
     // its diagonal block (L: columns < s0; U: columns >= s0 + w), then its dense triangle is
     // solved.  Level = longest path over the supernodes those entries reach.  Per level of the
     // L (U) solve: its supernodes in snl_seq (snu_seq) [snl_lvl[l], snl_lvl[l+1]), singletons
-    // first up to snl_single[l].
+    // first up to snl_single[l] (at most kSnSmallW rows and a short pull: a wavefront each).
+    // The workgroup units of level l: snl_unit [snl_ulvl[l], snl_ulvl[l+1]), int4 {position in
+    // snl_seq, slice p, slices P, first scratch block of the supernode (-1 when P = 1)}; a level
+    // uses at most snl_nscr scratch blocks.
     int snl_levels = 0, snu_levels = 0;
     std::vector<int> snl_lvl, snl_single, snl_seq, snu_lvl, snu_single, snu_seq;
+    std::vector<int> snl_unit, snl_ulvl, snu_unit, snu_ulvl;
+    int snl_nscr = 0, snu_nscr = 0;
 };
 
 // map_cap: most slot-map entries to build (-1: what a quarter of the device's free memory
@@ -194,7 +211,10 @@ struct Device {
     DevBuf Acp, Acj, Acsrc;
     DevBuf sn_rec, sn_cb, sn_seq, sn_task, sn_item, sn_moff, sn_map;   // supernodal sweep
     DevBuf snl_seq, snu_seq, Lrp, Urp;                                 // supernodal solves
+    DevBuf snl_unit, snu_unit, sn_part, sn_cnt;                        // their split units
+    DevBuf sn_punit, sn_sunit;                                         // split panels
     DevBuf ascale, gscale, sscale;     // static scaling: per nonzero of A, per solve row, per solve column
+    DevBuf schur_sn_items;             // supernodal Schur update items
     // values and status words
     DevBuf Fx64, Fx32;                 // factor values (FP64 always; FP32 in FP32_IR mode)
     DevBuf Aval;                       // copy of the last values (FP64) for residuals
@@ -246,6 +266,12 @@ struct RefactorArgs {
     // first row, supernodes by level, update tasks, their items and the rows' slots
     const int *sn_rec, *sn_cb, *sn_seq, *sn_task, *sn_item, *sn_map;
     const int64_t *sn_moff;
+    // wide panels split by rows of R: units int4 {position in sn_seq, slice, slices, first
+    // scratch block}; column maxima of the slices (64 doubles per block and instance) and an
+    // arrival counter per sn_seq position and instance (zero on entry and on exit)
+    const int *sn_punit, *sn_sunit;
+    double *sn_pmax;
+    int *sn_pcnt;
     const double *ascale;      // static scaling per nonzero of A (row scale x column scale), or null
 };
 
@@ -257,11 +283,15 @@ int launch_dense_reinit(const RefactorArgs &a, void *stream);
 // the previous level seq[pbeg, pend) (L = x / pivot), and update tasks [tbeg, tend).
 int launch_refactor_level(const RefactorArgs &a, int cbeg, int cend, int pbeg, int pend, int tbeg,
                           int tend, int lev, void *stream);
-// Supernodal sweep, level `lev` (dense.hip): the singleton supernodes sn_seq[sbeg, smid) (pivot test
-// and L = x / pivot, a wavefront each) and the panels sn_seq[smid, send) (a workgroup each: dense
-// LU of the diagonal block, L21 = A21 U11^-1, pivot test); then the level's update tasks [tbeg, tend).
-int launch_sn_panels(const RefactorArgs &a, int lev, int sbeg, int smid, int send, void *stream);
-int launch_sn_updates(const RefactorArgs &a, int lev, int tbeg, int tend, void *stream);
+// Supernodal sweep, level `lev` (dense.hip): the singleton supernodes sn_seq[sbeg, s1) (pivot test
+// and L = x / pivot, a wavefront each), the small panels as units sn_sunit[sub, sue) (a wavefront
+// each) and the wider panels as units sn_punit[ubeg, uend) (a workgroup each): dense LU of the
+// diagonal block,
+// L21 = A21 U11^-1, pivot test; then the level's update tasks: [tbeg, theavy) a workgroup each,
+// [theavy, ttiny) a wavefront each, [ttiny, tend) sixteen lanes each.
+int launch_sn_panels(const RefactorArgs &a, int lev, int sbeg, int s1, int sub, int sue, int ubeg, int uend,
+                     void *stream);
+int launch_sn_updates(const RefactorArgs &a, int lev, int tbeg, int theavy, int ttiny, int tend, void *stream);
 int launch_reset_ctrl(int *ctrl, int nwords, int value, void *stream);
 // status[i] = firstfail[i] == INT_MAX ? -1 : firstfail[i]
 int launch_status_out(const int *firstfail, int *status, int batch, void *stream);
@@ -278,12 +308,16 @@ struct SolveArgs {
     // supernodal solves: supernode records and first-row offsets (as RefactorArgs), and the row
     // pointers of the strictly lower L and strictly upper U (entries in Lrjs / Urjs)
     const int *sn_rec, *sn_cb, *Lrp, *Urp;
+    double *sn_part;           // partial sums of split supernodes: 512 doubles per block and instance
 };
 
-// One level of the supernodal L (U) solve: the singleton supernodes seq[sbeg, smid) and the
-// panel supernodes seq[smid, send).
-int launch_sn_lsolve(const SolveArgs &a, const int *seq, int sbeg, int smid, int send, void *stream);
-int launch_sn_usolve(const SolveArgs &a, const int *seq, int sbeg, int smid, int send, void *stream);
+// One level of the supernodal L (U) solve: a wavefront per singleton seq[sbeg, smid) and a
+// workgroup per unit units[ubeg, uend) (int4 {position in seq, slice, slices, first scratch
+// block}); cnt: an arrival counter per seq position and instance, zero on entry and on exit.
+int launch_sn_lsolve(const SolveArgs &a, const int *seq, const int *units, int sbeg, int smid, int ubeg, int uend,
+                     int *cnt, void *stream);
+int launch_sn_usolve(const SolveArgs &a, const int *seq, const int *units, int sbeg, int smid, int ubeg, int uend,
+                     int *cnt, void *stream);
 
 // Solve positions [lbeg, lend) of lrec / urec (one level of the solve graph).
 int launch_lsolve_level(const SolveArgs &a, int lbeg, int lend, void *stream);
@@ -330,6 +364,9 @@ int noalloc_scratch(double **out);
 // Dense trailing block (dense.hip): columns and rows [T, n) of the factors,
 // D = n - T, held per instance as a column-major D x D matrix S.
 constexpr int kDenseBlock = 64;  // panel width of the blocked LU and of the block solves
+constexpr int kSnSmallW = 16;    // supernodes up to this wide are factored by one wavefront
+constexpr int kTinyRows = 16;    // update tasks whose items have at most this many suffix rows and
+                                 // rows of R: 16 lanes each
 struct DenseArgs {
     int n, T, D, batch;
     const int *Dp, *Dlen, *Fi;
@@ -354,6 +391,10 @@ int launch_dense_gather(const DenseArgs &a, void *stream);
 // then the scratch columns added into S (nadd records {column, first scratch, count, 0})
 int launch_schur(const DenseArgs &a, const int *parts, int nparts, const int *add, int nadd, const int *l21,
                  void *stream);
+// The same update by supernodes: parts index the items sn_items ({supernode, first column,
+// columns, position of the first row in the dense column}); sn_rec and sn_cb as in RefactorArgs.
+int launch_schur_sn(const DenseArgs &a, const int *parts, int nparts, const int *add, int nadd, const int *sn_items,
+                    const int *sn_rec, const int *sn_cb, void *stream);
 // Look-ahead resources of the dense LU: a second stream (default priority) on which the
 // panels of group g+1 run while the trailing update of group g runs on the main stream,
 // and events that order the two (2 per group boundary).  side == nullptr: one stream.

@@ -31,6 +31,7 @@
 // the chained solve only the wavefronts of one workgroup (one CU) communicate.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <climits>
 #include <cstdint>
 #include <mutex>
@@ -557,57 +558,15 @@ __device__ __forceinline__ double readlane_f64(double v, int l) {
     return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
 }
 
-// One level of the supernodal L (U) solve.  Singleton supernodes (one row i) are solved by a
-// wavefront per (row, instance) as in the row kernel; a panel supernode [s0, s0 + w) by a
-// workgroup per (supernode, instance): its wavefronts pull the rows' entries outside the
-// diagonal block (L: columns < s0, the row's first entries; U: columns >= s0 + w, its last
-// entries) into LDS, then one wavefront solves the dense triangle, lane c holding row s0 + c:
-// L: y_c -= L(c, c') y_c' for c' < c in ascending c' (unit diagonal); U: x_c = t_c / U(c, c)
-// in descending c, then t_c'' -= U(c'', c) x_c for c'' < c.  The triangle's entries come from
-// the factor columns (sn_cb: offset of the supernode's first row in each column).
+// The dense triangle of supernode [s0, s0 + w) in one wavefront, lane c holding row s0 + c with
+// t = its right-hand sides minus the pulled sums: L: y_c -= L(c, c') y_c' for c' < c in
+// ascending c' (unit diagonal); U: x_c = t_c / U(c, c) in descending c, then
+// t_c'' -= U(c'', c) x_c for c'' < c.  The triangle's entries come from the factor columns
+// (sn_cb: offset of the supernode's first row in each column); the results go to y.
 template <typename T, int NR, bool UPPER>
-__global__ __launch_bounds__(WG) void sn_solve_kernel(SolveArgs a, const int *seq, int sbeg, int smid, int send) {
-    __shared__ double tv[64][8];
-    const int lane = threadIdx.x & (WAVE - 1), wv = threadIdx.x / WAVE;
-    const int64_t nsingle = (int64_t)(smid - sbeg) * a.batch;
-    const int64_t nsw = (nsingle + WAVES - 1) / WAVES;
-    const int *rp = UPPER ? a.Urp : a.Lrp;
-    if ((int64_t)blockIdx.x < nsw) {
-        const int64_t w = (int64_t)blockIdx.x * WAVES + wv;
-        if (w >= nsingle) return;
-        const int inst = (int)(w % a.batch);
-        if (a.skip && a.skip[inst] != -1) return;
-        const int i = a.sn_rec[4 * seq[sbeg + (int)(w / a.batch)]];
-        solve_row_rec<T, NR, UPPER>(a, inst, make_int4(i, rp[i], rp[i + 1], a.sn_cb[i]), lane);
-        return;
-    }
-    const int64_t pu = (int64_t)blockIdx.x - nsw;
-    const int inst = (int)(pu % a.batch);
-    if (a.skip && a.skip[inst] != -1) return;            // the whole workgroup
-    const int4 rec = reinterpret_cast<const int4 *>(a.sn_rec)[seq[smid + (int)(pu / a.batch)]];
-    const int s0 = rec.x, w = rec.y;
-    const int2 *rjs = reinterpret_cast<const int2 *>(UPPER ? a.Urjs : a.Lrjs);
-    const T *Fx = reinterpret_cast<const T *>(a.Fx) + (size_t)inst * a.nnzF;
-    double *y = a.y + (size_t)inst * a.n * YS;
-    for (int c = wv; c < w; c += WAVES) {
-        const int i = s0 + c;
-        const int beg = UPPER ? rp[i] + (w - 1 - c) : rp[i];
-        const int end = UPPER ? rp[i + 1] : rp[i + 1] - c;
-        const double yi = lane < NR ? y[(size_t)i * YS + lane] : 0.0;
-        double acc[NR];
-        row_pull<T, NR>(rjs, Fx, y, beg, end, lane, acc);
-        double mine = acc[0];
-#pragma unroll
-        for (int r = 1; r < NR; r++)
-            if (lane == r) mine = acc[r];
-        if (lane < NR) tv[c][lane] = yi - mine;
-    }
-    __syncthreads();
-    if (wv != 0) return;
+__device__ __forceinline__ void sn_triangle(const SolveArgs &a, const T *Fx, double *y, int s0, int w,
+                                            double (&t)[NR], int lane) {
     const int *cb = a.sn_cb + s0;
-    double t[NR];
-#pragma unroll
-    for (int r = 0; r < NR; r++) t[r] = lane < w ? tv[lane][r] : 0.0;
     if (!UPPER) {
         for (int c0 = 0; c0 < w; c0 += 8) {
             double lv[8];
@@ -657,19 +616,156 @@ __global__ __launch_bounds__(WG) void sn_solve_kernel(SolveArgs a, const int *se
     }
 }
 
+// One level of the supernodal L (U) solve.  Supernodes of at most kSnSmallW rows with a short
+// pull get a wavefront per (supernode, instance): a singleton as in the row kernel; a wider
+// one pulls its rows one after another (wavefront-wide over each row's entries) and solves
+// its triangle.  Every other supernode [s0, s0 + w) is cut into P units (P from its number of
+// entries outside the diagonal block), a workgroup of sixteen wavefronts per (unit, instance):
+// unit p pulls slice p of every row's entries outside the block (L: columns < s0, the row's
+// first entries; U: columns >= s0 + w, its last entries), each row slice cut again into
+// Q = ceil(16 / w) pieces so that all wavefronts work; the pieces meet in LDS and are summed in
+// order.  With P = 1 the workgroup then solves the triangle; with P > 1 each unit stores its
+// row sums in its scratch block and counts its arrival, and the last unit to arrive adds the
+// P blocks (the even slices and the odd slices in ascending order, by two halves of its
+// threads, then the two halves: the same sums whichever unit is last) and solves the
+// triangle.
+constexpr int kSnSolveWG = 1024;                     // threads of a supernodal solve workgroup
+constexpr int kSnSolveWaves = kSnSolveWG / WAVE;
+template <typename T, int NR, bool UPPER>
+__global__ __launch_bounds__(kSnSolveWG) void sn_solve_kernel(SolveArgs a, const int *seq, const int *units,
+                                                              int sbeg, int smid, int ubeg, int *cnt) {
+    __shared__ double part[64][8];
+    __shared__ double red[2][512];
+    __shared__ int arrived;
+    const int lane = threadIdx.x & (WAVE - 1), wv = threadIdx.x / WAVE;
+    const int64_t nsingle = (int64_t)(smid - sbeg) * a.batch;
+    const int64_t nsw = (nsingle + kSnSolveWaves - 1) / kSnSolveWaves;
+    const int *rp = UPPER ? a.Urp : a.Lrp;
+    const int2 *rjs = reinterpret_cast<const int2 *>(UPPER ? a.Urjs : a.Lrjs);
+    if ((int64_t)blockIdx.x < nsw) {
+        const int64_t wid = (int64_t)blockIdx.x * kSnSolveWaves + wv;
+        if (wid >= nsingle) return;
+        const int inst = (int)(wid % a.batch);
+        if (a.skip && a.skip[inst] != -1) return;
+        const int4 rec = reinterpret_cast<const int4 *>(a.sn_rec)[seq[sbeg + (int)(wid / a.batch)]];
+        const int s0 = rec.x, w = rec.y;
+        if (w == 1) {
+            solve_row_rec<T, NR, UPPER>(a, inst, make_int4(s0, rp[s0], rp[s0 + 1], a.sn_cb[s0]), lane);
+            return;
+        }
+        const T *Fx = reinterpret_cast<const T *>(a.Fx) + (size_t)inst * a.nnzF;
+        double *y = a.y + (size_t)inst * a.n * YS;
+        double t[NR];
+#pragma unroll
+        for (int r = 0; r < NR; r++) t[r] = 0.0;
+        for (int c = 0; c < w; c++) {
+            const int i = s0 + c;
+            double acc[NR];
+            row_pull<T, NR>(rjs, Fx, y, UPPER ? rp[i] + (w - 1 - c) : rp[i], UPPER ? rp[i + 1] : rp[i + 1] - c, lane,
+                            acc);
+            if (lane == c) {
+#pragma unroll
+                for (int r = 0; r < NR; r++) t[r] = y[(size_t)i * YS + r] - acc[r];
+            }
+        }
+        sn_triangle<T, NR, UPPER>(a, Fx, y, s0, w, t, lane);
+        return;
+    }
+    const int64_t pu = (int64_t)blockIdx.x - nsw;
+    const int inst = (int)(pu % a.batch);
+    if (a.skip && a.skip[inst] != -1) return;            // the whole workgroup
+    const int4 un = reinterpret_cast<const int4 *>(units)[ubeg + (int)(pu / a.batch)];
+    const int4 rec = reinterpret_cast<const int4 *>(a.sn_rec)[seq[un.x]];
+    const int s0 = rec.x, w = rec.y;
+    const T *Fx = reinterpret_cast<const T *>(a.Fx) + (size_t)inst * a.nnzF;
+    double *y = a.y + (size_t)inst * a.n * YS;
+    const int Q = (kSnSolveWaves + w - 1) / w;        // w * Q <= 64
+    const int64_t pieces = (int64_t)un.z * Q;
+    for (int t = wv; t < w * Q; t += kSnSolveWaves) {
+        const int c = t / Q, i = s0 + c;
+        const int beg = UPPER ? rp[i] + (w - 1 - c) : rp[i];
+        const int end = UPPER ? rp[i + 1] : rp[i + 1] - c;
+        const int64_t len = end - beg, k = (int64_t)un.y * Q + t % Q;
+        double acc[NR];
+        row_pull<T, NR>(rjs, Fx, y, beg + (int)(len * k / pieces), beg + (int)(len * (k + 1) / pieces), lane, acc);
+        double mine = acc[0];
+#pragma unroll
+        for (int r = 1; r < NR; r++)
+            if (lane == r) mine = acc[r];
+        if (lane < NR) part[t][lane] = mine;
+    }
+    __syncthreads();
+    double sum[NR];
+#pragma unroll
+    for (int r = 0; r < NR; r++) sum[r] = 0.0;
+    if (wv == 0 && lane < w)
+        for (int q = 0; q < Q; q++) {
+#pragma unroll
+            for (int r = 0; r < NR; r++) sum[r] += part[lane * Q + q][r];
+        }
+    if (un.z > 1) {
+        double *blk = a.sn_part + ((size_t)un.w * a.batch + inst) * 512;
+        const size_t bstride = (size_t)a.batch * 512;
+        if (wv == 0 && lane < w) {
+#pragma unroll
+            for (int r = 0; r < NR; r++) blk[un.y * bstride + lane * 8 + r] = sum[r];
+        }
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+        __syncthreads();
+        int *ctr = cnt + (size_t)un.x * a.batch + inst;
+        if (threadIdx.x == 0) {
+            const int prev = __hip_atomic_fetch_add(ctr, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            arrived = prev == un.z - 1;
+            if (arrived) __hip_atomic_store(ctr, 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        }
+        __syncthreads();
+        if (!arrived) return;                            // not the last unit of this supernode
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+        {
+            const int v = threadIdx.x & 511, h = threadIdx.x >> 9, c = v >> 3, r = v & 7;
+            double acc = 0.0;
+            if (c < w && r < NR) {
+                int p = h;
+                for (; p + 6 < un.z; p += 8) {         // four loads in flight
+                    const double x0 = blk[(size_t)p * bstride + v], x1 = blk[(size_t)(p + 2) * bstride + v];
+                    const double x2 = blk[(size_t)(p + 4) * bstride + v], x3 = blk[(size_t)(p + 6) * bstride + v];
+                    acc = (((acc + x0) + x1) + x2) + x3;
+                }
+                for (; p < un.z; p += 2) acc += blk[(size_t)p * bstride + v];
+            }
+            red[h][v] = acc;
+        }
+        __syncthreads();
+        if (wv != 0) return;
+        if (lane < w) {
+#pragma unroll
+            for (int r = 0; r < NR; r++) sum[r] = red[0][lane * 8 + r] + red[1][lane * 8 + r];
+        }
+    } else if (wv != 0) {
+        return;
+    }
+    double t[NR];
+#pragma unroll
+    for (int r = 0; r < NR; r++) t[r] = lane < w ? y[(size_t)(s0 + lane) * YS + r] - sum[r] : 0.0;
+    sn_triangle<T, NR, UPPER>(a, Fx, y, s0, w, t, lane);
+}
+
 template <bool UPPER>
-static int launch_sn_solve_impl(const SolveArgs &a, const int *seq, int sbeg, int smid, int send, void *stream) {
-    const int64_t nsw = ((int64_t)(smid - sbeg) * a.batch + WAVES - 1) / WAVES;
-    const int64_t units = nsw + (int64_t)(send - smid) * a.batch;
-    if (units == 0) return 0;
-    const dim3 grid((unsigned)units);
+static int launch_sn_solve_impl(const SolveArgs &a, const int *seq, const int *units, int sbeg, int smid, int ubeg,
+                                int uend, int *cnt, void *stream) {
+    const int64_t nsw = ((int64_t)(smid - sbeg) * a.batch + kSnSolveWaves - 1) / kSnSolveWaves;
+    const int64_t units_n = nsw + (int64_t)(uend - ubeg) * a.batch;
+    if (units_n == 0) return 0;
+    const dim3 grid((unsigned)units_n);
     hipStream_t st = (hipStream_t)stream;
 #define CKTLU_SNS_CASE(NRV)                                                                             \
     case NRV:                                                                                           \
         if (a.fp32)                                                                                     \
-            hipLaunchKernelGGL((sn_solve_kernel<float, NRV, UPPER>), grid, dim3(WG), 0, st, a, seq, sbeg, smid, send); \
+            hipLaunchKernelGGL((sn_solve_kernel<float, NRV, UPPER>), grid, dim3(kSnSolveWG), 0, st, a, seq, units, \
+                               sbeg, smid, ubeg, cnt);                                                  \
         else                                                                                            \
-            hipLaunchKernelGGL((sn_solve_kernel<double, NRV, UPPER>), grid, dim3(WG), 0, st, a, seq, sbeg, smid, send); \
+            hipLaunchKernelGGL((sn_solve_kernel<double, NRV, UPPER>), grid, dim3(kSnSolveWG), 0, st, a, seq, units, \
+                               sbeg, smid, ubeg, cnt);                                                  \
         break;
     switch (a.nrhs) {
         CKTLU_SNS_CASE(1)
@@ -682,11 +778,13 @@ static int launch_sn_solve_impl(const SolveArgs &a, const int *seq, int sbeg, in
     return (int)hipGetLastError();
 }
 
-int launch_sn_lsolve(const SolveArgs &a, const int *seq, int sbeg, int smid, int send, void *stream) {
-    return launch_sn_solve_impl<false>(a, seq, sbeg, smid, send, stream);
+int launch_sn_lsolve(const SolveArgs &a, const int *seq, const int *units, int sbeg, int smid, int ubeg, int uend,
+                     int *cnt, void *stream) {
+    return launch_sn_solve_impl<false>(a, seq, units, sbeg, smid, ubeg, uend, cnt, stream);
 }
-int launch_sn_usolve(const SolveArgs &a, const int *seq, int sbeg, int smid, int send, void *stream) {
-    return launch_sn_solve_impl<true>(a, seq, sbeg, smid, send, stream);
+int launch_sn_usolve(const SolveArgs &a, const int *seq, const int *units, int sbeg, int smid, int ubeg, int uend,
+                     int *cnt, void *stream) {
+    return launch_sn_solve_impl<true>(a, seq, units, sbeg, smid, ubeg, uend, cnt, stream);
 }
 
 // A run of narrow levels [l0, l1): one workgroup per instance takes the rows of a
@@ -856,36 +954,96 @@ __device__ __forceinline__ void atomic_max_nonneg(double *addr, double v) {
     atomicMax(reinterpret_cast<unsigned long long *>(addr), (unsigned long long)__double_as_longlong(v));
 }
 
-__global__ void residual_kernel(int n, int nrhs, const int *Acp, const int *Acj, const int *Acsrc,
-                                const double *Aval, const double *x, int64_t ldx, const double *b,
-                                int64_t ldb, double *r, int64_t ldr, double *norms) {
-    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
-        for (int rr = 0; rr < nrhs; rr++) {
-            const double *xv = x + rr * ldx;
-            double s = b[rr * ldb + i];
-            for (int p = Acp[i]; p < Acp[i + 1]; p++) s -= Aval[Acsrc[p]] * xv[Acj[p]];
-            r[rr * ldr + i] = s;
-            atomic_max_nonneg(&norms[3 * rr + 0], fabs(s));
-            atomic_max_nonneg(&norms[3 * rr + 1], fabs(xv[i]));
-            atomic_max_nonneg(&norms[3 * rr + 2], fabs(b[rr * ldb + i]));
+// maximum of non-negative values that keeps a NaN (whose bit pattern orders above +inf)
+__device__ __forceinline__ double max_keep_nan(double m, double v) { return (v != v || v > m) ? v : m; }
+__device__ __forceinline__ double wave_max_keep_nan(double v) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v = max_keep_nan(v, __shfl_xor(v, off));
+    return v;
+}
+
+// r = b - A x for up to eight right-hand sides [r0, r0 + nr) of one instance: every thread takes
+// rows i (grid stride) and reads row i of A once for all of them, keeps running maxima of
+// |r|, |x|, |b| and the wavefront adds them to norms with one atomic each.
+__device__ __forceinline__ void residual_rows(int n, int nr, const int *Acp, const int *Acj, const int *Acsrc,
+                                              const double *Aval, const double *x, int64_t ldx, const double *b,
+                                              int64_t ldb, double *r, int64_t ldr, double *norms, int64_t i0,
+                                              int64_t stride) {
+    double mr[8], mx[8], mb[8];
+#pragma unroll
+    for (int u = 0; u < 8; u++) mr[u] = mx[u] = mb[u] = 0.0;
+    for (int64_t i = i0; i < n; i += stride) {
+        double acc[8];
+#pragma unroll
+        for (int u = 0; u < 8; u++) acc[u] = u < nr ? b[u * ldb + i] : 0.0;
+#pragma unroll
+        for (int u = 0; u < 8; u++) mb[u] = max_keep_nan(mb[u], fabs(acc[u]));
+        for (int p = Acp[i]; p < Acp[i + 1]; p++) {
+            const double v = Aval[Acsrc[p]];
+            const int j = Acj[p];
+#pragma unroll
+            for (int u = 0; u < 8; u++)
+                if (u < nr) acc[u] -= v * x[u * ldx + j];
+        }
+#pragma unroll
+        for (int u = 0; u < 8; u++)
+            if (u < nr) {
+                r[u * ldr + i] = acc[u];
+                mr[u] = max_keep_nan(mr[u], fabs(acc[u]));
+                mx[u] = max_keep_nan(mx[u], fabs(x[u * ldx + i]));
+            }
+    }
+    // maxima over the workgroup (four wavefronts), then one atomic per norm and workgroup: the
+    // norms share a cache line, where atomics serialize
+    __shared__ double wmax[4][24];
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+#pragma unroll
+    for (int u = 0; u < 8; u++) {
+        const double a0 = wave_max_keep_nan(mr[u]), a1 = wave_max_keep_nan(mx[u]), a2 = wave_max_keep_nan(mb[u]);
+        if (lane == 0) {
+            wmax[wv][3 * u + 0] = a0;
+            wmax[wv][3 * u + 1] = a1;
+            wmax[wv][3 * u + 2] = a2;
         }
     }
+    __syncthreads();
+    if ((int)threadIdx.x < 3 * nr) {
+        double m = wmax[0][threadIdx.x];
+        for (int q = 1; q < 4; q++) m = max_keep_nan(m, wmax[q][threadIdx.x]);
+        atomic_max_nonneg(&norms[threadIdx.x], m);
+    }
+    __syncthreads();
+}
+
+__global__ __launch_bounds__(256) void residual_kernel(int n, int nrhs, const int *Acp, const int *Acj,
+                                                       const int *Acsrc, const double *Aval, const double *x,
+                                                       int64_t ldx, const double *b, int64_t ldb, double *r,
+                                                       int64_t ldr, double *norms) {
+    const int64_t i0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x, stride = (int64_t)gridDim.x * blockDim.x;
+    for (int r0 = 0; r0 < nrhs; r0 += 8)
+        residual_rows(n, min(8, nrhs - r0), Acp, Acj, Acsrc, Aval, x + r0 * ldx, ldx, b + r0 * ldb, ldb,
+                      r + r0 * ldr, ldr, norms + 3 * r0, i0, stride);
 }
 
 int launch_residual(int n, int nrhs, const int *Acp, const int *Acj, const int *Acsrc,
                     const double *Aval, const double *x, int64_t ldx, const double *b, int64_t ldb,
                     double *r, int64_t ldr, double *norms, void *stream) {
-    hipLaunchKernelGGL(residual_kernel, dim3(grid_for(n, 256)), dim3(256), 0, (hipStream_t)stream, n, nrhs,
+    const int grid = std::min(grid_for(n, 256), 1024);   // a few rows per thread, few atomics
+    hipLaunchKernelGGL(residual_kernel, dim3(grid), dim3(256), 0, (hipStream_t)stream, n, nrhs,
                        Acp, Acj, Acsrc, Aval, x, ldx, b, ldb, r, ldr, norms);
     return (int)hipGetLastError();
 }
 
-__global__ void anorm_kernel(int n, const int *Acp, const int *Acsrc, const double *Aval, double *out) {
+__global__ __launch_bounds__(256) void anorm_kernel(int n, const int *Acp, const int *Acsrc, const double *Aval,
+                                                    double *out) {
+    double m = 0.0;
     for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
         double s = 0.0;
         for (int p = Acp[i]; p < Acp[i + 1]; p++) s += fabs(Aval[Acsrc[p]]);
-        atomic_max_nonneg(out, s);
+        m = max_keep_nan(m, s);
     }
+    m = wave_max_keep_nan(m);
+    if ((threadIdx.x & 63) == 0) atomic_max_nonneg(out, m);
 }
 
 int launch_anorm(int n, const int *Acp, const int *Acsrc, const double *Aval, double *out, void *stream) {
@@ -896,37 +1054,35 @@ int launch_anorm(int n, const int *Acp, const int *Acsrc, const double *Aval, do
 
 // Batched refinement: instance i uses values Aval + i*nnzA and vectors at
 // (i*nrhs + r)*n; skip[i] != -1 leaves an instance out.
-__global__ void residual_batched_kernel(int n, int nrhs, int batch, int64_t nnzA, const int *Acp, const int *Acj,
-                                        const int *Acsrc, const double *Aval, const double *x, const double *b,
-                                        double *r, double *norms, const int *skip) {
-    const int64_t total = (int64_t)n * batch;
-    for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < total; t += (int64_t)gridDim.x * blockDim.x) {
-        const int inst = (int)(t / n), i = (int)(t % n);
-        if (skip[inst] != -1) continue;
-        const double *Av = Aval + (size_t)inst * nnzA;
-        for (int rr = 0; rr < nrhs; rr++) {
-            const size_t o = ((size_t)inst * nrhs + rr) * n;
-            double acc = b[o + i];
-            for (int p = Acp[i]; p < Acp[i + 1]; p++) acc -= Av[Acsrc[p]] * x[o + Acj[p]];
-            r[o + i] = acc;
-            double *nm = norms + ((size_t)inst * nrhs + rr) * 3;
-            atomic_max_nonneg(&nm[0], fabs(acc));
-            atomic_max_nonneg(&nm[1], fabs(x[o + i]));
-            atomic_max_nonneg(&nm[2], fabs(b[o + i]));
-        }
+// one instance per blockIdx.y
+__global__ __launch_bounds__(256) void residual_batched_kernel(int n, int nrhs, int64_t nnzA, const int *Acp,
+                                                               const int *Acj, const int *Acsrc, const double *Aval,
+                                                               const double *x, const double *b, double *r,
+                                                               double *norms, const int *skip) {
+    const int inst = (int)blockIdx.y;
+    if (skip[inst] != -1) return;
+    const int64_t i0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x, stride = (int64_t)gridDim.x * blockDim.x;
+    const double *Av = Aval + (size_t)inst * nnzA;
+    for (int r0 = 0; r0 < nrhs; r0 += 8) {
+        const size_t o = ((size_t)inst * nrhs + r0) * n;
+        residual_rows(n, min(8, nrhs - r0), Acp, Acj, Acsrc, Av, x + o, n, b + o, n, r + o, n,
+                      norms + ((size_t)inst * nrhs + r0) * 3, i0, stride);
     }
 }
 
-__global__ void anorm_batched_kernel(int n, int batch, int64_t nnzA, const int *Acp, const int *Acsrc,
-                                     const double *Aval, double *out) {
-    const int64_t total = (int64_t)n * batch;
-    for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < total; t += (int64_t)gridDim.x * blockDim.x) {
-        const int inst = (int)(t / n), i = (int)(t % n);
-        const double *Av = Aval + (size_t)inst * nnzA;
+// one instance per blockIdx.y
+__global__ __launch_bounds__(256) void anorm_batched_kernel(int n, int64_t nnzA, const int *Acp, const int *Acsrc,
+                                                            const double *Aval, double *out) {
+    const int inst = (int)blockIdx.y;
+    const double *Av = Aval + (size_t)inst * nnzA;
+    double m = 0.0;
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
         double s = 0.0;
         for (int p = Acp[i]; p < Acp[i + 1]; p++) s += fabs(Av[Acsrc[p]]);
-        atomic_max_nonneg(&out[inst], s);
+        m = max_keep_nan(m, s);
     }
+    m = wave_max_keep_nan(m);
+    if ((threadIdx.x & 63) == 0) atomic_max_nonneg(&out[inst], m);
 }
 
 // eta[i] = max over right-hand sides of |r| / (|A| |x| + |b|); an instance whose
@@ -949,15 +1105,17 @@ __global__ void ir_check_kernel(int batch, int nrhs, const double *norms, const 
 int launch_residual_batched(int n, int nrhs, int batch, int64_t nnzA, const int *Acp, const int *Acj,
                             const int *Acsrc, const double *Aval, const double *x, const double *b, double *r,
                             double *norms, const int *skip, void *stream) {
-    hipLaunchKernelGGL(residual_batched_kernel, dim3(grid_for((int64_t)n * batch, 256)), dim3(256), 0,
-                       (hipStream_t)stream, n, nrhs, batch, nnzA, Acp, Acj, Acsrc, Aval, x, b, r, norms, skip);
+    if (batch <= 0 || n <= 0) return 0;
+    hipLaunchKernelGGL(residual_batched_kernel, dim3(std::min(grid_for(n, 256), 1024), (unsigned)batch), dim3(256), 0,
+                       (hipStream_t)stream, n, nrhs, nnzA, Acp, Acj, Acsrc, Aval, x, b, r, norms, skip);
     return (int)hipGetLastError();
 }
 
 int launch_anorm_batched(int n, int batch, int64_t nnzA, const int *Acp, const int *Acsrc, const double *Aval,
                          double *out, void *stream) {
-    hipLaunchKernelGGL(anorm_batched_kernel, dim3(grid_for((int64_t)n * batch, 256)), dim3(256), 0,
-                       (hipStream_t)stream, n, batch, nnzA, Acp, Acsrc, Aval, out);
+    if (batch <= 0 || n <= 0) return 0;
+    hipLaunchKernelGGL(anorm_batched_kernel, dim3(grid_for(n, 256), (unsigned)batch), dim3(256), 0,
+                       (hipStream_t)stream, n, nnzA, Acp, Acsrc, Aval, out);
     return (int)hipGetLastError();
 }
 

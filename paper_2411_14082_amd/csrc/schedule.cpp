@@ -38,6 +38,19 @@ static int choose_tail(const Factor &f, const cktlu_options &opt) {
     return 0;
 }
 
+// update tasks of at least this many multiply-adds get a workgroup (four wavefronts)
+constexpr double kHeavyTask = 16384.0;
+// supernodal solves: a singleton whose row pulls at least kSolveLongRow entries gets a
+// workgroup; a supernode's pull is split into slices of about kSolvePullChunk entries (at most
+// kSolveMaxSplit slices), one workgroup each
+constexpr int64_t kSolveLongRow = 1024;
+constexpr int64_t kSolvePullChunk = 8192;
+constexpr int64_t kSolveMaxSplit = 1024;
+// rows of R per unit of a wide panel (two passes of its eight wavefronts) and of a small one
+// (two passes of its wavefront)
+constexpr int kPanelRows = 256;
+constexpr int kSmallPanelRows = 128;
+
 // Supernodal sweep schedule of the sparse columns [0, T) (see Schedule).  Needs the device
 // layout (Dp, Dlen, Fi_dev) and the row lists of L (Lrp, Lrj).
 static void build_supernodal(const Factor &f, Schedule &s, int T, int wmax) {
@@ -72,6 +85,10 @@ static void build_supernodal(const Factor &f, Schedule &s, int T, int wmax) {
         s.sn_rec[4 * (size_t)S + 0] = a;
         s.sn_rec[4 * (size_t)S + 1] = w;
         s.sn_rec[4 * (size_t)S + 2] = (int)(f.Fp[a + w] - lbeg(a + w - 1));   // |R| = |L(:, s1-1)|
+        {
+            const int *rb = f.Fi.data() + lbeg(a + w - 1), *re = f.Fi.data() + f.Fp[a + w];
+            s.sn_rec[4 * (size_t)S + 3] = (int)(std::lower_bound(rb, re, T) - rb);   // rows of R below T
+        }
         for (int j = a; j < a + w; j++) s.sn_cb[j] = s.Dp[j] + f.nU[j] - 1 - (j - a);
     }
     // ---- levels
@@ -94,25 +111,57 @@ static void build_supernodal(const Factor &f, Schedule &s, int T, int wmax) {
         nl = std::max(nl, l + 1);
     }
     s.sn_levels = nl;
-    // supernodes by level, singletons first inside a level, ascending ids otherwise
-    std::vector<int> cnt(nl + 1, 0), cnt1(nl, 0);
+    // supernodes by level: singletons, then small panels, then the wider ones; ascending ids
+    // inside each group
+    std::vector<int> cnt(nl + 1, 0), cnt1(nl, 0), cnt2(nl, 0);
     for (int S = 0; S < nsn; S++) {
+        const int w = s0v[S + 1] - s0v[S];
         cnt[lev[S] + 1]++;
-        if (s0v[S + 1] - s0v[S] == 1) cnt1[lev[S]]++;
+        if (w == 1) cnt1[lev[S]]++;
+        else if (w <= cktlu_dev::kSnSmallW) cnt2[lev[S]]++;
     }
     for (int l = 0; l < nl; l++) cnt[l + 1] += cnt[l];
     s.sn_lvl.assign(cnt.begin(), cnt.end());
     s.sn_lvl_single.resize(nl);
-    std::vector<int> fill1(nl), fill2(nl);
+    s.sn_lvl_small.resize(nl);
+    std::vector<int> fill1(nl), fill2(nl), fill3(nl);
     for (int l = 0; l < nl; l++) {
         s.sn_lvl_single[l] = cnt[l] + cnt1[l];
+        s.sn_lvl_small[l] = cnt[l] + cnt1[l] + cnt2[l];
         fill1[l] = cnt[l];
-        fill2[l] = cnt[l] + cnt1[l];
+        fill2[l] = s.sn_lvl_single[l];
+        fill3[l] = s.sn_lvl_small[l];
     }
     s.sn_seq.resize(nsn);
     for (int S = 0; S < nsn; S++) {
-        if (s0v[S + 1] - s0v[S] == 1) s.sn_seq[fill1[lev[S]]++] = S;
-        else s.sn_seq[fill2[lev[S]]++] = S;
+        const int w = s0v[S + 1] - s0v[S];
+        if (w == 1) s.sn_seq[fill1[lev[S]]++] = S;
+        else if (w <= cktlu_dev::kSnSmallW) s.sn_seq[fill2[lev[S]]++] = S;
+        else s.sn_seq[fill3[lev[S]]++] = S;
+    }
+    // panels as units, each taking a slice of R's rows: small panels (a wavefront each)
+    // P = ceil(m / kSmallPanelRows), wide ones (a workgroup each) P = ceil(m / kPanelRows).
+    // Scratch blocks are numbered per launch
+    s.sn_punit.clear();
+    s.sn_sunit.clear();
+    s.sn_pulvl.assign(nl + 1, 0);
+    s.sn_sulvl.assign(nl + 1, 0);
+    s.sn_pnscr = 0;
+    auto units = [&](int q0, int q1, int rows, std::vector<int> &u) {
+        int blocks = 0;
+        for (int q = q0; q < q1; q++) {
+            const int m = s.sn_rec[4 * (size_t)s.sn_seq[q] + 2];
+            const int P = std::max(1, (m + rows - 1) / rows);
+            for (int p = 0; p < P; p++) u.insert(u.end(), {q, p, P, P > 1 ? blocks : -1});
+            if (P > 1) blocks += P;
+        }
+        s.sn_pnscr = std::max(s.sn_pnscr, blocks);
+    };
+    for (int l = 0; l < nl; l++) {
+        units(s.sn_lvl_single[l], s.sn_lvl_small[l], kSmallPanelRows, s.sn_sunit);
+        units(s.sn_lvl_small[l], s.sn_lvl[l + 1], kPanelRows, s.sn_punit);
+        s.sn_sulvl[l + 1] = (int)(s.sn_sunit.size() / 4);
+        s.sn_pulvl[l + 1] = (int)(s.sn_punit.size() / 4);
     }
     // ---- update tasks: the pairs (S, k), k outside S with U(s1-1, k) != 0 (then U(S, k) is a
     // suffix of S's rows: a row of S present in k fills every later row of S in k), grouped
@@ -174,18 +223,104 @@ static void build_supernodal(const Factor &f, Schedule &s, int T, int wmax) {
     if (!s.sn_task.empty()) s.sn_task[s.sn_task.size() - 1] = (int)nitems;
     s.sn_moff[nitems] = moff;
     for (int q = 0; q < nl; q++) s.sn_task_lvl[q + 1] += s.sn_task_lvl[q];
+    // inside each level: heavy tasks (rows of R times suffix rows at least kHeavyTask) first, a
+    // workgroup each; then light tasks, a wavefront each; then tiny tasks (every item at most
+    // kTinyRows suffix rows and rows of R), sixteen lanes each.  The order of tasks does not
+    // change results
+    s.sn_task_heavy.assign(nl, 0);
+    s.sn_task_tiny.assign(nl, 0);
+    {
+        std::vector<int> tmp;
+        for (int q = 0; q < nl; q++) {
+            const int t0 = s.sn_task_lvl[q], t1 = s.sn_task_lvl[q + 1];
+            std::vector<int> heavy, light, tiny;
+            for (int t = t0; t < t1; t++) {
+                double cost = 0;
+                bool small = true;
+                for (int it2 = s.sn_task[4 * (size_t)t + 2]; it2 < s.sn_task[4 * (size_t)t + 3]; it2++) {
+                    cost += (double)s.sn_item[4 * (size_t)it2 + 3] * s.sn_item[4 * (size_t)it2 + 2];
+                    small = small && s.sn_item[4 * (size_t)it2 + 2] <= cktlu_dev::kTinyRows &&
+                            s.sn_item[4 * (size_t)it2 + 3] <= cktlu_dev::kTinyRows;
+                }
+                (cost >= kHeavyTask ? heavy : small ? tiny : light).push_back(t);
+            }
+            s.sn_task_heavy[q] = t0 + (int)heavy.size();
+            s.sn_task_tiny[q] = t0 + (int)(heavy.size() + light.size());
+            for (const std::vector<int> *g : {&heavy, &light, &tiny})
+                for (int t : *g) tmp.insert(tmp.end(), s.sn_task.begin() + 4 * (size_t)t, s.sn_task.begin() + 4 * (size_t)t + 4);
+        }
+        s.sn_task.swap(tmp);
+    }
     // panels: the diagonal block's LU and L21 = A21 U11^-1
     for (int S = 0; S < nsn; S++) {
         const double w = s0v[S + 1] - s0v[S], m = s.sn_rec[4 * (size_t)S + 2];
         macs += w * w * w / 3.0 + m * w * w / 2.0;
     }
     s.sn_macs = macs;
+    // ---- Schur update of the dense block by supernodes: a dense column k's rows < T (U entries)
+    // that belong to one supernode are consecutive columns of it, so S(:, k) -= L21_hi U(those, k)
+    // is one product per (supernode, k), L21_hi being the supernode's rows >= T.  Items {S, first
+    // column of S, columns, position of the first row in k}; each column's items are cut into
+    // parts of similar cost (one round trip per item plus one per 128 rows times columns / 8),
+    // part 0 in place and later parts in scratch columns added in part order.
+    s.schur_sn_items.clear();
+    s.schur_parts.clear();
+    s.schur_add.clear();
+    s.schur_nscr = 0;
+    if (T < n) {
+        const int Dn = n - T;
+        std::vector<std::vector<int>> citems(Dn);
+        std::vector<double> ccost(Dn, 0.0);
+        double tot = 0.0;
+        for (int c = 0; c < Dn; c++) {
+            const int k = T + c;
+            const int64_t b = f.Fp[k], e = f.Fp[k] + f.nU[k] - 1;
+            int64_t q = b;
+            while (q < e && f.Fi[q] < T) {
+                const int j = f.Fi[q], S = snof[j];
+                int g = 1;
+                while (q + g < e && f.Fi[q + g] == j + g && j + g < s0v[S + 1]) g++;
+                const int mhi = s.sn_rec[4 * (size_t)S + 2] - s.sn_rec[4 * (size_t)S + 3];
+                if (mhi > 0) {
+                    citems[c].insert(citems[c].end(), {S, j - s0v[S], g, (int)(q - b)});
+                    const double cost = 1.0 + (double)mhi * g / 1024.0;
+                    ccost[c] += cost;
+                    tot += cost;
+                }
+                q += g;
+            }
+        }
+        const double budget = std::max(1.0, 1.5 * tot / Dn);
+        for (int c = 0; c < Dn; c++) {
+            const int ni = (int)citems[c].size() / 4;
+            const int scr0 = s.schur_nscr;
+            for (int i0 = 0, part = 0; i0 < ni; part++) {
+                double acc = 0.0;
+                int i1 = i0;
+                while (i1 < ni) {
+                    const int *it = citems[c].data() + 4 * i1;
+                    const double cost = 1.0 + (double)(s.sn_rec[4 * (size_t)it[0] + 2] - s.sn_rec[4 * (size_t)it[0] + 3]) *
+                                                  it[2] / 1024.0;
+                    if (i1 > i0 && acc + cost > budget) break;
+                    acc += cost;
+                    i1++;
+                }
+                const int first = (int)(s.schur_sn_items.size() / 4);
+                s.schur_sn_items.insert(s.schur_sn_items.end(), citems[c].begin() + 4 * i0, citems[c].begin() + 4 * i1);
+                const int scr = part == 0 ? -1 : s.schur_nscr++;
+                s.schur_parts.insert(s.schur_parts.end(), {c, first, first + (i1 - i0), scr});
+                i0 = i1;
+            }
+            if (s.schur_nscr > scr0) s.schur_add.insert(s.schur_add.end(), {c, scr0, s.schur_nscr - scr0, 0});
+        }
+    }
     // ---- solve levels over the supernodes.  L: the rows of S reach column j < s0 through
     // L(i, j); U: the rows of S reach column k >= s1 through U(i, k) (k < T: dense columns are
     // solved before the sparse U rows)
     auto solve_levels = [&](bool upper, int &nlev, std::vector<int> &lvl, std::vector<int> &single,
-                            std::vector<int> &seq) {
+                            std::vector<int> &seq, std::vector<int> &unit, std::vector<int> &ulvl, int &nscr) {
         std::vector<int> lv(nsn, 0);
+        std::vector<int64_t> pull(nsn, 0);            // entries outside the diagonal block
         nlev = nsn ? 1 : 0;
         for (int q = 0; q < nsn; q++) {
             const int S = upper ? nsn - 1 - q : q;
@@ -194,18 +329,25 @@ static void build_supernodal(const Factor &f, Schedule &s, int T, int wmax) {
             for (int i = a; i < e; i++) {
                 if (!upper) {
                     for (int p = s.Lrp[i]; p < s.Lrp[i + 1] - (i - a); p++) v = std::max(v, lv[snof[s.Lrj[p]]] + 1);
+                    pull[S] += s.Lrp[i + 1] - (i - a) - s.Lrp[i];
                 } else {
                     for (int p = s.Urp[i] + (e - 1 - i); p < s.Urp[i + 1]; p++)
                         if (s.Urj[p] < T) v = std::max(v, lv[snof[s.Urj[p]]] + 1);
+                    pull[S] += s.Urp[i + 1] - (s.Urp[i] + (e - 1 - i));
                 }
             }
             lv[S] = v;
             nlev = std::max(nlev, v + 1);
         }
+        // a wavefront per supernode of at most kSnSmallW rows with a short pull; a workgroup per
+        // unit of every other supernode
+        auto wave_row = [&](int S) {
+            return s0v[S + 1] - s0v[S] <= cktlu_dev::kSnSmallW && pull[S] < kSolveLongRow;
+        };
         std::vector<int> c(nlev + 1, 0), c1(nlev, 0);
         for (int S = 0; S < nsn; S++) {
             c[lv[S] + 1]++;
-            if (s0v[S + 1] - s0v[S] == 1) c1[lv[S]]++;
+            if (wave_row(S)) c1[lv[S]]++;
         }
         for (int l2 = 0; l2 < nlev; l2++) c[l2 + 1] += c[l2];
         lvl.assign(c.begin(), c.end());
@@ -218,12 +360,29 @@ static void build_supernodal(const Factor &f, Schedule &s, int T, int wmax) {
         }
         seq.resize(nsn);
         for (int S = 0; S < nsn; S++) {
-            if (s0v[S + 1] - s0v[S] == 1) seq[f1[lv[S]]++] = S;
+            if (wave_row(S)) seq[f1[lv[S]]++] = S;
             else seq[f2[lv[S]]++] = S;
         }
+        // units: a supernode whose pull exceeds kSolvePullChunk entries is split into P units that
+        // pull a 1/P slice of every row; their partial sums meet in scratch blocks (P per
+        // supernode, numbered within the level) and the last unit to finish solves the triangle
+        unit.clear();
+        ulvl.assign(nlev + 1, 0);
+        nscr = 0;
+        for (int l2 = 0; l2 < nlev; l2++) {
+            int blocks = 0;
+            for (int q = single[l2]; q < lvl[l2 + 1]; q++) {
+                const int S = seq[q];
+                const int P = (int)std::min<int64_t>(kSolveMaxSplit, std::max<int64_t>(1, (pull[S] + kSolvePullChunk - 1) / kSolvePullChunk));
+                for (int p = 0; p < P; p++) unit.insert(unit.end(), {q, p, P, P > 1 ? blocks : -1});
+                if (P > 1) blocks += P;
+            }
+            ulvl[l2 + 1] = (int)(unit.size() / 4);
+            nscr = std::max(nscr, blocks);
+        }
     };
-    solve_levels(false, s.snl_levels, s.snl_lvl, s.snl_single, s.snl_seq);
-    solve_levels(true, s.snu_levels, s.snu_lvl, s.snu_single, s.snu_seq);
+    solve_levels(false, s.snl_levels, s.snl_lvl, s.snl_single, s.snl_seq, s.snl_unit, s.snl_ulvl, s.snl_nscr);
+    solve_levels(true, s.snu_levels, s.snu_lvl, s.snu_single, s.snu_seq, s.snu_unit, s.snu_ulvl, s.snu_nscr);
     // ---- slot map: where each row of R lands in the target column (struct R is inside it)
     s.sn_map.resize((size_t)moff);
     auto fill = [&](int64_t i0, int64_t i1) {

@@ -780,3 +780,49 @@ def test_supernodal_panel_failure_fallback(ck, oracle_mod):
         assert np.array_equal(pv2, lu.pivrow)
     finally:
         ck.cktlu_destroy(ctx)
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32_ir"])
+def test_static_pivoting_scaling_gpu(ck, oracle_mod, precision):
+    """Pre-processing with values (maximum-product matching and scaling, Section III-A): the
+    device refactorization factors S_r P A S_c, equal to the oracle's factorization of that
+    matrix; solutions solve the caller's unscaled system (eta <= 1e-12, 1e-10 with FP32
+    factors and refinement) and a batch gives each instance's single factors bit for bit."""
+    c = mnagen.mesh_vsrc(24, 24, 4, seed=61)
+    prec = ck.CKTLU_FP64 if precision == "fp64" else ck.CKTLU_FP32_IR
+    s = ck.SparseLU(c.n, c.colptr, c.rowind, eps=EPS, static_pivoting=2, values=c.values, precision=prec,
+                    ir_tol=1e-10, dense_tail=100)
+    s.factorize(dev(c.values))
+    a0 = s.analysis()
+    rs, cs = s.scaling()
+    assert not np.all(rs == 1.0)
+    cols = np.repeat(np.arange(c.n), np.diff(c.colptr))
+    vh = mnagen.restamp(c, 61, 0, 1)
+    rc, info = s.refactorize(dev(vh))
+    vs = vh * rs[c.rowind] * cs[cols]
+    lu = oracle_refactor(oracle_mod, c, vs, a0, EPS, a0["pivrow"])
+    assert lu.status == 0 and np.array_equal(s.analysis()["pivrow"], lu.pivrow)
+    if precision == "fp64":
+        compare_factors(s.factors(), lu)
+    b = c.rhs[0]
+    x = torch.zeros(c.n, dtype=torch.float64, device="cuda:0")
+    s.solve(dev(b), x)
+    torch.cuda.synchronize()
+    eta = oracle_mod.backward_error(c.colptr, c.rowind, vh, x.cpu().numpy(), b)
+    assert eta <= (1e-12 if precision == "fp64" else 1e-10), eta
+    if precision == "fp64":
+        batch = 3
+        V = np.stack([vh, mnagen.restamp(c, 61, 0, 2), vh])
+        st = torch.zeros(batch, dtype=torch.int32, device="cuda:0")
+        s.refactorize_batched(batch, dev(V), st)
+        X = torch.zeros((batch, 1, c.n), dtype=torch.float64, device="cuda:0")
+        s.solve_batched(batch, 1, dev(np.repeat(c.rhs[:1][None], batch, axis=0)), X, st)
+        torch.cuda.synchronize()
+        sth, Xh = st.cpu().numpy(), X.cpu().numpy()
+        for i in range(batch):
+            if sth[i] == -1:
+                assert oracle_mod.backward_error(c.colptr, c.rowind, V[i], Xh[i, 0], b) <= 1e-12
+        if sth[2] == -1:
+            fb = s.factors(instance=2)
+            f1 = s.factors()
+            assert np.array_equal(fb["Lx"], f1["Lx"])
