@@ -391,6 +391,9 @@ def main():
     ap.add_argument("--workload", default="power_grid_1000_8rhs", choices=sorted(WORKLOADS))
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp32", action="store_true")
+    ap.add_argument("--calibrate-copy-mib", type=int, default=0,
+                    help="before the legs, copy a device buffer of this many MiB once (a plain copy kernel of "
+                         "known size that HBM counters of the same run can be scaled by)")
     ap.add_argument("--dense-tail", type=int, default=None,
                     help="order of the dense trailing block: 0 automatic (default), -1 none, >0 forced")
     ap.add_argument("--dense-density", type=float, default=None,
@@ -452,6 +455,13 @@ def main():
                      sweep_slot_map=-1 if args.no_slot_map else None)
     if args.repivot_rates:
         return main_repivot(args, wl, c, vals_dev, b_dev, tail_opts, ck, torch)
+    if args.calibrate_copy_mib > 0:
+        src = torch.ones(args.calibrate_copy_mib << 17, dtype=torch.float64, device=dev)
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        log("calibration copy: %d bytes read and written" % (src.numel() * 8))
+        del src, dst
     res64 = run_leg(ck, torch, c, vals_dev, b_dev, ck.CKTLU_FP64, args.steps, args.warmup, tail_opts)
     log("fp64: %.3f steps/s, refactor %.2f ms, solve %.2f ms (setup %.1fs), dense tail %d" %
         (args.steps / res64["wall"], res64["ref_ms"].mean(), res64["sol_ms"].mean(), res64["setup_s"],
@@ -474,17 +484,19 @@ def main():
     tm = res64["timing"]
     steps_per_s = args.steps / res64["wall"]
     t_step = res64["wall"] / args.steps
-    # whole step on the compulsory bytes: refactorization (A values and map, factor index and
-    # value per entry); each solve pass (up to eight right-hand sides) reads the factor once and
-    # every right-hand side adds its rows (b read, x written, permutations)
+    # whole step on the survey's compulsory bytes: refactorization (A values and map, factor index
+    # and value per entry) and, per right-hand side, a solve's factor index and value per entry
+    # plus 24 B per row.  The library solves up to eight right-hand sides in one pass that reads
+    # the factor once; that count is reported beside it
+    b_step = st["bytes_refactor"] + nrhs * st["bytes_solve"]
     passes = solve_passes(nrhs)
-    fac_read = st["bytes_solve"] - 24.0 * c.n
-    b_step = st["bytes_refactor"] + passes * fac_read + nrhs * 24.0 * c.n
+    b_pass = st["bytes_refactor"] + passes * (st["bytes_solve"] - 24.0 * c.n) + nrhs * 24.0 * c.n
     roofline_step = dict(bound="hbm", achieved=b_step / t_step / 1e9, peak=HBM_PEAK_GBS, unit="GB/s",
                          frac=b_step / t_step / 1e9 / HBM_PEAK_GBS, bytes_per_step=b_step,
                          bytes_model="12 B per A nonzero + 12 B per factor entry (refactorization) + "
-                                     "12 B per factor entry per solve pass of up to 8 right-hand sides + "
-                                     "24 B per row per right-hand side")
+                                     "(12 B per factor entry + 24 B per row) per right-hand side",
+                         bytes_per_step_factor_read_once_per_pass=b_pass,
+                         frac_factor_read_once_per_pass=b_pass / t_step / 1e9 / HBM_PEAK_GBS)
     # dominant kernel: the sparse sweep.  Supernodal: sn_panel_kernel and sn_update_kernel, one of
     # each per level; column sweep: refactor_level_kernel, one per level.  Its launches run back
     # to back on the library's stream, so the average launch lasts sweep_ms / launches

@@ -109,6 +109,14 @@ typedef struct {
                               S_c with |diagonal| = 1 and every other entry at most 1 in magnitude: the library
                               then factors S_r P A S_c (its factors, pivot tests and getters refer to that
                               matrix) while values, right-hand sides and solutions stay the caller's */
+    int sweep_panel_rows;  /* supernodal sweep: a panel with more rows below its diagonal block than this is
+                              split into units of about this many rows (a workgroup each; panels of at most
+                              16 columns: half as many rows, a wavefront each), whose column maxima meet
+                              for the pivot test; 0 = 256, else 16 .. 65536.  Same results for any value */
+    int solve_split_entries; /* supernodal solves: a supernode whose rows hold more entries outside its
+                              diagonal block than this is split into units of about this many entries (a
+                              workgroup each) whose partial sums are added in a fixed order; 0 = 8192,
+                              else 64 .. 2^30.  Sums are grouped differently per value (rounding only) */
 } cktlu_options;
 
 typedef struct {
@@ -265,7 +273,8 @@ int cktlu_refactorize_nocheck(cktlu_ctx *ctx, const double *values_dev);
  * overlap.  In FP32_IR mode the residual, the update and the stopping test run
  * in FP64 against the values of the last refactorization (backward error
  * eta_inf <= ir_tol), falling back to FP64 factors when refinement stalls
- * (W_IR_FALLBACK).  After such a fallback the context keeps FP64 factors for
+ * (W_IR_FALLBACK); the first two refinement steps are queued together and
+ * decide convergence on the device, so the host waits once for them.  After such a fallback the context keeps FP64 factors for
  * its refactorizations and solves (info->used_fp64 = 1) until the next
  * cktlu_factorize: a circuit too ill-conditioned for FP32 factors stays so
  * while its values move by NR steps.  info may be NULL.  Errors: E_STATE,
@@ -346,7 +355,18 @@ typedef struct {
     int32_t dense_tail[16];       /* order D of the dense trailing block of each (0 = none) */
     double ms_per_step[16];       /* device time of one refactorization + solve of `batch` instances */
     int32_t best;                 /* index of the fastest, now in use */
+    /* second stage, with that D: the knobs the caller left at 0, one at a time */
+    int32_t n_knob_tried;         /* trials of the second stage */
+    int32_t knob[16];             /* CKTLU_KNOB_* of each trial */
+    int32_t knob_value[16];       /* the value tried */
+    double knob_ms_per_step[16];  /* its device time per step */
+    int32_t sweep_supernodes, sweep_panel_rows, solve_split_entries, dense_panel_width;  /* kept (0 = default) */
 } cktlu_tune_result;
+
+#define CKTLU_KNOB_SUPERNODE_WIDTH 0   /* options.sweep_supernodes: 64 (default) or 32 columns */
+#define CKTLU_KNOB_PANEL_ROWS 1        /* options.sweep_panel_rows: 256 (default), 128 or 512 */
+#define CKTLU_KNOB_SOLVE_SPLIT 2       /* options.solve_split_entries: 8192 (default), 4096 or 16384 */
+#define CKTLU_KNOB_DENSE_PANEL 3       /* options.dense_panel_width: 256 (default) or 128 */
 
 /*
  * Schedule autotuner (the dense-part threshold the paper fixes for its CPUs,
@@ -359,7 +379,12 @@ typedef struct {
  * on the context's stream, a step being the refactorization of `batch`
  * instances (values_dev: batch x nnz, as cktlu_refactorize_batched; batch 1
  * uses cktlu_refactorize) plus a solve of one right-hand side each.  The
- * fastest schedule stays in use (options.dense_tail_size is set to it).
+ * fastest schedule stays in use (options.dense_tail_size is set to it).  A
+ * second stage then tries, with that D and one knob at a time, the other
+ * values of each schedule knob the caller left at 0 (CKTLU_KNOB_*: the paper's
+ * CPU constants have GPU counterparts in the supernode width, the rows per
+ * panel unit, the entries per solve unit and the dense panel width), keeping
+ * a value when it is at least 2% faster.
  * The factors on the device are those of the last timed step.  Errors:
  * E_STATE, E_ARG, E_NOMEM, E_HIP.
  */

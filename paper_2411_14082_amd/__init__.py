@@ -61,7 +61,8 @@ class cktlu_options(ctypes.Structure):
                 ("timing", ctypes.c_int), ("solve_chain_width", ctypes.c_int),
                 ("dense_panel_width", ctypes.c_int), ("dense_lookahead", ctypes.c_int),
                 ("dense_device_repivot", ctypes.c_int), ("sweep_slot_map", ctypes.c_int),
-                ("sweep_supernodes", ctypes.c_int), ("static_pivoting", ctypes.c_int)]
+                ("sweep_supernodes", ctypes.c_int), ("static_pivoting", ctypes.c_int),
+                ("sweep_panel_rows", ctypes.c_int), ("solve_split_entries", ctypes.c_int)]
 
 
 class cktlu_refactor_info(ctypes.Structure):
@@ -98,7 +99,14 @@ class cktlu_stats(ctypes.Structure):
 
 class cktlu_tune_result(ctypes.Structure):
     _fields_ = [("n_tried", ctypes.c_int32), ("dense_tail", ctypes.c_int32 * 16),
-                ("ms_per_step", ctypes.c_double * 16), ("best", ctypes.c_int32)]
+                ("ms_per_step", ctypes.c_double * 16), ("best", ctypes.c_int32),
+                ("n_knob_tried", ctypes.c_int32), ("knob", ctypes.c_int32 * 16),
+                ("knob_value", ctypes.c_int32 * 16), ("knob_ms_per_step", ctypes.c_double * 16),
+                ("sweep_supernodes", ctypes.c_int32), ("sweep_panel_rows", ctypes.c_int32),
+                ("solve_split_entries", ctypes.c_int32), ("dense_panel_width", ctypes.c_int32)]
+
+
+KNOB_NAMES = {0: "sweep_supernodes", 1: "sweep_panel_rows", 2: "solve_split_entries", 3: "dense_panel_width"}
 
 
 class cktlu_server_options(ctypes.Structure):
@@ -421,7 +429,7 @@ class SparseLU:
                  ir_tol=1e-10, ir_max_iter=10, stream=None, transversal=1, dense_tail=None,
                  dense_tail_density=None, timing=False, solve_chain_width=None, dense_panel_width=None,
                  dense_lookahead=None, dense_device_repivot=None, sweep_slot_map=None, sweep_supernodes=None,
-                 static_pivoting=None, values=None):
+                 static_pivoting=None, values=None, sweep_panel_rows=None, solve_split_entries=None):
         opt = cktlu_default_options()
         opt.timing = 1 if timing else 0
         if dense_tail is not None:
@@ -442,6 +450,10 @@ class SparseLU:
             opt.sweep_supernodes = int(sweep_supernodes)
         if static_pivoting is not None:
             opt.static_pivoting = int(static_pivoting)
+        if sweep_panel_rows is not None:
+            opt.sweep_panel_rows = int(sweep_panel_rows)
+        if solve_split_entries is not None:
+            opt.solve_split_entries = int(solve_split_entries)
         opt.pivot_eps = eps
         opt.precision = precision
         opt.ordering = ordering
@@ -508,9 +520,12 @@ class SparseLU:
     def autotune(self, batch, values_dev, reps=3) -> dict:
         r = cktlu_tune_result()
         _check(cktlu_autotune(self.ctx, batch, values_dev, reps, r), "cktlu_autotune")
-        k = r.n_tried
+        k, m = r.n_tried, r.n_knob_tried
         return dict(dense_tail=list(r.dense_tail[:k]), ms_per_step=list(r.ms_per_step[:k]), best=r.best,
-                    best_dense_tail=r.dense_tail[r.best])
+                    best_dense_tail=r.dense_tail[r.best],
+                    knob_trials=[(KNOB_NAMES[r.knob[i]], r.knob_value[i], r.knob_ms_per_step[i]) for i in range(m)],
+                    kept=dict(sweep_supernodes=r.sweep_supernodes, sweep_panel_rows=r.sweep_panel_rows,
+                              solve_split_entries=r.solve_split_entries, dense_panel_width=r.dense_panel_width))
 
     def analysis(self, with_pivots=True):
         n = self.n

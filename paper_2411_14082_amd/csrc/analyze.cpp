@@ -1,12 +1,16 @@
-// Pre-processing (Section III-A): structural transversal, fill-reducing
-// ordering and the column elimination tree (Section II-B).
+// Pre-processing (Section III-A): static pivoting, fill-reducing ordering and the
+// column elimination tree (Section II-B).
 //
-// The paper's static pivoting is a maximum weighted matching on the values;
-// analyze() sees only the pattern, so a structural maximum transversal takes
-// its place: it gives a zero-free diagonal, which MNA matrices with ideal
-// voltage sources need.  The ordering is an approximate minimum degree
-// (Amestoy, Davis and Duff, SIAM J. Matrix Anal. Appl. 17(4), 1996) on the
-// pattern of B + B', written from the published method.
+// The paper's static pivoting is a maximum weighted matching on the values: with the
+// values (cktlu_analyze_values) the rows are matched to columns to maximise the product
+// of the matched magnitudes, optionally with the matching's row and column scaling; with
+// the pattern alone (cktlu_analyze) a structural maximum transversal takes its place.
+// Either gives a zero-free diagonal, which MNA matrices with ideal voltage sources need.
+// The orderings (approximate minimum degree after Amestoy, Davis and Duff, SIAM J. Matrix
+// Anal. Appl. 17(4), 1996, its minimum-fill variant, nested dissection, and nested
+// dissection followed by a constrained minimum degree) act on the pattern of B + B' and
+// are written from the published methods; the combined ordering keeps the one with the
+// least symbolic fill.
 #include <algorithm>
 #include <cmath>
 #include <cstring>

@@ -28,7 +28,6 @@ struct cktlu_ctx {
     bool fp64_sticky = false;      // FP32_IR: refinement fell back; FP64 until the next factorize
     int force_fail_pending = -1;
     int last_batch = 0;            // batch of the last batched refactorization
-    double anorm_host = 0.0;
     // the last pivot-check fallback: columns the device had not finished, and the restart set
     std::vector<char> last_unfinished, last_restart;
     // cktlu_factorize_host: the values, uploaded with the factors (FP32_IR residuals read them)
@@ -866,7 +865,8 @@ int tri_solves(cktlu_ctx *c, int nrhs, int batch, double *z, bool fp32, const in
     hipEvent_t t0 = phase_begin(c);
     int launches = 0;
     for (int l = 0; snodal && l < s.snl_levels; l++, launches++)
-        LCHK(launch_sn_lsolve(a, (const int *)d.snl_seq.p, (const int *)d.snl_unit.p, s.snl_lvl[l], s.snl_single[l],
+        LCHK(launch_sn_lsolve(a, (const int *)d.snl_seq.p, (const int *)d.snl_unit.p, s.snl_lvl[l], s.snl_tiny[l],
+                              s.snl_single[l],
                               s.snl_ulvl[l], s.snl_ulvl[l + 1], (int *)d.sn_cnt.p, st));
     const int ldense = s.tail0 < c->an.n ? (int)s.lsptr.size() - 2 : -1;   // level of the dense rows
     for (size_t g = 0; g < s.lseg.size(); g += 3) {
@@ -892,7 +892,8 @@ int tri_solves(cktlu_ctx *c, int nrhs, int batch, double *z, bool fp32, const in
     t0 = phase_begin(c);
     launches = 0;
     for (int l = 0; snodal && l < s.snu_levels; l++, launches++)
-        LCHK(launch_sn_usolve(a, (const int *)d.snu_seq.p, (const int *)d.snu_unit.p, s.snu_lvl[l], s.snu_single[l],
+        LCHK(launch_sn_usolve(a, (const int *)d.snu_seq.p, (const int *)d.snu_unit.p, s.snu_lvl[l], s.snu_tiny[l],
+                              s.snu_single[l],
                               s.snu_ulvl[l], s.snu_ulvl[l + 1],
                               d.sn_cnt.p ? (int *)d.sn_cnt.p + (size_t)s.sn_count * batch : nullptr, st));
     for (size_t g = 0; !snodal && g < s.useg.size(); g += 3, launches++) {
@@ -913,8 +914,9 @@ size_t vec_need(const cktlu_ctx *c, int nrhs) {
 }
 
 // zbuf: work rows (n x YS doubles) supplied by the caller, or nullptr for the context's own
+// skip: a device status word (-1 = solve), or null
 int solve_chunk(cktlu_ctx *c, int nrhs, const double *b, int64_t ldb, double *x, int64_t ldx, bool fp32,
-                bool accumulate, double *zbuf = nullptr) {
+                bool accumulate, double *zbuf = nullptr, const int *skip = nullptr) {
     const int n = c->an.n;
     int rc;
     double *z = zbuf;
@@ -924,17 +926,17 @@ int solve_chunk(cktlu_ctx *c, int nrhs, const double *b, int64_t ldb, double *x,
     }
     hipStream_t st = stream_of(c);
     LCHK(launch_gather_rhs(n, nrhs, 1, b, ldb, (const int *)c->dev.rowperm.p, z, st, (const double *)c->dev.gscale.p));
-    if ((rc = tri_solves(c, nrhs, 1, z, fp32, nullptr))) return rc;
+    if ((rc = tri_solves(c, nrhs, 1, z, fp32, skip))) return rc;
     LCHK(launch_scatter_sol(n, nrhs, 1, z, (const int *)c->dev.colperm_sol.p, x, ldx, accumulate ? 1 : 0,
-                            nullptr, st, (const double *)c->dev.sscale.p));
+                            skip, st, (const double *)c->dev.sscale.p));
     return CKTLU_OK;
 }
 
 int solve_plain(cktlu_ctx *c, int nrhs, const double *b, int64_t ldb, double *x, int64_t ldx, bool fp32,
-                bool accumulate, double *zbuf = nullptr) {
+                bool accumulate, double *zbuf = nullptr, const int *skip = nullptr) {
     for (int r0 = 0; r0 < nrhs;) {
         int chunk = nrhs - r0 >= 8 ? 8 : nrhs - r0 >= 4 ? 4 : nrhs - r0 >= 2 ? 2 : 1;
-        int rc = solve_chunk(c, chunk, b + r0 * ldb, ldb, x + r0 * ldx, ldx, fp32, accumulate, zbuf);
+        int rc = solve_chunk(c, chunk, b + r0 * ldb, ldb, x + r0 * ldx, ldx, fp32, accumulate, zbuf, skip);
         if (rc) return rc;
         r0 += chunk;
     }
@@ -943,44 +945,61 @@ int solve_plain(cktlu_ctx *c, int nrhs, const double *b, int64_t ldb, double *x,
 
 // Iterative refinement with FP32 factors: x = 0, r = b; repeat d = (LU)^{-1} r
 // (FP32 factors, FP64 accumulation), x += d, r = b - A x (FP64) until the
-// backward error of every right-hand side is at most ir_tol.
+// backward error of every right-hand side is at most ir_tol.  The first two steps are
+// queued together and decide convergence on the device (a converged step leaves the status
+// word, and the second step's kernels then return at once); the host reads the outcome once
+// after them and takes any further step, with the stall test, one at a time.
 int solve_ir(cktlu_ctx *c, int nrhs, const double *b, int64_t ldb, double *x, int64_t ldx,
              cktlu_solve_info *info, bool *converged) {
     const int n = c->an.n;
     hipStream_t st = stream_of(c);
     int rc = ensure_vec(c, vec_need(c, nrhs));
     if (rc) return rc;
-    double *r = (double *)c->dev.vec.p + (size_t)n * YS + 64;
+    double *vec = (double *)c->dev.vec.p;
+    double *r = vec + (size_t)n * YS + 64;
     double *norms = r + (size_t)n * nrhs;
-    for (int q = 0; q < nrhs; q++) HIPCHK(hipMemsetAsync(x + q * ldx, 0, (size_t)n * sizeof(double), st));
-    const double *rhs = b;
-    int64_t ldr = ldb;
-    double prev_eta = INFINITY, eta = INFINITY;
-    int it = 0;
-    *converged = false;
-    std::vector<double> h(3 * nrhs);
-    for (it = 1; it <= c->opt.ir_max_iter; it++) {
-        if ((rc = solve_plain(c, nrhs, rhs, ldr, x, ldx, true, true))) return rc;
-        HIPCHK(hipMemsetAsync(norms, 0, 3 * nrhs * sizeof(double), st));
-        LCHK(launch_residual(n, nrhs, (const int *)c->dev.Acp.p, (const int *)c->dev.Acj.p,
-                             (const int *)c->dev.Acsrc.p, (const double *)c->dev.Aval.p, x, ldx, b, ldb, r, n,
-                             norms, st));
-        HIPCHK(hipMemcpyAsync(h.data(), norms, 3 * nrhs * sizeof(double), hipMemcpyDeviceToHost, st));
+    double *anorm = vec + vec_need(c, nrhs) - 1;      // written by cktlu_solve
+    double *eta_d = anorm - 1;
+    int *skip = (int *)(anorm - 2);
+    for (int q = 0; q < nrhs; q++) LCHK(launch_fill_f64(x + q * ldx, n, 0.0, st));
+    LCHK(launch_fill_i32(skip, 1, -1, st));
+    LCHK(launch_fill_f64(eta_d, 1, INFINITY, st));
+    const int *Acp = (const int *)c->dev.Acp.p, *Acj = (const int *)c->dev.Acj.p;
+    const int *Acsrc = (const int *)c->dev.Acsrc.p;
+    const double *Aval = (const double *)c->dev.Aval.p;
+    auto step = [&](int it) -> int {
+        int e = solve_plain(c, nrhs, it == 1 ? b : r, it == 1 ? ldb : n, x, ldx, true, true, nullptr, skip);
+        if (e) return e;
+        LCHK(launch_fill_f64(norms, 3 * (int64_t)nrhs, 0.0, st));
+        LCHK(launch_residual(n, nrhs, Acp, Acj, Acsrc, Aval, x, ldx, b, ldb, r, n, norms, st, skip));
+        LCHK(launch_ir_check(1, nrhs, norms, anorm, c->opt.ir_tol, skip, eta_d, st));
+        return CKTLU_OK;
+    };
+    const int queued = std::min(2, c->opt.ir_max_iter);
+    int it = 0, hskip = -1;
+    double eta = INFINITY, prev_eta = INFINITY;
+    auto outcome = [&]() -> int {
+        HIPCHK(hipMemcpyAsync(&eta, eta_d, sizeof(double), hipMemcpyDeviceToHost, st));
+        HIPCHK(hipMemcpyAsync(&hskip, skip, sizeof(int), hipMemcpyDeviceToHost, st));
         HIPCHK(hipStreamSynchronize(st));
-        eta = 0.0;
-        for (int q = 0; q < nrhs; q++) {
-            const double den = c->anorm_host * h[3 * q + 1] + h[3 * q + 2];
-            const double e = den > 0 ? h[3 * q] / den : 0.0;
-            eta = std::max(eta, e);
-        }
-        if (info) info->backward_err = eta;
-        if (eta <= c->opt.ir_tol) { *converged = true; break; }
-        if (it >= 3 && eta > 0.5 * prev_eta) break;    // stalled
+        return CKTLU_OK;
+    };
+    *converged = false;
+    for (it = 1; it <= queued; it++)
+        if ((rc = step(it))) return rc;
+    if ((rc = outcome())) return rc;
+    it = queued;
+    while (hskip == -1 && it < c->opt.ir_max_iter) {
+        if (it >= 3 && eta > 0.5 * prev_eta) break;     // stalled
         prev_eta = eta;
-        rhs = r;
-        ldr = n;
+        if ((rc = step(++it))) return rc;
+        if ((rc = outcome())) return rc;
     }
-    if (info) info->ir_iters = std::min(it, c->opt.ir_max_iter);
+    *converged = hskip != -1;
+    if (info) {
+        info->backward_err = eta;
+        info->ir_iters = it;
+    }
     return CKTLU_OK;
 }
 
@@ -1017,6 +1036,8 @@ int cktlu_create(cktlu_ctx **out, const cktlu_options *opt) {
         (c->opt.sweep_slot_map != 0 && c->opt.sweep_slot_map != -1) ||
         c->opt.sweep_supernodes < -1 || c->opt.sweep_supernodes > 64 ||
         c->opt.static_pivoting < 0 || c->opt.static_pivoting > 2 ||
+        (c->opt.sweep_panel_rows != 0 && (c->opt.sweep_panel_rows < 16 || c->opt.sweep_panel_rows > 65536)) ||
+        (c->opt.solve_split_entries != 0 && (c->opt.solve_split_entries < 64 || c->opt.solve_split_entries > (1 << 30))) ||
         (c->opt.dense_panel_width != 0 && c->opt.dense_panel_width != 64 && c->opt.dense_panel_width != 128 &&
          c->opt.dense_panel_width != 256)) {
         delete c;
@@ -1171,12 +1192,10 @@ int cktlu_solve(cktlu_ctx *c, int32_t nrhs, const double *b, int32_t ldb, double
     hipStream_t st = stream_of(c);
     if ((rc = ensure_vec(c, vec_need(c, nrhs)))) return rc;
     {
-        double *an = (double *)c->dev.vec.p + vec_need(c, nrhs) - 1;
-        HIPCHK(hipMemsetAsync(an, 0, sizeof(double), st));
+        double *an = (double *)c->dev.vec.p + vec_need(c, nrhs) - 1;   // |A|_inf, read by solve_ir on the device
+        LCHK(launch_fill_f64(an, 1, 0.0, st));
         LCHK(launch_anorm(c->an.n, (const int *)c->dev.Acp.p, (const int *)c->dev.Acsrc.p,
                           (const double *)c->dev.Aval.p, an, st));
-        HIPCHK(hipMemcpyAsync(&c->anorm_host, an, sizeof(double), hipMemcpyDeviceToHost, st));
-        HIPCHK(hipStreamSynchronize(st));
     }
     bool conv = false;
     if ((rc = solve_ir(c, nrhs, b, ldb, x, ldx, info, &conv))) return rc;
@@ -1379,14 +1398,65 @@ int cktlu_autotune(cktlu_ctx *c, int32_t batch, const double *values_dev, int32_
             best_density = cd.density;
         }
     }
+    // second stage: with the best D, each knob left at 0 by the caller, one value at a time
+    cktlu_options tuned = saved;
+    tuned.dense_tail_size = best_size;
+    tuned.dense_tail_density = best_density;
+    struct Knob { int id; int cktlu_options::*field; std::vector<int> values; };
+    const std::vector<Knob> knobs = {
+        {CKTLU_KNOB_SUPERNODE_WIDTH, &cktlu_options::sweep_supernodes, {32}},
+        {CKTLU_KNOB_PANEL_ROWS, &cktlu_options::sweep_panel_rows, {128, 512}},
+        {CKTLU_KNOB_SOLVE_SPLIT, &cktlu_options::solve_split_entries, {4096, 16384}},
+        {CKTLU_KNOB_DENSE_PANEL, &cktlu_options::dense_panel_width, {128}},
+    };
+    for (const Knob &kb : knobs) {
+        if (rc || saved.*kb.field != 0) continue;
+        if (kb.id == CKTLU_KNOB_DENSE_PANEL && best_size <= 0) continue;
+        for (int v : kb.values) {
+            if (out->n_knob_tried >= 16) break;
+            c->opt = tuned;
+            c->opt.timing = 0;
+            c->opt.*kb.field = v;
+            Schedule trial;
+            size_t fr = 0, tot = 0;
+            const int64_t cap = hipMemGetInfo(&fr, &tot) == hipSuccess ? (int64_t)(0.25 * (double)fr / sizeof(int)) : 0;
+            build_schedule(c->an, c->f, c->opt, trial, std::min<int64_t>(cap, (int64_t)1 << 30));
+            c->s = std::move(trial);
+            fill_stats_pattern(c);
+            if ((rc = upload_all(c))) break;
+            if ((rc = step())) break;
+            if (hipEventRecord(e0, st) != hipSuccess) { rc = CKTLU_E_HIP; break; }
+            for (int r = 0; r < reps && !rc; r++) rc = step();
+            if (rc) break;
+            float ms = 0.f;
+            if (hipEventRecord(e1, st) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+                hipEventElapsedTime(&ms, e0, e1) != hipSuccess) { rc = CKTLU_E_HIP; break; }
+            const int k = out->n_knob_tried++;
+            out->knob[k] = kb.id;
+            out->knob_value[k] = v;
+            out->knob_ms_per_step[k] = ms / reps;
+            if (ms / reps < 0.98 * best_ms) {
+                best_ms = ms / reps;
+                tuned.*kb.field = v;
+            }
+        }
+    }
+    out->sweep_supernodes = tuned.sweep_supernodes;
+    out->sweep_panel_rows = tuned.sweep_panel_rows;
+    out->solve_split_entries = tuned.solve_split_entries;
+    out->dense_panel_width = tuned.dense_panel_width;
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
     release();
     c->opt = saved;
     if (rc) return rc;
     // keep the fastest schedule
-    c->opt.dense_tail_size = best_size;
-    c->opt.dense_tail_density = best_density;
+    c->opt.dense_tail_size = tuned.dense_tail_size;
+    c->opt.dense_tail_density = tuned.dense_tail_density;
+    c->opt.sweep_supernodes = tuned.sweep_supernodes;
+    c->opt.sweep_panel_rows = tuned.sweep_panel_rows;
+    c->opt.solve_split_entries = tuned.solve_split_entries;
+    c->opt.dense_panel_width = tuned.dense_panel_width;
     build_schedule(c->an, c->f, c->opt, c->s);
     fill_stats_pattern(c);
     return upload_all(c);
@@ -1459,6 +1529,9 @@ int cktlu_solve_batched(cktlu_ctx *c, int32_t batch, int32_t nrhs, const double 
         LCHK(launch_fill_f64(norms, 3 * (int64_t)nrhs * batch, 0.0, st));
         LCHK(launch_residual_batched(n, nrhs, batch, nnzA, Acp, Acj, Acsrc, Aval, x, b, r, norms, skip, st));
         LCHK(launch_ir_check(batch, nrhs, norms, anorm, c->opt.ir_tol, skip, eta, st));
+        // the first step's outcome stays on the device (converged instances skip the second
+        // step's kernels); the host reads it after the second
+        if (it == 1 && c->opt.ir_max_iter >= 2) continue;
         HIPCHK(hipMemcpyAsync(hskip.data(), skip, batch * sizeof(int), hipMemcpyDeviceToHost, st));
         HIPCHK(hipMemcpyAsync(heta.data(), eta, batch * sizeof(double), hipMemcpyDeviceToHost, st));
         HIPCHK(hipStreamSynchronize(st));

@@ -1,4 +1,5 @@
-// Dense trailing block of the factorization (gfx950).
+// Dense trailing block of the factorization, and the supernodal sweep of the sparse
+// columns before it (gfx950).
 //
 // The last D columns of the factors are nearly dense: the paper's dense
 // triangular block (Section V-A), whose order it picks from the fill density.
@@ -26,6 +27,9 @@
 // solves run one launch per NB-row block: the launch for block b applies block
 // b-1's solution to every row below it (the rectangle of the paper's trapezoid
 // slices, Section V-A) and then one wavefront solves block b (the triangle).
+// The Schur update S -= L21 U12 runs by supernode column runs (schur_sn_kernel)
+// after a supernodal sweep, by bridge columns (schur_kernel) after a column sweep.
+// The supernodal sweep itself (sn_*_kernel) is described at its section below.
 #include <hip/hip_runtime.h>
 
 #include <climits>

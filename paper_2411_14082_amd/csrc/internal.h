@@ -180,12 +180,13 @@ struct Schedule {
     // its diagonal block (L: columns < s0; U: columns >= s0 + w), then its dense triangle is
     // solved.  Level = longest path over the supernodes those entries reach.  Per level of the
     // L (U) solve: its supernodes in snl_seq (snu_seq) [snl_lvl[l], snl_lvl[l+1]), singletons
-    // first up to snl_single[l] (at most kSnSmallW rows and a short pull: a wavefront each).
+    // first: singletons with a short row up to snl_tiny[l] (sixteen lanes each), then up to
+    // snl_single[l] the others of at most kSnSmallW rows and a short pull (a wavefront each).
     // The workgroup units of level l: snl_unit [snl_ulvl[l], snl_ulvl[l+1]), int4 {position in
     // snl_seq, slice p, slices P, first scratch block of the supernode (-1 when P = 1)}; a level
     // uses at most snl_nscr scratch blocks.
     int snl_levels = 0, snu_levels = 0;
-    std::vector<int> snl_lvl, snl_single, snl_seq, snu_lvl, snu_single, snu_seq;
+    std::vector<int> snl_lvl, snl_tiny, snl_single, snl_seq, snu_lvl, snu_tiny, snu_single, snu_seq;
     std::vector<int> snl_unit, snl_ulvl, snu_unit, snu_ulvl;
     int snl_nscr = 0, snu_nscr = 0;
 };
@@ -311,13 +312,14 @@ struct SolveArgs {
     double *sn_part;           // partial sums of split supernodes: 512 doubles per block and instance
 };
 
-// One level of the supernodal L (U) solve: a wavefront per singleton seq[sbeg, smid) and a
-// workgroup per unit units[ubeg, uend) (int4 {position in seq, slice, slices, first scratch
-// block}); cnt: an arrival counter per seq position and instance, zero on entry and on exit.
-int launch_sn_lsolve(const SolveArgs &a, const int *seq, const int *units, int sbeg, int smid, int ubeg, int uend,
-                     int *cnt, void *stream);
-int launch_sn_usolve(const SolveArgs &a, const int *seq, const int *units, int sbeg, int smid, int ubeg, int uend,
-                     int *cnt, void *stream);
+// One level of the supernodal L (U) solve: sixteen lanes per singleton seq[sbeg, stiny), a
+// wavefront per supernode seq[stiny, smid) and a workgroup per unit units[ubeg, uend) (int4
+// {position in seq, slice, slices, first scratch block}); cnt: an arrival counter per seq
+// position and instance, zero on entry and on exit.
+int launch_sn_lsolve(const SolveArgs &a, const int *seq, const int *units, int sbeg, int stiny, int smid, int ubeg,
+                     int uend, int *cnt, void *stream);
+int launch_sn_usolve(const SolveArgs &a, const int *seq, const int *units, int sbeg, int stiny, int smid, int ubeg,
+                     int uend, int *cnt, void *stream);
 
 // Solve positions [lbeg, lend) of lrec / urec (one level of the solve graph).
 int launch_lsolve_level(const SolveArgs &a, int lbeg, int lend, void *stream);
@@ -335,10 +337,11 @@ int launch_gather_rhs(int n, int nrhs, int batch, const double *b, int64_t ldb, 
 // x[(i*nrhs + r)*ldx + perm[k]] (+)= y[(i*n + k)*YS + r]
 int launch_scatter_sol(int n, int nrhs, int batch, const double *z, const int *perm, double *x,
                        int64_t ldx, int accumulate, const int *skip, void *stream, const double *scale = nullptr);
-// r = b - A x (user space, FP64), per rhs; also writes |r|_inf, |x|_inf, |b|_inf maxima
+// r = b - A x (user space, FP64), per rhs; also writes |r|_inf, |x|_inf, |b|_inf maxima.  Nothing
+// when skip is given and *skip != -1.
 int launch_residual(int n, int nrhs, const int *Acp, const int *Acj, const int *Acsrc,
                     const double *Aval, const double *x, int64_t ldx, const double *b,
-                    int64_t ldb, double *r, int64_t ldr, double *norms, void *stream);
+                    int64_t ldb, double *r, int64_t ldr, double *norms, void *stream, const int *skip = nullptr);
 int launch_anorm(int n, const int *Acp, const int *Acsrc, const double *Aval, double *out,
                  void *stream);
 int launch_copy_f64(const double *src, double *dst, int64_t count, void *stream);

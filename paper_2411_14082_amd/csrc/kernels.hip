@@ -1,34 +1,36 @@
-// Device kernels of the cktlu hot path (gfx950).
+// Device kernels of the cktlu hot path (gfx950), apart from the dense block and the
+// supernodal sweep (dense.hip).
 //
-// Refactorization (fast factorization with pivot check, Section IV-B) runs as
-// right-looking sweeps over dependency levels, one launch per level:
+// Refactorization (fast factorization with pivot check, Section IV-B):
 //   refactor_init_kernel   zeroes every factor column and scatters the matrix
 //                          values into it (one wavefront per column);
-//   refactor_level_kernel  for level l: (a) tests the pivot of every column of
-//                          level l against eps times the largest entry of its L
-//                          part (its values are final: every update came from an
-//                          earlier level); (b) divides the L part of every column
-//                          of level l-1 by its pivot; (c) runs the update tasks of
-//                          level l: a task owns one target column k and applies
-//                          x_k -= L(:,j) * U(j,k) for every source j of level l
-//                          with U(j,k) != 0, in ascending j, so no two wavefronts
-//                          write the same column and results are bit-reproducible.
-// This is the paper's cluster mode (Algorithm 3) with the left-looking column
-// update of the paper turned around: a column's updates are spread over the
-// levels of its sources, so the critical path is the number of levels, not the
-// length of a column's update list.  A failed test records the column (atomic
-// minimum) and raises the instance's interrupt word; later levels of that
-// instance return at once.
+//   refactor_level_kernel  the column sweep (options.sweep_supernodes = -1), one launch
+//                          per level l: (a) tests the pivot of every column of level l
+//                          against eps times the largest entry of its L part (its values
+//                          are final: every update came from an earlier level); (b)
+//                          divides the L part of every column of level l-1 by its pivot;
+//                          (c) runs the update tasks of level l: a task owns one target
+//                          column k and applies x_k -= L(:,j) * U(j,k) for every source j
+//                          of level l with U(j,k) != 0, in ascending j, so no two
+//                          wavefronts write the same column and results are
+//                          bit-reproducible.
+// This is the paper's cluster mode (Algorithm 3) with the left-looking column update of
+// the paper turned around: a column's updates are spread over the levels of its sources,
+// so the critical path is the number of levels, not the length of a column's update list.
+// A failed test records the column (atomic minimum) and the level in the instance's
+// interrupt word; later levels of that instance return at once.  The default sweep works
+// on supernodes (dense.hip) with the same ownership rules.
 //
-// Solves (Section II-C, Algorithm 2): trisolve_level_kernel, row ("pull") form,
-// one launch per level of the solve dependency graph, one wavefront per row;
-// levels with long rows go to trisolve_rowwg_kernel (a workgroup per row), and
-// runs of narrow levels optionally to trisolve_chain_kernel (a workgroup per
-// instance).
+// Solves (Section II-C, Algorithm 2), row ("pull") form: sn_solve_kernel takes one level
+// of supernodes per launch (the default); trisolve_level_kernel / trisolve_rowwg_kernel /
+// trisolve_chain_kernel take one level of rows (the column sweep's schedule, and the rows
+// of the dense block's L entries in sparse columns).
 //
-// All communication between workgroups happens at kernel boundaries, where the
-// runtime makes device memory coherent across the MI355X's eight XCDs; inside
-// the chained solve only the wavefronts of one workgroup (one CU) communicate.
+// All communication between workgroups happens at kernel boundaries, where the runtime
+// makes device memory coherent across the MI355X's eight XCDs, except for the arrival
+// counters of split supernodes: the units of one supernode publish partial sums with a
+// release fence and an atomic increment, and the last to arrive (which never waits for
+// another) reads them after an acquire fence.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -563,17 +565,16 @@ __device__ __forceinline__ double readlane_f64(double v, int l) {
 // ascending c' (unit diagonal); U: x_c = t_c / U(c, c) in descending c, then
 // t_c'' -= U(c'', c) x_c for c'' < c.  The triangle's entries come from the factor columns
 // (sn_cb: offset of the supernode's first row in each column); the results go to y.
-template <typename T, int NR, bool UPPER>
-__device__ __forceinline__ void sn_triangle(const SolveArgs &a, const T *Fx, double *y, int s0, int w,
-                                            double (&t)[NR], int lane) {
-    const int *cb = a.sn_cb + s0;
+// elem(c, r): the diagonal block's entry in column c, row r (both local to the supernode)
+template <typename T, int NR, bool UPPER, typename Elem>
+__device__ __forceinline__ void sn_triangle(Elem elem, double *y, int s0, int w, double (&t)[NR], int lane) {
     if (!UPPER) {
         for (int c0 = 0; c0 < w; c0 += 8) {
             double lv[8];
 #pragma unroll
             for (int u = 0; u < 8; u++) {
                 const int c = c0 + u;
-                lv[u] = (c < w && lane > c && lane < w) ? (double)Fx[cb[c] + lane] : 0.0;
+                lv[u] = (c < w && lane > c && lane < w) ? elem(c, lane) : 0.0;
             }
 #pragma unroll
             for (int u = 0; u < 8; u++) {
@@ -593,8 +594,8 @@ __device__ __forceinline__ void sn_triangle(const SolveArgs &a, const T *Fx, dou
 #pragma unroll
             for (int u = 0; u < 8; u++) {
                 const int c = c0 - u;
-                lv[u] = (c >= 0 && lane < c) ? (double)Fx[cb[c] + lane] : 0.0;
-                dg[u] = c >= 0 ? (double)Fx[cb[c] + c] : 1.0;
+                lv[u] = (c >= 0 && lane < c) ? elem(c, lane) : 0.0;
+                dg[u] = c >= 0 ? elem(c, c) : 1.0;
             }
 #pragma unroll
             for (int u = 0; u < 8; u++) {
@@ -616,10 +617,10 @@ __device__ __forceinline__ void sn_triangle(const SolveArgs &a, const T *Fx, dou
     }
 }
 
-// One level of the supernodal L (U) solve.  Supernodes of at most kSnSmallW rows with a short
-// pull get a wavefront per (supernode, instance): a singleton as in the row kernel; a wider
-// one pulls its rows one after another (wavefront-wide over each row's entries) and solves
-// its triangle.  Every other supernode [s0, s0 + w) is cut into P units (P from its number of
+// One level of the supernodal L (U) solve.  Singletons with a short row get sixteen lanes per
+// (row, instance).  Other supernodes of at most kSnSmallW rows with a short pull get a
+// wavefront per (supernode, instance): a singleton as in the row kernel; a wider one pulls all
+// its rows at once (a group of lanes per row) and solves its triangle.  Every other supernode [s0, s0 + w) is cut into P units (P from its number of
 // entries outside the diagonal block), a workgroup of sixteen wavefronts per (unit, instance):
 // unit p pulls slice p of every row's entries outside the block (L: columns < s0, the row's
 // first entries; U: columns >= s0 + w, its last entries), each row slice cut again into
@@ -633,21 +634,68 @@ constexpr int kSnSolveWG = 1024;                     // threads of a supernodal 
 constexpr int kSnSolveWaves = kSnSolveWG / WAVE;
 template <typename T, int NR, bool UPPER>
 __global__ __launch_bounds__(kSnSolveWG) void sn_solve_kernel(SolveArgs a, const int *seq, const int *units,
-                                                              int sbeg, int smid, int ubeg, int *cnt) {
+                                                              int sbeg, int stiny, int smid, int ubeg, int *cnt) {
     __shared__ double part[64][8];
     __shared__ double red[2][512];
+    __shared__ double tri[64][65];                       // a unit's diagonal block, column-major
     __shared__ int arrived;
     const int lane = threadIdx.x & (WAVE - 1), wv = threadIdx.x / WAVE;
-    const int64_t nsingle = (int64_t)(smid - sbeg) * a.batch;
-    const int64_t nsw = (nsingle + kSnSolveWaves - 1) / kSnSolveWaves;
+    const int64_t ntiny = (int64_t)(stiny - sbeg) * a.batch;
+    const int64_t ntb = (ntiny + kSnSolveWG / 16 - 1) / (kSnSolveWG / 16);
+    const int64_t nsingle = (int64_t)(smid - stiny) * a.batch;
+    const int64_t nsw = ntb + (nsingle + kSnSolveWaves - 1) / kSnSolveWaves;
     const int *rp = UPPER ? a.Urp : a.Lrp;
     const int2 *rjs = reinterpret_cast<const int2 *>(UPPER ? a.Urjs : a.Lrjs);
+    if ((int64_t)blockIdx.x < ntb) {
+        // a short singleton row on sixteen lanes: two entries per lane in flight, the sums
+        // reduced over the sixteen lanes
+        const int64_t gid = (int64_t)blockIdx.x * (kSnSolveWG / 16) + threadIdx.x / 16;
+        if (gid >= ntiny) return;
+        const int inst = (int)(gid % a.batch);
+        if (a.skip && a.skip[inst] != -1) return;
+        const int i = a.sn_rec[4 * seq[sbeg + (int)(gid / a.batch)]];
+        const int l16 = lane & 15;
+        const T *Fx = reinterpret_cast<const T *>(a.Fx) + (size_t)inst * a.nnzF;
+        double *y = a.y + (size_t)inst * a.n * YS;
+        double acc[NR];
+#pragma unroll
+        for (int r = 0; r < NR; r++) acc[r] = 0.0;
+        const int beg = rp[i], end = rp[i + 1];
+        for (int q0 = beg; q0 < end; q0 += 32) {
+            int2 e[2];
+#pragma unroll
+            for (int u = 0; u < 2; u++) e[u] = q0 + 16 * u + l16 < end ? rjs[q0 + 16 * u + l16] : make_int2(-1, 0);
+            double l[2];
+#pragma unroll
+            for (int u = 0; u < 2; u++) l[u] = e[u].x >= 0 ? (double)Fx[e[u].y] : 0.0;
+#pragma unroll
+            for (int u = 0; u < 2; u++)
+                if (e[u].x >= 0) {
+#pragma unroll
+                    for (int r = 0; r < NR; r++) acc[r] += l[u] * y[(size_t)e[u].x * YS + r];
+                }
+        }
+#pragma unroll
+        for (int r = 0; r < NR; r++)
+#pragma unroll
+            for (int off = 8; off > 0; off >>= 1) acc[r] += __shfl_xor(acc[r], off, 16);
+        double mine = acc[0];
+#pragma unroll
+        for (int r = 1; r < NR; r++)
+            if (l16 == r) mine = acc[r];
+        if (l16 < NR) {
+            double v = y[(size_t)i * YS + l16] - mine;
+            if (UPPER) v = v / (double)Fx[a.sn_cb[i]];
+            y[(size_t)i * YS + l16] = v;
+        }
+        return;
+    }
     if ((int64_t)blockIdx.x < nsw) {
-        const int64_t wid = (int64_t)blockIdx.x * kSnSolveWaves + wv;
+        const int64_t wid = ((int64_t)blockIdx.x - ntb) * kSnSolveWaves + wv;
         if (wid >= nsingle) return;
         const int inst = (int)(wid % a.batch);
         if (a.skip && a.skip[inst] != -1) return;
-        const int4 rec = reinterpret_cast<const int4 *>(a.sn_rec)[seq[sbeg + (int)(wid / a.batch)]];
+        const int4 rec = reinterpret_cast<const int4 *>(a.sn_rec)[seq[stiny + (int)(wid / a.batch)]];
         const int s0 = rec.x, w = rec.y;
         if (w == 1) {
             solve_row_rec<T, NR, UPPER>(a, inst, make_int4(s0, rp[s0], rp[s0 + 1], a.sn_cb[s0]), lane);
@@ -655,20 +703,44 @@ __global__ __launch_bounds__(kSnSolveWG) void sn_solve_kernel(SolveArgs a, const
         }
         const T *Fx = reinterpret_cast<const T *>(a.Fx) + (size_t)inst * a.nnzF;
         double *y = a.y + (size_t)inst * a.n * YS;
-        double t[NR];
+        // the rows pull at the same time: G = 64 / 2^ceil(log2 w) lanes per row (at least 4),
+        // two entries per lane in flight, the sums reduced over the G lanes
+        const int lg = 32 - __builtin_clz((unsigned)(w - 1));   // w <= 2^lg
+        const int G = WAVE >> lg, c = lane / G, lq = lane % G;
+        double acc[NR];
 #pragma unroll
-        for (int r = 0; r < NR; r++) t[r] = 0.0;
-        for (int c = 0; c < w; c++) {
+        for (int r = 0; r < NR; r++) acc[r] = 0.0;
+        if (c < w) {
             const int i = s0 + c;
-            double acc[NR];
-            row_pull<T, NR>(rjs, Fx, y, UPPER ? rp[i] + (w - 1 - c) : rp[i], UPPER ? rp[i + 1] : rp[i + 1] - c, lane,
-                            acc);
-            if (lane == c) {
+            const int beg = UPPER ? rp[i] + (w - 1 - c) : rp[i], end = UPPER ? rp[i + 1] : rp[i + 1] - c;
+            for (int q0 = beg; q0 < end; q0 += 2 * G) {
+                int2 e[2];
 #pragma unroll
-                for (int r = 0; r < NR; r++) t[r] = y[(size_t)i * YS + r] - acc[r];
+                for (int u = 0; u < 2; u++) e[u] = q0 + u * G + lq < end ? rjs[q0 + u * G + lq] : make_int2(-1, 0);
+                double l[2];
+#pragma unroll
+                for (int u = 0; u < 2; u++) l[u] = e[u].x >= 0 ? (double)Fx[e[u].y] : 0.0;
+#pragma unroll
+                for (int u = 0; u < 2; u++)
+                    if (e[u].x >= 0) {
+#pragma unroll
+                        for (int r = 0; r < NR; r++) acc[r] += l[u] * y[(size_t)e[u].x * YS + r];
+                    }
             }
         }
-        sn_triangle<T, NR, UPPER>(a, Fx, y, s0, w, t, lane);
+        for (int off = G >> 1; off > 0; off >>= 1) {
+#pragma unroll
+            for (int r = 0; r < NR; r++) acc[r] += __shfl_xor(acc[r], off);
+        }
+        // lane c takes row c's sums from the first lane of its group
+        double t[NR];
+#pragma unroll
+        for (int r = 0; r < NR; r++) {
+            const double sr = __shfl(acc[r], (lane < w ? lane : 0) * G);
+            t[r] = lane < w ? y[(size_t)(s0 + lane) * YS + r] - sr : 0.0;
+        }
+        const int *cb = a.sn_cb + s0;
+        sn_triangle<T, NR, UPPER>([=](int cc, int r) { return (double)Fx[cb[cc] + r]; }, y, s0, w, t, lane);
         return;
     }
     const int64_t pu = (int64_t)blockIdx.x - nsw;
@@ -735,25 +807,32 @@ __global__ __launch_bounds__(kSnSolveWG) void sn_solve_kernel(SolveArgs a, const
             }
             red[h][v] = acc;
         }
-        __syncthreads();
-        if (wv != 0) return;
-        if (lane < w) {
-#pragma unroll
-            for (int r = 0; r < NR; r++) sum[r] = red[0][lane * 8 + r] + red[1][lane * 8 + r];
+    }
+    // the diagonal block into LDS by every thread (one round of loads), read by the triangle
+    {
+        const int *cb = a.sn_cb + s0;
+        for (int e = threadIdx.x; e < w * w; e += kSnSolveWG) {
+            const int cc = e / w, r = e - cc * w;
+            tri[cc][r] = (double)Fx[cb[cc] + r];
         }
-    } else if (wv != 0) {
-        return;
+    }
+    __syncthreads();
+    if (wv != 0) return;
+    if (un.z > 1 && lane < w) {
+#pragma unroll
+        for (int r = 0; r < NR; r++) sum[r] = red[0][lane * 8 + r] + red[1][lane * 8 + r];
     }
     double t[NR];
 #pragma unroll
     for (int r = 0; r < NR; r++) t[r] = lane < w ? y[(size_t)(s0 + lane) * YS + r] - sum[r] : 0.0;
-    sn_triangle<T, NR, UPPER>(a, Fx, y, s0, w, t, lane);
+    sn_triangle<T, NR, UPPER>([&](int cc, int r) { return tri[cc][r]; }, y, s0, w, t, lane);
 }
 
 template <bool UPPER>
-static int launch_sn_solve_impl(const SolveArgs &a, const int *seq, const int *units, int sbeg, int smid, int ubeg,
-                                int uend, int *cnt, void *stream) {
-    const int64_t nsw = ((int64_t)(smid - sbeg) * a.batch + kSnSolveWaves - 1) / kSnSolveWaves;
+static int launch_sn_solve_impl(const SolveArgs &a, const int *seq, const int *units, int sbeg, int stiny, int smid,
+                                int ubeg, int uend, int *cnt, void *stream) {
+    const int64_t ntb = ((int64_t)(stiny - sbeg) * a.batch + kSnSolveWG / 16 - 1) / (kSnSolveWG / 16);
+    const int64_t nsw = ntb + ((int64_t)(smid - stiny) * a.batch + kSnSolveWaves - 1) / kSnSolveWaves;
     const int64_t units_n = nsw + (int64_t)(uend - ubeg) * a.batch;
     if (units_n == 0) return 0;
     const dim3 grid((unsigned)units_n);
@@ -762,10 +841,10 @@ static int launch_sn_solve_impl(const SolveArgs &a, const int *seq, const int *u
     case NRV:                                                                                           \
         if (a.fp32)                                                                                     \
             hipLaunchKernelGGL((sn_solve_kernel<float, NRV, UPPER>), grid, dim3(kSnSolveWG), 0, st, a, seq, units, \
-                               sbeg, smid, ubeg, cnt);                                                  \
+                               sbeg, stiny, smid, ubeg, cnt);                                           \
         else                                                                                            \
             hipLaunchKernelGGL((sn_solve_kernel<double, NRV, UPPER>), grid, dim3(kSnSolveWG), 0, st, a, seq, units, \
-                               sbeg, smid, ubeg, cnt);                                                  \
+                               sbeg, stiny, smid, ubeg, cnt);                                           \
         break;
     switch (a.nrhs) {
         CKTLU_SNS_CASE(1)
@@ -778,13 +857,13 @@ static int launch_sn_solve_impl(const SolveArgs &a, const int *seq, const int *u
     return (int)hipGetLastError();
 }
 
-int launch_sn_lsolve(const SolveArgs &a, const int *seq, const int *units, int sbeg, int smid, int ubeg, int uend,
-                     int *cnt, void *stream) {
-    return launch_sn_solve_impl<false>(a, seq, units, sbeg, smid, ubeg, uend, cnt, stream);
+int launch_sn_lsolve(const SolveArgs &a, const int *seq, const int *units, int sbeg, int stiny, int smid, int ubeg,
+                     int uend, int *cnt, void *stream) {
+    return launch_sn_solve_impl<false>(a, seq, units, sbeg, stiny, smid, ubeg, uend, cnt, stream);
 }
-int launch_sn_usolve(const SolveArgs &a, const int *seq, const int *units, int sbeg, int smid, int ubeg, int uend,
-                     int *cnt, void *stream) {
-    return launch_sn_solve_impl<true>(a, seq, units, sbeg, smid, ubeg, uend, cnt, stream);
+int launch_sn_usolve(const SolveArgs &a, const int *seq, const int *units, int sbeg, int stiny, int smid, int ubeg,
+                     int uend, int *cnt, void *stream) {
+    return launch_sn_solve_impl<true>(a, seq, units, sbeg, stiny, smid, ubeg, uend, cnt, stream);
 }
 
 // A run of narrow levels [l0, l1): one workgroup per instance takes the rows of a
@@ -1018,7 +1097,8 @@ __device__ __forceinline__ void residual_rows(int n, int nr, const int *Acp, con
 __global__ __launch_bounds__(256) void residual_kernel(int n, int nrhs, const int *Acp, const int *Acj,
                                                        const int *Acsrc, const double *Aval, const double *x,
                                                        int64_t ldx, const double *b, int64_t ldb, double *r,
-                                                       int64_t ldr, double *norms) {
+                                                       int64_t ldr, double *norms, const int *skip) {
+    if (skip && *skip != -1) return;
     const int64_t i0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x, stride = (int64_t)gridDim.x * blockDim.x;
     for (int r0 = 0; r0 < nrhs; r0 += 8)
         residual_rows(n, min(8, nrhs - r0), Acp, Acj, Acsrc, Aval, x + r0 * ldx, ldx, b + r0 * ldb, ldb,
@@ -1027,10 +1107,10 @@ __global__ __launch_bounds__(256) void residual_kernel(int n, int nrhs, const in
 
 int launch_residual(int n, int nrhs, const int *Acp, const int *Acj, const int *Acsrc,
                     const double *Aval, const double *x, int64_t ldx, const double *b, int64_t ldb,
-                    double *r, int64_t ldr, double *norms, void *stream) {
+                    double *r, int64_t ldr, double *norms, void *stream, const int *skip) {
     const int grid = std::min(grid_for(n, 256), 1024);   // a few rows per thread, few atomics
     hipLaunchKernelGGL(residual_kernel, dim3(grid), dim3(256), 0, (hipStream_t)stream, n, nrhs,
-                       Acp, Acj, Acsrc, Aval, x, ldx, b, ldb, r, ldr, norms);
+                       Acp, Acj, Acsrc, Aval, x, ldx, b, ldb, r, ldr, norms, skip);
     return (int)hipGetLastError();
 }
 

@@ -1,8 +1,10 @@
 // Schedule construction for a fixed factor pattern (Section II-B, Section
 // IV-B, Section V-C): dependency levels of the columns (the "guessed"
 // elimination graph), the column sequence ordered by level, the scatter map
-// of the matrix values into the factor storage, and the row-wise structures
-// of L and U used by the triangular solves.
+// of the matrix values into the factor storage, the row-wise structures
+// of L and U used by the triangular solves, the dense trailing block, and (by
+// default) the supernodes with their sweep levels, panel units, update tasks,
+// slot maps, Schur items and solve levels.
 #include <algorithm>
 #include <climits>
 #include <thread>
@@ -41,19 +43,19 @@ static int choose_tail(const Factor &f, const cktlu_options &opt) {
 // update tasks of at least this many multiply-adds get a workgroup (four wavefronts)
 constexpr double kHeavyTask = 16384.0;
 // supernodal solves: a singleton whose row pulls at least kSolveLongRow entries gets a
-// workgroup; a supernode's pull is split into slices of about kSolvePullChunk entries (at most
-// kSolveMaxSplit slices), one workgroup each
+// workgroup; a supernode's pull is split into slices of about kSolvePullChunk entries (the
+// default of options.solve_split_entries; at most kSolveMaxSplit slices), one workgroup each
 constexpr int64_t kSolveLongRow = 1024;
+constexpr int64_t kSolveTinyRow = 32;      // singletons with this many entries at most: 16 lanes
 constexpr int64_t kSolvePullChunk = 8192;
 constexpr int64_t kSolveMaxSplit = 1024;
-// rows of R per unit of a wide panel (two passes of its eight wavefronts) and of a small one
-// (two passes of its wavefront)
+// rows of R per unit of a wide panel (two passes of its eight wavefronts; the default of
+// options.sweep_panel_rows), half of it for a small one (two passes of its wavefront)
 constexpr int kPanelRows = 256;
-constexpr int kSmallPanelRows = 128;
 
 // Supernodal sweep schedule of the sparse columns [0, T) (see Schedule).  Needs the device
 // layout (Dp, Dlen, Fi_dev) and the row lists of L (Lrp, Lrj).
-static void build_supernodal(const Factor &f, Schedule &s, int T, int wmax) {
+static void build_supernodal(const Factor &f, Schedule &s, int T, int wmax, int panel_rows, int64_t pull_chunk) {
     const int n = f.n;
     auto lbeg = [&](int j) { return f.Fp[j] + f.nU[j]; };
     // ---- supernodes: j joins the supernode of j-1 when L(:,j-1) = {j} u L(:,j) and U(s0..j-1, j)
@@ -140,7 +142,7 @@ static void build_supernodal(const Factor &f, Schedule &s, int T, int wmax) {
         else s.sn_seq[fill3[lev[S]]++] = S;
     }
     // panels as units, each taking a slice of R's rows: small panels (a wavefront each)
-    // P = ceil(m / kSmallPanelRows), wide ones (a workgroup each) P = ceil(m / kPanelRows).
+    // P = ceil(m / (panel_rows / 2)), wide ones (a workgroup each) P = ceil(m / panel_rows).
     // Scratch blocks are numbered per launch
     s.sn_punit.clear();
     s.sn_sunit.clear();
@@ -158,8 +160,8 @@ static void build_supernodal(const Factor &f, Schedule &s, int T, int wmax) {
         s.sn_pnscr = std::max(s.sn_pnscr, blocks);
     };
     for (int l = 0; l < nl; l++) {
-        units(s.sn_lvl_single[l], s.sn_lvl_small[l], kSmallPanelRows, s.sn_sunit);
-        units(s.sn_lvl_small[l], s.sn_lvl[l + 1], kPanelRows, s.sn_punit);
+        units(s.sn_lvl_single[l], s.sn_lvl_small[l], std::max(1, panel_rows / 2), s.sn_sunit);
+        units(s.sn_lvl_small[l], s.sn_lvl[l + 1], panel_rows, s.sn_punit);
         s.sn_sulvl[l + 1] = (int)(s.sn_sunit.size() / 4);
         s.sn_pulvl[l + 1] = (int)(s.sn_punit.size() / 4);
     }
@@ -317,8 +319,9 @@ static void build_supernodal(const Factor &f, Schedule &s, int T, int wmax) {
     // ---- solve levels over the supernodes.  L: the rows of S reach column j < s0 through
     // L(i, j); U: the rows of S reach column k >= s1 through U(i, k) (k < T: dense columns are
     // solved before the sparse U rows)
-    auto solve_levels = [&](bool upper, int &nlev, std::vector<int> &lvl, std::vector<int> &single,
-                            std::vector<int> &seq, std::vector<int> &unit, std::vector<int> &ulvl, int &nscr) {
+    auto solve_levels = [&](bool upper, int &nlev, std::vector<int> &lvl, std::vector<int> &tiny,
+                            std::vector<int> &single, std::vector<int> &seq, std::vector<int> &unit,
+                            std::vector<int> &ulvl, int &nscr) {
         std::vector<int> lv(nsn, 0);
         std::vector<int64_t> pull(nsn, 0);            // entries outside the diagonal block
         nlev = nsn ? 1 : 0;
@@ -339,31 +342,36 @@ static void build_supernodal(const Factor &f, Schedule &s, int T, int wmax) {
             lv[S] = v;
             nlev = std::max(nlev, v + 1);
         }
-        // a wavefront per supernode of at most kSnSmallW rows with a short pull; a workgroup per
-        // unit of every other supernode
-        auto wave_row = [&](int S) {
-            return s0v[S + 1] - s0v[S] <= cktlu_dev::kSnSmallW && pull[S] < kSolveLongRow;
+        // sixteen lanes per singleton with at most kSolveTinyRow entries; a wavefront per other
+        // supernode of at most kSnSmallW rows with a short pull; a workgroup per unit of every
+        // other supernode
+        auto kind = [&](int S) {
+            const int w = s0v[S + 1] - s0v[S];
+            if (w == 1 && pull[S] <= kSolveTinyRow) return 0;
+            return w <= cktlu_dev::kSnSmallW && pull[S] < kSolveLongRow ? 1 : 2;
         };
-        std::vector<int> c(nlev + 1, 0), c1(nlev, 0);
+        std::vector<int> c(nlev + 1, 0), c0(nlev, 0), c1(nlev, 0);
         for (int S = 0; S < nsn; S++) {
             c[lv[S] + 1]++;
-            if (wave_row(S)) c1[lv[S]]++;
+            const int k = kind(S);
+            if (k == 0) c0[lv[S]]++;
+            else if (k == 1) c1[lv[S]]++;
         }
         for (int l2 = 0; l2 < nlev; l2++) c[l2 + 1] += c[l2];
         lvl.assign(c.begin(), c.end());
+        tiny.resize(nlev);
         single.resize(nlev);
-        std::vector<int> f1(nlev), f2(nlev);
+        std::vector<int> f[3] = {std::vector<int>(nlev), std::vector<int>(nlev), std::vector<int>(nlev)};
         for (int l2 = 0; l2 < nlev; l2++) {
-            single[l2] = c[l2] + c1[l2];
-            f1[l2] = c[l2];
-            f2[l2] = c[l2] + c1[l2];
+            tiny[l2] = c[l2] + c0[l2];
+            single[l2] = c[l2] + c0[l2] + c1[l2];
+            f[0][l2] = c[l2];
+            f[1][l2] = tiny[l2];
+            f[2][l2] = single[l2];
         }
         seq.resize(nsn);
-        for (int S = 0; S < nsn; S++) {
-            if (wave_row(S)) seq[f1[lv[S]]++] = S;
-            else seq[f2[lv[S]]++] = S;
-        }
-        // units: a supernode whose pull exceeds kSolvePullChunk entries is split into P units that
+        for (int S = 0; S < nsn; S++) seq[f[kind(S)][lv[S]]++] = S;
+        // units: a supernode whose pull exceeds pull_chunk entries is split into P units that
         // pull a 1/P slice of every row; their partial sums meet in scratch blocks (P per
         // supernode, numbered within the level) and the last unit to finish solves the triangle
         unit.clear();
@@ -373,7 +381,7 @@ static void build_supernodal(const Factor &f, Schedule &s, int T, int wmax) {
             int blocks = 0;
             for (int q = single[l2]; q < lvl[l2 + 1]; q++) {
                 const int S = seq[q];
-                const int P = (int)std::min<int64_t>(kSolveMaxSplit, std::max<int64_t>(1, (pull[S] + kSolvePullChunk - 1) / kSolvePullChunk));
+                const int P = (int)std::min<int64_t>(kSolveMaxSplit, std::max<int64_t>(1, (pull[S] + pull_chunk - 1) / pull_chunk));
                 for (int p = 0; p < P; p++) unit.insert(unit.end(), {q, p, P, P > 1 ? blocks : -1});
                 if (P > 1) blocks += P;
             }
@@ -381,8 +389,10 @@ static void build_supernodal(const Factor &f, Schedule &s, int T, int wmax) {
             nscr = std::max(nscr, blocks);
         }
     };
-    solve_levels(false, s.snl_levels, s.snl_lvl, s.snl_single, s.snl_seq, s.snl_unit, s.snl_ulvl, s.snl_nscr);
-    solve_levels(true, s.snu_levels, s.snu_lvl, s.snu_single, s.snu_seq, s.snu_unit, s.snu_ulvl, s.snu_nscr);
+    solve_levels(false, s.snl_levels, s.snl_lvl, s.snl_tiny, s.snl_single, s.snl_seq, s.snl_unit, s.snl_ulvl,
+                 s.snl_nscr);
+    solve_levels(true, s.snu_levels, s.snu_lvl, s.snu_tiny, s.snu_single, s.snu_seq, s.snu_unit, s.snu_ulvl,
+                 s.snu_nscr);
     // ---- slot map: where each row of R lands in the target column (struct R is inside it)
     s.sn_map.resize((size_t)moff);
     auto fill = [&](int64_t i0, int64_t i1) {
@@ -765,7 +775,10 @@ void build_schedule(const Analysis &an, const Factor &f, const cktlu_options &op
             }
         }
     }
-    if (snodal) build_supernodal(f, s, T, opt.sweep_supernodes > 0 ? std::min(opt.sweep_supernodes, 64) : 64);
+    if (snodal)
+        build_supernodal(f, s, T, opt.sweep_supernodes > 0 ? std::min(opt.sweep_supernodes, 64) : 64,
+                         opt.sweep_panel_rows > 0 ? opt.sweep_panel_rows : kPanelRows,
+                         opt.solve_split_entries > 0 ? opt.solve_split_entries : kSolvePullChunk);
     // ---- solve levels of the sparse rows [0, T): row i of L waits for every j with
     // L(i,j) != 0, row i of U for every j > i with U(i,j) != 0 (rows >= T of U are
     // solved densely before any sparse U row).  The L sequence ends with one more

@@ -87,6 +87,12 @@ def test_autotune_keeps_fastest_schedule_and_results(ck, oracle_mod, batch):
     assert len(r["dense_tail"]) >= 3 and len(set(r["dense_tail"])) == len(r["dense_tail"])
     assert r["ms_per_step"][r["best"]] == min(r["ms_per_step"])
     assert s.stats()["dense_tail"] == r["best_dense_tail"]
+    # second stage: every knob left at its default was tried, and a kept value is one that was tried
+    tried = {(k, v) for k, v, _ in r["knob_trials"]}
+    for name in ("sweep_supernodes", "sweep_panel_rows", "solve_split_entries"):
+        assert any(k == name for k, _ in tried), name
+        kept = r["kept"][name]
+        assert kept == 0 or (name, kept) in tried, (name, kept)
     status = torch.zeros(batch, dtype=torch.int32, device="cuda:0")
     s.refactorize_batched(batch, dev(V), status)
     B = np.repeat(c.rhs[:1][None], batch, axis=0)

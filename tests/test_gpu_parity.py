@@ -739,6 +739,68 @@ def test_supernodal_sweep_vs_oracle(ck, oracle_mod, name, make, width, tail):
     assert oracle_mod.backward_error(c.colptr, c.rowind, vh, x.cpu().numpy(), c.rhs[0]) <= 1e-10
 
 
+@pytest.mark.parametrize("tail", [-1, 100])
+@pytest.mark.parametrize("name,make", SN_CASES, ids=[c[0] for c in SN_CASES])
+def test_supernodal_split_units_vs_oracle(ck, oracle_mod, name, make, tail):
+    """Panels split into units of 16 rows (8 for panels of at most 16 columns) and supernodal
+    solves split into units of 64 entries, so that the arrival counters and the slice
+    combines run on small circuits: the factors equal those of the unsplit schedule bit for
+    bit (splitting rows of R changes no operation), pattern and pivots equal the oracle's,
+    the solutions reach eta <= 1e-12 (FP64; 1e-10 refined from FP32 factors, one and eight
+    right-hand sides, a batch of three instances) and agree with the oracle's within the
+    condition-scaled bound; the test is repeated to catch counters not reset."""
+    c = make()
+    say("split units", name, "tail", tail)
+    vh = mnagen.restamp(c, 47, 0, 1)
+    ref = ck.SparseLU(c.n, c.colptr, c.rowind, eps=EPS, dense_tail=tail)
+    ref.factorize(dev(c.values))
+    a0 = ref.analysis()
+    ref.refactorize(dev(vh))
+    fref = ref.factors()
+    lu = oracle_refactor(oracle_mod, c, vh, a0, EPS, a0["pivrow"])
+    kap = kappa_est(oracle_mod, lu, c, vh, a0)
+    for prec in (ck.CKTLU_FP64, ck.CKTLU_FP32_IR):
+        s = ck.SparseLU(c.n, c.colptr, c.rowind, eps=EPS, dense_tail=tail, precision=prec, ir_tol=1e-10,
+                        sweep_panel_rows=16, solve_split_entries=64)
+        s.factorize(dev(c.values))
+        for rep in range(2):
+            rc, info = s.refactorize(dev(vh))
+            assert np.array_equal(s.analysis()["pivrow"], lu.pivrow)
+            if prec == ck.CKTLU_FP64:
+                f = s.factors()
+                for key in ("Lp", "Li", "Lx", "Up", "Ui", "Ux"):
+                    assert np.array_equal(f[key], fref[key]), key
+            for nrhs in (1, 8):
+                B = np.stack([c.rhs[r % len(c.rhs)] * (1.0 + r) for r in range(nrhs)])
+                X = torch.zeros((nrhs, c.n), dtype=torch.float64, device="cuda:0")
+                s.solve(dev(B), X, nrhs=nrhs)
+                torch.cuda.synchronize()
+                Xh = X.cpu().numpy()
+                tol = 1e-12 if prec == ck.CKTLU_FP64 else 1e-10
+                for r in range(nrhs):
+                    eta = oracle_mod.backward_error(c.colptr, c.rowind, vh, Xh[r], B[r])
+                    assert eta <= tol, (nrhs, r, eta)
+                    xo = oracle_mod.solve(lu, a0["rowperm_pre"], a0["colperm"], B[r])
+                    eta_o = oracle_mod.backward_error(c.colptr, c.rowind, vh, xo, B[r])
+                    check_solution(Xh[r], xo, kap, eta, eta_o, "split rhs %d/%d" % (r, nrhs))
+        if rc == 0:
+            batch = 3
+            V = np.stack([vh, mnagen.restamp(c, 47, 0, 2), vh])
+            stt = torch.zeros(batch, dtype=torch.int32, device="cuda:0")
+            s.refactorize_batched(batch, dev(V), stt)
+            B = np.stack([c.rhs[0]] * batch)
+            X = torch.zeros((batch, c.n), dtype=torch.float64, device="cuda:0")
+            eta_d = torch.zeros(batch, dtype=torch.float64, device="cuda:0")
+            s.solve_batched(batch, 1, dev(B), X, stt, eta_d)
+            torch.cuda.synchronize()
+            st_h = stt.cpu().numpy()
+            for i in range(batch):
+                if st_h[i] == -1:
+                    vi = V[i]
+                    eta = oracle_mod.backward_error(c.colptr, c.rowind, vi, X[i].cpu().numpy(), B[i])
+                    assert eta <= (1e-12 if prec == ck.CKTLU_FP64 else 1e-10), (i, eta)
+
+
 def test_supernodal_panel_failure_fallback(ck, oracle_mod):
     """The pivot test forced to fail at a column inside a wide supernode (a panel): the
     fallback's result equals the oracle's re-factorization, and the unfinished set holds
