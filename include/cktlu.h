@@ -143,10 +143,12 @@ typedef struct {
     int64_t n_fp64_fallback_solves;
     double bytes_refactor, bytes_solve;  /* algorithmic HBM bytes per refactorization / per RHS solve */
     double macs_sweep;                /* multiply-adds of the sparse sweep's update tasks */
-    double bytes_sweep;               /* its traffic model: 28 per MAC (L value + row index gathered,
-                                         target read and written) + 24 per L entry of a sparse column
-                                         (pivot test read, division read and write): what the update
-                                         moves when nothing is reused from caches */
+    double bytes_sweep;               /* its traffic model, what the sweep moves when nothing is reused
+                                         from caches: supernodal, 8 per panel or update multiply-add (L
+                                         value) + 20 per row of R updated (slot, target read and written);
+                                         column sweep, 28 per MAC (L value + row index gathered, target read
+                                         and written); both + 24 per L entry of a sparse column (pivot test
+                                         read, division read and write) */
     double flops_dense;               /* FLOPs of the dense trailing block's LU (2/3 D^3 + lower order) */
     double macs_schur;                /* multiply-adds of the dense block's update by the sparse columns */
     int64_t sweep_launches;           /* kernel launches of one sparse sweep */
@@ -171,6 +173,8 @@ typedef struct {
     int64_t sweep_supernodes;         /* supernodes of the supernodal sweep (0: the column sweep runs) */
     int64_t sweep_levels;             /* dependency levels of the sweep (supernodal or right-looking) */
     int64_t fill_ndc;                 /* CKTLU_ORDER_AUTO: the same count under ND + constrained AMD */
+    int64_t n_fp32_check_retries;     /* FP32_IR refactorizations whose pivot test failed on the FP32 values
+                                         and passed in FP64 (the context then keeps FP64 factors) */
 } cktlu_stats;
 
 /* Device time of the phases, accumulated over the calls made with options.timing = 1
@@ -277,7 +281,8 @@ int cktlu_refactorize_nocheck(cktlu_ctx *ctx, const double *values_dev);
  * decide convergence on the device, so the host waits once for them.  After such a fallback the context keeps FP64 factors for
  * its refactorizations and solves (info->used_fp64 = 1) until the next
  * cktlu_factorize: a circuit too ill-conditioned for FP32 factors stays so
- * while its values move by NR steps.  info may be NULL.  Errors: E_STATE,
+ * while its values move by NR steps.  The same holds after a refactorization
+ * whose pivot test failed on the FP32 values but passed in FP64.  info may be NULL.  Errors: E_STATE,
  * E_ARG, E_HIP.
  */
 int cktlu_solve(cktlu_ctx *ctx, int32_t nrhs, const double *b_dev, int32_t ldb,

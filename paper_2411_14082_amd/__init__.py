@@ -91,7 +91,8 @@ class cktlu_stats(ctypes.Structure):
                 ("schur_scratch_cols", ctypes.c_int64), ("entries_sweep", ctypes.c_double),
                 ("entries_dense", ctypes.c_double), ("macs_dense", ctypes.c_double),
                 ("alg_bytes_refactor_sweep", ctypes.c_double), ("sweep_supernodes", ctypes.c_int64),
-                ("sweep_levels", ctypes.c_int64), ("fill_ndc", ctypes.c_int64)]
+                ("sweep_levels", ctypes.c_int64), ("fill_ndc", ctypes.c_int64),
+                ("n_fp32_check_retries", ctypes.c_int64)]
 
     def as_dict(self):
         return {f: getattr(self, f) for f, _ in self._fields_}

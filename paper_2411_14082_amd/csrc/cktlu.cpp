@@ -811,11 +811,15 @@ int refactor_single(cktlu_ctx *c, const double *values_dev, cktlu_refactor_info 
     if (!h[1]) return CKTLU_OK;
     int first = h[2];
     if (fp32) {
-        // pivot decisions come from FP64: retry the check with FP64 arithmetic
+        // pivot decisions come from FP64: retry the check with FP64 arithmetic.  When it passes,
+        // the FP32 values sit too close to the threshold for this circuit: like a stalled
+        // refinement, the context keeps FP64 factors until its next full factorization (each
+        // later step would otherwise pay both refactorizations)
         if ((rc = run_refactor(c, 1, values_dev, false, true, force))) return rc;
         if ((rc = read_status(c, h))) return rc;
         if (!h[1]) {
-            LCHK(launch_f64_to_f32((const double *)d.Fx64.p, (float *)d.Fx32.p, nnzF(c), st));
+            c->stats.n_fp32_check_retries++;
+            c->fp64_sticky = true;
             d.S_prec = -1;
             return CKTLU_OK;
         }

@@ -1417,14 +1417,15 @@ __device__ __forceinline__ void sn_rows_update(const T *Fx, T *xk, const int *cb
 // rows (rows < T only for a dense-block target: its rows >= T are the Schur update's), their
 // slots in k from sn_map.  Rows of one supernode are distinct, so the stores of one pass
 // never feed its own loads.  Tasks [tbeg, theavy) are heavy: a workgroup per (task,
-// instance), wavefront 0 solving the suffix and passing U(S, k) through LDS, the four
-// wavefronts then splitting R's rows, a barrier between supernodes; tasks [theavy, tend) get
-// a wavefront per (task, instance).  Either way every row of k receives the same operations
-// in the same order.
+// instance), the suffixes of up to kHeavyChunk items solved first (a wavefront each) and
+// passed through LDS, the four wavefronts then splitting R's rows item by item, a barrier
+// between items; tasks [theavy, ttiny) get a wavefront per (task, instance), [ttiny, tend)
+// sixteen lanes.  Either way every row of k receives the same operations in the same order.
+constexpr int kHeavyChunk = 16;                      // items of a heavy task whose suffixes are solved together
 template <typename T>
 __global__ __launch_bounds__(256) void sn_update_kernel(RefactorArgs a, int lev, int tbeg, int theavy, int ttiny,
                                                         int tend) {
-    __shared__ T us[WAVE];
+    __shared__ T us[kHeavyChunk][WAVE];
     const int lane = threadIdx.x & (WAVE - 1), wv = threadIdx.x / WAVE;
     // grid sizes fit 32 bits (one dimension of a launch)
     const unsigned nheavy = (unsigned)(theavy - tbeg) * (unsigned)a.batch;
@@ -1482,30 +1483,49 @@ __global__ __launch_bounds__(256) void sn_update_kernel(RefactorArgs a, int lev,
     T *Fx = reinterpret_cast<T *>(a.Fx) + (size_t)inst * a.nnzF;
     const int4 tk = reinterpret_cast<const int4 *>(a.sn_task)[t];
     T *xk = Fx + tk.y;
-    for (int it = tk.z; it < tk.w; it++) {
-        const int4 item = reinterpret_cast<const int4 *>(a.sn_item)[it];
-        const int4 rec = reinterpret_cast<const int4 *>(a.sn_rec)[item.x];
-        const int w = rec.y, len = item.z, off = w - len, mcnt = item.w;
-        const int *cb = a.sn_cb + rec.x + off;           // the suffix's columns
-        const int *mp = a.sn_map + a.sn_moff[it];
-        if (!heavy) {
+    if (!heavy) {
+        for (int it = tk.z; it < tk.w; it++) {
+            const int4 item = reinterpret_cast<const int4 *>(a.sn_item)[it];
+            const int4 rec = reinterpret_cast<const int4 *>(a.sn_rec)[item.x];
+            const int w = rec.y, len = item.z, off = w - len, mcnt = item.w;
+            const int *cb = a.sn_cb + rec.x + off;       // the suffix's columns
+            const int *mp = a.sn_map + a.sn_moff[it];
             const T xv = sn_suffix_solve<T>(Fx, xk, cb, item.y, off, len, lane);
             if (lane < len) xk[item.y + lane] = xv;
             for (int r0 = 0; r0 < mcnt; r0 += 2 * WAVE)
                 sn_rows_update<T>(Fx, xk, cb, mp, w, len, mcnt, r0, lane, [&](int c) { return readlane(xv, c); });
             __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "workgroup");
             __builtin_amdgcn_wave_barrier();
-        } else {
-            if (wv == 0) {
-                const T xv = sn_suffix_solve<T>(Fx, xk, cb, item.y, off, len, lane);
-                if (lane < len) {
-                    xk[item.y + lane] = xv;
-                    us[lane] = xv;
-                }
+        }
+        return;
+    }
+    // heavy task: items in chunks of kHeavyChunk.  The chunk's suffix solves go first, a
+    // wavefront each: they are independent of every item's row update (the supernodes of one
+    // level hold no rows of each other's R, so no update reaches another item's suffix rows).
+    // Then the chunk's row updates in item order, R's rows split over the four wavefronts, a
+    // barrier between items (their rows of R may meet in column k)
+    for (int i0 = tk.z; i0 < tk.w; i0 += kHeavyChunk) {
+        const int i1 = min(tk.w, i0 + kHeavyChunk);
+        for (int it = i0 + wv; it < i1; it += 4) {       // uniform per wavefront
+            const int4 item = reinterpret_cast<const int4 *>(a.sn_item)[it];
+            const int4 rec = reinterpret_cast<const int4 *>(a.sn_rec)[item.x];
+            const int len = item.z, off = rec.y - len;
+            const T xv = sn_suffix_solve<T>(Fx, xk, a.sn_cb + rec.x + off, item.y, off, len, lane);
+            if (lane < len) {
+                xk[item.y + lane] = xv;
+                us[it - i0][lane] = xv;
             }
-            __syncthreads();
+        }
+        __syncthreads();
+        for (int it = i0; it < i1; it++) {
+            const int4 item = reinterpret_cast<const int4 *>(a.sn_item)[it];
+            const int4 rec = reinterpret_cast<const int4 *>(a.sn_rec)[item.x];
+            const int w = rec.y, len = item.z, off = w - len, mcnt = item.w;
+            const int *cb = a.sn_cb + rec.x + off;
+            const int *mp = a.sn_map + a.sn_moff[it];
+            const T *u = us[it - i0];
             for (int r0 = 2 * WAVE * wv; r0 < mcnt; r0 += 8 * WAVE)
-                sn_rows_update<T>(Fx, xk, cb, mp, w, len, mcnt, r0, lane, [&](int c) { return us[c]; });
+                sn_rows_update<T>(Fx, xk, cb, mp, w, len, mcnt, r0, lane, [&](int c) { return u[c]; });
             __syncthreads();
         }
     }

@@ -426,6 +426,38 @@ def test_fp32_ir_fallback_then_fp64(ck, oracle_mod):
     assert info.used_fp64 == 1 and rc == ck.CKTLU_W_IR_FALLBACK   # the target is still out of reach
 
 
+@pytest.mark.parametrize("width", [0, -1])
+def test_fp32_check_retry_keeps_fp64(ck, oracle_mod, width):
+    """A pivot exactly at the threshold in FP64 (|a| = eps |c|) that rounds below it in FP32:
+    the FP32 refactorization fails its test, the FP64 retry passes (no re-pivot, the oracle's
+    pivots), and the context then keeps FP64 factors for its solves and later steps until
+    the next factorize."""
+    import struct
+    eps = 0.00099999996                    # float32(eps) rounds down, below eps
+    assert struct.unpack("f", struct.pack("f", eps))[0] < eps
+    colptr = np.array([0, 2, 4], np.int32)
+    rowind = np.array([0, 1, 0, 1], np.int32)
+    vals = np.array([eps, 1.0, 1.0, 3.0])   # A = [[eps, 1], [1, 3]]
+    b = np.array([1.0, 2.0])
+    s = ck.SparseLU(2, colptr, rowind, eps=eps, precision=ck.CKTLU_FP32_IR, ordering=ck.CKTLU_ORDER_NATURAL,
+                    dense_tail=-1, sweep_supernodes=width)
+    s.factorize(dev(vals))
+    assert list(s.analysis()["pivrow"]) == [0, 1]
+    for step in range(2):
+        rc, info = s.refactorize(dev(vals))
+        assert rc == 0 and info.repivoted == 0
+        assert list(s.analysis()["pivrow"]) == [0, 1]
+        x = torch.zeros(2, dtype=torch.float64, device="cuda:0")
+        rc, sinfo = s.solve(dev(b), x)
+        torch.cuda.synchronize()
+        assert rc == 0 and sinfo.used_fp64 == 1
+        assert oracle_mod.backward_error(colptr, rowind, vals, x.cpu().numpy(), b) <= 1e-12
+    assert s.stats()["n_fp32_check_retries"] == 1
+    s.factorize(dev(vals))                  # back to FP32 factors: the retry happens again
+    s.refactorize(dev(vals))
+    assert s.stats()["n_fp32_check_retries"] == 2
+
+
 @pytest.mark.parametrize("tail", [-1, 100])
 @pytest.mark.parametrize("nrhs", [1, 3])
 def test_solve_chain_widths_identical(ck, oracle_mod, tail, nrhs):
