@@ -175,7 +175,8 @@ DevBuf *all_buffers(Device &d, int i) {
                      &d.ctrl, &d.vec, &d.S, &d.Dg, &d.Dinv, &d.sn_rec, &d.sn_cb, &d.sn_seq, &d.sn_task,
                      &d.sn_item, &d.sn_moff, &d.sn_map, &d.snl_seq, &d.snu_seq, &d.Lrp, &d.Urp,
                      &d.ascale, &d.gscale, &d.sscale, &d.schur_sn_items,
-                     &d.snl_unit, &d.snu_unit, &d.sn_part, &d.sn_cnt, &d.sn_punit, &d.sn_sunit};
+                     &d.snl_unit, &d.snu_unit, &d.sn_part, &d.sn_cnt, &d.sn_punit, &d.sn_sunit,
+                     &d.sn_grp, &d.sn_gsrc, &d.sn_gent};
     const int cnt = (int)(sizeof(all) / sizeof(all[0]));
     return i < cnt ? all[i] : nullptr;
 }
@@ -334,6 +335,9 @@ int upload_all(cktlu_ctx *c) {
     if ((rc = upload(d.snl_unit, s.snl_unit, st))) return rc;
     if ((rc = upload(d.sn_punit, s.sn_punit, st))) return rc;
     if ((rc = upload(d.sn_sunit, s.sn_sunit, st))) return rc;
+    if ((rc = upload(d.sn_grp, s.sn_grp, st))) return rc;
+    if ((rc = upload(d.sn_gsrc, s.sn_gsrc, st))) return rc;
+    if ((rc = upload(d.sn_gent, s.sn_gent, st))) return rc;
     if ((rc = upload(d.snu_unit, s.snu_unit, st))) return rc;
     if ((rc = upload(d.Lrp, s.Lrp, st))) return rc;
     if ((rc = upload(d.Urp, s.Urp, st))) return rc;
@@ -616,14 +620,17 @@ int run_refactor(cktlu_ctx *c, int batch, const double *values_dev, bool fp32, b
     a.sn_moff = (const int64_t *)d.sn_moff.p;
     a.sn_punit = (const int *)d.sn_punit.p;
     a.sn_sunit = (const int *)d.sn_sunit.p;
+    a.sn_grp = (const int *)d.sn_grp.p;
+    a.sn_gsrc = (const int *)d.sn_gsrc.p;
+    a.sn_gent = (const int *)d.sn_gent.p;
     a.sn_pmax = (double *)d.sn_part.p;
     a.sn_pcnt = d.sn_cnt.p ? (int *)d.sn_cnt.p + (size_t)2 * s.sn_count * batch : nullptr;
     // supernodal sweep: per level, the supernodes' panels, then the updates they apply
     for (int l = 0; l < s.sn_levels; l++) {
         LCHK(launch_sn_panels(a, l, s.sn_lvl[l], s.sn_lvl_single[l], s.sn_sulvl[l], s.sn_sulvl[l + 1], s.sn_pulvl[l],
                               s.sn_pulvl[l + 1], st));
-        LCHK(launch_sn_updates(a, l, s.sn_task_lvl[l], s.sn_task_heavy[l], s.sn_task_tiny[l], s.sn_task_lvl[l + 1],
-                               st));
+        LCHK(launch_sn_updates(a, l, s.sn_grp_lvl[l], s.sn_grp_lvl[l + 1], s.sn_task_heavy[l], s.sn_task_tiny[l],
+                               s.sn_task_lvl[l + 1], st));
         launches += sn_level_launches(s, l);
     }
     // column sweep: level l checks level l, normalises level l-1, runs the update tasks of

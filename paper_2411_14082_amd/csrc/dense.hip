@@ -1358,9 +1358,10 @@ __global__ __launch_bounds__(kSnPanelWaves * WAVE) void sn_panel_kernel(Refactor
 }
 
 // U(S, k) = L11^-1 x_k(S) on the suffix of S's rows present in k (len rows; lane c holds row
-// c), eight L11 loads in flight; returns this lane's value.
+// c), eight L11 loads in flight; returns this lane's value.  cbv: lane c holds the storage
+// offset of the suffix's column c (read by readlane, no dependent load).
 template <typename T>
-__device__ __forceinline__ T sn_suffix_solve(const T *Fx, const T *xk, const int *cb, int slot0, int off, int len,
+__device__ __forceinline__ T sn_suffix_solve(const T *Fx, const T *xk, int cbv, int slot0, int off, int len,
                                              int lane) {
     T xv = lane < len ? xk[slot0 + lane] : T(0);
     for (int c0 = 0; c0 < len; c0 += 8) {
@@ -1368,7 +1369,8 @@ __device__ __forceinline__ T sn_suffix_solve(const T *Fx, const T *xk, const int
 #pragma unroll
         for (int u = 0; u < 8; u++) {
             const int c = c0 + u;
-            lv[u] = (c < len && lane > c && lane < len) ? Fx[cb[c] + off + lane] : T(0);
+            const int base = __builtin_amdgcn_readlane(cbv, c < len ? c : 0);
+            lv[u] = (c < len && lane > c && lane < len) ? Fx[base + off + lane] : T(0);
         }
 #pragma unroll
         for (int u = 0; u < 8; u++) {
@@ -1382,33 +1384,147 @@ __device__ __forceinline__ T sn_suffix_solve(const T *Fx, const T *xk, const int
     return xv;
 }
 
-// x_k(R rows [r0, r0 + 128) of the item) -= L21 u: two rows per lane, sixteen loads in flight.
-// u(c) comes from get(c) (a readlane or an LDS read), the same for every lane.
+// Sums over the suffix's columns [c_lo, c_hi) of L21(row, c) u_c for the rows r0 + lane and
+// r0 + 64 + lane of R (two rows per lane, sixteen loads in flight).  u_c comes from get(c)
+// (a readlane or an LDS read), the column offsets from cbv as above.
 template <typename T, typename GetU>
-__device__ __forceinline__ void sn_rows_update(const T *Fx, T *xk, const int *cb, const int *mp, int w, int len,
-                                               int mcnt, int r0, int lane, GetU get) {
+__device__ __forceinline__ void sn_rows_partial(const T *Fx, int cbv, int w, int c_lo, int c_hi, int mcnt, int r0,
+                                                int lane, GetU get, T &acca, T &accb) {
     const int ra = r0 + lane, rb = r0 + WAVE + lane;
     const bool ina = ra < mcnt, inb = rb < mcnt;
-    const int sla = ina ? mp[ra] : 0, slb = inb ? mp[rb] : 0;
-    T acca = T(0), accb = T(0);
-    for (int c0 = 0; c0 < len; c0 += 8) {
+    acca = T(0);
+    accb = T(0);
+    for (int c0 = c_lo; c0 < c_hi; c0 += 8) {
         T la[8], lb[8];
 #pragma unroll
         for (int u = 0; u < 8; u++) {
             const int c = c0 + u;
-            la[u] = (ina && c < len) ? Fx[cb[c] + w + ra] : T(0);
-            lb[u] = (inb && c < len) ? Fx[cb[c] + w + rb] : T(0);
+            const int base = __builtin_amdgcn_readlane(cbv, c < c_hi ? c : c_lo) + w;
+            la[u] = (ina && c < c_hi) ? Fx[base + ra] : T(0);
+            lb[u] = (inb && c < c_hi) ? Fx[base + rb] : T(0);
         }
 #pragma unroll
         for (int u = 0; u < 8; u++)
-            if (c0 + u < len) {
+            if (c0 + u < c_hi) {
                 const T uc = get(c0 + u);
                 acca = fma(la[u], uc, acca);
                 accb = fma(lb[u], uc, accb);
             }
     }
-    if (ina) xk[sla] -= acca;
-    if (inb) xk[slb] -= accb;
+}
+
+// x_k(R rows r0 + lane, r0 + 64 + lane) -= the sums above over all len columns; the rows'
+// slots in k from mp.
+template <typename T, typename GetU>
+__device__ __forceinline__ void sn_rows_update(const T *Fx, T *xk, int cbv, const int *mp, int w, int len, int mcnt,
+                                               int r0, int lane, GetU get) {
+    const int ra = r0 + lane, rb = r0 + WAVE + lane;
+    const int sla = ra < mcnt ? mp[ra] : 0, slb = rb < mcnt ? mp[rb] : 0;
+    T acca, accb;
+    sn_rows_partial<T>(Fx, cbv, w, 0, len, mcnt, r0, lane, get, acca, accb);
+    if (ra < mcnt) xk[sla] -= acca;
+    if (rb < mcnt) xk[slb] -= accb;
+}
+
+constexpr int kHeavyChunk = 16;                      // entries of a heavy group whose suffixes are solved together
+
+// A heavy group (up to kGroupTargets target columns sharing most of their sources; one
+// workgroup per (group, instance)).  Its sources are taken in ascending order, in chunks of at
+// most kHeavyChunk (source, target) entries.  A chunk's suffix solves U(S, k) = L11^-1 x_k(S) go
+// first, a wavefront each: they are independent of every row update of the level (its
+// supernodes hold no rows of each other's R).  Then each source of the chunk, in order, reads
+// its rows of R once for all the group's targets it reaches: x_k(R) -= L21 U(S, k) for each of
+// them (its suffix columns only, in ascending order: each target row gets the operations of a
+// single-target task in the same order), two rows per lane, R's rows split over the four
+// wavefronts, a barrier between sources (their rows of R may meet in a target).
+template <typename T>
+__device__ void sn_heavy_group(const RefactorArgs &a, int inst, int g, T (*us)[WAVE], int *gdp, int *eoff, int *edp,
+                               int64_t *emoff, int lane, int wv) {
+    const int tid = threadIdx.x;
+    T *Fx = reinterpret_cast<T *>(a.Fx) + (size_t)inst * a.nnzF;
+    const int4 gr = reinterpret_cast<const int4 *>(a.sn_grp)[g];
+    const int4 *gsrc = reinterpret_cast<const int4 *>(a.sn_gsrc);
+    const int2 *gent = reinterpret_cast<const int2 *>(a.sn_gent);
+    if (tid < gr.y) gdp[tid] = a.sn_task[4 * (gr.x + tid) + 1];
+    __syncthreads();
+    for (int s0r = gr.z; s0r < gr.w;) {
+        // the chunk: sources [s0r, s1r) with at most kHeavyChunk entries (a source has at most
+        // kGroupTargets of them)
+        const int e_lo = gsrc[s0r].y;
+        int s1r = s0r, e_hi = e_lo;
+        while (s1r < gr.w && gsrc[s1r].y + gsrc[s1r].z - e_lo <= kHeavyChunk) {
+            e_hi = gsrc[s1r].y + gsrc[s1r].z;
+            s1r++;
+        }
+        for (int e = e_lo + wv; e < e_hi; e += 4) {       // uniform per wavefront
+            const int2 en = gent[e];
+            const int4 item = reinterpret_cast<const int4 *>(a.sn_item)[en.y];
+            const int4 rec = reinterpret_cast<const int4 *>(a.sn_rec)[item.x];
+            const int len = item.z, off = rec.y - len;
+            T *xk = Fx + gdp[en.x];
+            const int cbv = lane < len ? a.sn_cb[rec.x + off + lane] : 0;
+            const T xv = sn_suffix_solve<T>(Fx, xk, cbv, item.y, off, len, lane);
+            if (lane < len) {
+                xk[item.y + lane] = xv;
+                us[e - e_lo][off + lane] = xv;
+            }
+            if (lane < off) us[e - e_lo][lane] = T(0);
+            if (lane == 0) {
+                eoff[e - e_lo] = off;
+                edp[e - e_lo] = gdp[en.x];
+                emoff[e - e_lo] = a.sn_moff[en.y];
+            }
+        }
+        __syncthreads();
+        for (int sr = s0r; sr < s1r; sr++) {
+            const int4 src = gsrc[sr];
+            const int4 rec = reinterpret_cast<const int4 *>(a.sn_rec)[src.x];
+            const int w = rec.y, ns = src.z, mcnt = src.w, e0 = src.y - e_lo;
+            int offmin = w;
+            for (int j = 0; j < ns; j++) offmin = min(offmin, eoff[e0 + j]);
+            const int cbv = lane < w ? a.sn_cb[rec.x + lane] : 0;   // S's columns
+            for (int r0 = 2 * WAVE * wv; r0 < mcnt; r0 += 8 * WAVE) {
+                const int ra = r0 + lane, rb = r0 + WAVE + lane;
+                const bool ina = ra < mcnt, inb = rb < mcnt;
+                T acca[kGroupTargets], accb[kGroupTargets];
+#pragma unroll
+                for (int j = 0; j < kGroupTargets; j++) acca[j] = accb[j] = T(0);
+                for (int c0 = offmin; c0 < w; c0 += 8) {
+                    T la[8], lb[8];
+#pragma unroll
+                    for (int u = 0; u < 8; u++) {
+                        const int c = c0 + u;
+                        const int base = __builtin_amdgcn_readlane(cbv, c < w ? c : offmin) + w;
+                        la[u] = (ina && c < w) ? Fx[base + ra] : T(0);
+                        lb[u] = (inb && c < w) ? Fx[base + rb] : T(0);
+                    }
+#pragma unroll
+                    for (int u = 0; u < 8; u++) {
+                        const int c = c0 + u;
+                        if (c < w) {
+#pragma unroll
+                            for (int j = 0; j < kGroupTargets; j++)
+                                if (j < ns && c >= eoff[e0 + j]) {
+                                    const T uc = us[e0 + j][c];
+                                    acca[j] = fma(la[u], uc, acca[j]);
+                                    accb[j] = fma(lb[u], uc, accb[j]);
+                                }
+                        }
+                    }
+                }
+#pragma unroll
+                for (int j = 0; j < kGroupTargets; j++)
+                    if (j < ns) {
+                        T *xk = Fx + edp[e0 + j];
+                        const int *mp = a.sn_map + emoff[e0 + j];
+                        if (ina) xk[mp[ra]] -= acca[j];
+                        if (inb) xk[mp[rb]] -= accb[j];
+                    }
+            }
+            __syncthreads();
+        }
+        s0r = s1r;
+    }
 }
 
 // Update tasks of a level: a task owns one target column k and applies the level's
@@ -1416,27 +1532,28 @@ __device__ __forceinline__ void sn_rows_update(const T *Fx, T *xk, const int *cb
 // on the suffix of S's rows present in k, written to k; then x_k(R) -= L21 U(S, k) on R's
 // rows (rows < T only for a dense-block target: its rows >= T are the Schur update's), their
 // slots in k from sn_map.  Rows of one supernode are distinct, so the stores of one pass
-// never feed its own loads.  Tasks [tbeg, theavy) are heavy: a workgroup per (task,
-// instance), the suffixes of up to kHeavyChunk items solved first (a wavefront each) and
-// passed through LDS, the four wavefronts then splitting R's rows item by item, a barrier
-// between items; tasks [theavy, ttiny) get a wavefront per (task, instance), [ttiny, tend)
-// sixteen lanes.  Either way every row of k receives the same operations in the same order.
-constexpr int kHeavyChunk = 16;                      // items of a heavy task whose suffixes are solved together
+// never feed its own loads.  Heavy tasks come in groups sn_grp [gbeg, ...) (nheavy
+// workgroups: groups x instances, see sn_heavy_group); tasks [theavy, ttiny) get a wavefront
+// per (task, instance), [ttiny, tend) sixteen lanes.  Every way, each row of k receives the
+// same operations in the same order.
 template <typename T>
-__global__ __launch_bounds__(256) void sn_update_kernel(RefactorArgs a, int lev, int tbeg, int theavy, int ttiny,
-                                                        int tend) {
+__global__ __launch_bounds__(256) void sn_update_kernel(RefactorArgs a, int lev, int gbeg, int theavy, int ttiny,
+                                                        int tend, unsigned nheavy) {
     __shared__ T us[kHeavyChunk][WAVE];
+    __shared__ int gdp[kGroupTargets];
+    __shared__ int eoff[kHeavyChunk], edp[kHeavyChunk];
+    __shared__ int64_t emoff[kHeavyChunk];
     const int lane = threadIdx.x & (WAVE - 1), wv = threadIdx.x / WAVE;
-    // grid sizes fit 32 bits (one dimension of a launch)
-    const unsigned nheavy = (unsigned)(theavy - tbeg) * (unsigned)a.batch;
+    // grid sizes fit 32 bits (one dimension of a launch); nheavy = heavy groups x instances
     const unsigned nlight = ((unsigned)(ttiny - theavy) * (unsigned)a.batch + 3) / 4;
     const unsigned bid = blockIdx.x, batch = (unsigned)a.batch;
     int t, inst;
-    const bool heavy = bid < nheavy;
-    if (heavy) {
+    if (bid < nheavy) {
         const unsigned b = xcd_contiguous(bid, nheavy);
         inst = (int)(b % batch);
-        t = tbeg + (int)(b / batch);
+        if (sn_stopped(a, inst, lev)) return;            // uniform over the workgroup
+        sn_heavy_group<T>(a, inst, gbeg + (int)(b / batch), us, gdp, eoff, edp, emoff, lane, wv);
+        return;
     } else if (bid < nheavy + nlight) {
         const unsigned wid = xcd_contiguous(bid - nheavy, nlight) * 4 + wv;
         if (wid >= (unsigned)(ttiny - theavy) * batch) return;
@@ -1479,55 +1596,22 @@ __global__ __launch_bounds__(256) void sn_update_kernel(RefactorArgs a, int lev,
         }
         return;
     }
-    if (sn_stopped(a, inst, lev)) return;                // uniform over a heavy task's workgroup
+    if (sn_stopped(a, inst, lev)) return;
     T *Fx = reinterpret_cast<T *>(a.Fx) + (size_t)inst * a.nnzF;
     const int4 tk = reinterpret_cast<const int4 *>(a.sn_task)[t];
     T *xk = Fx + tk.y;
-    if (!heavy) {
-        for (int it = tk.z; it < tk.w; it++) {
-            const int4 item = reinterpret_cast<const int4 *>(a.sn_item)[it];
-            const int4 rec = reinterpret_cast<const int4 *>(a.sn_rec)[item.x];
-            const int w = rec.y, len = item.z, off = w - len, mcnt = item.w;
-            const int *cb = a.sn_cb + rec.x + off;       // the suffix's columns
-            const int *mp = a.sn_map + a.sn_moff[it];
-            const T xv = sn_suffix_solve<T>(Fx, xk, cb, item.y, off, len, lane);
-            if (lane < len) xk[item.y + lane] = xv;
-            for (int r0 = 0; r0 < mcnt; r0 += 2 * WAVE)
-                sn_rows_update<T>(Fx, xk, cb, mp, w, len, mcnt, r0, lane, [&](int c) { return readlane(xv, c); });
-            __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "workgroup");
-            __builtin_amdgcn_wave_barrier();
-        }
-        return;
-    }
-    // heavy task: items in chunks of kHeavyChunk.  The chunk's suffix solves go first, a
-    // wavefront each: they are independent of every item's row update (the supernodes of one
-    // level hold no rows of each other's R, so no update reaches another item's suffix rows).
-    // Then the chunk's row updates in item order, R's rows split over the four wavefronts, a
-    // barrier between items (their rows of R may meet in column k)
-    for (int i0 = tk.z; i0 < tk.w; i0 += kHeavyChunk) {
-        const int i1 = min(tk.w, i0 + kHeavyChunk);
-        for (int it = i0 + wv; it < i1; it += 4) {       // uniform per wavefront
-            const int4 item = reinterpret_cast<const int4 *>(a.sn_item)[it];
-            const int4 rec = reinterpret_cast<const int4 *>(a.sn_rec)[item.x];
-            const int len = item.z, off = rec.y - len;
-            const T xv = sn_suffix_solve<T>(Fx, xk, a.sn_cb + rec.x + off, item.y, off, len, lane);
-            if (lane < len) {
-                xk[item.y + lane] = xv;
-                us[it - i0][lane] = xv;
-            }
-        }
-        __syncthreads();
-        for (int it = i0; it < i1; it++) {
-            const int4 item = reinterpret_cast<const int4 *>(a.sn_item)[it];
-            const int4 rec = reinterpret_cast<const int4 *>(a.sn_rec)[item.x];
-            const int w = rec.y, len = item.z, off = w - len, mcnt = item.w;
-            const int *cb = a.sn_cb + rec.x + off;
-            const int *mp = a.sn_map + a.sn_moff[it];
-            const T *u = us[it - i0];
-            for (int r0 = 2 * WAVE * wv; r0 < mcnt; r0 += 8 * WAVE)
-                sn_rows_update<T>(Fx, xk, cb, mp, w, len, mcnt, r0, lane, [&](int c) { return u[c]; });
-            __syncthreads();
-        }
+    for (int it = tk.z; it < tk.w; it++) {
+        const int4 item = reinterpret_cast<const int4 *>(a.sn_item)[it];
+        const int4 rec = reinterpret_cast<const int4 *>(a.sn_rec)[item.x];
+        const int w = rec.y, len = item.z, off = w - len, mcnt = item.w;
+        const int cbv = lane < len ? a.sn_cb[rec.x + off + lane] : 0;   // the suffix's columns
+        const int *mp = a.sn_map + a.sn_moff[it];
+        const T xv = sn_suffix_solve<T>(Fx, xk, cbv, item.y, off, len, lane);
+        if (lane < len) xk[item.y + lane] = xv;
+        for (int r0 = 0; r0 < mcnt; r0 += 2 * WAVE)
+            sn_rows_update<T>(Fx, xk, cbv, mp, w, len, mcnt, r0, lane, [&](int c) { return readlane(xv, c); });
+        __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "workgroup");
+        __builtin_amdgcn_wave_barrier();
     }
 }
 
@@ -1754,17 +1838,18 @@ int launch_sn_panels(const RefactorArgs &a, int lev, int sbeg, int s1, int sub, 
     return (int)hipGetLastError();
 }
 
-int launch_sn_updates(const RefactorArgs &a, int lev, int tbeg, int theavy, int ttiny, int tend, void *stream) {
-    const int64_t heavy = (int64_t)(theavy - tbeg) * a.batch;
+int launch_sn_updates(const RefactorArgs &a, int lev, int gbeg, int gend, int theavy, int ttiny, int tend,
+                      void *stream) {
+    const int64_t heavy = (int64_t)(gend - gbeg) * a.batch;
     const int64_t light = ((int64_t)(ttiny - theavy) * a.batch + 3) / 4;
     const int64_t tiny = ((int64_t)(tend - ttiny) * a.batch + 15) / 16;
     if (heavy + light + tiny == 0) return 0;
-    if (heavy + light + tiny > INT_MAX || (int64_t)(tend - tbeg) * a.batch > INT_MAX) return (int)hipErrorInvalidValue;
+    if (heavy + light + tiny > INT_MAX || (int64_t)(tend - theavy) * a.batch > INT_MAX) return (int)hipErrorInvalidValue;
     const dim3 grid((unsigned)(heavy + light + tiny));
-    if (a.fp32) hipLaunchKernelGGL(sn_update_kernel<float>, grid, dim3(256), 0, (hipStream_t)stream, a, lev, tbeg,
-                                   theavy, ttiny, tend);
-    else hipLaunchKernelGGL(sn_update_kernel<double>, grid, dim3(256), 0, (hipStream_t)stream, a, lev, tbeg, theavy,
-                            ttiny, tend);
+    if (a.fp32) hipLaunchKernelGGL(sn_update_kernel<float>, grid, dim3(256), 0, (hipStream_t)stream, a, lev, gbeg,
+                                   theavy, ttiny, tend, (unsigned)heavy);
+    else hipLaunchKernelGGL(sn_update_kernel<double>, grid, dim3(256), 0, (hipStream_t)stream, a, lev, gbeg, theavy,
+                            ttiny, tend, (unsigned)heavy);
     return (int)hipGetLastError();
 }
 

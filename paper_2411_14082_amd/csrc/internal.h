@@ -169,6 +169,11 @@ struct Schedule {
     std::vector<int> sn_task_lvl;             // [sn_levels+1] tasks of level l
     std::vector<int> sn_task_heavy;           // [sn_levels] its heavy tasks (a workgroup each) end here
     std::vector<int> sn_task_tiny;            // [sn_levels] its tiny tasks (sixteen lanes each) start here
+    // the heavy tasks of level l as groups sn_grp [sn_grp_lvl[l], sn_grp_lvl[l+1]): int4 {first task,
+    // tasks, first source record, end source record}; source records sn_gsrc int4 {S, first
+    // entry, entries, rows of R updated}, ascending in S; entries sn_gent int2 {task index in the
+    // group, item}
+    std::vector<int> sn_grp, sn_gsrc, sn_gent, sn_grp_lvl;
     std::vector<int> sn_task;                 // int4 per task {k, Dp[k], first item, end item}
     std::vector<int> sn_item;                 // int4 per item {supernode, slot of its first row in k, rows
                                               // of S present in k (the suffix), rows of R updated}
@@ -214,6 +219,7 @@ struct Device {
     DevBuf snl_seq, snu_seq, Lrp, Urp;                                 // supernodal solves
     DevBuf snl_unit, snu_unit, sn_part, sn_cnt;                        // their split units
     DevBuf sn_punit, sn_sunit;                                         // split panels
+    DevBuf sn_grp, sn_gsrc, sn_gent;                                   // grouped heavy tasks
     DevBuf ascale, gscale, sscale;     // static scaling: per nonzero of A, per solve row, per solve column
     DevBuf schur_sn_items;             // supernodal Schur update items
     // values and status words
@@ -271,6 +277,7 @@ struct RefactorArgs {
     // scratch block}; column maxima of the slices (64 doubles per block and instance) and an
     // arrival counter per sn_seq position and instance (zero on entry and on exit)
     const int *sn_punit, *sn_sunit;
+    const int *sn_grp, *sn_gsrc, *sn_gent;   // grouped heavy update tasks (see Schedule)
     double *sn_pmax;
     int *sn_pcnt;
     const double *ascale;      // static scaling per nonzero of A (row scale x column scale), or null
@@ -288,11 +295,13 @@ int launch_refactor_level(const RefactorArgs &a, int cbeg, int cend, int pbeg, i
 // and L = x / pivot, a wavefront each), the small panels as units sn_sunit[sub, sue) (a wavefront
 // each) and the wider panels as units sn_punit[ubeg, uend) (a workgroup each): dense LU of the
 // diagonal block,
-// L21 = A21 U11^-1, pivot test; then the level's update tasks: [tbeg, theavy) a workgroup each,
-// [theavy, ttiny) a wavefront each, [ttiny, tend) sixteen lanes each.
+// L21 = A21 U11^-1, pivot test; then the level's update tasks: the heavy ones as groups
+// sn_grp [gbeg, gend) (a workgroup each), [theavy, ttiny) a wavefront each, [ttiny, tend)
+// sixteen lanes each.
 int launch_sn_panels(const RefactorArgs &a, int lev, int sbeg, int s1, int sub, int sue, int ubeg, int uend,
                      void *stream);
-int launch_sn_updates(const RefactorArgs &a, int lev, int tbeg, int theavy, int ttiny, int tend, void *stream);
+int launch_sn_updates(const RefactorArgs &a, int lev, int gbeg, int gend, int theavy, int ttiny, int tend,
+                      void *stream);
 int launch_reset_ctrl(int *ctrl, int nwords, int value, void *stream);
 // status[i] = firstfail[i] == INT_MAX ? -1 : firstfail[i]
 int launch_status_out(const int *firstfail, int *status, int batch, void *stream);
@@ -368,6 +377,7 @@ int noalloc_scratch(double **out);
 // D = n - T, held per instance as a column-major D x D matrix S.
 constexpr int kDenseBlock = 64;  // panel width of the blocked LU and of the block solves
 constexpr int kSnSmallW = 16;    // supernodes up to this wide are factored by one wavefront
+constexpr int kGroupTargets = 4; // heavy update tasks with shared sources grouped this many at a time
 constexpr int kTinyRows = 16;    // update tasks whose items have at most this many suffix rows and
                                  // rows of R: 16 lanes each
 struct DenseArgs {

@@ -6,6 +6,7 @@
 // default) the supernodes with their sweep levels, panel units, update tasks,
 // slot maps, Schur items and solve levels.
 #include <algorithm>
+#include <array>
 #include <climits>
 #include <thread>
 #include <new>
@@ -252,6 +253,59 @@ static void build_supernodal(const Factor &f, Schedule &s, int T, int wmax, int 
                 for (int t : *g) tmp.insert(tmp.end(), s.sn_task.begin() + 4 * (size_t)t, s.sn_task.begin() + 4 * (size_t)t + 4);
         }
         s.sn_task.swap(tmp);
+    }
+    // heavy tasks in groups of up to kGroupTargets consecutive targets that lie in one sparse
+    // supernode or are all dense-block columns: such targets share most of their sources, and
+    // a group reads each source's rows of R once for all its targets.  Source records {S,
+    // first entry, entries, rows of R updated} ascend in S; entries {target index in the
+    // group, item}.
+    s.sn_grp.clear();
+    s.sn_gsrc.clear();
+    s.sn_gent.clear();
+    s.sn_grp_lvl.assign(nl + 1, 0);
+    for (int q = 0; q < nl; q++) {
+        const int t0 = s.sn_task_lvl[q], t1 = s.sn_task_heavy[q];
+        for (int ga = t0; ga < t1;) {
+            const int ka = s.sn_task[4 * (size_t)ga];
+            const int key = ka < T ? snof[ka] : -1;
+            int gb = ga + 1;
+            while (gb < t1 && gb - ga < cktlu_dev::kGroupTargets) {
+                const int kb = s.sn_task[4 * (size_t)gb];
+                if ((kb < T ? snof[kb] : -1) != key) break;
+                gb++;
+            }
+            std::vector<std::array<int, 3>> ent;    // {S, target index, item}
+            auto collect = [&]() {
+                ent.clear();
+                for (int t = ga; t < gb; t++)
+                    for (int it = s.sn_task[4 * (size_t)t + 2]; it < s.sn_task[4 * (size_t)t + 3]; it++)
+                        ent.push_back({s.sn_item[4 * (size_t)it], t - ga, it});
+                std::sort(ent.begin(), ent.end());
+                // a source's entries must update the same rows of R (they do: targets in one
+                // sparse supernode take all of R, dense-block targets its rows < T)
+                for (size_t e = 1; e < ent.size(); e++)
+                    if (ent[e][0] == ent[e - 1][0] &&
+                        s.sn_item[4 * (size_t)ent[e][2] + 3] != s.sn_item[4 * (size_t)ent[e - 1][2] + 3])
+                        return false;
+                return true;
+            };
+            if (!collect()) {
+                gb = ga + 1;                        // a group of one: one entry per source
+                collect();
+            }
+            const int src0 = (int)(s.sn_gsrc.size() / 4);
+            for (size_t e = 0; e < ent.size();) {
+                size_t f = e;
+                while (f < ent.size() && ent[f][0] == ent[e][0]) f++;
+                s.sn_gsrc.insert(s.sn_gsrc.end(), {ent[e][0], (int)(s.sn_gent.size() / 2), (int)(f - e),
+                                                   s.sn_item[4 * (size_t)ent[e][2] + 3]});
+                for (size_t h = e; h < f; h++) s.sn_gent.insert(s.sn_gent.end(), {ent[h][1], ent[h][2]});
+                e = f;
+            }
+            s.sn_grp.insert(s.sn_grp.end(), {ga, gb - ga, src0, (int)(s.sn_gsrc.size() / 4)});
+            ga = gb;
+        }
+        s.sn_grp_lvl[q + 1] = (int)(s.sn_grp.size() / 4);
     }
     // panels: the diagonal block's LU and L21 = A21 U11^-1
     for (int S = 0; S < nsn; S++) {
