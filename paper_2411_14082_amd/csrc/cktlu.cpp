@@ -175,8 +175,8 @@ DevBuf *all_buffers(Device &d, int i) {
                      &d.ctrl, &d.vec, &d.S, &d.Dg, &d.Dinv, &d.sn_rec, &d.sn_cb, &d.sn_seq, &d.sn_task,
                      &d.sn_item, &d.sn_moff, &d.sn_map, &d.snl_seq, &d.snu_seq, &d.Lrp, &d.Urp,
                      &d.ascale, &d.gscale, &d.sscale, &d.schur_sn_items,
-                     &d.snl_unit, &d.snu_unit, &d.sn_part, &d.sn_cnt, &d.sn_punit, &d.sn_sunit,
-                     &d.sn_grp, &d.sn_gsrc, &d.sn_gent};
+                     &d.snl_unit, &d.snu_unit, &d.snl_urange, &d.snl_runs, &d.snu_urange, &d.snu_runs,
+                     &d.sn_part, &d.sn_cnt, &d.sn_punit, &d.sn_sunit, &d.sn_grp, &d.sn_gsrc, &d.sn_gent};
     const int cnt = (int)(sizeof(all) / sizeof(all[0]));
     return i < cnt ? all[i] : nullptr;
 }
@@ -333,12 +333,16 @@ int upload_all(cktlu_ctx *c) {
     if ((rc = upload(d.snl_seq, s.snl_seq, st))) return rc;
     if ((rc = upload(d.snu_seq, s.snu_seq, st))) return rc;
     if ((rc = upload(d.snl_unit, s.snl_unit, st))) return rc;
+    if ((rc = upload(d.snl_urange, s.snl_urange, st))) return rc;
+    if ((rc = upload(d.snl_runs, s.snl_runs, st))) return rc;
     if ((rc = upload(d.sn_punit, s.sn_punit, st))) return rc;
     if ((rc = upload(d.sn_sunit, s.sn_sunit, st))) return rc;
     if ((rc = upload(d.sn_grp, s.sn_grp, st))) return rc;
     if ((rc = upload(d.sn_gsrc, s.sn_gsrc, st))) return rc;
     if ((rc = upload(d.sn_gent, s.sn_gent, st))) return rc;
     if ((rc = upload(d.snu_unit, s.snu_unit, st))) return rc;
+    if ((rc = upload(d.snu_urange, s.snu_urange, st))) return rc;
+    if ((rc = upload(d.snu_runs, s.snu_runs, st))) return rc;
     if ((rc = upload(d.Lrp, s.Lrp, st))) return rc;
     if ((rc = upload(d.Urp, s.Urp, st))) return rc;
     if ((rc = upload(d.lrec, s.lrec, st))) return rc;
@@ -876,7 +880,8 @@ int tri_solves(cktlu_ctx *c, int nrhs, int batch, double *z, bool fp32, const in
     hipEvent_t t0 = phase_begin(c);
     int launches = 0;
     for (int l = 0; snodal && l < s.snl_levels; l++, launches++)
-        LCHK(launch_sn_lsolve(a, (const int *)d.snl_seq.p, (const int *)d.snl_unit.p, s.snl_lvl[l], s.snl_tiny[l],
+        LCHK(launch_sn_lsolve(a, (const int *)d.snl_seq.p, (const int *)d.snl_unit.p, (const int *)d.snl_urange.p,
+                              (const int *)d.snl_runs.p, s.snl_lvl[l], s.snl_tiny[l],
                               s.snl_single[l],
                               s.snl_ulvl[l], s.snl_ulvl[l + 1], (int *)d.sn_cnt.p, st));
     const int ldense = s.tail0 < c->an.n ? (int)s.lsptr.size() - 2 : -1;   // level of the dense rows
@@ -903,7 +908,8 @@ int tri_solves(cktlu_ctx *c, int nrhs, int batch, double *z, bool fp32, const in
     t0 = phase_begin(c);
     launches = 0;
     for (int l = 0; snodal && l < s.snu_levels; l++, launches++)
-        LCHK(launch_sn_usolve(a, (const int *)d.snu_seq.p, (const int *)d.snu_unit.p, s.snu_lvl[l], s.snu_tiny[l],
+        LCHK(launch_sn_usolve(a, (const int *)d.snu_seq.p, (const int *)d.snu_unit.p, (const int *)d.snu_urange.p,
+                              (const int *)d.snu_runs.p, s.snu_lvl[l], s.snu_tiny[l],
                               s.snu_single[l],
                               s.snu_ulvl[l], s.snu_ulvl[l + 1],
                               d.sn_cnt.p ? (int *)d.sn_cnt.p + (size_t)s.sn_count * batch : nullptr, st));

@@ -188,11 +188,15 @@ struct Schedule {
     // first: singletons with a short row up to snl_tiny[l] (sixteen lanes each), then up to
     // snl_single[l] the others of at most kSnSmallW rows and a short pull (a wavefront each).
     // The workgroup units of level l: snl_unit [snl_ulvl[l], snl_ulvl[l+1]), int4 {position in
-    // snl_seq, slice p, slices P, first scratch block of the supernode (-1 when P = 1)}; a level
-    // uses at most snl_nscr scratch blocks.
+    // snl_seq, unit p, units P, first scratch block of the supernode (-1 when P = 1)}; a level
+    // uses at most snl_nscr scratch blocks.  A workgroup supernode's pull is a list of runs
+    // (snl_runs, int4 {column j, position of the first entry, first row c_a, rows}: rows
+    // s0 + c_a ... of the supernode present in column j, at consecutive positions); unit u pulls
+    // the runs [snl_urange[2u], snl_urange[2u+1]).
     int snl_levels = 0, snu_levels = 0;
     std::vector<int> snl_lvl, snl_tiny, snl_single, snl_seq, snu_lvl, snu_tiny, snu_single, snu_seq;
     std::vector<int> snl_unit, snl_ulvl, snu_unit, snu_ulvl;
+    std::vector<int> snl_urange, snl_runs, snu_urange, snu_runs;
     int snl_nscr = 0, snu_nscr = 0;
 };
 
@@ -218,6 +222,7 @@ struct Device {
     DevBuf sn_rec, sn_cb, sn_seq, sn_task, sn_item, sn_moff, sn_map;   // supernodal sweep
     DevBuf snl_seq, snu_seq, Lrp, Urp;                                 // supernodal solves
     DevBuf snl_unit, snu_unit, sn_part, sn_cnt;                        // their split units
+    DevBuf snl_urange, snl_runs, snu_urange, snu_runs;                 // the units' runs
     DevBuf sn_punit, sn_sunit;                                         // split panels
     DevBuf sn_grp, sn_gsrc, sn_gent;                                   // grouped heavy tasks
     DevBuf ascale, gscale, sscale;     // static scaling: per nonzero of A, per solve row, per solve column
@@ -325,10 +330,10 @@ struct SolveArgs {
 // wavefront per supernode seq[stiny, smid) and a workgroup per unit units[ubeg, uend) (int4
 // {position in seq, slice, slices, first scratch block}); cnt: an arrival counter per seq
 // position and instance, zero on entry and on exit.
-int launch_sn_lsolve(const SolveArgs &a, const int *seq, const int *units, int sbeg, int stiny, int smid, int ubeg,
-                     int uend, int *cnt, void *stream);
-int launch_sn_usolve(const SolveArgs &a, const int *seq, const int *units, int sbeg, int stiny, int smid, int ubeg,
-                     int uend, int *cnt, void *stream);
+int launch_sn_lsolve(const SolveArgs &a, const int *seq, const int *units, const int *urange, const int *runs, int sbeg,
+                     int stiny, int smid, int ubeg, int uend, int *cnt, void *stream);
+int launch_sn_usolve(const SolveArgs &a, const int *seq, const int *units, const int *urange, const int *runs, int sbeg,
+                     int stiny, int smid, int ubeg, int uend, int *cnt, void *stream);
 
 // Solve positions [lbeg, lend) of lrec / urec (one level of the solve graph).
 int launch_lsolve_level(const SolveArgs &a, int lbeg, int lend, void *stream);

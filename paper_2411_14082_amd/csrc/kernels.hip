@@ -620,22 +620,25 @@ __device__ __forceinline__ void sn_triangle(Elem elem, double *y, int s0, int w,
 // One level of the supernodal L (U) solve.  Singletons with a short row get sixteen lanes per
 // (row, instance).  Other supernodes of at most kSnSmallW rows with a short pull get a
 // wavefront per (supernode, instance): a singleton as in the row kernel; a wider one pulls all
-// its rows at once (a group of lanes per row) and solves its triangle.  Every other supernode [s0, s0 + w) is cut into P units (P from its number of
-// entries outside the diagonal block), a workgroup of sixteen wavefronts per (unit, instance):
-// unit p pulls slice p of every row's entries outside the block (L: columns < s0, the row's
-// first entries; U: columns >= s0 + w, its last entries), each row slice cut again into
-// Q = ceil(16 / w) pieces so that all wavefronts work; the pieces meet in LDS and are summed in
-// order.  With P = 1 the workgroup then solves the triangle; with P > 1 each unit stores its
-// row sums in its scratch block and counts its arrival, and the last unit to arrive adds the
-// P blocks (the even slices and the odd slices in ascending order, by two halves of its
-// threads, then the two halves: the same sums whichever unit is last) and solves the
-// triangle.
+// its rows at once (a group of lanes per row) and solves its triangle.  Every other supernode
+// [s0, s0 + w) pulls by runs: a run is a column j and the rows of the supernode present in it,
+// consecutive rows at consecutive positions of j's storage, so lane c (row s0 + c) reads its
+// entry of the run next to its neighbours' and y_j once per run instead of once per entry.  The
+// supernode's runs are cut into P units, a workgroup of sixteen wavefronts per (unit,
+// instance); wavefront v takes the unit's runs v, v + 16, ... (four in flight) and its lanes
+// add the products to their rows' sums in that order; the sixteen wavefronts' sums meet in LDS
+// by a fixed tree.  With P = 1 the workgroup then solves the triangle; with P > 1 each unit
+// stores its row sums in its scratch block and counts its arrival, and the last unit to arrive
+// adds the P blocks (the even units and the odd units in ascending order, by two halves of its
+// threads, then the two halves: the same sums whichever unit is last) and solves the triangle.
+// Every unit loads the diagonal block into LDS while it pulls.
 constexpr int kSnSolveWG = 1024;                     // threads of a supernodal solve workgroup
 constexpr int kSnSolveWaves = kSnSolveWG / WAVE;
 template <typename T, int NR, bool UPPER>
 __global__ __launch_bounds__(kSnSolveWG) void sn_solve_kernel(SolveArgs a, const int *seq, const int *units,
-                                                              int sbeg, int stiny, int smid, int ubeg, int *cnt) {
-    __shared__ double part[64][8];
+                                                              const int *urange, const int *runs, int sbeg, int stiny,
+                                                              int smid, int ubeg, int *cnt) {
+    __shared__ double wsum[8][8][WAVE];                  // the wavefronts' sums, [wavefront][rhs][row]
     __shared__ double red[2][512];
     __shared__ double tri[64][65];                       // a unit's diagonal block, column-major
     __shared__ int arrived;
@@ -746,35 +749,64 @@ __global__ __launch_bounds__(kSnSolveWG) void sn_solve_kernel(SolveArgs a, const
     const int64_t pu = (int64_t)blockIdx.x - nsw;
     const int inst = (int)(pu % a.batch);
     if (a.skip && a.skip[inst] != -1) return;            // the whole workgroup
-    const int4 un = reinterpret_cast<const int4 *>(units)[ubeg + (int)(pu / a.batch)];
+    const int ui = ubeg + (int)(pu / a.batch);
+    const int4 un = reinterpret_cast<const int4 *>(units)[ui];
+    const int2 ur = reinterpret_cast<const int2 *>(urange)[ui];
     const int4 rec = reinterpret_cast<const int4 *>(a.sn_rec)[seq[un.x]];
     const int s0 = rec.x, w = rec.y;
     const T *Fx = reinterpret_cast<const T *>(a.Fx) + (size_t)inst * a.nnzF;
     double *y = a.y + (size_t)inst * a.n * YS;
-    const int Q = (kSnSolveWaves + w - 1) / w;        // w * Q <= 64
-    const int64_t pieces = (int64_t)un.z * Q;
-    for (int t = wv; t < w * Q; t += kSnSolveWaves) {
-        const int c = t / Q, i = s0 + c;
-        const int beg = UPPER ? rp[i] + (w - 1 - c) : rp[i];
-        const int end = UPPER ? rp[i + 1] : rp[i + 1] - c;
-        const int64_t len = end - beg, k = (int64_t)un.y * Q + t % Q;
-        double acc[NR];
-        row_pull<T, NR>(rjs, Fx, y, beg + (int)(len * k / pieces), beg + (int)(len * (k + 1) / pieces), lane, acc);
-        double mine = acc[0];
+    // the diagonal block, loaded now and stored to LDS after the pull (up to four per thread)
+    double dv[4];
+    {
+        const int *cb = a.sn_cb + s0;
 #pragma unroll
-        for (int r = 1; r < NR; r++)
-            if (lane == r) mine = acc[r];
-        if (lane < NR) part[t][lane] = mine;
+        for (int u = 0; u < 4; u++) {
+            const int e = threadIdx.x + u * kSnSolveWG;
+            dv[u] = e < w * w ? (double)Fx[cb[e / w] + e % w] : 0.0;
+        }
     }
-    __syncthreads();
+    const int4 *rr = reinterpret_cast<const int4 *>(runs);
     double sum[NR];
 #pragma unroll
     for (int r = 0; r < NR; r++) sum[r] = 0.0;
-    if (wv == 0 && lane < w)
-        for (int q = 0; q < Q; q++) {
+    for (int q0 = ur.x + wv; q0 < ur.y; q0 += 4 * kSnSolveWaves) {   // uniform per wavefront
+        int4 g[4];
 #pragma unroll
-            for (int r = 0; r < NR; r++) sum[r] += part[lane * Q + q][r];
+        for (int u = 0; u < 4; u++) {
+            const int q = q0 + u * kSnSolveWaves;
+            g[u] = q < ur.y ? rr[q] : make_int4(0, 0, 0, 0);
         }
+        double lv[4], yv[4][NR];
+        bool on[4];
+#pragma unroll
+        for (int u = 0; u < 4; u++) {
+            const int c = lane - g[u].z;
+            on[u] = c >= 0 && c < g[u].w;
+            lv[u] = on[u] ? (double)Fx[g[u].y + c] : 0.0;
+#pragma unroll
+            for (int r = 0; r < NR; r++) yv[u][r] = g[u].w > 0 ? y[(size_t)g[u].x * YS + r] : 0.0;
+        }
+#pragma unroll
+        for (int u = 0; u < 4; u++)
+            if (on[u]) {
+#pragma unroll
+                for (int r = 0; r < NR; r++) sum[r] = fma(lv[u], yv[u][r], sum[r]);
+            }
+    }
+    // the sixteen wavefronts' sums: v + 8 into v, then v + 4 into v, ... (a fixed tree)
+    for (int h = kSnSolveWaves / 2; h >= 1; h >>= 1) {
+        if (wv >= h && wv < 2 * h) {
+#pragma unroll
+            for (int r = 0; r < NR; r++) wsum[wv - h][r][lane] = sum[r];
+        }
+        __syncthreads();
+        if (wv < h) {
+#pragma unroll
+            for (int r = 0; r < NR; r++) sum[r] += wsum[wv][r][lane];
+        }
+        __syncthreads();
+    }
     if (un.z > 1) {
         double *blk = a.sn_part + ((size_t)un.w * a.batch + inst) * 512;
         const size_t bstride = (size_t)a.batch * 512;
@@ -808,13 +840,10 @@ __global__ __launch_bounds__(kSnSolveWG) void sn_solve_kernel(SolveArgs a, const
             red[h][v] = acc;
         }
     }
-    // the diagonal block into LDS by every thread (one round of loads), read by the triangle
-    {
-        const int *cb = a.sn_cb + s0;
-        for (int e = threadIdx.x; e < w * w; e += kSnSolveWG) {
-            const int cc = e / w, r = e - cc * w;
-            tri[cc][r] = (double)Fx[cb[cc] + r];
-        }
+#pragma unroll
+    for (int u = 0; u < 4; u++) {
+        const int e = threadIdx.x + u * kSnSolveWG;
+        if (e < w * w) tri[e / w][e % w] = dv[u];
     }
     __syncthreads();
     if (wv != 0) return;
@@ -829,8 +858,9 @@ __global__ __launch_bounds__(kSnSolveWG) void sn_solve_kernel(SolveArgs a, const
 }
 
 template <bool UPPER>
-static int launch_sn_solve_impl(const SolveArgs &a, const int *seq, const int *units, int sbeg, int stiny, int smid,
-                                int ubeg, int uend, int *cnt, void *stream) {
+static int launch_sn_solve_impl(const SolveArgs &a, const int *seq, const int *units, const int *urange,
+                                const int *runs, int sbeg, int stiny, int smid, int ubeg, int uend, int *cnt,
+                                void *stream) {
     const int64_t ntb = ((int64_t)(stiny - sbeg) * a.batch + kSnSolveWG / 16 - 1) / (kSnSolveWG / 16);
     const int64_t nsw = ntb + ((int64_t)(smid - stiny) * a.batch + kSnSolveWaves - 1) / kSnSolveWaves;
     const int64_t units_n = nsw + (int64_t)(uend - ubeg) * a.batch;
@@ -841,10 +871,10 @@ static int launch_sn_solve_impl(const SolveArgs &a, const int *seq, const int *u
     case NRV:                                                                                           \
         if (a.fp32)                                                                                     \
             hipLaunchKernelGGL((sn_solve_kernel<float, NRV, UPPER>), grid, dim3(kSnSolveWG), 0, st, a, seq, units, \
-                               sbeg, stiny, smid, ubeg, cnt);                                           \
+                               urange, runs, sbeg, stiny, smid, ubeg, cnt);                             \
         else                                                                                            \
             hipLaunchKernelGGL((sn_solve_kernel<double, NRV, UPPER>), grid, dim3(kSnSolveWG), 0, st, a, seq, units, \
-                               sbeg, stiny, smid, ubeg, cnt);                                           \
+                               urange, runs, sbeg, stiny, smid, ubeg, cnt);                             \
         break;
     switch (a.nrhs) {
         CKTLU_SNS_CASE(1)
@@ -857,13 +887,13 @@ static int launch_sn_solve_impl(const SolveArgs &a, const int *seq, const int *u
     return (int)hipGetLastError();
 }
 
-int launch_sn_lsolve(const SolveArgs &a, const int *seq, const int *units, int sbeg, int stiny, int smid, int ubeg,
-                     int uend, int *cnt, void *stream) {
-    return launch_sn_solve_impl<false>(a, seq, units, sbeg, stiny, smid, ubeg, uend, cnt, stream);
+int launch_sn_lsolve(const SolveArgs &a, const int *seq, const int *units, const int *urange, const int *runs, int sbeg,
+                     int stiny, int smid, int ubeg, int uend, int *cnt, void *stream) {
+    return launch_sn_solve_impl<false>(a, seq, units, urange, runs, sbeg, stiny, smid, ubeg, uend, cnt, stream);
 }
-int launch_sn_usolve(const SolveArgs &a, const int *seq, const int *units, int sbeg, int stiny, int smid, int ubeg,
-                     int uend, int *cnt, void *stream) {
-    return launch_sn_solve_impl<true>(a, seq, units, sbeg, stiny, smid, ubeg, uend, cnt, stream);
+int launch_sn_usolve(const SolveArgs &a, const int *seq, const int *units, const int *urange, const int *runs, int sbeg,
+                     int stiny, int smid, int ubeg, int uend, int *cnt, void *stream) {
+    return launch_sn_solve_impl<true>(a, seq, units, urange, runs, sbeg, stiny, smid, ubeg, uend, cnt, stream);
 }
 
 // A run of narrow levels [l0, l1): one workgroup per instance takes the rows of a

@@ -44,8 +44,9 @@ static int choose_tail(const Factor &f, const cktlu_options &opt) {
 // update tasks of at least this many multiply-adds get a workgroup (four wavefronts)
 constexpr double kHeavyTask = 16384.0;
 // supernodal solves: a singleton whose row pulls at least kSolveLongRow entries gets a
-// workgroup; a supernode's pull is split into slices of about kSolvePullChunk entries (the
-// default of options.solve_split_entries; at most kSolveMaxSplit slices), one workgroup each
+// workgroup; a supernode's pull, as runs of rows present in one column, is split into units of
+// kSolvePullChunk / 64 runs (the default of options.solve_split_entries; a run counts as a
+// wavefront's 64 entries; at most kSolveMaxSplit units), one workgroup each
 constexpr int64_t kSolveLongRow = 1024;
 constexpr int64_t kSolveTinyRow = 32;      // singletons with this many entries at most: 16 lanes
 constexpr int64_t kSolvePullChunk = 8192;
@@ -373,9 +374,10 @@ static void build_supernodal(const Factor &f, Schedule &s, int T, int wmax, int 
     // ---- solve levels over the supernodes.  L: the rows of S reach column j < s0 through
     // L(i, j); U: the rows of S reach column k >= s1 through U(i, k) (k < T: dense columns are
     // solved before the sparse U rows)
+    std::vector<int> lastc(n, -2), lastpos(n, -2), recidx(n, 0);
     auto solve_levels = [&](bool upper, int &nlev, std::vector<int> &lvl, std::vector<int> &tiny,
                             std::vector<int> &single, std::vector<int> &seq, std::vector<int> &unit,
-                            std::vector<int> &ulvl, int &nscr) {
+                            std::vector<int> &urange, std::vector<int> &runs, std::vector<int> &ulvl, int &nscr) {
         std::vector<int> lv(nsn, 0);
         std::vector<int64_t> pull(nsn, 0);            // entries outside the diagonal block
         nlev = nsn ? 1 : 0;
@@ -425,28 +427,61 @@ static void build_supernodal(const Factor &f, Schedule &s, int T, int wmax, int 
         }
         seq.resize(nsn);
         for (int S = 0; S < nsn; S++) seq[f[kind(S)][lv[S]]++] = S;
-        // units: a supernode whose pull exceeds pull_chunk entries is split into P units that
-        // pull a 1/P slice of every row; their partial sums meet in scratch blocks (P per
+        // the pull of a workgroup supernode S as runs {column j, position of its first entry,
+        // first row c_a, rows}: rows s0 + c_a .. s0 + c_a + rows - 1 of S all present in column
+        // j (their entries are consecutive in j's storage, rows being sorted); a run per column
+        // unless its rows of S have a gap.  The runs are cut into P units of at most
+        // pull_chunk / 64 runs each; P > 1 units' partial sums meet in scratch blocks (P per
         // supernode, numbered within the level) and the last unit to finish solves the triangle
+        const int64_t per_unit = std::max<int64_t>(1, pull_chunk / 64);
         unit.clear();
+        urange.clear();
+        runs.clear();
         ulvl.assign(nlev + 1, 0);
         nscr = 0;
+        std::vector<int> touched;
         for (int l2 = 0; l2 < nlev; l2++) {
             int blocks = 0;
             for (int q = single[l2]; q < lvl[l2 + 1]; q++) {
                 const int S = seq[q];
-                const int P = (int)std::min<int64_t>(kSolveMaxSplit, std::max<int64_t>(1, (pull[S] + pull_chunk - 1) / pull_chunk));
-                for (int p = 0; p < P; p++) unit.insert(unit.end(), {q, p, P, P > 1 ? blocks : -1});
+                const int a = s0v[S], w = s0v[S + 1] - a;
+                const int64_t r0 = (int64_t)runs.size() / 4;
+                touched.clear();
+                for (int c = 0; c < w; c++) {
+                    const int i = a + c;
+                    const int beg = upper ? s.Urp[i] + (w - 1 - c) : s.Lrp[i];
+                    const int end = upper ? s.Urp[i + 1] : s.Lrp[i + 1] - c;
+                    for (int p = beg; p < end; p++) {
+                        const int j = upper ? s.Urj[p] : s.Lrj[p], pos = upper ? s.Ursrc[p] : s.Lrsrc[p];
+                        if (lastc[j] == c - 1 && lastpos[j] == pos - 1) {
+                            runs[4 * (size_t)recidx[j] + 3]++;
+                        } else {
+                            if (lastc[j] < 0) touched.push_back(j);
+                            recidx[j] = (int)(runs.size() / 4);
+                            runs.insert(runs.end(), {j, pos, c, 1});
+                        }
+                        lastc[j] = c;
+                        lastpos[j] = pos;
+                    }
+                }
+                for (int j : touched) lastc[j] = lastpos[j] = -2;
+                const int64_t r1 = (int64_t)runs.size() / 4, nr = r1 - r0;
+                const int P = (int)std::min<int64_t>(kSolveMaxSplit, std::max<int64_t>(1, (nr + per_unit - 1) / per_unit));
+                for (int p = 0; p < P; p++) {
+                    unit.insert(unit.end(), {q, p, P, P > 1 ? blocks : -1});
+                    urange.insert(urange.end(), {(int)(r0 + nr * p / P), (int)(r0 + nr * (p + 1) / P)});
+                }
                 if (P > 1) blocks += P;
             }
             ulvl[l2 + 1] = (int)(unit.size() / 4);
             nscr = std::max(nscr, blocks);
         }
     };
-    solve_levels(false, s.snl_levels, s.snl_lvl, s.snl_tiny, s.snl_single, s.snl_seq, s.snl_unit, s.snl_ulvl,
-                 s.snl_nscr);
-    solve_levels(true, s.snu_levels, s.snu_lvl, s.snu_tiny, s.snu_single, s.snu_seq, s.snu_unit, s.snu_ulvl,
-                 s.snu_nscr);
+    solve_levels(false, s.snl_levels, s.snl_lvl, s.snl_tiny, s.snl_single, s.snl_seq, s.snl_unit, s.snl_urange,
+                 s.snl_runs, s.snl_ulvl, s.snl_nscr);
+    solve_levels(true, s.snu_levels, s.snu_lvl, s.snu_tiny, s.snu_single, s.snu_seq, s.snu_unit, s.snu_urange,
+                 s.snu_runs, s.snu_ulvl, s.snu_nscr);
+    // (runs never outnumber the entries, which the int row pointers index)
     // ---- slot map: where each row of R lands in the target column (struct R is inside it)
     s.sn_map.resize((size_t)moff);
     auto fill = [&](int64_t i0, int64_t i1) {
