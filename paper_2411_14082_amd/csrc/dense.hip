@@ -718,158 +718,123 @@ __global__ __launch_bounds__(64) void dlu_inverse_kernel(DenseArgs a) {
 }
 
 // ------------------------------------------------------------- dense solves
-// y rows T.. of each instance hold the partial solution (YS doubles per row).
-// Lower, unit diagonal: launch b applies block b-1 to rows >= b*NB (a row per
-// thread, 256-row chunks per workgroup); workgroup 0, which updated the rows of
-// block b itself, then solves block b.
-template <typename T, int NR>
-__global__ __launch_bounds__(256) void dtrsv_lower_kernel(DenseArgs a, double *y, int b, const int *skip) {
-    __shared__ double yb[NB][NR];
-    __shared__ double tri[NB][NB + 1];                // tri[col][row] of the diagonal block
+// y rows T.. of each instance hold the partial solution (YS doubles per row).  Launch b of a
+// triangle applies one solved block to the rows that still need it and solves the next
+// diagonal block.  A workgroup takes 64 rows, its four wavefronts a quarter of the applied
+// block's 64 columns each (a row per lane, sixteen loads in flight); the quarters' sums meet in
+// LDS in quarter order.  Workgroup 0 holds exactly the rows of the block it then solves: it
+// keeps their updated values in LDS and multiplies them by the block's inverse (made at
+// factorization time), again a quarter of the columns per wavefront.
+// Lower, unit diagonal: launch b applies block b-1 to rows >= b*NB and solves block b.
+// Upper with its diagonal: launch b applies block blk+1 (blk = nblk-1-b) to the rows above it
+// and solves block blk.
+template <typename T, int NR, bool UPPER>
+__global__ __launch_bounds__(256) void dtrsv_kernel(DenseArgs a, double *y, int b, const int *skip) {
+    __shared__ double yb[NB][NR];                     // the applied block's x, then the solved block's rows
+    __shared__ double part[4][NR][NB];                // the quarters' sums, [quarter][rhs][row]
+    __shared__ double tri[NB][NB + 1];                // tri[col][row] of the diagonal block's inverse
     const int inst = blockIdx.y;
     if (skip && skip[inst] != -1) return;
     const T *S = inst_S<T>(a, inst);
     double *yt = y + ((size_t)inst * a.n + a.T) * YS;
-    const int D = a.D, tid = threadIdx.x;
-    const int p = b * NB, nb = min(NB, D - p);
-    // workgroup 0: the inverse of block b's unit-lower triangle (made at factorization time),
-    // loaded before the rectangle
-    const double *inv = a.Dinv + ((size_t)inst * ((D + NB - 1) / NB) + b) * 2 * NB * NB;   // [col][row]
-    double t[16];
-    if (blockIdx.x == 0) {
-#pragma unroll
-        for (int u = 0; u < 16; u++) t[u] = inv[tid + 256 * u];
-    }
-    if (b > 0) {
-        const int pb = (b - 1) * NB;
-        if (tid < NB * NR / 2) {                      // NB * NR <= 512: two loads per thread
-            const double y0 = yt[(size_t)(pb + tid / NR) * YS + tid % NR];
-            const int e1 = tid + NB * NR / 2;
-            const double y1 = yt[(size_t)(pb + e1 / NR) * YS + e1 % NR];
-            yb[tid / NR][tid % NR] = y0;
-            yb[e1 / NR][e1 % NR] = y1;
-        }
-        __syncthreads();
-        const int i = b * NB + blockIdx.x * 256 + tid;
-        if (i < D) {
-            double acc[NR];
-#pragma unroll
-            for (int r = 0; r < NR; r++) acc[r] = 0.0;
-            for (int m = 0; m < NB; m++) {
-                const double l = (double)S[(size_t)(pb + m) * D + i];
-#pragma unroll
-                for (int r = 0; r < NR; r++) acc[r] += l * yb[m][r];
-            }
-#pragma unroll
-            for (int r = 0; r < NR; r++) yt[(size_t)i * YS + r] -= acc[r];
-        }
-        __syncthreads();
-    }
-    if (blockIdx.x != 0) return;
-    // block b: y_b = L_bb^-1 y_b (a row per lane, the block's values read from LDS by broadcast)
-    if (tid < NB * NR / 2) {
-        const int e1 = tid + NB * NR / 2;
-        const double y0 = tid / NR < nb ? yt[(size_t)(p + tid / NR) * YS + tid % NR] : 0.0;
-        const double y1 = e1 / NR < nb ? yt[(size_t)(p + e1 / NR) * YS + e1 % NR] : 0.0;
-        yb[tid / NR][tid % NR] = y0;
-        yb[e1 / NR][e1 % NR] = y1;
-    }
-#pragma unroll
-    for (int u = 0; u < 16; u++) tri[(tid + 256 * u) / NB][(tid + 256 * u) % NB] = t[u];
-    __syncthreads();
-    if (tid >= nb) return;
-    double acc[NR];
-#pragma unroll
-    for (int r = 0; r < NR; r++) acc[r] = 0.0;
-    for (int k = 0; k <= tid; k++) {                  // the unit-lower inverse is lower triangular
-        const double l = tri[k][tid];
-#pragma unroll
-        for (int r = 0; r < NR; r++) acc[r] += l * yb[k][r];
-    }
-#pragma unroll
-    for (int r = 0; r < NR; r++) yt[(size_t)(p + tid) * YS + r] = acc[r];
-}
-
-// Upper with its diagonal: launch b handles block blk = nblk-1-b: it applies
-// block blk+1 to every row above it, then workgroup 0 solves block blk.
-template <typename T, int NR>
-__global__ __launch_bounds__(256) void dtrsv_upper_kernel(DenseArgs a, double *y, int b, const int *skip) {
-    __shared__ double yb[NB][NR];
-    __shared__ double tri[NB][NB + 1];                // tri[col][row] of the diagonal block
-    const int inst = blockIdx.y;
-    if (skip && skip[inst] != -1) return;
-    const T *S = inst_S<T>(a, inst);
-    double *yt = y + ((size_t)inst * a.n + a.T) * YS;
-    const int D = a.D, tid = threadIdx.x;
+    const int D = a.D, tid = threadIdx.x, lane = tid & (NB - 1), q = tid / NB;
     const int nblk = (D + NB - 1) / NB;
-    const int blk = nblk - 1 - b;
+    const int blk = UPPER ? nblk - 1 - b : b;         // the block this launch solves
     const int p = blk * NB, nb = min(NB, D - p);
-    // workgroup 0: the inverse of block blk's upper triangle, loaded before the rectangle
-    const double *inv = a.Dinv + ((size_t)inst * nblk + blk) * 2 * NB * NB + NB * NB;   // [col][row]
+    // the applied block (columns [pa, pa + na)) and this workgroup's rows
+    const int pa = UPPER ? (blk + 1) * NB : (blk - 1) * NB;
+    const int na = b > 0 ? min(NB, D - pa) : 0;
+    const int i = UPPER ? p - (int)blockIdx.x * NB + lane : p + (int)blockIdx.x * NB + lane;
+    const bool row = UPPER ? i >= 0 && i < p + nb : i < D;
+    // workgroup 0: the inverse of the diagonal block, loaded before the rectangle
+    const double *inv = a.Dinv + ((size_t)inst * nblk + blk) * 2 * NB * NB + (UPPER ? NB * NB : 0);   // [col][row]
     double t[16];
     if (blockIdx.x == 0) {
 #pragma unroll
         for (int u = 0; u < 16; u++) t[u] = inv[tid + 256 * u];
     }
+    double yi[NR];
+#pragma unroll
+    for (int r = 0; r < NR; r++) yi[r] = q == 0 && row ? yt[(size_t)i * YS + r] : 0.0;
     if (b > 0) {
-        const int pb = (blk + 1) * NB, nbb = min(NB, D - pb);
         if (tid < NB * NR / 2) {                      // NB * NR <= 512: two loads per thread
             const int e1 = tid + NB * NR / 2;
-            const double y0 = tid / NR < nbb ? yt[(size_t)(pb + tid / NR) * YS + tid % NR] : 0.0;
-            const double y1 = e1 / NR < nbb ? yt[(size_t)(pb + e1 / NR) * YS + e1 % NR] : 0.0;
+            const double y0 = tid / NR < na ? yt[(size_t)(pa + tid / NR) * YS + tid % NR] : 0.0;
+            const double y1 = e1 / NR < na ? yt[(size_t)(pa + e1 / NR) * YS + e1 % NR] : 0.0;
             yb[tid / NR][tid % NR] = y0;
             yb[e1 / NR][e1 % NR] = y1;
         }
-        __syncthreads();
-        const int i = pb - 1 - (int)(blockIdx.x * 256 + tid);   // rows above block blk+1, bottom up
-        if (i >= 0) {
-            double acc[NR];
+        double acc[NR];
 #pragma unroll
-            for (int r = 0; r < NR; r++) acc[r] = 0.0;
-            for (int m = 0; m < nbb; m++) {
-                const double u = (double)S[(size_t)(pb + m) * D + i];
+        for (int r = 0; r < NR; r++) acc[r] = 0.0;
+        double l[16];
 #pragma unroll
-                for (int r = 0; r < NR; r++) acc[r] += u * yb[m][r];
-            }
-#pragma unroll
-            for (int r = 0; r < NR; r++) yt[(size_t)i * YS + r] -= acc[r];
+        for (int m = 0; m < 16; m++) {
+            const int c = 16 * q + m;
+            l[m] = row && c < na ? (double)S[(size_t)(pa + c) * D + i] : 0.0;
         }
         __syncthreads();
+#pragma unroll
+        for (int m = 0; m < 16; m++) {
+#pragma unroll
+            for (int r = 0; r < NR; r++) acc[r] = fma(l[m], yb[16 * q + m][r], acc[r]);
+        }
+#pragma unroll
+        for (int r = 0; r < NR; r++) part[q][r][lane] = acc[r];
+        __syncthreads();
+        if (q == 0 && row) {
+#pragma unroll
+            for (int r = 0; r < NR; r++)
+                yi[r] -= ((part[0][r][lane] + part[1][r][lane]) + part[2][r][lane]) + part[3][r][lane];
+            if (blockIdx.x != 0) {
+#pragma unroll
+                for (int r = 0; r < NR; r++) yt[(size_t)i * YS + r] = yi[r];
+            }
+        }
     }
     if (blockIdx.x != 0) return;
-    // block blk: x = U_bb^-1 y
-    if (tid < NB * NR / 2) {
-        const int e1 = tid + NB * NR / 2;
-        const double y0 = tid / NR < nb ? yt[(size_t)(p + tid / NR) * YS + tid % NR] : 0.0;
-        const double y1 = e1 / NR < nb ? yt[(size_t)(p + e1 / NR) * YS + e1 % NR] : 0.0;
-        yb[tid / NR][tid % NR] = y0;
-        yb[e1 / NR][e1 % NR] = y1;
+    // the solved block: x = inverse * (its rows' values), row lane of the block from quarter q's
+    // sixteen columns, the quarters added in order
+    __syncthreads();                                  // yb's last reads (the rectangle) are done
+    if (q == 0) {
+#pragma unroll
+        for (int r = 0; r < NR; r++) yb[lane][r] = lane < nb ? yi[r] : 0.0;
     }
 #pragma unroll
     for (int u = 0; u < 16; u++) tri[(tid + 256 * u) / NB][(tid + 256 * u) % NB] = t[u];
     __syncthreads();
-    if (tid >= nb) return;
     double acc[NR];
 #pragma unroll
     for (int r = 0; r < NR; r++) acc[r] = 0.0;
-    for (int k = tid; k < nb; k++) {                  // the upper inverse is upper triangular
-        const double u = tri[k][tid];
 #pragma unroll
-        for (int r = 0; r < NR; r++) acc[r] += u * yb[k][r];
+    for (int m = 0; m < 16; m++) {
+        const int k = 16 * q + m;                     // the inverse is triangular: zero entries add nothing
+        const bool in = UPPER ? k >= lane : k <= lane;
+        if (in) {
+            const double v = tri[k][lane];
+#pragma unroll
+            for (int r = 0; r < NR; r++) acc[r] = fma(v, yb[k][r], acc[r]);
+        }
     }
 #pragma unroll
-    for (int r = 0; r < NR; r++) yt[(size_t)(p + tid) * YS + r] = acc[r];
+    for (int r = 0; r < NR; r++) part[q][r][lane] = acc[r];
+    __syncthreads();
+    if (q == 0 && lane < nb) {
+#pragma unroll
+        for (int r = 0; r < NR; r++)
+            yt[(size_t)(p + lane) * YS + r] = ((part[0][r][lane] + part[1][r][lane]) + part[2][r][lane]) + part[3][r][lane];
+    }
 }
 
 template <typename T, int NR>
 void dense_solve_impl(const DenseArgs &a, double *y, const int *skip, bool upper, hipStream_t st) {
     const int nblk = (a.D + NB - 1) / NB;
     for (int b = 0; b < nblk; b++) {
-        // rows the launch updates: lower -> rows >= b*NB; upper -> rows above block nblk-b
+        // rows the launch takes: lower -> rows >= b*NB; upper -> rows above block nblk-b
         const int rows = b == 0 ? 1 : (upper ? (nblk - b) * NB : a.D - b * NB);
-        const dim3 g((unsigned)((rows + 255) / 256), (unsigned)a.batch);
-        if (upper) hipLaunchKernelGGL((dtrsv_upper_kernel<T, NR>), g, dim3(256), 0, st, a, y, b, skip);
-        else hipLaunchKernelGGL((dtrsv_lower_kernel<T, NR>), g, dim3(256), 0, st, a, y, b, skip);
+        const dim3 g((unsigned)((rows + NB - 1) / NB), (unsigned)a.batch);
+        if (upper) hipLaunchKernelGGL((dtrsv_kernel<T, NR, true>), g, dim3(256), 0, st, a, y, b, skip);
+        else hipLaunchKernelGGL((dtrsv_kernel<T, NR, false>), g, dim3(256), 0, st, a, y, b, skip);
     }
 }
 
