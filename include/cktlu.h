@@ -113,8 +113,9 @@ typedef struct {
                               split into units of about this many rows (a workgroup each; panels of at most
                               16 columns: half as many rows, a wavefront each), whose column maxima meet
                               for the pivot test; 0 = 256, else 16 .. 65536.  Same results for any value */
-    int solve_split_entries; /* supernodal solves: a supernode whose rows hold more entries outside its
-                              diagonal block than this is split into units of about this many entries (a
+    int solve_split_entries; /* supernodal solves: a supernode pulls its entries outside the diagonal block
+                              as runs (a column and the consecutive rows of the supernode in it); more than
+                              solve_split_entries / 16 runs are split into units of about that many (a
                               workgroup each) whose partial sums are added in a fixed order; 0 = 8192,
                               else 64 .. 2^30.  Sums are grouped differently per value (rounding only) */
 } cktlu_options;

@@ -625,8 +625,9 @@ __device__ __forceinline__ void sn_triangle(Elem elem, double *y, int s0, int w,
 // consecutive rows at consecutive positions of j's storage, so lane c (row s0 + c) reads its
 // entry of the run next to its neighbours' and y_j once per run instead of once per entry.  The
 // supernode's runs are cut into P units, a workgroup of sixteen wavefronts per (unit,
-// instance); wavefront v takes the unit's runs v, v + 16, ... (four in flight) and its lanes
-// add the products to their rows' sums in that order; the sixteen wavefronts' sums meet in LDS
+// instance); wavefront v takes the unit's runs v, v + 16, ... (eight in flight, their solution
+// rows loaded by one instruction and broadcast) and its lanes add the products to their rows'
+// sums in that order; the sixteen wavefronts' sums meet in LDS
 // by a fixed tree.  With P = 1 the workgroup then solves the triangle; with P > 1 each unit
 // stores its row sums in its scratch block and counts its arrival, and the last unit to arrive
 // adds the P blocks (the even units and the odd units in ascending order, by two halves of its
@@ -766,33 +767,33 @@ __global__ __launch_bounds__(kSnSolveWG) void sn_solve_kernel(SolveArgs a, const
             dv[u] = e < w * w ? (double)Fx[cb[e / w] + e % w] : 0.0;
         }
     }
+    // eight runs per round: lanes 0-7 load the runs, lane l then the solution row entry
+    // (l % 8) of run l / 8's column, broadcast by readlane
     const int4 *rr = reinterpret_cast<const int4 *>(runs);
     double sum[NR];
 #pragma unroll
     for (int r = 0; r < NR; r++) sum[r] = 0.0;
-    for (int q0 = ur.x + wv; q0 < ur.y; q0 += 4 * kSnSolveWaves) {   // uniform per wavefront
-        int4 g[4];
+    for (int q0 = ur.x + wv; q0 < ur.y; q0 += 8 * kSnSolveWaves) {   // uniform per wavefront
+        const int qa = q0 + (lane & 7) * kSnSolveWaves;
+        const int4 gl = lane < 8 && qa < ur.y ? rr[qa] : make_int4(0, 0, 0, 0);
+        const int jl = __shfl(gl.x, lane >> 3), nl = __shfl(gl.w, lane >> 3);
+        const double yl = nl > 0 && (lane & 7) < NR ? y[(size_t)jl * YS + (lane & 7)] : 0.0;
+        double lv[8];
+        bool on[8];
 #pragma unroll
-        for (int u = 0; u < 4; u++) {
-            const int q = q0 + u * kSnSolveWaves;
-            g[u] = q < ur.y ? rr[q] : make_int4(0, 0, 0, 0);
-        }
-        double lv[4], yv[4][NR];
-        bool on[4];
-#pragma unroll
-        for (int u = 0; u < 4; u++) {
-            const int c = lane - g[u].z;
-            on[u] = c >= 0 && c < g[u].w;
-            lv[u] = on[u] ? (double)Fx[g[u].y + c] : 0.0;
-#pragma unroll
-            for (int r = 0; r < NR; r++) yv[u][r] = g[u].w > 0 ? y[(size_t)g[u].x * YS + r] : 0.0;
+        for (int u = 0; u < 8; u++) {
+            const int c = lane - __builtin_amdgcn_readlane(gl.z, u);
+            on[u] = c >= 0 && c < __builtin_amdgcn_readlane(gl.w, u);
+            lv[u] = on[u] ? (double)Fx[__builtin_amdgcn_readlane(gl.y, u) + c] : 0.0;
         }
 #pragma unroll
-        for (int u = 0; u < 4; u++)
-            if (on[u]) {
+        for (int u = 0; u < 8; u++) {
 #pragma unroll
-                for (int r = 0; r < NR; r++) sum[r] = fma(lv[u], yv[u][r], sum[r]);
+            for (int r = 0; r < NR; r++) {
+                const double yv = readlane_f64(yl, 8 * u + r);
+                if (on[u]) sum[r] = fma(lv[u], yv, sum[r]);
             }
+        }
     }
     // the sixteen wavefronts' sums: v + 8 into v, then v + 4 into v, ... (a fixed tree)
     for (int h = kSnSolveWaves / 2; h >= 1; h >>= 1) {

@@ -45,8 +45,8 @@ static int choose_tail(const Factor &f, const cktlu_options &opt) {
 constexpr double kHeavyTask = 16384.0;
 // supernodal solves: a singleton whose row pulls at least kSolveLongRow entries gets a
 // workgroup; a supernode's pull, as runs of rows present in one column, is split into units of
-// kSolvePullChunk / 64 runs (the default of options.solve_split_entries; a run counts as a
-// wavefront's 64 entries; at most kSolveMaxSplit units), one workgroup each
+// kSolvePullChunk / 16 runs (the default of options.solve_split_entries; a run counts as 16
+// entries; at most kSolveMaxSplit units), one workgroup each
 constexpr int64_t kSolveLongRow = 1024;
 constexpr int64_t kSolveTinyRow = 32;      // singletons with this many entries at most: 16 lanes
 constexpr int64_t kSolvePullChunk = 8192;
@@ -431,9 +431,9 @@ static void build_supernodal(const Factor &f, Schedule &s, int T, int wmax, int 
         // first row c_a, rows}: rows s0 + c_a .. s0 + c_a + rows - 1 of S all present in column
         // j (their entries are consecutive in j's storage, rows being sorted); a run per column
         // unless its rows of S have a gap.  The runs are cut into P units of at most
-        // pull_chunk / 64 runs each; P > 1 units' partial sums meet in scratch blocks (P per
+        // pull_chunk / 16 runs each; P > 1 units' partial sums meet in scratch blocks (P per
         // supernode, numbered within the level) and the last unit to finish solves the triangle
-        const int64_t per_unit = std::max<int64_t>(1, pull_chunk / 64);
+        const int64_t per_unit = std::max<int64_t>(1, pull_chunk / 16);
         unit.clear();
         urange.clear();
         runs.clear();

@@ -775,7 +775,7 @@ def test_supernodal_sweep_vs_oracle(ck, oracle_mod, name, make, width, tail):
 @pytest.mark.parametrize("name,make", SN_CASES, ids=[c[0] for c in SN_CASES])
 def test_supernodal_split_units_vs_oracle(ck, oracle_mod, name, make, tail):
     """Panels split into units of 16 rows (8 for panels of at most 16 columns) and supernodal
-    solves split into units of 64 entries, so that the arrival counters and the slice
+    solves split into units of four runs (solve_split_entries = 64), so that the arrival counters and the slice
     combines run on small circuits: the factors equal those of the unsplit schedule bit for
     bit (splitting rows of R changes no operation), pattern and pivots equal the oracle's,
     the solutions reach eta <= 1e-12 (FP64; 1e-10 refined from FP32 factors, one and eight
