@@ -43,6 +43,7 @@ static int choose_tail(const Factor &f, const cktlu_options &opt) {
 
 // update tasks of at least this many multiply-adds get a workgroup (four wavefronts)
 constexpr double kHeavyTask = 16384.0;
+constexpr int kHeavyRows = 384;          // a task with an item of this many rows of R is heavy too
 // supernodal solves: a singleton whose row pulls at least kSolveLongRow entries gets a
 // workgroup; a supernode's pull, as runs of rows present in one column, is split into units of
 // kSolvePullChunk / 16 runs (the default of options.solve_split_entries; a run counts as 16
@@ -227,7 +228,8 @@ static void build_supernodal(const Factor &f, Schedule &s, int T, int wmax, int 
     if (!s.sn_task.empty()) s.sn_task[s.sn_task.size() - 1] = (int)nitems;
     s.sn_moff[nitems] = moff;
     for (int q = 0; q < nl; q++) s.sn_task_lvl[q + 1] += s.sn_task_lvl[q];
-    // inside each level: heavy tasks (rows of R times suffix rows at least kHeavyTask) first, a
+    // inside each level: heavy tasks (rows of R times suffix rows at least kHeavyTask, or an
+    // item with at least kHeavyRows rows of R: its rows split over four wavefronts) first, a
     // workgroup each; then light tasks, a wavefront each; then tiny tasks (every item at most
     // kTinyRows suffix rows and rows of R), sixteen lanes each.  The order of tasks does not
     // change results
@@ -241,12 +243,14 @@ static void build_supernodal(const Factor &f, Schedule &s, int T, int wmax, int 
             for (int t = t0; t < t1; t++) {
                 double cost = 0;
                 bool small = true;
+                int rows = 0;
                 for (int it2 = s.sn_task[4 * (size_t)t + 2]; it2 < s.sn_task[4 * (size_t)t + 3]; it2++) {
                     cost += (double)s.sn_item[4 * (size_t)it2 + 3] * s.sn_item[4 * (size_t)it2 + 2];
+                    rows = std::max(rows, s.sn_item[4 * (size_t)it2 + 3]);
                     small = small && s.sn_item[4 * (size_t)it2 + 2] <= cktlu_dev::kTinyRows &&
                             s.sn_item[4 * (size_t)it2 + 3] <= cktlu_dev::kTinyRows;
                 }
-                (cost >= kHeavyTask ? heavy : small ? tiny : light).push_back(t);
+                (cost >= kHeavyTask || rows >= kHeavyRows ? heavy : small ? tiny : light).push_back(t);
             }
             s.sn_task_heavy[q] = t0 + (int)heavy.size();
             s.sn_task_tiny[q] = t0 + (int)(heavy.size() + light.size());
