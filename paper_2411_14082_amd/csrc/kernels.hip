@@ -562,8 +562,9 @@ __device__ __forceinline__ double readlane_f64(double v, int l) {
 
 // The dense triangle of supernode [s0, s0 + w) in one wavefront, lane c holding row s0 + c with
 // t = its right-hand sides minus the pulled sums: L: y_c -= L(c, c') y_c' for c' < c in
-// ascending c' (unit diagonal); U: x_c = t_c / U(c, c) in descending c, then
-// t_c'' -= U(c'', c) x_c for c'' < c.  The triangle's entries come from the factor columns
+// ascending c' (unit diagonal); U: x_c = t_c * (1 / U(c, c)) in descending c (the reciprocals
+// formed by all lanes at once before the chain, not a division per step and right-hand side),
+// then t_c'' -= U(c'', c) x_c for c'' < c.  The triangle's entries come from the factor columns
 // (sn_cb: offset of the supernode's first row in each column); the results go to y.
 // elem(c, r): the diagonal block's entry in column c, row r (both local to the supernode)
 template <typename T, int NR, bool UPPER, typename Elem>
@@ -589,22 +590,23 @@ __device__ __forceinline__ void sn_triangle(Elem elem, double *y, int s0, int w,
             }
         }
     } else {
+        const double rdiag = lane < w ? 1.0 / elem(lane, lane) : 1.0;
         for (int c0 = w - 1; c0 >= 0; c0 -= 8) {
-            double lv[8], dg[8];
+            double lv[8];
 #pragma unroll
             for (int u = 0; u < 8; u++) {
                 const int c = c0 - u;
                 lv[u] = (c >= 0 && lane < c) ? elem(c, lane) : 0.0;
-                dg[u] = c >= 0 ? elem(c, c) : 1.0;
             }
 #pragma unroll
             for (int u = 0; u < 8; u++) {
                 const int c = c0 - u;
                 if (c >= 0) {
+                    const double rd = readlane_f64(rdiag, c);
 #pragma unroll
                     for (int r = 0; r < NR; r++) {
-                        if (lane == c) t[r] = t[r] / dg[u];
-                        const double xc = readlane_f64(t[r], c);
+                        const double xc = readlane_f64(t[r], c) * rd;
+                        if (lane == c) t[r] = xc;
                         if (lane < c) t[r] = fma(-lv[u], xc, t[r]);
                     }
                 }
