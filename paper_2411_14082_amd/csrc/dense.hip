@@ -1323,22 +1323,22 @@ __global__ __launch_bounds__(kSnPanelWaves * WAVE) void sn_panel_kernel(Refactor
 }
 
 // U(S, k) = L11^-1 x_k(S) on the suffix of S's rows present in k (len rows; lane c holds row
-// c), sixteen L11 loads in flight; returns this lane's value.  cbv: lane c holds the storage
+// c), eight L11 loads in flight; returns this lane's value.  cbv: lane c holds the storage
 // offset of the suffix's column c (read by readlane, no dependent load).
 template <typename T>
 __device__ __forceinline__ T sn_suffix_solve(const T *Fx, const T *xk, int cbv, int slot0, int off, int len,
                                              int lane) {
     T xv = lane < len ? xk[slot0 + lane] : T(0);
-    for (int c0 = 0; c0 < len; c0 += 16) {
-        T lv[16];
+    for (int c0 = 0; c0 < len; c0 += 8) {
+        T lv[8];
 #pragma unroll
-        for (int u = 0; u < 16; u++) {
+        for (int u = 0; u < 8; u++) {
             const int c = c0 + u;
             const int base = __builtin_amdgcn_readlane(cbv, c < len ? c : 0);
             lv[u] = (c < len && lane > c && lane < len) ? Fx[base + off + lane] : T(0);
         }
 #pragma unroll
-        for (int u = 0; u < 16; u++) {
+        for (int u = 0; u < 8; u++) {
             const int c = c0 + u;
             if (c < len) {
                 const T uc = readlane(xv, c);
@@ -1350,7 +1350,7 @@ __device__ __forceinline__ T sn_suffix_solve(const T *Fx, const T *xk, int cbv, 
 }
 
 // Sums over the suffix's columns [c_lo, c_hi) of L21(row, c) u_c for the rows r0 + lane and
-// r0 + 64 + lane of R (two rows per lane, thirty-two loads in flight).  u_c comes from get(c)
+// r0 + 64 + lane of R (two rows per lane, sixteen loads in flight).  u_c comes from get(c)
 // (a readlane or an LDS read), the column offsets from cbv as above.
 template <typename T, typename GetU>
 __device__ __forceinline__ void sn_rows_partial(const T *Fx, int cbv, int w, int c_lo, int c_hi, int mcnt, int r0,
@@ -1359,17 +1359,17 @@ __device__ __forceinline__ void sn_rows_partial(const T *Fx, int cbv, int w, int
     const bool ina = ra < mcnt, inb = rb < mcnt;
     acca = T(0);
     accb = T(0);
-    for (int c0 = c_lo; c0 < c_hi; c0 += 16) {
-        T la[16], lb[16];
+    for (int c0 = c_lo; c0 < c_hi; c0 += 8) {
+        T la[8], lb[8];
 #pragma unroll
-        for (int u = 0; u < 16; u++) {
+        for (int u = 0; u < 8; u++) {
             const int c = c0 + u;
             const int base = __builtin_amdgcn_readlane(cbv, c < c_hi ? c : c_lo) + w;
             la[u] = (ina && c < c_hi) ? Fx[base + ra] : T(0);
             lb[u] = (inb && c < c_hi) ? Fx[base + rb] : T(0);
         }
 #pragma unroll
-        for (int u = 0; u < 16; u++)
+        for (int u = 0; u < 8; u++)
             if (c0 + u < c_hi) {
                 const T uc = get(c0 + u);
                 acca = fma(la[u], uc, acca);
@@ -1454,17 +1454,17 @@ __device__ void sn_heavy_group(const RefactorArgs &a, int inst, int g, T (*us)[W
                 T acca[kGroupTargets], accb[kGroupTargets];
 #pragma unroll
                 for (int j = 0; j < kGroupTargets; j++) acca[j] = accb[j] = T(0);
-                for (int c0 = offmin; c0 < w; c0 += 16) {
-                    T la[16], lb[16];
+                for (int c0 = offmin; c0 < w; c0 += 8) {
+                    T la[8], lb[8];
 #pragma unroll
-                    for (int u = 0; u < 16; u++) {
+                    for (int u = 0; u < 8; u++) {
                         const int c = c0 + u;
                         const int base = __builtin_amdgcn_readlane(cbv, c < w ? c : offmin) + w;
                         la[u] = (ina && c < w) ? Fx[base + ra] : T(0);
                         lb[u] = (inb && c < w) ? Fx[base + rb] : T(0);
                     }
 #pragma unroll
-                    for (int u = 0; u < 16; u++) {
+                    for (int u = 0; u < 8; u++) {
                         const int c = c0 + u;
                         if (c < w) {
 #pragma unroll
