@@ -1445,8 +1445,13 @@ __device__ void sn_heavy_group(const RefactorArgs &a, int inst, int g, T (*us)[W
             const int4 src = gsrc[sr];
             const int4 rec = reinterpret_cast<const int4 *>(a.sn_rec)[src.x];
             const int w = rec.y, ns = src.z, mcnt = src.w, e0 = src.y - e_lo;
+            int ej[kGroupTargets];                       // first suffix column per target (w: none)
             int offmin = w;
-            for (int j = 0; j < ns; j++) offmin = min(offmin, eoff[e0 + j]);
+#pragma unroll
+            for (int j = 0; j < kGroupTargets; j++) {
+                ej[j] = j < ns ? eoff[e0 + j] : w;
+                offmin = min(offmin, ej[j]);
+            }
             const int cbv = lane < w ? a.sn_cb[rec.x + lane] : 0;   // S's columns
             for (int r0 = 2 * WAVE * wv; r0 < mcnt; r0 += 8 * WAVE) {
                 const int ra = r0 + lane, rb = r0 + WAVE + lane;
@@ -1469,7 +1474,7 @@ __device__ void sn_heavy_group(const RefactorArgs &a, int inst, int g, T (*us)[W
                         if (c < w) {
 #pragma unroll
                             for (int j = 0; j < kGroupTargets; j++)
-                                if (j < ns && c >= eoff[e0 + j]) {
+                                if (c >= ej[j]) {
                                     const T uc = us[e0 + j][c];
                                     acca[j] = fma(la[u], uc, acca[j]);
                                     accb[j] = fma(lb[u], uc, accb[j]);
