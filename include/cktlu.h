@@ -114,10 +114,11 @@ typedef struct {
                               16 columns: half as many rows, a wavefront each), whose column maxima meet
                               for the pivot test; 0 = 256, else 16 .. 65536.  Same results for any value */
     int solve_split_entries; /* supernodal solves: a supernode pulls its entries outside the diagonal block
-                              as runs (a column and the consecutive rows of the supernode in it); more than
-                              solve_split_entries / 16 runs are split into units of about that many (a
-                              workgroup each) whose partial sums are added in a fixed order; 0 = 8192,
-                              else 64 .. 2^30.  Sums are grouped differently per value (rounding only) */
+                              as runs (a column and the consecutive rows of the supernode in it), split into
+                              units (a workgroup each) whose partial sums are added in a fixed order; a
+                              level's units hold its runs / 128, clamped to solve_split_entries / 64 ..
+                              solve_split_entries / 16 runs; 0 = 8192, else 64 .. 2^30.  Sums are grouped
+                              differently per value (rounding only) */
 } cktlu_options;
 
 typedef struct {

@@ -46,8 +46,8 @@ constexpr double kHeavyTask = 16384.0;
 constexpr int kHeavyRows = 384;          // a task with an item of this many rows of R is heavy too
 // supernodal solves: a singleton whose row pulls at least kSolveLongRow entries gets a
 // workgroup; a supernode's pull, as runs of rows present in one column, is split into units of
-// kSolvePullChunk / 16 runs (the default of options.solve_split_entries; a run counts as 16
-// entries; at most kSolveMaxSplit units), one workgroup each
+// kSolvePullChunk / 64 to kSolvePullChunk / 16 runs (the default of options.solve_split_entries;
+// at most kSolveMaxSplit units), one workgroup each
 constexpr int64_t kSolveLongRow = 1024;
 constexpr int64_t kSolveTinyRow = 32;      // singletons with this many entries at most: 16 lanes
 constexpr int64_t kSolvePullChunk = 8192;
@@ -434,22 +434,27 @@ static void build_supernodal(const Factor &f, Schedule &s, int T, int wmax, int 
         // the pull of a workgroup supernode S as runs {column j, position of its first entry,
         // first row c_a, rows}: rows s0 + c_a .. s0 + c_a + rows - 1 of S all present in column
         // j (their entries are consecutive in j's storage, rows being sorted); a run per column
-        // unless its rows of S have a gap.  The runs are cut into P units of at most
-        // pull_chunk / 16 runs each; P > 1 units' partial sums meet in scratch blocks (P per
-        // supernode, numbered within the level) and the last unit to finish solves the triangle
-        const int64_t per_unit = std::max<int64_t>(1, pull_chunk / 16);
+        // unless its rows of S have a gap.  The runs are cut into P units; P > 1 units' partial
+        // sums meet in scratch blocks (P per supernode, numbered within the level) and the last
+        // unit to finish solves the triangle.  Units hold up to pull_chunk / 16 runs, fewer (down
+        // to pull_chunk / 64) on a level with few runs, whose time is its units' chain, not
+        // their number: the level's runs / 128, clamped to that range
+        const int64_t unit_max = std::max<int64_t>(1, pull_chunk / 16);
+        const int64_t unit_min = std::max<int64_t>(1, pull_chunk / 64);
         unit.clear();
         urange.clear();
         runs.clear();
         ulvl.assign(nlev + 1, 0);
         nscr = 0;
         std::vector<int> touched;
+        std::vector<int64_t> rbeg;
         for (int l2 = 0; l2 < nlev; l2++) {
             int blocks = 0;
+            rbeg.clear();
             for (int q = single[l2]; q < lvl[l2 + 1]; q++) {
                 const int S = seq[q];
                 const int a = s0v[S], w = s0v[S + 1] - a;
-                const int64_t r0 = (int64_t)runs.size() / 4;
+                rbeg.push_back((int64_t)runs.size() / 4);
                 touched.clear();
                 for (int c = 0; c < w; c++) {
                     const int i = a + c;
@@ -469,7 +474,11 @@ static void build_supernodal(const Factor &f, Schedule &s, int T, int wmax, int 
                     }
                 }
                 for (int j : touched) lastc[j] = lastpos[j] = -2;
-                const int64_t r1 = (int64_t)runs.size() / 4, nr = r1 - r0;
+            }
+            rbeg.push_back((int64_t)runs.size() / 4);
+            const int64_t per_unit = std::min(unit_max, std::max(unit_min, (rbeg.back() - rbeg.front() + 127) / 128));
+            for (int q = single[l2]; q < lvl[l2 + 1]; q++) {
+                const int64_t r0 = rbeg[q - single[l2]], nr = rbeg[q - single[l2] + 1] - r0;
                 const int P = (int)std::min<int64_t>(kSolveMaxSplit, std::max<int64_t>(1, (nr + per_unit - 1) / per_unit));
                 for (int p = 0; p < P; p++) {
                     unit.insert(unit.end(), {q, p, P, P > 1 ? blocks : -1});
