@@ -1530,9 +1530,11 @@ __global__ __launch_bounds__(256) void sn_update_kernel(RefactorArgs a, int lev,
         inst = (int)(wid % batch);
         t = theavy + (int)(wid / batch);
     } else {
-        // tiny tasks (every item at most kTinyRows suffix rows and rows of R): sixteen lanes
-        // each, the same operations in the same order as a wavefront's: the suffix solve with
-        // lane c holding suffix row c, then a row of R per lane
+        // tiny tasks (every item at most kTinyRows suffix rows and kTinyRowsR rows of R):
+        // sixteen lanes each, the same operations in the same order as a wavefront's: the
+        // suffix solve with lane c holding suffix row c, then two rows of R per lane and pass.
+        // Lane c holds the suffix's column c offset (shuffled, not re-read); eight columns'
+        // loads go out before their multiply-adds
         const unsigned ntiny = gridDim.x - nheavy - nlight;
         const unsigned gid = xcd_contiguous(bid - nheavy - nlight, ntiny) * 16 + threadIdx.x / 16;
         if (gid >= (unsigned)(tend - ttiny) * batch) return;
@@ -1546,21 +1548,56 @@ __global__ __launch_bounds__(256) void sn_update_kernel(RefactorArgs a, int lev,
             const int4 item = reinterpret_cast<const int4 *>(a.sn_item)[it];
             const int4 rec = reinterpret_cast<const int4 *>(a.sn_rec)[item.x];
             const int w = rec.y, len = item.z, off = w - len, mcnt = item.w;
-            const int *cb = a.sn_cb + rec.x + off;        // the suffix's columns
+            const int cbl = l16 < len ? a.sn_cb[rec.x + off + l16] : 0;   // the suffix's columns
+            const int *mp = a.sn_map + a.sn_moff[it];
             T xv = l16 < len ? xk[item.y + l16] : T(0);
-            for (int c = 0; c < len - 1; c++) {
-                const T uc = __shfl(xv, c, 16);
-                if (l16 > c && l16 < len) xv = fma(-Fx[cb[c] + off + l16], uc, xv);
+            // every lane of the group takes part in the shuffles (a shuffle reads active lanes);
+            // the loop bounds are the group's own
+            for (int c0 = 0; c0 < len; c0 += 8) {
+                T lv[8];
+#pragma unroll
+                for (int u = 0; u < 8; u++) {
+                    const int c = c0 + u;
+                    const int base = __shfl(cbl, c & 15, 16);
+                    lv[u] = (c < len && l16 > c && l16 < len) ? Fx[base + off + l16] : T(0);
+                }
+#pragma unroll
+                for (int u = 0; u < 8; u++) {
+                    const int c = c0 + u;
+                    if (c < len - 1) {
+                        const T uc = __shfl(xv, c, 16);
+                        if (l16 > c && l16 < len) xv = fma(-lv[u], uc, xv);
+                    }
+                }
             }
             if (l16 < len) xk[item.y + l16] = xv;
-            // every lane of the group takes part in the shuffles (a shuffle reads active lanes)
-            T acc = T(0);
-            for (int c = 0; c < len; c++) {
-                const T uc = __shfl(xv, c, 16);
-                const T lv = l16 < mcnt ? Fx[cb[c] + w + l16] : T(0);
-                acc = fma(lv, uc, acc);
+            for (int r0 = 0; r0 < mcnt; r0 += 32) {
+                const int ra = r0 + l16, rb = r0 + 16 + l16;
+                const bool ina = ra < mcnt, inb = rb < mcnt;
+                const int sla = ina ? mp[ra] : 0, slb = inb ? mp[rb] : 0;
+                T acca = T(0), accb = T(0);
+                for (int c0 = 0; c0 < len; c0 += 8) {
+                    T la[8], lb[8];
+#pragma unroll
+                    for (int u = 0; u < 8; u++) {
+                        const int c = c0 + u;
+                        const int base = __shfl(cbl, c & 15, 16) + w;
+                        la[u] = (c < len && ina) ? Fx[base + ra] : T(0);
+                        lb[u] = (c < len && inb) ? Fx[base + rb] : T(0);
+                    }
+#pragma unroll
+                    for (int u = 0; u < 8; u++) {
+                        const int c = c0 + u;
+                        if (c < len) {
+                            const T uc = __shfl(xv, c, 16);
+                            acca = fma(la[u], uc, acca);
+                            accb = fma(lb[u], uc, accb);
+                        }
+                    }
+                }
+                if (ina) xk[sla] -= acca;
+                if (inb) xk[slb] -= accb;
             }
-            if (l16 < mcnt) xk[a.sn_map[a.sn_moff[it] + l16]] -= acc;
             __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "workgroup");
             __builtin_amdgcn_wave_barrier();
         }

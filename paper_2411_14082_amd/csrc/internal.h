@@ -384,7 +384,7 @@ constexpr int kDenseBlock = 64;  // panel width of the blocked LU and of the blo
 constexpr int kSnSmallW = 16;    // supernodes up to this wide are factored by one wavefront
 constexpr int kGroupTargets = 4; // heavy update tasks with shared sources grouped this many at a time
 constexpr int kTinyRows = 16;    // update tasks whose items have at most this many suffix rows and
-                                 // rows of R: 16 lanes each
+constexpr int kTinyRowsR = 64;   // at most this many rows of R: 16 lanes each
 struct DenseArgs {
     int n, T, D, batch;
     const int *Dp, *Dlen, *Fi;

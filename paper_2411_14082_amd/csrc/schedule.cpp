@@ -231,7 +231,7 @@ static void build_supernodal(const Factor &f, Schedule &s, int T, int wmax, int 
     // inside each level: heavy tasks (rows of R times suffix rows at least kHeavyTask, or an
     // item with at least kHeavyRows rows of R: its rows split over four wavefronts) first, a
     // workgroup each; then light tasks, a wavefront each; then tiny tasks (every item at most
-    // kTinyRows suffix rows and rows of R), sixteen lanes each.  The order of tasks does not
+    // kTinyRows suffix rows and kTinyRowsR rows of R), sixteen lanes each.  The order of tasks does not
     // change results
     s.sn_task_heavy.assign(nl, 0);
     s.sn_task_tiny.assign(nl, 0);
@@ -248,7 +248,7 @@ static void build_supernodal(const Factor &f, Schedule &s, int T, int wmax, int 
                     cost += (double)s.sn_item[4 * (size_t)it2 + 3] * s.sn_item[4 * (size_t)it2 + 2];
                     rows = std::max(rows, s.sn_item[4 * (size_t)it2 + 3]);
                     small = small && s.sn_item[4 * (size_t)it2 + 2] <= cktlu_dev::kTinyRows &&
-                            s.sn_item[4 * (size_t)it2 + 3] <= cktlu_dev::kTinyRows;
+                            s.sn_item[4 * (size_t)it2 + 3] <= cktlu_dev::kTinyRowsR;
                 }
                 (cost >= kHeavyTask || rows >= kHeavyRows ? heavy : small ? tiny : light).push_back(t);
             }
