@@ -636,11 +636,12 @@ __device__ __forceinline__ void sn_triangle(Elem elem, double *y, int s0, int w,
 // threads, then the two halves: the same sums whichever unit is last) and solves the triangle.
 // Every unit loads the diagonal block into LDS while it pulls.
 constexpr int kSnSolveWG = 1024;                     // threads of a supernodal solve workgroup
+constexpr int kSolveWholeBatch = 8;
 constexpr int kSnSolveWaves = kSnSolveWG / WAVE;
 template <typename T, int NR, bool UPPER>
 __global__ __launch_bounds__(kSnSolveWG) void sn_solve_kernel(SolveArgs a, const int *seq, const int *units,
                                                               const int *urange, const int *runs, int sbeg, int stiny,
-                                                              int smid, int ubeg, int *cnt) {
+                                                              int smid, int ubeg, int *cnt, int whole) {
     __shared__ double wsum[8][8][WAVE];                  // the wavefronts' sums, [wavefront][rhs][row]
     __shared__ double red[2][512];
     __shared__ double tri[64][65];                       // a unit's diagonal block, column-major
@@ -753,8 +754,15 @@ __global__ __launch_bounds__(kSnSolveWG) void sn_solve_kernel(SolveArgs a, const
     const int inst = (int)(pu % a.batch);
     if (a.skip && a.skip[inst] != -1) return;            // the whole workgroup
     const int ui = ubeg + (int)(pu / a.batch);
-    const int4 un = reinterpret_cast<const int4 *>(units)[ui];
-    const int2 ur = reinterpret_cast<const int2 *>(urange)[ui];
+    int4 un = reinterpret_cast<const int4 *>(units)[ui];
+    int2 ur = reinterpret_cast<const int2 *>(urange)[ui];
+    if (whole && un.z > 1) {
+        // one workgroup per supernode: the first unit takes every unit's runs (they are
+        // consecutive), the others leave
+        if (un.y > 0) return;
+        ur.y = reinterpret_cast<const int2 *>(urange)[ui + un.z - 1].y;
+        un.z = 1;
+    }
     const int4 rec = reinterpret_cast<const int4 *>(a.sn_rec)[seq[un.x]];
     const int s0 = rec.x, w = rec.y;
     const T *Fx = reinterpret_cast<const T *>(a.Fx) + (size_t)inst * a.nnzF;
@@ -864,6 +872,9 @@ template <bool UPPER>
 static int launch_sn_solve_impl(const SolveArgs &a, const int *seq, const int *units, const int *urange,
                                 const int *runs, int sbeg, int stiny, int smid, int ubeg, int uend, int *cnt,
                                 void *stream) {
+    // a batch of kSolveWholeBatch instances or more fills the device with one workgroup per
+    // supernode and instance: split units would only add combines
+    const int whole = a.batch >= kSolveWholeBatch ? 1 : 0;
     const int64_t ntb = ((int64_t)(stiny - sbeg) * a.batch + kSnSolveWG / 16 - 1) / (kSnSolveWG / 16);
     const int64_t nsw = ntb + ((int64_t)(smid - stiny) * a.batch + kSnSolveWaves - 1) / kSnSolveWaves;
     const int64_t units_n = nsw + (int64_t)(uend - ubeg) * a.batch;
@@ -874,10 +885,10 @@ static int launch_sn_solve_impl(const SolveArgs &a, const int *seq, const int *u
     case NRV:                                                                                           \
         if (a.fp32)                                                                                     \
             hipLaunchKernelGGL((sn_solve_kernel<float, NRV, UPPER>), grid, dim3(kSnSolveWG), 0, st, a, seq, units, \
-                               urange, runs, sbeg, stiny, smid, ubeg, cnt);                             \
+                               urange, runs, sbeg, stiny, smid, ubeg, cnt, whole);                      \
         else                                                                                            \
             hipLaunchKernelGGL((sn_solve_kernel<double, NRV, UPPER>), grid, dim3(kSnSolveWG), 0, st, a, seq, units, \
-                               urange, runs, sbeg, stiny, smid, ubeg, cnt);                             \
+                               urange, runs, sbeg, stiny, smid, ubeg, cnt, whole);                      \
         break;
     switch (a.nrhs) {
         CKTLU_SNS_CASE(1)
