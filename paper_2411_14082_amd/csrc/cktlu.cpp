@@ -850,7 +850,7 @@ int ensure_vec(cktlu_ctx *c, size_t doubles) {
     return CKTLU_OK;
 }
 
-// z (n rows of YS doubles per instance) <- (LU)^{-1} z, in place; level by level.
+// z (n rows of solve_slots(nrhs) doubles per instance) <- (LU)^{-1} z, in place; level by level.
 int tri_solves(cktlu_ctx *c, int nrhs, int batch, double *z, bool fp32, const int *skip) {
     Device &d = c->dev;
     hipStream_t st = stream_of(c);
@@ -924,13 +924,13 @@ int tri_solves(cktlu_ctx *c, int nrhs, int batch, double *z, bool fp32, const in
     return CKTLU_OK;
 }
 
-// Device work vectors: z = n rows of YS doubles, then r = n x nrhs doubles, then
+// Device work vectors: z = room for n rows of YS doubles, then r = n x nrhs doubles, then
 // 3 x nrhs norms and one more word.
 size_t vec_need(const cktlu_ctx *c, int nrhs) {
     return (size_t)c->an.n * YS + 64 + (size_t)c->an.n * nrhs + 3 * (size_t)nrhs + 8;
 }
 
-// zbuf: work rows (n x YS doubles) supplied by the caller, or nullptr for the context's own
+// zbuf: work rows (room for n x YS doubles) supplied by the caller, or nullptr for the context's own
 // skip: a device status word (-1 = solve), or null
 int solve_chunk(cktlu_ctx *c, int nrhs, const double *b, int64_t ldb, double *x, int64_t ldx, bool fp32,
                 bool accumulate, double *zbuf = nullptr, const int *skip = nullptr) {

@@ -718,7 +718,7 @@ __global__ __launch_bounds__(64) void dlu_inverse_kernel(DenseArgs a) {
 }
 
 // ------------------------------------------------------------- dense solves
-// y rows T.. of each instance hold the partial solution (YS doubles per row).  Launch b of a
+// y rows T.. of each instance hold the partial solution (NR doubles per row).  Launch b of a
 // triangle applies one solved block to the rows that still need it and solves the next
 // diagonal block.  A workgroup takes 64 rows, its four wavefronts a quarter of the applied
 // block's 64 columns each (a row per lane, sixteen loads in flight); the quarters' sums meet in
@@ -736,7 +736,7 @@ __global__ __launch_bounds__(256) void dtrsv_kernel(DenseArgs a, double *y, int 
     const int inst = blockIdx.y;
     if (skip && skip[inst] != -1) return;
     const T *S = inst_S<T>(a, inst);
-    double *yt = y + ((size_t)inst * a.n + a.T) * YS;
+    double *yt = y + ((size_t)inst * a.n + a.T) * NR;
     const int D = a.D, tid = threadIdx.x, lane = tid & (NB - 1), q = tid / NB;
     const int nblk = (D + NB - 1) / NB;
     const int blk = UPPER ? nblk - 1 - b : b;         // the block this launch solves
@@ -755,12 +755,12 @@ __global__ __launch_bounds__(256) void dtrsv_kernel(DenseArgs a, double *y, int 
     }
     double yi[NR];
 #pragma unroll
-    for (int r = 0; r < NR; r++) yi[r] = q == 0 && row ? yt[(size_t)i * YS + r] : 0.0;
+    for (int r = 0; r < NR; r++) yi[r] = q == 0 && row ? yt[(size_t)i * NR + r] : 0.0;
     if (b > 0) {
         if (tid < NB * NR / 2) {                      // NB * NR <= 512: two loads per thread
             const int e1 = tid + NB * NR / 2;
-            const double y0 = tid / NR < na ? yt[(size_t)(pa + tid / NR) * YS + tid % NR] : 0.0;
-            const double y1 = e1 / NR < na ? yt[(size_t)(pa + e1 / NR) * YS + e1 % NR] : 0.0;
+            const double y0 = tid / NR < na ? yt[(size_t)(pa + tid / NR) * NR + tid % NR] : 0.0;
+            const double y1 = e1 / NR < na ? yt[(size_t)(pa + e1 / NR) * NR + e1 % NR] : 0.0;
             yb[tid / NR][tid % NR] = y0;
             yb[e1 / NR][e1 % NR] = y1;
         }
@@ -788,7 +788,7 @@ __global__ __launch_bounds__(256) void dtrsv_kernel(DenseArgs a, double *y, int 
                 yi[r] -= ((part[0][r][lane] + part[1][r][lane]) + part[2][r][lane]) + part[3][r][lane];
             if (blockIdx.x != 0) {
 #pragma unroll
-                for (int r = 0; r < NR; r++) yt[(size_t)i * YS + r] = yi[r];
+                for (int r = 0; r < NR; r++) yt[(size_t)i * NR + r] = yi[r];
             }
         }
     }
@@ -822,7 +822,7 @@ __global__ __launch_bounds__(256) void dtrsv_kernel(DenseArgs a, double *y, int 
     if (q == 0 && lane < nb) {
 #pragma unroll
         for (int r = 0; r < NR; r++)
-            yt[(size_t)(p + lane) * YS + r] = ((part[0][r][lane] + part[1][r][lane]) + part[2][r][lane]) + part[3][r][lane];
+            yt[(size_t)(p + lane) * NR + r] = ((part[0][r][lane] + part[1][r][lane]) + part[2][r][lane]) + part[3][r][lane];
     }
 }
 

@@ -247,7 +247,7 @@ struct Device {
 namespace cktlu_dev {
 
 constexpr int kColAlign = 32;   // factor column alignment in entries (>= one 128-byte line)
-constexpr int YS = 16;          // doubles per solve-vector row (one 128-byte line); nrhs <= 8
+constexpr int YS = 16;          // doubles per solve-vector row at most (rows hold solve_slots(nrhs) doubles)
 constexpr int kSolveRowWG = 256; // threads of the workgroup that solves one long row
 constexpr int kSolveLongRow = 64; // levels holding a longer row get a workgroup per row (64, 128 and
                                   // 256 measured: 64 best on the RC mesh and the power grid)
@@ -318,7 +318,7 @@ struct SolveArgs {
     const void *Fx;            // factor values (double or float), batch x nnzF
     int64_t nnzF;
     int fp32;
-    double *y;                 // batch x n rows of YS doubles, rhs r in slot r
+    double *y;                 // batch x n rows of solve_slots(nrhs) doubles, rhs r in slot r
     const int *skip;           // per-instance status (-1 = solve), may be null
     // supernodal solves: supernode records and first-row offsets (as RefactorArgs), and the row
     // pointers of the strictly lower L and strictly upper U (entries in Lrjs / Urjs)
@@ -345,10 +345,10 @@ int launch_usolve_level_wg(const SolveArgs &a, int lbeg, int lend, void *stream)
 // a barrier between levels; lvptr = level boundaries in solve positions (device).
 int launch_lsolve_chain(const SolveArgs &a, const int *lvptr, int l0, int l1, void *stream);
 int launch_usolve_chain(const SolveArgs &a, const int *lvptr, int l0, int l1, void *stream);
-// y[((i*n + k)*YS + r] = b[(i*nrhs + r)*ldb + perm[k]] for r < nrhs, 0 for r < solve_slots(nrhs)
+// y[((i*n + k)*ns + r] = b[(i*nrhs + r)*ldb + perm[k]] for r < nrhs, 0 for r < ns = solve_slots(nrhs)
 int launch_gather_rhs(int n, int nrhs, int batch, const double *b, int64_t ldb, const int *perm,
                       double *y, void *stream, const double *scale = nullptr);
-// x[(i*nrhs + r)*ldx + perm[k]] (+)= y[(i*n + k)*YS + r]
+// x[(i*nrhs + r)*ldx + perm[k]] (+)= y[(i*n + k)*solve_slots(nrhs) + r]
 int launch_scatter_sol(int n, int nrhs, int batch, const double *z, const int *perm, double *x,
                        int64_t ldx, int accumulate, const int *skip, void *stream, const double *scale = nullptr);
 // r = b - A x (user space, FP64), per rhs; also writes |r|_inf, |x|_inf, |b|_inf maxima.  Nothing

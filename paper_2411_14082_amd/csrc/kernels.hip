@@ -434,7 +434,8 @@ int launch_refactor_level(const RefactorArgs &a, int cbeg, int cend, int pbeg, i
 }
 
 // ----------------------------------------------------------------- solves
-// y holds one cache line (YS doubles) per row and instance: y[(inst*n + i)*YS + r].
+// y holds NR doubles per row and instance (NR: the right-hand sides padded to 1, 2, 4 or 8):
+// y[(inst*n + i)*NR + r].
 // One row of a triangular solve, by one wavefront: its record, then its entries
 // {column, value position}, then the values and the y rows they multiply.
 // sum over the row entries [beg, end) of value * y(column), per right-hand side, over the
@@ -455,7 +456,7 @@ __device__ __forceinline__ void row_pull(const int2 *rjs, const T *Fx, const dou
         for (int u = 0; u < 2; u++)
             if (e[u].x >= 0) {
 #pragma unroll
-                for (int r = 0; r < NR; r++) acc[r] += l[u] * y[(size_t)e[u].x * YS + r];
+                for (int r = 0; r < NR; r++) acc[r] += l[u] * y[(size_t)e[u].x * NR + r];
             }
     }
 #pragma unroll
@@ -466,10 +467,10 @@ template <typename T, int NR, bool UPPER>
 __device__ __forceinline__ void solve_row_rec(const SolveArgs &a, int inst, int4 rec, int lane) {
     const int2 *rjs = reinterpret_cast<const int2 *>(UPPER ? a.Urjs : a.Lrjs);
     const T *Fx = reinterpret_cast<const T *>(a.Fx) + (size_t)inst * a.nnzF;
-    double *y = a.y + (size_t)inst * a.n * YS;
+    double *y = a.y + (size_t)inst * a.n * NR;
     const int i = rec.x;
     const double diag = UPPER ? (double)Fx[rec.w] : 1.0;
-    const double yi = lane < NR ? y[(size_t)i * YS + lane] : 0.0;
+    const double yi = lane < NR ? y[(size_t)i * NR + lane] : 0.0;
     double acc[NR];
     row_pull<T, NR>(rjs, Fx, y, rec.y, rec.z, lane, acc);
     double mine = acc[0];
@@ -479,7 +480,7 @@ __device__ __forceinline__ void solve_row_rec(const SolveArgs &a, int inst, int4
     if (lane < NR) {
         double v = yi - mine;
         if (UPPER) v = v / diag;
-        y[(size_t)i * YS + lane] = v;
+        y[(size_t)i * NR + lane] = v;
     }
 }
 
@@ -513,7 +514,7 @@ __global__ __launch_bounds__(kSolveRowWG) void trisolve_rowwg_kernel(SolveArgs a
     const int4 rec = reinterpret_cast<const int4 *>(UPPER ? a.urec : a.lrec)[t / a.batch];
     const int2 *rjs = reinterpret_cast<const int2 *>(UPPER ? a.Urjs : a.Lrjs);
     const T *Fx = reinterpret_cast<const T *>(a.Fx) + (size_t)inst * a.nnzF;
-    double *y = a.y + (size_t)inst * a.n * YS;
+    double *y = a.y + (size_t)inst * a.n * NR;
     double acc[NR];
 #pragma unroll
     for (int r = 0; r < NR; r++) acc[r] = 0.0;
@@ -531,7 +532,7 @@ __global__ __launch_bounds__(kSolveRowWG) void trisolve_rowwg_kernel(SolveArgs a
         for (int u = 0; u < 4; u++)
             if (e[u].x >= 0) {
 #pragma unroll
-                for (int r = 0; r < NR; r++) acc[r] += l[u] * y[(size_t)e[u].x * YS + r];
+                for (int r = 0; r < NR; r++) acc[r] += l[u] * y[(size_t)e[u].x * NR + r];
             }
     }
 #pragma unroll
@@ -546,9 +547,9 @@ __global__ __launch_bounds__(kSolveRowWG) void trisolve_rowwg_kernel(SolveArgs a
 #pragma unroll
         for (int w = 1; w < NW; w++) sum += part[w][lane];
         const int i = rec.x;
-        double v = y[(size_t)i * YS + lane] - sum;
+        double v = y[(size_t)i * NR + lane] - sum;
         if (UPPER) v = v / (double)Fx[rec.w];
-        y[(size_t)i * YS + lane] = v;
+        y[(size_t)i * NR + lane] = v;
     }
 }
 
@@ -615,7 +616,7 @@ __device__ __forceinline__ void sn_triangle(Elem elem, double *y, int s0, int w,
     }
     if (lane < w) {
 #pragma unroll
-        for (int r = 0; r < NR; r++) y[(size_t)(s0 + lane) * YS + r] = t[r];
+        for (int r = 0; r < NR; r++) y[(size_t)(s0 + lane) * NR + r] = t[r];
     }
 }
 
@@ -663,7 +664,7 @@ __global__ __launch_bounds__(kSnSolveWG) void sn_solve_kernel(SolveArgs a, const
         const int i = a.sn_rec[4 * seq[sbeg + (int)(gid / a.batch)]];
         const int l16 = lane & 15;
         const T *Fx = reinterpret_cast<const T *>(a.Fx) + (size_t)inst * a.nnzF;
-        double *y = a.y + (size_t)inst * a.n * YS;
+        double *y = a.y + (size_t)inst * a.n * NR;
         double acc[NR];
 #pragma unroll
         for (int r = 0; r < NR; r++) acc[r] = 0.0;
@@ -679,7 +680,7 @@ __global__ __launch_bounds__(kSnSolveWG) void sn_solve_kernel(SolveArgs a, const
             for (int u = 0; u < 2; u++)
                 if (e[u].x >= 0) {
 #pragma unroll
-                    for (int r = 0; r < NR; r++) acc[r] += l[u] * y[(size_t)e[u].x * YS + r];
+                    for (int r = 0; r < NR; r++) acc[r] += l[u] * y[(size_t)e[u].x * NR + r];
                 }
         }
 #pragma unroll
@@ -691,9 +692,9 @@ __global__ __launch_bounds__(kSnSolveWG) void sn_solve_kernel(SolveArgs a, const
         for (int r = 1; r < NR; r++)
             if (l16 == r) mine = acc[r];
         if (l16 < NR) {
-            double v = y[(size_t)i * YS + l16] - mine;
+            double v = y[(size_t)i * NR + l16] - mine;
             if (UPPER) v = v / (double)Fx[a.sn_cb[i]];
-            y[(size_t)i * YS + l16] = v;
+            y[(size_t)i * NR + l16] = v;
         }
         return;
     }
@@ -709,7 +710,7 @@ __global__ __launch_bounds__(kSnSolveWG) void sn_solve_kernel(SolveArgs a, const
             return;
         }
         const T *Fx = reinterpret_cast<const T *>(a.Fx) + (size_t)inst * a.nnzF;
-        double *y = a.y + (size_t)inst * a.n * YS;
+        double *y = a.y + (size_t)inst * a.n * NR;
         // the rows pull at the same time: G = 64 / 2^ceil(log2 w) lanes per row (at least 4),
         // two entries per lane in flight, the sums reduced over the G lanes
         const int lg = 32 - __builtin_clz((unsigned)(w - 1));   // w <= 2^lg
@@ -731,7 +732,7 @@ __global__ __launch_bounds__(kSnSolveWG) void sn_solve_kernel(SolveArgs a, const
                 for (int u = 0; u < 2; u++)
                     if (e[u].x >= 0) {
 #pragma unroll
-                        for (int r = 0; r < NR; r++) acc[r] += l[u] * y[(size_t)e[u].x * YS + r];
+                        for (int r = 0; r < NR; r++) acc[r] += l[u] * y[(size_t)e[u].x * NR + r];
                     }
             }
         }
@@ -744,7 +745,7 @@ __global__ __launch_bounds__(kSnSolveWG) void sn_solve_kernel(SolveArgs a, const
 #pragma unroll
         for (int r = 0; r < NR; r++) {
             const double sr = __shfl(acc[r], (lane < w ? lane : 0) * G);
-            t[r] = lane < w ? y[(size_t)(s0 + lane) * YS + r] - sr : 0.0;
+            t[r] = lane < w ? y[(size_t)(s0 + lane) * NR + r] - sr : 0.0;
         }
         const int *cb = a.sn_cb + s0;
         sn_triangle<T, NR, UPPER>([=](int cc, int r) { return (double)Fx[cb[cc] + r]; }, y, s0, w, t, lane);
@@ -766,7 +767,7 @@ __global__ __launch_bounds__(kSnSolveWG) void sn_solve_kernel(SolveArgs a, const
     const int4 rec = reinterpret_cast<const int4 *>(a.sn_rec)[seq[un.x]];
     const int s0 = rec.x, w = rec.y;
     const T *Fx = reinterpret_cast<const T *>(a.Fx) + (size_t)inst * a.nnzF;
-    double *y = a.y + (size_t)inst * a.n * YS;
+    double *y = a.y + (size_t)inst * a.n * NR;
     // the diagonal block, loaded now and stored to LDS after the pull (up to four per thread)
     double dv[4];
     {
@@ -787,7 +788,7 @@ __global__ __launch_bounds__(kSnSolveWG) void sn_solve_kernel(SolveArgs a, const
         const int qa = q0 + (lane & 7) * kSnSolveWaves;
         const int4 gl = lane < 8 && qa < ur.y ? rr[qa] : make_int4(0, 0, 0, 0);
         const int jl = __shfl(gl.x, lane >> 3), nl = __shfl(gl.w, lane >> 3);
-        const double yl = nl > 0 && (lane & 7) < NR ? y[(size_t)jl * YS + (lane & 7)] : 0.0;
+        const double yl = nl > 0 && (lane & 7) < NR ? y[(size_t)jl * NR + (lane & 7)] : 0.0;
         double lv[8];
         bool on[8];
 #pragma unroll
@@ -864,7 +865,7 @@ __global__ __launch_bounds__(kSnSolveWG) void sn_solve_kernel(SolveArgs a, const
     }
     double t[NR];
 #pragma unroll
-    for (int r = 0; r < NR; r++) t[r] = lane < w ? y[(size_t)(s0 + lane) * YS + r] - sum[r] : 0.0;
+    for (int r = 0; r < NR; r++) t[r] = lane < w ? y[(size_t)(s0 + lane) * NR + r] - sum[r] : 0.0;
     sn_triangle<T, NR, UPPER>([&](int cc, int r) { return tri[cc][r]; }, y, s0, w, t, lane);
 }
 
@@ -1029,12 +1030,12 @@ __global__ void gather_rhs_kernel(int n, int nrhs, int nslots, int batch, const 
         const int k = (int)(ik % n);
         const int64_t i = ik / n;
         const double v = r < nrhs ? b[(i * nrhs + r) * ldb + perm[k]] : 0.0;
-        y[ik * YS + r] = scale ? v * scale[k] : v;
+        y[ik * nslots + r] = scale ? v * scale[k] : v;
     }
 }
 
 // scale (may be null): per solve position, the static column scaling of its user column
-__global__ void scatter_sol_kernel(int n, int nrhs, int batch, const double *z, const int *perm,
+__global__ void scatter_sol_kernel(int n, int nrhs, int nslots, int batch, const double *z, const int *perm,
                                    double *x, int64_t ldx, int accumulate, const int *skip, const double *scale) {
     const int64_t total = (int64_t)n * nrhs * batch;
     for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < total;
@@ -1045,7 +1046,7 @@ __global__ void scatter_sol_kernel(int n, int nrhs, int batch, const double *z, 
         const int64_t i = ik / n;
         if (skip && skip[i] != -1) continue;
         double *dst = x + (i * nrhs + r) * ldx + perm[k];
-        const double v = scale ? z[ik * YS + r] * scale[k] : z[ik * YS + r];
+        const double v = scale ? z[ik * nslots + r] * scale[k] : z[ik * nslots + r];
         *dst = accumulate ? *dst + v : v;
     }
 }
@@ -1068,7 +1069,8 @@ int launch_gather_rhs(int n, int nrhs, int batch, const double *b, int64_t ldb, 
 int launch_scatter_sol(int n, int nrhs, int batch, const double *z, const int *perm, double *x,
                        int64_t ldx, int accumulate, const int *skip, void *stream, const double *scale) {
     hipLaunchKernelGGL(scatter_sol_kernel, dim3(grid_for((int64_t)n * nrhs * batch, 256)), dim3(256), 0,
-                       (hipStream_t)stream, n, nrhs, batch, z, perm, x, ldx, accumulate, skip, scale);
+                       (hipStream_t)stream, n, nrhs, solve_slots(nrhs), batch, z, perm, x, ldx, accumulate, skip,
+                       scale);
     return (int)hipGetLastError();
 }
 
