@@ -192,7 +192,7 @@ struct Schedule {
     // uses at most snl_nscr scratch blocks.  A workgroup supernode's pull is a list of runs
     // (snl_runs, int4 {column j, position of the first entry, first row c_a, rows}: rows
     // s0 + c_a ... of the supernode present in column j, at consecutive positions); unit u pulls
-    // the runs [snl_urange[2u], snl_urange[2u+1]).
+    // the runs [snl_urange[4u], snl_urange[4u+1]) of supernode [snl_urange[4u+2], + snl_urange[4u+3]).
     int snl_levels = 0, snu_levels = 0;
     std::vector<int> snl_lvl, snl_tiny, snl_single, snl_seq, snu_lvl, snu_tiny, snu_single, snu_seq;
     std::vector<int> snl_unit, snl_ulvl, snu_unit, snu_ulvl;

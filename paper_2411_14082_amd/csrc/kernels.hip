@@ -756,16 +756,15 @@ __global__ __launch_bounds__(kSnSolveWG) void sn_solve_kernel(SolveArgs a, const
     if (a.skip && a.skip[inst] != -1) return;            // the whole workgroup
     const int ui = ubeg + (int)(pu / a.batch);
     int4 un = reinterpret_cast<const int4 *>(units)[ui];
-    int2 ur = reinterpret_cast<const int2 *>(urange)[ui];
+    int4 ur = reinterpret_cast<const int4 *>(urange)[ui];   // runs [x, y) of supernode [z, z + w)
     if (whole && un.z > 1) {
         // one workgroup per supernode: the first unit takes every unit's runs (they are
         // consecutive), the others leave
         if (un.y > 0) return;
-        ur.y = reinterpret_cast<const int2 *>(urange)[ui + un.z - 1].y;
+        ur.y = reinterpret_cast<const int4 *>(urange)[ui + un.z - 1].y;
         un.z = 1;
     }
-    const int4 rec = reinterpret_cast<const int4 *>(a.sn_rec)[seq[un.x]];
-    const int s0 = rec.x, w = rec.y;
+    const int s0 = ur.z, w = ur.w;
     const T *Fx = reinterpret_cast<const T *>(a.Fx) + (size_t)inst * a.nnzF;
     double *y = a.y + (size_t)inst * a.n * NR;
     // the diagonal block, loaded now and stored to LDS after the pull (up to four per thread)

@@ -482,7 +482,8 @@ static void build_supernodal(const Factor &f, Schedule &s, int T, int wmax, int 
                 const int P = (int)std::min<int64_t>(kSolveMaxSplit, std::max<int64_t>(1, (nr + per_unit - 1) / per_unit));
                 for (int p = 0; p < P; p++) {
                     unit.insert(unit.end(), {q, p, P, P > 1 ? blocks : -1});
-                    urange.insert(urange.end(), {(int)(r0 + nr * p / P), (int)(r0 + nr * (p + 1) / P)});
+                    urange.insert(urange.end(), {(int)(r0 + nr * p / P), (int)(r0 + nr * (p + 1) / P),
+                                                 s0v[seq[q]], s0v[seq[q] + 1] - s0v[seq[q]]});
                 }
                 if (P > 1) blocks += P;
             }
