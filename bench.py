@@ -32,13 +32,15 @@ WORKLOADS = {
     "mesh_transistor_141": dict(make=lambda: __import__("mnagen").mesh_transistor(141, 141, seed=0), cfg=3,
                                 desc="mesh 141x141 + transistor stamps"),
     "power_grid_1000_8rhs": dict(make=lambda: __import__("mnagen").power_grid(1000, 1000, seed=0), cfg=4, nrhs=8,
+                                 autotune=True,
                                  desc="power grid 1000x1000 (n = 1M), pads and current loads, 8 right-hand sides"),
     "mesh_vsrc_32": dict(make=lambda: __import__("mnagen").mesh_vsrc(32, 32, 4, seed=0), cfg=1,
                          desc="mesh 32x32 + 4 ideal voltage sources"),
     "serving_mix": dict(make=None, cfg=5, serving=True,
                         desc="Poisson arrivals of circuits n ~ logU[1k, 200k], 20 NR steps each"),
     "corners_141_x256": dict(make=lambda: __import__("mnagen").mesh_transistor(141, 141, seed=0), cfg=3,
-                             batch=256, desc="256 corners of mesh 141x141 + transistor stamps, lognormal(0.3)"),
+                             batch=256, autotune=True,
+                             desc="256 corners of mesh 141x141 + transistor stamps, lognormal(0.3)"),
 }
 
 
@@ -159,7 +161,8 @@ def main_batched(args, wl):
     batch = wl["batch"]
     tail_opts = dict(dense_tail=args.dense_tail, dense_tail_density=args.dense_density, autotune=args.autotune,
                      solve_chain_width=args.solve_chain, dense_panel_width=args.dense_panel_width,
-                     dense_lookahead=args.dense_lookahead, ordering=args.ordering)
+                     dense_lookahead=args.dense_lookahead, ordering=args.ordering,
+                     solve_split_entries=args.solve_split_entries)
     legs = {}
     for name, prec, graph in (("fp64_eager", ck.CKTLU_FP64, False), ("fp64_graph", ck.CKTLU_FP64, True),
                               ("fp32_ir_eager", ck.CKTLU_FP32_IR, False), ("fp32_ir_graph", ck.CKTLU_FP32_IR, True)):
@@ -260,8 +263,10 @@ def run_leg(ck, torch, c, vals_dev, b_dev, precision, steps, warmup, tail_opts, 
     t0 = time.time()
     s.factorize(vals_dev[0])
     t_setup = time.time() - t0
+    tuned = None
     if tail_opts.get("autotune"):
-        log("autotune:", s.autotune(1, vals_dev[0], reps=2))
+        tuned = s.autotune(1, vals_dev[0], reps=2)
+        log("autotune:", tuned)
     x = torch.zeros_like(b_dev)
     nrep = 0
     for w in range(warmup):
@@ -310,7 +315,7 @@ def run_leg(ck, torch, c, vals_dev, b_dev, precision, steps, warmup, tail_opts, 
     tm = s.timing()
     s.close()
     return dict(wall=wall, step_ms=step_ms, ref_ms=ref_ms, sol_ms=sol_ms, stats=st, setup_s=t_setup,
-                repivots=int(nrep), infos=infos, x=x, timing=tm)
+                repivots=int(nrep), infos=infos, x=x, timing=tm, tuned=tuned)
 
 
 def cpu_baseline(c, values, B):
@@ -411,7 +416,12 @@ def main():
     ap.add_argument("--requests", type=int, default=16, help="serving_mix: number of requests")
     ap.add_argument("--slots", type=int, default=4, help="serving_mix: requests on the device at once")
     ap.add_argument("--autotune", action="store_true",
-                    help="measure the dense-block candidates on the device first and keep the fastest")
+                    help="measure the dense-block candidates and schedule knobs on the device first and keep the "
+                         "fastest (the default for the workloads whose configuration is autotuned)")
+    ap.add_argument("--no-autotune", action="store_true",
+                    help="use the library's default schedule (or the options given) without measuring candidates")
+    ap.add_argument("--solve-split-entries", type=int, default=None,
+                    help="supernodal solves: unit size option (see cktlu_options.solve_split_entries)")
     ap.add_argument("--perturb", default="element", choices=["element", "nonzero"],
                     help="element: every circuit element x U[0.95,1.05], re-assembled (NR re-stamping); "
                          "nonzero: every assembled nonzero x U[0.95,1.05] (pivot stress)")
@@ -430,6 +440,10 @@ def main():
     import paper_2411_14082_amd as ck
 
     wl = WORKLOADS[args.workload]
+    # the autotuner runs by default where the workload's configuration asks for it, unless
+    # the schedule is forced from the command line
+    args.autotune = not args.no_autotune and (args.autotune or (
+        wl.get("autotune", False) and args.dense_tail is None and args.solve_split_entries is None))
     if "batch" in wl:
         return main_batched(args, wl)
     if wl.get("serving"):
@@ -452,7 +466,8 @@ def main():
     tail_opts = dict(dense_tail=args.dense_tail, dense_tail_density=args.dense_density, autotune=args.autotune,
                      solve_chain_width=args.solve_chain, dense_panel_width=args.dense_panel_width,
                      dense_lookahead=args.dense_lookahead, ordering=args.ordering,
-                     sweep_slot_map=-1 if args.no_slot_map else None)
+                     sweep_slot_map=-1 if args.no_slot_map else None,
+                     solve_split_entries=args.solve_split_entries)
     if args.repivot_rates:
         return main_repivot(args, wl, c, vals_dev, b_dev, tail_opts, ck, torch)
     if args.calibrate_copy_mib > 0:
@@ -477,7 +492,10 @@ def main():
         leg32 = dict(leg_summary(res32, args.steps), ir_iters_mean=float(np.mean(iters)),
                      backward_err_max=max(eta_inf(c, vals[-1], X32[r], B[r]) for r in range(nrhs)),
                      backward_err_reported_max=float(np.max([i[1] for i in res32["infos"]])),
-                     fp64_fallbacks=int(sum(i[2] for i in res32["infos"])), phases_ms=phases_of(res32["timing"]))
+                     fp64_fallbacks=int(sum(i[2] for i in res32["infos"])), phases_ms=phases_of(res32["timing"]),
+                     dense_tail=res32["stats"]["dense_tail"],
+                     autotuned=(dict(dense_tail=res32["tuned"]["best_dense_tail"], kept=res32["tuned"]["kept"])
+                                if res32.get("tuned") else None))
         log("fp32+ir: %.3f steps/s" % leg32["steps_per_s"])
 
     st = res64["stats"]
@@ -557,7 +575,10 @@ def main():
                    "flops_per_refactor": st["flops"], "levels": st["levels"], "dense_tail": st["dense_tail"],
                    "nrhs": nrhs, "ordering": ["amd", "natural", "amf", "auto", "nd", "nd+camd"][int(st.get("ordering_used", 0))],
                    "slot_map_entries": int(st.get("slot_map_entries", 0)),
-                   "value_perturbation": "+-5%% per %s" % args.perturb},
+                   "value_perturbation": "+-5%% per %s" % args.perturb,
+                   "schedule": "autotuned on this device before timing" if res64.get("tuned") else "library default",
+                   "autotuned": (dict(dense_tail=res64["tuned"]["best_dense_tail"], kept=res64["tuned"]["kept"])
+                                 if res64.get("tuned") else None)},
         "p50_ms": float(np.percentile(res64["step_ms"], 50)),
         "p99_ms": float(np.percentile(res64["step_ms"], 99)),
         "refactor_ms": float(res64["ref_ms"].mean()), "solve_ms": float(res64["sol_ms"].mean()),
