@@ -173,7 +173,7 @@ DevBuf *all_buffers(Device &d, int i) {
                      &d.Lrjs, &d.Urjs, &d.lsptr, &d.usptr, &d.rowperm,
                      &d.colperm_sol, &d.Acp, &d.Acj, &d.Acsrc, &d.Fx64, &d.Fx32, &d.Aval, &d.done,
                      &d.ctrl, &d.vec, &d.S, &d.Dg, &d.Dinv, &d.sn_rec, &d.sn_cb, &d.sn_seq, &d.sn_task,
-                     &d.sn_item, &d.sn_moff, &d.sn_map, &d.snl_seq, &d.snu_seq, &d.Lrp, &d.Urp,
+                     &d.sn_item, &d.sn_moff, &d.sn_item2, &d.sn_map, &d.snl_seq, &d.snu_seq, &d.Lrp, &d.Urp,
                      &d.ascale, &d.gscale, &d.sscale, &d.schur_sn_items,
                      &d.snl_unit, &d.snu_unit, &d.snl_urange, &d.snl_runs, &d.snu_urange, &d.snu_runs,
                      &d.sn_part, &d.sn_cnt, &d.sn_punit, &d.sn_sunit, &d.sn_grp, &d.sn_gsrc, &d.sn_gent};
@@ -309,6 +309,7 @@ int upload_all(cktlu_ctx *c) {
     if ((rc = upload(d.sn_task, s.sn_task, st))) return rc;
     if ((rc = upload(d.sn_item, s.sn_item, st))) return rc;
     if ((rc = upload(d.sn_moff, s.sn_moff, st))) return rc;
+    if ((rc = upload(d.sn_item2, s.sn_item2, st))) return rc;
     if ((rc = upload(d.sn_map, s.sn_map, st))) return rc;
     if ((rc = upload(d.schur_sn_items, s.schur_sn_items, st))) return rc;
     if (!c->an.rscale.empty()) {
@@ -622,6 +623,7 @@ int run_refactor(cktlu_ctx *c, int batch, const double *values_dev, bool fp32, b
     a.sn_item = (const int *)d.sn_item.p;
     a.sn_map = (const int *)d.sn_map.p;
     a.sn_moff = (const int64_t *)d.sn_moff.p;
+    a.sn_item2 = (const int *)d.sn_item2.p;
     a.sn_punit = (const int *)d.sn_punit.p;
     a.sn_sunit = (const int *)d.sn_sunit.p;
     a.sn_grp = (const int *)d.sn_grp.p;

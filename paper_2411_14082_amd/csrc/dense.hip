@@ -1544,12 +1544,13 @@ __global__ __launch_bounds__(256) void sn_update_kernel(RefactorArgs a, int lev,
         T *Fx = reinterpret_cast<T *>(a.Fx) + (size_t)inst * a.nnzF;
         const int4 tk = reinterpret_cast<const int4 *>(a.sn_task)[ttiny + (int)(gid / batch)];
         T *xk = Fx + tk.y;
+        const int4 *items = reinterpret_cast<const int4 *>(a.sn_item);
+        const int4 *items2 = reinterpret_cast<const int4 *>(a.sn_item2);
         for (int it = tk.z; it < tk.w; it++) {
-            const int4 item = reinterpret_cast<const int4 *>(a.sn_item)[it];
-            const int4 rec = reinterpret_cast<const int4 *>(a.sn_rec)[item.x];
-            const int w = rec.y, len = item.z, off = w - len, mcnt = item.w;
-            const int cbl = l16 < len ? a.sn_cb[rec.x + off + l16] : 0;   // the suffix's columns
-            const int *mp = a.sn_map + a.sn_moff[it];
+            const int4 item = items[it], it2 = items2[it];
+            const int w = it2.y, len = item.z, off = w - len, mcnt = item.w;
+            const int cbl = l16 < len ? a.sn_cb[it2.x + l16] : 0;   // the suffix's columns
+            const int *mp = a.sn_map + (int64_t)(((uint64_t)(uint32_t)it2.w << 32) | (uint32_t)it2.z);
             T xv = l16 < len ? xk[item.y + l16] : T(0);
             // every lane of the group takes part in the shuffles (a shuffle reads active lanes);
             // the loop bounds are the group's own
@@ -1607,12 +1608,13 @@ __global__ __launch_bounds__(256) void sn_update_kernel(RefactorArgs a, int lev,
     T *Fx = reinterpret_cast<T *>(a.Fx) + (size_t)inst * a.nnzF;
     const int4 tk = reinterpret_cast<const int4 *>(a.sn_task)[t];
     T *xk = Fx + tk.y;
+    const int4 *items = reinterpret_cast<const int4 *>(a.sn_item);
+    const int4 *items2 = reinterpret_cast<const int4 *>(a.sn_item2);
     for (int it = tk.z; it < tk.w; it++) {
-        const int4 item = reinterpret_cast<const int4 *>(a.sn_item)[it];
-        const int4 rec = reinterpret_cast<const int4 *>(a.sn_rec)[item.x];
-        const int w = rec.y, len = item.z, off = w - len, mcnt = item.w;
-        const int cbv = lane < len ? a.sn_cb[rec.x + off + lane] : 0;   // the suffix's columns
-        const int *mp = a.sn_map + a.sn_moff[it];
+        const int4 item = items[it], it2 = items2[it];
+        const int w = it2.y, len = item.z, off = w - len, mcnt = item.w;
+        const int cbv = lane < len ? a.sn_cb[it2.x + lane] : 0;   // the suffix's columns
+        const int *mp = a.sn_map + (int64_t)(((uint64_t)(uint32_t)it2.w << 32) | (uint32_t)it2.z);
         const T xv = sn_suffix_solve<T>(Fx, xk, cbv, item.y, off, len, lane);
         if (lane < len) xk[item.y + lane] = xv;
         for (int r0 = 0; r0 < mcnt; r0 += 2 * WAVE)

@@ -178,6 +178,9 @@ struct Schedule {
     std::vector<int> sn_item;                 // int4 per item {supernode, slot of its first row in k, rows
                                               // of S present in k (the suffix), rows of R updated}
     std::vector<int64_t> sn_moff;             // per item: its slots of R's rows in column k in sn_map
+    std::vector<int> sn_item2;                // per item: int4 {sn_cb index of the suffix's first column
+                                              // (the source's first column + its rows not in k), the
+                                              // source's width, sn_moff low and high 32 bits}
     std::vector<int> sn_map;
     int64_t sn_items = 0;
     double sn_macs = 0;                       // multiply-adds of the supernodal updates and panels
@@ -220,6 +223,7 @@ struct Device {
     DevBuf lrec, urec, Lrjs, Urjs, lsptr, usptr, rowperm, colperm_sol;
     DevBuf Acp, Acj, Acsrc;
     DevBuf sn_rec, sn_cb, sn_seq, sn_task, sn_item, sn_moff, sn_map;   // supernodal sweep
+    DevBuf sn_item2;
     DevBuf snl_seq, snu_seq, Lrp, Urp;                                 // supernodal solves
     DevBuf snl_unit, snu_unit, sn_part, sn_cnt;                        // their split units
     DevBuf snl_urange, snl_runs, snu_urange, snu_runs;                 // the units' runs
@@ -278,6 +282,7 @@ struct RefactorArgs {
     // first row, supernodes by level, update tasks, their items and the rows' slots
     const int *sn_rec, *sn_cb, *sn_seq, *sn_task, *sn_item, *sn_map;
     const int64_t *sn_moff;
+    const int *sn_item2;       // per item: {suffix's first sn_cb index, source width, map offset lo, hi}
     // wide panels split by rows of R: units int4 {position in sn_seq, slice, slices, first
     // scratch block}; column maxima of the slices (64 doubles per block and instance) and an
     // arrival counter per sn_seq position and instance (zero on entry and on exit)

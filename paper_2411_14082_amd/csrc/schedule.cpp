@@ -227,6 +227,15 @@ static void build_supernodal(const Factor &f, Schedule &s, int T, int wmax, int 
     }
     if (!s.sn_task.empty()) s.sn_task[s.sn_task.size() - 1] = (int)nitems;
     s.sn_moff[nitems] = moff;
+    s.sn_item2.resize(4 * (size_t)nitems);
+    for (int64_t i = 0; i < nitems; i++) {
+        const int S = s.sn_item[4 * i], len = s.sn_item[4 * i + 2];
+        const int w = s.sn_rec[4 * (size_t)S + 1];
+        s.sn_item2[4 * i] = s.sn_rec[4 * (size_t)S] + (w - len);
+        s.sn_item2[4 * i + 1] = w;
+        s.sn_item2[4 * i + 2] = (int)(uint32_t)(uint64_t)s.sn_moff[i];
+        s.sn_item2[4 * i + 3] = (int)(uint32_t)((uint64_t)s.sn_moff[i] >> 32);
+    }
     for (int q = 0; q < nl; q++) s.sn_task_lvl[q + 1] += s.sn_task_lvl[q];
     // inside each level: heavy tasks (rows of R times suffix rows at least kHeavyTask, or an
     // item with at least kHeavyRows rows of R: its rows split over four wavefronts) first, a
