@@ -331,8 +331,8 @@ int upload_all(cktlu_ctx *c) {
         dfree(d.gscale);
         dfree(d.sscale);
     }
-    if ((rc = upload(d.snl_seq, s.snl_seq, st))) return rc;
-    if ((rc = upload(d.snu_seq, s.snu_seq, st))) return rc;
+    if ((rc = upload(d.snl_seq, s.snl_sw, st))) return rc;
+    if ((rc = upload(d.snu_seq, s.snu_sw, st))) return rc;
     if ((rc = upload(d.snl_unit, s.snl_unit, st))) return rc;
     if ((rc = upload(d.snl_urange, s.snl_urange, st))) return rc;
     if ((rc = upload(d.snl_runs, s.snl_runs, st))) return rc;

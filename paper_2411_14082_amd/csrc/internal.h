@@ -200,6 +200,8 @@ struct Schedule {
     std::vector<int> snl_lvl, snl_tiny, snl_single, snl_seq, snu_lvl, snu_tiny, snu_single, snu_seq;
     std::vector<int> snl_unit, snl_ulvl, snu_unit, snu_ulvl;
     std::vector<int> snl_urange, snl_runs, snu_urange, snu_runs;
+    // the device copies of the sequences: int2 {first column, width} per position
+    std::vector<int> snl_sw, snu_sw;
     int snl_nscr = 0, snu_nscr = 0;
 };
 
@@ -224,7 +226,7 @@ struct Device {
     DevBuf Acp, Acj, Acsrc;
     DevBuf sn_rec, sn_cb, sn_seq, sn_task, sn_item, sn_moff, sn_map;   // supernodal sweep
     DevBuf sn_item2;
-    DevBuf snl_seq, snu_seq, Lrp, Urp;                                 // supernodal solves
+    DevBuf snl_seq, snu_seq, Lrp, Urp;                                 // supernodal solves ({s0, w} per position)
     DevBuf snl_unit, snu_unit, sn_part, sn_cnt;                        // their split units
     DevBuf snl_urange, snl_runs, snu_urange, snu_runs;                 // the units' runs
     DevBuf sn_punit, sn_sunit;                                         // split panels
@@ -335,9 +337,9 @@ struct SolveArgs {
 // wavefront per supernode seq[stiny, smid) and a workgroup per unit units[ubeg, uend) (int4
 // {position in seq, slice, slices, first scratch block}); cnt: an arrival counter per seq
 // position and instance, zero on entry and on exit.
-int launch_sn_lsolve(const SolveArgs &a, const int *seq, const int *units, const int *urange, const int *runs, int sbeg,
+int launch_sn_lsolve(const SolveArgs &a, const int *sw, const int *units, const int *urange, const int *runs, int sbeg,
                      int stiny, int smid, int ubeg, int uend, int *cnt, void *stream);
-int launch_sn_usolve(const SolveArgs &a, const int *seq, const int *units, const int *urange, const int *runs, int sbeg,
+int launch_sn_usolve(const SolveArgs &a, const int *sw, const int *units, const int *urange, const int *runs, int sbeg,
                      int stiny, int smid, int ubeg, int uend, int *cnt, void *stream);
 
 // Solve positions [lbeg, lend) of lrec / urec (one level of the solve graph).

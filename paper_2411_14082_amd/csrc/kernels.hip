@@ -635,12 +635,13 @@ __device__ __forceinline__ void sn_triangle(Elem elem, double *y, int s0, int w,
 // stores its row sums in its scratch block and counts its arrival, and the last unit to arrive
 // adds the P blocks (the even units and the odd units in ascending order, by two halves of its
 // threads, then the two halves: the same sums whichever unit is last) and solves the triangle.
-// Every unit loads the diagonal block into LDS while it pulls.
+// Every unit loads the diagonal block into LDS while it pulls.  sw holds, per position of the
+// level sequence, the supernode's first column and width (int2).
 constexpr int kSnSolveWG = 1024;                     // threads of a supernodal solve workgroup
 constexpr int kSolveWholeBatch = 8;
 constexpr int kSnSolveWaves = kSnSolveWG / WAVE;
 template <typename T, int NR, bool UPPER>
-__global__ __launch_bounds__(kSnSolveWG) void sn_solve_kernel(SolveArgs a, const int *seq, const int *units,
+__global__ __launch_bounds__(kSnSolveWG) void sn_solve_kernel(SolveArgs a, const int *sw, const int *units,
                                                               const int *urange, const int *runs, int sbeg, int stiny,
                                                               int smid, int ubeg, int *cnt, int whole) {
     __shared__ double wsum[8][8][WAVE];                  // the wavefronts' sums, [wavefront][rhs][row]
@@ -661,7 +662,7 @@ __global__ __launch_bounds__(kSnSolveWG) void sn_solve_kernel(SolveArgs a, const
         if (gid >= ntiny) return;
         const int inst = (int)(gid % a.batch);
         if (a.skip && a.skip[inst] != -1) return;
-        const int i = a.sn_rec[4 * seq[sbeg + (int)(gid / a.batch)]];
+        const int i = sw[2 * (sbeg + (int)(gid / a.batch))];
         const int l16 = lane & 15;
         const T *Fx = reinterpret_cast<const T *>(a.Fx) + (size_t)inst * a.nnzF;
         double *y = a.y + (size_t)inst * a.n * NR;
@@ -703,7 +704,7 @@ __global__ __launch_bounds__(kSnSolveWG) void sn_solve_kernel(SolveArgs a, const
         if (wid >= nsingle) return;
         const int inst = (int)(wid % a.batch);
         if (a.skip && a.skip[inst] != -1) return;
-        const int4 rec = reinterpret_cast<const int4 *>(a.sn_rec)[seq[stiny + (int)(wid / a.batch)]];
+        const int2 rec = reinterpret_cast<const int2 *>(sw)[stiny + (int)(wid / a.batch)];
         const int s0 = rec.x, w = rec.y;
         if (w == 1) {
             solve_row_rec<T, NR, UPPER>(a, inst, make_int4(s0, rp[s0], rp[s0 + 1], a.sn_cb[s0]), lane);
@@ -869,7 +870,7 @@ __global__ __launch_bounds__(kSnSolveWG) void sn_solve_kernel(SolveArgs a, const
 }
 
 template <bool UPPER>
-static int launch_sn_solve_impl(const SolveArgs &a, const int *seq, const int *units, const int *urange,
+static int launch_sn_solve_impl(const SolveArgs &a, const int *sw, const int *units, const int *urange,
                                 const int *runs, int sbeg, int stiny, int smid, int ubeg, int uend, int *cnt,
                                 void *stream) {
     // a batch of kSolveWholeBatch instances or more fills the device with one workgroup per
@@ -884,10 +885,10 @@ static int launch_sn_solve_impl(const SolveArgs &a, const int *seq, const int *u
 #define CKTLU_SNS_CASE(NRV)                                                                             \
     case NRV:                                                                                           \
         if (a.fp32)                                                                                     \
-            hipLaunchKernelGGL((sn_solve_kernel<float, NRV, UPPER>), grid, dim3(kSnSolveWG), 0, st, a, seq, units, \
+            hipLaunchKernelGGL((sn_solve_kernel<float, NRV, UPPER>), grid, dim3(kSnSolveWG), 0, st, a, sw, units, \
                                urange, runs, sbeg, stiny, smid, ubeg, cnt, whole);                      \
         else                                                                                            \
-            hipLaunchKernelGGL((sn_solve_kernel<double, NRV, UPPER>), grid, dim3(kSnSolveWG), 0, st, a, seq, units, \
+            hipLaunchKernelGGL((sn_solve_kernel<double, NRV, UPPER>), grid, dim3(kSnSolveWG), 0, st, a, sw, units, \
                                urange, runs, sbeg, stiny, smid, ubeg, cnt, whole);                      \
         break;
     switch (a.nrhs) {
@@ -901,13 +902,13 @@ static int launch_sn_solve_impl(const SolveArgs &a, const int *seq, const int *u
     return (int)hipGetLastError();
 }
 
-int launch_sn_lsolve(const SolveArgs &a, const int *seq, const int *units, const int *urange, const int *runs, int sbeg,
+int launch_sn_lsolve(const SolveArgs &a, const int *sw, const int *units, const int *urange, const int *runs, int sbeg,
                      int stiny, int smid, int ubeg, int uend, int *cnt, void *stream) {
-    return launch_sn_solve_impl<false>(a, seq, units, urange, runs, sbeg, stiny, smid, ubeg, uend, cnt, stream);
+    return launch_sn_solve_impl<false>(a, sw, units, urange, runs, sbeg, stiny, smid, ubeg, uend, cnt, stream);
 }
-int launch_sn_usolve(const SolveArgs &a, const int *seq, const int *units, const int *urange, const int *runs, int sbeg,
+int launch_sn_usolve(const SolveArgs &a, const int *sw, const int *units, const int *urange, const int *runs, int sbeg,
                      int stiny, int smid, int ubeg, int uend, int *cnt, void *stream) {
-    return launch_sn_solve_impl<true>(a, seq, units, urange, runs, sbeg, stiny, smid, ubeg, uend, cnt, stream);
+    return launch_sn_solve_impl<true>(a, sw, units, urange, runs, sbeg, stiny, smid, ubeg, uend, cnt, stream);
 }
 
 // A run of narrow levels [l0, l1): one workgroup per instance takes the rows of a

@@ -504,6 +504,15 @@ static void build_supernodal(const Factor &f, Schedule &s, int T, int wmax, int 
                  s.snl_runs, s.snl_ulvl, s.snl_nscr);
     solve_levels(true, s.snu_levels, s.snu_lvl, s.snu_tiny, s.snu_single, s.snu_seq, s.snu_unit, s.snu_urange,
                  s.snu_runs, s.snu_ulvl, s.snu_nscr);
+    for (int up = 0; up < 2; up++) {
+        const std::vector<int> &seq = up ? s.snu_seq : s.snl_seq;
+        std::vector<int> &sw = up ? s.snu_sw : s.snl_sw;
+        sw.resize(2 * seq.size());
+        for (size_t q = 0; q < seq.size(); q++) {
+            sw[2 * q] = s0v[seq[q]];
+            sw[2 * q + 1] = s0v[seq[q] + 1] - s0v[seq[q]];
+        }
+    }
     // (runs never outnumber the entries, which the int row pointers index)
     // ---- slot map: where each row of R lands in the target column (struct R is inside it)
     s.sn_map.resize((size_t)moff);
