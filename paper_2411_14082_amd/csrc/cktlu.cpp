@@ -883,7 +883,7 @@ int tri_solves(cktlu_ctx *c, int nrhs, int batch, double *z, bool fp32, const in
     int launches = 0;
     for (int l = 0; snodal && l < s.snl_levels; l++, launches++)
         LCHK(launch_sn_lsolve(a, (const int *)d.snl_seq.p, (const int *)d.snl_unit.p, (const int *)d.snl_urange.p,
-                              (const int *)d.snl_runs.p, s.snl_lvl[l], s.snl_tiny[l],
+                              (const int *)d.snl_runs.p, s.snl_first[l], s.snl_tiny[l],
                               s.snl_single[l],
                               s.snl_ulvl[l], s.snl_ulvl[l + 1], (int *)d.sn_cnt.p, st));
     const int ldense = s.tail0 < c->an.n ? (int)s.lsptr.size() - 2 : -1;   // level of the dense rows
@@ -911,7 +911,7 @@ int tri_solves(cktlu_ctx *c, int nrhs, int batch, double *z, bool fp32, const in
     launches = 0;
     for (int l = 0; snodal && l < s.snu_levels; l++, launches++)
         LCHK(launch_sn_usolve(a, (const int *)d.snu_seq.p, (const int *)d.snu_unit.p, (const int *)d.snu_urange.p,
-                              (const int *)d.snu_runs.p, s.snu_lvl[l], s.snu_tiny[l],
+                              (const int *)d.snu_runs.p, s.snu_first[l], s.snu_tiny[l],
                               s.snu_single[l],
                               s.snu_ulvl[l], s.snu_ulvl[l + 1],
                               d.sn_cnt.p ? (int *)d.sn_cnt.p + (size_t)s.sn_count * batch : nullptr, st));

@@ -198,6 +198,9 @@ struct Schedule {
     // the runs [snl_urange[4u], snl_urange[4u+1]) of supernode [snl_urange[4u+2], + snl_urange[4u+3]).
     int snl_levels = 0, snu_levels = 0;
     std::vector<int> snl_lvl, snl_tiny, snl_single, snl_seq, snu_lvl, snu_tiny, snu_single, snu_seq;
+    // first position of level l that a launch takes (L: singletons with no L entries come
+    // first and need nothing; U: snu_lvl[l])
+    std::vector<int> snl_first, snu_first;
     std::vector<int> snl_unit, snl_ulvl, snu_unit, snu_ulvl;
     std::vector<int> snl_urange, snl_runs, snu_urange, snu_runs;
     // the device copies of the sequences: int2 {first column, width} per position

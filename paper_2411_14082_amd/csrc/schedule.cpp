@@ -389,7 +389,7 @@ static void build_supernodal(const Factor &f, Schedule &s, int T, int wmax, int 
     // solved before the sparse U rows)
     std::vector<int> lastc(n, -2), lastpos(n, -2), recidx(n, 0);
     auto solve_levels = [&](bool upper, int &nlev, std::vector<int> &lvl, std::vector<int> &tiny,
-                            std::vector<int> &single, std::vector<int> &seq, std::vector<int> &unit,
+                            std::vector<int> &single, std::vector<int> &first, std::vector<int> &seq, std::vector<int> &unit,
                             std::vector<int> &urange, std::vector<int> &runs, std::vector<int> &ulvl, int &nscr) {
         std::vector<int> lv(nsn, 0);
         std::vector<int64_t> pull(nsn, 0);            // entries outside the diagonal block
@@ -414,29 +414,37 @@ static void build_supernodal(const Factor &f, Schedule &s, int T, int wmax, int 
         // sixteen lanes per singleton with at most kSolveTinyRow entries; a wavefront per other
         // supernode of at most kSnSmallW rows with a short pull; a workgroup per unit of every
         // other supernode
+        // (L only: a singleton that pulls nothing has y_i = b_i already: nothing to launch; it
+        // is placed first in its level, before first[l])
         auto kind = [&](int S) {
             const int w = s0v[S + 1] - s0v[S];
-            if (w == 1 && pull[S] <= kSolveTinyRow) return 0;
-            return w <= cktlu_dev::kSnSmallW && pull[S] < kSolveLongRow ? 1 : 2;
+            if (!upper && w == 1 && pull[S] == 0) return 0;
+            if (w == 1 && pull[S] <= kSolveTinyRow) return 1;
+            return w <= cktlu_dev::kSnSmallW && pull[S] < kSolveLongRow ? 2 : 3;
         };
-        std::vector<int> c(nlev + 1, 0), c0(nlev, 0), c1(nlev, 0);
+        std::vector<int> c(nlev + 1, 0), cn(nlev, 0), c0(nlev, 0), c1(nlev, 0);
         for (int S = 0; S < nsn; S++) {
             c[lv[S] + 1]++;
             const int k = kind(S);
-            if (k == 0) c0[lv[S]]++;
-            else if (k == 1) c1[lv[S]]++;
+            if (k == 0) cn[lv[S]]++;
+            else if (k == 1) c0[lv[S]]++;
+            else if (k == 2) c1[lv[S]]++;
         }
         for (int l2 = 0; l2 < nlev; l2++) c[l2 + 1] += c[l2];
         lvl.assign(c.begin(), c.end());
+        first.resize(nlev);
         tiny.resize(nlev);
         single.resize(nlev);
-        std::vector<int> f[3] = {std::vector<int>(nlev), std::vector<int>(nlev), std::vector<int>(nlev)};
+        std::vector<int> f[4] = {std::vector<int>(nlev), std::vector<int>(nlev), std::vector<int>(nlev),
+                                 std::vector<int>(nlev)};
         for (int l2 = 0; l2 < nlev; l2++) {
-            tiny[l2] = c[l2] + c0[l2];
-            single[l2] = c[l2] + c0[l2] + c1[l2];
+            first[l2] = c[l2] + cn[l2];
+            tiny[l2] = first[l2] + c0[l2];
+            single[l2] = tiny[l2] + c1[l2];
             f[0][l2] = c[l2];
-            f[1][l2] = tiny[l2];
-            f[2][l2] = single[l2];
+            f[1][l2] = first[l2];
+            f[2][l2] = tiny[l2];
+            f[3][l2] = single[l2];
         }
         seq.resize(nsn);
         for (int S = 0; S < nsn; S++) seq[f[kind(S)][lv[S]]++] = S;
@@ -500,10 +508,10 @@ static void build_supernodal(const Factor &f, Schedule &s, int T, int wmax, int 
             nscr = std::max(nscr, blocks);
         }
     };
-    solve_levels(false, s.snl_levels, s.snl_lvl, s.snl_tiny, s.snl_single, s.snl_seq, s.snl_unit, s.snl_urange,
-                 s.snl_runs, s.snl_ulvl, s.snl_nscr);
-    solve_levels(true, s.snu_levels, s.snu_lvl, s.snu_tiny, s.snu_single, s.snu_seq, s.snu_unit, s.snu_urange,
-                 s.snu_runs, s.snu_ulvl, s.snu_nscr);
+    solve_levels(false, s.snl_levels, s.snl_lvl, s.snl_tiny, s.snl_single, s.snl_first, s.snl_seq, s.snl_unit,
+                 s.snl_urange, s.snl_runs, s.snl_ulvl, s.snl_nscr);
+    solve_levels(true, s.snu_levels, s.snu_lvl, s.snu_tiny, s.snu_single, s.snu_first, s.snu_seq, s.snu_unit,
+                 s.snu_urange, s.snu_runs, s.snu_ulvl, s.snu_nscr);
     for (int up = 0; up < 2; up++) {
         const std::vector<int> &seq = up ? s.snu_seq : s.snl_seq;
         std::vector<int> &sw = up ? s.snu_sw : s.snl_sw;
