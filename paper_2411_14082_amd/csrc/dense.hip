@@ -1012,10 +1012,10 @@ __device__ __forceinline__ void sn_fail(const RefactorArgs &a, int inst, int lev
     atomicExch(&a.ctrl[1 + inst], lev + 1);          // every writer of this launch writes the same
 }
 
-// Small supernodes (w <= kSnSmallW columns): one wavefront per (supernode, instance).
-// A singleton (one column j): the pivot test on its values before division (Section II-A: fail
-// when x(j) is zero or not finite, or |x(j)| < eps max |L part|), then L(:,j) = x / x(j), four
-// loads in flight.  A small panel: lane r < w holds row r of the diagonal block, factored by
+// Small supernodes (w <= kSnSmallW columns).  A singleton (one column j; sixteen lanes, see
+// sn_single_kernel): the pivot test on its values before division (Section II-A: fail when
+// x(j) is zero or not finite, or |x(j)| < eps max |L part|), then L(:,j) = x / x(j).  A small
+// panel (one wavefront per unit and instance): lane r < w holds row r of the diagonal block, factored by
 // right-looking steps (column c: L(r, c) = x(r, c) / u_cc below the diagonal, then
 // x(r, c') -= L(r, c) U(c, c') for c' > c); the rows of R, 64 at a time (a row per lane), by
 // the same steps with U11 read from the block's lanes.  The pivot test of column c is taken
@@ -1134,31 +1134,34 @@ __global__ __launch_bounds__(256) void sn_small_kernel(RefactorArgs a, int lev, 
     sn_small_panel<T>(a, inst, lev, rec.x, rec.y, rec.z, un, lane);
 }
 
+// Singleton supernodes: sixteen lanes per (column, instance), four entries per lane in flight:
+// the pivot test on the values before division (their maximum over the sixteen lanes), then
+// L = x / pivot, as one wavefront per column would.
 template <typename T>
 __global__ __launch_bounds__(256) void sn_single_kernel(RefactorArgs a, int lev, int sbeg, int send) {
-    const int lane = threadIdx.x & (WAVE - 1);
-    const int64_t w = (int64_t)blockIdx.x * 4 + threadIdx.x / WAVE;
-    if (w >= (int64_t)(send - sbeg) * a.batch) return;
-    const int inst = (int)(w % a.batch);
-    const int j = a.sn_rec[4 * a.sn_seq[sbeg + (int)(w / a.batch)]];
-    if (sn_stopped(a, inst, lev)) return;
+    const int l16 = threadIdx.x & 15;
+    const int64_t g = (int64_t)blockIdx.x * 16 + threadIdx.x / 16;
+    if (g >= (int64_t)(send - sbeg) * a.batch) return;
+    const int inst = (int)(g % a.batch);
+    const int j = a.sn_rec[4 * a.sn_seq[sbeg + (int)(g / a.batch)]];
+    if (sn_stopped(a, inst, lev)) return;                 // uniform over the sixteen lanes
     T *x = reinterpret_cast<T *>(a.Fx) + (size_t)inst * a.nnzF + a.Dp[j];
     const int nu = a.nU[j], len = a.Dlen[j];
     const T d = x[nu - 1];
     double m = 0.0;
-    for (int i0 = nu; i0 < len; i0 += 4 * WAVE) {
+    for (int i0 = nu; i0 < len; i0 += 64) {
         T v[4];
 #pragma unroll
-        for (int u = 0; u < 4; u++) v[u] = i0 + u * WAVE + lane < len ? x[i0 + u * WAVE + lane] : T(0);
+        for (int u = 0; u < 4; u++) v[u] = i0 + 16 * u + l16 < len ? x[i0 + 16 * u + l16] : T(0);
 #pragma unroll
         for (int u = 0; u < 4; u++) {
             m = nanmax(m, fabs((double)v[u]));
-            if (i0 + u * WAVE + lane < len) x[i0 + u * WAVE + lane] = v[u] / d;
+            if (i0 + 16 * u + l16 < len) x[i0 + 16 * u + l16] = v[u] / d;
         }
     }
 #pragma unroll
-    for (int off = 32; off > 0; off >>= 1) m = nanmax(m, __shfl_xor(m, off));
-    if (lane != 0) return;
+    for (int off = 8; off > 0; off >>= 1) m = nanmax(m, __shfl_xor(m, off, 16));
+    if (l16 != 0) return;
     const double dd = (double)d;
     if (a.check && (!isfinite(dd) || dd == 0.0 || !isfinite(m) || fabs(dd) < a.eps * m || j == a.force_fail_col))
         sn_fail(a, inst, lev, j);
@@ -1822,9 +1825,9 @@ int launch_dense_solve(const DenseArgs &a, double *y, int nrhs, const int *skip,
 int launch_sn_panels(const RefactorArgs &a, int lev, int sbeg, int s1, int sub, int sue, int ubeg, int uend,
                      void *stream) {
     hipStream_t st = (hipStream_t)stream;
-    const int64_t waves = (int64_t)(s1 - sbeg) * a.batch;
-    if (waves > 0) {
-        const dim3 grid((unsigned)((waves + 3) / 4));
+    const int64_t groups = (int64_t)(s1 - sbeg) * a.batch;   // sixteen lanes each
+    if (groups > 0) {
+        const dim3 grid((unsigned)((groups + 15) / 16));
         if (a.fp32) hipLaunchKernelGGL(sn_single_kernel<float>, grid, dim3(256), 0, st, a, lev, sbeg, s1);
         else hipLaunchKernelGGL(sn_single_kernel<double>, grid, dim3(256), 0, st, a, lev, sbeg, s1);
         const hipError_t e = hipGetLastError();
