@@ -65,25 +65,37 @@ __device__ __forceinline__ double wave_sum(double v) {
 }
 
 // ------------------------------------------------------------ refactorize
-// one wavefront per (column, instance).  Columns of the dense block keep their
-// rows >= T in S (column k at S + (k - T) D), so those rows are zeroed there.
+// sixteen lanes per (sparse column, instance), one wavefront per (dense-block column,
+// instance).  Columns of the dense block keep their rows >= T in S (column k at
+// S + (k - T) D), so those rows are zeroed there.
 template <typename T>
-__global__ __launch_bounds__(WG) void refactor_init_kernel(RefactorArgs a) {
+__global__ __launch_bounds__(WG) void refactor_init_kernel(RefactorArgs a, unsigned nsb) {
     const int lane = threadIdx.x & (WAVE - 1), wv = threadIdx.x / WAVE;
-    const int64_t w = (int64_t)blockIdx.x * WAVES + wv;
-    if (w >= (int64_t)a.n * a.batch) return;
-    const int inst = (int)(w % a.batch);
-    const int k = (int)(w / a.batch);
-    T *x = reinterpret_cast<T *>(a.Fx) + (size_t)inst * a.nnzF + a.Dp[k];
-    const double *Av = a.Aval + (size_t)inst * a.nnzA;
-    const int len = a.Dlen[k];
-    const int c = a.colperm[k];
-    if (k < a.T) {
-        for (int i = lane; i < len; i += WAVE) x[i] = T(0);
+    const double *Av;
+    if (blockIdx.x < nsb) {
+        // sparse columns: sixteen per workgroup
+        const int l16 = threadIdx.x & 15;
+        const int64_t g = (int64_t)blockIdx.x * 16 + threadIdx.x / 16;
+        if (g >= (int64_t)a.T * a.batch) return;
+        const int inst = (int)(g % a.batch);
+        const int k = (int)(g / a.batch);
+        T *x = reinterpret_cast<T *>(a.Fx) + (size_t)inst * a.nnzF + a.Dp[k];
+        Av = a.Aval + (size_t)inst * a.nnzA;
+        const int len = a.Dlen[k];
+        const int c = a.colperm[k];
+        for (int i = l16; i < len; i += 16) x[i] = T(0);
         wave_sync();
-        for (int p = a.Ap[c] + lane; p < a.Ap[c + 1]; p += WAVE) x[a.amap[p]] = (T)(a.ascale ? Av[p] * a.ascale[p] : Av[p]);
+        for (int p = a.Ap[c] + l16; p < a.Ap[c + 1]; p += 16) x[a.amap[p]] = (T)(a.ascale ? Av[p] * a.ascale[p] : Av[p]);
         return;
     }
+    const int64_t w = (int64_t)(blockIdx.x - nsb) * WAVES + wv;
+    if (w >= (int64_t)(a.n - a.T) * a.batch) return;
+    const int inst = (int)(w % a.batch);
+    const int k = a.T + (int)(w / a.batch);
+    T *x = reinterpret_cast<T *>(a.Fx) + (size_t)inst * a.nnzF + a.Dp[k];
+    Av = a.Aval + (size_t)inst * a.nnzA;
+    const int len = a.Dlen[k];
+    const int c = a.colperm[k];
     T *Sk = reinterpret_cast<T *>(a.S) + (size_t)inst * a.D * a.D + (size_t)(k - a.T) * a.D;
     const int *rows = a.Fi + a.Dp[k];
     for (int i = lane; i < len; i += WAVE) x[i] = T(0);
@@ -401,11 +413,13 @@ int launch_status_out(const int *firstfail, int *status, int batch, void *stream
 
 int launch_refactor_init(const RefactorArgs &a, void *stream) {
     hipStream_t st = (hipStream_t)stream;
-    const int64_t waves = (int64_t)a.n * a.batch;
-    const dim3 grid((unsigned)((waves + WAVES - 1) / WAVES));
-    if (waves == 0) return 0;
-    if (a.fp32) hipLaunchKernelGGL((refactor_init_kernel<float>), grid, dim3(WG), 0, st, a);
-    else hipLaunchKernelGGL((refactor_init_kernel<double>), grid, dim3(WG), 0, st, a);
+    const int64_t sparse = (int64_t)a.T * a.batch, dense = (int64_t)(a.n - a.T) * a.batch;
+    const int64_t nsb = (sparse + 15) / 16, blocks = nsb + (dense + WAVES - 1) / WAVES;
+    if (blocks == 0) return 0;
+    if (blocks > UINT_MAX) return (int)hipErrorInvalidValue;
+    const dim3 grid((unsigned)blocks);
+    if (a.fp32) hipLaunchKernelGGL((refactor_init_kernel<float>), grid, dim3(WG), 0, st, a, (unsigned)nsb);
+    else hipLaunchKernelGGL((refactor_init_kernel<double>), grid, dim3(WG), 0, st, a, (unsigned)nsb);
     return (int)hipGetLastError();
 }
 
