@@ -353,7 +353,12 @@ int upload_all(cktlu_ctx *c) {
     if ((rc = upload(d.lsptr, s.lsptr, st))) return rc;
     if ((rc = upload(d.usptr, s.usptr, st))) return rc;
     if ((rc = upload(d.rowperm, s.rowperm_final, st))) return rc;
-    if ((rc = upload(d.colperm_sol, c->an.colperm, st))) return rc;
+    {
+        // the solution scatter takes, per user index, its solve position
+        std::vector<int> inv(c->an.colperm.size());
+        for (size_t k = 0; k < inv.size(); k++) inv[c->an.colperm[k]] = (int)k;
+        if ((rc = upload(d.colperm_sol, inv, st))) return rc;
+    }
     if ((rc = upload(d.Acp, s.Acp, st))) return rc;
     if ((rc = upload(d.Acj, s.Acj, st))) return rc;
     if ((rc = upload(d.Acsrc, s.Acsrc, st))) return rc;

@@ -225,7 +225,7 @@ struct Device {
     // pattern / schedule
     DevBuf seq, Dp, Dlen, Fi, nU, Ap, colperm, amap;
     DevBuf colrec, task8, item4, smap, tmoff, tail_nb, l21, schur_parts, schur_add, schur_scr;
-    DevBuf lrec, urec, Lrjs, Urjs, lsptr, usptr, rowperm, colperm_sol;
+    DevBuf lrec, urec, Lrjs, Urjs, lsptr, usptr, rowperm, colperm_sol;   // colperm_sol: user index -> position
     DevBuf Acp, Acj, Acsrc;
     DevBuf sn_rec, sn_cb, sn_seq, sn_task, sn_item, sn_moff, sn_map;   // supernodal sweep
     DevBuf sn_item2;
@@ -358,8 +358,8 @@ int launch_usolve_chain(const SolveArgs &a, const int *lvptr, int l0, int l1, vo
 // y[((i*n + k)*ns + r] = b[(i*nrhs + r)*ldb + perm[k]] for r < nrhs, 0 for r < ns = solve_slots(nrhs)
 int launch_gather_rhs(int n, int nrhs, int batch, const double *b, int64_t ldb, const int *perm,
                       double *y, void *stream, const double *scale = nullptr);
-// x[(i*nrhs + r)*ldx + perm[k]] (+)= y[(i*n + k)*solve_slots(nrhs) + r]
-int launch_scatter_sol(int n, int nrhs, int batch, const double *z, const int *perm, double *x,
+// x[(i*nrhs + r)*ldx + j] (+)= y[(i*n + inv[j])*solve_slots(nrhs) + r]; inv: user index -> solve position
+int launch_scatter_sol(int n, int nrhs, int batch, const double *z, const int *inv, double *x,
                        int64_t ldx, int accumulate, const int *skip, void *stream, const double *scale = nullptr);
 // r = b - A x (user space, FP64), per rhs; also writes |r|_inf, |x|_inf, |b|_inf maxima.  Nothing
 // when skip is given and *skip != -1.

@@ -1048,20 +1048,25 @@ __global__ void gather_rhs_kernel(int n, int nrhs, int nslots, int batch, const 
     }
 }
 
-// scale (may be null): per solve position, the static column scaling of its user column
-__global__ void scatter_sol_kernel(int n, int nrhs, int nslots, int batch, const double *z, const int *perm,
+// x[(i*nrhs + r)*ldx + j] (+)= z[(i*n + inv[j])*nslots + r]: a thread per (user index j,
+// instance), so that the writes of each right-hand side are consecutive in j; inv: user index ->
+// solve position.  scale (may be null): per solve position, the static column scaling of its
+// user column
+__global__ void scatter_sol_kernel(int n, int nrhs, int nslots, int batch, const double *z, const int *inv,
                                    double *x, int64_t ldx, int accumulate, const int *skip, const double *scale) {
-    const int64_t total = (int64_t)n * nrhs * batch;
+    const int64_t total = (int64_t)n * batch;
     for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < total;
          t += (int64_t)gridDim.x * blockDim.x) {
-        const int r = (int)(t % nrhs);
-        const int64_t ik = t / nrhs;
-        const int k = (int)(ik % n);
-        const int64_t i = ik / n;
+        const int j = (int)(t % n);
+        const int64_t i = t / n;
         if (skip && skip[i] != -1) continue;
-        double *dst = x + (i * nrhs + r) * ldx + perm[k];
-        const double v = scale ? z[ik * nslots + r] * scale[k] : z[ik * nslots + r];
-        *dst = accumulate ? *dst + v : v;
+        const int k = inv[j];
+        const double *zr = z + ((size_t)i * n + k) * nslots;
+        for (int r = 0; r < nrhs; r++) {
+            double *dst = x + (i * nrhs + r) * ldx + j;
+            const double v = scale ? zr[r] * scale[k] : zr[r];
+            *dst = accumulate ? *dst + v : v;
+        }
     }
 }
 
@@ -1080,10 +1085,10 @@ int launch_gather_rhs(int n, int nrhs, int batch, const double *b, int64_t ldb, 
     return (int)hipGetLastError();
 }
 
-int launch_scatter_sol(int n, int nrhs, int batch, const double *z, const int *perm, double *x,
+int launch_scatter_sol(int n, int nrhs, int batch, const double *z, const int *inv, double *x,
                        int64_t ldx, int accumulate, const int *skip, void *stream, const double *scale) {
-    hipLaunchKernelGGL(scatter_sol_kernel, dim3(grid_for((int64_t)n * nrhs * batch, 256)), dim3(256), 0,
-                       (hipStream_t)stream, n, nrhs, solve_slots(nrhs), batch, z, perm, x, ldx, accumulate, skip,
+    hipLaunchKernelGGL(scatter_sol_kernel, dim3(grid_for((int64_t)n * batch, 256)), dim3(256), 0,
+                       (hipStream_t)stream, n, nrhs, solve_slots(nrhs), batch, z, inv, x, ldx, accumulate, skip,
                        scale);
     return (int)hipGetLastError();
 }
@@ -1104,28 +1109,46 @@ __device__ __forceinline__ double wave_max_keep_nan(double v) {
 // r = b - A x for up to eight right-hand sides [r0, r0 + nr) of one instance: every thread takes
 // rows i (grid stride) and reads row i of A once for all of them, keeps running maxima of
 // |r|, |x|, |b| and the wavefront adds them to norms with one atomic each.
+template <int NRM>
 __device__ __forceinline__ void residual_rows(int n, int nr, const int *Acp, const int *Acj, const int *Acsrc,
                                               const double *Aval, const double *x, int64_t ldx, const double *b,
                                               int64_t ldb, double *r, int64_t ldr, double *norms, int64_t i0,
                                               int64_t stride) {
+    constexpr int E = NRM == 1 ? 4 : 2;                 // entries whose loads are in flight together
     double mr[8], mx[8], mb[8];
 #pragma unroll
     for (int u = 0; u < 8; u++) mr[u] = mx[u] = mb[u] = 0.0;
     for (int64_t i = i0; i < n; i += stride) {
-        double acc[8];
+        double acc[NRM];
 #pragma unroll
-        for (int u = 0; u < 8; u++) acc[u] = u < nr ? b[u * ldb + i] : 0.0;
+        for (int u = 0; u < NRM; u++) acc[u] = u < nr ? b[u * ldb + i] : 0.0;
 #pragma unroll
-        for (int u = 0; u < 8; u++) mb[u] = max_keep_nan(mb[u], fabs(acc[u]));
-        for (int p = Acp[i]; p < Acp[i + 1]; p++) {
-            const double v = Aval[Acsrc[p]];
-            const int j = Acj[p];
+        for (int u = 0; u < NRM; u++) mb[u] = max_keep_nan(mb[u], fabs(acc[u]));
+        const int pe = Acp[i + 1];
+        for (int p0 = Acp[i]; p0 < pe; p0 += E) {       // E entries' loads in flight, then in order
+            int src[E], j[E];
 #pragma unroll
-            for (int u = 0; u < 8; u++)
-                if (u < nr) acc[u] -= v * x[u * ldx + j];
+            for (int q = 0; q < E; q++) {
+                src[q] = p0 + q < pe ? Acsrc[p0 + q] : 0;
+                j[q] = p0 + q < pe ? Acj[p0 + q] : 0;
+            }
+            double v[E], xv[E][NRM];
+#pragma unroll
+            for (int q = 0; q < E; q++) {
+                v[q] = p0 + q < pe ? Aval[src[q]] : 0.0;
+#pragma unroll
+                for (int u = 0; u < NRM; u++) xv[q][u] = (p0 + q < pe && u < nr) ? x[u * ldx + j[q]] : 0.0;
+            }
+#pragma unroll
+            for (int q = 0; q < E; q++)
+                if (p0 + q < pe) {
+#pragma unroll
+                    for (int u = 0; u < NRM; u++)
+                        if (u < nr) acc[u] -= v[q] * xv[q][u];
+                }
         }
 #pragma unroll
-        for (int u = 0; u < 8; u++)
+        for (int u = 0; u < NRM; u++)
             if (u < nr) {
                 r[u * ldr + i] = acc[u];
                 mr[u] = max_keep_nan(mr[u], fabs(acc[u]));
@@ -1137,7 +1160,7 @@ __device__ __forceinline__ void residual_rows(int n, int nr, const int *Acp, con
     __shared__ double wmax[4][24];
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
 #pragma unroll
-    for (int u = 0; u < 8; u++) {
+    for (int u = 0; u < NRM; u++) {
         const double a0 = wave_max_keep_nan(mr[u]), a1 = wave_max_keep_nan(mx[u]), a2 = wave_max_keep_nan(mb[u]);
         if (lane == 0) {
             wmax[wv][3 * u + 0] = a0;
@@ -1154,6 +1177,7 @@ __device__ __forceinline__ void residual_rows(int n, int nr, const int *Acp, con
     __syncthreads();
 }
 
+template <int NRM>
 __global__ __launch_bounds__(256) void residual_kernel(int n, int nrhs, const int *Acp, const int *Acj,
                                                        const int *Acsrc, const double *Aval, const double *x,
                                                        int64_t ldx, const double *b, int64_t ldb, double *r,
@@ -1161,7 +1185,7 @@ __global__ __launch_bounds__(256) void residual_kernel(int n, int nrhs, const in
     if (skip && *skip != -1) return;
     const int64_t i0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x, stride = (int64_t)gridDim.x * blockDim.x;
     for (int r0 = 0; r0 < nrhs; r0 += 8)
-        residual_rows(n, min(8, nrhs - r0), Acp, Acj, Acsrc, Aval, x + r0 * ldx, ldx, b + r0 * ldb, ldb,
+        residual_rows<NRM>(n, min(8, nrhs - r0), Acp, Acj, Acsrc, Aval, x + r0 * ldx, ldx, b + r0 * ldb, ldb,
                       r + r0 * ldr, ldr, norms + 3 * r0, i0, stride);
 }
 
@@ -1169,32 +1193,61 @@ int launch_residual(int n, int nrhs, const int *Acp, const int *Acj, const int *
                     const double *Aval, const double *x, int64_t ldx, const double *b, int64_t ldb,
                     double *r, int64_t ldr, double *norms, void *stream, const int *skip) {
     const int grid = std::min(grid_for(n, 256), 1024);   // a few rows per thread, few atomics
-    hipLaunchKernelGGL(residual_kernel, dim3(grid), dim3(256), 0, (hipStream_t)stream, n, nrhs,
-                       Acp, Acj, Acsrc, Aval, x, ldx, b, ldb, r, ldr, norms, skip);
+    if (nrhs == 1)
+        hipLaunchKernelGGL(residual_kernel<1>, dim3(grid), dim3(256), 0, (hipStream_t)stream, n, nrhs,
+                           Acp, Acj, Acsrc, Aval, x, ldx, b, ldb, r, ldr, norms, skip);
+    else
+        hipLaunchKernelGGL(residual_kernel<8>, dim3(grid), dim3(256), 0, (hipStream_t)stream, n, nrhs,
+                           Acp, Acj, Acsrc, Aval, x, ldx, b, ldb, r, ldr, norms, skip);
     return (int)hipGetLastError();
+}
+
+// max over rows i (grid stride from i0) of sum |A(i, :)|, four entries' loads in flight; the
+// workgroup's maximum goes to *out with one atomic (they serialize on one address)
+__device__ __forceinline__ void anorm_rows(int n, const int *Acp, const int *Acsrc, const double *Aval, double *out,
+                                           int i0, int stride) {
+    double m = 0.0;
+    for (int i = i0; i < n; i += stride) {
+        double s = 0.0;
+        const int pe = Acp[i + 1];
+        for (int p0 = Acp[i]; p0 < pe; p0 += 4) {
+            int src[4];
+#pragma unroll
+            for (int q = 0; q < 4; q++) src[q] = p0 + q < pe ? Acsrc[p0 + q] : -1;
+            double v[4];
+#pragma unroll
+            for (int q = 0; q < 4; q++) v[q] = src[q] >= 0 ? fabs(Aval[src[q]]) : 0.0;
+#pragma unroll
+            for (int q = 0; q < 4; q++) s += v[q];
+        }
+        m = max_keep_nan(m, s);
+    }
+    __shared__ double wm[4];
+    m = wave_max_keep_nan(m);
+    if ((threadIdx.x & 63) == 0) wm[threadIdx.x >> 6] = m;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double w = wm[0];
+        for (int q = 1; q < (int)(blockDim.x >> 6); q++) w = max_keep_nan(w, wm[q]);
+        atomic_max_nonneg(out, w);
+    }
 }
 
 __global__ __launch_bounds__(256) void anorm_kernel(int n, const int *Acp, const int *Acsrc, const double *Aval,
                                                     double *out) {
-    double m = 0.0;
-    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
-        double s = 0.0;
-        for (int p = Acp[i]; p < Acp[i + 1]; p++) s += fabs(Aval[Acsrc[p]]);
-        m = max_keep_nan(m, s);
-    }
-    m = wave_max_keep_nan(m);
-    if ((threadIdx.x & 63) == 0) atomic_max_nonneg(out, m);
+    anorm_rows(n, Acp, Acsrc, Aval, out, blockIdx.x * blockDim.x + threadIdx.x, gridDim.x * blockDim.x);
 }
 
 int launch_anorm(int n, const int *Acp, const int *Acsrc, const double *Aval, double *out, void *stream) {
-    hipLaunchKernelGGL(anorm_kernel, dim3(grid_for(n, 256)), dim3(256), 0, (hipStream_t)stream, n, Acp, Acsrc,
-                       Aval, out);
+    hipLaunchKernelGGL(anorm_kernel, dim3(std::min(grid_for(n, 256), 1024)), dim3(256), 0, (hipStream_t)stream, n,
+                       Acp, Acsrc, Aval, out);
     return (int)hipGetLastError();
 }
 
 // Batched refinement: instance i uses values Aval + i*nnzA and vectors at
 // (i*nrhs + r)*n; skip[i] != -1 leaves an instance out.
 // one instance per blockIdx.y
+template <int NRM>
 __global__ __launch_bounds__(256) void residual_batched_kernel(int n, int nrhs, int64_t nnzA, const int *Acp,
                                                                const int *Acj, const int *Acsrc, const double *Aval,
                                                                const double *x, const double *b, double *r,
@@ -1205,7 +1258,7 @@ __global__ __launch_bounds__(256) void residual_batched_kernel(int n, int nrhs, 
     const double *Av = Aval + (size_t)inst * nnzA;
     for (int r0 = 0; r0 < nrhs; r0 += 8) {
         const size_t o = ((size_t)inst * nrhs + r0) * n;
-        residual_rows(n, min(8, nrhs - r0), Acp, Acj, Acsrc, Av, x + o, n, b + o, n, r + o, n,
+        residual_rows<NRM>(n, min(8, nrhs - r0), Acp, Acj, Acsrc, Av, x + o, n, b + o, n, r + o, n,
                       norms + ((size_t)inst * nrhs + r0) * 3, i0, stride);
     }
 }
@@ -1214,15 +1267,8 @@ __global__ __launch_bounds__(256) void residual_batched_kernel(int n, int nrhs, 
 __global__ __launch_bounds__(256) void anorm_batched_kernel(int n, int64_t nnzA, const int *Acp, const int *Acsrc,
                                                             const double *Aval, double *out) {
     const int inst = (int)blockIdx.y;
-    const double *Av = Aval + (size_t)inst * nnzA;
-    double m = 0.0;
-    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
-        double s = 0.0;
-        for (int p = Acp[i]; p < Acp[i + 1]; p++) s += fabs(Av[Acsrc[p]]);
-        m = max_keep_nan(m, s);
-    }
-    m = wave_max_keep_nan(m);
-    if ((threadIdx.x & 63) == 0) atomic_max_nonneg(&out[inst], m);
+    anorm_rows(n, Acp, Acsrc, Aval + (size_t)inst * nnzA, &out[inst], blockIdx.x * blockDim.x + threadIdx.x,
+               gridDim.x * blockDim.x);
 }
 
 // eta[i] = max over right-hand sides of |r| / (|A| |x| + |b|); an instance whose
@@ -1246,8 +1292,13 @@ int launch_residual_batched(int n, int nrhs, int batch, int64_t nnzA, const int 
                             const int *Acsrc, const double *Aval, const double *x, const double *b, double *r,
                             double *norms, const int *skip, void *stream) {
     if (batch <= 0 || n <= 0) return 0;
-    hipLaunchKernelGGL(residual_batched_kernel, dim3(std::min(grid_for(n, 256), 1024), (unsigned)batch), dim3(256), 0,
-                       (hipStream_t)stream, n, nrhs, nnzA, Acp, Acj, Acsrc, Aval, x, b, r, norms, skip);
+    const dim3 grid(std::min(grid_for(n, 256), 1024), (unsigned)batch);
+    if (nrhs == 1)
+        hipLaunchKernelGGL(residual_batched_kernel<1>, grid, dim3(256), 0, (hipStream_t)stream, n, nrhs, nnzA, Acp,
+                           Acj, Acsrc, Aval, x, b, r, norms, skip);
+    else
+        hipLaunchKernelGGL(residual_batched_kernel<8>, grid, dim3(256), 0, (hipStream_t)stream, n, nrhs, nnzA, Acp,
+                           Acj, Acsrc, Aval, x, b, r, norms, skip);
     return (int)hipGetLastError();
 }
 
