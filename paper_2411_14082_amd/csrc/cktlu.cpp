@@ -176,7 +176,7 @@ DevBuf *all_buffers(Device &d, int i) {
                      &d.sn_item, &d.sn_moff, &d.sn_item2, &d.sn_map, &d.snl_seq, &d.snu_seq, &d.Lrp, &d.Urp,
                      &d.ascale, &d.gscale, &d.sscale, &d.schur_sn_items,
                      &d.snl_unit, &d.snu_unit, &d.snl_urange, &d.snl_runs, &d.snu_urange, &d.snu_runs,
-                     &d.sn_part, &d.sn_cnt, &d.sn_punit, &d.sn_sunit, &d.sn_grp, &d.sn_gsrc, &d.sn_gent};
+                     &d.sn_part, &d.sn_cnt, &d.sn_punit, &d.sn_sunit, &d.sn_pu2, &d.sn_su2, &d.sn_grp, &d.sn_gsrc, &d.sn_gent};
     const int cnt = (int)(sizeof(all) / sizeof(all[0]));
     return i < cnt ? all[i] : nullptr;
 }
@@ -338,6 +338,8 @@ int upload_all(cktlu_ctx *c) {
     if ((rc = upload(d.snl_runs, s.snl_runs, st))) return rc;
     if ((rc = upload(d.sn_punit, s.sn_punit, st))) return rc;
     if ((rc = upload(d.sn_sunit, s.sn_sunit, st))) return rc;
+    if ((rc = upload(d.sn_pu2, s.sn_pu2, st))) return rc;
+    if ((rc = upload(d.sn_su2, s.sn_su2, st))) return rc;
     if ((rc = upload(d.sn_grp, s.sn_grp, st))) return rc;
     if ((rc = upload(d.sn_gsrc, s.sn_gsrc, st))) return rc;
     if ((rc = upload(d.sn_gent, s.sn_gent, st))) return rc;
@@ -631,6 +633,8 @@ int run_refactor(cktlu_ctx *c, int batch, const double *values_dev, bool fp32, b
     a.sn_item2 = (const int *)d.sn_item2.p;
     a.sn_punit = (const int *)d.sn_punit.p;
     a.sn_sunit = (const int *)d.sn_sunit.p;
+    a.sn_pu2 = (const int *)d.sn_pu2.p;
+    a.sn_su2 = (const int *)d.sn_su2.p;
     a.sn_grp = (const int *)d.sn_grp.p;
     a.sn_gsrc = (const int *)d.sn_gsrc.p;
     a.sn_gent = (const int *)d.sn_gent.p;

@@ -1129,7 +1129,7 @@ __global__ __launch_bounds__(256) void sn_small_kernel(RefactorArgs a, int lev, 
     if (w >= (int64_t)(uend - ubeg) * a.batch) return;
     const int inst = (int)(w % a.batch);
     const int4 un = reinterpret_cast<const int4 *>(a.sn_sunit)[ubeg + (int)(w / a.batch)];
-    const int4 rec = reinterpret_cast<const int4 *>(a.sn_rec)[a.sn_seq[un.x]];
+    const int4 rec = reinterpret_cast<const int4 *>(a.sn_su2)[ubeg + (int)(w / a.batch)];
     if (sn_stopped(a, inst, lev)) return;
     sn_small_panel<T>(a, inst, lev, rec.x, rec.y, rec.z, un, lane);
 }
@@ -1186,6 +1186,7 @@ __global__ __launch_bounds__(kSnPanelWaves * WAVE) void sn_panel_kernel(Refactor
     __shared__ T winv[4][16][17];
     __shared__ T lbuf[4][WAVE];
     __shared__ double cmax[kSnPanelWaves][NB];
+    __shared__ double dmax[kSnPanelWaves][NB];           // L11's column maxima, by slices of eight rows
     __shared__ int arrived;
     const int inst = blockIdx.y;
     if (sn_stopped(a, inst, lev)) return;                 // uniform over the workgroup
@@ -1193,7 +1194,7 @@ __global__ __launch_bounds__(kSnPanelWaves * WAVE) void sn_panel_kernel(Refactor
     const int wv = __builtin_amdgcn_readfirstlane(tid / WAVE);
     const int i16 = lane & 15, g = lane >> 4;
     const int4 un = reinterpret_cast<const int4 *>(a.sn_punit)[ubeg + (int)blockIdx.x];
-    const int4 rec = reinterpret_cast<const int4 *>(a.sn_rec)[a.sn_seq[un.x]];
+    const int4 rec = reinterpret_cast<const int4 *>(a.sn_pu2)[ubeg + (int)blockIdx.x];
     const int s0 = rec.x, w = rec.y, m = rec.z;
     // this unit's rows of R: slice un.y of un.z
     const int rb = (int)((int64_t)m * un.y / un.z), re = (int)((int64_t)m * (un.y + 1) / un.z);
@@ -1311,9 +1312,21 @@ __global__ __launch_bounds__(kSnPanelWaves * WAVE) void sn_panel_kernel(Refactor
             Fx[cb[c] + r] = blk[c][r];
         }
     }
+    {
+        // L11's column maxima below the diagonal: every thread takes eight rows of a column
+        const int c = tid & (NB - 1), sl = tid / NB;
+        double mm = 0.0;
+#pragma unroll
+        for (int u = 0; u < NB / kSnPanelWaves; u++) {
+            const int r = (NB / kSnPanelWaves) * sl + u;
+            if (c < w && r > c && r < w) mm = nanmax(mm, fabs((double)blk[c][r]));
+        }
+        dmax[sl][c] = mm;
+    }
+    __syncthreads();
     if (tid < w) {
         const int c = tid;
-        for (int r = c + 1; r < w; r++) M = nanmax(M, fabs((double)blk[c][r]));
+        for (int q = 0; q < kSnPanelWaves; q++) M = nanmax(M, dmax[q][c]);
         const double piv = (double)blk[c][c];
         const double xmax = fabs(piv) * M;
         const int col = s0 + c;

@@ -165,6 +165,7 @@ struct Schedule {
                                               // slices P, first scratch block (-1 when P = 1)}
     std::vector<int> sn_pulvl;                // [sn_levels+1] units of level l
     std::vector<int> sn_sunit, sn_sulvl;      // the same for the small panels
+    std::vector<int> sn_pu2, sn_su2;          // per unit: int4 {s0, w, m, 0} of its supernode
     int sn_pnscr = 0;                         // scratch blocks a launch uses at most
     std::vector<int> sn_task_lvl;             // [sn_levels+1] tasks of level l
     std::vector<int> sn_task_heavy;           // [sn_levels] its heavy tasks (a workgroup each) end here
@@ -232,7 +233,7 @@ struct Device {
     DevBuf snl_seq, snu_seq, Lrp, Urp;                                 // supernodal solves ({s0, w} per position)
     DevBuf snl_unit, snu_unit, sn_part, sn_cnt;                        // their split units
     DevBuf snl_urange, snl_runs, snu_urange, snu_runs;                 // the units' runs
-    DevBuf sn_punit, sn_sunit;                                         // split panels
+    DevBuf sn_punit, sn_sunit, sn_pu2, sn_su2;                         // split panels
     DevBuf sn_grp, sn_gsrc, sn_gent;                                   // grouped heavy tasks
     DevBuf ascale, gscale, sscale;     // static scaling: per nonzero of A, per solve row, per solve column
     DevBuf schur_sn_items;             // supernodal Schur update items
@@ -292,6 +293,7 @@ struct RefactorArgs {
     // scratch block}; column maxima of the slices (64 doubles per block and instance) and an
     // arrival counter per sn_seq position and instance (zero on entry and on exit)
     const int *sn_punit, *sn_sunit;
+    const int *sn_pu2, *sn_su2;    // per unit: {s0, w, m, 0} (the supernode record, read with the unit)
     const int *sn_grp, *sn_gsrc, *sn_gent;   // grouped heavy update tasks (see Schedule)
     double *sn_pmax;
     int *sn_pcnt;

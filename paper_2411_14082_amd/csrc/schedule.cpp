@@ -152,19 +152,25 @@ static void build_supernodal(const Factor &f, Schedule &s, int T, int wmax, int 
     s.sn_pulvl.assign(nl + 1, 0);
     s.sn_sulvl.assign(nl + 1, 0);
     s.sn_pnscr = 0;
-    auto units = [&](int q0, int q1, int rows, std::vector<int> &u) {
+    s.sn_pu2.clear();
+    s.sn_su2.clear();
+    auto units = [&](int q0, int q1, int rows, std::vector<int> &u, std::vector<int> &u2) {
         int blocks = 0;
         for (int q = q0; q < q1; q++) {
-            const int m = s.sn_rec[4 * (size_t)s.sn_seq[q] + 2];
+            const int S = s.sn_seq[q];
+            const int m = s.sn_rec[4 * (size_t)S + 2];
             const int P = std::max(1, (m + rows - 1) / rows);
-            for (int p = 0; p < P; p++) u.insert(u.end(), {q, p, P, P > 1 ? blocks : -1});
+            for (int p = 0; p < P; p++) {
+                u.insert(u.end(), {q, p, P, P > 1 ? blocks : -1});
+                u2.insert(u2.end(), {s.sn_rec[4 * (size_t)S], s.sn_rec[4 * (size_t)S + 1], m, 0});
+            }
             if (P > 1) blocks += P;
         }
         s.sn_pnscr = std::max(s.sn_pnscr, blocks);
     };
     for (int l = 0; l < nl; l++) {
-        units(s.sn_lvl_single[l], s.sn_lvl_small[l], std::max(1, panel_rows / 2), s.sn_sunit);
-        units(s.sn_lvl_small[l], s.sn_lvl[l + 1], panel_rows, s.sn_punit);
+        units(s.sn_lvl_single[l], s.sn_lvl_small[l], std::max(1, panel_rows / 2), s.sn_sunit, s.sn_su2);
+        units(s.sn_lvl_small[l], s.sn_lvl[l + 1], panel_rows, s.sn_punit, s.sn_pu2);
         s.sn_sulvl[l + 1] = (int)(s.sn_sunit.size() / 4);
         s.sn_pulvl[l + 1] = (int)(s.sn_punit.size() / 4);
     }
