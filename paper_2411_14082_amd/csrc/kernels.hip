@@ -3,7 +3,8 @@
 //
 // Refactorization (fast factorization with pivot check, Section IV-B):
 //   refactor_init_kernel   zeroes every factor column and scatters the matrix
-//                          values into it (one wavefront per column);
+//                          values into it (sixteen lanes per sparse column, a wavefront
+//                          per dense-block column);
 //   refactor_level_kernel  the column sweep (options.sweep_supernodes = -1), one launch
 //                          per level l: (a) tests the pivot of every column of level l
 //                          against eps times the largest entry of its L part (its values
@@ -22,7 +23,8 @@
 // on supernodes (dense.hip) with the same ownership rules.
 //
 // Solves (Section II-C, Algorithm 2), row ("pull") form: sn_solve_kernel takes one level
-// of supernodes per launch (the default); trisolve_level_kernel / trisolve_rowwg_kernel /
+// of supernodes per launch (the default; wide supernodes pull by runs of consecutive rows
+// in one column); trisolve_level_kernel / trisolve_rowwg_kernel /
 // trisolve_chain_kernel take one level of rows (the column sweep's schedule, and the rows
 // of the dense block's L entries in sparse columns).
 //
