@@ -309,10 +309,10 @@ int launch_dense_reinit(const RefactorArgs &a, void *stream);
 int launch_refactor_level(const RefactorArgs &a, int cbeg, int cend, int pbeg, int pend, int tbeg,
                           int tend, int lev, void *stream);
 // Supernodal sweep, level `lev` (dense.hip): the singleton supernodes sn_seq[sbeg, s1) (pivot test
-// and L = x / pivot, a wavefront each), the small panels as units sn_sunit[sub, sue) (a wavefront
-// each) and the wider panels as units sn_punit[ubeg, uend) (a workgroup each): dense LU of the
-// diagonal block,
-// L21 = A21 U11^-1, pivot test; then the level's update tasks: the heavy ones as groups
+// and L = x / pivot, sixteen lanes each), the small panels as units sn_sunit[sub, sue) (a
+// wavefront each) and the wider panels as units sn_punit[ubeg, uend) (a workgroup each): dense
+// LU of the diagonal block, L21 = A21 U11^-1, pivot test; then the level's update tasks: the
+// heavy ones as groups
 // sn_grp [gbeg, gend) (a workgroup each), [theavy, ttiny) a wavefront each, [ttiny, tend)
 // sixteen lanes each.
 int launch_sn_panels(const RefactorArgs &a, int lev, int sbeg, int s1, int sub, int sue, int ubeg, int uend,
