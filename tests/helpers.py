@@ -1,6 +1,13 @@
-"""Comparison helpers shared by the parity tests (library vs CPU oracle)."""
+"""Comparison helpers shared by the parity tests (library vs CPU oracle), and the circuits and
+build step of the host schedule checks."""
+import os
+import shutil
+import subprocess
+
 import numpy as np
 import scipy.sparse as sp
+
+import mnagen
 
 U64 = np.finfo(np.float64).eps / 2
 
@@ -145,3 +152,54 @@ def kappa_inf(c, values):
     """Infinity-norm condition number of A (dense; for small n only)."""
     A = sp.csc_matrix((values, c.rowind, c.colptr), shape=(c.n, c.n)).toarray()
     return float(np.linalg.norm(A, np.inf) * np.linalg.norm(np.linalg.inv(A), np.inf))
+
+
+# ---- host schedule checks (tests/schedule_check.cpp, tests/sched_sim.cpp): small circuits of
+# each generator; the power grid is large enough to have heavy update groups and solve
+# supernodes pulled by several units
+SCHEDULE_CASES = {
+    "power_grid_200x200": lambda: mnagen.power_grid(200, 200, n_src=200, nrhs=1, seed=3),
+    "mesh_transistor_50x50": lambda: mnagen.mesh_transistor(50, 50, seed=5),
+    "layered_rc_3x24x24": lambda: mnagen.layered_rc(24, 24, 3, seed=7),
+    "mesh_vsrc_30x30": lambda: mnagen.mesh_vsrc(30, 30, n_vsrc=6, seed=2),
+}
+
+# (dense_tail_size, solve_split_entries, sweep_panel_rows): the defaults; a dense tail of 256
+# with small solve units (several units per supernode) and split panels; no dense tail
+SCHEDULE_KNOBS = [(0, 0, 0), (256, 64, 16), (-1, 256, 64)]
+
+_TESTS = os.path.dirname(os.path.abspath(__file__))
+_ROOT = os.path.dirname(_TESTS)
+
+
+def write_csc_binary(path, c):
+    """The host tools' matrix file: int32 n, int64 nnz, int32 colptr[n+1], int32 rowind[nnz],
+    float64 values[nnz]."""
+    with open(path, "wb") as f:
+        np.array([c.n], dtype=np.int32).tofile(f)
+        np.array([c.nnz], dtype=np.int64).tofile(f)
+        np.asarray(c.colptr, dtype=np.int32).tofile(f)
+        np.asarray(c.rowind, dtype=np.int32).tofile(f)
+        np.asarray(c.values, dtype=np.float64).tofile(f)
+
+
+def build_host_tool(tmp_path_factory, source, flags=(), tag=""):
+    """Compiles tests/<source> with g++ against the in-tree libcktlu.so (its schedule builder
+    and host factorization); skips when g++, the HIP headers or the library are missing."""
+    import pytest
+    import paper_2411_14082_amd as ck
+    if shutil.which("g++") is None or not os.path.exists("/opt/rocm/include/hip/hip_runtime.h"):
+        pytest.skip("g++ or the HIP headers are not available")
+    if not os.path.exists(ck.LIB_PATH):
+        pytest.skip("libcktlu.so is not built")
+    out = str(tmp_path_factory.mktemp("hosttool") / (os.path.splitext(source)[0] + tag))
+    libdir = os.path.dirname(ck.LIB_PATH)
+    cmd = ["g++", "-std=c++17", "-O1", "-g", *flags, "-D__HIP_PLATFORM_AMD__", "-I/opt/rocm/include",
+           "-I" + os.path.join(_ROOT, "include"), "-I" + os.path.join(_ROOT, "paper_2411_14082_amd", "csrc"),
+           os.path.join(_TESTS, source), "-o", out, "-L" + libdir, "-l:libcktlu.so", "-Wl,-rpath," + libdir,
+           "-L/opt/rocm/lib", "-lamdhip64", "-Wl,-rpath,/opt/rocm/lib", "-pthread"]
+    r = subprocess.run(cmd, capture_output=True, text=True)
+    if r.returncode != 0 and flags:
+        pytest.skip("the sanitizer runtime is not available: " + r.stderr[-300:])
+    assert r.returncode == 0, r.stderr[-4000:]
+    return out
