@@ -1418,7 +1418,7 @@ constexpr int kHeavyChunk = 16;                      // entries of a heavy group
 // them (its suffix columns only, in ascending order: each target row gets the operations of a
 // single-target task in the same order), two rows per lane, R's rows split over the four
 // wavefronts, a barrier between sources (their rows of R may meet in a target).
-template <typename T, int CB>
+template <typename T>
 __device__ void sn_heavy_group(const RefactorArgs &a, int inst, int g, T (*us)[WAVE], int *gdp, int *eoff, int *edp,
                                int64_t *emoff, int lane, int wv) {
     const int tid = threadIdx.x;
@@ -1475,17 +1475,17 @@ __device__ void sn_heavy_group(const RefactorArgs &a, int inst, int g, T (*us)[W
                 T acca[kGroupTargets], accb[kGroupTargets];
 #pragma unroll
                 for (int j = 0; j < kGroupTargets; j++) acca[j] = accb[j] = T(0);
-                for (int c0 = offmin; c0 < w; c0 += CB) {
-                    T la[CB], lb[CB];
+                for (int c0 = offmin; c0 < w; c0 += 8) {
+                    T la[8], lb[8];
 #pragma unroll
-                    for (int u = 0; u < CB; u++) {
+                    for (int u = 0; u < 8; u++) {
                         const int c = c0 + u;
                         const int base = __builtin_amdgcn_readlane(cbv, c < w ? c : offmin) + w;
                         la[u] = (ina && c < w) ? Fx[base + ra] : T(0);
                         lb[u] = (inb && c < w) ? Fx[base + rb] : T(0);
                     }
 #pragma unroll
-                    for (int u = 0; u < CB; u++) {
+                    for (int u = 0; u < 8; u++) {
                         const int c = c0 + u;
                         if (c < w) {
 #pragma unroll
@@ -1522,7 +1522,7 @@ __device__ void sn_heavy_group(const RefactorArgs &a, int inst, int g, T (*us)[W
 // workgroups: groups x instances, see sn_heavy_group); tasks [theavy, ttiny) get a wavefront
 // per (task, instance), [ttiny, tend) sixteen lanes.  Every way, each row of k receives the
 // same operations in the same order.
-template <typename T, int CB>
+template <typename T>
 __global__ __launch_bounds__(256) void sn_update_kernel(RefactorArgs a, int lev, int gbeg, int theavy, int ttiny,
                                                         int tend, unsigned nheavy) {
     __shared__ T us[kHeavyChunk][WAVE];
@@ -1538,7 +1538,7 @@ __global__ __launch_bounds__(256) void sn_update_kernel(RefactorArgs a, int lev,
         const unsigned b = xcd_contiguous(bid, nheavy);
         inst = (int)(b % batch);
         if (sn_stopped(a, inst, lev)) return;            // uniform over the workgroup
-        sn_heavy_group<T, CB>(a, inst, gbeg + (int)(b / batch), us, gdp, eoff, edp, emoff, lane, wv);
+        sn_heavy_group<T>(a, inst, gbeg + (int)(b / batch), us, gdp, eoff, edp, emoff, lane, wv);
         return;
     } else if (bid < nheavy + nlight) {
         const unsigned wid = xcd_contiguous(bid - nheavy, nlight) * 4 + wv;
@@ -1871,18 +1871,10 @@ int launch_sn_updates(const RefactorArgs &a, int lev, int gbeg, int gend, int th
     if (heavy + light + tiny == 0) return 0;
     if (heavy + light + tiny > INT_MAX || (int64_t)(tend - theavy) * a.batch > INT_MAX) return (int)hipErrorInvalidValue;
     const dim3 grid((unsigned)(heavy + light + tiny));
-    // a launch whose wavefronts all fit on the chip at four per SIMD (the upper separators'
-    // levels: a few hundred heavy groups; MI355X: 256 CUs of four SIMDs) takes the kernel that
-    // loads sixteen columns per batch (half the dependent round trips of eight, in registers
-    // that leave room for four wavefronts per SIMD); a larger launch needs the occupancy of
-    // eight.  The same operations in the same order either way
-    const bool wide = heavy * 4 + light * 4 + tiny * 4 <= 256 * 4 * 4;
-    auto go = [&](auto kern) {
-        hipLaunchKernelGGL(kern, grid, dim3(256), 0, (hipStream_t)stream, a, lev, gbeg, theavy, ttiny, tend,
-                           (unsigned)heavy);
-    };
-    if (a.fp32) wide ? go(sn_update_kernel<float, 16>) : go(sn_update_kernel<float, 8>);
-    else wide ? go(sn_update_kernel<double, 16>) : go(sn_update_kernel<double, 8>);
+    if (a.fp32) hipLaunchKernelGGL(sn_update_kernel<float>, grid, dim3(256), 0, (hipStream_t)stream, a, lev, gbeg,
+                                   theavy, ttiny, tend, (unsigned)heavy);
+    else hipLaunchKernelGGL(sn_update_kernel<double>, grid, dim3(256), 0, (hipStream_t)stream, a, lev, gbeg, theavy,
+                            ttiny, tend, (unsigned)heavy);
     return (int)hipGetLastError();
 }
 
