@@ -734,7 +734,7 @@ __global__ __launch_bounds__(256) void dtrsv_kernel(DenseArgs a, double *y, int 
     __shared__ double part[4][NR][NB];                // the quarters' sums, [quarter][rhs][row]
     __shared__ double tri[NB][NB + 1];                // tri[col][row] of the diagonal block's inverse
     const int inst = blockIdx.y;
-    const int skv = skip ? skip[inst] : -1;           // tested once the first loads are out
+    if (skip && skip[inst] != -1) return;
     const T *S = inst_S<T>(a, inst);
     double *yt = y + ((size_t)inst * a.n + a.T) * NR;
     const int D = a.D, tid = threadIdx.x, lane = tid & (NB - 1), q = tid / NB;
@@ -756,7 +756,6 @@ __global__ __launch_bounds__(256) void dtrsv_kernel(DenseArgs a, double *y, int 
     double yi[NR];
 #pragma unroll
     for (int r = 0; r < NR; r++) yi[r] = q == 0 && row ? yt[(size_t)i * NR + r] : 0.0;
-    if (skv != -1) return;                            // the whole workgroup
     if (b > 0) {
         if (tid < NB * NR / 2) {                      // NB * NR <= 512: two loads per thread
             const int e1 = tid + NB * NR / 2;
@@ -1008,11 +1007,6 @@ __device__ __forceinline__ bool sn_stopped(const RefactorArgs &a, int inst, int 
     const int st = a.ctrl[1 + inst];
     return st != 0 && st <= lev;
 }
-// The same test in two halves, so that the interrupt word's load goes out with a task's first
-// record loads instead of before them: sn_stop_word issues it, sn_stop_at tests it once those
-// loads are in flight (nothing is written before the test)
-__device__ __forceinline__ int sn_stop_word(const RefactorArgs &a, int inst) { return a.check ? a.ctrl[1 + inst] : 0; }
-__device__ __forceinline__ bool sn_stop_at(int st, int lev) { return st != 0 && st <= lev; }
 __device__ __forceinline__ void sn_fail(const RefactorArgs &a, int inst, int lev, int col) {
     atomicMin(&a.ctrl[1 + a.batch + inst], col);
     atomicExch(&a.ctrl[1 + inst], lev + 1);          // every writer of this launch writes the same
@@ -1149,9 +1143,8 @@ __global__ __launch_bounds__(256) void sn_single_kernel(RefactorArgs a, int lev,
     const int64_t g = (int64_t)blockIdx.x * 16 + threadIdx.x / 16;
     if (g >= (int64_t)(send - sbeg) * a.batch) return;
     const int inst = (int)(g % a.batch);
-    const int st = sn_stop_word(a, inst);
     const int j = a.sn_rec[4 * a.sn_seq[sbeg + (int)(g / a.batch)]];
-    if (sn_stop_at(st, lev)) return;                      // uniform over the sixteen lanes
+    if (sn_stopped(a, inst, lev)) return;                 // uniform over the sixteen lanes
     T *x = reinterpret_cast<T *>(a.Fx) + (size_t)inst * a.nnzF + a.Dp[j];
     const int nu = a.nU[j], len = a.Dlen[j];
     const T d = x[nu - 1];
@@ -1196,13 +1189,12 @@ __global__ __launch_bounds__(kSnPanelWaves * WAVE) void sn_panel_kernel(Refactor
     __shared__ double dmax[kSnPanelWaves][NB];           // L11's column maxima, by slices of eight rows
     __shared__ int arrived;
     const int inst = blockIdx.y;
-    const int st = sn_stop_word(a, inst);
+    if (sn_stopped(a, inst, lev)) return;                 // uniform over the workgroup
     const int tid = threadIdx.x, lane = tid & (WAVE - 1);
     const int wv = __builtin_amdgcn_readfirstlane(tid / WAVE);
     const int i16 = lane & 15, g = lane >> 4;
     const int4 un = reinterpret_cast<const int4 *>(a.sn_punit)[ubeg + (int)blockIdx.x];
     const int4 rec = reinterpret_cast<const int4 *>(a.sn_pu2)[ubeg + (int)blockIdx.x];
-    if (sn_stop_at(st, lev)) return;                      // uniform over the workgroup
     const int s0 = rec.x, w = rec.y, m = rec.z;
     // this unit's rows of R: slice un.y of un.z
     const int rb = (int)((int64_t)m * un.y / un.z), re = (int)((int64_t)m * (un.y + 1) / un.z);
@@ -1427,10 +1419,11 @@ constexpr int kHeavyChunk = 16;                      // entries of a heavy group
 // single-target task in the same order), two rows per lane, R's rows split over the four
 // wavefronts, a barrier between sources (their rows of R may meet in a target).
 template <typename T>
-__device__ void sn_heavy_group(const RefactorArgs &a, int inst, int4 gr, T (*us)[WAVE], int *gdp, int *eoff, int *edp,
+__device__ void sn_heavy_group(const RefactorArgs &a, int inst, int g, T (*us)[WAVE], int *gdp, int *eoff, int *edp,
                                int64_t *emoff, int lane, int wv) {
     const int tid = threadIdx.x;
     T *Fx = reinterpret_cast<T *>(a.Fx) + (size_t)inst * a.nnzF;
+    const int4 gr = reinterpret_cast<const int4 *>(a.sn_grp)[g];
     const int4 *gsrc = reinterpret_cast<const int4 *>(a.sn_gsrc);
     const int2 *gent = reinterpret_cast<const int2 *>(a.sn_gent);
     if (tid < gr.y) gdp[tid] = a.sn_task[4 * (gr.x + tid) + 1];
@@ -1544,10 +1537,8 @@ __global__ __launch_bounds__(256) void sn_update_kernel(RefactorArgs a, int lev,
     if (bid < nheavy) {
         const unsigned b = xcd_contiguous(bid, nheavy);
         inst = (int)(b % batch);
-        const int st = sn_stop_word(a, inst);
-        const int4 gr = reinterpret_cast<const int4 *>(a.sn_grp)[gbeg + (int)(b / batch)];
-        if (sn_stop_at(st, lev)) return;                 // uniform over the workgroup
-        sn_heavy_group<T>(a, inst, gr, us, gdp, eoff, edp, emoff, lane, wv);
+        if (sn_stopped(a, inst, lev)) return;            // uniform over the workgroup
+        sn_heavy_group<T>(a, inst, gbeg + (int)(b / batch), us, gdp, eoff, edp, emoff, lane, wv);
         return;
     } else if (bid < nheavy + nlight) {
         const unsigned wid = xcd_contiguous(bid - nheavy, nlight) * 4 + wv;
@@ -1564,11 +1555,10 @@ __global__ __launch_bounds__(256) void sn_update_kernel(RefactorArgs a, int lev,
         const unsigned gid = xcd_contiguous(bid - nheavy - nlight, ntiny) * 16 + threadIdx.x / 16;
         if (gid >= (unsigned)(tend - ttiny) * batch) return;
         inst = (int)(gid % batch);
-        const int st = sn_stop_word(a, inst);
+        if (sn_stopped(a, inst, lev)) return;
         const int l16 = lane & 15;
         T *Fx = reinterpret_cast<T *>(a.Fx) + (size_t)inst * a.nnzF;
         const int4 tk = reinterpret_cast<const int4 *>(a.sn_task)[ttiny + (int)(gid / batch)];
-        if (sn_stop_at(st, lev)) return;
         T *xk = Fx + tk.y;
         const int4 *items = reinterpret_cast<const int4 *>(a.sn_item);
         const int4 *items2 = reinterpret_cast<const int4 *>(a.sn_item2);
@@ -1630,10 +1620,9 @@ __global__ __launch_bounds__(256) void sn_update_kernel(RefactorArgs a, int lev,
         }
         return;
     }
-    const int st = sn_stop_word(a, inst);
+    if (sn_stopped(a, inst, lev)) return;
     T *Fx = reinterpret_cast<T *>(a.Fx) + (size_t)inst * a.nnzF;
     const int4 tk = reinterpret_cast<const int4 *>(a.sn_task)[t];
-    if (sn_stop_at(st, lev)) return;
     T *xk = Fx + tk.y;
     const int4 *items = reinterpret_cast<const int4 *>(a.sn_item);
     const int4 *items2 = reinterpret_cast<const int4 *>(a.sn_item2);

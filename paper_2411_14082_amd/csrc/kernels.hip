@@ -677,9 +677,8 @@ __global__ __launch_bounds__(kSnSolveWG) void sn_solve_kernel(SolveArgs a, const
         const int64_t gid = (int64_t)blockIdx.x * (kSnSolveWG / 16) + threadIdx.x / 16;
         if (gid >= ntiny) return;
         const int inst = (int)(gid % a.batch);
-        const int skv = a.skip ? a.skip[inst] : -1;      // tested once the row's record is out
+        if (a.skip && a.skip[inst] != -1) return;
         const int i = sw[2 * (sbeg + (int)(gid / a.batch))];
-        if (skv != -1) return;
         const int l16 = lane & 15;
         const T *Fx = reinterpret_cast<const T *>(a.Fx) + (size_t)inst * a.nnzF;
         double *y = a.y + (size_t)inst * a.n * NR;
@@ -720,9 +719,8 @@ __global__ __launch_bounds__(kSnSolveWG) void sn_solve_kernel(SolveArgs a, const
         const int64_t wid = ((int64_t)blockIdx.x - ntb) * kSnSolveWaves + wv;
         if (wid >= nsingle) return;
         const int inst = (int)(wid % a.batch);
-        const int skv = a.skip ? a.skip[inst] : -1;
+        if (a.skip && a.skip[inst] != -1) return;
         const int2 rec = reinterpret_cast<const int2 *>(sw)[stiny + (int)(wid / a.batch)];
-        if (skv != -1) return;
         const int s0 = rec.x, w = rec.y;
         if (w == 1) {
             solve_row_rec<T, NR, UPPER>(a, inst, make_int4(s0, rp[s0], rp[s0 + 1], a.sn_cb[s0]), lane);
@@ -772,11 +770,10 @@ __global__ __launch_bounds__(kSnSolveWG) void sn_solve_kernel(SolveArgs a, const
     }
     const int64_t pu = (int64_t)blockIdx.x - nsw;
     const int inst = (int)(pu % a.batch);
-    const int skv = a.skip ? a.skip[inst] : -1;          // tested once the unit's records are out
+    if (a.skip && a.skip[inst] != -1) return;            // the whole workgroup
     const int ui = ubeg + (int)(pu / a.batch);
     int4 un = reinterpret_cast<const int4 *>(units)[ui];
     int4 ur = reinterpret_cast<const int4 *>(urange)[ui];   // runs [x, y) of supernode [z, z + w)
-    if (skv != -1) return;                               // the whole workgroup
     if (whole && un.z > 1) {
         // one workgroup per supernode: the first unit takes every unit's runs (they are
         // consecutive), the others leave
