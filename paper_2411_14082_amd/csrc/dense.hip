@@ -1418,7 +1418,7 @@ constexpr int kHeavyChunk = 16;                      // entries of a heavy group
 // them (its suffix columns only, in ascending order: each target row gets the operations of a
 // single-target task in the same order), two rows per lane, R's rows split over the four
 // wavefronts, a barrier between sources (their rows of R may meet in a target).
-template <typename T>
+template <typename T, bool PF>
 __device__ void sn_heavy_group(const RefactorArgs &a, int inst, int g, T (*us)[WAVE], int *gdp, int *eoff, int *edp,
                                int64_t *emoff, int lane, int wv) {
     const int tid = threadIdx.x;
@@ -1472,6 +1472,27 @@ __device__ void sn_heavy_group(const RefactorArgs &a, int inst, int g, T (*us)[W
             for (int r0 = 2 * WAVE * wv; r0 < mcnt; r0 += 8 * WAVE) {
                 const int ra = r0 + lane, rb = r0 + WAVE + lane;
                 const bool ina = ra < mcnt, inb = rb < mcnt;
+                // PF: the pass's target slots and their values go out first, with the
+                // columns' loads (the write-back then waits on no load): nothing else writes
+                // them during the pass (the source's rows are distinct, the group's sources are
+                // apart by a barrier, no other supernode of the level holds rows of R), so
+                // x - sum stores the same bits as the read-modify-write at the end
+                int sa[kGroupTargets], sb[kGroupTargets];
+                T xa[kGroupTargets], xb[kGroupTargets];
+                if constexpr (PF) {
+#pragma unroll
+                    for (int j = 0; j < kGroupTargets; j++) {
+                        const int *mp = a.sn_map + emoff[e0 + j];
+                        sa[j] = (j < ns && ina) ? mp[ra] : 0;
+                        sb[j] = (j < ns && inb) ? mp[rb] : 0;
+                    }
+#pragma unroll
+                    for (int j = 0; j < kGroupTargets; j++) {
+                        const T *xk = Fx + edp[e0 + j];
+                        xa[j] = (j < ns && ina) ? xk[sa[j]] : T(0);
+                        xb[j] = (j < ns && inb) ? xk[sb[j]] : T(0);
+                    }
+                }
                 T acca[kGroupTargets], accb[kGroupTargets];
 #pragma unroll
                 for (int j = 0; j < kGroupTargets; j++) acca[j] = accb[j] = T(0);
@@ -1502,9 +1523,14 @@ __device__ void sn_heavy_group(const RefactorArgs &a, int inst, int g, T (*us)[W
                 for (int j = 0; j < kGroupTargets; j++)
                     if (j < ns) {
                         T *xk = Fx + edp[e0 + j];
-                        const int *mp = a.sn_map + emoff[e0 + j];
-                        if (ina) xk[mp[ra]] -= acca[j];
-                        if (inb) xk[mp[rb]] -= accb[j];
+                        if constexpr (PF) {
+                            if (ina) xk[sa[j]] = xa[j] - acca[j];
+                            if (inb) xk[sb[j]] = xb[j] - accb[j];
+                        } else {
+                            const int *mp = a.sn_map + emoff[e0 + j];
+                            if (ina) xk[mp[ra]] -= acca[j];
+                            if (inb) xk[mp[rb]] -= accb[j];
+                        }
                     }
             }
             __syncthreads();
@@ -1522,7 +1548,7 @@ __device__ void sn_heavy_group(const RefactorArgs &a, int inst, int g, T (*us)[W
 // workgroups: groups x instances, see sn_heavy_group); tasks [theavy, ttiny) get a wavefront
 // per (task, instance), [ttiny, tend) sixteen lanes.  Every way, each row of k receives the
 // same operations in the same order.
-template <typename T>
+template <typename T, bool PF>
 __global__ __launch_bounds__(256) void sn_update_kernel(RefactorArgs a, int lev, int gbeg, int theavy, int ttiny,
                                                         int tend, unsigned nheavy) {
     __shared__ T us[kHeavyChunk][WAVE];
@@ -1538,7 +1564,7 @@ __global__ __launch_bounds__(256) void sn_update_kernel(RefactorArgs a, int lev,
         const unsigned b = xcd_contiguous(bid, nheavy);
         inst = (int)(b % batch);
         if (sn_stopped(a, inst, lev)) return;            // uniform over the workgroup
-        sn_heavy_group<T>(a, inst, gbeg + (int)(b / batch), us, gdp, eoff, edp, emoff, lane, wv);
+        sn_heavy_group<T, PF>(a, inst, gbeg + (int)(b / batch), us, gdp, eoff, edp, emoff, lane, wv);
         return;
     } else if (bid < nheavy + nlight) {
         const unsigned wid = xcd_contiguous(bid - nheavy, nlight) * 4 + wv;
@@ -1871,10 +1897,18 @@ int launch_sn_updates(const RefactorArgs &a, int lev, int gbeg, int gend, int th
     if (heavy + light + tiny == 0) return 0;
     if (heavy + light + tiny > INT_MAX || (int64_t)(tend - theavy) * a.batch > INT_MAX) return (int)hipErrorInvalidValue;
     const dim3 grid((unsigned)(heavy + light + tiny));
-    if (a.fp32) hipLaunchKernelGGL(sn_update_kernel<float>, grid, dim3(256), 0, (hipStream_t)stream, a, lev, gbeg,
-                                   theavy, ttiny, tend, (unsigned)heavy);
-    else hipLaunchKernelGGL(sn_update_kernel<double>, grid, dim3(256), 0, (hipStream_t)stream, a, lev, gbeg, theavy,
-                            ttiny, tend, (unsigned)heavy);
+    // a launch whose wavefronts all fit on the chip at four per SIMD (MI355X: 256 CUs of four
+    // SIMDs; the upper separators' levels of a few hundred heavy groups) takes the kernel that
+    // loads each pass's target slots and values up front, in registers that leave room for
+    // four wavefronts per SIMD; a larger launch needs the occupancy of the other.  The same
+    // operations in the same order either way
+    const bool pf = (heavy + light + tiny) * 4 <= 256 * 4 * 4;
+    auto go = [&](auto kern) {
+        hipLaunchKernelGGL(kern, grid, dim3(256), 0, (hipStream_t)stream, a, lev, gbeg, theavy, ttiny, tend,
+                           (unsigned)heavy);
+    };
+    if (a.fp32) pf ? go(sn_update_kernel<float, true>) : go(sn_update_kernel<float, false>);
+    else pf ? go(sn_update_kernel<double, true>) : go(sn_update_kernel<double, false>);
     return (int)hipGetLastError();
 }
 
