@@ -9,6 +9,7 @@
 #include <cstdint>
 #include <cstdio>
 #include <cstdlib>
+#include <iterator>
 #include <tuple>
 #include <vector>
 
@@ -92,6 +93,30 @@ static int check(const Schedule &s) {
                     if (k >= T) REQ(s.Fi_dev[s.Dp[k] + slot] < T);
                 }
             }
+        }
+        // ---- within a task (one target column, one level): the suffix slots of its items are
+        // pairwise distinct and none is a slot of any item's rows of R (a source's suffix solve
+        // reads no slot another source of the level updates, so the suffix solves may go
+        // first), and one item's rows of R land on distinct slots (a pass may load its target
+        // values before its sums).  Rows of R of different items may meet: those updates
+        // accumulate, one source after another
+        for (int t = s.sn_task_lvl[l]; t < s.sn_task_lvl[l + 1]; t++) {
+            std::vector<int> suffix, rrows;
+            for (int it = s.sn_task[4 * (size_t)t + 2]; it < s.sn_task[4 * (size_t)t + 3]; it++) {
+                const int slot0 = s.sn_item[4 * (size_t)it + 1], len = s.sn_item[4 * (size_t)it + 2];
+                const int mcnt = s.sn_item[4 * (size_t)it + 3];
+                for (int c = 0; c < len; c++) suffix.push_back(slot0 + c);
+                std::vector<int> mine(s.sn_map.begin() + s.sn_moff[it], s.sn_map.begin() + s.sn_moff[it] + mcnt);
+                std::sort(mine.begin(), mine.end());
+                REQ(std::adjacent_find(mine.begin(), mine.end()) == mine.end());
+                rrows.insert(rrows.end(), mine.begin(), mine.end());
+            }
+            std::sort(suffix.begin(), suffix.end());
+            std::sort(rrows.begin(), rrows.end());
+            REQ(std::adjacent_find(suffix.begin(), suffix.end()) == suffix.end());
+            std::vector<int> both;
+            std::set_intersection(suffix.begin(), suffix.end(), rrows.begin(), rrows.end(), std::back_inserter(both));
+            REQ(both.empty());
         }
         // ---- heavy groups: consecutive heavy tasks of one target supernode (or all dense);
         // every item exactly once; a source's entries update the same rows of R

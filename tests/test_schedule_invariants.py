@@ -6,8 +6,10 @@ What is checked, per level of the sweep (Section IV's right-looking supernodal u
 singletons, small and wide panels in their ranges; panel units covering every panel once and
 carrying their supernode's record; every update item's suffix at consecutive slots of its
 target column holding the source's rows, and its map sending R's rows to the same rows of the
-target (rows below the dense tail only, for a dense target); heavy groups covering each of
-their tasks' items exactly once with the sources ascending.  Per level of the L and U solves:
+target (rows below the dense tail only, for a dense target); within a task, suffix slots
+distinct and never a slot of any item's rows of R, and each item's rows of R on distinct
+slots (what lets the suffix solves go first and a pass load its target values up front);
+heavy groups covering each of their tasks' items exactly once with the sources ascending.  Per level of the L and U solves:
 the singletons left out of the L launches pull nothing, and the runs of every workgroup
 supernode hold exactly its entries outside the diagonal block, each at a position that holds
 its row.
